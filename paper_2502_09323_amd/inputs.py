@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs for the linearized Poisson-Boltzmann grid solve.
+
+This module only draws random molecules and grid descriptions. It holds none of
+the method's arithmetic (no geometry tests, no operator, no energies), so that the
+GPU path and the CPU oracle can both be fed from it without sharing any code.
+
+Molecules follow the paper's model of a solute as a union of charged atom balls
+(Sect. 2.1): centres are drawn by rejection sampling inside a ball of radius
+``sphere_R`` with a minimum pair distance, radii are uniform, and partial charges
+are normal and then shifted so that the net charge is an integer.
+
+Random draws happen in a fixed order: candidate centres (batches of 4096 points,
+three uniforms each, in [-R, R]^3), then radii, then charges.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Boundary-condition codes and precision codes (same values as the C header).
+BC_ZERO, BC_DH, BC_USER = 0, 1, 2
+FP64, MIXED = 0, 1
+
+
+@dataclass
+class Molecule:
+    xyz: np.ndarray      # (N, 3) float64, Angstrom
+    radius: np.ndarray   # (N,) float64, Angstrom
+    charge: np.ndarray   # (N,) float64, units of e
+
+    @property
+    def n(self) -> int:
+        return int(self.radius.shape[0])
+
+
+@dataclass
+class GridSpec:
+    n: tuple             # nodes per axis (nx, ny, nz)
+    h: float             # spacing, Angstrom
+    origin: tuple        # coordinates of node (0, 0, 0), Angstrom
+    eps_in: float = 2.0
+    eps_out: float = 80.0
+    ionic_M: float = 0.145
+    temp_K: float = 298.0
+    bc: int = BC_DH
+    rtol: float = 1e-10
+    max_iter: int = 20000
+    precision: int = FP64
+    inner_rtol: float = 1e-4
+    bc_values: np.ndarray | None = field(default=None, repr=False)  # BC_USER: full grid
+
+    @property
+    def nodes(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    @property
+    def unknowns(self) -> int:
+        return (int(self.n[0]) - 2) * (int(self.n[1]) - 2) * (int(self.n[2]) - 2)
+
+
+def random_molecule(n_atoms: int, sphere_R: float, seed: int,
+                    min_dist: float = 1.0, r_lo: float = 1.2, r_hi: float = 2.0,
+                    q_sigma: float = 0.4, center=(0.0, 0.0, 0.0)) -> Molecule:
+    """Rejection-sampled synthetic molecule (seeded, PCG64)."""
+    rng = np.random.default_rng(seed)
+    cell = min_dist
+    grid: dict = {}
+    acc = np.empty((n_atoms, 3))
+    na = 0
+    md2 = min_dist * min_dist
+    R2 = sphere_R * sphere_R
+    while na < n_atoms:
+        cand = rng.uniform(-sphere_R, sphere_R, size=(4096, 3))
+        for c in cand:
+            if na >= n_atoms:
+                break
+            if c[0] * c[0] + c[1] * c[1] + c[2] * c[2] > R2:
+                continue
+            key = (int(math.floor(c[0] / cell)), int(math.floor(c[1] / cell)),
+                   int(math.floor(c[2] / cell)))
+            ok = True
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        lst = grid.get((key[0] + dx, key[1] + dy, key[2] + dz))
+                        if not lst:
+                            continue
+                        for idx in lst:
+                            d = acc[idx] - c
+                            if d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < md2:
+                                ok = False
+                                break
+                        if not ok:
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                continue
+            acc[na] = c
+            grid.setdefault(key, []).append(na)
+            na += 1
+    radius = rng.uniform(r_lo, r_hi, size=n_atoms)
+    charge = rng.normal(0.0, q_sigma, size=n_atoms)
+    net = charge.sum()
+    charge = charge - (net - np.round(net)) / n_atoms   # np.round: half to even
+    xyz = acc + np.asarray(center, dtype=np.float64)[None, :]
+    return Molecule(np.ascontiguousarray(xyz), np.ascontiguousarray(radius),
+                    np.ascontiguousarray(charge))
+
+
+def single_charge_sphere(R: float = 2.0, q: float = 1.0, center=(0.0, 0.0, 0.0)) -> Molecule:
+    return Molecule(np.array([center], dtype=np.float64), np.array([R]), np.array([q]))
+
+
+def cubic_grid(n: int, h: float, center=(0.0, 0.0, 0.0), **kw) -> GridSpec:
+    """Cubic grid of n^3 nodes with spacing h centred on ``center``."""
+    half = 0.5 * (n - 1) * h
+    origin = tuple(float(c) - half for c in center)
+    return GridSpec(n=(n, n, n), h=h, origin=origin, **kw)
+
+
+# --- the five workloads -------------------------------------------------------
+
+def kirkwood_c1(**kw):
+    """One +1 e charge at the centre of a 2 A sphere; 65^3 nodes at 0.25 A."""
+    mol = single_charge_sphere()
+    g = cubic_grid(65, 0.25, **kw)
+    return mol, g
+
+
+def protein_c2(seed: int = 2502, **kw):
+    """2,000-atom synthetic molecule in a 20 A ball; 161^3 nodes at 0.5 A."""
+    mol = random_molecule(2000, 20.0, seed)
+    return mol, cubic_grid(161, 0.5, **kw)
+
+
+def refined_c3(seed: int = 2503, **kw):
+    """20,000-atom molecule in a 45 A ball; coarse 193^3 nodes at 1.0 A."""
+    mol = random_molecule(20000, 45.0, seed)
+    return mol, cubic_grid(193, 1.0, **kw)
+
+
+def large_c4(seed: int = 2504, **kw):
+    """60,000-atom molecule in a 65 A ball; 385^3 nodes at 0.5 A."""
+    mol = random_molecule(60000, 65.0, seed)
+    return mol, cubic_grid(385, 0.5, **kw)
+
+
+def serving_sizes(n_atoms: int, h: float):
+    """Placement-ball radius and cubic node count for a serving request."""
+    Rs = 20.0 * (n_atoms / 2000.0) ** (1.0 / 3.0)
+    cells = 32 * math.ceil(4.0 * Rs / (32.0 * h))
+    cells = min(max(cells, 64), 256)
+    return Rs, cells + 1
+
+
+def serving_stream_c5(n_req: int = 512, seed: int = 2505, rate_hz: float = 1.0, **kw):
+    """Request list for the serving stream: (arrival_s, molecule, grid).
+
+    Atom counts are log-uniform in [200, 20000], spacings uniform in
+    {0.5, 0.75, 1.0} A; arrivals are a Poisson process of the given rate.
+    Per-request molecules use seed ``seed * 100003 + k``.
+    """
+    rng = np.random.default_rng(seed)
+    logn = rng.uniform(math.log(200.0), math.log(20000.0), size=n_req)
+    hs = rng.choice(np.array([0.5, 0.75, 1.0]), size=n_req)
+    gaps = rng.exponential(1.0 / rate_hz, size=n_req)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for k in range(n_req):
+        na = int(round(math.exp(logn[k])))
+        Rs, n = serving_sizes(na, float(hs[k]))
+        mol = random_molecule(na, Rs, seed * 100003 + k)
+        out.append((float(t[k]), mol, cubic_grid(n, float(hs[k]), **kw)))
+    return out
