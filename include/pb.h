@@ -1,0 +1,187 @@
+/*
+ * pb.h -- C ABI of the MI355X (gfx950) linearized Poisson-Boltzmann grid solver.
+ *
+ * The library solves, on one GPU, the linearized Poisson-Boltzmann equation of
+ * Sect. 2.1 (eq. LPBE) for a solute made of charged atom balls, discretized as in
+ * Sect. 3 of the paper: a vertex-based Cartesian scheme whose condensed operator is a
+ * 7-point stencil with one permittivity per grid edge (Sect. 3.1, eq. matrixequation),
+ * the weighted harmonic average on edges that cross the molecular surface (Sect. 3.2,
+ * eq. WHA), and the solvation energy read back from surface quantities only
+ * (Sect. 3.3: Coulomb pair sum, flux-based polarization charges, and the ionic surface
+ * integral of eq. energy_ion with the surface potential of eq. phi0).
+ *
+ * Units.  Lengths in Angstrom, charges in units of e, temperature in K, ionic strength
+ * in mol/L of a 1:1 salt.  Energies are returned in kT, potentials in kT/e.
+ *
+ * Grid.  n[0] x n[1] x n[2] nodes, node (i,j,k) at origin + h*(i,j,k).  All nodes on the
+ * box faces carry Dirichlet values; the unknowns are the interior nodes.  Host arrays
+ * over the grid use the order ((i*n[1] + j)*n[2] + k), z fastest.
+ *
+ * Ownership.  The caller owns every input array; the library copies what it needs.
+ * Device memory is obtained only through the allocator callbacks given to
+ * pb_ctx_create and is returned through them by the matching *_free/destroy call.
+ * All GPU work is issued on the stream given to pb_ctx_create.
+ *
+ * Errors.  Every int-returning call returns PB_OK (0) or a negative PB_E* code and
+ * never aborts.  pb_last_error() returns a message describing the last failure on the
+ * calling thread.
+ */
+#ifndef PB_H
+#define PB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PB_OK = 0,
+    PB_EINVAL = -1,      /* bad parameters or atoms (checked on the host before any launch) */
+    PB_ENOMEM = -2,      /* allocation failed or a request exceeds the memory budget */
+    PB_ENOCONV = -3,     /* max_iter reached; the last iterate and statistics are returned */
+    PB_EBREAKDOWN = -4,  /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
+    PB_EDEVICE = -5      /* a HIP runtime call failed; see pb_last_error() */
+};
+
+enum { PB_BC_ZERO = 0, PB_BC_DH = 1, PB_BC_USER = 2 };
+enum { PB_FP64 = 0, PB_MIXED = 1 };
+
+typedef struct pb_ctx pb_ctx;
+typedef struct pb_problem pb_problem;
+typedef struct pb_server pb_server;
+
+/* Device allocator: must return memory usable by kernels on the context's device and
+ * stream, aligned to at least 256 bytes, or NULL on failure. */
+typedef void* (*pb_alloc_fn)(size_t bytes, void* user);
+typedef void (*pb_free_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device` issuing work on `hip_stream` (a hipStream_t;
+ * NULL means the null stream).  `alloc`/`free_fn` are required.  `hbm_budget_bytes`
+ * bounds the device memory of problems admitted by a server (0 = no bound).
+ * Errors: PB_EINVAL (missing callbacks, bad device), PB_EDEVICE. */
+int pb_ctx_create(int device, void* hip_stream, pb_alloc_fn alloc, pb_free_fn free_fn,
+                  void* user, size_t hbm_budget_bytes, pb_ctx** out);
+void pb_ctx_destroy(pb_ctx* ctx);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pb_last_error(void);
+
+/* Problem statement (Sect. 2: eps_in, eps_out, ionic strength, temperature; Sect. 2.3:
+ * box boundary conditions; Sect. 3: grid spacing). */
+typedef struct {
+    double eps_in;          /* solute relative permittivity (e.g. 2) */
+    double eps_out;         /* solvent relative permittivity (e.g. 80) */
+    double ionic_strength_M;/* 1:1 salt, mol/L (e.g. 0.145) */
+    double temperature_K;   /* e.g. 298 */
+    double h;               /* grid spacing, Angstrom */
+    int32_t n[3];           /* nodes per axis, each >= 3 */
+    double origin[3];       /* coordinates of node (0,0,0) */
+    int32_t bc;             /* PB_BC_ZERO | PB_BC_DH | PB_BC_USER */
+    const double* bc_values;/* PB_BC_USER: host array over the full grid; only box-face
+                               entries are read.  Ignored otherwise. */
+    int32_t precision;      /* PB_FP64 or PB_MIXED (FP32 inner CG, FP64 refinement) */
+    double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64 path: CG
+                               recursive residual; mixed: the FP64 true residual) */
+    double inner_rtol;      /* PB_MIXED: relative residual reduction of each inner solve */
+    int32_t max_iter;       /* FP64: CG iterations; mixed: total inner iterations */
+} pb_params;
+
+/* Build the coefficient maps of a problem on the device (paper Sect. 2.1 and 3.1-3.2):
+ * atom cell list, solute/solvent node classification (a node is solute iff strictly
+ * inside an atom ball), edge permittivities with the WHA on cut edges (alpha measured
+ * from the solute end to the first exit from the union of balls), the cut-edge list with
+ * crossing points and sphere normals, marching-cubes area weights, the trilinear load
+ * 4 pi sum q_i w_n(r_i) (eq. RVop_), boundary values and their lift, and the Jacobi
+ * diagonal.
+ *   xyz    : host, 3*n_atoms doubles, atom centres (x0,y0,z0,x1,...)
+ *   radius : host, n_atoms doubles, > 0
+ *   charge : host, n_atoms doubles
+ * Every atom ball must lie strictly inside [origin + h, origin + (n-2) h] on each axis.
+ * On success *out owns all device state of the problem.
+ * Errors: PB_EINVAL (non-finite values, eps <= 0, n < 3, h <= 0, an atom too close to the
+ * box, bad bc/precision, missing bc_values), PB_ENOMEM, PB_EDEVICE. */
+int pb_build_coeffs(pb_ctx* ctx, const pb_params* params, int64_t n_atoms, const double* xyz,
+                    const double* radius, const double* charge, pb_problem** out);
+
+typedef struct {
+    int32_t iters;          /* FP64: CG iterations; mixed: total inner iterations */
+    int32_t outer_iters;    /* mixed: refinement steps (FP64 residual sweeps); FP64: 0 */
+    int32_t status;         /* PB_OK, PB_ENOCONV or PB_EBREAKDOWN */
+    int32_t reserved;
+    double relres;          /* final relative residual (see pb_params.rtol) */
+    double t_solve_s;       /* wall time of pb_solve */
+} pb_solve_stats;
+
+/* Solve A phi = b with Jacobi-preconditioned CG (the paper uses CG, Sect. 4), either in
+ * FP64 throughout or with FP32 inner CG inside FP64 iterative refinement.  The solution
+ * stays on the device.  Returns PB_OK, PB_ENOCONV or PB_EBREAKDOWN (stats filled in all
+ * three cases), or PB_EDEVICE. */
+int pb_solve(pb_problem* pb, pb_solve_stats* stats);
+
+typedef struct {
+    double e_coul;          /* sum_{i<j} q_i q_j /(eps_in r_ij)            (Sect. 3.3) */
+    double e_pol;           /* 1/2 sum_i q_i sum_p q_p / |r_p - r_i|        (Sect. 3.3.1) */
+    double e_ion;           /* eq. energy_ion with MC areas and eq. phi0     (Sect. 3.3.2) */
+    double e_solv;          /* e_pol + e_ion */
+    double e_total;         /* e_coul + e_pol + e_ion */
+    double q_pol_total;     /* sum_p q_p, in e */
+    double area_total;      /* sum of marching-cubes area weights, Angstrom^2 */
+    int64_t n_cut;          /* number of cut edges (= polarization charges) */
+    double t_energy_s;      /* wall time of pb_energy */
+} pb_energy_out;
+
+/* Energy read-back after pb_solve.  phi_reac_per_atom (optional, host, n_atoms doubles)
+ * receives phi_pol + phi_ion at each atom centre in kT/e.  Errors: PB_EINVAL (not
+ * solved), PB_EDEVICE. */
+int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac_per_atom);
+
+/* Copy the potential on the full grid (kT/e, box nodes hold the boundary values) into a
+ * host array of n[0]*n[1]*n[2] doubles. */
+int pb_copy_potential(const pb_problem* pb, double* host_phi);
+
+/* Release all device memory of a problem (waits for its stream). */
+void pb_problem_free(pb_problem* pb);
+
+/* --- inspection (used by the parity tests) ------------------------------------- */
+
+/* Coefficient maps on the full grid (host arrays of n[0]*n[1]*n[2] entries, any may be
+ * NULL): solute flag; edge coefficients K = h*eps_e of the edges to (i+1,j,k),
+ * (i,j+1,k), (i,j,k+1) (0 where the edge leaves the grid); the operator diagonal
+ * (0 on box nodes); the right-hand side including the boundary lift (0 on box nodes). */
+int pb_copy_coeffs(const pb_problem* pb, uint8_t* solute, double* kx, double* ky, double* kz,
+                   double* diag, double* rhs);
+
+/* Number of cut edges of a built problem (or a negative error code). */
+int64_t pb_num_cut(const pb_problem* pb);
+
+/* Cut-edge list in ascending key order, key = 3*((i*n1 + j)*n2 + k) + axis of the edge's
+ * low end (i,j,k).  Host arrays of m = pb_num_cut entries (rp, np: 3*m), any may be NULL.
+ * F (flux K_e (phi_s - phi_w)) and phip (eq. phi0) are valid after pb_energy. */
+int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, double* np,
+                int64_t* owner, double* wp, double* F, double* phip);
+
+/* Average duration in milliseconds of `reps` back-to-back launches of the fused stencil
+ * kernel of the problem's CG (one launch = one operator application plus the
+ * search-direction update and the p.Ap partial sums), FP64 or FP32 (fp32 != 0), timed with
+ * HIP events on the problem's stream.  It overwrites the solver state: call pb_solve again
+ * before pb_energy. */
+int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms);
+
+/* Turn on (1) or off (0) sampled HIP-event timing of the CG kernels: every 8th iteration's
+ * stencil and update launches are bracketed by events on the context stream. */
+int pb_ctx_set_profiling(pb_ctx* ctx, int on);
+
+/* Average durations (ms) of the sampled stencil and update launches of the last pb_solve
+ * (only iterations that did work are counted), and the number of samples. */
+int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples);
+
+/* Bytes of device memory held by a problem. */
+size_t pb_problem_bytes(const pb_problem* pb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PB_H */

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of ``libpb.so`` (the C ABI declared in ``include/pb.h``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.
+PyTorch supplies device memory (its caching allocator, through the library's allocator
+callbacks) and the stream.  Loading fails loudly when the HIP library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpb.so")
+
+PB_OK, PB_EINVAL, PB_ENOMEM, PB_ENOCONV, PB_EBREAKDOWN, PB_EDEVICE = 0, -1, -2, -3, -4, -5
+PB_BC_ZERO, PB_BC_DH, PB_BC_USER = 0, 1, 2
+PB_FP64, PB_MIXED = 0, 1
+
+EXPORTED = [
+    "pb_ctx_create", "pb_ctx_destroy", "pb_last_error", "pb_build_coeffs", "pb_solve", "pb_energy",
+    "pb_copy_potential", "pb_problem_free", "pb_copy_coeffs", "pb_num_cut", "pb_copy_cut",
+    "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes",
+]
+
+
+class PbParams(C.Structure):
+    _fields_ = [
+        ("eps_in", C.c_double), ("eps_out", C.c_double), ("ionic_strength_M", C.c_double),
+        ("temperature_K", C.c_double), ("h", C.c_double), ("n", C.c_int32 * 3),
+        ("origin", C.c_double * 3), ("bc", C.c_int32), ("bc_values", C.c_void_p),
+        ("precision", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
+        ("max_iter", C.c_int32),
+    ]
+
+
+class PbSolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("relres", C.c_double), ("t_solve_s", C.c_double)]
+
+
+class PbEnergyOut(C.Structure):
+    _fields_ = [("e_coul", C.c_double), ("e_pol", C.c_double), ("e_ion", C.c_double),
+                ("e_solv", C.c_double), ("e_total", C.c_double), ("q_pol_total", C.c_double),
+                ("area_total", C.c_double), ("n_cut", C.c_int64), ("t_energy_s", C.c_double)]
+
+
+class PbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpb HIP library not found at {path}; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.pb_ctx_create.argtypes = [C.c_int, P, ALLOC_FN, FREE_FN, P, C.c_size_t, C.POINTER(P)]
+    L.pb_ctx_destroy.argtypes = [P]
+    L.pb_ctx_destroy.restype = None
+    L.pb_last_error.restype = C.c_char_p
+    L.pb_build_coeffs.argtypes = [P, C.POINTER(PbParams), i64, P, P, P, C.POINTER(P)]
+    L.pb_solve.argtypes = [P, C.POINTER(PbSolveStats)]
+    L.pb_energy.argtypes = [P, C.POINTER(PbEnergyOut), P]
+    L.pb_copy_potential.argtypes = [P, P]
+    L.pb_problem_free.argtypes = [P]
+    L.pb_problem_free.restype = None
+    L.pb_copy_coeffs.argtypes = [P, P, P, P, P, P, P]
+    L.pb_num_cut.argtypes = [P]
+    L.pb_num_cut.restype = i64
+    L.pb_copy_cut.argtypes = [P, P, P, P, P, P, P, P, P]
+    L.pb_time_stencil.argtypes = [P, i32, i32, C.POINTER(C.c_double)]
+    L.pb_ctx_set_profiling.argtypes = [P, C.c_int]
+    L.pb_get_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i32)]
+    L.pb_problem_bytes.argtypes = [P]
+    L.pb_problem_bytes.restype = C.c_size_t
+    _lib = L
+    return L
+
+
+def _err(code: int):
+    msg = _lib.pb_last_error()
+    return PbError(code, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """Device, stream and allocator (PyTorch's caching allocator) for problems."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0):
+        import torch
+        L = load()
+        self.device = device
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        dev, strm = device, self.stream
+
+        def _alloc(nbytes, user):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm))
+            except Exception:
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+        h = C.c_void_p()
+        rc = L.pb_ctx_create(device, C.c_void_p(self.stream.cuda_stream), self._cb[0], self._cb[1], None,
+                             int(hbm_budget_bytes), C.byref(h))
+        if rc != PB_OK:
+            raise _err(rc)
+        self.h = h
+
+    def set_profiling(self, on: bool):
+        rc = _lib.pb_ctx_set_profiling(self.h, 1 if on else 0)
+        if rc != PB_OK:
+            raise _err(rc)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pb_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(grid) -> PbParams:
+    p = PbParams()
+    p.eps_in, p.eps_out = float(grid.eps_in), float(grid.eps_out)
+    p.ionic_strength_M, p.temperature_K = float(grid.ionic_M), float(grid.temp_K)
+    p.h = float(grid.h)
+    for d in range(3):
+        p.n[d] = int(grid.n[d])
+        p.origin[d] = float(grid.origin[d])
+    p.bc = int(grid.bc)
+    p.precision = int(grid.precision)
+    p.rtol, p.inner_rtol = float(grid.rtol), float(grid.inner_rtol)
+    p.max_iter = int(grid.max_iter)
+    return p
+
+
+class Problem:
+    """One linearized-PB problem resident on the device."""
+
+    def __init__(self, ctx: Context, mol, grid):
+        L = load()
+        self.ctx = ctx
+        self.grid = grid
+        self.n_atoms = int(mol.n)
+        p = make_params(grid)
+        keep = None
+        if grid.bc == PB_BC_USER:
+            keep = np.ascontiguousarray(grid.bc_values, dtype=np.float64).reshape(-1)
+            p.bc_values = keep.ctypes.data_as(C.c_void_p)
+        xyz = np.ascontiguousarray(mol.xyz, dtype=np.float64).reshape(-1)
+        rad = np.ascontiguousarray(mol.radius, dtype=np.float64)
+        chg = np.ascontiguousarray(mol.charge, dtype=np.float64)
+        h = C.c_void_p()
+        rc = L.pb_build_coeffs(ctx.h, C.byref(p), self.n_atoms, _ptr(xyz), _ptr(rad), _ptr(chg), C.byref(h))
+        if rc != PB_OK:
+            raise _err(rc)
+        self.h = h
+
+    @property
+    def shape(self):
+        return tuple(int(v) for v in self.grid.n)
+
+    def solve(self) -> dict:
+        st = PbSolveStats()
+        rc = _lib.pb_solve(self.h, C.byref(st))
+        if rc not in (PB_OK, PB_ENOCONV, PB_EBREAKDOWN):
+            raise _err(rc)
+        return dict(iters=st.iters, outer_iters=st.outer_iters, status=st.status, relres=st.relres,
+                    t_solve_s=st.t_solve_s)
+
+    def energy(self, per_atom: bool = False) -> dict:
+        out = PbEnergyOut()
+        pa = np.zeros(max(self.n_atoms, 1)) if per_atom else None
+        rc = _lib.pb_energy(self.h, C.byref(out), _ptr(pa))
+        if rc != PB_OK:
+            raise _err(rc)
+        d = {k: getattr(out, k) for k, _ in PbEnergyOut._fields_}
+        if per_atom:
+            d["phi_reac"] = pa[: self.n_atoms]
+        return d
+
+    def potential(self) -> np.ndarray:
+        phi = np.zeros(self.shape)
+        rc = _lib.pb_copy_potential(self.h, _ptr(phi))
+        if rc != PB_OK:
+            raise _err(rc)
+        return phi
+
+    def coeffs(self) -> dict:
+        sh = self.shape
+        sol = np.zeros(sh, np.uint8)
+        arrs = {k: np.zeros(sh) for k in ("kx", "ky", "kz", "diag", "rhs")}
+        rc = _lib.pb_copy_coeffs(self.h, _ptr(sol), *(_ptr(arrs[k]) for k in ("kx", "ky", "kz", "diag", "rhs")))
+        if rc != PB_OK:
+            raise _err(rc)
+        arrs["solute"] = sol
+        return arrs
+
+    def num_cut(self) -> int:
+        return int(_lib.pb_num_cut(self.h))
+
+    def cut(self, fields: bool = False) -> dict:
+        m = self.num_cut()
+        d = dict(key=np.zeros(m, np.int64), alpha=np.zeros(m), rp=np.zeros((m, 3)), np=np.zeros((m, 3)),
+                 owner=np.zeros(m, np.int64), wp=np.zeros(m))
+        if fields:
+            d["F"] = np.zeros(m)
+            d["phip"] = np.zeros(m)
+        rc = _lib.pb_copy_cut(self.h, _ptr(d["key"]), _ptr(d["alpha"]), _ptr(d["rp"]), _ptr(d["np"]),
+                              _ptr(d["owner"]), _ptr(d["wp"]), _ptr(d.get("F")), _ptr(d.get("phip")))
+        if rc != PB_OK:
+            raise _err(rc)
+        return d
+
+    def time_stencil(self, reps: int = 20, fp32: bool = False) -> float:
+        ms = C.c_double()
+        rc = _lib.pb_time_stencil(self.h, int(reps), 1 if fp32 else 0, C.byref(ms))
+        if rc != PB_OK:
+            raise _err(rc)
+        return float(ms.value)
+
+    def profile(self) -> dict:
+        a, b, n = C.c_double(), C.c_double(), C.c_int32()
+        rc = _lib.pb_get_profile(self.h, C.byref(a), C.byref(b), C.byref(n))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(stencil_ms=a.value, update_ms=b.value, samples=n.value)
+
+    def nbytes(self) -> int:
+        return int(_lib.pb_problem_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pb_problem_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(mol, grid, ctx: Context | None = None, per_atom: bool = False) -> dict:
+    """Build, solve and read back the energy of one problem."""
+    own = ctx is None
+    ctx = ctx or Context()
+    pb = Problem(ctx, mol, grid)
+    try:
+        st = pb.solve()
+        en = pb.energy(per_atom=per_atom)
+        en.update(st)
+        return en
+    finally:
+        pb.close()
+        if own:
+            ctx.close()

@@ -1,0 +1,888 @@
+// pb_api.hip -- the C ABI of libpb: validation, device memory through the caller's
+// allocator, and the order of kernel launches for build, solve and energy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pb_internal.h"
+
+using namespace pbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(PB_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// physical constants (CODATA 2018) -> Bjerrum length (Angstrom) and kD^2 (1/Angstrom^2)
+void reduced_constants(double T, double I, double eps_out, double* lB, double* kD2)
+{
+    const double e = 1.602176634e-19, kB = 1.380649e-23, NA = 6.02214076e23, eps0 = 8.8541878128e-12;
+    const double pi = 3.14159265358979323846;
+    const double lb_m = e * e / (4.0 * pi * eps0 * kB * T);
+    *lB = lb_m * 1e10;
+    // 1:1 salt: kD^2 = e^2 sum z^2 rho /(eps0 eps_out kB T) = 8 pi lB I NA 1e3 / eps_out  [1/m^2]
+    *kD2 = 8.0 * pi * lb_m * I * NA * 1e3 / eps_out * 1e-20;
+}
+
+}  // namespace
+
+struct pb_ctx {
+    int device;
+    hipStream_t stream;
+    pb_alloc_fn alloc;
+    pb_free_fn free_fn;
+    void* user;
+    size_t budget;
+    int profile;
+    CGState* host_state;  // pinned, 2 slots for pipelined polling
+    hipEvent_t ev[2];
+};
+
+struct DevAlloc {
+    pb_ctx* ctx;
+    std::vector<std::pair<void*, size_t>> held;
+    size_t bytes = 0;
+    void* get(size_t n)
+    {
+        n = (n + 255) & ~(size_t)255;
+        if (n == 0) n = 256;
+        void* p = ctx->alloc(n, ctx->user);
+        if (p) {
+            held.emplace_back(p, n);
+            bytes += n;
+        }
+        return p;
+    }
+    void put(void* p)
+    {
+        for (size_t i = 0; i < held.size(); ++i)
+            if (held[i].first == p) {
+                bytes -= held[i].second;
+                ctx->free_fn(p, ctx->user);
+                held.erase(held.begin() + (long)i);
+                return;
+            }
+    }
+    void release()
+    {
+        for (auto& h : held) ctx->free_fn(h.first, ctx->user);
+        held.clear();
+        bytes = 0;
+    }
+};
+
+struct pb_problem {
+    pb_ctx* ctx;
+    pb_params prm;
+    int64_t na;
+    Grid g;
+    TileShape ts;
+    Coef cf;
+    double lB, kD;
+    DevAlloc mem;
+    // inputs
+    double* xyzr = nullptr;
+    double* q = nullptr;
+    // coefficient maps
+    uint32_t* code = nullptr;
+    float* dinv = nullptr;
+    double* ck64 = nullptr;
+    float* ck32 = nullptr;
+    int* cutbase = nullptr;
+    double* rhs = nullptr;
+    double* gb = nullptr;
+    double* x = nullptr;
+    int64_t ncut = 0, nslot = 0;
+    int64_t* cutkey = nullptr;
+    double *alpha = nullptr, *kcut = nullptr, *rp = nullptr, *np = nullptr, *wp = nullptr;
+    int* owner = nullptr;
+    double *F = nullptr, *phip = nullptr, *pts = nullptr;
+    // CG work
+    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr;
+    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *res32 = nullptr;
+    double *part1 = nullptr, *part2 = nullptr, *part_res = nullptr, *scal = nullptr;
+    CGState* st = nullptr;
+    int nb1 = 0, nb2 = 0, nbres = 0;
+    bool solved = false;
+    // sampled kernel timings of the last solve
+    double prof_stencil_ms = 0, prof_update_ms = 0;
+    int prof_n = 0;
+};
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const pb_params* p, int64_t na, const double* xyz, const double* rad, const double* chg)
+{
+    if (!p) return fail(PB_EINVAL, "params is NULL");
+    if (!finite(p->eps_in) || !finite(p->eps_out) || p->eps_in <= 0 || p->eps_out <= 0)
+        return fail(PB_EINVAL, "permittivities must be finite and > 0");
+    if (!finite(p->ionic_strength_M) || p->ionic_strength_M < 0)
+        return fail(PB_EINVAL, "ionic strength must be finite and >= 0");
+    if (!finite(p->temperature_K) || p->temperature_K <= 0) return fail(PB_EINVAL, "temperature must be > 0");
+    if (!finite(p->h) || p->h <= 0) return fail(PB_EINVAL, "grid spacing must be finite and > 0");
+    for (int d = 0; d < 3; ++d) {
+        if (p->n[d] < 3) return fail(PB_EINVAL, "n[%d] = %d < 3", d, p->n[d]);
+        if (p->n[d] > 4096) return fail(PB_EINVAL, "n[%d] = %d > 4096", d, p->n[d]);
+        if (!finite(p->origin[d])) return fail(PB_EINVAL, "origin must be finite");
+    }
+    if (p->bc != PB_BC_ZERO && p->bc != PB_BC_DH && p->bc != PB_BC_USER) return fail(PB_EINVAL, "bad bc");
+    if (p->bc == PB_BC_USER && !p->bc_values) return fail(PB_EINVAL, "PB_BC_USER needs bc_values");
+    if (p->precision != PB_FP64 && p->precision != PB_MIXED) return fail(PB_EINVAL, "bad precision");
+    if (!finite(p->rtol) || p->rtol <= 0 || p->rtol >= 1) return fail(PB_EINVAL, "rtol must be in (0, 1)");
+    if (p->precision == PB_MIXED && (!finite(p->inner_rtol) || p->inner_rtol <= 0 || p->inner_rtol >= 1))
+        return fail(PB_EINVAL, "inner_rtol must be in (0, 1)");
+    if (p->max_iter <= 0) return fail(PB_EINVAL, "max_iter must be > 0");
+    if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
+    if (na > 0 && (!xyz || !rad || !chg)) return fail(PB_EINVAL, "atom arrays are NULL");
+    for (int64_t a = 0; a < na; ++a) {
+        if (!finite(rad[a]) || rad[a] <= 0 || !finite(chg[a])) return fail(PB_EINVAL, "atom %lld: bad radius/charge", (long long)a);
+        for (int d = 0; d < 3; ++d) {
+            double c = xyz[3 * a + d];
+            if (!finite(c)) return fail(PB_EINVAL, "atom %lld: non-finite coordinate", (long long)a);
+            double lo = p->origin[d] + p->h, hi = p->origin[d] + p->h * (double)(p->n[d] - 2);
+            if (!(c - rad[a] > lo && c + rad[a] < hi))
+                return fail(PB_EINVAL, "atom %lld: ball not strictly inside the box interior on axis %d",
+                            (long long)a, d);
+        }
+    }
+    return PB_OK;
+}
+
+template <typename T>
+T* dalloc(pb_problem* pb, size_t count, int* rc)
+{
+    void* p = pb->mem.get(sizeof(T) * count);
+    if (!p) *rc = fail(PB_ENOMEM, "device allocation of %zu bytes failed", sizeof(T) * count);
+    return (T*)p;
+}
+
+// Pipelined CG: launch chunks of iterations, poll the device state of the previous chunk.
+template <typename T>
+int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGState* out)
+{
+    pb_ctx* ctx = pb->ctx;
+    hipStream_t s = ctx->stream;
+    const int M = 16;
+    int launched = 0, c = 0;
+    const bool prof = ctx->profile != 0;
+    std::vector<hipEvent_t> evs;
+    std::vector<int> ev_it;
+    auto enqueue = [&](int slot) -> int {
+        int n = std::min(M, max_iter - launched);
+        for (int t = 0; t < n; ++t) {
+            const int it = launched + t;
+            const int par = it & 1;
+            const bool sample = prof && (it % 8 == 0) && evs.size() < 3 * 256;
+            hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+            if (sample) {
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                HIPCHK(hipEventCreate(&e2));
+                HIPCHK(hipEventRecord(e0, s));
+            }
+            HIPCHK(launch_cg_stencil<T>(s, pb->g, pb->ts, B, pb->cf, par, tol2));
+            if (sample) HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(launch_cg_update<T>(s, pb->g, B, par));
+            if (sample) {
+                HIPCHK(hipEventRecord(e2, s));
+                evs.push_back(e0);
+                evs.push_back(e1);
+                evs.push_back(e2);
+                ev_it.push_back(it);
+            }
+        }
+        launched += n;
+        HIPCHK(hipMemcpyAsync(&ctx->host_state[slot], B.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev[slot], s));
+        return PB_OK;
+    };
+    int rc = enqueue(0);
+    if (rc) return rc;
+    for (;;) {
+        const bool more = launched < max_iter;
+        if (more && (rc = enqueue((c + 1) & 1))) return rc;
+        HIPCHK(hipEventSynchronize(ctx->ev[c & 1]));
+        const CGState snap = ctx->host_state[c & 1];
+        if (snap.status != 0 || !more) break;
+        ++c;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(out, B.st, sizeof(CGState), hipMemcpyDeviceToHost));
+    if (prof) {
+        const int done = out->status == 1 ? out->iters : out->iter_count;
+        double ts = 0, tu = 0;
+        int n = 0;
+        for (size_t k = 0; k < ev_it.size(); ++k) {
+            if (ev_it[k] < done) {
+                float a = 0, b = 0;
+                HIPCHK(hipEventElapsedTime(&a, evs[3 * k], evs[3 * k + 1]));
+                HIPCHK(hipEventElapsedTime(&b, evs[3 * k + 1], evs[3 * k + 2]));
+                ts += a;
+                tu += b;
+                ++n;
+            }
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
+        pb->prof_stencil_ms += ts;
+        pb->prof_update_ms += tu;
+        pb->prof_n += n;
+    }
+    return PB_OK;
+}
+
+int ensure_cg64(pb_problem* pb)
+{
+    int rc = PB_OK;
+    if (pb->r) return PB_OK;
+    const size_t N = (size_t)pb->g.N;
+    pb->r = dalloc<double>(pb, N, &rc);
+    if (!rc) pb->p0 = dalloc<double>(pb, N, &rc);
+    if (!rc) pb->p1 = dalloc<double>(pb, N, &rc);
+    if (!rc) pb->qv = dalloc<double>(pb, N, &rc);
+    return rc;
+}
+
+int ensure_cg32(pb_problem* pb)
+{
+    int rc = PB_OK;
+    if (pb->d32) return PB_OK;
+    const size_t N = (size_t)pb->g.N;
+    pb->d32 = dalloc<float>(pb, N, &rc);
+    if (!rc) pb->r32 = dalloc<float>(pb, N, &rc);
+    if (!rc) pb->p32a = dalloc<float>(pb, N, &rc);
+    if (!rc) pb->p32b = dalloc<float>(pb, N, &rc);
+    if (!rc) pb->q32 = dalloc<float>(pb, N, &rc);
+    if (!rc) pb->res32 = dalloc<float>(pb, N, &rc);
+    return rc;
+}
+
+template <typename T>
+CGBufs<T> bufs(pb_problem* pb);
+
+template <>
+CGBufs<double> bufs<double>(pb_problem* pb)
+{
+    CGBufs<double> B;
+    B.x = pb->x;
+    B.r = pb->r;
+    B.p[0] = pb->p0;
+    B.p[1] = pb->p1;
+    B.q = pb->qv;
+    B.ck = pb->ck64;
+    B.dinv = pb->dinv;
+    B.code = pb->code;
+    B.part1 = pb->part1;
+    B.part2 = pb->part2;
+    B.st = pb->st;
+    B.nb1 = pb->nb1;
+    B.nb2 = pb->nb2;
+    return B;
+}
+
+template <>
+CGBufs<float> bufs<float>(pb_problem* pb)
+{
+    CGBufs<float> B;
+    B.x = pb->d32;
+    B.r = pb->r32;
+    B.p[0] = pb->p32a;
+    B.p[1] = pb->p32b;
+    B.q = pb->q32;
+    B.ck = pb->ck32;
+    B.dinv = pb->dinv;
+    B.code = pb->code;
+    B.part1 = pb->part1;
+    B.part2 = pb->part2;
+    B.st = pb->st;
+    B.nb1 = pb->nb1;
+    B.nb2 = pb->nb2;
+    return B;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pb_last_error(void) { return g_err.c_str(); }
+
+int pb_ctx_create(int device, void* hip_stream, pb_alloc_fn alloc, pb_free_fn free_fn, void* user,
+                  size_t hbm_budget_bytes, pb_ctx** out)
+{
+    if (!out) return fail(PB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!alloc || !free_fn) return fail(PB_EINVAL, "allocator callbacks are required");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(PB_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    pb_ctx* c = new pb_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    c->budget = hbm_budget_bytes;
+    c->profile = 0;
+    if (hipHostMalloc((void**)&c->host_state, 2 * sizeof(CGState), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(PB_EDEVICE, "hipHostMalloc failed");
+    }
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            return fail(PB_EDEVICE, "hipEventCreate failed");
+        }
+    *out = c;
+    return PB_OK;
+}
+
+void pb_ctx_destroy(pb_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k) (void)hipEventDestroy(c->ev[k]);
+    (void)hipHostFree(c->host_state);
+    delete c;
+}
+
+int pb_ctx_set_profiling(pb_ctx* c, int on)
+{
+    if (!c) return fail(PB_EINVAL, "ctx is NULL");
+    c->profile = on;
+    return PB_OK;
+}
+
+int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                    const double* chg, pb_problem** out)
+{
+    if (!ctx || !out) return fail(PB_EINVAL, "ctx/out is NULL");
+    *out = nullptr;
+    int rc = validate(prm, na, xyz, rad, chg);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+
+    pb_problem* pb = new pb_problem();
+    pb->ctx = ctx;
+    pb->prm = *prm;
+    pb->prm.bc_values = nullptr;
+    pb->na = na;
+    pb->mem.ctx = ctx;
+    Grid& g = pb->g;
+    g.nx = prm->n[0];
+    g.ny = prm->n[1];
+    g.nz = prm->n[2];
+    g.S = ((g.nz + Z0) + 7) / 8 * 8;
+    g.N = (int64_t)g.nx * g.ny * g.S;
+    g.h = prm->h;
+    g.ox = prm->origin[0];
+    g.oy = prm->origin[1];
+    g.oz = prm->origin[2];
+    pb->ts = make_tiles(g);
+    double kd2 = 0;
+    reduced_constants(prm->temperature_K, prm->ionic_strength_M, prm->eps_out, &pb->lB, &kd2);
+    pb->kD = std::sqrt(kd2);
+    pb->cf.kin = prm->h * prm->eps_in;
+    pb->cf.kout = prm->h * prm->eps_out;
+    pb->cf.mass = prm->h * prm->h * prm->h * prm->eps_out * kd2;
+
+    auto bail = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        pb->mem.release();
+        delete pb;
+        return code;
+    };
+#define CK(expr)                    \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_) return bail(rc_);  \
+    } while (0)
+#define HK(expr)                                                                              \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bail(fail(PB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
+    } while (0)
+
+    const size_t N = (size_t)g.N;
+    const size_t na1 = (size_t)std::max<int64_t>(na, 1);
+    pb->xyzr = dalloc<double>(pb, 4 * na1, &rc);
+    CK(rc);
+    pb->q = dalloc<double>(pb, na1, &rc);
+    CK(rc);
+    // host staging of the atoms (x, y, z, R) and the bin geometry
+    std::vector<double> hx(4 * na1, 0.0), hq(na1, 0.0);
+    double rmax = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int64_t a = 0; a < na; ++a) {
+        for (int d = 0; d < 3; ++d) {
+            hx[4 * a + d] = xyz[3 * a + d];
+            lo[d] = a ? std::min(lo[d], xyz[3 * a + d]) : xyz[3 * a + d];
+            hi[d] = a ? std::max(hi[d], xyz[3 * a + d]) : xyz[3 * a + d];
+        }
+        hx[4 * a + 3] = rad[a];
+        hq[a] = chg[a];
+        rmax = std::max(rmax, rad[a]);
+    }
+    HK(hipMemcpyAsync(pb->xyzr, hx.data(), sizeof(double) * 4 * na1, hipMemcpyHostToDevice, s));
+    HK(hipMemcpyAsync(pb->q, hq.data(), sizeof(double) * na1, hipMemcpyHostToDevice, s));
+    Atoms at{(int)na, pb->xyzr, pb->q};
+
+    // bins of edge >= R_max + h (and >= 2h) so that the 27 bins around a node or an edge end
+    // hold every atom whose ball can touch it
+    Bins bn;
+    bn.bs = std::max(rmax + prm->h, 2.0 * prm->h);
+    bn.lox = lo[0] - bn.bs;
+    bn.loy = lo[1] - bn.bs;
+    bn.loz = lo[2] - bn.bs;
+    bn.nbx = (int)std::floor((hi[0] - bn.lox) / bn.bs) + 2;
+    bn.nby = (int)std::floor((hi[1] - bn.loy) / bn.bs) + 2;
+    bn.nbz = (int)std::floor((hi[2] - bn.loz) / bn.bs) + 2;
+    const int nbins = bn.nbx * bn.nby * bn.nbz;
+    int* bcnt = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    CK(rc);
+    int* bstart = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    CK(rc);
+    int* bcur = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    CK(rc);
+    int* bids = dalloc<int>(pb, na1, &rc);
+    CK(rc);
+    if (na > 0) {
+        HK(launch_bins(s, at, bn, bcnt, bstart, bids, bcur));
+    } else {
+        HK(launch_fill(s, bstart, sizeof(int) * ((size_t)nbins + 1)));
+        bn.start = bstart;
+        bn.ids = bids;
+    }
+
+    // classification and ordered compaction of the cut edges
+    uint32_t* cls = dalloc<uint32_t>(pb, N, &rc);
+    CK(rc);
+    HK(launch_classify(s, g, bn, at, cls));
+    const int nblk = (int)((N + 255) / 256);
+    int* bslots = dalloc<int>(pb, (size_t)nblk + 1, &rc);
+    CK(rc);
+    int* bcuts = dalloc<int>(pb, (size_t)nblk + 1, &rc);
+    CK(rc);
+    int* tot = dalloc<int>(pb, 2, &rc);
+    CK(rc);
+    HK(launch_cutflags(s, g, cls, bslots, bcuts, nblk));
+    HK(launch_scan2(s, bslots, bcuts, nblk, tot));
+    int htot[2] = {0, 0};
+    HK(hipMemcpyAsync(htot, tot, sizeof htot, hipMemcpyDeviceToHost, s));
+    HK(hipStreamSynchronize(s));
+    pb->nslot = htot[0];
+    pb->ncut = htot[1];
+    const size_t ns1 = (size_t)std::max<int64_t>(pb->nslot, 1), nc1 = (size_t)std::max<int64_t>(pb->ncut, 1);
+
+    pb->code = dalloc<uint32_t>(pb, N, &rc);
+    CK(rc);
+    pb->cutbase = dalloc<int>(pb, ns1, &rc);
+    CK(rc);
+    pb->cutkey = dalloc<int64_t>(pb, nc1, &rc);
+    CK(rc);
+    HK(launch_assign(s, g, cls, pb->code, bslots, bcuts, pb->cutbase, pb->cutkey));
+    pb->ck64 = dalloc<double>(pb, 3 * ns1, &rc);
+    CK(rc);
+    pb->ck32 = dalloc<float>(pb, 3 * ns1, &rc);
+    CK(rc);
+    HK(launch_fill(s, pb->ck64, sizeof(double) * 3 * ns1));
+    HK(launch_fill(s, pb->ck32, sizeof(float) * 3 * ns1));
+    pb->alpha = dalloc<double>(pb, nc1, &rc);
+    CK(rc);
+    pb->kcut = dalloc<double>(pb, nc1, &rc);
+    CK(rc);
+    pb->rp = dalloc<double>(pb, 3 * nc1, &rc);
+    CK(rc);
+    pb->np = dalloc<double>(pb, 3 * nc1, &rc);
+    CK(rc);
+    pb->owner = dalloc<int>(pb, nc1, &rc);
+    CK(rc);
+    pb->wp = dalloc<double>(pb, nc1, &rc);
+    CK(rc);
+    HK(launch_cut_geom(s, g, bn, at, prm->eps_in, prm->eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
+                       pb->kcut, pb->rp, pb->np, pb->owner, pb->ck64, pb->ck32));
+
+    // load vector, boundary values, diagonal and lift
+    pb->rhs = dalloc<double>(pb, N, &rc);
+    CK(rc);
+    pb->gb = dalloc<double>(pb, N, &rc);
+    CK(rc);
+    pb->dinv = dalloc<float>(pb, N, &rc);
+    CK(rc);
+    pb->x = dalloc<double>(pb, N, &rc);
+    CK(rc);
+    HK(launch_deposit(s, g, bn, at, pb->rhs));
+    HK(launch_fill(s, pb->gb, sizeof(double) * N));
+    HK(launch_fill(s, pb->x, sizeof(double) * N));
+    if (prm->bc == PB_BC_DH && na > 0) {
+        HK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
+    } else if (prm->bc == PB_BC_USER) {
+        const size_t nfull = (size_t)g.nx * g.ny * g.nz;
+        double* full = dalloc<double>(pb, nfull, &rc);
+        CK(rc);
+        HK(hipMemcpyAsync(full, prm->bc_values, sizeof(double) * nfull, hipMemcpyHostToDevice, s));
+        HK(launch_bc_user(s, g, full, pb->gb));
+        HK(hipStreamSynchronize(s));
+        pb->mem.put(full);
+    }
+    HK(launch_diag_lift(s, g, pb->code, pb->ck64, pb->cf, pb->gb, pb->rhs, pb->dinv, nullptr));
+    HK(launch_mc_weights(s, g, pb->code, pb->cutbase, pb->ncut, pb->cutkey, pb->rp, pb->wp));
+
+    // solver scalars and partial sums
+    pb->nb1 = pb->ts.items;
+    pb->nb2 = update_blocks(g);
+    pb->nbres = (int)((N + 255) / 256);
+    pb->part1 = dalloc<double>(pb, (size_t)pb->nb1, &rc);
+    CK(rc);
+    pb->part2 = dalloc<double>(pb, 2 * (size_t)pb->nb2, &rc);
+    CK(rc);
+    pb->part_res = dalloc<double>(pb, (size_t)pb->nbres, &rc);
+    CK(rc);
+    pb->scal = dalloc<double>(pb, 8, &rc);
+    CK(rc);
+    pb->st = dalloc<CGState>(pb, 1, &rc);
+    CK(rc);
+    HK(hipStreamSynchronize(s));
+    // temporaries
+    for (void* t : {(void*)bcnt, (void*)bstart, (void*)bcur, (void*)bids, (void*)cls, (void*)bslots,
+                    (void*)bcuts, (void*)tot})
+        pb->mem.put(t);
+#undef CK
+#undef HK
+    *out = pb;
+    return PB_OK;
+}
+
+int pb_solve(pb_problem* pb, pb_solve_stats* stats)
+{
+    if (!pb || !stats) return fail(PB_EINVAL, "NULL argument");
+    memset(stats, 0, sizeof *stats);
+    pb_ctx* ctx = pb->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const double t0 = now_s();
+    pb->solved = false;
+    pb->prof_stencil_ms = pb->prof_update_ms = 0;
+    pb->prof_n = 0;
+    int rc = ensure_cg64(pb);
+    if (rc) return rc;
+    const pb_params& P = pb->prm;
+    int status = PB_OK;
+    if (P.precision == PB_FP64) {
+        CGBufs<double> B = bufs<double>(pb);
+        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, B, pb->part2, pb->nb2, pb->st));
+        CGState st;
+        rc = run_cg<double>(pb, B, P.rtol * P.rtol, P.max_iter, &st);
+        if (rc) return rc;
+        stats->iters = st.status == 1 ? st.iters : st.iter_count;
+        stats->relres = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
+        status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
+    } else {
+        if ((rc = ensure_cg32(pb))) return rc;
+        HIPCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
+        CGBufs<float> B = bufs<float>(pb);
+        // ||b||^2 through the FP64 residual with x = 0
+        HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
+                                 pb->part_res, pb->nbres));
+        HIPCHK(launch_reduce_to(s, pb->part_res, pb->nbres, pb->scal));
+        double bn2 = 0;
+        HIPCHK(hipMemcpyAsync(&bn2, pb->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double rr = bn2;
+        int inner_total = 0, outer = 0;
+        status = PB_ENOCONV;
+        const double tol2 = P.rtol * P.rtol * bn2;
+        for (;;) {
+            if (rr <= tol2) {
+                status = PB_OK;
+                break;
+            }
+            if (inner_total >= P.max_iter || outer >= 200) break;
+            HIPCHK(launch_cg_init<float>(s, pb->g, B, nullptr, pb->res32));
+            CGBufs<double> dummy{};
+            HIPCHK(launch_cg_fin(s, dummy, pb->part2, pb->nb2, pb->st));
+            CGState st;
+            const double itol = P.inner_rtol;
+            rc = run_cg<float>(pb, B, itol * itol, P.max_iter - inner_total, &st);
+            if (rc) return rc;
+            inner_total += st.status == 1 ? st.iters : st.iter_count;
+            if (st.status == 2) {
+                status = PB_EBREAKDOWN;
+                break;
+            }
+            HIPCHK(launch_add_correction(s, pb->g, pb->x, pb->d32));
+            ++outer;
+            HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
+                                     pb->part_res, pb->nbres));
+            HIPCHK(launch_reduce_to(s, pb->part_res, pb->nbres, pb->scal));
+            HIPCHK(hipMemcpyAsync(&rr, pb->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!std::isfinite(rr)) {
+                status = PB_EBREAKDOWN;
+                break;
+            }
+        }
+        stats->iters = inner_total;
+        stats->outer_iters = outer;
+        stats->relres = bn2 > 0 ? std::sqrt(rr / bn2) : 0.0;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    stats->status = status;
+    stats->t_solve_s = now_s() - t0;
+    pb->solved = status == PB_OK || status == PB_ENOCONV;
+    return status;
+}
+
+int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples)
+{
+    if (!pb) return fail(PB_EINVAL, "NULL problem");
+    const int n = pb->prof_n;
+    if (stencil_ms_avg) *stencil_ms_avg = n ? pb->prof_stencil_ms / n : 0.0;
+    if (update_ms_avg) *update_ms_avg = n ? pb->prof_update_ms / n : 0.0;
+    if (samples) *samples = n;
+    return PB_OK;
+}
+
+int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac)
+{
+    if (!pb || !out) return fail(PB_EINVAL, "NULL argument");
+    if (!pb->solved) return fail(PB_EINVAL, "pb_energy before a successful pb_solve");
+    memset(out, 0, sizeof *out);
+    pb_ctx* ctx = pb->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const double t0 = now_s();
+    int rc = PB_OK;
+    const size_t nc1 = (size_t)std::max<int64_t>(pb->ncut, 1), na1 = (size_t)std::max<int64_t>(pb->na, 1);
+    if (!pb->F) {
+        pb->F = dalloc<double>(pb, nc1, &rc);
+        if (rc) return rc;
+        pb->phip = dalloc<double>(pb, nc1, &rc);
+        if (rc) return rc;
+        pb->pts = dalloc<double>(pb, 8 * nc1, &rc);
+        if (rc) return rc;
+    }
+    Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    const int nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
+    double* partial = dalloc<double>(pb, 2 * na1 * (size_t)nchunk, &rc);
+    if (rc) return rc;
+    double* phic = dalloc<double>(pb, na1, &rc);
+    double* preac = rc ? nullptr : dalloc<double>(pb, na1, &rc);
+    double* dout = rc ? nullptr : dalloc<double>(pb, 8, &rc);
+    auto cleanup = [&]() {
+        for (void* t : {(void*)partial, (void*)phic, (void*)preac, (void*)dout})
+            if (t) pb->mem.put(t);
+    };
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    double h[8] = {0};
+    hipError_t e = launch_edge_fields(s, pb->g, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code,
+                                      pb->alpha, pb->kcut, pb->x, pb->gb, pb->wp, pb->F, pb->phip, pb->pts, pb->rp,
+                                      pb->np);
+    if (e == hipSuccess && pb->na > 0) {
+        if (pb->ncut > 0)
+            e = launch_nbody(s, at, pb->ncut, pb->pts, partial, nchunk);
+        else
+            e = launch_fill(s, partial, sizeof(double) * 2 * na1 * (size_t)nchunk);
+    }
+    if (e == hipSuccess && pb->na > 0) e = launch_coulomb(s, at, phic);
+    if (e == hipSuccess && pb->na > 0)
+        e = launch_energy_reduce(s, at, partial, nchunk, phic, pb->prm.eps_in, pb->prm.eps_out, pb->lB, preac, dout,
+                                 pb->F, pb->ncut, pb->wp);
+    if (e == hipSuccess && pb->na > 0) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && phi_reac && pb->na > 0)
+        e = hipMemcpyAsync(phi_reac, preac, sizeof(double) * (size_t)pb->na, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(PB_EDEVICE, "energy kernels failed: %s", hipGetErrorString(e));
+    out->e_coul = h[0];
+    out->e_pol = h[1];
+    out->e_ion = h[2];
+    out->e_solv = h[1] + h[2];
+    out->e_total = h[0] + h[1] + h[2];
+    out->q_pol_total = h[3];
+    out->area_total = h[4];
+    out->n_cut = pb->ncut;
+    out->t_energy_s = now_s() - t0;
+    return PB_OK;
+}
+
+int pb_copy_potential(const pb_problem* pb, double* host_phi)
+{
+    if (!pb || !host_phi) return fail(PB_EINVAL, "NULL argument");
+    pb_problem* p = const_cast<pb_problem*>(pb);
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    const size_t n = (size_t)pb->g.nx * pb->g.ny * pb->g.nz;
+    int rc = PB_OK;
+    double* tmp = dalloc<double>(p, n, &rc);
+    if (rc) return rc;
+    hipError_t e = launch_export_phi(s, pb->g, pb->x, pb->gb, pb->lB, tmp);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_phi, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    p->mem.put(tmp);
+    if (e != hipSuccess) return fail(PB_EDEVICE, "export failed: %s", hipGetErrorString(e));
+    return PB_OK;
+}
+
+int pb_copy_coeffs(const pb_problem* pb, uint8_t* sol, double* kx, double* ky, double* kz, double* diag,
+                   double* rhs)
+{
+    if (!pb) return fail(PB_EINVAL, "NULL problem");
+    pb_problem* p = const_cast<pb_problem*>(pb);
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    const size_t n = (size_t)pb->g.nx * pb->g.ny * pb->g.nz;
+    int rc = PB_OK;
+    uint8_t* dsol = dalloc<uint8_t>(p, n, &rc);
+    double* dk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double* hk[5] = {kx, ky, kz, diag, rhs};
+    for (int t = 0; t < 5 && !rc; ++t)
+        if (hk[t]) dk[t] = dalloc<double>(p, n, &rc);
+    hipError_t e = hipSuccess;
+    if (!rc) {
+        e = launch_export_coeffs(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, dsol, dk[0], dk[1], dk[2], dk[3],
+                                 dk[4]);
+        if (e == hipSuccess && sol) e = hipMemcpyAsync(sol, dsol, n, hipMemcpyDeviceToHost, s);
+        for (int t = 0; t < 5 && e == hipSuccess; ++t)
+            if (hk[t]) e = hipMemcpyAsync(hk[t], dk[t], sizeof(double) * n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (dsol) p->mem.put(dsol);
+    for (int t = 0; t < 5; ++t)
+        if (dk[t]) p->mem.put(dk[t]);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(PB_EDEVICE, "export failed: %s", hipGetErrorString(e));
+    return PB_OK;
+}
+
+int64_t pb_num_cut(const pb_problem* pb)
+{
+    if (!pb) return fail(PB_EINVAL, "NULL problem");
+    return pb->ncut;
+}
+
+int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, double* np, int64_t* owner,
+                double* wp, double* F, double* phip)
+{
+    if (!pb) return fail(PB_EINVAL, "NULL problem");
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    const size_t m = (size_t)pb->ncut;
+    if (m == 0) return PB_OK;
+    if ((F || phip) && !pb->F) return fail(PB_EINVAL, "F/phip requested before pb_energy");
+    std::vector<int64_t> sk(m);
+    std::vector<int> ow(m);
+    HIPCHK(hipMemcpyAsync(sk.data(), pb->cutkey, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ow.data(), pb->owner, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    if (alpha) HIPCHK(hipMemcpyAsync(alpha, pb->alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    if (rp) HIPCHK(hipMemcpyAsync(rp, pb->rp, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
+    if (np) HIPCHK(hipMemcpyAsync(np, pb->np, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
+    if (wp) HIPCHK(hipMemcpyAsync(wp, pb->wp, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    if (F) HIPCHK(hipMemcpyAsync(F, pb->F, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    if (phip) HIPCHK(hipMemcpyAsync(phip, pb->phip, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Grid& g = pb->g;
+    for (size_t c = 0; c < m; ++c) {
+        // storage element -> (i, j, k) -> unpadded key
+        const int64_t e = sk[c] >> 2;
+        const int ax = (int)(sk[c] & 3);
+        const int64_t row = e / g.S;
+        const int64_t k = e - row * g.S - Z0;
+        const int64_t j = row % g.ny, i = row / g.ny;
+        if (key) key[c] = 3 * ((i * g.ny + j) * g.nz + k) + ax;
+        if (owner) owner[c] = ow[c];
+    }
+    return PB_OK;
+}
+
+int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
+{
+    if (!pb || !avg_ms || reps <= 0) return fail(PB_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    int rc = ensure_cg64(pb);
+    if (!rc && fp32) rc = ensure_cg32(pb);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    pb->solved = false;
+    if (fp32) {
+        CGBufs<float> B = bufs<float>(pb);
+        HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
+                                 pb->part_res, pb->nbres));
+        HIPCHK(launch_cg_init<float>(s, pb->g, B, nullptr, pb->res32));
+        CGBufs<double> dummy{};
+        HIPCHK(launch_cg_fin(s, dummy, pb->part2, pb->nb2, pb->st));
+        HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf, 0, 0.0));
+        HIPCHK(hipEventRecord(a, s));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf, t & 1, 0.0));
+        HIPCHK(hipEventRecord(b, s));
+    } else {
+        CGBufs<double> B = bufs<double>(pb);
+        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, B, pb->part2, pb->nb2, pb->st));
+        HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf, 0, 0.0));
+        HIPCHK(hipEventRecord(a, s));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf, t & 1, 0.0));
+        HIPCHK(hipEventRecord(b, s));
+    }
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / reps;
+    return PB_OK;
+}
+
+size_t pb_problem_bytes(const pb_problem* pb) { return pb ? pb->mem.bytes : 0; }
+
+void pb_problem_free(pb_problem* pb)
+{
+    if (!pb) return;
+    (void)hipSetDevice(pb->ctx->device);
+    (void)hipStreamSynchronize(pb->ctx->stream);
+    pb->mem.release();
+    delete pb;
+}
+
+}  // extern "C"

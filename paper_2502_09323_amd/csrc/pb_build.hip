@@ -1,0 +1,800 @@
+// pb_build.hip -- coefficient-map construction on the GPU (gfx950).
+//
+// Steps (paper Sect. 2.1, 3.1, 3.2, 3.3.2):
+//   atom cell list -> node classification (solute iff strictly inside an atom ball) ->
+//   ordered compaction of the surface-crossing edges -> first-exit crossing geometry and
+//   WHA edge coefficients -> trilinear charge load -> boundary values (Sect. 2.3) ->
+//   diagonal, Jacobi inverse and boundary lift -> marching-cubes area weights.
+//
+// Every kernel is deterministic: no floating-point atomics, fixed summation orders.
+// Geometry that decides a node's medium is evaluated without contraction so that the
+// classification is bit-identical to the plain definition x = origin + h*i,
+// d2 = (dx*dx + dy*dy) + dz*dz, solute iff d2 < R*R.
+#include "pb_internal.h"
+
+#include <cmath>
+
+namespace pbk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ void decode(const Grid& g, int64_t e, int& i, int& j, int& k)
+{
+    int64_t row = e / g.S;
+    k = (int)(e - row * g.S) - Z0;
+    j = (int)(row % g.ny);
+    i = (int)(row / g.ny);
+}
+
+__device__ __forceinline__ bool is_box(const Grid& g, int i, int j, int k)
+{
+    return i == 0 || j == 0 || k == 0 || i == g.nx - 1 || j == g.ny - 1 || k == g.nz - 1;
+}
+
+__device__ __forceinline__ double node_x(const Grid& g, int ax, int i)
+{
+#pragma clang fp contract(off)
+    double o = ax == 0 ? g.ox : ax == 1 ? g.oy : g.oz;
+    return o + g.h * (double)i;
+}
+
+// range of bins to visit around point p (clamped); false when no atom can be within bs
+__device__ __forceinline__ bool bin_range(const Bins& b, const double* p, int* lo, int* hi)
+{
+    const double l[3] = {b.lox, b.loy, b.loz};
+    const int nb[3] = {b.nbx, b.nby, b.nbz};
+    for (int d = 0; d < 3; ++d) {
+        double f = floor((p[d] - l[d]) / b.bs);
+        if (f < -1.0 || f > (double)nb[d]) return false;
+        int c = (int)f;
+        lo[d] = c - 1 < 0 ? 0 : c - 1;
+        hi[d] = c + 1 > nb[d] - 1 ? nb[d] - 1 : c + 1;
+    }
+    return true;
+}
+
+// ---- cell list -----------------------------------------------------------------------
+
+__device__ __forceinline__ int atom_bin(const Bins& b, const double* c)
+{
+    int x = (int)floor((c[0] - b.lox) / b.bs);
+    int y = (int)floor((c[1] - b.loy) / b.bs);
+    int z = (int)floor((c[2] - b.loz) / b.bs);
+    return (x * b.nby + y) * b.nbz + z;
+}
+
+__global__ void k_bin_count(Atoms at, Bins b, int* cnt)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= at.n) return;
+    atomicAdd(&cnt[atom_bin(b, at.xyzr + 4 * a)], 1);
+}
+
+__global__ void k_bin_scatter(Atoms at, Bins b, int* cursor, int* ids)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= at.n) return;
+    int pos = atomicAdd(&cursor[atom_bin(b, at.xyzr + 4 * a)], 1);
+    ids[pos] = a;
+}
+
+// the scatter order depends on scheduling; sorting each bin makes the list deterministic
+__global__ void k_bin_sort(int nbins, const int* start, int* ids)
+{
+    int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= nbins) return;
+    int s = start[bi], e = start[bi + 1];
+    for (int x = s + 1; x < e; ++x) {
+        int v = ids[x];
+        int y = x - 1;
+        while (y >= s && ids[y] > v) {
+            ids[y + 1] = ids[y];
+            --y;
+        }
+        ids[y + 1] = v;
+    }
+}
+
+// single-block exclusive scan of up to n ints (in place into out[0..n]; out[n] = total)
+__global__ void __launch_bounds__(1024) k_scan1(const int* in, int n, int* out)
+{
+    __shared__ int sh[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = i < n ? in[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n) out[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+// ---- classification -------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, Atoms at, uint32_t* code)
+{
+#pragma clang fp contract(off)
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    if (k < 0 || k >= g.nz) {
+        code[e] = C_BOX;
+        return;
+    }
+    if (is_box(g, i, j, k)) {
+        code[e] = C_BOX;
+        return;
+    }
+    double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    uint32_t c = 0;
+    int lo[3], hi[3];
+    if (bin_range(b, p, lo, hi)) {
+        for (int x = lo[0]; x <= hi[0] && !c; ++x)
+            for (int y = lo[1]; y <= hi[1] && !c; ++y)
+                for (int z = lo[2]; z <= hi[2] && !c; ++z) {
+                    int bi = (x * b.nby + y) * b.nbz + z;
+                    for (int t = b.start[bi]; t < b.start[bi + 1]; ++t) {
+                        const double* a = at.xyzr + 4 * b.ids[t];
+                        double dx = p[0] - a[0], dy = p[1] - a[1], dz = p[2] - a[2];
+                        double d2 = dx * dx + dy * dy + dz * dz;
+                        if (d2 < a[3] * a[3]) {
+                            c = C_SOLUTE;
+                            break;
+                        }
+                    }
+                }
+    }
+    code[e] = c;
+}
+
+// ---- ordered compaction of cut edges -----------------------------------------------------
+
+__device__ __forceinline__ uint32_t cut_bits(const Grid& g, const uint32_t* cls, int64_t e)
+{
+    int i, j, k;
+    decode(g, e, i, j, k);
+    if (k < 0 || k >= g.nz) return 0;
+    uint32_t s = cls[e] & C_SOLUTE, m = 0;
+    if (i + 1 < g.nx && ((cls[e + (int64_t)g.ny * g.S] & C_SOLUTE) != s)) m |= 1u;
+    if (j + 1 < g.ny && ((cls[e + g.S] & C_SOLUTE) != s)) m |= 2u;
+    if (k + 1 < g.nz && ((cls[e + 1] & C_SOLUTE) != s)) m |= 4u;
+    return m;
+}
+
+// exclusive block scan of one int over 256 threads (4 waves of 64)
+__device__ __forceinline__ int block_exscan(int v, int* sh, int& total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < w; ++q) off += sh[q];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ void __launch_bounds__(256) k_cutcount(Grid g, const uint32_t* cls, int* blk_slots, int* blk_cuts)
+{
+    __shared__ int sh[4];
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t m = e < g.N ? cut_bits(g, cls, e) : 0;
+    int t1, t2;
+    block_exscan(m ? 1 : 0, sh, t1);
+    block_exscan(__popc(m), sh, t2);
+    if (threadIdx.x == 0) {
+        blk_slots[blockIdx.x] = t1;
+        blk_cuts[blockIdx.x] = t2;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_assign(Grid g, const uint32_t* cls, uint32_t* code,
+                                                const int* blk_slots, const int* blk_cuts,
+                                                int* cutbase, int64_t* cutkey)
+{
+    __shared__ int sh[4];
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t m = e < g.N ? cut_bits(g, cls, e) : 0;
+    int t1, t2;
+    int ps = block_exscan(m ? 1 : 0, sh, t1) + blk_slots[blockIdx.x];
+    int pc = block_exscan(__popc(m), sh, t2) + blk_cuts[blockIdx.x];
+    if (e >= g.N) return;
+    uint32_t c = cls[e] | (m << 2);
+    if (m) {
+        c |= (uint32_t)ps << C_SLOT_SHIFT;
+        cutbase[ps] = pc;
+        for (int ax = 0; ax < 3; ++ax)
+            if (m & (1u << ax)) cutkey[pc++] = e * 4 + ax;
+    }
+    code[e] = c;
+}
+
+// ---- crossing geometry (first exit from the union of balls) -----------------------------
+
+__global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, double eps_in, double eps_out,
+                                                  int64_t ncut, const int64_t* cutkey,
+                                                  const uint32_t* code, double* alpha, double* kcut,
+                                                  double* rp, double* np, int* owner, double* ck64,
+                                                  float* ck32)
+{
+#pragma clang fp contract(off)
+    int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncut) return;
+    int64_t key = cutkey[c];
+    int64_t e = key >> 2;
+    int ax = (int)(key & 3);
+    int i, j, k;
+    decode(g, e, i, j, k);
+    int lo_n[3] = {i, j, k}, hi_n[3] = {i, j, k};
+    hi_n[ax] += 1;
+    bool low_solute = (code[e] & C_SOLUTE) != 0;
+    double s[3], w[3];
+    for (int d = 0; d < 3; ++d) {
+        double a = node_x(g, d, lo_n[d]), bb = node_x(g, d, hi_n[d]);
+        s[d] = low_solute ? a : bb;
+        w[d] = low_solute ? bb : a;
+    }
+    (void)w;
+    double dir = low_solute ? 1.0 : -1.0;
+    int lo[3], hi[3];
+    double t = 0.0;
+    int ow = -1;
+    if (bin_range(b, s, lo, hi)) {
+        for (;;) {
+            double tn = t;
+            for (int x = lo[0]; x <= hi[0]; ++x)
+                for (int y = lo[1]; y <= hi[1]; ++y)
+                    for (int z = lo[2]; z <= hi[2]; ++z) {
+                        int bi = (x * b.nby + y) * b.nbz + z;
+                        for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
+                            const double* a = at.xyzr + 4 * b.ids[u];
+                            double dperp2 = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                if (d == ax) continue;
+                                double dd = s[d] - a[d];
+                                dperp2 = dperp2 + dd * dd;
+                            }
+                            double R2 = a[3] * a[3];
+                            if (!(dperp2 < R2)) continue;
+                            double half = sqrt(R2 - dperp2);
+                            double tc = (a[ax] - s[ax]) * dir;
+                            double clo = tc - half, chi = tc + half;
+                            if (clo <= t && t < chi && chi > tn) tn = chi;
+                        }
+                    }
+            if (tn == t) break;
+            t = tn;
+        }
+        for (int x = lo[0]; x <= hi[0]; ++x)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int z = lo[2]; z <= hi[2]; ++z) {
+                    int bi = (x * b.nby + y) * b.nbz + z;
+                    for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
+                        int id = b.ids[u];
+                        const double* a = at.xyzr + 4 * id;
+                        double dperp2 = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            if (d == ax) continue;
+                            double dd = s[d] - a[d];
+                            dperp2 = dperp2 + dd * dd;
+                        }
+                        double R2 = a[3] * a[3];
+                        if (!(dperp2 < R2)) continue;
+                        double half = sqrt(R2 - dperp2);
+                        double tc = (a[ax] - s[ax]) * dir;
+                        double clo = tc - half, chi = tc + half;
+                        if (chi == t && clo < t && (ow < 0 || id < ow)) ow = id;
+                    }
+                }
+    }
+    if (t > g.h) t = g.h;
+    if (ow < 0) ow = 0;  // unreachable for a valid solute end; keeps indexing in range
+    double al = t / g.h;
+    double ee = 1.0 / (al / eps_in + (1.0 - al) / eps_out);
+    double K = g.h * ee;
+    alpha[c] = al;
+    kcut[c] = K;
+    const double* ao = at.xyzr + 4 * ow;
+    for (int d = 0; d < 3; ++d) {
+        double r = (d == ax) ? s[d] + dir * t : s[d];
+        rp[3 * c + d] = r;
+        np[3 * c + d] = (r - ao[d]) / ao[3];
+    }
+    owner[c] = ow;
+    uint32_t slot = code[e] >> C_SLOT_SHIFT;
+    ck64[3 * (int64_t)slot + ax] = K;
+    ck32[3 * (int64_t)slot + ax] = (float)K;
+}
+
+// ---- load vector ------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, double* rhs)
+{
+#pragma clang fp contract(off)
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    if (k < 0 || k >= g.nz || is_box(g, i, j, k)) {
+        rhs[e] = 0.0;
+        return;
+    }
+    double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    const int nd[3] = {i, j, k};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const double org[3] = {g.ox, g.oy, g.oz};
+    double sum = 0.0;
+    int lo[3], hi[3];
+    if (bin_range(b, p, lo, hi)) {
+        for (int x = lo[0]; x <= hi[0]; ++x)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int z = lo[2]; z <= hi[2]; ++z) {
+                    int bi = (x * b.nby + y) * b.nbz + z;
+                    for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
+                        int id = b.ids[u];
+                        const double* a = at.xyzr + 4 * id;
+                        double w = 1.0;
+                        bool corner = true;
+                        for (int d = 0; d < 3; ++d) {
+                            double f = (a[d] - org[d]) / g.h;
+                            double fl = floor(f);
+                            if (fl < 0) fl = 0;
+                            if (fl > nn[d] - 2) fl = nn[d] - 2;
+                            int cl = (int)fl;
+                            double t = f - fl;
+                            if (nd[d] == cl) w = w * (1.0 - t);
+                            else if (nd[d] == cl + 1) w = w * t;
+                            else corner = false;
+                        }
+                        if (corner) sum += 4.0 * kPi * at.q[id] * w;
+                    }
+                }
+    }
+    rhs[e] = sum;
+}
+
+// ---- boundary values ----------------------------------------------------------------------
+
+__device__ __forceinline__ void box_node(const Grid& g, int64_t t, int& i, int& j, int& k)
+{
+    const int64_t fx = (int64_t)g.ny * g.nz, fy = (int64_t)(g.nx - 2) * g.nz,
+                  fz = (int64_t)(g.nx - 2) * (g.ny - 2);
+    if (t < 2 * fx) {
+        i = t < fx ? 0 : g.nx - 1;
+        int64_t r = t % fx;
+        j = (int)(r / g.nz);
+        k = (int)(r % g.nz);
+    } else if ((t -= 2 * fx) < 2 * fy) {
+        j = t < fy ? 0 : g.ny - 1;
+        int64_t r = t % fy;
+        i = 1 + (int)(r / g.nz);
+        k = (int)(r % g.nz);
+    } else {
+        t -= 2 * fy;
+        k = t < fz ? 0 : g.nz - 1;
+        int64_t r = t % fz;
+        i = 1 + (int)(r / (g.ny - 2));
+        j = 1 + (int)(r % (g.ny - 2));
+    }
+}
+
+__device__ __forceinline__ int64_t n_box(const Grid& g)
+{
+    return 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
+}
+
+// g(x) = sum_i q_i exp(-kD r)/(eps_out r), in atom order (Sect. 2.3, Debye-Hueckel form)
+__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, double eps_out, double* gb)
+{
+    __shared__ double sa[256 * 4];
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool act = t < n_box(g);
+    int i = 0, j = 0, k = 0;
+    if (act) box_node(g, t, i, j, k);
+    double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    double s = 0.0;
+    for (int base = 0; base < at.n; base += 256) {
+        int a = base + threadIdx.x;
+        __syncthreads();
+        if (a < at.n) {
+            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
+            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
+            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
+            sa[4 * threadIdx.x + 3] = at.q[a];
+        }
+        __syncthreads();
+        int m = at.n - base < 256 ? at.n - base : 256;
+        if (act)
+            for (int u = 0; u < m; ++u) {
+                double dx = p[0] - sa[4 * u], dy = p[1] - sa[4 * u + 1], dz = p[2] - sa[4 * u + 2];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                s += sa[4 * u + 3] * exp(-kD * r) / (eps_out * r);
+            }
+    }
+    if (act) gb[g.idx(i, j, k)] = s;
+}
+
+__global__ void __launch_bounds__(256) k_bc_user(Grid g, const double* full, double* gb)
+{
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_box(g)) return;
+    int i, j, k;
+    box_node(g, t, i, j, k);
+    gb[g.idx(i, j, k)] = full[((int64_t)i * g.ny + j) * g.nz + k];
+}
+
+// ---- diagonal, Jacobi inverse, boundary lift ------------------------------------------------
+
+__device__ __forceinline__ double edgeK(uint32_t c, int ax, const double* ck, const Coef& cf)
+{
+    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
+    return (c & C_SOLUTE) ? cf.kin : cf.kout;
+}
+
+__global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code, const double* ck,
+                                                   Coef cf, const double* gb, double* rhs,
+                                                   float* dinv, double* diag)
+{
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    uint32_t c = code[e];
+    if (c & C_BOX) {
+        dinv[e] = 0.0f;
+        if (diag) diag[e] = 0.0;
+        return;
+    }
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    const int64_t nb[6] = {e - sx, e + sx, e - sy, e + sy, e - 1, e + 1};
+    double K[6];
+    K[0] = edgeK(code[e - sx], 0, ck, cf);
+    K[1] = edgeK(c, 0, ck, cf);
+    K[2] = edgeK(code[e - sy], 1, ck, cf);
+    K[3] = edgeK(c, 1, ck, cf);
+    K[4] = edgeK(code[e - 1], 2, ck, cf);
+    K[5] = edgeK(c, 2, ck, cf);
+    double D = K[0] + K[1] + K[2] + K[3] + K[4] + K[5] + ((c & C_SOLUTE) ? 0.0 : cf.mass);
+    double lift = 0.0;
+    for (int q = 0; q < 6; ++q)
+        if (code[nb[q]] & C_BOX) lift += K[q] * gb[nb[q]];
+    rhs[e] += lift;
+    dinv[e] = (float)(1.0 / D);
+    if (diag) diag[e] = D;
+}
+
+// ---- marching-cubes area weights ------------------------------------------------------------
+// Cell corners are numbered x + 2y + 4z.  Cell edges 0..3 run along x at (y,z) = 00,10,01,11;
+// 4..7 along y at (x,z) = 00,10,01,11; 8..11 along z at (x,y) = 00,10,01,11.
+
+__device__ __forceinline__ void cedge(int e, int& ax, int& c0, int& c1)
+{
+    int grp = e >> 2, u = e & 1, v = (e >> 1) & 1;
+    ax = grp;
+    if (grp == 0) { c0 = 2 * u + 4 * v; c1 = c0 + 1; }
+    else if (grp == 1) { c0 = u + 4 * v; c1 = c0 + 2; }
+    else { c0 = u + 2 * v; c1 = c0 + 4; }
+}
+
+__device__ __forceinline__ double tri_area(const double* a, const double* b, const double* c)
+{
+    double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double x = u[1] * v[2] - u[2] * v[1];
+    double y = u[2] * v[0] - u[0] * v[2];
+    double z = u[0] * v[1] - u[1] * v[0];
+    return 0.5 * sqrt(x * x + y * y + z * z);
+}
+
+__global__ void __launch_bounds__(128) k_mc_weights(Grid g, const uint32_t* code, const int* cutbase,
+                                                    int64_t ncut, const int64_t* cutkey,
+                                                    const double* rp, double* wp)
+{
+    int64_t c = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    if (c >= ncut) return;
+    int64_t key = cutkey[c];
+    int64_t e = key >> 2;
+    int ax = (int)(key & 3);
+    int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+    const int64_t stride[3] = {(int64_t)g.ny * g.S, g.S, 1};
+    double total = 0.0;
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            int64_t base = e - u * stride[a1] - v * stride[a2];  // cell lower corner
+            uint32_t cc[8];
+            int sol[8];
+            for (int q = 0; q < 8; ++q) {
+                int64_t nq = base + (q & 1) * stride[0] + ((q >> 1) & 1) * stride[1] + ((q >> 2) & 1) * stride[2];
+                cc[q] = code[nq];
+                sol[q] = (int)(cc[q] & C_SOLUTE);
+            }
+            bool cut[12];
+            int64_t gi[12];
+            int link[12][2];
+            int me = -1;
+            for (int le = 0; le < 12; ++le) {
+                int lax, c0, c1;
+                cedge(le, lax, c0, c1);
+                cut[le] = sol[c0] != sol[c1];
+                link[le][0] = link[le][1] = -1;
+                gi[le] = -1;
+                if (cut[le]) {
+                    uint32_t cd = cc[c0];
+                    uint32_t bits = (cd >> 2) & 7u;
+                    gi[le] = cutbase[cd >> C_SLOT_SHIFT] + __popc(bits & ((1u << lax) - 1u));
+                    if (gi[le] == c) me = le;
+                }
+            }
+            for (int fa = 0; fa < 3; ++fa)
+                for (int sd = 0; sd < 2; ++sd) {
+                    int fe[4], nf = 0, ncf = 0;
+                    for (int le = 0; le < 12; ++le) {
+                        int lax, c0, c1;
+                        cedge(le, lax, c0, c1);
+                        if (lax == fa) continue;
+                        if (((c0 >> fa) & 1) == sd && ((c1 >> fa) & 1) == sd) fe[nf++] = le;
+                    }
+                    for (int t = 0; t < 4; ++t) ncf += cut[fe[t]] ? 1 : 0;
+                    int pr[2][2], npr = 0;
+                    if (ncf == 2) {
+                        int x = -1, y = -1;
+                        for (int t = 0; t < 4; ++t)
+                            if (cut[fe[t]]) { if (x < 0) x = fe[t]; else y = fe[t]; }
+                        pr[0][0] = x; pr[0][1] = y; npr = 1;
+                    } else if (ncf == 4) {
+                        for (int q = 0; q < 8; ++q) {
+                            if (((q >> fa) & 1) != sd || !sol[q]) continue;
+                            int x = -1, y = -1;
+                            for (int t = 0; t < 4; ++t) {
+                                int lax, c0, c1;
+                                cedge(fe[t], lax, c0, c1);
+                                if (c0 == q || c1 == q) { if (x < 0) x = fe[t]; else y = fe[t]; }
+                            }
+                            pr[npr][0] = x; pr[npr][1] = y; npr++;
+                        }
+                    }
+                    for (int t = 0; t < npr; ++t) {
+                        int x = pr[t][0], y = pr[t][1];
+                        if (link[x][0] < 0) link[x][0] = y; else link[x][1] = y;
+                        if (link[y][0] < 0) link[y][0] = x; else link[y][1] = x;
+                    }
+                }
+            // walk loops in ascending start order until the loop holding `me` is found
+            bool seen[12];
+            for (int le = 0; le < 12; ++le) seen[le] = false;
+            int loop[12], m = 0;
+            for (int e0 = 0; e0 < 12; ++e0) {
+                if (!cut[e0] || seen[e0]) continue;
+                m = 0;
+                int prev = -1, cur = e0;
+                bool hit = false;
+                for (;;) {
+                    loop[m++] = cur;
+                    seen[cur] = true;
+                    hit = hit || (cur == me);
+                    int nxt = (link[cur][0] != prev) ? link[cur][0] : link[cur][1];
+                    if (nxt == e0 || nxt < 0 || m >= 12) break;
+                    prev = cur;
+                    cur = nxt;
+                }
+                if (hit) break;
+                m = 0;
+            }
+            if (m < 3) continue;
+            int pe = 0;
+            for (int t = 0; t < m; ++t)
+                if (loop[t] == me) pe = t;
+            // average over the m fans: every fan triangle touching `me` gives area/(3m)
+            double acc = 0.0;
+            for (int st = 0; st < m; ++st) {
+                const double* v0 = rp + 3 * gi[loop[st]];
+                for (int t = 1; t + 1 < m; ++t) {
+                    int i1 = (st + t) % m, i2 = (st + t + 1) % m;
+                    if (st != pe && i1 != pe && i2 != pe) continue;
+                    acc += tri_area(v0, rp + 3 * gi[loop[i1]], rp + 3 * gi[loop[i2]]);
+                }
+            }
+            total += acc / (3.0 * (double)m);
+        }
+    wp[c] = total;
+}
+
+__global__ void k_zero(uint4* p, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; t < n; t += st) p[t] = make_uint4(0, 0, 0, 0);
+}
+
+// ---- inspection exports (unpadded node order) -------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_export_coeffs(Grid g, const uint32_t* code, const double* ck, Coef cf,
+                                                       const double* rhs, uint8_t* sol, double* kx,
+                                                       double* ky, double* kz, double* diag, double* b)
+{
+    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    if (u >= n) return;
+    const int k = (int)(u % g.nz), j = (int)((u / g.nz) % g.ny), i = (int)(u / ((int64_t)g.nz * g.ny));
+    const int64_t e = g.idx(i, j, k);
+    const uint32_t c = code[e];
+    if (sol) sol[u] = (uint8_t)(c & C_SOLUTE);
+    if (kx) kx[u] = i + 1 < g.nx ? edgeK(c, 0, ck, cf) : 0.0;
+    if (ky) ky[u] = j + 1 < g.ny ? edgeK(c, 1, ck, cf) : 0.0;
+    if (kz) kz[u] = k + 1 < g.nz ? edgeK(c, 2, ck, cf) : 0.0;
+    if (diag || b) {
+        double D = 0.0, bv = 0.0;
+        if (!(c & C_BOX)) {
+            const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+            D = edgeK(code[e - sx], 0, ck, cf) + edgeK(c, 0, ck, cf) + edgeK(code[e - sy], 1, ck, cf) +
+                edgeK(c, 1, ck, cf) + edgeK(code[e - 1], 2, ck, cf) + edgeK(c, 2, ck, cf) +
+                ((c & C_SOLUTE) ? 0.0 : cf.mass);
+            bv = rhs[e];
+        }
+        if (diag) diag[u] = D;
+        if (b) b[u] = bv;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_export_phi(Grid g, const double* x, const double* gb, double lB,
+                                                    double* out)
+{
+    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    if (u >= n) return;
+    const int k = (int)(u % g.nz), j = (int)((u / g.nz) % g.ny), i = (int)(u / ((int64_t)g.nz * g.ny));
+    const int64_t e = g.idx(i, j, k);
+    out[u] = lB * (x[e] + gb[e]);
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_fill(hipStream_t s, void* p, size_t bytes)
+{
+    // zero fill with a kernel (no memset nodes, so callers may capture it in a graph)
+    int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 > 0) {
+        unsigned g = nblk(n16, 256);
+        if (g > 65536) g = 65536;
+        k_zero<<<g, 256, 0, s>>>((uint4*)p, n16);
+    }
+    size_t rem = bytes - (size_t)n16 * 16;
+    if (rem) return hipMemsetAsync((char*)p + n16 * 16, 0, rem, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
+                       int* cursor)
+{
+    int nb = b.nbx * b.nby * b.nbz;
+    hipError_t err = launch_fill(s, cnt, sizeof(int) * (size_t)nb);
+    if (err != hipSuccess) return err;
+    k_bin_count<<<nblk(at.n, 256), 256, 0, s>>>(at, b, cnt);
+    k_scan1<<<1, 1024, 0, s>>>(cnt, nb, start);
+    err = hipMemcpyAsync(cursor, start, sizeof(int) * (size_t)nb, hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return err;
+    k_bin_scatter<<<nblk(at.n, 256), 256, 0, s>>>(at, b, cursor, ids);
+    k_bin_sort<<<nblk(nb, 256), 256, 0, s>>>(nb, start, ids);
+    b.start = start;
+    b.ids = ids;
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, uint32_t* code)
+{
+    k_classify<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, code);
+    return hipGetLastError();
+}
+
+hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk_slots, int* blk_cuts,
+                           int nb)
+{
+    k_cutcount<<<nb, 256, 0, s>>>(g, cls, blk_slots, blk_cuts);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals)
+{
+    // in-place exclusive scans through a copy: out[i] written after in[i] is read by the
+    // same thread and only the carry crosses chunks, so in == out is safe
+    k_scan1<<<1, 1024, 0, s>>>(a, n, a);
+    k_scan1<<<1, 1024, 0, s>>>(b, n, b);
+    hipError_t err = hipMemcpyAsync(totals, a + n, sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return err;
+    err = hipMemcpyAsync(totals + 1, b + n, sizeof(int), hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return err;
+    return hipGetLastError();
+}
+
+hipError_t launch_assign(hipStream_t s, const Grid& g, const uint32_t* cls, uint32_t* code,
+                         const int* blk_slots, const int* blk_cuts, int* cutbase, int64_t* cutkey)
+{
+    k_assign<<<nblk(g.N, 256), 256, 0, s>>>(g, cls, code, blk_slots, blk_cuts, cutbase, cutkey);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double eps_in,
+                           double eps_out, int64_t ncut, const int64_t* cutkey, const uint32_t* code,
+                           double* alpha, double* kcut, double* rp, double* np, int* owner,
+                           double* ck64, float* ck32)
+{
+    if (ncut == 0) return hipSuccess;
+    k_cut_geom<<<nblk(ncut, 256), 256, 0, s>>>(g, b, at, eps_in, eps_out, ncut, cutkey, code, alpha,
+                                                kcut, rp, np, owner, ck64, ck32);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* rhs)
+{
+    k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
+                        double* gb)
+{
+    int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
+    k_bc_dh<<<nblk(nbx, 256), 256, 0, s>>>(g, at, kD, eps_out, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc_user(hipStream_t s, const Grid& g, const double* full, double* gb)
+{
+    int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
+    k_bc_user<<<nblk(nbx, 256), 256, 0, s>>>(g, full, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_lift(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
+                            Coef c, const double* gb, double* rhs, float* dinv, double* diag)
+{
+    k_diag_lift<<<nblk(g.N, 256), 256, 0, s>>>(g, code, ck64, c, gb, rhs, dinv, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_coeffs(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, Coef c,
+                                const double* rhs, uint8_t* sol, double* kx, double* ky, double* kz,
+                                double* diag, double* b)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    k_export_coeffs<<<nblk(n, 256), 256, 0, s>>>(g, code, ck64, c, rhs, sol, kx, ky, kz, diag, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_phi(hipStream_t s, const Grid& g, const double* x, const double* gb, double lB,
+                             double* out)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    k_export_phi<<<nblk(n, 256), 256, 0, s>>>(g, x, gb, lB, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_weights(hipStream_t s, const Grid& g, const uint32_t* code, const int* cutbase,
+                             int64_t ncut, const int64_t* cutkey, const double* rp, double* wp)
+{
+    if (ncut == 0) return hipSuccess;
+    k_mc_weights<<<nblk(ncut, 128), 128, 0, s>>>(g, code, cutbase, ncut, cutkey, rp, wp);
+    return hipGetLastError();
+}
+
+}  // namespace pbk

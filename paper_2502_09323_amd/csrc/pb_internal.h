@@ -1,0 +1,161 @@
+// pb_internal.h -- device data layout and kernel launchers of libpb (gfx950).
+//
+// Node arrays live in a padded z-contiguous layout: node (i,j,k) is element
+// ((i*ny + j)*S + k + Z0) with Z0 = 7 and S a multiple of 8, so that the first interior
+// node of every z-row (k = 1) starts a 64-byte line for FP64 data.  Padding elements are
+// treated as Dirichlet nodes with value 0.
+//
+// Per node the solver keeps one 32-bit code instead of three edge coefficients:
+//   bit 0      solute (node strictly inside an atom ball)
+//   bit 1      box or padding node (Dirichlet)
+//   bits 2..4  the edge to (i+1,j,k), (i,j+1,k), (i,j,k+1) crosses the molecular surface
+//   bits 5..31 slot of the node in the compact cut-edge tables (valid if any of bits 2..4)
+// An edge inside one medium has K = h*eps_in or h*eps_out; a cut edge reads its WHA value
+// from ck[3*slot + axis].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pb.h"
+
+namespace pbk {
+
+constexpr uint32_t C_SOLUTE = 1u;
+constexpr uint32_t C_BOX = 2u;
+constexpr uint32_t C_CUTX = 4u;
+constexpr int C_SLOT_SHIFT = 5;
+constexpr int Z0 = 7;
+
+struct Grid {
+    int nx, ny, nz;   // nodes per axis
+    int S;            // z-row stride in elements
+    int64_t N;        // storage elements nx*ny*S
+    double h, ox, oy, oz;
+    __host__ __device__ int64_t idx(int i, int j, int k) const
+    {
+        return ((int64_t)i * ny + j) * S + k + Z0;
+    }
+};
+
+struct Bins {          // atom cell list: bins of edge bs covering the atom centres
+    double lox, loy, loz, bs;
+    int nbx, nby, nbz;
+    const int* start;  // nbins + 1
+    const int* ids;    // atom ids, ascending within each bin
+};
+
+struct Atoms {
+    int n;
+    const double* xyzr;  // 4 per atom: x, y, z, radius
+    const double* q;
+};
+
+struct Coef {          // what the operator needs on the device
+    double kin, kout, mass;  // h*eps_in, h*eps_out, h^3*eps_out*kD^2
+};
+
+// deterministic CG state, one per solve
+struct CGState {
+    double rz[2];      // r.z of the two most recent iterations (indexed by parity)
+    double bnorm2;
+    double rr;         // last ||r||^2 seen
+    double pq;
+    int status;        // 0 running, 1 converged, 2 breakdown
+    int iters;         // iteration count at convergence
+    int iter_count;    // completed iterations
+    int pad;
+};
+
+struct TileShape {     // tiling of the interior for the stencil kernel
+    int LX;            // planes per x-chunk
+    int nxc, njt, nkt; // chunks / tiles along x, y, z
+    int items;         // nxc*njt*nkt
+};
+
+constexpr int TY = 8;  // rows (y) per stencil tile = 4 waves x 2 rows
+
+// ---- build kernels (pb_build.hip) -----------------------------------------------------
+hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
+                       int* cursor);
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at,
+                           uint32_t* code);
+hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk_slots,
+                           int* blk_cuts, int nblk);
+hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals);
+hipError_t launch_assign(hipStream_t s, const Grid& g, const uint32_t* cls, uint32_t* code,
+                         const int* blk_slots, const int* blk_cuts, int* cutbase, int64_t* cutkey);
+hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at,
+                           double eps_in, double eps_out, int64_t ncut, const int64_t* cutkey,
+                           const uint32_t* code, double* alpha, double* kcut, double* rp,
+                           double* np, int* owner, double* ck64, float* ck32);
+hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* rhs);
+hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
+                        double* gb);
+hipError_t launch_bc_user(hipStream_t s, const Grid& g, const double* full, double* gb);
+hipError_t launch_diag_lift(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
+                            Coef c, const double* gb, double* rhs, float* dinv, double* diag);
+hipError_t launch_mc_weights(hipStream_t s, const Grid& g, const uint32_t* code, const int* cutbase,
+                             int64_t ncut, const int64_t* cutkey, const double* rp, double* wp);
+hipError_t launch_fill(hipStream_t s, void* p, size_t bytes);
+hipError_t launch_export_coeffs(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, Coef c,
+                                const double* rhs, uint8_t* sol, double* kx, double* ky, double* kz,
+                                double* diag, double* b);
+hipError_t launch_export_phi(hipStream_t s, const Grid& g, const double* x, const double* gb, double lB,
+                             double* out);
+
+// ---- solver kernels (pb_solve.hip) ------------------------------------------------------
+TileShape make_tiles(const Grid& g);
+int update_blocks(const Grid& g);
+
+template <typename T>
+struct CGBufs {
+    T* x;
+    T* r;
+    T* p[2];
+    T* q;
+    const T* ck;
+    const float* dinv;
+    const uint32_t* code;
+    double* part1;     // [nb1]    p.q partials
+    double* part2;     // [2*nb2]  r.z and r.r partials
+    CGState* st;
+    int nb1, nb2;
+};
+
+template <typename T>
+hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, const double* b64,
+                          const T* bT);
+hipError_t launch_cg_fin(hipStream_t s, const CGBufs<double>& B64, double* part2, int nb2,
+                         CGState* st);
+template <typename T>
+hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B,
+                             Coef c, int par, double tol2);
+template <typename T>
+hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B, int par);
+
+// mixed precision refinement
+hipError_t launch_residual64(hipStream_t s, const Grid& g, const TileShape& ts, const uint32_t* code,
+                             const double* ck64, Coef c, const double* b, const double* x,
+                             float* r32, double* part, int nbp);
+hipError_t launch_reduce_to(hipStream_t s, const double* part, int n, double* out);
+hipError_t launch_add_correction(hipStream_t s, const Grid& g, double* x, const float* d);
+
+// ---- energy kernels (pb_energy.hip) -------------------------------------------------------
+hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, double eps_out,
+                              int64_t ncut, const int64_t* cutkey, const uint32_t* code,
+                              const double* alpha, const double* kcut, const double* x,
+                              const double* gb, const double* wp, double* F, double* phip,
+                              double* pts /* 8 per cut: rp, np, F, w*phip */, const double* rp,
+                              const double* np);
+hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const double* pts,
+                        double* partial, int nchunk);
+hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic);
+hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, const double* partial, int nchunk,
+                                const double* phic, double eps_in, double eps_out, double lB,
+                                double* phi_reac, double* out /* 4 */, const double* F, int64_t ncut,
+                                const double* wp);
+int nbody_chunks(int n_atoms, int64_t ncut);
+
+}  // namespace pbk

@@ -1,0 +1,458 @@
+// pb_solve.hip -- Jacobi-preconditioned conjugate gradients on the condensed 7-point
+// operator (paper Sect. 3.1, eq. matrixequation, with the edge permittivities of Sect. 3.2),
+// matrix-free, for FP64 and FP32 data.
+//
+// One CG iteration is two kernels and no host round trip:
+//   stencil(par): reduce the previous r.z and r.r partials (every block, fixed order),
+//                 test convergence, beta = rz/rz_old; then per tile
+//                 p_new = D^-1 r + beta p_old (also on the halo), q = A p_new,
+//                 partial sums of p_new.q
+//   update(par):  reduce the p.q partials, alpha = rz/pq; x += alpha p, r -= alpha q,
+//                 partial sums of r.(D^-1 r) and r.r
+// The scalars never leave the device; every block reduces the same partial array in the
+// same order, so all blocks agree bit for bit and the result is run-to-run deterministic.
+//
+// The stencil kernel tiles the interior into 64 (z, one wave) x 8 (y, 4 waves x 2 rows)
+// columns and marches along x over a chunk of planes, carrying the x-neighbours in
+// registers and staging the current plane with its y/z halo in LDS.  Tiles are numbered
+// z-fastest and handed out so that each XCD gets one contiguous range of tiles, which keeps
+// the y-halo rows of neighbouring tiles in the same L2.
+#include "pb_internal.h"
+
+#include <cmath>
+
+namespace pbk {
+
+namespace {
+
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        sh[w] = a;
+        sh[4 + w] = b;
+    }
+    __syncthreads();
+    a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+}
+
+template <typename T>
+__device__ __forceinline__ T eK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
+{
+    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
+    return (c & C_SOLUTE) ? kin : kout;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf, int par,
+                                                    double tol2)
+{
+    __shared__ double sh[8];
+    __shared__ T sp[TY + 2][66];
+    __shared__ uint32_t sc[TY + 1][65];
+    CGState* st = B.st;
+    if (st->status != 0) return;
+
+    double rz = 0.0, rr = 0.0;
+    for (int t = threadIdx.x; t < B.nb2; t += 256) {
+        rz += B.part2[t];
+        rr += B.part2[B.nb2 + t];
+    }
+    block_sum2(rz, rr, sh);
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (rr <= tol2 * st->bnorm2) {
+        if (first) {
+            st->status = 1;
+            st->iters = st->iter_count;
+            st->rr = rr;
+        }
+        return;
+    }
+    if (!isfinite(rz) || !isfinite(rr)) {
+        if (first) st->status = 2;
+        return;
+    }
+    const double beta = rz / st->rz[par ^ 1];
+    if (first) {
+        st->rz[par] = rz;
+        st->rr = rr;
+    }
+    const T bT = (T)beta;
+    const T kin = (T)cf.kin, kout = (T)cf.kout, mass = (T)cf.mass;
+
+    // XCD-aware bijective block -> tile map (blocks are dealt round-robin to 8 XCDs)
+    const int W = ts.items, b = blockIdx.x;
+    const int q8 = W >> 3, rem = W & 7, xcd = b & 7;
+    const int item = xcd * q8 + (xcd < rem ? xcd : rem) + (b >> 3);
+    const int kt = item % ts.nkt;
+    const int t2 = item / ts.nkt;
+    const int jt = t2 % ts.njt;
+    const int xc = t2 / ts.njt;
+    const int k0 = 1 + kt * 64, j0 = 1 + jt * TY;
+    const int ib = 1 + xc * ts.LX;
+    const int ie = (ib + ts.LX < g.nx - 1) ? ib + ts.LX : g.nx - 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = k0 + lane;
+    constexpr int RY = TY / 4;
+
+    const T* __restrict__ r = B.r;
+    const T* __restrict__ pold = B.p[par ^ 1];
+    T* __restrict__ pnew = B.p[par];
+    const float* __restrict__ dinv = B.dinv;
+    const uint32_t* __restrict__ code = B.code;
+    const T* __restrict__ ck = B.ck;
+
+    auto pn = [&](int i, int j, int kk) -> T {
+        if (i <= 0 || i >= g.nx - 1 || j <= 0 || j >= g.ny - 1 || kk <= 0 || kk >= g.nz - 1) return (T)0;
+        const int64_t e = g.idx(i, j, kk);
+        return (T)dinv[e] * r[e] + bT * pold[e];
+    };
+    auto cd = [&](int i, int j, int kk) -> uint32_t {
+        if (j < 0 || j >= g.ny || kk < 0 || kk >= g.nz) return C_BOX;
+        return code[g.idx(i, j, kk)];
+    };
+
+    T pm[RY], pc[RY], px[RY];
+    uint32_t cm[RY], cc[RY], cx[RY];
+#pragma unroll
+    for (int q = 0; q < RY; ++q) {
+        const int j = j0 + wv * RY + q;
+        pm[q] = pn(ib - 1, j, k);
+        cm[q] = cd(ib - 1, j, k);
+        pc[q] = pn(ib, j, k);
+        cc[q] = cd(ib, j, k);
+    }
+    T acc = (T)0;
+    for (int i = ib; i < ie; ++i) {
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            const int j = j0 + wv * RY + q;
+            px[q] = pn(i + 1, j, k);
+            cx[q] = cd(i + 1, j, k);
+            sp[1 + wv * RY + q][1 + lane] = pc[q];
+            sc[1 + wv * RY + q][1 + lane] = cc[q];
+        }
+        if (wv == 0) {
+            sp[0][1 + lane] = pn(i, j0 - 1, k);
+            sc[0][1 + lane] = cd(i, j0 - 1, k);
+        } else if (wv == 1) {
+            sp[TY + 1][1 + lane] = pn(i, j0 + TY, k);
+        } else if (wv == 2) {
+            if (lane < TY) {
+                sp[1 + lane][0] = pn(i, j0 + lane, k0 - 1);
+                sc[1 + lane][0] = cd(i, j0 + lane, k0 - 1);
+            }
+        } else {
+            if (lane < TY) sp[1 + lane][65] = pn(i, j0 + lane, k0 + 64);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            const int j = j0 + wv * RY + q;
+            const int row = 1 + wv * RY + q;
+            if (j <= g.ny - 2 && k <= g.nz - 2) {
+                const uint32_t c = cc[q];
+                const T Kxp = eK(c, 0, ck, kin, kout), Kyp = eK(c, 1, ck, kin, kout),
+                        Kzp = eK(c, 2, ck, kin, kout);
+                const T Kxm = eK(cm[q], 0, ck, kin, kout);
+                const T Kym = eK(sc[row - 1][1 + lane], 1, ck, kin, kout);
+                const T Kzm = eK(sc[row][lane], 2, ck, kin, kout);
+                const T D = ((Kxm + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((c & C_SOLUTE) ? (T)0 : mass));
+                const T p0 = pc[q];
+                const T nbs = Kxm * pm[q] + Kxp * px[q] + Kym * sp[row - 1][1 + lane] +
+                              Kyp * sp[row + 1][1 + lane] + Kzm * sp[row][lane] + Kzp * sp[row][2 + lane];
+                const T qv = D * p0 - nbs;
+                const int64_t e = g.idx(i, j, k);
+                pnew[e] = p0;
+                B.q[e] = qv;
+                acc += p0 * qv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            pm[q] = pc[q];
+            pc[q] = px[q];
+            cm[q] = cc[q];
+            cc[q] = cx[q];
+        }
+    }
+    double a = (double)acc, dummy = 0.0;
+    block_sum2(a, dummy, sh);
+    if (threadIdx.x == 0) B.part1[blockIdx.x] = a;
+}
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B, int par)
+{
+    __shared__ double sh[8];
+    CGState* st = B.st;
+    if (st->status != 0) return;
+    double pq = 0.0, dummy = 0.0;
+    for (int t = threadIdx.x; t < B.nb1; t += 256) pq += B.part1[t];
+    block_sum2(pq, dummy, sh);
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (first) {
+            st->status = 2;
+            st->pq = pq;
+        }
+        return;
+    }
+    const T aT = (T)(st->rz[par] / pq);
+    using V = typename Vec4<T>::type;
+    V* __restrict__ x = reinterpret_cast<V*>(B.x);
+    V* __restrict__ r = reinterpret_cast<V*>(B.r);
+    const V* __restrict__ p = reinterpret_cast<const V*>(B.p[par]);
+    const V* __restrict__ q = reinterpret_cast<const V*>(B.q);
+    const float4* __restrict__ dv = reinterpret_cast<const float4*>(B.dinv);
+    T rz = (T)0, rr = (T)0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+        V xv = x[v], rv = r[v];
+        const V pv = p[v], qv = q[v];
+        const float4 d = dv[v];
+        xv.x += aT * pv.x; xv.y += aT * pv.y; xv.z += aT * pv.z; xv.w += aT * pv.w;
+        rv.x -= aT * qv.x; rv.y -= aT * qv.y; rv.z -= aT * qv.z; rv.w -= aT * qv.w;
+        x[v] = xv;
+        r[v] = rv;
+        rz += rv.x * ((T)d.x * rv.x) + rv.y * ((T)d.y * rv.y) + rv.z * ((T)d.z * rv.z) + rv.w * ((T)d.w * rv.w);
+        rr += rv.x * rv.x + rv.y * rv.y + rv.z * rv.z + rv.w * rv.w;
+    }
+    double a = (double)rz, c = (double)rr;
+    block_sum2(a, c, sh);
+    if (threadIdx.x == 0) {
+        B.part2[blockIdx.x] = a;
+        B.part2[B.nb2 + blockIdx.x] = c;
+    }
+    if (first) st->iter_count += 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_init(int64_t n4, CGBufs<T> B, const double* b64, const T* bT)
+{
+    __shared__ double sh[8];
+    using V = typename Vec4<T>::type;
+    T rz = (T)0, rr = (T)0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    V* x = reinterpret_cast<V*>(B.x);
+    V* r = reinterpret_cast<V*>(B.r);
+    V* p0 = reinterpret_cast<V*>(B.p[0]);
+    V* p1 = reinterpret_cast<V*>(B.p[1]);
+    V* q = reinterpret_cast<V*>(B.q);
+    const float4* dv = reinterpret_cast<const float4*>(B.dinv);
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+        V bv;
+        if (b64) {
+            const double4 t = reinterpret_cast<const double4*>(b64)[v];
+            bv.x = (T)t.x; bv.y = (T)t.y; bv.z = (T)t.z; bv.w = (T)t.w;
+        } else {
+            bv = reinterpret_cast<const V*>(bT)[v];
+        }
+        const float4 d = dv[v];
+        V z0;
+        z0.x = 0; z0.y = 0; z0.z = 0; z0.w = 0;
+        x[v] = z0;
+        p0[v] = z0;
+        p1[v] = z0;
+        q[v] = z0;
+        r[v] = bv;
+        rz += bv.x * ((T)d.x * bv.x) + bv.y * ((T)d.y * bv.y) + bv.z * ((T)d.z * bv.z) + bv.w * ((T)d.w * bv.w);
+        rr += bv.x * bv.x + bv.y * bv.y + bv.z * bv.z + bv.w * bv.w;
+    }
+    double a = (double)rz, c = (double)rr;
+    block_sum2(a, c, sh);
+    if (threadIdx.x == 0) {
+        B.part2[blockIdx.x] = a;
+        B.part2[B.nb2 + blockIdx.x] = c;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CGState* st)
+{
+    __shared__ double sh[8];
+    double rz = 0.0, rr = 0.0;
+    for (int t = threadIdx.x; t < nb2; t += 256) {
+        rz += part2[t];
+        rr += part2[nb2 + t];
+    }
+    block_sum2(rz, rr, sh);
+    if (threadIdx.x == 0) {
+        st->rz[0] = rz;
+        st->rz[1] = INFINITY;  // first iteration: beta = rz / inf = 0
+        st->bnorm2 = rr;
+        st->rr = rr;
+        st->pq = 0.0;
+        st->status = 0;
+        st->iters = 0;
+        st->iter_count = 0;
+        st->pad = 0;
+    }
+}
+
+// ---- mixed precision: FP64 true residual and FP64 solution accumulation ------------------
+
+__global__ void __launch_bounds__(256) k_residual64(Grid g, const uint32_t* __restrict__ code,
+                                                    const double* __restrict__ ck, Coef cf,
+                                                    const double* __restrict__ b, const double* __restrict__ x,
+                                                    float* __restrict__ r32, double* __restrict__ part)
+{
+    __shared__ double sh[8];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rr = 0.0;
+    if (e < g.N) {
+        const uint32_t c = code[e];
+        float out = 0.0f;
+        if (!(c & C_BOX)) {
+            const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+            const double Kxm = eK(code[e - sx], 0, ck, cf.kin, cf.kout);
+            const double Kxp = eK(c, 0, ck, cf.kin, cf.kout);
+            const double Kym = eK(code[e - sy], 1, ck, cf.kin, cf.kout);
+            const double Kyp = eK(c, 1, ck, cf.kin, cf.kout);
+            const double Kzm = eK(code[e - 1], 2, ck, cf.kin, cf.kout);
+            const double Kzp = eK(c, 2, ck, cf.kin, cf.kout);
+            const double D = ((Kxm + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((c & C_SOLUTE) ? 0.0 : cf.mass));
+            const double ax = D * x[e] - (Kxm * x[e - sx] + Kxp * x[e + sx] + Kym * x[e - sy] +
+                                          Kyp * x[e + sy] + Kzm * x[e - 1] + Kzp * x[e + 1]);
+            const double rv = b[e] - ax;
+            rr = rv * rv;
+            out = (float)rv;
+        }
+        r32[e] = out;
+    }
+    double dummy = 0.0;
+    block_sum2(rr, dummy, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_to(const double* part, int n, double* out)
+{
+    __shared__ double sh[8];
+    double a = 0.0, dummy = 0.0;
+    for (int t = threadIdx.x; t < n; t += 256) a += part[t];
+    block_sum2(a, dummy, sh);
+    if (threadIdx.x == 0) *out = a;
+}
+
+__global__ void __launch_bounds__(256) k_add_correction(int64_t n4, double* x, const float* d)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+        double4 xv = reinterpret_cast<double4*>(x)[v];
+        const float4 dv = reinterpret_cast<const float4*>(d)[v];
+        xv.x += (double)dv.x; xv.y += (double)dv.y; xv.z += (double)dv.z; xv.w += (double)dv.w;
+        reinterpret_cast<double4*>(x)[v] = xv;
+    }
+}
+
+}  // namespace
+
+TileShape make_tiles(const Grid& g)
+{
+    TileShape t;
+    t.njt = (g.ny - 2 + TY - 1) / TY;
+    t.nkt = (g.nz - 2 + 63) / 64;
+    const int tiles = t.njt * t.nkt;
+    // chunk length along x: long enough to amortise the chunk's extra halo plane, short
+    // enough to give the chip several thousand tiles
+    int lx = 32;
+    while (lx > 4 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 2048) lx >>= 1;
+    t.LX = lx;
+    t.nxc = (g.nx - 2 + lx - 1) / lx;
+    t.items = tiles * t.nxc;
+    return t;
+}
+
+int update_blocks(const Grid& g)
+{
+    const int64_t n4 = g.N / 4;
+    int64_t b = (n4 + 255) / 256;
+    if (b > 512) b = 512;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename T>
+hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, const double* b64, const T* bT)
+{
+    k_cg_init<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B, b64, bT);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_fin(hipStream_t s, const CGBufs<double>& B64, double* part2, int nb2, CGState* st)
+{
+    (void)B64;
+    k_cg_fin<<<1, 256, 0, s>>>(part2, nb2, st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c,
+                             int par, double tol2)
+{
+    k_cg_stencil<T><<<ts.items, 256, 0, s>>>(g, ts, B, c, par, tol2);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B, int par)
+{
+    k_cg_update<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B, par);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cg_init<double>(hipStream_t, const Grid&, const CGBufs<double>&, const double*,
+                                           const double*);
+template hipError_t launch_cg_init<float>(hipStream_t, const Grid&, const CGBufs<float>&, const double*,
+                                          const float*);
+template hipError_t launch_cg_stencil<double>(hipStream_t, const Grid&, const TileShape&,
+                                              const CGBufs<double>&, Coef, int, double);
+template hipError_t launch_cg_stencil<float>(hipStream_t, const Grid&, const TileShape&, const CGBufs<float>&,
+                                             Coef, int, double);
+template hipError_t launch_cg_update<double>(hipStream_t, const Grid&, const CGBufs<double>&, int);
+template hipError_t launch_cg_update<float>(hipStream_t, const Grid&, const CGBufs<float>&, int);
+
+hipError_t launch_residual64(hipStream_t s, const Grid& g, const TileShape& ts, const uint32_t* code,
+                             const double* ck64, Coef c, const double* b, const double* x, float* r32,
+                             double* part, int nbp)
+{
+    (void)ts;
+    (void)nbp;
+    const unsigned nb = (unsigned)((g.N + 255) / 256);
+    k_residual64<<<nb, 256, 0, s>>>(g, code, ck64, c, b, x, r32, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_to(hipStream_t s, const double* part, int n, double* out)
+{
+    k_reduce_to<<<1, 256, 0, s>>>(part, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_correction(hipStream_t s, const Grid& g, double* x, const float* d)
+{
+    const int64_t n4 = g.N / 4;
+    int64_t nb = (n4 + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    k_add_correction<<<(unsigned)nb, 256, 0, s>>>(n4, x, d);
+    return hipGetLastError();
+}
+
+}  // namespace pbk

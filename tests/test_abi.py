@@ -1,0 +1,58 @@
+"""The C-ABI library loads on the CPU, exports every function declared in include/pb.h,
+and rejects bad calls before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2502_09323_amd import binding as B
+from paper_2502_09323_amd import build as BB
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        BB.build()
+    return B.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(pb_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("pb_build_coeffs", "pb_solve", "pb_energy", "pb_ctx_create", "pb_problem_free"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    for n in B.EXPORTED:
+        assert n in declared_functions(), n
+
+
+def test_struct_sizes_match_binding():
+    # pb_params: 5 doubles, 3 int32 (+pad), 3 doubles, int32 (+pad), ptr, int32 (+pad), 2 doubles, int32 (+pad)
+    assert C.sizeof(B.PbParams) == 5 * 8 + 16 + 24 + 8 + 8 + 8 + 16 + 8
+    assert C.sizeof(B.PbSolveStats) == 32
+    assert C.sizeof(B.PbEnergyOut) == 72
+
+
+def test_null_arguments_are_rejected_without_a_gpu(lib):
+    out = C.c_void_p()
+    rc = lib.pb_ctx_create(0, None, B.ALLOC_FN(0), B.FREE_FN(0), None, 0, C.byref(out))
+    assert rc == B.PB_EINVAL
+    assert b"allocator" in lib.pb_last_error()
+    rc = lib.pb_build_coeffs(None, None, 0, None, None, None, C.byref(out))
+    assert rc == B.PB_EINVAL
+    st = B.PbSolveStats()
+    assert lib.pb_solve(None, C.byref(st)) == B.PB_EINVAL
+    assert lib.pb_num_cut(None) == B.PB_EINVAL
