@@ -49,13 +49,56 @@ __device__ __forceinline__ T eK(uint32_t c, int ax, const T* __restrict__ ck, T 
     return (c & C_SOLUTE) ? kin : kout;
 }
 
+// K of the edge from a node along +axis without a branch: a cut edge reads its WHA value
+// from the compact table, an edge inside one medium takes h*eps of that medium.  The table
+// is always read (slot 0 for uncut edges) and the result is blended arithmetically, so the
+// load is never turned into a branch whose join would wait on every load in flight.
+template <typename T>
+__device__ __forceinline__ T edgeK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
+{
+    const bool cut = (c & (C_CUTX << ax)) != 0;
+    const int64_t ix = cut ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0;
+    const T v = ck[ix];
+    const T base = (c & C_SOLUTE) ? kin : kout;
+    const T m = cut ? (T)1 : (T)0;
+    return v * m + base * ((T)1 - m);
+}
+
+// the same split in two: the table index (any edge; slot 0 when uncut) and the blend
+__device__ __forceinline__ int64_t ck_index(uint32_t c, int ax)
+{
+    return (c & (C_CUTX << ax)) ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T ck_blend(T v, uint32_t c, int ax, T kin, T kout)
+{
+    const T base = (c & C_SOLUTE) ? kin : kout;
+    const T m = (c & (C_CUTX << ax)) ? (T)1 : (T)0;
+    return v * m + base * ((T)1 - m);
+}
+
+template <typename T>
+struct Raw {   // what one node contributes to p_new = D^-1 r + beta p_old
+    T r, po;
+    float di;
+    uint32_t c;
+};
+
+template <typename T>
+struct K3 {    // coefficients of the +x, +y, +z edges of a node
+    T x, y, z;
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf, int par,
                                                     double tol2)
 {
+    constexpr int RY = TY / 4;
     __shared__ double sh[8];
-    __shared__ T sp[TY + 2][66];
-    __shared__ uint32_t sc[TY + 1][65];
+    __shared__ T sp[TY + 2][66];   // p_new of plane i: rows j0-1..j0+TY, cols k0-1..k0+64
+    __shared__ T sky[TY + 1][64];  // K of the +y edge: rows j0-1..j0+TY-1, cols k0..k0+63
+    __shared__ T skz[TY][65];      // K of the +z edge: own rows, cols k0-1..k0+63
     CGState* st = B.st;
     if (st->status != 0) return;
 
@@ -98,8 +141,6 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     const int ib = 1 + xc * ts.LX;
     const int ie = (ib + ts.LX < g.nx - 1) ? ib + ts.LX : g.nx - 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = k0 + lane;
-    constexpr int RY = TY / 4;
 
     const T* __restrict__ r = B.r;
     const T* __restrict__ pold = B.p[par ^ 1];
@@ -107,81 +148,143 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     const float* __restrict__ dinv = B.dinv;
     const uint32_t* __restrict__ code = B.code;
     const T* __restrict__ ck = B.ck;
+    const int64_t sx = (int64_t)g.ny * g.S;
 
-    auto pn = [&](int i, int j, int kk) -> T {
-        if (i <= 0 || i >= g.nx - 1 || j <= 0 || j >= g.ny - 1 || kk <= 0 || kk >= g.nz - 1) return (T)0;
-        const int64_t e = g.idx(i, j, kk);
-        return (T)dinv[e] * r[e] + bT * pold[e];
+    // Out-of-interior positions are clamped onto box nodes, where r = p = D^-1 = 0: every
+    // load below is unconditional and in bounds, and a clamped node contributes p_new = 0.
+    auto clampj = [&](int j) { return j < 0 ? 0 : (j > g.ny - 1 ? g.ny - 1 : j); };
+    auto clampk = [&](int k) { return k < 0 ? 0 : (k > g.nz - 1 ? g.nz - 1 : k); };
+    auto load = [&](int64_t e) {
+        Raw<T> v;
+        v.r = r[e];
+        v.po = pold[e];
+        v.di = dinv[e];
+        v.c = code[e];
+        return v;
     };
-    auto cd = [&](int i, int j, int kk) -> uint32_t {
-        if (j < 0 || j >= g.ny || kk < 0 || kk >= g.nz) return C_BOX;
-        return code[g.idx(i, j, kk)];
-    };
+    auto pval = [&](const Raw<T>& v) { return (T)v.di * v.r + bT * v.po; };
 
-    T pm[RY], pc[RY], px[RY];
-    uint32_t cm[RY], cc[RY], cx[RY];
+    // own columns (z = k0 + lane, rows j0 + wv*RY + q) and this thread's halo point
+    const int k = k0 + lane;
+    const int kc = clampk(k);
+    int64_t eo[RY];
+    bool valid[RY];
 #pragma unroll
     for (int q = 0; q < RY; ++q) {
         const int j = j0 + wv * RY + q;
-        pm[q] = pn(ib - 1, j, k);
-        cm[q] = cd(ib - 1, j, k);
-        pc[q] = pn(ib, j, k);
-        cc[q] = cd(ib, j, k);
+        valid[q] = j <= g.ny - 2 && k <= g.nz - 2;
+        eo[q] = g.idx(0, clampj(j), kc);
     }
+    // halo: wave 0 row j0-1 (needs p and K+y), wave 1 row j0+TY (p), wave 2 column k0-1
+    // (p and K+z), wave 3 column k0+64 (p); waves 2 and 3 use their first TY lanes
+    int hj, hk;
+    bool hact = true;
+    if (wv == 0) { hj = j0 - 1; hk = k0 + lane; }
+    else if (wv == 1) { hj = j0 + TY; hk = k0 + lane; }
+    else { hact = lane < TY; hj = j0 + (lane < TY ? lane : TY - 1); hk = (wv == 2) ? k0 - 1 : k0 + 64; }
+    const int64_t eh = g.idx(0, clampj(hj), clampk(hk));
+    const int hax = wv == 0 ? 1 : 2;
+
+    // prologue: plane ib-1 (p, K+x), ib (p, K), ib+1 (p, K), halo of ib (p, K)
+    T pm[RY], pc[RY], px[RY], kxm[RY];
+    uint32_t cc[RY], cxn[RY];   // node codes of planes i and i+1
+    K3<T> kr[RY];               // raw table reads for the edge coefficients of plane i
+    Raw<T> nxt[RY];
+#pragma unroll
+    for (int q = 0; q < RY; ++q) {
+        const Raw<T> a = load(eo[q] + (int64_t)(ib - 1) * sx);
+        const Raw<T> c0 = load(eo[q] + (int64_t)ib * sx);
+        const Raw<T> c1 = load(eo[q] + (int64_t)(ib + 1) * sx);
+        pm[q] = pval(a);
+        kxm[q] = edgeK(a.c, 0, ck, kin, kout);
+        pc[q] = pval(c0);
+        cc[q] = c0.c;
+        kr[q].x = ck[ck_index(c0.c, 0)];
+        kr[q].y = ck[ck_index(c0.c, 1)];
+        kr[q].z = ck[ck_index(c0.c, 2)];
+        px[q] = pval(c1);
+        cxn[q] = c1.c;
+    }
+    Raw<T> hraw = load(eh + (int64_t)ib * sx);
+    T hv = pval(hraw);
+    uint32_t hc = hraw.c;
+    T hr = ck[ck_index(hc, hax)];
+
     T acc = (T)0;
     for (int i = ib; i < ie; ++i) {
+        // prefetch: own plane i+2 (clamped to the last box plane) and the halo of plane i+1
+        const int i2 = (i + 2 < g.nx) ? i + 2 : g.nx - 1;
+#pragma unroll
+        for (int q = 0; q < RY; ++q) nxt[q] = load(eo[q] + (int64_t)i2 * sx);
+        const Raw<T> hn = load(eh + (int64_t)(i + 1) * sx);
+
+        // stage plane i in LDS: p_new and the +y/+z edge coefficients
+        K3<T> kc3[RY];
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
-            const int j = j0 + wv * RY + q;
-            px[q] = pn(i + 1, j, k);
-            cx[q] = cd(i + 1, j, k);
-            sp[1 + wv * RY + q][1 + lane] = pc[q];
-            sc[1 + wv * RY + q][1 + lane] = cc[q];
+            const int row = wv * RY + q;
+            kc3[q].x = ck_blend(kr[q].x, cc[q], 0, kin, kout);
+            kc3[q].y = ck_blend(kr[q].y, cc[q], 1, kin, kout);
+            kc3[q].z = ck_blend(kr[q].z, cc[q], 2, kin, kout);
+            sp[1 + row][1 + lane] = pc[q];
+            sky[1 + row][lane] = kc3[q].y;
+            skz[row][1 + lane] = kc3[q].z;
         }
+        const T hK = ck_blend(hr, hc, hax, kin, kout);
         if (wv == 0) {
-            sp[0][1 + lane] = pn(i, j0 - 1, k);
-            sc[0][1 + lane] = cd(i, j0 - 1, k);
+            sp[0][1 + lane] = hv;
+            sky[0][lane] = hK;
         } else if (wv == 1) {
-            sp[TY + 1][1 + lane] = pn(i, j0 + TY, k);
-        } else if (wv == 2) {
-            if (lane < TY) {
-                sp[1 + lane][0] = pn(i, j0 + lane, k0 - 1);
-                sc[1 + lane][0] = cd(i, j0 + lane, k0 - 1);
+            sp[TY + 1][1 + lane] = hv;
+        } else if (hact) {
+            if (wv == 2) {
+                sp[1 + lane][0] = hv;
+                skz[lane][0] = hK;
+            } else {
+                sp[1 + lane][65] = hv;
             }
-        } else {
-            if (lane < TY) sp[1 + lane][65] = pn(i, j0 + lane, k0 + 64);
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
-            const int j = j0 + wv * RY + q;
-            const int row = 1 + wv * RY + q;
-            if (j <= g.ny - 2 && k <= g.nz - 2) {
-                const uint32_t c = cc[q];
-                const T Kxp = eK(c, 0, ck, kin, kout), Kyp = eK(c, 1, ck, kin, kout),
-                        Kzp = eK(c, 2, ck, kin, kout);
-                const T Kxm = eK(cm[q], 0, ck, kin, kout);
-                const T Kym = eK(sc[row - 1][1 + lane], 1, ck, kin, kout);
-                const T Kzm = eK(sc[row][lane], 2, ck, kin, kout);
-                const T D = ((Kxm + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((c & C_SOLUTE) ? (T)0 : mass));
-                const T p0 = pc[q];
-                const T nbs = Kxm * pm[q] + Kxp * px[q] + Kym * sp[row - 1][1 + lane] +
-                              Kyp * sp[row + 1][1 + lane] + Kzm * sp[row][lane] + Kzp * sp[row][2 + lane];
-                const T qv = D * p0 - nbs;
-                const int64_t e = g.idx(i, j, k);
-                pnew[e] = p0;
-                B.q[e] = qv;
-                acc += p0 * qv;
-            }
+            const int row = wv * RY + q;
+            const T Kym = sky[row][lane], Kyp = sky[1 + row][lane];
+            const T Kzm = skz[row][lane], Kzp = skz[row][1 + lane];
+            const T Kxp = kc3[q].x;
+            const T D = ((kxm[q] + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((cc[q] & C_SOLUTE) ? (T)0 : mass));
+            const T p0 = pc[q];
+            const T nbs = kxm[q] * pm[q] + Kxp * px[q] + Kym * sp[row][1 + lane] +
+                          Kyp * sp[row + 2][1 + lane] + Kzm * sp[1 + row][lane] + Kzp * sp[1 + row][2 + lane];
+            const T qv = D * p0 - nbs;
+            // a lane outside the interior was clamped onto a box node, whose p and q stay
+            // 0: it stores zeros there, so the stores need no branch
+            const int64_t e = eo[q] + (int64_t)i * sx;
+            pnew[e] = valid[q] ? p0 : (T)0;
+            B.q[e] = valid[q] ? qv : (T)0;
+            acc += valid[q] ? p0 * qv : (T)0;
         }
         __syncthreads();
+        // rotate.  The coefficient lookups of plane i+1 are issued last, straight into the
+        // registers that consume them, so no register copy waits on a load in flight and
+        // the next step's prefetch loads are never waited for before they are needed.
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             pm[q] = pc[q];
+            kxm[q] = kc3[q].x;
             pc[q] = px[q];
-            cm[q] = cc[q];
-            cc[q] = cx[q];
+            cc[q] = cxn[q];
+            px[q] = pval(nxt[q]);
+            cxn[q] = nxt[q].c;
         }
+        hv = pval(hn);
+        hc = hn.c;
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            kr[q].x = ck[ck_index(cc[q], 0)];
+            kr[q].y = ck[ck_index(cc[q], 1)];
+            kr[q].z = ck[ck_index(cc[q], 2)];
+        }
+        hr = ck[ck_index(hc, hax)];
     }
     double a = (double)acc, dummy = 0.0;
     block_sum2(a, dummy, sh);
