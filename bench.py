@@ -28,11 +28,12 @@ from paper_2502_09323_amd import inputs as I  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 METRIC = "PBE solves/s + p99 latency at 1e-6 energy err; PCG Gnode-iter/s vs FP64 plain"
 
-# residual tolerances that keep |dE/E| <= 1e-6 for the energies of the synthetic molecules
-# (measured against FP64 solves at 1e-12)
-RTOL_FP64 = 1e-7
-RTOL_MIXED = 1e-7
-INNER_RTOL = 1e-3
+# residual tolerance that keeps |dE/E| <= 1e-6 for the energies of the synthetic molecules
+# (measured against FP64 solves at 1e-12; both forms use it, so they are compared at equal
+# energy error), and the reliable-update factor of the mixed form
+RTOL_FP64 = 2e-7
+RTOL_MIXED = 2e-7
+INNER_RTOL = 1e-2
 
 
 def workload(name: str):

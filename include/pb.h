@@ -81,11 +81,13 @@ typedef struct {
     int32_t bc;             /* PB_BC_ZERO | PB_BC_DH | PB_BC_USER */
     const double* bc_values;/* PB_BC_USER: host array over the full grid; only box-face
                                entries are read.  Ignored otherwise. */
-    int32_t precision;      /* PB_FP64 or PB_MIXED (FP32 inner CG, FP64 refinement) */
+    int32_t precision;      /* PB_FP64, or PB_MIXED: FP32 coefficients, vectors and CG with
+                               FP64 reliable updates (true residual, solution accumulation) */
     double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64 path: CG
                                recursive residual; mixed: the FP64 true residual) */
-    double inner_rtol;      /* PB_MIXED: relative residual reduction of each inner solve */
-    int32_t max_iter;       /* FP64: CG iterations; mixed: total inner iterations */
+    double inner_rtol;      /* PB_MIXED: reliable-update factor: the FP32 recursive residual
+                               may drop by this factor before an FP64 true-residual update */
+    int32_t max_iter;       /* bound on launched CG iterations */
 } pb_params;
 
 /* Build the coefficient maps of a problem on the device (paper Sect. 2.1 and 3.1-3.2):
@@ -106,8 +108,8 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* params, int64_t n_atoms, const
                     const double* radius, const double* charge, pb_problem** out);
 
 typedef struct {
-    int32_t iters;          /* FP64: CG iterations; mixed: total inner iterations */
-    int32_t outer_iters;    /* mixed: refinement steps (FP64 residual sweeps); FP64: 0 */
+    int32_t iters;          /* CG iterations (FP32 iterations in the mixed form) */
+    int32_t outer_iters;    /* mixed: FP64 reliable updates after the first; FP64: 0 */
     int32_t status;         /* PB_OK, PB_ENOCONV or PB_EBREAKDOWN */
     int32_t reserved;
     double relres;          /* final relative residual (see pb_params.rtol) */
@@ -115,7 +117,10 @@ typedef struct {
 } pb_solve_stats;
 
 /* Solve A phi = b with Jacobi-preconditioned CG (the paper uses CG, Sect. 4), either in
- * FP64 throughout or with FP32 inner CG inside FP64 iterative refinement.  The solution
+ * FP64 throughout or as FP32 CG with FP64 reliable updates: whenever the FP32 recursive
+ * residual has dropped by inner_rtol, the FP32 correction is added to the FP64 solution and
+ * the FP32 residual is replaced by the FP64 true residual b - A x (exact coefficients), with
+ * the search direction kept; convergence is judged on the FP64 true residual.  The solution
  * stays on the device.  Returns PB_OK, PB_ENOCONV or PB_EBREAKDOWN (stats filled in all
  * three cases), or PB_EDEVICE. */
 int pb_solve(pb_problem* pb, pb_solve_stats* stats);
@@ -176,6 +181,11 @@ int pb_ctx_set_profiling(pb_ctx* ctx, int on);
 /* Average durations (ms) of the sampled stencil and update launches of the last pb_solve
  * (only iterations that did work are counted), and the number of samples. */
 int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples);
+
+/* Attainable-bandwidth reference: `reps` launches of a plain streaming copy of `bytes`
+ * bytes between two buffers from the context allocator, timed with HIP events; *gbps is
+ * (bytes read + bytes written) per second / 1e9. */
+int pb_stream_copy(pb_ctx* ctx, size_t bytes, int32_t reps, double* gbps);
 
 /* Bytes of device memory held by a problem. */
 size_t pb_problem_bytes(const pb_problem* pb);

@@ -21,7 +21,7 @@ PB_FP64, PB_MIXED = 0, 1
 EXPORTED = [
     "pb_ctx_create", "pb_ctx_destroy", "pb_last_error", "pb_build_coeffs", "pb_solve", "pb_energy",
     "pb_copy_potential", "pb_problem_free", "pb_copy_coeffs", "pb_num_cut", "pb_copy_cut",
-    "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes",
+    "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
 ]
 
 
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     L.pb_time_stencil.argtypes = [P, i32, i32, C.POINTER(C.c_double)]
     L.pb_ctx_set_profiling.argtypes = [P, C.c_int]
     L.pb_get_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i32)]
+    L.pb_stream_copy.argtypes = [P, C.c_size_t, i32, C.POINTER(C.c_double)]
     L.pb_problem_bytes.argtypes = [P]
     L.pb_problem_bytes.restype = C.c_size_t
     _lib = L
@@ -130,6 +131,13 @@ class Context:
         rc = _lib.pb_ctx_set_profiling(self.h, 1 if on else 0)
         if rc != PB_OK:
             raise _err(rc)
+
+    def stream_copy_gbps(self, nbytes: int = 1 << 30, reps: int = 10) -> float:
+        v = C.c_double()
+        rc = _lib.pb_stream_copy(self.h, int(nbytes), int(reps), C.byref(v))
+        if rc != PB_OK:
+            raise _err(rc)
+        return float(v.value)
 
     def close(self):
         if getattr(self, "h", None):

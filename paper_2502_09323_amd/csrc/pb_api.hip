@@ -130,7 +130,7 @@ struct pb_problem {
     double *F = nullptr, *phip = nullptr, *pts = nullptr;
     // CG work
     double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr;
-    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *res32 = nullptr;
+    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
     double *part1 = nullptr, *part2 = nullptr, *part_res = nullptr, *scal = nullptr;
     CGState* st = nullptr;
     int nb1 = 0, nb2 = 0, nbres = 0;
@@ -189,9 +189,11 @@ T* dalloc(pb_problem* pb, size_t count, int* rc)
     return (T*)p;
 }
 
-// Pipelined CG: launch chunks of iterations, poll the device state of the previous chunk.
+// Pipelined CG: launch chunks of iterations (for the mixed form each chunk ends with the
+// reliable-update kernels, which do nothing unless an update is due) and poll the device
+// state of the previous chunk while the next one runs.
 template <typename T>
-int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGState* out)
+int run_cg(pb_problem* pb, const CGBufs<T>& B, int max_iter, bool mixed, CGState* out)
 {
     pb_ctx* ctx = pb->ctx;
     hipStream_t s = ctx->stream;
@@ -204,7 +206,6 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGStat
         int n = std::min(M, max_iter - launched);
         for (int t = 0; t < n; ++t) {
             const int it = launched + t;
-            const int par = it & 1;
             const bool sample = prof && (it % 8 == 0) && evs.size() < 3 * 256;
             hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
             if (sample) {
@@ -213,9 +214,9 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGStat
                 HIPCHK(hipEventCreate(&e2));
                 HIPCHK(hipEventRecord(e0, s));
             }
-            HIPCHK(launch_cg_stencil<T>(s, pb->g, pb->ts, B, pb->cf, par, tol2));
+            HIPCHK(launch_cg_stencil<T>(s, pb->g, pb->ts, B, pb->cf));
             if (sample) HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(launch_cg_update<T>(s, pb->g, B, par));
+            HIPCHK(launch_cg_update<T>(s, pb->g, B));
             if (sample) {
                 HIPCHK(hipEventRecord(e2, s));
                 evs.push_back(e0);
@@ -223,6 +224,12 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGStat
                 evs.push_back(e2);
                 ev_it.push_back(it);
             }
+        }
+        if (mixed) {
+            HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, 0));
+            HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+                                      pb->part_res, B.st));
+            HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, B.part2, B.nb2, 0, 0.0, 0.0));
         }
         launched += n;
         HIPCHK(hipMemcpyAsync(&ctx->host_state[slot], B.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -236,8 +243,15 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, double tol2, int max_iter, CGStat
         if (more && (rc = enqueue((c + 1) & 1))) return rc;
         HIPCHK(hipEventSynchronize(ctx->ev[c & 1]));
         const CGState snap = ctx->host_state[c & 1];
-        if (snap.status != 0 || !more) break;
+        if ((snap.status != 0 && snap.status != 3) || !more) break;
         ++c;
+    }
+    if (mixed) {
+        // a final update folds in the last correction when the iteration did not converge
+        HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, 1));
+        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+                                  pb->part_res, B.st));
+        HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, B.part2, B.nb2, 0, 0.0, 0.0));
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(out, B.st, sizeof(CGState), hipMemcpyDeviceToHost));
@@ -285,7 +299,6 @@ int ensure_cg32(pb_problem* pb)
     if (!rc) pb->p32a = dalloc<float>(pb, N, &rc);
     if (!rc) pb->p32b = dalloc<float>(pb, N, &rc);
     if (!rc) pb->q32 = dalloc<float>(pb, N, &rc);
-    if (!rc) pb->res32 = dalloc<float>(pb, N, &rc);
     return rc;
 }
 
@@ -565,12 +578,12 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     // solver scalars and partial sums
     pb->nb1 = pb->ts.items;
     pb->nb2 = update_blocks(g);
-    pb->nbres = (int)((N + 255) / 256);
+    pb->nbres = residual_blocks(g);
     pb->part1 = dalloc<double>(pb, (size_t)pb->nb1, &rc);
     CK(rc);
     pb->part2 = dalloc<double>(pb, 2 * (size_t)pb->nb2, &rc);
     CK(rc);
-    pb->part_res = dalloc<double>(pb, (size_t)pb->nbres, &rc);
+    pb->part_res = dalloc<double>(pb, 3 * (size_t)pb->nbres, &rc);
     CK(rc);
     pb->scal = dalloc<double>(pb, 8, &rc);
     CK(rc);
@@ -602,65 +615,38 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     if (rc) return rc;
     const pb_params& P = pb->prm;
     int status = PB_OK;
+    CGState st;
     if (P.precision == PB_FP64) {
         CGBufs<double> B = bufs<double>(pb);
         HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
-        HIPCHK(launch_cg_fin(s, B, pb->part2, pb->nb2, pb->st));
-        CGState st;
-        rc = run_cg<double>(pb, B, P.rtol * P.rtol, P.max_iter, &st);
+        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, P.rtol * P.rtol));
+        rc = run_cg<double>(pb, B, P.max_iter, false, &st);
         if (rc) return rc;
         stats->iters = st.status == 1 ? st.iters : st.iter_count;
         stats->relres = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
-        status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
     } else {
         if ((rc = ensure_cg32(pb))) return rc;
-        HIPCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
+        const size_t N = (size_t)pb->g.N;
         CGBufs<float> B = bufs<float>(pb);
-        // ||b||^2 through the FP64 residual with x = 0
-        HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
-                                 pb->part_res, pb->nbres));
-        HIPCHK(launch_reduce_to(s, pb->part_res, pb->nbres, pb->scal));
-        double bn2 = 0;
-        HIPCHK(hipMemcpyAsync(&bn2, pb->scal, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        double rr = bn2;
-        int inner_total = 0, outer = 0;
-        status = PB_ENOCONV;
-        const double tol2 = P.rtol * P.rtol * bn2;
-        for (;;) {
-            if (rr <= tol2) {
-                status = PB_OK;
-                break;
-            }
-            if (inner_total >= P.max_iter || outer >= 200) break;
-            HIPCHK(launch_cg_init<float>(s, pb->g, B, nullptr, pb->res32));
-            CGBufs<double> dummy{};
-            HIPCHK(launch_cg_fin(s, dummy, pb->part2, pb->nb2, pb->st));
-            CGState st;
-            const double itol = P.inner_rtol;
-            rc = run_cg<float>(pb, B, itol * itol, P.max_iter - inner_total, &st);
-            if (rc) return rc;
-            inner_total += st.status == 1 ? st.iters : st.iter_count;
-            if (st.status == 2) {
-                status = PB_EBREAKDOWN;
-                break;
-            }
-            HIPCHK(launch_add_correction(s, pb->g, pb->x, pb->d32));
-            ++outer;
-            HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
-                                     pb->part_res, pb->nbres));
-            HIPCHK(launch_reduce_to(s, pb->part_res, pb->nbres, pb->scal));
-            HIPCHK(hipMemcpyAsync(&rr, pb->scal, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (!std::isfinite(rr)) {
-                status = PB_EBREAKDOWN;
-                break;
-            }
-        }
-        stats->iters = inner_total;
-        stats->outer_iters = outer;
-        stats->relres = bn2 > 0 ? std::sqrt(rr / bn2) : 0.0;
+        HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
+        HIPCHK(launch_fill(s, pb->d32, sizeof(float) * N));
+        HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * N));
+        HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * N));
+        HIPCHK(launch_fill(s, pb->q32, sizeof(float) * N));
+        // first "update": r32 = b - A*0, norms, and the mixed iteration state
+        HIPCHK(launch_ru_begin(s, pb->st));
+        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+                                  pb->part_res, pb->st));
+        HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 1, P.rtol * P.rtol,
+                             P.inner_rtol * P.inner_rtol));
+        rc = run_cg<float>(pb, B, P.max_iter, true, &st);
+        if (rc) return rc;
+        stats->iters = st.status == 1 ? st.iters : st.iter_count;
+        stats->outer_iters = st.n_ru;
+        const double bn2 = P.rtol > 0 ? st.goal64 / (P.rtol * P.rtol) : 0.0;
+        stats->relres = bn2 > 0 ? std::sqrt(st.rr64 / bn2) : 0.0;
     }
+    status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
     HIPCHK(hipStreamSynchronize(s));
     stats->status = status;
     stats->t_solve_s = now_s() - t0;
@@ -845,24 +831,24 @@ int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     pb->solved = false;
+    const double rtol2 = pb->prm.rtol * pb->prm.rtol;
     if (fp32) {
         CGBufs<float> B = bufs<float>(pb);
-        HIPCHK(launch_residual64(s, pb->g, pb->ts, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->res32,
-                                 pb->part_res, pb->nbres));
-        HIPCHK(launch_cg_init<float>(s, pb->g, B, nullptr, pb->res32));
-        CGBufs<double> dummy{};
-        HIPCHK(launch_cg_fin(s, dummy, pb->part2, pb->nb2, pb->st));
-        HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf, 0, 0.0));
+        HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * (size_t)pb->g.N));
+        HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * (size_t)pb->g.N));
+        HIPCHK(launch_cg_init<float>(s, pb->g, B, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, rtol2));
+        HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(a, s));
-        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf, t & 1, 0.0));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(b, s));
     } else {
         CGBufs<double> B = bufs<double>(pb);
         HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
-        HIPCHK(launch_cg_fin(s, B, pb->part2, pb->nb2, pb->st));
-        HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf, 0, 0.0));
+        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, rtol2));
+        HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(a, s));
-        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf, t & 1, 0.0));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(b, s));
     }
     HIPCHK(hipEventSynchronize(b));
@@ -871,6 +857,38 @@ int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     *avg_ms = ms / reps;
+    return PB_OK;
+}
+
+int pb_stream_copy(pb_ctx* ctx, size_t bytes, int32_t reps, double* gbps)
+{
+    if (!ctx || !gbps || reps <= 0 || bytes < 16) return fail(PB_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    bytes &= ~(size_t)15;
+    void* a = ctx->alloc(bytes, ctx->user);
+    void* b = a ? ctx->alloc(bytes, ctx->user) : nullptr;
+    if (!a || !b) {
+        if (a) ctx->free_fn(a, ctx->user);
+        return fail(PB_ENOMEM, "stream copy buffers");
+    }
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_fill(s, a, bytes);
+    for (int t = 0; t < 2 && e == hipSuccess; ++t) e = launch_stream_copy(s, a, b, bytes);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int t = 0; t < reps && e == hipSuccess; ++t) e = launch_stream_copy(s, a, b, bytes);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->free_fn(a, ctx->user);
+    ctx->free_fn(b, ctx->user);
+    if (e != hipSuccess) return fail(PB_EDEVICE, "stream copy: %s", hipGetErrorString(e));
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return PB_OK;
 }
 

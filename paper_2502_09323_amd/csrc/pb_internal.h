@@ -56,15 +56,24 @@ struct Coef {          // what the operator needs on the device
     double kin, kout, mass;  // h*eps_in, h*eps_out, h^3*eps_out*kD^2
 };
 
-// deterministic CG state, one per solve
+// deterministic CG state, one per solve; written by single designated threads only
 struct CGState {
     double rz[2];      // r.z of the two most recent iterations (indexed by parity)
-    double bnorm2;
-    double rr;         // last ||r||^2 seen
+    double bnorm2;     // ||b||^2 of the iterated system
+    double rr;         // last recursive ||r||^2
     double pq;
-    int status;        // 0 running, 1 converged, 2 breakdown
+    double stop2;      // the stencil kernel stops the iteration when rr <= stop2 ...
+    double trig2;      // mixed: a reliable update runs at a chunk end once rr <= trig2
+    double delta2;     // mixed: after an update trig2 = delta2 * ||r||^2
+    double goal64;     // mixed: converged when the FP64 true ||b - A x||^2 <= goal64
+    double rr64;       // mixed: FP64 true residual norm^2 at the last update
+    int status;        // 0 running, 1 converged, 2 breakdown, 3 true-residual check requested
+    int stop_status;   // ... and sets status = stop_status (1 for FP64, 3 for mixed)
     int iters;         // iteration count at convergence
-    int iter_count;    // completed iterations
+    int iter_count;    // completed iterations (its parity selects the p buffer)
+    int par;           // parity of the iteration in flight (stencil writes, update reads)
+    int ru;            // 1 while a reliable update is in progress
+    int n_ru;          // reliable updates done
     int pad;
 };
 
@@ -127,20 +136,23 @@ struct CGBufs {
 template <typename T>
 hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, const double* b64,
                           const T* bT);
-hipError_t launch_cg_fin(hipStream_t s, const CGBufs<double>& B64, double* part2, int nb2,
-                         CGState* st);
+hipError_t launch_cg_fin(hipStream_t s, double* part2, int nb2, CGState* st, double rtol2);
 template <typename T>
 hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B,
-                             Coef c, int par, double tol2);
+                             Coef c);
 template <typename T>
-hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B, int par);
+hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B);
+hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes);
 
-// mixed precision refinement
-hipError_t launch_residual64(hipStream_t s, const Grid& g, const TileShape& ts, const uint32_t* code,
-                             const double* ck64, Coef c, const double* b, const double* x,
-                             float* r32, double* part, int nbp);
-hipError_t launch_reduce_to(hipStream_t s, const double* part, int n, double* out);
-hipError_t launch_add_correction(hipStream_t s, const Grid& g, double* x, const float* d);
+// mixed precision: FP32 CG with FP64 reliable updates (true residual + solution accumulation)
+hipError_t launch_ru_begin(hipStream_t s, CGState* st);
+hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force);
+hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
+                              Coef c, const double* b, const double* x64, const float* dinv, float* r32,
+                              double* part3, CGState* st);
+hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, double* part2,
+                         int nb2, int init, double rtol2, double delta2);
+int residual_blocks(const Grid& g);
 
 // ---- energy kernels (pb_energy.hip) -------------------------------------------------------
 hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, double eps_out,

@@ -91,8 +91,7 @@ struct K3 {    // coefficients of the +x, +y, +z edges of a node
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf, int par,
-                                                    double tol2)
+__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf)
 {
     constexpr int RY = TY / 4;
     __shared__ double sh[8];
@@ -101,6 +100,7 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     __shared__ T skz[TY][65];      // K of the +z edge: own rows, cols k0-1..k0+63
     CGState* st = B.st;
     if (st->status != 0) return;
+    const int par = st->iter_count & 1;
 
     double rz = 0.0, rr = 0.0;
     for (int t = threadIdx.x; t < B.nb2; t += 256) {
@@ -109,9 +109,9 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     }
     block_sum2(rz, rr, sh);
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
-    if (rr <= tol2 * st->bnorm2) {
+    if (rr <= st->stop2) {
         if (first) {
-            st->status = 1;
+            st->status = st->stop_status;
             st->iters = st->iter_count;
             st->rr = rr;
         }
@@ -125,6 +125,7 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     if (first) {
         st->rz[par] = rz;
         st->rr = rr;
+        st->par = par;
     }
     const T bT = (T)beta;
     const T kin = (T)cf.kin, kout = (T)cf.kout, mass = (T)cf.mass;
@@ -303,11 +304,12 @@ struct Vec4<float> {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B, int par)
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
 {
     __shared__ double sh[8];
     CGState* st = B.st;
     if (st->status != 0) return;
+    const int par = st->par;
     double pq = 0.0, dummy = 0.0;
     for (int t = threadIdx.x; t < B.nb1; t += 256) pq += B.part1[t];
     block_sum2(pq, dummy, sh);
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__(256) k_cg_init(int64_t n4, CGBufs<T> B, const 
     }
 }
 
-__global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CGState* st)
+__global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CGState* st, double rtol2)
 {
     __shared__ double sh[8];
     double rz = 0.0, rr = 0.0;
@@ -403,23 +405,56 @@ __global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CG
         st->bnorm2 = rr;
         st->rr = rr;
         st->pq = 0.0;
+        st->stop2 = rtol2 * rr;
+        st->trig2 = -1.0;
+        st->delta2 = 0.0;
+        st->goal64 = 0.0;
+        st->rr64 = 0.0;
         st->status = 0;
+        st->stop_status = 1;
         st->iters = 0;
         st->iter_count = 0;
+        st->par = 0;
+        st->ru = 0;
+        st->n_ru = 0;
         st->pad = 0;
     }
 }
 
-// ---- mixed precision: FP64 true residual and FP64 solution accumulation ------------------
+// ---- mixed precision: FP32 CG with FP64 reliable updates ------------------------------------
+// The FP32 iteration runs on; a reliable update folds the FP32 correction into the FP64
+// solution and replaces the FP32 residual by the FP64 true residual b - A x64 (FP64 operator,
+// exact coefficients), keeping the search direction.  An update runs at a chunk end once the
+// recursive residual has dropped by delta since the last one, or when the recursive residual
+// reaches the target (the stencil kernel then stops with status 3).
 
-__global__ void __launch_bounds__(256) k_residual64(Grid g, const uint32_t* __restrict__ code,
-                                                    const double* __restrict__ ck, Coef cf,
-                                                    const double* __restrict__ b, const double* __restrict__ x,
-                                                    float* __restrict__ r32, double* __restrict__ part)
+__global__ void __launch_bounds__(256) k_ru_add(int64_t n4, CGState* st, double* x, float* d, int force)
+{
+    const int s0 = st->status;
+    const bool go = (s0 == 3) || (s0 == 0 && (force || st->rr <= st->trig2));
+    if (!go) return;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+        double4 xv = reinterpret_cast<double4*>(x)[v];
+        const float4 dv = reinterpret_cast<const float4*>(d)[v];
+        xv.x += (double)dv.x; xv.y += (double)dv.y; xv.z += (double)dv.z; xv.w += (double)dv.w;
+        reinterpret_cast<double4*>(x)[v] = xv;
+        reinterpret_cast<float4*>(d)[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->ru = 1;
+}
+
+__global__ void __launch_bounds__(256) k_ru_residual(Grid g, const uint32_t* __restrict__ code,
+                                                     const double* __restrict__ ck, Coef cf,
+                                                     const double* __restrict__ b, const double* __restrict__ x,
+                                                     const float* __restrict__ dinv, float* __restrict__ r32,
+                                                     double* __restrict__ part3, CGState* st)
 {
     __shared__ double sh[8];
+    if (!st->ru) return;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rr = 0.0;
+    double rr64 = 0.0;
+    float rz32 = 0.0f, rr32 = 0.0f;
     if (e < g.N) {
         const uint32_t c = code[e];
         float out = 0.0f;
@@ -435,37 +470,95 @@ __global__ void __launch_bounds__(256) k_residual64(Grid g, const uint32_t* __re
             const double ax = D * x[e] - (Kxm * x[e - sx] + Kxp * x[e + sx] + Kym * x[e - sy] +
                                           Kyp * x[e + sy] + Kzm * x[e - 1] + Kzp * x[e + 1]);
             const double rv = b[e] - ax;
-            rr = rv * rv;
+            rr64 = rv * rv;
             out = (float)rv;
+            rz32 = out * (dinv[e] * out);
+            rr32 = out * out;
         }
         r32[e] = out;
     }
+    double a = (double)rz32, c2 = (double)rr32;
+    block_sum2(a, c2, sh);
     double dummy = 0.0;
-    block_sum2(rr, dummy, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = rr;
-}
-
-__global__ void __launch_bounds__(256) k_reduce_to(const double* part, int n, double* out)
-{
-    __shared__ double sh[8];
-    double a = 0.0, dummy = 0.0;
-    for (int t = threadIdx.x; t < n; t += 256) a += part[t];
-    block_sum2(a, dummy, sh);
-    if (threadIdx.x == 0) *out = a;
-}
-
-__global__ void __launch_bounds__(256) k_add_correction(int64_t n4, double* x, const float* d)
-{
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
-        double4 xv = reinterpret_cast<double4*>(x)[v];
-        const float4 dv = reinterpret_cast<const float4*>(d)[v];
-        xv.x += (double)dv.x; xv.y += (double)dv.y; xv.z += (double)dv.z; xv.w += (double)dv.w;
-        reinterpret_cast<double4*>(x)[v] = xv;
+    block_sum2(rr64, dummy, sh);
+    if (threadIdx.x == 0) {
+        part3[blockIdx.x] = rr64;
+        part3[gridDim.x + blockIdx.x] = a;
+        part3[2 * gridDim.x + blockIdx.x] = c2;
     }
 }
 
+__global__ void k_ru_begin(CGState* st)
+{
+    st->status = 0;
+    st->ru = 1;
+}
+
+// one block: finish a reliable update (or, with init, set up the mixed iteration)
+__global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3, int nbres, double* part2,
+                                                int nb2, int init, double rtol2, double delta2)
+{
+    __shared__ double sh[8];
+    if (!st->ru) return;
+    double rr64 = 0.0, rz = 0.0, rr = 0.0, dummy = 0.0;
+    for (int t = threadIdx.x; t < nbres; t += 256) {
+        rr64 += part3[t];
+        rz += part3[nbres + t];
+        rr += part3[2 * nbres + t];
+    }
+    block_sum2(rz, rr, sh);
+    block_sum2(rr64, dummy, sh);
+    for (int t = threadIdx.x; t < nb2; t += 256) {
+        part2[t] = t == 0 ? rz : 0.0;
+        part2[nb2 + t] = t == 0 ? rr : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        if (init) {
+            st->rz[0] = rz;
+            st->rz[1] = INFINITY;
+            st->bnorm2 = rr;
+            st->pq = 0.0;
+            st->stop2 = rtol2 * rr;
+            st->delta2 = delta2;
+            st->goal64 = rtol2 * rr64;
+            st->stop_status = 3;
+            st->iters = 0;
+            st->iter_count = 0;
+            st->par = 0;
+            st->n_ru = 0;
+            st->pad = 0;
+        } else {
+            st->n_ru += 1;
+        }
+        st->rr = rr;
+        st->rr64 = rr64;
+        st->trig2 = st->delta2 * rr;
+        if (rr64 <= st->goal64) {
+            st->status = 1;
+            st->iters = st->iter_count;
+        } else {
+            st->status = 0;
+        }
+        st->ru = 0;
+    }
+}
+
+// plain streaming copy: the attainable-bandwidth reference (and the kernel used to scale the
+// HBM byte counters)
+__global__ void __launch_bounds__(256) k_stream_copy(const float4* __restrict__ a, float4* __restrict__ b, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) b[v] = a[v];
+}
+
 }  // namespace
+
+hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    k_stream_copy<<<8192, 256, 0, s>>>((const float4*)a, (float4*)b, n);
+    return hipGetLastError();
+}
 
 TileShape make_tiles(const Grid& g)
 {
@@ -499,25 +592,23 @@ hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, cons
     return hipGetLastError();
 }
 
-hipError_t launch_cg_fin(hipStream_t s, const CGBufs<double>& B64, double* part2, int nb2, CGState* st)
+hipError_t launch_cg_fin(hipStream_t s, double* part2, int nb2, CGState* st, double rtol2)
 {
-    (void)B64;
-    k_cg_fin<<<1, 256, 0, s>>>(part2, nb2, st);
+    k_cg_fin<<<1, 256, 0, s>>>(part2, nb2, st, rtol2);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c,
-                             int par, double tol2)
+hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c)
 {
-    k_cg_stencil<T><<<ts.items, 256, 0, s>>>(g, ts, B, c, par, tol2);
+    k_cg_stencil<T><<<ts.items, 256, 0, s>>>(g, ts, B, c);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B, int par)
+hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B)
 {
-    k_cg_update<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B, par);
+    k_cg_update<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B);
     return hipGetLastError();
 }
 
@@ -526,35 +617,41 @@ template hipError_t launch_cg_init<double>(hipStream_t, const Grid&, const CGBuf
 template hipError_t launch_cg_init<float>(hipStream_t, const Grid&, const CGBufs<float>&, const double*,
                                           const float*);
 template hipError_t launch_cg_stencil<double>(hipStream_t, const Grid&, const TileShape&,
-                                              const CGBufs<double>&, Coef, int, double);
+                                              const CGBufs<double>&, Coef);
 template hipError_t launch_cg_stencil<float>(hipStream_t, const Grid&, const TileShape&, const CGBufs<float>&,
-                                             Coef, int, double);
-template hipError_t launch_cg_update<double>(hipStream_t, const Grid&, const CGBufs<double>&, int);
-template hipError_t launch_cg_update<float>(hipStream_t, const Grid&, const CGBufs<float>&, int);
+                                             Coef);
+template hipError_t launch_cg_update<double>(hipStream_t, const Grid&, const CGBufs<double>&);
+template hipError_t launch_cg_update<float>(hipStream_t, const Grid&, const CGBufs<float>&);
 
-hipError_t launch_residual64(hipStream_t s, const Grid& g, const TileShape& ts, const uint32_t* code,
-                             const double* ck64, Coef c, const double* b, const double* x, float* r32,
-                             double* part, int nbp)
-{
-    (void)ts;
-    (void)nbp;
-    const unsigned nb = (unsigned)((g.N + 255) / 256);
-    k_residual64<<<nb, 256, 0, s>>>(g, code, ck64, c, b, x, r32, part);
-    return hipGetLastError();
-}
+int residual_blocks(const Grid& g) { return (int)((g.N + 255) / 256); }
 
-hipError_t launch_reduce_to(hipStream_t s, const double* part, int n, double* out)
-{
-    k_reduce_to<<<1, 256, 0, s>>>(part, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_add_correction(hipStream_t s, const Grid& g, double* x, const float* d)
+hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force)
 {
     const int64_t n4 = g.N / 4;
     int64_t nb = (n4 + 255) / 256;
     if (nb > 4096) nb = 4096;
-    k_add_correction<<<(unsigned)nb, 256, 0, s>>>(n4, x, d);
+    k_ru_add<<<(unsigned)nb, 256, 0, s>>>(n4, st, x64, d32, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, Coef c,
+                              const double* b, const double* x64, const float* dinv, float* r32, double* part3,
+                              CGState* st)
+{
+    k_ru_residual<<<(unsigned)residual_blocks(g), 256, 0, s>>>(g, code, ck64, c, b, x64, dinv, r32, part3, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ru_begin(hipStream_t s, CGState* st)
+{
+    k_ru_begin<<<1, 1, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, double* part2, int nb2,
+                         int init, double rtol2, double delta2)
+{
+    k_ru_fin<<<1, 256, 0, s>>>(st, part3, nbres, part2, nb2, init, rtol2, delta2);
     return hipGetLastError();
 }
 
