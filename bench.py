@@ -115,6 +115,7 @@ def main():
     ctx = B.Context(0)
     mol, grid, desc = workload(args.workload)
     nu = grid.unknowns
+    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)   # attainable-bandwidth reference
 
     # FP64 reference energies of this workload (untimed)
     ref_grid = I.GridSpec(**{k: getattr(grid, k) for k in grid.__dataclass_fields__})
@@ -196,6 +197,7 @@ def main():
         "mixed": {"iters": mx["iters"], "outer_iters": mx["outer_iters"], "t_solve_ms": round(mx["t_solve_ms"], 3),
                   "update_ms": round(mx["update_ms"], 5)},
         "roofline": roofline,
+        "stream_copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -83,7 +83,10 @@ struct TileShape {     // tiling of the interior for the stencil kernel
     int items;         // nxc*njt*nkt
 };
 
-constexpr int TY = 16;  // rows (y) per stencil tile = 4 waves x 4 rows
+#ifndef PB_TILE_ROWS
+#define PB_TILE_ROWS 8
+#endif
+constexpr int TY = PB_TILE_ROWS;  // rows (y) per stencil tile = 4 waves x TY/4 rows
 
 // ---- build kernels (pb_build.hip) -----------------------------------------------------
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,

@@ -12,7 +12,7 @@
 // The scalars never leave the device; every block reduces the same partial array in the
 // same order, so all blocks agree bit for bit and the result is run-to-run deterministic.
 //
-// The stencil kernel tiles the interior into 64 (z, one wave) x 8 (y, 4 waves x 2 rows)
+// The stencil kernel tiles the interior into 64 (z, one wave) x TY (y, 4 waves x TY/4 rows)
 // columns and marches along x over a chunk of planes, carrying the x-neighbours in
 // registers and staging the current plane with its y/z halo in LDS.  Tiles are numbered
 // z-fastest and handed out so that each XCD gets one contiguous range of tiles, which keeps
@@ -213,8 +213,9 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
 
     T acc = (T)0;
     for (int i = ib; i < ie; ++i) {
-        // prefetch: own plane i+2 (clamped to the last box plane) and the halo of plane i+1
-        const int i2 = (i + 2 < g.nx) ? i + 2 : g.nx - 1;
+        // prefetch: own plane i+2 (never past plane ie, the last one this chunk needs) and
+        // the halo of plane i+1
+        const int i2 = (i + 2 < ie) ? i + 2 : ie;
 #pragma unroll
         for (int q = 0; q < RY; ++q) nxt[q] = load(eo[q] + (int64_t)i2 * sx);
         const Raw<T> hn = load(eh + (int64_t)(i + 1) * sx);
@@ -543,12 +544,16 @@ __global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3
     }
 }
 
-// plain streaming copy: the attainable-bandwidth reference (and the kernel used to scale the
-// HBM byte counters)
-__global__ void __launch_bounds__(256) k_stream_copy(const float4* __restrict__ a, float4* __restrict__ b, int64_t n)
+// plain streaming copy with non-temporal accesses: the attainable-bandwidth reference (and the
+// kernel used to scale the HBM byte counters)
+typedef float f4v __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_stream_copy(const f4v* __restrict__ a, f4v* __restrict__ b, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) b[v] = a[v];
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) {
+        const f4v x = __builtin_nontemporal_load(a + v);
+        __builtin_nontemporal_store(x, b + v);
+    }
 }
 
 }  // namespace
@@ -556,7 +561,7 @@ __global__ void __launch_bounds__(256) k_stream_copy(const float4* __restrict__ 
 hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes)
 {
     const int64_t n = (int64_t)(bytes / 16);
-    k_stream_copy<<<8192, 256, 0, s>>>((const float4*)a, (float4*)b, n);
+    k_stream_copy<<<1024, 256, 0, s>>>((const f4v*)a, (f4v*)b, n);
     return hipGetLastError();
 }
 
@@ -566,10 +571,15 @@ TileShape make_tiles(const Grid& g)
     t.njt = (g.ny - 2 + TY - 1) / TY;
     t.nkt = (g.nz - 2 + 63) / 64;
     const int tiles = t.njt * t.nkt;
-    // chunk length along x: long enough to amortise the chunk's extra halo plane, short
-    // enough to give the chip several thousand tiles
+#ifdef PB_FORCE_LX
+    int lx = PB_FORCE_LX;
+#else
+    // chunk length along x: every chunk re-reads the planes next to it, so chunks stay long;
+    // they are shortened (down to 8 planes) while the grid would give fewer than 4096 tiles,
+    // so that the 256 CUs have several blocks each
     int lx = 32;
-    while (lx > 4 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 2048) lx >>= 1;
+    while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 4096) lx >>= 1;
+#endif
     t.LX = lx;
     t.nxc = (g.nx - 2 + lx - 1) / lx;
     t.items = tiles * t.nxc;
