@@ -190,6 +190,46 @@ int pb_stream_copy(pb_ctx* ctx, size_t bytes, int32_t reps, double* gbps);
 /* Bytes of device memory held by a problem. */
 size_t pb_problem_bytes(const pb_problem* pb);
 
+/* --- serving: continuous batching of many solves ----------------------------------- */
+
+/* A serving loop for a stream of requests in the mixed form (the paper treats one molecule
+ * at a time; solving many molecules, e.g. for binding free energies over complexes and
+ * their parts, Sect. 5.2, is the workload this serves).  Iteration kernels run on ctx's
+ * stream, coefficient builds and energy read-backs on build_ctx's stream (same device).
+ * Requests are admitted first-come first-served once arrived, while at most max_resident
+ * problems are resident and ctx's hbm_budget_bytes (if non-zero) is not exceeded; all
+ * resident problems advance together, 16 CG iterations per batched chunk.
+ * Errors: PB_EINVAL, PB_EDEVICE. */
+int pb_server_create(pb_ctx* ctx, pb_ctx* build_ctx, int32_t max_resident, pb_server** out);
+
+/* Seconds since the server was created (the clock of arrival and completion times). */
+double pb_server_now(const pb_server* srv);
+
+/* Queue a request (copied; params->precision must be PB_MIXED).  It becomes eligible for
+ * admission once pb_server_now() >= arrival_time_s.  A request whose estimated memory
+ * exceeds the whole budget completes with code PB_ENOMEM. */
+int pb_submit(pb_server* srv, const pb_params* params, int64_t n_atoms, const double* xyz,
+              const double* radius, const double* charge, uint64_t request_id,
+              double arrival_time_s);
+
+/* One scheduling step: retire finished problems (energy read-back), admit arrived requests,
+ * launch one chunk for all resident problems, and wait for the older of the two chunks kept
+ * in flight.  Returns the resident and queued counts. */
+int pb_server_step(pb_server* srv, int32_t* n_active, int32_t* n_queued);
+
+/* Move up to max finished requests out of the server: ids, energies, solve statistics,
+ * completion times (server clock) and result codes (PB_OK, PB_ENOCONV, PB_EBREAKDOWN,
+ * PB_ENOMEM, ...).  Any output array may be NULL. */
+int pb_poll(pb_server* srv, uint64_t* ids, pb_energy_out* results, pb_solve_stats* stats,
+            double* done_time_s, int32_t* codes, int32_t max, int32_t* n_done);
+
+/* Host seconds spent so far in the four phases of pb_server_step: waiting for chunks,
+ * retiring (energy read-back), admitting (coefficient builds), launching. */
+int pb_server_times(const pb_server* srv, double* out4);
+
+/* Wait for the device, release every resident problem and the server. */
+void pb_server_destroy(pb_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,8 @@ EXPORTED = [
     "pb_ctx_create", "pb_ctx_destroy", "pb_last_error", "pb_build_coeffs", "pb_solve", "pb_energy",
     "pb_copy_potential", "pb_problem_free", "pb_copy_coeffs", "pb_num_cut", "pb_copy_cut",
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
+    "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
+    "pb_server_times",
 ]
 
 
@@ -86,6 +88,15 @@ def load(path: str = LIB_PATH):
     L.pb_stream_copy.argtypes = [P, C.c_size_t, i32, C.POINTER(C.c_double)]
     L.pb_problem_bytes.argtypes = [P]
     L.pb_problem_bytes.restype = C.c_size_t
+    L.pb_server_create.argtypes = [P, P, i32, C.POINTER(P)]
+    L.pb_server_now.argtypes = [P]
+    L.pb_server_now.restype = C.c_double
+    L.pb_submit.argtypes = [P, C.POINTER(PbParams), i64, P, P, P, C.c_uint64, C.c_double]
+    L.pb_server_step.argtypes = [P, C.POINTER(i32), C.POINTER(i32)]
+    L.pb_poll.argtypes = [P, P, P, P, P, P, i32, C.POINTER(i32)]
+    L.pb_server_times.argtypes = [P, P]
+    L.pb_server_destroy.argtypes = [P]
+    L.pb_server_destroy.restype = None
     _lib = L
     return L
 
@@ -264,6 +275,80 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             _lib.pb_problem_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching serving loop (mixed form).  Iteration runs on ``ctx``'s stream,
+    builds and energy read-backs on a second context with its own stream."""
+
+    def __init__(self, ctx: Context, build_ctx: Context, max_resident: int = 64):
+        load()
+        self.ctx, self.build_ctx = ctx, build_ctx
+        h = C.c_void_p()
+        rc = _lib.pb_server_create(ctx.h, build_ctx.h, int(max_resident), C.byref(h))
+        if rc != PB_OK:
+            raise _err(rc)
+        self.h = h
+
+    def now(self) -> float:
+        return float(_lib.pb_server_now(self.h))
+
+    def submit(self, mol, grid, request_id: int, arrival_s: float | None = None):
+        p = make_params(grid)
+        keep = None
+        if grid.bc == PB_BC_USER:
+            keep = np.ascontiguousarray(grid.bc_values, dtype=np.float64).reshape(-1)
+            p.bc_values = keep.ctypes.data_as(C.c_void_p)
+        xyz = np.ascontiguousarray(mol.xyz, dtype=np.float64).reshape(-1)
+        rad = np.ascontiguousarray(mol.radius, dtype=np.float64)
+        chg = np.ascontiguousarray(mol.charge, dtype=np.float64)
+        t = self.now() if arrival_s is None else float(arrival_s)
+        rc = _lib.pb_submit(self.h, C.byref(p), int(mol.n), _ptr(xyz), _ptr(rad), _ptr(chg), int(request_id), t)
+        if rc != PB_OK:
+            raise _err(rc)
+
+    def step(self):
+        a, q = C.c_int32(), C.c_int32()
+        rc = _lib.pb_server_step(self.h, C.byref(a), C.byref(q))
+        if rc != PB_OK:
+            raise _err(rc)
+        return a.value, q.value
+
+    def poll(self, max_n: int = 1024) -> list:
+        ids = np.zeros(max_n, np.uint64)
+        res = (PbEnergyOut * max_n)()
+        sts = (PbSolveStats * max_n)()
+        tdone = np.zeros(max_n)
+        codes = np.zeros(max_n, np.int32)
+        n = C.c_int32()
+        rc = _lib.pb_poll(self.h, _ptr(ids), res, sts, _ptr(tdone), _ptr(codes), max_n, C.byref(n))
+        if rc != PB_OK:
+            raise _err(rc)
+        out = []
+        for i in range(n.value):
+            d = {k: getattr(res[i], k) for k, _ in PbEnergyOut._fields_}
+            d.update(iters=sts[i].iters, outer_iters=sts[i].outer_iters, status=sts[i].status, relres=sts[i].relres)
+            d.update(id=int(ids[i]), done_s=float(tdone[i]), code=int(codes[i]))
+            out.append(d)
+        return out
+
+    def times(self) -> dict:
+        v = np.zeros(4)
+        rc = _lib.pb_server_times(self.h, _ptr(v))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(wait=v[0], retire=v[1], admit=v[2], launch=v[3])
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pb_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "pb_host.h"
 #include "pb_internal.h"
 
 using namespace pbk;
@@ -19,8 +20,9 @@ namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...)
+}  // namespace
+
+int pbi_fail(int code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -30,6 +32,10 @@ int fail(int code, const char* fmt, ...)
     g_err = buf;
     return code;
 }
+
+namespace {
+
+#define fail pbi_fail
 
 #define HIPCHK(expr)                                                                        \
     do {                                                                                    \
@@ -56,89 +62,6 @@ void reduced_constants(double T, double I, double eps_out, double* lB, double* k
 }
 
 }  // namespace
-
-struct pb_ctx {
-    int device;
-    hipStream_t stream;
-    pb_alloc_fn alloc;
-    pb_free_fn free_fn;
-    void* user;
-    size_t budget;
-    int profile;
-    CGState* host_state;  // pinned, 2 slots for pipelined polling
-    hipEvent_t ev[2];
-};
-
-struct DevAlloc {
-    pb_ctx* ctx;
-    std::vector<std::pair<void*, size_t>> held;
-    size_t bytes = 0;
-    void* get(size_t n)
-    {
-        n = (n + 255) & ~(size_t)255;
-        if (n == 0) n = 256;
-        void* p = ctx->alloc(n, ctx->user);
-        if (p) {
-            held.emplace_back(p, n);
-            bytes += n;
-        }
-        return p;
-    }
-    void put(void* p)
-    {
-        for (size_t i = 0; i < held.size(); ++i)
-            if (held[i].first == p) {
-                bytes -= held[i].second;
-                ctx->free_fn(p, ctx->user);
-                held.erase(held.begin() + (long)i);
-                return;
-            }
-    }
-    void release()
-    {
-        for (auto& h : held) ctx->free_fn(h.first, ctx->user);
-        held.clear();
-        bytes = 0;
-    }
-};
-
-struct pb_problem {
-    pb_ctx* ctx;
-    pb_params prm;
-    int64_t na;
-    Grid g;
-    TileShape ts;
-    Coef cf;
-    double lB, kD;
-    DevAlloc mem;
-    // inputs
-    double* xyzr = nullptr;
-    double* q = nullptr;
-    // coefficient maps
-    uint32_t* code = nullptr;
-    float* dinv = nullptr;
-    double* ck64 = nullptr;
-    float* ck32 = nullptr;
-    int* cutbase = nullptr;
-    double* rhs = nullptr;
-    double* gb = nullptr;
-    double* x = nullptr;
-    int64_t ncut = 0, nslot = 0;
-    int64_t* cutkey = nullptr;
-    double *alpha = nullptr, *kcut = nullptr, *rp = nullptr, *np = nullptr, *wp = nullptr;
-    int* owner = nullptr;
-    double *F = nullptr, *phip = nullptr, *pts = nullptr;
-    // CG work
-    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr;
-    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
-    double *part1 = nullptr, *part2 = nullptr, *part_res = nullptr, *scal = nullptr;
-    CGState* st = nullptr;
-    int nb1 = 0, nb2 = 0, nbres = 0;
-    bool solved = false;
-    // sampled kernel timings of the last solve
-    double prof_stencil_ms = 0, prof_update_ms = 0;
-    int prof_n = 0;
-};
 
 namespace {
 
@@ -347,6 +270,120 @@ CGBufs<float> bufs<float>(pb_problem* pb)
 
 }  // namespace
 
+int pbi_mixed_begin(pb_problem* pb)
+{
+    int rc = ensure_cg32(pb);
+    if (rc) return rc;
+    hipStream_t s = pb->ctx->stream;
+    const size_t N = (size_t)pb->g.N;
+    const pb_params& P = pb->prm;
+    HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
+    HIPCHK(launch_fill(s, pb->d32, sizeof(float) * N));
+    HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * N));
+    HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * N));
+    HIPCHK(launch_fill(s, pb->q32, sizeof(float) * N));
+    // first "update": r32 = b - A*0, the norms and the mixed iteration state
+    HIPCHK(launch_ru_begin(s, pb->st));
+    HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32, pb->part_res,
+                              pb->st));
+    HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 1, P.rtol * P.rtol,
+                         P.inner_rtol * P.inner_rtol));
+    return PB_OK;
+}
+
+// energy read-back: kernels and the read-back of the sums (and, with finish_mixed, the final
+// reliable update and the CG state) behind pb->ev; pbi_energy_end collects after the event
+int pbi_energy_begin(pb_problem* pb, int finish_mixed)
+{
+    hipStream_t s = pb->ctx->stream;
+    int rc = PB_OK;
+    const size_t nc1 = (size_t)std::max<int64_t>(pb->ncut, 1), na1 = (size_t)std::max<int64_t>(pb->na, 1);
+    if (!pb->F) {
+        pb->F = dalloc<double>(pb, nc1, &rc);
+        if (!rc) pb->phip = dalloc<double>(pb, nc1, &rc);
+        if (!rc) pb->pts = dalloc<double>(pb, 8 * nc1, &rc);
+        if (rc) return rc;
+    }
+    if (!pb->hout) HIPCHK(hipHostMalloc((void**)&pb->hout, 16 * sizeof(double) + sizeof(CGState), hipHostMallocDefault));
+    if (!pb->ev) HIPCHK(hipEventCreateWithFlags(&pb->ev, hipEventDisableTiming));
+    pb->e_nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
+    pb->e_tmp[0] = dalloc<double>(pb, 2 * na1 * (size_t)pb->e_nchunk, &rc);   // partial sums
+    if (!rc) pb->e_tmp[1] = dalloc<double>(pb, na1, &rc);                      // Coulomb potentials
+    if (!rc) pb->e_tmp[2] = dalloc<double>(pb, na1, &rc);                      // reaction potentials
+    if (!rc) pb->e_tmp[3] = dalloc<double>(pb, 16, &rc);                       // energy sums
+    if (rc) return rc;
+    if (finish_mixed) {
+        HIPCHK(launch_ru_add(s, pb->g, pb->st, pb->x, pb->d32, 1));
+        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+                                  pb->part_res, pb->st));
+        HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 0, 0.0, 0.0));
+    }
+    Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    HIPCHK(launch_fill(s, pb->e_tmp[3], 16 * sizeof(double)));
+    HIPCHK(launch_edge_fields(s, pb->g, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
+                              pb->kcut, pb->x, pb->gb, pb->wp, pb->F, pb->phip, pb->pts, pb->rp, pb->np));
+    if (pb->na > 0) {
+        if (pb->ncut > 0)
+            HIPCHK(launch_nbody(s, at, pb->ncut, pb->pts, pb->e_tmp[0], pb->e_nchunk));
+        else
+            HIPCHK(launch_fill(s, pb->e_tmp[0], sizeof(double) * 2 * na1 * (size_t)pb->e_nchunk));
+        HIPCHK(launch_coulomb(s, at, pb->e_tmp[1]));
+        HIPCHK(launch_energy_reduce(s, at, pb->e_tmp[0], pb->e_nchunk, pb->e_tmp[1], pb->prm.eps_in, pb->prm.eps_out,
+                                    pb->lB, pb->e_tmp[2], pb->e_tmp[3], pb->F, pb->ncut, pb->wp));
+    }
+    HIPCHK(hipMemcpyAsync(pb->hout, pb->e_tmp[3], 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pb->hout + 16, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(pb->ev, s));
+    return PB_OK;
+}
+
+int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* stats)
+{
+    for (int t = 0; t < 4; ++t)
+        if (pb->e_tmp[t]) {
+            pb->mem.put(pb->e_tmp[t]);
+            pb->e_tmp[t] = nullptr;
+        }
+    const double* h = pb->hout;
+    memset(out, 0, sizeof *out);
+    out->e_coul = h[0];
+    out->e_pol = h[1];
+    out->e_ion = h[2];
+    out->e_solv = h[1] + h[2];
+    out->e_total = h[0] + h[1] + h[2];
+    out->q_pol_total = h[3];
+    out->area_total = h[4];
+    out->n_cut = pb->ncut;
+    if (stats) {
+        CGState st;
+        memcpy(&st, h + 16, sizeof st);
+        const pb_params& P = pb->prm;
+        memset(stats, 0, sizeof *stats);
+        stats->iters = st.status == 1 ? st.iters : st.iter_count;
+        stats->outer_iters = st.n_ru;
+        const double bn2 = P.rtol > 0 ? st.goal64 / (P.rtol * P.rtol) : 0.0;
+        stats->relres = bn2 > 0 ? std::sqrt(st.rr64 / bn2) : 0.0;
+        stats->status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
+    }
+    return PB_OK;
+}
+
+ProbDev<float> pbi_probdev(pb_problem* pb)
+{
+    ProbDev<float> d;
+    d.g = pb->g;
+    d.ts = pb->ts;
+    d.cf = pb->cf;
+    d.B = bufs<float>(pb);
+    d.x64 = pb->x;
+    d.rhs = pb->rhs;
+    d.ck64 = pb->ck64;
+    d.part3 = pb->part_res;
+    d.nbres = pb->nbres;
+    d.nadd = add_blocks(pb->g);
+    return d;
+}
+
 extern "C" {
 
 const char* pb_last_error(void) { return g_err.c_str(); }
@@ -399,7 +436,52 @@ int pb_ctx_set_profiling(pb_ctx* c, int on)
     return PB_OK;
 }
 
-int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+}  // extern "C"
+
+// ---- coefficient build in three asynchronous phases ----------------------------------------
+// begin:    atoms to the device, cell list, classification, counting of the cut edges; the
+//           two counts come back through pinned memory behind an event
+// continue: (counts known) allocation and the rest of the build, behind an event
+// end:      release of the build temporaries
+// pb_build_coeffs runs the three with waits in between; the serving loop polls the events.
+
+namespace {
+
+void release_tmp(pb_problem* pb)
+{
+    BuildTmp* t = pb->bt;
+    if (!t) return;
+    for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->cls,
+                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full})
+        if (d) pb->mem.put(d);
+    if (t->hpin) (void)hipHostFree(t->hpin);
+    delete t;
+    pb->bt = nullptr;
+}
+
+}  // namespace
+
+void pbi_problem_destroy(pb_problem* pb, bool sync)
+{
+    if (!pb) return;
+    (void)hipSetDevice(pb->ctx->device);
+    if (sync) (void)hipStreamSynchronize(pb->ctx->stream);
+    release_tmp(pb);
+    if (pb->hout) (void)hipHostFree(pb->hout);
+    if (pb->ev) (void)hipEventDestroy(pb->ev);
+    pb->mem.release();
+    delete pb;
+}
+
+int pbi_event_done(pb_problem* pb)
+{
+    const hipError_t e = hipEventQuery(pb->ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return fail(PB_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+}
+
+int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
                     const double* chg, pb_problem** out)
 {
     if (!ctx || !out) return fail(PB_EINVAL, "ctx/out is NULL");
@@ -415,6 +497,8 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     pb->prm.bc_values = nullptr;
     pb->na = na;
     pb->mem.ctx = ctx;
+    pb->bt = new BuildTmp();
+    BuildTmp& T = *pb->bt;
     Grid& g = pb->g;
     g.nx = prm->n[0];
     g.ny = prm->n[1];
@@ -434,9 +518,7 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     pb->cf.mass = prm->h * prm->h * prm->h * prm->eps_out * kd2;
 
     auto bail = [&](int code) {
-        (void)hipStreamSynchronize(s);
-        pb->mem.release();
-        delete pb;
+        pbi_problem_destroy(pb, true);
         return code;
     };
 #define CK(expr)                    \
@@ -451,15 +533,23 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
             return bail(fail(PB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
     } while (0)
 
+    HK(hipEventCreateWithFlags(&pb->ev, hipEventDisableTiming));
     const size_t N = (size_t)g.N;
     const size_t na1 = (size_t)std::max<int64_t>(na, 1);
     pb->xyzr = dalloc<double>(pb, 4 * na1, &rc);
     CK(rc);
     pb->q = dalloc<double>(pb, na1, &rc);
     CK(rc);
-    // host staging of the atoms (x, y, z, R) and the bin geometry
-    std::vector<double> hx(4 * na1, 0.0), hq(na1, 0.0);
+    // pinned staging: atoms (x, y, z, R), charges, and the two counts read back later
+    HK(hipHostMalloc((void**)&T.hpin, sizeof(double) * 5 * na1 + 64, hipHostMallocDefault));
+    double* hx = T.hpin;
+    double* hq = T.hpin + 4 * na1;
+    T.htot = (int*)(T.hpin + 5 * na1);
     double rmax = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (size_t a = 0; a < na1; ++a) {
+        for (int d = 0; d < 4; ++d) hx[4 * a + d] = 0.0;
+        hq[a] = 0.0;
+    }
     for (int64_t a = 0; a < na; ++a) {
         for (int d = 0; d < 3; ++d) {
             hx[4 * a + d] = xyz[3 * a + d];
@@ -470,13 +560,13 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
         hq[a] = chg[a];
         rmax = std::max(rmax, rad[a]);
     }
-    HK(hipMemcpyAsync(pb->xyzr, hx.data(), sizeof(double) * 4 * na1, hipMemcpyHostToDevice, s));
-    HK(hipMemcpyAsync(pb->q, hq.data(), sizeof(double) * na1, hipMemcpyHostToDevice, s));
+    HK(hipMemcpyAsync(pb->xyzr, hx, sizeof(double) * 4 * na1, hipMemcpyHostToDevice, s));
+    HK(hipMemcpyAsync(pb->q, hq, sizeof(double) * na1, hipMemcpyHostToDevice, s));
     Atoms at{(int)na, pb->xyzr, pb->q};
 
     // bins of edge >= R_max + h (and >= 2h) so that the 27 bins around a node or an edge end
     // hold every atom whose ball can touch it
-    Bins bn;
+    Bins& bn = T.bn;
     bn.bs = std::max(rmax + prm->h, 2.0 * prm->h);
     bn.lox = lo[0] - bn.bs;
     bn.loy = lo[1] - bn.bs;
@@ -485,41 +575,66 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     bn.nby = (int)std::floor((hi[1] - bn.loy) / bn.bs) + 2;
     bn.nbz = (int)std::floor((hi[2] - bn.loz) / bn.bs) + 2;
     const int nbins = bn.nbx * bn.nby * bn.nbz;
-    int* bcnt = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    T.bcnt = dalloc<int>(pb, (size_t)nbins + 1, &rc);
     CK(rc);
-    int* bstart = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    T.bstart = dalloc<int>(pb, (size_t)nbins + 1, &rc);
     CK(rc);
-    int* bcur = dalloc<int>(pb, (size_t)nbins + 1, &rc);
+    T.bcur = dalloc<int>(pb, (size_t)nbins + 1, &rc);
     CK(rc);
-    int* bids = dalloc<int>(pb, na1, &rc);
+    T.bids = dalloc<int>(pb, na1, &rc);
     CK(rc);
     if (na > 0) {
-        HK(launch_bins(s, at, bn, bcnt, bstart, bids, bcur));
+        HK(launch_bins(s, at, bn, T.bcnt, T.bstart, T.bids, T.bcur));
     } else {
-        HK(launch_fill(s, bstart, sizeof(int) * ((size_t)nbins + 1)));
-        bn.start = bstart;
-        bn.ids = bids;
+        HK(launch_fill(s, T.bstart, sizeof(int) * ((size_t)nbins + 1)));
+        bn.start = T.bstart;
+        bn.ids = T.bids;
     }
 
-    // classification and ordered compaction of the cut edges
-    uint32_t* cls = dalloc<uint32_t>(pb, N, &rc);
+    // classification and counting of the cut edges
+    T.cls = dalloc<uint32_t>(pb, N, &rc);
     CK(rc);
-    HK(launch_classify(s, g, bn, at, cls));
-    const int nblk = (int)((N + 255) / 256);
-    int* bslots = dalloc<int>(pb, (size_t)nblk + 1, &rc);
+    HK(launch_classify(s, g, bn, at, T.cls));
+    T.nblk = (int)((N + 255) / 256);
+    T.bslots = dalloc<int>(pb, (size_t)T.nblk + 1, &rc);
     CK(rc);
-    int* bcuts = dalloc<int>(pb, (size_t)nblk + 1, &rc);
+    T.bcuts = dalloc<int>(pb, (size_t)T.nblk + 1, &rc);
     CK(rc);
-    int* tot = dalloc<int>(pb, 2, &rc);
+    T.tot = dalloc<int>(pb, 2, &rc);
     CK(rc);
-    HK(launch_cutflags(s, g, cls, bslots, bcuts, nblk));
-    HK(launch_scan2(s, bslots, bcuts, nblk, tot));
-    int htot[2] = {0, 0};
-    HK(hipMemcpyAsync(htot, tot, sizeof htot, hipMemcpyDeviceToHost, s));
-    HK(hipStreamSynchronize(s));
-    pb->nslot = htot[0];
-    pb->ncut = htot[1];
+    HK(launch_cutflags(s, g, T.cls, T.bslots, T.bcuts, T.nblk));
+    HK(launch_scan2(s, T.bslots, T.bcuts, T.nblk, T.tot));
+    HK(hipMemcpyAsync(T.htot, T.tot, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (prm->bc == PB_BC_USER) {
+        const size_t nfull = (size_t)g.nx * g.ny * g.nz;
+        T.full = dalloc<double>(pb, nfull, &rc);
+        CK(rc);
+        HK(hipMemcpy(T.full, prm->bc_values, sizeof(double) * nfull, hipMemcpyHostToDevice));
+    }
+    HK(hipEventRecord(pb->ev, s));
+#undef CK
+#undef HK
+    *out = pb;
+    return PB_OK;
+}
+
+int pbi_build_continue(pb_problem* pb)
+{
+    BuildTmp& T = *pb->bt;
+    const pb_params* prm = &pb->prm;
+    const Grid& g = pb->g;
+    hipStream_t s = pb->ctx->stream;
+    int rc = PB_OK;
+#define CK(expr)                    \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_) return rc_;        \
+    } while (0)
+    pb->nslot = T.htot[0];
+    pb->ncut = T.htot[1];
+    const size_t N = (size_t)g.N;
     const size_t ns1 = (size_t)std::max<int64_t>(pb->nslot, 1), nc1 = (size_t)std::max<int64_t>(pb->ncut, 1);
+    Atoms at{(int)pb->na, pb->xyzr, pb->q};
 
     pb->code = dalloc<uint32_t>(pb, N, &rc);
     CK(rc);
@@ -527,13 +642,13 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     CK(rc);
     pb->cutkey = dalloc<int64_t>(pb, nc1, &rc);
     CK(rc);
-    HK(launch_assign(s, g, cls, pb->code, bslots, bcuts, pb->cutbase, pb->cutkey));
+    HIPCHK(launch_assign(s, g, T.cls, pb->code, T.bslots, T.bcuts, pb->cutbase, pb->cutkey));
     pb->ck64 = dalloc<double>(pb, 3 * ns1, &rc);
     CK(rc);
     pb->ck32 = dalloc<float>(pb, 3 * ns1, &rc);
     CK(rc);
-    HK(launch_fill(s, pb->ck64, sizeof(double) * 3 * ns1));
-    HK(launch_fill(s, pb->ck32, sizeof(float) * 3 * ns1));
+    HIPCHK(launch_fill(s, pb->ck64, sizeof(double) * 3 * ns1));
+    HIPCHK(launch_fill(s, pb->ck32, sizeof(float) * 3 * ns1));
     pb->alpha = dalloc<double>(pb, nc1, &rc);
     CK(rc);
     pb->kcut = dalloc<double>(pb, nc1, &rc);
@@ -546,8 +661,8 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     CK(rc);
     pb->wp = dalloc<double>(pb, nc1, &rc);
     CK(rc);
-    HK(launch_cut_geom(s, g, bn, at, prm->eps_in, prm->eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
-                       pb->kcut, pb->rp, pb->np, pb->owner, pb->ck64, pb->ck32));
+    HIPCHK(launch_cut_geom(s, g, T.bn, at, prm->eps_in, prm->eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
+                           pb->kcut, pb->rp, pb->np, pb->owner, pb->ck64, pb->ck32));
 
     // load vector, boundary values, diagonal and lift
     pb->rhs = dalloc<double>(pb, N, &rc);
@@ -558,22 +673,16 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     CK(rc);
     pb->x = dalloc<double>(pb, N, &rc);
     CK(rc);
-    HK(launch_deposit(s, g, bn, at, pb->rhs));
-    HK(launch_fill(s, pb->gb, sizeof(double) * N));
-    HK(launch_fill(s, pb->x, sizeof(double) * N));
-    if (prm->bc == PB_BC_DH && na > 0) {
-        HK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
+    HIPCHK(launch_deposit(s, g, T.bn, at, pb->rhs));
+    HIPCHK(launch_fill(s, pb->gb, sizeof(double) * N));
+    HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
+    if (prm->bc == PB_BC_DH && pb->na > 0) {
+        HIPCHK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
     } else if (prm->bc == PB_BC_USER) {
-        const size_t nfull = (size_t)g.nx * g.ny * g.nz;
-        double* full = dalloc<double>(pb, nfull, &rc);
-        CK(rc);
-        HK(hipMemcpyAsync(full, prm->bc_values, sizeof(double) * nfull, hipMemcpyHostToDevice, s));
-        HK(launch_bc_user(s, g, full, pb->gb));
-        HK(hipStreamSynchronize(s));
-        pb->mem.put(full);
+        HIPCHK(launch_bc_user(s, g, T.full, pb->gb));
     }
-    HK(launch_diag_lift(s, g, pb->code, pb->ck64, pb->cf, pb->gb, pb->rhs, pb->dinv, nullptr));
-    HK(launch_mc_weights(s, g, pb->code, pb->cutbase, pb->ncut, pb->cutkey, pb->rp, pb->wp));
+    HIPCHK(launch_diag_lift(s, g, pb->code, pb->ck64, pb->cf, pb->gb, pb->rhs, pb->dinv, nullptr));
+    HIPCHK(launch_mc_weights(s, g, pb->code, pb->cutbase, pb->ncut, pb->cutkey, pb->rp, pb->wp));
 
     // solver scalars and partial sums
     pb->nb1 = pb->ts.items;
@@ -589,13 +698,29 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     CK(rc);
     pb->st = dalloc<CGState>(pb, 1, &rc);
     CK(rc);
-    HK(hipStreamSynchronize(s));
-    // temporaries
-    for (void* t : {(void*)bcnt, (void*)bstart, (void*)bcur, (void*)bids, (void*)cls, (void*)bslots,
-                    (void*)bcuts, (void*)tot})
-        pb->mem.put(t);
 #undef CK
-#undef HK
+    HIPCHK(hipEventRecord(pb->ev, s));
+    return PB_OK;
+}
+
+void pbi_build_end(pb_problem* pb) { release_tmp(pb); }
+
+extern "C" {
+
+int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                    const double* chg, pb_problem** out)
+{
+    pb_problem* pb = nullptr;
+    int rc = pbi_build_begin(ctx, prm, na, xyz, rad, chg, &pb);
+    if (rc) return rc;
+    if (hipEventSynchronize(pb->ev) != hipSuccess) rc = fail(PB_EDEVICE, "build: counting failed");
+    if (!rc) rc = pbi_build_continue(pb);
+    if (!rc && hipEventSynchronize(pb->ev) != hipSuccess) rc = fail(PB_EDEVICE, "build failed");
+    if (rc) {
+        pbi_problem_destroy(pb, true);
+        return rc;
+    }
+    pbi_build_end(pb);
     *out = pb;
     return PB_OK;
 }
@@ -611,9 +736,9 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     pb->solved = false;
     pb->prof_stencil_ms = pb->prof_update_ms = 0;
     pb->prof_n = 0;
-    int rc = ensure_cg64(pb);
-    if (rc) return rc;
+    int rc = PB_OK;
     const pb_params& P = pb->prm;
+    if (P.precision == PB_FP64 && (rc = ensure_cg64(pb))) return rc;
     int status = PB_OK;
     CGState st;
     if (P.precision == PB_FP64) {
@@ -625,20 +750,8 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
         stats->iters = st.status == 1 ? st.iters : st.iter_count;
         stats->relres = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
     } else {
-        if ((rc = ensure_cg32(pb))) return rc;
-        const size_t N = (size_t)pb->g.N;
+        if ((rc = pbi_mixed_begin(pb))) return rc;
         CGBufs<float> B = bufs<float>(pb);
-        HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
-        HIPCHK(launch_fill(s, pb->d32, sizeof(float) * N));
-        HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * N));
-        HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * N));
-        HIPCHK(launch_fill(s, pb->q32, sizeof(float) * N));
-        // first "update": r32 = b - A*0, norms, and the mixed iteration state
-        HIPCHK(launch_ru_begin(s, pb->st));
-        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
-                                  pb->part_res, pb->st));
-        HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 1, P.rtol * P.rtol,
-                             P.inner_rtol * P.inner_rtol));
         rc = run_cg<float>(pb, B, P.max_iter, true, &st);
         if (rc) return rc;
         stats->iters = st.status == 1 ? st.iters : st.iter_count;
@@ -668,66 +781,21 @@ int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac)
 {
     if (!pb || !out) return fail(PB_EINVAL, "NULL argument");
     if (!pb->solved) return fail(PB_EINVAL, "pb_energy before a successful pb_solve");
-    memset(out, 0, sizeof *out);
-    pb_ctx* ctx = pb->ctx;
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(pb->ctx->device));
     const double t0 = now_s();
-    int rc = PB_OK;
-    const size_t nc1 = (size_t)std::max<int64_t>(pb->ncut, 1), na1 = (size_t)std::max<int64_t>(pb->na, 1);
-    if (!pb->F) {
-        pb->F = dalloc<double>(pb, nc1, &rc);
-        if (rc) return rc;
-        pb->phip = dalloc<double>(pb, nc1, &rc);
-        if (rc) return rc;
-        pb->pts = dalloc<double>(pb, 8 * nc1, &rc);
-        if (rc) return rc;
-    }
-    Atoms at{(int)pb->na, pb->xyzr, pb->q};
-    const int nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
-    double* partial = dalloc<double>(pb, 2 * na1 * (size_t)nchunk, &rc);
+    int rc = pbi_energy_begin(pb, 0);
     if (rc) return rc;
-    double* phic = dalloc<double>(pb, na1, &rc);
-    double* preac = rc ? nullptr : dalloc<double>(pb, na1, &rc);
-    double* dout = rc ? nullptr : dalloc<double>(pb, 8, &rc);
-    auto cleanup = [&]() {
-        for (void* t : {(void*)partial, (void*)phic, (void*)preac, (void*)dout})
-            if (t) pb->mem.put(t);
-    };
-    if (rc) {
-        cleanup();
-        return rc;
+    if (hipEventSynchronize(pb->ev) != hipSuccess) rc = fail(PB_EDEVICE, "energy kernels failed");
+    if (!rc && phi_reac && pb->na > 0) {
+        hipError_t e = hipMemcpyAsync(phi_reac, pb->e_tmp[2], sizeof(double) * (size_t)pb->na, hipMemcpyDeviceToHost,
+                                      pb->ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pb->ctx->stream);
+        if (e != hipSuccess) rc = fail(PB_EDEVICE, "per-atom copy: %s", hipGetErrorString(e));
     }
-    double h[8] = {0};
-    hipError_t e = launch_edge_fields(s, pb->g, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code,
-                                      pb->alpha, pb->kcut, pb->x, pb->gb, pb->wp, pb->F, pb->phip, pb->pts, pb->rp,
-                                      pb->np);
-    if (e == hipSuccess && pb->na > 0) {
-        if (pb->ncut > 0)
-            e = launch_nbody(s, at, pb->ncut, pb->pts, partial, nchunk);
-        else
-            e = launch_fill(s, partial, sizeof(double) * 2 * na1 * (size_t)nchunk);
-    }
-    if (e == hipSuccess && pb->na > 0) e = launch_coulomb(s, at, phic);
-    if (e == hipSuccess && pb->na > 0)
-        e = launch_energy_reduce(s, at, partial, nchunk, phic, pb->prm.eps_in, pb->prm.eps_out, pb->lB, preac, dout,
-                                 pb->F, pb->ncut, pb->wp);
-    if (e == hipSuccess && pb->na > 0) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && phi_reac && pb->na > 0)
-        e = hipMemcpyAsync(phi_reac, preac, sizeof(double) * (size_t)pb->na, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cleanup();
-    if (e != hipSuccess) return fail(PB_EDEVICE, "energy kernels failed: %s", hipGetErrorString(e));
-    out->e_coul = h[0];
-    out->e_pol = h[1];
-    out->e_ion = h[2];
-    out->e_solv = h[1] + h[2];
-    out->e_total = h[0] + h[1] + h[2];
-    out->q_pol_total = h[3];
-    out->area_total = h[4];
-    out->n_cut = pb->ncut;
+    const int rc2 = pbi_energy_end(pb, out, nullptr);
+    if (!rc) rc = rc2;
     out->t_energy_s = now_s() - t0;
-    return PB_OK;
+    return rc;
 }
 
 int pb_copy_potential(const pb_problem* pb, double* host_phi)
@@ -824,8 +892,7 @@ int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
     if (!pb || !avg_ms || reps <= 0) return fail(PB_EINVAL, "bad argument");
     HIPCHK(hipSetDevice(pb->ctx->device));
     hipStream_t s = pb->ctx->stream;
-    int rc = ensure_cg64(pb);
-    if (!rc && fp32) rc = ensure_cg32(pb);
+    int rc = fp32 ? ensure_cg32(pb) : ensure_cg64(pb);
     if (rc) return rc;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
@@ -894,13 +961,6 @@ int pb_stream_copy(pb_ctx* ctx, size_t bytes, int32_t reps, double* gbps)
 
 size_t pb_problem_bytes(const pb_problem* pb) { return pb ? pb->mem.bytes : 0; }
 
-void pb_problem_free(pb_problem* pb)
-{
-    if (!pb) return;
-    (void)hipSetDevice(pb->ctx->device);
-    (void)hipStreamSynchronize(pb->ctx->stream);
-    pb->mem.release();
-    delete pb;
-}
+void pb_problem_free(pb_problem* pb) { pbi_problem_destroy(pb, true); }
 
 }  // extern "C"

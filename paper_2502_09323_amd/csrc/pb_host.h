@@ -1,0 +1,128 @@
+// pb_host.h -- host-side objects of libpb shared by the C ABI and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <utility>
+#include <vector>
+
+#include "pb_internal.h"
+
+int pbi_fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+struct pb_ctx {
+    int device;
+    hipStream_t stream;
+    pb_alloc_fn alloc;
+    pb_free_fn free_fn;
+    void* user;
+    size_t budget;
+    int profile;
+    pbk::CGState* host_state;  // pinned, 2 slots for pipelined polling
+    hipEvent_t ev[2];
+};
+
+struct DevAlloc {
+    pb_ctx* ctx;
+    std::vector<std::pair<void*, size_t>> held;
+    size_t bytes = 0;
+    void* get(size_t n)
+    {
+        n = (n + 255) & ~(size_t)255;
+        if (n == 0) n = 256;
+        void* p = ctx->alloc(n, ctx->user);
+        if (p) {
+            held.emplace_back(p, n);
+            bytes += n;
+        }
+        return p;
+    }
+    void put(void* p)
+    {
+        for (size_t i = 0; i < held.size(); ++i)
+            if (held[i].first == p) {
+                bytes -= held[i].second;
+                ctx->free_fn(p, ctx->user);
+                held.erase(held.begin() + (long)i);
+                return;
+            }
+    }
+    void release()
+    {
+        for (auto& h : held) ctx->free_fn(h.first, ctx->user);
+        held.clear();
+        bytes = 0;
+    }
+};
+
+// temporaries of an asynchronous coefficient build
+struct BuildTmp {
+    pbk::Bins bn;
+    int *bcnt = nullptr, *bstart = nullptr, *bcur = nullptr, *bids = nullptr;
+    uint32_t* cls = nullptr;
+    int *bslots = nullptr, *bcuts = nullptr, *tot = nullptr;
+    int nblk = 0;
+    double* hpin = nullptr;   // pinned: atoms, charges, then the two counts
+    int* htot = nullptr;
+    double* full = nullptr;   // device copy of user boundary values
+};
+
+struct pb_problem {
+    pb_ctx* ctx;
+    pb_params prm;
+    int64_t na;
+    pbk::Grid g;
+    pbk::TileShape ts;
+    pbk::Coef cf;
+    double lB, kD;
+    DevAlloc mem;
+    // inputs
+    double* xyzr = nullptr;
+    double* q = nullptr;
+    // coefficient maps
+    uint32_t* code = nullptr;
+    float* dinv = nullptr;
+    double* ck64 = nullptr;
+    float* ck32 = nullptr;
+    int* cutbase = nullptr;
+    double* rhs = nullptr;
+    double* gb = nullptr;
+    double* x = nullptr;
+    int64_t ncut = 0, nslot = 0;
+    int64_t* cutkey = nullptr;
+    double *alpha = nullptr, *kcut = nullptr, *rp = nullptr, *np = nullptr, *wp = nullptr;
+    int* owner = nullptr;
+    double *F = nullptr, *phip = nullptr, *pts = nullptr;
+    // CG work
+    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr;
+    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
+    double *part1 = nullptr, *part2 = nullptr, *part_res = nullptr, *scal = nullptr;
+    pbk::CGState* st = nullptr;
+    int nb1 = 0, nb2 = 0, nbres = 0;
+    bool solved = false;
+    BuildTmp* bt = nullptr;      // set while a build is in progress
+    hipEvent_t ev = nullptr;     // marks the end of the last asynchronous phase
+    double* hout = nullptr;      // pinned: energy sums and the final CG state
+    double* e_tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // energy temporaries
+    int e_nchunk = 0;
+
+    // sampled kernel timings of the last solve
+    double prof_stencil_ms = 0, prof_update_ms = 0;
+    int prof_n = 0;
+};
+
+
+// asynchronous phases (all work on the problem's stream; pbi_event_done polls pb->ev)
+int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                    const double* chg, pb_problem** out);
+int pbi_build_continue(pb_problem* pb);
+void pbi_build_end(pb_problem* pb);
+int pbi_event_done(pb_problem* pb);
+void pbi_problem_destroy(pb_problem* pb, bool sync);   // sync=false: its event has completed
+int pbi_energy_begin(pb_problem* pb, int finish_mixed);            // kernels + read-back
+int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* st);
+
+// mixed-form solve split in steps for the serving loop (all work on the problem's stream)
+int pbi_mixed_begin(pb_problem* pb);                              // buffers + first update
+pbk::ProbDev<float> pbi_probdev(pb_problem* pb);

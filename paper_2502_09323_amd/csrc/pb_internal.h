@@ -147,6 +147,28 @@ template <typename T>
 hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B);
 hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes);
 
+// everything a batched launch needs to act for one problem
+template <typename T>
+struct ProbDev {
+    Grid g;
+    TileShape ts;
+    Coef cf;
+    CGBufs<T> B;          // FP32 CG state (x = FP32 correction, r = FP32 residual)
+    double* x64;          // FP64 solution
+    const double* rhs;    // FP64 right-hand side
+    const double* ck64;   // FP64 cut-edge coefficients
+    double* part3;        // reliable-update partial sums [3][nbres]
+    int nbres, nadd;      // block counts of the reliable-update kernels
+};
+
+struct BatchTotals {     // grid sizes of the batched launches (sums over the problems)
+    int st, up, add, res;
+};
+
+hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int* off, int P, const BatchTotals& t,
+                              int iters, CGState* gather_out);
+int add_blocks(const Grid& g);
+
 // mixed precision: FP32 CG with FP64 reliable updates (true residual + solution accumulation)
 hipError_t launch_ru_begin(hipStream_t s, CGState* st);
 hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force);

@@ -1,0 +1,470 @@
+// pb_server.hip -- continuous-batching serving loop for linearized-PB solves.
+//
+// Requests (a molecule and a grid, mixed precision) queue on the host.  A request moves
+// through: queued -> counting -> filling -> resident -> finishing -> done.  Coefficient builds
+// and energy read-backs run on a second stream and each phase ends with an event the loop
+// polls, so the host never blocks on them.  Each step of the loop
+//   1. finishes the older of the two chunks kept in flight and reads every member's state
+//      from one gathered copy;
+//   2. advances builds whose phase has finished, and collects finished read-backs;
+//   3. starts the read-back (final reliable update, energies) of problems that converged (or
+//      ran out of iterations) once no chunk in flight still touches them;
+//   4. starts builds for arrived requests while the resident count and the device-memory
+//      budget allow;
+//   5. launches one chunk for every resident problem: 16 CG iterations as batched launches
+//      (each launch covers the tiles of all problems), then the batched reliable-update
+//      kernels and a gather of all problem states.
+// Every problem's blocks run the code and block numbering of its own solo launch, so a result
+// does not depend on which other problems shared the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <vector>
+
+#include "pb_host.h"
+
+using namespace pbk;
+
+namespace {
+
+constexpr int kChunkIters = 16;   // same chunk length as a solo mixed solve
+
+struct Request {
+    pb_params prm;
+    std::vector<double> xyz, rad, chg, bc;
+    uint64_t id;
+    double arrival;
+    size_t est_bytes;
+};
+
+struct Active {
+    pb_problem* pb;
+    uint64_t id;
+    double arrival;
+    int launched;       // CG iterations launched for it
+    int last_chunk;     // the last chunk that included it
+    bool finished;      // converged, broke down or out of iterations; no more chunks
+    CGState snap;
+};
+
+struct Pending {        // a problem being built or read back on the build stream
+    pb_problem* pb;
+    uint64_t id;
+    double arrival;
+    int phase;          // 1 counting, 2 filling, 3 read-back
+    size_t reserved;    // budget reserved before the build knew its size
+};
+
+struct Result {
+    uint64_t id;
+    pb_energy_out e;
+    pb_solve_stats st;
+    double done;
+    int32_t code;
+};
+
+#define SCHK(expr)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return pbi_fail(PB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+}  // namespace
+
+struct pb_server {
+    pb_ctx* ctx;     // batched iteration stream
+    pb_ctx* bctx;    // build / energy stream
+    int max_resident;
+    size_t budget = 0, in_use = 0;
+    std::deque<Request> queue;
+    std::vector<Active> act;
+    std::vector<Pending> pend;
+    std::vector<Result> done;
+    std::chrono::steady_clock::time_point t0;
+    // per in-flight slot: descriptors, offsets, gathered states (device and pinned host)
+    ProbDev<float>* ddesc[2] = {nullptr, nullptr};
+    int* doff[2] = {nullptr, nullptr};
+    CGState* dgather[2] = {nullptr, nullptr};
+    ProbDev<float>* hdesc[2] = {nullptr, nullptr};
+    int* hoff[2] = {nullptr, nullptr};
+    CGState* hgather[2] = {nullptr, nullptr};
+    int cap[2] = {0, 0};
+    std::vector<uint64_t> members[2];
+    hipEvent_t ev[2];
+    bool inflight[2] = {false, false};
+    int slot_chunk[2] = {-1, -1};
+    int next = 0;
+    int chunk_id = 0;
+    int completed = -1;
+    double t_wait = 0, t_retire = 0, t_admit = 0, t_launch = 0;   // host seconds per phase
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void free_slot(pb_server* s, int k)
+{
+    if (s->ddesc[k]) s->ctx->free_fn(s->ddesc[k], s->ctx->user);
+    if (s->doff[k]) s->ctx->free_fn(s->doff[k], s->ctx->user);
+    if (s->dgather[k]) s->ctx->free_fn(s->dgather[k], s->ctx->user);
+    if (s->hdesc[k]) (void)hipHostFree(s->hdesc[k]);
+    if (s->hoff[k]) (void)hipHostFree(s->hoff[k]);
+    if (s->hgather[k]) (void)hipHostFree(s->hgather[k]);
+    s->ddesc[k] = nullptr;
+    s->doff[k] = nullptr;
+    s->dgather[k] = nullptr;
+    s->hdesc[k] = nullptr;
+    s->hoff[k] = nullptr;
+    s->hgather[k] = nullptr;
+    s->cap[k] = 0;
+}
+
+int ensure_slot(pb_server* s, int k, int P)
+{
+    if (s->cap[k] >= P) return PB_OK;
+    free_slot(s, k);
+    const int c = std::max(P, 8);
+    s->ddesc[k] = (ProbDev<float>*)s->ctx->alloc(sizeof(ProbDev<float>) * c, s->ctx->user);
+    s->doff[k] = (int*)s->ctx->alloc(sizeof(int) * 4 * (c + 1), s->ctx->user);
+    s->dgather[k] = (CGState*)s->ctx->alloc(sizeof(CGState) * c, s->ctx->user);
+    if (!s->ddesc[k] || !s->doff[k] || !s->dgather[k]) return pbi_fail(PB_ENOMEM, "batch descriptors");
+    SCHK(hipHostMalloc((void**)&s->hdesc[k], sizeof(ProbDev<float>) * c, hipHostMallocDefault));
+    SCHK(hipHostMalloc((void**)&s->hoff[k], sizeof(int) * 4 * (c + 1), hipHostMallocDefault));
+    SCHK(hipHostMalloc((void**)&s->hgather[k], sizeof(CGState) * c, hipHostMallocDefault));
+    s->cap[k] = c;
+    return PB_OK;
+}
+
+size_t estimate_bytes(const pb_params& p, int64_t na)
+{
+    const int64_t S = ((p.n[2] + Z0) + 7) / 8 * 8;
+    const int64_t N = (int64_t)p.n[0] * p.n[1] * S;
+    // node data of the mixed form (code, D^-1, b, g, x64, five FP32 vectors) + build scratch
+    return (size_t)N * 56 + (size_t)na * 64 + ((size_t)1 << 20);
+}
+
+// wait for the chunk in slot k and record every member's state
+int complete_slot(pb_server* s, int k)
+{
+    if (!s->inflight[k]) return PB_OK;
+    SCHK(hipEventSynchronize(s->ev[k]));
+    s->inflight[k] = false;
+    s->completed = std::max(s->completed, s->slot_chunk[k]);
+    for (size_t m = 0; m < s->members[k].size(); ++m) {
+        for (auto& a : s->act) {
+            if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
+            a.snap = s->hgather[k][m];
+            const int stt = a.snap.status;
+            if (stt == 1 || stt == 2 || a.launched >= a.pb->prm.max_iter) a.finished = true;
+        }
+    }
+    return PB_OK;
+}
+
+void add_result(pb_server* s, uint64_t id, int code, const pb_energy_out* e, const pb_solve_stats* st)
+{
+    Result r;
+    memset(&r, 0, sizeof r);
+    r.id = id;
+    r.code = code;
+    if (e) r.e = *e;
+    if (st) r.st = *st;
+    r.done = s->now();
+    s->done.push_back(r);
+}
+
+// advance builds and read-backs whose last phase has finished (never blocks)
+int progress(pb_server* s)
+{
+    for (size_t i = 0; i < s->pend.size();) {
+        Pending& p = s->pend[i];
+        const int d = pbi_event_done(p.pb);
+        if (d < 0) return d;
+        if (!d) {
+            ++i;
+            continue;
+        }
+        int rc = PB_OK;
+        if (p.phase == 1) {
+            rc = pbi_build_continue(p.pb);
+            if (!rc) rc = pbi_mixed_begin(p.pb);
+            if (!rc && hipEventRecord(p.pb->ev, p.pb->ctx->stream) != hipSuccess) rc = PB_EDEVICE;
+            if (!rc) {
+                p.phase = 2;
+                ++i;
+                continue;
+            }
+        } else if (p.phase == 2) {
+            pbi_build_end(p.pb);
+            const size_t b = pb_problem_bytes(p.pb);
+            s->in_use = s->in_use - std::min(s->in_use, p.reserved) + b;
+            Active a;
+            memset(&a.snap, 0, sizeof a.snap);
+            a.pb = p.pb;
+            a.id = p.id;
+            a.arrival = p.arrival;
+            a.launched = 0;
+            a.last_chunk = -1;
+            a.finished = false;
+            s->act.push_back(a);
+            s->pend.erase(s->pend.begin() + (long)i);
+            continue;
+        } else {
+            pb_energy_out e;
+            pb_solve_stats st;
+            pbi_energy_end(p.pb, &e, &st);
+            add_result(s, p.id, st.status, &e, &st);
+            s->in_use -= std::min(s->in_use, pb_problem_bytes(p.pb));
+            pbi_problem_destroy(p.pb, false);  // its read-back event has completed
+            s->pend.erase(s->pend.begin() + (long)i);
+            continue;
+        }
+        // a phase failed: report and drop the problem
+        add_result(s, p.id, rc, nullptr, nullptr);
+        s->in_use -= std::min(s->in_use, std::max(p.reserved, pb_problem_bytes(p.pb)));
+        pb_problem_free(p.pb);
+        s->pend.erase(s->pend.begin() + (long)i);
+    }
+    return PB_OK;
+}
+
+// start the read-back of problems that stopped iterating and are in no chunk in flight
+int retire(pb_server* s)
+{
+    for (size_t i = 0; i < s->act.size();) {
+        Active& a = s->act[i];
+        if (!(a.finished && a.last_chunk <= s->completed)) {
+            ++i;
+            continue;
+        }
+        const int rc = pbi_energy_begin(a.pb, 1);
+        if (rc) {
+            add_result(s, a.id, rc, nullptr, nullptr);
+            s->in_use -= std::min(s->in_use, pb_problem_bytes(a.pb));
+            pb_problem_free(a.pb);
+        } else {
+            s->pend.push_back(Pending{a.pb, a.id, a.arrival, 3, 0});
+        }
+        s->act.erase(s->act.begin() + (long)i);
+    }
+    return PB_OK;
+}
+
+int building(const pb_server* s)
+{
+    int n = 0;
+    for (const auto& p : s->pend) n += p.phase < 3;
+    return n;
+}
+
+int admit(pb_server* s)
+{
+    const double t = s->now();
+    while (!s->queue.empty() && s->queue.front().arrival <= t &&
+           (int)s->act.size() + building(s) < s->max_resident) {
+        Request& q = s->queue.front();
+        if (s->budget && q.est_bytes > s->budget) {
+            add_result(s, q.id, PB_ENOMEM, nullptr, nullptr);
+            s->queue.pop_front();
+            continue;
+        }
+        if (s->budget && s->in_use + q.est_bytes > s->budget) break;  // wait for memory
+        pb_params prm = q.prm;
+        prm.bc_values = q.bc.empty() ? nullptr : q.bc.data();
+        pb_problem* pb = nullptr;
+        const int rc = pbi_build_begin(s->bctx, &prm, (int64_t)q.rad.size(), q.xyz.data(), q.rad.data(),
+                                       q.chg.data(), &pb);
+        if (rc != PB_OK) {
+            add_result(s, q.id, rc, nullptr, nullptr);
+            s->queue.pop_front();
+            continue;
+        }
+        s->in_use += q.est_bytes;
+        s->pend.push_back(Pending{pb, q.id, q.arrival, 1, q.est_bytes});
+        s->queue.pop_front();
+    }
+    return PB_OK;
+}
+
+int launch_chunk(pb_server* s, int k)
+{
+    std::vector<Active*> mem;
+    for (auto& a : s->act)
+        if (!a.finished) mem.push_back(&a);
+    const int P = (int)mem.size();
+    s->members[k].clear();
+    if (P == 0) return PB_OK;
+    int rc = ensure_slot(s, k, P);
+    if (rc) return rc;
+    BatchTotals t{0, 0, 0, 0};
+    int* o = s->hoff[k];
+    for (int p = 0; p < P; ++p) {
+        const ProbDev<float> d = pbi_probdev(mem[p]->pb);
+        s->hdesc[k][p] = d;
+        o[p] = t.st;
+        o[(P + 1) + p] = t.up;
+        o[2 * (P + 1) + p] = t.add;
+        o[3 * (P + 1) + p] = t.res;
+        t.st += d.ts.items;
+        t.up += d.B.nb2;
+        t.add += d.nadd;
+        t.res += d.nbres;
+        s->members[k].push_back(mem[p]->id);
+    }
+    o[P] = t.st;
+    o[(P + 1) + P] = t.up;
+    o[2 * (P + 1) + P] = t.add;
+    o[3 * (P + 1) + P] = t.res;
+    hipStream_t st = s->ctx->stream;
+    SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 4 * (P + 1), hipMemcpyHostToDevice, st));
+    SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k]));
+    SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * P, hipMemcpyDeviceToHost, st));
+    SCHK(hipEventRecord(s->ev[k], st));
+    s->inflight[k] = true;
+    s->slot_chunk[k] = s->chunk_id;
+    for (auto* a : mem) {
+        a->launched += kChunkIters;
+        a->last_chunk = s->chunk_id;
+    }
+    s->chunk_id++;
+    return PB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pb_server_create(pb_ctx* ctx, pb_ctx* build_ctx, int32_t max_resident, pb_server** out)
+{
+    if (!ctx || !build_ctx || !out || max_resident <= 0) return pbi_fail(PB_EINVAL, "bad argument");
+    if (ctx->device != build_ctx->device) return pbi_fail(PB_EINVAL, "contexts on different devices");
+    *out = nullptr;
+    SCHK(hipSetDevice(ctx->device));
+    pb_server* s = new pb_server();
+    s->ctx = ctx;
+    s->bctx = build_ctx;
+    s->max_resident = max_resident;
+    s->budget = ctx->budget;
+    s->t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) != hipSuccess) {
+            delete s;
+            return pbi_fail(PB_EDEVICE, "hipEventCreate failed");
+        }
+    *out = s;
+    return PB_OK;
+}
+
+double pb_server_now(const pb_server* s) { return s ? s->now() : 0.0; }
+
+int pb_submit(pb_server* s, const pb_params* prm, int64_t n_atoms, const double* xyz, const double* radius,
+              const double* charge, uint64_t request_id, double arrival_time_s)
+{
+    if (!s || !prm) return pbi_fail(PB_EINVAL, "NULL argument");
+    if (prm->precision != PB_MIXED) return pbi_fail(PB_EINVAL, "the serving loop runs the mixed form only");
+    if (n_atoms < 0 || (n_atoms > 0 && (!xyz || !radius || !charge))) return pbi_fail(PB_EINVAL, "bad atoms");
+    Request q;
+    q.prm = *prm;
+    q.xyz.assign(xyz, xyz + 3 * n_atoms);
+    q.rad.assign(radius, radius + n_atoms);
+    q.chg.assign(charge, charge + n_atoms);
+    if (prm->bc == PB_BC_USER && prm->bc_values) {
+        const size_t nf = (size_t)prm->n[0] * prm->n[1] * prm->n[2];
+        q.bc.assign(prm->bc_values, prm->bc_values + nf);
+    }
+    q.prm.bc_values = nullptr;
+    q.id = request_id;
+    q.arrival = arrival_time_s;
+    q.est_bytes = estimate_bytes(*prm, n_atoms);
+    s->queue.push_back(std::move(q));
+    return PB_OK;
+}
+
+int pb_server_step(pb_server* s, int32_t* n_active, int32_t* n_queued)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    SCHK(hipSetDevice(s->ctx->device));
+    const int k = s->next;
+    double t = s->now(), t2;
+    int rc = complete_slot(s, k);  // the slot about to be reused holds the older chunk
+    t2 = s->now(); s->t_wait += t2 - t; t = t2;
+    if (!rc) rc = progress(s);
+    if (!rc) rc = retire(s);
+    t2 = s->now(); s->t_retire += t2 - t; t = t2;
+    if (!rc) rc = admit(s);
+    t2 = s->now(); s->t_admit += t2 - t; t = t2;
+    if (!rc) rc = launch_chunk(s, k);
+    t2 = s->now(); s->t_launch += t2 - t; t = t2;
+    if (rc) return rc;
+    if (s->inflight[k]) {
+        s->next ^= 1;
+    } else if (s->inflight[k ^ 1]) {
+        // nothing new to launch: drain the other chunk so its finished problems can retire
+        if ((rc = complete_slot(s, k ^ 1))) return rc;
+        if ((rc = retire(s))) return rc;
+        t2 = s->now(); s->t_wait += t2 - t; t = t2;
+    } else if (!s->pend.empty()) {
+        // only builds or read-backs are pending: wait for the oldest instead of spinning
+        (void)hipEventSynchronize(s->pend.front().pb->ev);
+        if ((rc = progress(s))) return rc;
+        t2 = s->now(); s->t_wait += t2 - t; t = t2;
+    }
+    if (n_active) *n_active = (int32_t)(s->act.size() + s->pend.size());
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return PB_OK;
+}
+
+int pb_poll(pb_server* s, uint64_t* ids, pb_energy_out* results, pb_solve_stats* stats, double* done_time_s,
+            int32_t* codes, int32_t max, int32_t* n_done)
+{
+    if (!s || !n_done || max < 0) return pbi_fail(PB_EINVAL, "bad argument");
+    const int n = std::min<int>(max, (int)s->done.size());
+    for (int i = 0; i < n; ++i) {
+        const Result& r = s->done[i];
+        if (ids) ids[i] = r.id;
+        if (results) results[i] = r.e;
+        if (stats) stats[i] = r.st;
+        if (done_time_s) done_time_s[i] = r.done;
+        if (codes) codes[i] = r.code;
+    }
+    s->done.erase(s->done.begin(), s->done.begin() + n);
+    *n_done = n;
+    return PB_OK;
+}
+
+int pb_server_times(const pb_server* s, double* out4)
+{
+    if (!s || !out4) return pbi_fail(PB_EINVAL, "NULL argument");
+    out4[0] = s->t_wait;
+    out4[1] = s->t_retire;
+    out4[2] = s->t_admit;
+    out4[3] = s->t_launch;
+    return PB_OK;
+}
+
+void pb_server_destroy(pb_server* s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    (void)hipStreamSynchronize(s->bctx->stream);
+    for (auto& a : s->act) pb_problem_free(a.pb);
+    for (auto& p : s->pend) pb_problem_free(p.pb);
+    for (int k = 0; k < 2; ++k) {
+        free_slot(s, k);
+        (void)hipEventDestroy(s->ev[k]);
+    }
+    delete s;
+}
+
+}  // extern "C"

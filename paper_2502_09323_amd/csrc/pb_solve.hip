@@ -91,7 +91,8 @@ struct K3 {    // coefficients of the +x, +y, +z edges of a node
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf)
+__device__ __forceinline__ void stencil_body(const Grid& g, const TileShape& ts, const CGBufs<T>& B, const Coef& cf,
+                                             const int bid)
 {
     constexpr int RY = TY / 4;
     __shared__ double sh[8];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
         rr += B.part2[B.nb2 + t];
     }
     block_sum2(rz, rr, sh);
-    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool first = bid == 0 && threadIdx.x == 0;
     if (rr <= st->stop2) {
         if (first) {
             st->status = st->stop_status;
@@ -131,7 +132,7 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     const T kin = (T)cf.kin, kout = (T)cf.kout, mass = (T)cf.mass;
 
     // XCD-aware bijective block -> tile map (blocks are dealt round-robin to 8 XCDs)
-    const int W = ts.items, b = blockIdx.x;
+    const int W = ts.items, b = bid;
     const int q8 = W >> 3, rem = W & 7, xcd = b & 7;
     const int item = xcd * q8 + (xcd < rem ? xcd : rem) + (b >> 3);
     const int kt = item % ts.nkt;
@@ -290,7 +291,13 @@ __global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs
     }
     double a = (double)acc, dummy = 0.0;
     block_sum2(a, dummy, sh);
-    if (threadIdx.x == 0) B.part1[blockIdx.x] = a;
+    if (threadIdx.x == 0) B.part1[bid] = a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf)
+{
+    stencil_body(g, ts, B, cf, (int)blockIdx.x);
 }
 
 template <typename T>
@@ -305,7 +312,7 @@ struct Vec4<float> {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
+__device__ __forceinline__ void update_body(int64_t n4, const CGBufs<T>& B, const int bid, const int nblk)
 {
     __shared__ double sh[8];
     CGState* st = B.st;
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
     double pq = 0.0, dummy = 0.0;
     for (int t = threadIdx.x; t < B.nb1; t += 256) pq += B.part1[t];
     block_sum2(pq, dummy, sh);
-    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool first = bid == 0 && threadIdx.x == 0;
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (first) {
             st->status = 2;
@@ -330,8 +337,8 @@ __global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
     const V* __restrict__ q = reinterpret_cast<const V*>(B.q);
     const float4* __restrict__ dv = reinterpret_cast<const float4*>(B.dinv);
     T rz = (T)0, rr = (T)0;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+    const int64_t stride = (int64_t)nblk * 256;
+    for (int64_t v = (int64_t)bid * 256 + threadIdx.x; v < n4; v += stride) {
         V xv = x[v], rv = r[v];
         const V pv = p[v], qv = q[v];
         const float4 d = dv[v];
@@ -345,10 +352,16 @@ __global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
     double a = (double)rz, c = (double)rr;
     block_sum2(a, c, sh);
     if (threadIdx.x == 0) {
-        B.part2[blockIdx.x] = a;
-        B.part2[B.nb2 + blockIdx.x] = c;
+        B.part2[bid] = a;
+        B.part2[B.nb2 + bid] = c;
     }
     if (first) st->iter_count += 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
+{
+    update_body(n4, B, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <typename T>
@@ -429,31 +442,37 @@ __global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CG
 // recursive residual has dropped by delta since the last one, or when the recursive residual
 // reaches the target (the stencil kernel then stops with status 3).
 
-__global__ void __launch_bounds__(256) k_ru_add(int64_t n4, CGState* st, double* x, float* d, int force)
+__device__ __forceinline__ void ru_add_body(int64_t n4, CGState* st, double* x, float* d, int force, const int bid,
+                                            const int nblk)
 {
     const int s0 = st->status;
     const bool go = (s0 == 3) || (s0 == 0 && (force || st->rr <= st->trig2));
     if (!go) return;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
+    const int64_t stride = (int64_t)nblk * 256;
+    for (int64_t v = (int64_t)bid * 256 + threadIdx.x; v < n4; v += stride) {
         double4 xv = reinterpret_cast<double4*>(x)[v];
         const float4 dv = reinterpret_cast<const float4*>(d)[v];
         xv.x += (double)dv.x; xv.y += (double)dv.y; xv.z += (double)dv.z; xv.w += (double)dv.w;
         reinterpret_cast<double4*>(x)[v] = xv;
         reinterpret_cast<float4*>(d)[v] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->ru = 1;
+    if (bid == 0 && threadIdx.x == 0) st->ru = 1;
 }
 
-__global__ void __launch_bounds__(256) k_ru_residual(Grid g, const uint32_t* __restrict__ code,
-                                                     const double* __restrict__ ck, Coef cf,
-                                                     const double* __restrict__ b, const double* __restrict__ x,
-                                                     const float* __restrict__ dinv, float* __restrict__ r32,
-                                                     double* __restrict__ part3, CGState* st)
+__global__ void __launch_bounds__(256) k_ru_add(int64_t n4, CGState* st, double* x, float* d, int force)
+{
+    ru_add_body(n4, st, x, d, force, (int)blockIdx.x, (int)gridDim.x);
+}
+
+__device__ __forceinline__ void ru_residual_body(const Grid& g, const uint32_t* __restrict__ code,
+                                                 const double* __restrict__ ck, const Coef& cf,
+                                                 const double* __restrict__ b, const double* __restrict__ x,
+                                                 const float* __restrict__ dinv, float* __restrict__ r32,
+                                                 double* __restrict__ part3, CGState* st, const int bid, const int nblk)
 {
     __shared__ double sh[8];
     if (!st->ru) return;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = (int64_t)bid * 256 + threadIdx.x;
     double rr64 = 0.0;
     float rz32 = 0.0f, rr32 = 0.0f;
     if (e < g.N) {
@@ -483,10 +502,19 @@ __global__ void __launch_bounds__(256) k_ru_residual(Grid g, const uint32_t* __r
     double dummy = 0.0;
     block_sum2(rr64, dummy, sh);
     if (threadIdx.x == 0) {
-        part3[blockIdx.x] = rr64;
-        part3[gridDim.x + blockIdx.x] = a;
-        part3[2 * gridDim.x + blockIdx.x] = c2;
+        part3[bid] = rr64;
+        part3[nblk + bid] = a;
+        part3[2 * nblk + bid] = c2;
     }
+}
+
+__global__ void __launch_bounds__(256) k_ru_residual(Grid g, const uint32_t* __restrict__ code,
+                                                     const double* __restrict__ ck, Coef cf,
+                                                     const double* __restrict__ b, const double* __restrict__ x,
+                                                     const float* __restrict__ dinv, float* __restrict__ r32,
+                                                     double* __restrict__ part3, CGState* st)
+{
+    ru_residual_body(g, code, ck, cf, b, x, dinv, r32, part3, st, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ void k_ru_begin(CGState* st)
@@ -496,8 +524,8 @@ __global__ void k_ru_begin(CGState* st)
 }
 
 // one block: finish a reliable update (or, with init, set up the mixed iteration)
-__global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3, int nbres, double* part2,
-                                                int nb2, int init, double rtol2, double delta2)
+__device__ __forceinline__ void ru_fin_body(CGState* st, const double* part3, int nbres, double* part2, int nb2,
+                                            int init, double rtol2, double delta2)
 {
     __shared__ double sh[8];
     if (!st->ru) return;
@@ -544,6 +572,12 @@ __global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3
     }
 }
 
+__global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3, int nbres, double* part2,
+                                                int nb2, int init, double rtol2, double delta2)
+{
+    ru_fin_body(st, part3, nbres, part2, nb2, init, rtol2, delta2);
+}
+
 // plain streaming copy with non-temporal accesses: the attainable-bandwidth reference (and the
 // kernel used to scale the HBM byte counters)
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -556,7 +590,85 @@ __global__ void __launch_bounds__(256) k_stream_copy(const f4v* __restrict__ a, 
     }
 }
 
+// ---- batched launches: one launch advances every resident problem ---------------------------
+// Block b of a batched launch belongs to the problem p with off[p] <= b < off[p+1] and acts as
+// block b - off[p] of that problem's own launch, so each problem computes exactly what it
+// computes when solved alone.
+
+__device__ __forceinline__ int find_prob(const int* __restrict__ off, int P, int b)
+{
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_stencil(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
+{
+    const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
+    const ProbDev<T>& d = D[p];
+    stencil_body(d.g, d.ts, d.B, d.cf, (int)blockIdx.x - off[p]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_update(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
+{
+    const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
+    const ProbDev<T>& d = D[p];
+    update_body(d.g.N / 4, d.B, (int)blockIdx.x - off[p], d.B.nb2);
+}
+
+__global__ void __launch_bounds__(256) kb_ru_add(const ProbDev<float>* __restrict__ D, const int* __restrict__ off, int P)
+{
+    const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
+    const ProbDev<float>& d = D[p];
+    ru_add_body(d.g.N / 4, d.B.st, d.x64, d.B.x, 0, (int)blockIdx.x - off[p], d.nadd);
+}
+
+__global__ void __launch_bounds__(256) kb_ru_residual(const ProbDev<float>* __restrict__ D, const int* __restrict__ off,
+                                                      int P)
+{
+    const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
+    const ProbDev<float>& d = D[p];
+    ru_residual_body(d.g, d.B.code, d.ck64, d.cf, d.rhs, d.x64, d.B.dinv, d.B.r, d.part3, d.B.st,
+                     (int)blockIdx.x - off[p], d.nbres);
+}
+
+__global__ void __launch_bounds__(256) kb_ru_fin(const ProbDev<float>* __restrict__ D)
+{
+    const ProbDev<float>& d = D[blockIdx.x];
+    ru_fin_body(d.B.st, d.part3, d.nbres, d.B.part2, d.B.nb2, 0, 0.0, 0.0);
+}
+
+__global__ void kb_gather(const ProbDev<float>* __restrict__ D, int P, CGState* out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) out[p] = *D[p].B.st;
+}
+
 }  // namespace
+
+hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int* off, int P, const BatchTotals& t,
+                              int iters, CGState* gather_out)
+{
+    const int* off_st = off;
+    const int* off_up = off + (P + 1);
+    const int* off_add = off + 2 * (P + 1);
+    const int* off_res = off + 3 * (P + 1);
+    for (int it = 0; it < iters; ++it) {
+        kb_stencil<float><<<t.st, 256, 0, s>>>(D, off_st, P);
+        kb_update<float><<<t.up, 256, 0, s>>>(D, off_up, P);
+    }
+    kb_ru_add<<<t.add, 256, 0, s>>>(D, off_add, P);
+    kb_ru_residual<<<t.res, 256, 0, s>>>(D, off_res, P);
+    kb_ru_fin<<<P, 256, 0, s>>>(D);
+    kb_gather<<<(P + 63) / 64, 64, 0, s>>>(D, P, gather_out);
+    return hipGetLastError();
+}
 
 hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes)
 {
@@ -635,12 +747,15 @@ template hipError_t launch_cg_update<float>(hipStream_t, const Grid&, const CGBu
 
 int residual_blocks(const Grid& g) { return (int)((g.N + 255) / 256); }
 
+int add_blocks(const Grid& g)
+{
+    int64_t nb = (g.N / 4 + 255) / 256;
+    return (int)(nb > 4096 ? 4096 : (nb < 1 ? 1 : nb));
+}
+
 hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force)
 {
-    const int64_t n4 = g.N / 4;
-    int64_t nb = (n4 + 255) / 256;
-    if (nb > 4096) nb = 4096;
-    k_ru_add<<<(unsigned)nb, 256, 0, s>>>(n4, st, x64, d32, force);
+    k_ru_add<<<(unsigned)add_blocks(g), 256, 0, s>>>(g.N / 4, st, x64, d32, force);
     return hipGetLastError();
 }
 

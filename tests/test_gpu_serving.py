@@ -1,0 +1,110 @@
+"""Serving loop on the GPU: continuous batching must not change any result.
+
+Each request's energies and iteration count in the mix are compared bit for bit with the
+same request solved alone through pb_solve; admission honours the memory budget; requests
+are not admitted before their arrival time."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_09323_amd import binding as B
+from paper_2502_09323_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    import torch
+
+    B.load()
+    main = B.Context(0)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    yield main, side
+    main.close()
+    side.close()
+
+
+def small_stream(n=10, seed=7):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        na = int(rng.integers(20, 400))
+        R = 3.0 + 4.0 * (na / 400) ** (1 / 3)
+        h = float(rng.choice([0.4, 0.5, 0.6]))
+        nn = int(2 * (R + 3.0) / h) + 5
+        mol = I.random_molecule(na, R, 1000 + k)
+        grid = I.cubic_grid(nn, h, precision=I.MIXED, rtol=1e-8, inner_rtol=1e-2)
+        reqs.append((mol, grid))
+    return reqs
+
+
+def run_server(srv, reqs, arrivals=None, timeout_s=60.0):
+    for i, (mol, grid) in enumerate(reqs):
+        srv.submit(mol, grid, i, None if arrivals is None else arrivals[i])
+    out = {}
+    t0 = time.time()
+    while len(out) < len(reqs):
+        srv.step()
+        for r in srv.poll():
+            out[r["id"]] = r
+        assert time.time() - t0 < timeout_s, "serving loop did not finish"
+    return out
+
+
+def test_mix_equals_alone_bitwise(ctxs):
+    main, side = ctxs
+    reqs = small_stream()
+    srv = B.Server(main, side, max_resident=4)
+    served = run_server(srv, reqs)
+    srv.close()
+    for i, (mol, grid) in enumerate(reqs):
+        r = served[i]
+        assert r["code"] == 0
+        alone = B.solve(mol, grid, main)
+        for k in ("e_pol", "e_ion", "e_coul", "q_pol_total", "area_total"):
+            assert r[k] == alone[k], (i, k, r[k], alone[k])
+        assert r["iters"] == alone["iters"] and r["outer_iters"] == alone["outer_iters"]
+
+
+def test_served_energies_match_fp64_oracle(ctxs):
+    main, side = ctxs
+    reqs = small_stream(n=4, seed=11)
+    srv = B.Server(main, side, max_resident=8)
+    served = run_server(srv, reqs)
+    srv.close()
+    for i, (mol, grid) in enumerate(reqs):
+        ref = O.run(mol, grid, rtol=1e-12).energy
+        for k in ("e_pol", "e_ion"):
+            assert abs(served[i][k] - ref[k]) <= 1e-6 * abs(ref[k]), (i, k)
+
+
+def test_budget_admission_and_rejection(ctxs):
+    import torch
+
+    main_tight = B.Context(0, hbm_budget_bytes=60 << 20)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    reqs = small_stream(n=4, seed=3)
+    big = (I.random_molecule(50, 4.0, 9), I.cubic_grid(161, 0.25, precision=I.MIXED, rtol=1e-6))
+    srv = B.Server(main_tight, side, max_resident=8)
+    served = run_server(srv, reqs + [big])
+    srv.close()
+    assert all(served[i]["code"] == 0 for i in range(4))
+    assert served[4]["code"] == B.PB_ENOMEM
+    main_tight.close()
+    side.close()
+
+
+def test_future_arrivals_wait(ctxs):
+    main, side = ctxs
+    reqs = small_stream(n=3, seed=5)
+    srv = B.Server(main, side, max_resident=4)
+    t = srv.now()
+    arrivals = [t, t + 0.3, t + 0.6]
+    served = run_server(srv, reqs, arrivals)
+    srv.close()
+    for i in range(3):
+        assert served[i]["code"] == 0
+        assert served[i]["done_s"] >= arrivals[i]
