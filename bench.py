@@ -1,22 +1,27 @@
 """Benchmark of the MI355X linearized Poisson-Boltzmann grid solve.
 
-One step = one whole pass of the hot path on one synthetic molecule: coefficient maps
-(build), Jacobi-PCG solve, and the energy read-back, i.e. one PBE solve.  The default
-workload is the 2,000-atom synthetic molecule on a 161^3 grid at 0.5 A.  The timed form is
-the mixed FP32-inner / FP64-refinement solve at the residual tolerance that keeps the
-energies within 1e-6 of the FP64 result; the plain FP64 solve at the tolerance with the
-same energy error is timed beside it.
+Default workload: the serving stream -- 512 synthetic molecules (200-20,000 atoms,
+log-uniform), grids 65^3-257^3 at h in {0.5, 0.75, 1.0} A, all in the mixed form (FP32 CG,
+FP64 reliable updates and energies).  One step = the whole stream through the
+continuous-batching server with every request present at t=0 (closed loop); value = solves/s
+of that step.  Also reported: p50/p99 latency of the same stream with Poisson arrivals at
+0.8x that rate (open loop), the same 512 requests solved one at a time in plain FP64
+(throughput, and latency under the same arrivals), the energy error of every served result,
+PCG Gnode-iter/s of the 385^3 single solve in FP64 and mixed form, the roofline of the
+dominant kernel, and the CPU oracle on a bounded sample.
 
-Prints ONE JSON line (see the fields below).
+Other workloads (--workload c1|c2|c4) time single solves (build + solve + energy).
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
+from dataclasses import replace
 
 import numpy as np
 
@@ -28,82 +33,281 @@ from paper_2502_09323_amd import inputs as I  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 METRIC = "PBE solves/s + p99 latency at 1e-6 energy err; PCG Gnode-iter/s vs FP64 plain"
 
-# residual tolerance that keeps |dE/E| <= 1e-6 for the energies of the synthetic molecules
-# (measured against FP64 solves at 1e-12; both forms use it, so they are compared at equal
-# energy error), and the reliable-update factor of the mixed form
-RTOL_FP64 = 2e-7
-RTOL_MIXED = 2e-7
-INNER_RTOL = 1e-2
+# Residual tolerance that keeps |dE/E| <= 1e-6 (both forms use it, so they are compared at
+# equal energy error), and the reliable-update factor of the mixed form.
+RTOL = 5e-8
+DELTA = 1e-2
+N_REQ = 512
+SEED = 2505
+MAX_RESIDENT = 32
+OPEN_LOOP_LOAD = 0.8
 
 
-def workload(name: str):
-    if name == "c1":
-        mol, grid = I.kirkwood_c1()
-        return mol, grid, "kirkwood sphere R=2A q=+1e, 65^3 nodes, h=0.25A"
-    if name == "c2":
-        mol, grid = I.protein_c2()
-        return mol, grid, "synthetic 2000-atom molecule in a 20A ball, 161^3 nodes, h=0.5A"
-    if name == "c4":
-        mol, grid = I.large_c4()
-        return mol, grid, "synthetic 60000-atom molecule in a 65A ball, 385^3 nodes, h=0.5A"
-    raise SystemExit(f"unknown workload {name}")
-
-
-def stencil_bytes_per_node(fp32: bool) -> int:
-    # r, p_old, p_new, q (T) + dinv (f32) + node code (u32)
-    t = 4 if fp32 else 8
-    return 4 * t + 4 + 4
-
-
-def run_steps(ctx, B, mol, grid, steps, warmup, profile):
-    import torch
-
-    lat, res = [], []
-    for s in range(warmup + steps):
-        timed = s >= warmup
-        ctx.set_profiling(profile and timed)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pb = B.Problem(ctx, mol, grid)
-        st = pb.solve()
-        en = pb.energy()
-        prof = pb.profile() if (profile and timed) else None
-        pb.close()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if timed:
-            lat.append(t1 - t0)
-            res.append((st, en, prof))
-    ctx.set_profiling(False)
-    return lat, res
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def relerr(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-def cpu_baseline(mol, grid, rtol):
+def pct(x, q):
+    return float(np.percentile(np.asarray(x), q))
+
+
+# ---- serving stream ---------------------------------------------------------------------------
+
+def stream(n):
+    reqs = I.serving_stream_c5(n_req=n, seed=SEED, rate_hz=1.0, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA)
+    unit_arrivals = np.array([r[0] for r in reqs])  # Poisson process at 1 request/s
+    return [(m, g) for _, m, g in reqs], unit_arrivals
+
+
+def serve(B, main, side, reqs, arrivals=None):
+    """Run requests through a fresh server; returns (results by id, wall seconds, server)."""
+    srv = B.Server(main, side, max_resident=MAX_RESIDENT)
+    t0 = srv.now()
+    for i, (mol, g) in enumerate(reqs):
+        srv.submit(mol, g, i, t0 if arrivals is None else t0 + float(arrivals[i]))
+    out = {}
+    while len(out) < len(reqs):
+        srv.step()
+        for r in srv.poll():
+            r["latency_s"] = r["done_s"] - (t0 if arrivals is None else t0 + float(arrivals[r["id"]]))
+            out[r["id"]] = r
+    wall = srv.now() - t0
+    return out, wall, srv
+
+
+def fifo_latency(arrivals, service):
+    """Latency of a single FIFO server with the given arrivals and service times."""
+    free = 0.0
+    lat = []
+    for a, s in zip(arrivals, service):
+        start = max(a, free)
+        free = start + s
+        lat.append(free - a)
+    return np.array(lat)
+
+
+def bench_serving(args, B, torch):
+    main = B.Context(0)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    copy_gbs = main.stream_copy_gbps(1 << 30, 20)
+    reqs, unit_arr = stream(N_REQ)
+    nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
+    log(f"generated {N_REQ} requests")
+
+    # warmup: the first requests through a server (untimed)
+    for _ in range(args.warmup):
+        serve(B, main, side, reqs[:32])[2].close()
+
+    # timed: the whole stream, closed loop
+    main.set_profiling(True)
+    walls, res = [], None
+    prof = dict(stencil_ms=0.0, stencil_bytes=0.0, launches=0)
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        res, wall, srv = serve(B, main, side, reqs)
+        torch.cuda.synchronize()
+        p = srv.profile()
+        for k in prof:
+            prof[k] += p[k]
+        srv.close()
+        walls.append(wall)
+    main.set_profiling(False)
+    value = N_REQ / float(np.mean(walls))
+    codes = sorted({r["code"] for r in res.values()})
+    log(f"closed loop: {value:.2f} solves/s")
+
+    # open loop: Poisson arrivals at OPEN_LOOP_LOAD x the closed-loop rate
+    rate = OPEN_LOOP_LOAD * value
+    arr = unit_arr / rate
+    res_open, wall_open, srv = serve(B, main, side, reqs, arr)
+    srv.close()
+    lat_open = [res_open[i]["latency_s"] for i in range(N_REQ)]
+    log(f"open loop at {rate:.2f}/s done")
+
+    # baseline: one at a time, plain FP64, same tolerance (same energy error)
+    svc, e64 = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for mol, g in reqs:
+        t = time.perf_counter()
+        r = B.solve(mol, replace(g, precision=I.FP64), main)
+        svc.append(time.perf_counter() - t)
+        e64.append(r)
+    t_fp64 = time.perf_counter() - t0
+    log(f"fp64 one at a time: {N_REQ / t_fp64:.2f} solves/s")
+    lat64 = fifo_latency(arr, svc)
+    err_mix_vs_64 = max(max(relerr(res[i][k], e64[i][k]) for k in ("e_pol", "e_ion")) for i in range(N_REQ))
+
+    # energy error against tight FP64 solves on a sample of the stream
+    sample = list(range(0, N_REQ, N_REQ // 16))
+    err_ref = 0.0
+    for i in sample:
+        mol, g = reqs[i]
+        ref = B.solve(mol, replace(g, precision=I.FP64, rtol=1e-12), main)
+        err_ref = max(err_ref, max(relerr(res[i][k], ref[k]) for k in ("e_pol", "e_ion")))
+
+    # precision comparison on the 385^3 single solve
+    mol4, g4 = I.large_c4()
+    c4 = {}
+    for name, prec in (("mixed", I.MIXED), ("fp64", I.FP64)):
+        g = replace(g4, precision=prec, rtol=RTOL, inner_rtol=DELTA)
+        B.solve(mol4, g, main)  # warm
+        r = B.solve(mol4, g, main)
+        c4[name] = dict(gnode_iter_per_s=round(g4.unknowns * r["iters"] / r["t_solve_s"] / 1e9, 3),
+                        iters=r["iters"], t_solve_ms=round(1e3 * r["t_solve_s"], 2))
+
+    log("precision comparison done")
+    achieved = prof["stencil_bytes"] / (prof["stencil_ms"] * 1e-3) / 1e9 if prof["stencil_ms"] > 0 else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                "kernel": "kb_stencil<float> (batched FP32 stencil)",
+                "bytes_per_launch": round(prof["stencil_bytes"] / max(prof["launches"], 1)),
+                "avg_launch_ms": round(prof["stencil_ms"] / max(prof["launches"], 1), 5),
+                "launches_timed": prof["launches"]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_stream(reqs)
+
+    lat_closed = [r["latency_s"] for r in res.values()]
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * float(np.mean(walls)), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 CG + f64 reliable updates/energy",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {N_REQ} synthetic molecules (200-20000 atoms, log-uniform), "
+                               f"grids 65^3-257^3, h in {{0.5,0.75,1.0}} A, mixed precision",
+                   "n_requests": N_REQ, "seed": SEED, "rtol": RTOL, "reliable_update_factor": DELTA,
+                   "max_resident": MAX_RESIDENT, "unknowns_total": float(nu.sum()),
+                   "atoms_total": int(sum(m.n for m, _ in reqs))},
+        "served_closed_loop": {"solves_per_s": round(value, 3), "p50_s": round(pct(lat_closed, 50), 3),
+                               "p99_s": round(pct(lat_closed, 99), 3), "codes": codes},
+        "served_open_loop": {"arrival_rate_hz": round(rate, 3), "solves_per_s": round(N_REQ / wall_open, 3),
+                             "p50_ms": round(1e3 * pct(lat_open, 50), 1), "p99_ms": round(1e3 * pct(lat_open, 99), 1)},
+        "fp64_one_at_a_time": {"solves_per_s": round(N_REQ / t_fp64, 3), "mean_service_ms": round(1e3 * float(np.mean(svc)), 2),
+                               "p50_ms_same_arrivals": round(1e3 * pct(lat64, 50), 1),
+                               "p99_ms_same_arrivals": round(1e3 * pct(lat64, 99), 1)},
+        "speedup_vs_fp64_one_at_a_time": round(value / (N_REQ / t_fp64), 3),
+        "energy_relerr": {"served_vs_fp64_same_rtol_max": err_mix_vs_64,
+                          "served_vs_fp64_rtol1e-12_sample_max": err_ref, "sample_size": len(sample)},
+        "pcg_gnode_iter_per_s": {"workload": "385^3 single solve (60000 atoms, h=0.5 A)",
+                                 "mixed": c4["mixed"], "fp64": c4["fp64"]},
+        "roofline": roofline,
+        "stream_copy_GBs": round(copy_gbs, 1),
+        "cpu_baseline": cpu,
+    }
+    main.close()
+    side.close()
+    return out
+
+
+def cpu_baseline_stream(reqs, budget_s=15.0):
+    """The oracle (FP64, all host threads) on the first requests of the same stream."""
     from oracle import oracle as O
 
-    g = I.GridSpec(**{k: getattr(grid, k) for k in grid.__dataclass_fields__})
-    g.rtol = rtol
     t0 = time.perf_counter()
-    run = O.run(mol, g, rtol=rtol)
+    n = 0
+    for mol, g in reqs:
+        O.run(mol, replace(g, precision=I.FP64), rtol=RTOL)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
     dt = time.perf_counter() - t0
-    return run, dt, O.num_threads()
+    return {"value": round(n / dt, 4), "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"the first {n} requests of the same stream solved by the FP64 CPU oracle at rtol {RTOL} "
+                      f"({dt:.1f} s)"}
+
+
+# ---- single solves (c1, c2, c4) ---------------------------------------------------------------
+
+def workload(name: str):
+    if name == "c1":
+        return I.kirkwood_c1() + ("kirkwood sphere R=2A q=+1e, 65^3 nodes, h=0.25A",)
+    if name == "c2":
+        return I.protein_c2() + ("synthetic 2000-atom molecule in a 20A ball, 161^3 nodes, h=0.5A",)
+    if name == "c4":
+        return I.large_c4() + ("synthetic 60000-atom molecule in a 65A ball, 385^3 nodes, h=0.5A",)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bench_single(args, B, torch):
+    ctx = B.Context(0)
+    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)
+    mol, grid, desc = workload(args.workload)
+    nu = grid.unknowns
+    ref = B.solve(mol, replace(grid, rtol=1e-12, precision=I.FP64), ctx)
+
+    def run(g):
+        lat, res = [], []
+        for s in range(args.warmup + args.steps):
+            timed = s >= args.warmup
+            ctx.set_profiling(timed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pb = B.Problem(ctx, mol, g)
+            st = pb.solve()
+            en = pb.energy()
+            prof = pb.profile() if timed else None
+            pb.close()
+            torch.cuda.synchronize()
+            if timed:
+                lat.append(time.perf_counter() - t0)
+                res.append((st, en, prof))
+        ctx.set_profiling(False)
+        st, en, _ = res[-1]
+        t_solve = np.mean([r[0]["t_solve_s"] for r in res])
+        iters = np.mean([r[0]["iters"] for r in res])
+        stencil_ms = float(np.mean([r[2]["stencil_ms"] for r in res if r[2]["samples"]]))
+        return dict(solves_per_s=len(lat) / sum(lat), ms=1e3 * float(np.mean(lat)), p50=1e3 * pct(lat, 50),
+                    p99=1e3 * pct(lat, 99), iters=float(iters), gnode=nu * iters / t_solve / 1e9,
+                    stencil_ms=stencil_ms, err=max(relerr(en[k], ref[k]) for k in ("e_pol", "e_ion")))
+
+    mx = run(replace(grid, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA))
+    p64 = run(replace(grid, precision=I.FP64, rtol=RTOL))
+    ach = nu * 24 / (mx["stencil_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mx["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(mx["ms"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 CG + f64 reliable updates/energy", "data": "synthetic",
+        "config": {"workload": desc, "unknowns": nu, "n_atoms": mol.n, "rtol": RTOL, "reliable_update_factor": DELTA},
+        "p50_ms": round(mx["p50"], 3), "p99_ms": round(mx["p99"], 3), "energy_relerr_vs_fp64": mx["err"],
+        "pcg_gnode_iter_per_s": {"mixed": round(mx["gnode"], 3), "fp64": round(p64["gnode"], 3)},
+        "fp64_plain": {"solves_per_s": round(p64["solves_per_s"], 3), "p50_ms": round(p64["p50"], 3),
+                       "p99_ms": round(p64["p99"], 3), "energy_relerr_vs_fp64": p64["err"]},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cg_stencil<float>",
+                     "bytes_per_launch": nu * 24, "avg_launch_ms": round(mx["stencil_ms"], 5)},
+        "stream_copy_GBs": round(copy_gbs, 1),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        t0 = time.perf_counter()
+        run_o = O.run(mol, replace(grid, precision=I.FP64), rtol=RTOL)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": O.num_threads(),
+                               "kind": "oracle", "sample": f"one full FP64 oracle solve of the same workload at rtol "
+                                                           f"{RTOL}: {dt:.1f} s, {run_o.iters} CG iterations"}
+    ctx.close()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); how the solve would shard "
+              "over several GPUs is described in DESIGN.md and is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -112,95 +316,7 @@ def main():
 
     B.load()
     torch.cuda.set_device(0)
-    ctx = B.Context(0)
-    mol, grid, desc = workload(args.workload)
-    nu = grid.unknowns
-    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)   # attainable-bandwidth reference
-
-    # FP64 reference energies of this workload (untimed)
-    ref_grid = I.GridSpec(**{k: getattr(grid, k) for k in grid.__dataclass_fields__})
-    ref_grid.rtol, ref_grid.precision = 1e-12, I.FP64
-    ref = B.solve(mol, ref_grid, ctx)
-
-    g64 = I.GridSpec(**{k: getattr(grid, k) for k in grid.__dataclass_fields__})
-    g64.rtol, g64.precision = RTOL_FP64, I.FP64
-    gmx = I.GridSpec(**{k: getattr(grid, k) for k in grid.__dataclass_fields__})
-    gmx.rtol, gmx.precision, gmx.inner_rtol = RTOL_MIXED, I.MIXED, INNER_RTOL
-
-    lat_mx, res_mx = run_steps(ctx, B, mol, gmx, args.steps, args.warmup, profile=True)
-    lat_64, res_64 = run_steps(ctx, B, mol, g64, args.steps, args.warmup, profile=True)
-
-    def summarize(lat, res):
-        st, en, _ = res[-1]
-        t_solve = np.mean([r[0]["t_solve_s"] for r in res])
-        iters = np.mean([r[0]["iters"] for r in res])
-        prof = [r[2] for r in res if r[2] and r[2]["samples"] > 0]
-        stencil_ms = float(np.mean([p["stencil_ms"] for p in prof])) if prof else float("nan")
-        update_ms = float(np.mean([p["update_ms"] for p in prof])) if prof else float("nan")
-        err = max(relerr(en[k], ref[k]) for k in ("e_pol", "e_ion"))
-        return dict(
-            solves_per_s=len(lat) / sum(lat), ms_per_solve=1e3 * float(np.mean(lat)),
-            p50_ms=1e3 * float(np.percentile(lat, 50)), p99_ms=1e3 * float(np.percentile(lat, 99)),
-            iters=float(iters), outer_iters=st["outer_iters"], relres=st["relres"],
-            gnode_iter_per_s=nu * iters / t_solve / 1e9, t_solve_ms=1e3 * float(t_solve),
-            stencil_ms=stencil_ms, update_ms=update_ms, energy_relerr_vs_fp64=err,
-            e_pol=en["e_pol"], e_ion=en["e_ion"], e_coul=en["e_coul"])
-
-    mx = summarize(lat_mx, res_mx)
-    p64 = summarize(lat_64, res_64)
-
-    fp32 = True
-    bpn = stencil_bytes_per_node(fp32)
-    alg_bytes = nu * bpn
-    achieved = alg_bytes / (mx["stencil_ms"] * 1e-3) / 1e9 if mx["stencil_ms"] > 0 else float("nan")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_cg_stencil<float>", "bytes_per_launch": alg_bytes,
-                "avg_launch_ms": round(mx["stencil_ms"], 5)}
-    bpn64 = stencil_bytes_per_node(False)
-    ach64 = nu * bpn64 / (p64["stencil_ms"] * 1e-3) / 1e9 if p64["stencil_ms"] > 0 else float("nan")
-
-    cpu = None
-    if not args.no_cpu:
-        run, dt, cores = cpu_baseline(mol, grid, RTOL_FP64)
-        cpu = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
-               "sample": f"one full FP64 oracle solve of the same workload ({desc}) at rtol {RTOL_FP64}: "
-                         f"{dt:.1f} s, {run.iters} CG iterations",
-               "gnode_iter_per_s": round(nu * run.iters / run.times['solve'] / 1e9, 5),
-               "energy_relerr_gpu_fp64_ref_vs_oracle":
-                   max(relerr(ref[k], run.energy[k]) for k in ("e_pol", "e_ion"))}
-
-    out = {
-        "metric": METRIC,
-        "value": round(mx["solves_per_s"], 4),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(mx["ms_per_solve"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 inner + f64 refinement",
-        "data": "synthetic",
-        "config": {"workload": desc, "unknowns": nu, "n_atoms": mol.n,
-                   "rtol_mixed": RTOL_MIXED, "inner_rtol": INNER_RTOL, "rtol_fp64": RTOL_FP64},
-        "p50_ms": round(mx["p50_ms"], 3),
-        "p99_ms": round(mx["p99_ms"], 3),
-        "energy_relerr_vs_fp64": mx["energy_relerr_vs_fp64"],
-        "pcg_gnode_iter_per_s": {"mixed": round(mx["gnode_iter_per_s"], 3),
-                                 "fp64": round(p64["gnode_iter_per_s"], 3)},
-        "fp64_plain": {"solves_per_s": round(p64["solves_per_s"], 4), "p50_ms": round(p64["p50_ms"], 3),
-                       "p99_ms": round(p64["p99_ms"], 3), "iters": p64["iters"],
-                       "energy_relerr_vs_fp64": p64["energy_relerr_vs_fp64"],
-                       "stencil_ms": round(p64["stencil_ms"], 5), "stencil_GBs": round(ach64, 1)},
-        "mixed": {"iters": mx["iters"], "outer_iters": mx["outer_iters"], "t_solve_ms": round(mx["t_solve_ms"], 3),
-                  "update_ms": round(mx["update_ms"], 5)},
-        "roofline": roofline,
-        "stream_copy_GBs": round(copy_gbs, 1),
-        "cpu_baseline": cpu,
-    }
-    ctx.close()
+    out = bench_serving(args, B, torch) if args.workload == "c5" else bench_single(args, B, torch)
     print(json.dumps(out))
 
 

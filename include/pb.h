@@ -227,6 +227,12 @@ int pb_poll(pb_server* srv, uint64_t* ids, pb_energy_out* results, pb_solve_stat
  * retiring (energy read-back), admitting (coefficient builds), launching. */
 int pb_server_times(const pb_server* srv, double* out4);
 
+/* With profiling on in ctx (pb_ctx_set_profiling): total HIP-event time (ms) of the batched
+ * stencil launches, their algorithmic bytes (24 per interior unknown per CG iteration actually
+ * performed), and the number of launches timed. */
+int pb_server_profile(const pb_server* srv, double* stencil_ms_total, double* stencil_bytes_total,
+                      int64_t* stencil_launches);
+
 /* Wait for the device, release every resident problem and the server. */
 void pb_server_destroy(pb_server* srv);
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "pb_copy_potential", "pb_problem_free", "pb_copy_coeffs", "pb_num_cut", "pb_copy_cut",
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
-    "pb_server_times",
+    "pb_server_times", "pb_server_profile",
 ]
 
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     L.pb_server_step.argtypes = [P, C.POINTER(i32), C.POINTER(i32)]
     L.pb_poll.argtypes = [P, P, P, P, P, P, i32, C.POINTER(i32)]
     L.pb_server_times.argtypes = [P, P]
+    L.pb_server_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
     L.pb_server_destroy.argtypes = [P]
     L.pb_server_destroy.restype = None
     _lib = L
@@ -338,6 +339,13 @@ class Server:
             d.update(id=int(ids[i]), done_s=float(tdone[i]), code=int(codes[i]))
             out.append(d)
         return out
+
+    def profile(self) -> dict:
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        rc = _lib.pb_server_profile(self.h, C.byref(a), C.byref(b), C.byref(n))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(stencil_ms=a.value, stencil_bytes=b.value, launches=n.value)
 
     def times(self) -> dict:
         v = np.zeros(4)

@@ -165,8 +165,9 @@ struct BatchTotals {     // grid sizes of the batched launches (sums over the pr
     int st, up, add, res;
 };
 
+// ev (optional): 2*iters events recorded around every batched stencil launch
 hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int* off, int P, const BatchTotals& t,
-                              int iters, CGState* gather_out);
+                              int iters, CGState* gather_out, hipEvent_t* ev);
 int add_blocks(const Grid& g);
 
 // mixed precision: FP32 CG with FP64 reliable updates (true residual + solution accumulation)

@@ -102,6 +102,13 @@ struct pb_server {
     int chunk_id = 0;
     int completed = -1;
     double t_wait = 0, t_retire = 0, t_admit = 0, t_launch = 0;   // host seconds per phase
+    // sampled timing of the batched stencil launches (context profiling on)
+    hipEvent_t pev[2][2 * kChunkIters];
+    bool pev_made = false;
+    bool prof_slot[2] = {false, false};
+    std::vector<int64_t> prof_nu[2];     // interior unknowns of each member
+    double prof_ms = 0, prof_bytes = 0;
+    int64_t prof_launches = 0;
 
     double now() const
     {
@@ -159,9 +166,22 @@ int complete_slot(pb_server* s, int k)
     SCHK(hipEventSynchronize(s->ev[k]));
     s->inflight[k] = false;
     s->completed = std::max(s->completed, s->slot_chunk[k]);
+    if (s->prof_slot[k]) {
+        for (int it = 0; it < kChunkIters; ++it) {
+            float ms = 0;
+            SCHK(hipEventElapsedTime(&ms, s->pev[k][2 * it], s->pev[k][2 * it + 1]));
+            s->prof_ms += ms;
+        }
+        s->prof_launches += kChunkIters;
+    }
     for (size_t m = 0; m < s->members[k].size(); ++m) {
         for (auto& a : s->act) {
             if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
+            if (s->prof_slot[k]) {
+                // algorithmic bytes of the FP32 stencil: r, p_old, p_new, q, D^-1, code per unknown
+                const int done = s->hgather[k][m].iter_count - a.snap.iter_count;
+                s->prof_bytes += (double)s->prof_nu[k][m] * 24.0 * (done > 0 ? done : 0);
+            }
             a.snap = s->hgather[k][m];
             const int stt = a.snap.status;
             if (stt == 1 || stt == 2 || a.launched >= a.pb->prm.max_iter) a.finished = true;
@@ -325,9 +345,21 @@ int launch_chunk(pb_server* s, int k)
     o[2 * (P + 1) + P] = t.add;
     o[3 * (P + 1) + P] = t.res;
     hipStream_t st = s->ctx->stream;
+    s->prof_slot[k] = s->ctx->profile != 0;
+    if (s->prof_slot[k] && !s->pev_made) {
+        for (int a = 0; a < 2; ++a)
+            for (int e = 0; e < 2 * kChunkIters; ++e) SCHK(hipEventCreate(&s->pev[a][e]));
+        s->pev_made = true;
+    }
+    s->prof_nu[k].clear();
+    for (int p = 0; p < P; ++p) {
+        const Grid& g = mem[p]->pb->g;
+        s->prof_nu[k].push_back((int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2));
+    }
     SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
     SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 4 * (P + 1), hipMemcpyHostToDevice, st));
-    SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k]));
+    SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
+                            s->prof_slot[k] ? s->pev[k] : nullptr));
     SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * P, hipMemcpyDeviceToHost, st));
     SCHK(hipEventRecord(s->ev[k], st));
     s->inflight[k] = true;
@@ -442,6 +474,16 @@ int pb_poll(pb_server* s, uint64_t* ids, pb_energy_out* results, pb_solve_stats*
     return PB_OK;
 }
 
+int pb_server_profile(const pb_server* s, double* stencil_ms_total, double* stencil_bytes_total,
+                      int64_t* stencil_launches)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    if (stencil_ms_total) *stencil_ms_total = s->prof_ms;
+    if (stencil_bytes_total) *stencil_bytes_total = s->prof_bytes;
+    if (stencil_launches) *stencil_launches = s->prof_launches;
+    return PB_OK;
+}
+
 int pb_server_times(const pb_server* s, double* out4)
 {
     if (!s || !out4) return pbi_fail(PB_EINVAL, "NULL argument");
@@ -463,6 +505,8 @@ void pb_server_destroy(pb_server* s)
     for (int k = 0; k < 2; ++k) {
         free_slot(s, k);
         (void)hipEventDestroy(s->ev[k]);
+        if (s->pev_made)
+            for (int e = 0; e < 2 * kChunkIters; ++e) (void)hipEventDestroy(s->pev[k][e]);
     }
     delete s;
 }

@@ -653,14 +653,16 @@ __global__ void kb_gather(const ProbDev<float>* __restrict__ D, int P, CGState* 
 }  // namespace
 
 hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int* off, int P, const BatchTotals& t,
-                              int iters, CGState* gather_out)
+                              int iters, CGState* gather_out, hipEvent_t* ev)
 {
     const int* off_st = off;
     const int* off_up = off + (P + 1);
     const int* off_add = off + 2 * (P + 1);
     const int* off_res = off + 3 * (P + 1);
     for (int it = 0; it < iters; ++it) {
+        if (ev) (void)hipEventRecord(ev[2 * it], s);
         kb_stencil<float><<<t.st, 256, 0, s>>>(D, off_st, P);
+        if (ev) (void)hipEventRecord(ev[2 * it + 1], s);
         kb_update<float><<<t.up, 256, 0, s>>>(D, off_up, P);
     }
     kb_ru_add<<<t.add, 256, 0, s>>>(D, off_add, P);
