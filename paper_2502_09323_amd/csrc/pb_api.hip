@@ -81,6 +81,12 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
         if (p->n[d] > 4096) return fail(PB_EINVAL, "n[%d] = %d > 4096", d, p->n[d]);
         if (!finite(p->origin[d])) return fail(PB_EINVAL, "origin must be finite");
     }
+    {
+        // the iteration kernel addresses FP64 vectors with 32-bit byte offsets
+        const int64_t S = ((int64_t)p->n[2] + Z0 + 7) / 8 * 8;
+        if ((int64_t)p->n[0] * p->n[1] * S >= ((int64_t)1 << 29))
+            return fail(PB_EINVAL, "grid of %d x %d x %d nodes exceeds 2^29 stored nodes", p->n[0], p->n[1], p->n[2]);
+    }
     if (p->bc != PB_BC_ZERO && p->bc != PB_BC_DH && p->bc != PB_BC_USER) return fail(PB_EINVAL, "bad bc");
     if (p->bc == PB_BC_USER && !p->bc_values) return fail(PB_EINVAL, "PB_BC_USER needs bc_values");
     if (p->precision != PB_FP64 && p->precision != PB_MIXED) return fail(PB_EINVAL, "bad precision");
@@ -137,9 +143,9 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, int max_iter, bool mixed, CGState
                 HIPCHK(hipEventCreate(&e2));
                 HIPCHK(hipEventRecord(e0, s));
             }
-            HIPCHK(launch_cg_stencil<T>(s, pb->g, pb->ts, B, pb->cf));
+            HIPCHK(launch_cg_iter<T>(s, pb->g, pb->ts, B, pb->cf));
             if (sample) HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(launch_cg_update<T>(s, pb->g, B));
+            HIPCHK(launch_cg_tail(s, B.part, B.nb, B.st));
             if (sample) {
                 HIPCHK(hipEventRecord(e2, s));
                 evs.push_back(e0);
@@ -149,10 +155,10 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, int max_iter, bool mixed, CGState
             }
         }
         if (mixed) {
-            HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, 0));
-            HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+            HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, pb->p32, 0));
+            HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->ck32, pb->cf, pb->rhs, pb->x, pb->z32,
                                       pb->part_res, B.st));
-            HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, B.part2, B.nb2, 0, 0.0, 0.0));
+            HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, 0, 0.0, 0.0));
         }
         launched += n;
         HIPCHK(hipMemcpyAsync(&ctx->host_state[slot], B.st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -171,10 +177,10 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, int max_iter, bool mixed, CGState
     }
     if (mixed) {
         // a final update folds in the last correction when the iteration did not converge
-        HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, 1));
-        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+        HIPCHK(launch_ru_add(s, pb->g, B.st, pb->x, pb->d32, pb->p32, 1));
+        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->ck32, pb->cf, pb->rhs, pb->x, pb->z32,
                                   pb->part_res, B.st));
-        HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, B.part2, B.nb2, 0, 0.0, 0.0));
+        HIPCHK(launch_ru_fin(s, B.st, pb->part_res, pb->nbres, 0, 0.0, 0.0));
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(out, B.st, sizeof(CGState), hipMemcpyDeviceToHost));
@@ -203,12 +209,13 @@ int run_cg(pb_problem* pb, const CGBufs<T>& B, int max_iter, bool mixed, CGState
 int ensure_cg64(pb_problem* pb)
 {
     int rc = PB_OK;
-    if (pb->r) return PB_OK;
+    if (pb->z64[0]) return PB_OK;
     const size_t N = (size_t)pb->g.N;
-    pb->r = dalloc<double>(pb, N, &rc);
-    if (!rc) pb->p0 = dalloc<double>(pb, N, &rc);
-    if (!rc) pb->p1 = dalloc<double>(pb, N, &rc);
-    if (!rc) pb->qv = dalloc<double>(pb, N, &rc);
+    for (int k = 0; k < 2 && !rc; ++k) {
+        pb->z64[k] = dalloc<double>(pb, N, &rc);
+        if (!rc) pb->w64[k] = dalloc<double>(pb, N, &rc);
+        if (!rc) pb->p64[k] = dalloc<double>(pb, N, &rc);
+    }
     return rc;
 }
 
@@ -218,10 +225,11 @@ int ensure_cg32(pb_problem* pb)
     if (pb->d32) return PB_OK;
     const size_t N = (size_t)pb->g.N;
     pb->d32 = dalloc<float>(pb, N, &rc);
-    if (!rc) pb->r32 = dalloc<float>(pb, N, &rc);
-    if (!rc) pb->p32a = dalloc<float>(pb, N, &rc);
-    if (!rc) pb->p32b = dalloc<float>(pb, N, &rc);
-    if (!rc) pb->q32 = dalloc<float>(pb, N, &rc);
+    for (int k = 0; k < 2 && !rc; ++k) {
+        pb->z32[k] = dalloc<float>(pb, N, &rc);
+        if (!rc) pb->w32[k] = dalloc<float>(pb, N, &rc);
+        if (!rc) pb->p32[k] = dalloc<float>(pb, N, &rc);
+    }
     return rc;
 }
 
@@ -233,18 +241,16 @@ CGBufs<double> bufs<double>(pb_problem* pb)
 {
     CGBufs<double> B;
     B.x = pb->x;
-    B.r = pb->r;
-    B.p[0] = pb->p0;
-    B.p[1] = pb->p1;
-    B.q = pb->qv;
+    for (int k = 0; k < 2; ++k) {
+        B.z[k] = pb->z64[k];
+        B.w[k] = pb->w64[k];
+        B.p[k] = pb->p64[k];
+    }
     B.ck = pb->ck64;
-    B.dinv = pb->dinv;
     B.code = pb->code;
-    B.part1 = pb->part1;
-    B.part2 = pb->part2;
+    B.part = pb->part;
     B.st = pb->st;
-    B.nb1 = pb->nb1;
-    B.nb2 = pb->nb2;
+    B.nb = pb->nb;
     return B;
 }
 
@@ -253,18 +259,16 @@ CGBufs<float> bufs<float>(pb_problem* pb)
 {
     CGBufs<float> B;
     B.x = pb->d32;
-    B.r = pb->r32;
-    B.p[0] = pb->p32a;
-    B.p[1] = pb->p32b;
-    B.q = pb->q32;
+    for (int k = 0; k < 2; ++k) {
+        B.z[k] = pb->z32[k];
+        B.w[k] = pb->w32[k];
+        B.p[k] = pb->p32[k];
+    }
     B.ck = pb->ck32;
-    B.dinv = pb->dinv;
     B.code = pb->code;
-    B.part1 = pb->part1;
-    B.part2 = pb->part2;
+    B.part = pb->part;
     B.st = pb->st;
-    B.nb1 = pb->nb1;
-    B.nb2 = pb->nb2;
+    B.nb = pb->nb;
     return B;
 }
 
@@ -279,15 +283,16 @@ int pbi_mixed_begin(pb_problem* pb)
     const pb_params& P = pb->prm;
     HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
     HIPCHK(launch_fill(s, pb->d32, sizeof(float) * N));
-    HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * N));
-    HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * N));
-    HIPCHK(launch_fill(s, pb->q32, sizeof(float) * N));
-    // first "update": r32 = b - A*0, the norms and the mixed iteration state
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(launch_fill(s, pb->z32[k], sizeof(float) * N));
+        HIPCHK(launch_fill(s, pb->w32[k], sizeof(float) * N));
+        HIPCHK(launch_fill(s, pb->p32[k], sizeof(float) * N));
+    }
+    // first "update": z32 = D^-1 (b - A*0), the norms and the mixed iteration state
     HIPCHK(launch_ru_begin(s, pb->st));
-    HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32, pb->part_res,
+    HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->ck32, pb->cf, pb->rhs, pb->x, pb->z32, pb->part_res,
                               pb->st));
-    HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 1, P.rtol * P.rtol,
-                         P.inner_rtol * P.inner_rtol));
+    HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, 1, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol));
     return PB_OK;
 }
 
@@ -313,10 +318,10 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     if (!rc) pb->e_tmp[3] = dalloc<double>(pb, 16, &rc);                       // energy sums
     if (rc) return rc;
     if (finish_mixed) {
-        HIPCHK(launch_ru_add(s, pb->g, pb->st, pb->x, pb->d32, 1));
-        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->cf, pb->rhs, pb->x, pb->dinv, pb->r32,
+        HIPCHK(launch_ru_add(s, pb->g, pb->st, pb->x, pb->d32, pb->p32, 1));
+        HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->ck32, pb->cf, pb->rhs, pb->x, pb->z32,
                                   pb->part_res, pb->st));
-        HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, pb->part2, pb->nb2, 0, 0.0, 0.0));
+        HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, 0, 0.0, 0.0));
     }
     Atoms at{(int)pb->na, pb->xyzr, pb->q};
     HIPCHK(launch_fill(s, pb->e_tmp[3], 16 * sizeof(double)));
@@ -669,8 +674,6 @@ int pbi_build_continue(pb_problem* pb)
     CK(rc);
     pb->gb = dalloc<double>(pb, N, &rc);
     CK(rc);
-    pb->dinv = dalloc<float>(pb, N, &rc);
-    CK(rc);
     pb->x = dalloc<double>(pb, N, &rc);
     CK(rc);
     HIPCHK(launch_deposit(s, g, T.bn, at, pb->rhs));
@@ -681,20 +684,15 @@ int pbi_build_continue(pb_problem* pb)
     } else if (prm->bc == PB_BC_USER) {
         HIPCHK(launch_bc_user(s, g, T.full, pb->gb));
     }
-    HIPCHK(launch_diag_lift(s, g, pb->code, pb->ck64, pb->cf, pb->gb, pb->rhs, pb->dinv, nullptr));
+    HIPCHK(launch_diag_lift(s, g, pb->code, pb->ck64, pb->cf, pb->gb, pb->rhs, nullptr, nullptr));
     HIPCHK(launch_mc_weights(s, g, pb->code, pb->cutbase, pb->ncut, pb->cutkey, pb->rp, pb->wp));
 
     // solver scalars and partial sums
-    pb->nb1 = pb->ts.items;
-    pb->nb2 = update_blocks(g);
+    pb->nb = pb->ts.items;
     pb->nbres = residual_blocks(g);
-    pb->part1 = dalloc<double>(pb, (size_t)pb->nb1, &rc);
-    CK(rc);
-    pb->part2 = dalloc<double>(pb, 2 * (size_t)pb->nb2, &rc);
+    pb->part = dalloc<double>(pb, 5 * (size_t)pb->nb, &rc);
     CK(rc);
     pb->part_res = dalloc<double>(pb, 3 * (size_t)pb->nbres, &rc);
-    CK(rc);
-    pb->scal = dalloc<double>(pb, 8, &rc);
     CK(rc);
     pb->st = dalloc<CGState>(pb, 1, &rc);
     CK(rc);
@@ -743,8 +741,8 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     CGState st;
     if (P.precision == PB_FP64) {
         CGBufs<double> B = bufs<double>(pb);
-        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
-        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, P.rtol * P.rtol));
+        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->cf, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, pb->part, pb->nb, pb->st, P.rtol * P.rtol));
         rc = run_cg<double>(pb, B, P.max_iter, false, &st);
         if (rc) return rc;
         stats->iters = st.status == 1 ? st.iters : st.iter_count;
@@ -901,21 +899,19 @@ int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
     const double rtol2 = pb->prm.rtol * pb->prm.rtol;
     if (fp32) {
         CGBufs<float> B = bufs<float>(pb);
-        HIPCHK(launch_fill(s, pb->p32a, sizeof(float) * (size_t)pb->g.N));
-        HIPCHK(launch_fill(s, pb->p32b, sizeof(float) * (size_t)pb->g.N));
-        HIPCHK(launch_cg_init<float>(s, pb->g, B, pb->rhs, nullptr));
-        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, rtol2));
-        HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf));
+        HIPCHK(launch_cg_init<float>(s, pb->g, B, pb->cf, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, pb->part, pb->nb, pb->st, rtol2));
+        HIPCHK(launch_cg_iter<float>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(a, s));
-        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<float>(s, pb->g, pb->ts, B, pb->cf));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_iter<float>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(b, s));
     } else {
         CGBufs<double> B = bufs<double>(pb);
-        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->rhs, nullptr));
-        HIPCHK(launch_cg_fin(s, pb->part2, pb->nb2, pb->st, rtol2));
-        HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf));
+        HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->cf, pb->rhs, nullptr));
+        HIPCHK(launch_cg_fin(s, pb->part, pb->nb, pb->st, rtol2));
+        HIPCHK(launch_cg_iter<double>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(a, s));
-        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_stencil<double>(s, pb->g, pb->ts, B, pb->cf));
+        for (int t = 0; t < reps; ++t) HIPCHK(launch_cg_iter<double>(s, pb->g, pb->ts, B, pb->cf));
         HIPCHK(hipEventRecord(b, s));
     }
     HIPCHK(hipEventSynchronize(b));

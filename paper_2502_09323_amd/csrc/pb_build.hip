@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code,
     if (e >= g.N) return;
     uint32_t c = code[e];
     if (c & C_BOX) {
-        dinv[e] = 0.0f;
+        if (dinv) dinv[e] = 0.0f;
         if (diag) diag[e] = 0.0;
         return;
     }
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code,
     for (int q = 0; q < 6; ++q)
         if (code[nb[q]] & C_BOX) lift += K[q] * gb[nb[q]];
     rhs[e] += lift;
-    dinv[e] = (float)(1.0 / D);
+    if (dinv) dinv[e] = (float)(1.0 / D);
     if (diag) diag[e] = D;
 }
 

@@ -82,7 +82,6 @@ struct pb_problem {
     double* q = nullptr;
     // coefficient maps
     uint32_t* code = nullptr;
-    float* dinv = nullptr;
     double* ck64 = nullptr;
     float* ck32 = nullptr;
     int* cutbase = nullptr;
@@ -94,12 +93,17 @@ struct pb_problem {
     double *alpha = nullptr, *kcut = nullptr, *rp = nullptr, *np = nullptr, *wp = nullptr;
     int* owner = nullptr;
     double *F = nullptr, *phip = nullptr, *pts = nullptr;
-    // CG work
-    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr;
-    float *d32 = nullptr, *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
-    double *part1 = nullptr, *part2 = nullptr, *part_res = nullptr, *scal = nullptr;
+    // CG work: z = D^-1 r, w = D^-1 q and p, double buffered by iteration parity
+    double* z64[2] = {nullptr, nullptr};
+    double* w64[2] = {nullptr, nullptr};
+    double* p64[2] = {nullptr, nullptr};
+    float* d32 = nullptr;   // FP32 correction (the mixed form's x)
+    float* z32[2] = {nullptr, nullptr};
+    float* w32[2] = {nullptr, nullptr};
+    float* p32[2] = {nullptr, nullptr};
+    double *part = nullptr, *part_res = nullptr;
     pbk::CGState* st = nullptr;
-    int nb1 = 0, nb2 = 0, nbres = 0;
+    int nb = 0, nbres = 0;
     bool solved = false;
     BuildTmp* bt = nullptr;      // set while a build is in progress
     hipEvent_t ev = nullptr;     // marks the end of the last asynchronous phase
@@ -107,7 +111,7 @@ struct pb_problem {
     double* e_tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // energy temporaries
     int e_nchunk = 0;
 
-    // sampled kernel timings of the last solve
+    // sampled kernel timings of the last solve (iteration kernel, tail kernel)
     double prof_stencil_ms = 0, prof_update_ms = 0;
     int prof_n = 0;
 };

@@ -56,25 +56,26 @@ struct Coef {          // what the operator needs on the device
     double kin, kout, mass;  // h*eps_in, h*eps_out, h^3*eps_out*kD^2
 };
 
-// deterministic CG state, one per solve; written by single designated threads only
+// deterministic CG state, one per solve; written by single designated threads only (the
+// one-block tail and reliable-update kernels), read by every block of the iteration kernel
 struct CGState {
-    double rz[2];      // r.z of the two most recent iterations (indexed by parity)
+    double alpha;      // step the next iteration applies: x += alpha p_old, r -= alpha q_old
+    double beta;       // p_new = D^-1 r_new + beta p_old
+    double gamma;      // r.D^-1 r of the last iterate
     double bnorm2;     // ||b||^2 of the iterated system
-    double rr;         // last recursive ||r||^2
-    double pq;
-    double stop2;      // the stencil kernel stops the iteration when rr <= stop2 ...
+    double rr;         // ||r||^2 of the last iterate (recursive residual)
+    double pq;         // p.A p of the last iteration
+    double stop2;      // the tail stops the iteration when rr <= stop2 ...
     double trig2;      // mixed: a reliable update runs at a chunk end once rr <= trig2
     double delta2;     // mixed: after an update trig2 = delta2 * ||r||^2
     double goal64;     // mixed: converged when the FP64 true ||b - A x||^2 <= goal64
     double rr64;       // mixed: FP64 true residual norm^2 at the last update
     int status;        // 0 running, 1 converged, 2 breakdown, 3 true-residual check requested
     int stop_status;   // ... and sets status = stop_status (1 for FP64, 3 for mixed)
-    int iters;         // iteration count at convergence
-    int iter_count;    // completed iterations (its parity selects the p buffer)
-    int par;           // parity of the iteration in flight (stencil writes, update reads)
+    int iters;         // CG steps applied to x when the iteration stopped
+    int iter_count;    // completed iteration kernels; its parity selects the buffers
     int ru;            // 1 while a reliable update is in progress
     int n_ru;          // reliable updates done
-    int pad;
 };
 
 struct TileShape {     // tiling of the interior for the stencil kernel
@@ -86,7 +87,12 @@ struct TileShape {     // tiling of the interior for the stencil kernel
 #ifndef PB_TILE_ROWS
 #define PB_TILE_ROWS 8
 #endif
-constexpr int TY = PB_TILE_ROWS;  // rows (y) per stencil tile = 4 waves x TY/4 rows
+#ifndef PB_TILE_WAVES
+#define PB_TILE_WAVES 8
+#endif
+constexpr int TY = PB_TILE_ROWS;   // rows (y) per tile of the iteration kernel
+constexpr int NWV = PB_TILE_WAVES; // waves per block of the iteration kernel, TY/NWV rows each
+static_assert(TY % NWV == 0 && NWV >= 4 && TY <= 64, "tile shape");
 
 // ---- build kernels (pb_build.hip) -----------------------------------------------------
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
@@ -119,32 +125,26 @@ hipError_t launch_export_phi(hipStream_t s, const Grid& g, const double* x, cons
 
 // ---- solver kernels (pb_solve.hip) ------------------------------------------------------
 TileShape make_tiles(const Grid& g);
-int update_blocks(const Grid& g);
 
 template <typename T>
 struct CGBufs {
     T* x;
-    T* r;
+    T* z[2];           // D^-1 r; z, w and p are double buffered by iteration parity
+    T* w[2];           // D^-1 q
     T* p[2];
-    T* q;
     const T* ck;
-    const float* dinv;
     const uint32_t* code;
-    double* part1;     // [nb1]    p.q partials
-    double* part2;     // [2*nb2]  r.z and r.r partials
+    double* part;      // [5*nb] per-block partial sums of the iteration kernel
     CGState* st;
-    int nb1, nb2;
+    int nb;            // blocks of the iteration kernel (= tiles)
 };
 
 template <typename T>
-hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, const double* b64,
-                          const T* bT);
-hipError_t launch_cg_fin(hipStream_t s, double* part2, int nb2, CGState* st, double rtol2);
+hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, Coef c, const double* b64, const T* bT);
+hipError_t launch_cg_fin(hipStream_t s, const double* part, int nb, CGState* st, double rtol2);
 template <typename T>
-hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B,
-                             Coef c);
-template <typename T>
-hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B);
+hipError_t launch_cg_iter(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c);
+hipError_t launch_cg_tail(hipStream_t s, const double* part, int nb, CGState* st);
 hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t bytes);
 
 // everything a batched launch needs to act for one problem
@@ -153,7 +153,7 @@ struct ProbDev {
     Grid g;
     TileShape ts;
     Coef cf;
-    CGBufs<T> B;          // FP32 CG state (x = FP32 correction, r = FP32 residual)
+    CGBufs<T> B;          // FP32 CG state (x = FP32 correction, z = FP32 preconditioned residual)
     double* x64;          // FP64 solution
     const double* rhs;    // FP64 right-hand side
     const double* ck64;   // FP64 cut-edge coefficients
@@ -162,22 +162,22 @@ struct ProbDev {
 };
 
 struct BatchTotals {     // grid sizes of the batched launches (sums over the problems)
-    int st, up, add, res;
+    int st, add, res;
 };
 
-// ev (optional): 2*iters events recorded around every batched stencil launch
+// ev (optional): 2*iters events recorded around every batched iteration kernel
 hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int* off, int P, const BatchTotals& t,
                               int iters, CGState* gather_out, hipEvent_t* ev);
 int add_blocks(const Grid& g);
 
 // mixed precision: FP32 CG with FP64 reliable updates (true residual + solution accumulation)
 hipError_t launch_ru_begin(hipStream_t s, CGState* st);
-hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force);
-hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
-                              Coef c, const double* b, const double* x64, const float* dinv, float* r32,
-                              double* part3, CGState* st);
-hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, double* part2,
-                         int nb2, int init, double rtol2, double delta2);
+hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, float* const* p32,
+                         int force);
+hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, const float* ck32,
+                              Coef c, const double* b, const double* x64, float* const* z32, double* part3, CGState* st);
+hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, int init, double rtol2,
+                         double delta2);
 int residual_blocks(const Grid& g);
 
 // ---- energy kernels (pb_energy.hip) -------------------------------------------------------

@@ -155,8 +155,8 @@ size_t estimate_bytes(const pb_params& p, int64_t na)
 {
     const int64_t S = ((p.n[2] + Z0) + 7) / 8 * 8;
     const int64_t N = (int64_t)p.n[0] * p.n[1] * S;
-    // node data of the mixed form (code, D^-1, b, g, x64, five FP32 vectors) + build scratch
-    return (size_t)N * 56 + (size_t)na * 64 + ((size_t)1 << 20);
+    // node data of the mixed form (code, b, g, x64, seven FP32 vectors) + build scratch
+    return (size_t)N * 60 + (size_t)na * 64 + ((size_t)1 << 20);
 }
 
 // wait for the chunk in slot k and record every member's state
@@ -178,9 +178,10 @@ int complete_slot(pb_server* s, int k)
         for (auto& a : s->act) {
             if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
             if (s->prof_slot[k]) {
-                // algorithmic bytes of the FP32 stencil: r, p_old, p_new, q, D^-1, code per unknown
+                // algorithmic bytes of the FP32 iteration kernel per unknown: read z, w, p, x
+                // and the node code, write z, w, p, x
                 const int done = s->hgather[k][m].iter_count - a.snap.iter_count;
-                s->prof_bytes += (double)s->prof_nu[k][m] * 24.0 * (done > 0 ? done : 0);
+                s->prof_bytes += (double)s->prof_nu[k][m] * 36.0 * (done > 0 ? done : 0);
             }
             a.snap = s->hgather[k][m];
             const int stt = a.snap.status;
@@ -325,25 +326,22 @@ int launch_chunk(pb_server* s, int k)
     if (P == 0) return PB_OK;
     int rc = ensure_slot(s, k, P);
     if (rc) return rc;
-    BatchTotals t{0, 0, 0, 0};
+    BatchTotals t{0, 0, 0};
     int* o = s->hoff[k];
     for (int p = 0; p < P; ++p) {
         const ProbDev<float> d = pbi_probdev(mem[p]->pb);
         s->hdesc[k][p] = d;
         o[p] = t.st;
-        o[(P + 1) + p] = t.up;
-        o[2 * (P + 1) + p] = t.add;
-        o[3 * (P + 1) + p] = t.res;
+        o[(P + 1) + p] = t.add;
+        o[2 * (P + 1) + p] = t.res;
         t.st += d.ts.items;
-        t.up += d.B.nb2;
         t.add += d.nadd;
         t.res += d.nbres;
         s->members[k].push_back(mem[p]->id);
     }
     o[P] = t.st;
-    o[(P + 1) + P] = t.up;
-    o[2 * (P + 1) + P] = t.add;
-    o[3 * (P + 1) + P] = t.res;
+    o[(P + 1) + P] = t.add;
+    o[2 * (P + 1) + P] = t.res;
     hipStream_t st = s->ctx->stream;
     s->prof_slot[k] = s->ctx->profile != 0;
     if (s->prof_slot[k] && !s->pev_made) {
@@ -357,7 +355,7 @@ int launch_chunk(pb_server* s, int k)
         s->prof_nu[k].push_back((int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2));
     }
     SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
-    SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 4 * (P + 1), hipMemcpyHostToDevice, st));
+    SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 3 * (P + 1), hipMemcpyHostToDevice, st));
     SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
                             s->prof_slot[k] ? s->pev[k] : nullptr));
     SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * P, hipMemcpyDeviceToHost, st));

@@ -2,44 +2,58 @@
 // operator (paper Sect. 3.1, eq. matrixequation, with the edge permittivities of Sect. 3.2),
 // matrix-free, for FP64 and FP32 data.
 //
-// One CG iteration is two kernels and no host round trip:
-//   stencil(par): reduce the previous r.z and r.r partials (every block, fixed order),
-//                 test convergence, beta = rz/rz_old; then per tile
-//                 p_new = D^-1 r + beta p_old (also on the halo), q = A p_new,
-//                 partial sums of p_new.q
-//   update(par):  reduce the p.q partials, alpha = rz/pq; x += alpha p, r -= alpha q,
-//                 partial sums of r.(D^-1 r) and r.r
-// The scalars never leave the device; every block reduces the same partial array in the
-// same order, so all blocks agree bit for bit and the result is run-to-run deterministic.
+// One CG iteration is one pass over the vectors plus a one-block tail, with no host round
+// trip.  The vectors kept are z = D^-1 r and w = D^-1 q (the preconditioned residual and
+// operator image), p and x:
+//   iter(it): per node  z = z_old - alpha w_old,  x += alpha p_old,  p = z + beta p_old,
+//             q = A p,  w = q / D  (r = D z and q are formed where needed),
+//             and per-block partial sums of p.q, r.z, r.r, z.q and q.D^-1 q
+//   tail(it): reduce the partial sums in a fixed order, test convergence, and prepare the
+//             next step: alpha = r.z / p.q, and beta from the next r.z, which follows from
+//             the expansion (r - alpha q).D^-1 (r - alpha q) = r.z - 2 alpha z.q +
+//             alpha^2 q.D^-1 q without another pass over the vectors.
+// This is the iteration of Jacobi-preconditioned CG with the residual and solution updates
+// of one step moved into the pass of the next; it reads z, w, p, x and the node code once
+// and writes z, w, p and x once per iteration.  z, w and p are double buffered by iteration
+// parity, because each tile also needs p on its halo, which it recomputes from the old
+// vectors of its neighbours.  The scalars never leave the device and all reductions run in
+// a fixed order, so a solve is run-to-run deterministic.
 //
-// The stencil kernel tiles the interior into 64 (z, one wave) x TY (y, 4 waves x TY/4 rows)
-// columns and marches along x over a chunk of planes, carrying the x-neighbours in
+// The iteration kernel tiles the interior into 64 (z, one wave) x TY (y, NWV waves x TY/NWV
+// rows) columns and marches along x over a chunk of planes, carrying the x-neighbours in
 // registers and staging the current plane with its y/z halo in LDS.  Tiles are numbered
 // z-fastest and handed out so that each XCD gets one contiguous range of tiles, which keeps
-// the y-halo rows of neighbouring tiles in the same L2.
+// the halo rows of neighbouring tiles in the same L2.
 #include "pb_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace pbk {
 
 namespace {
 
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh)
+// sum of NV doubles over a block of NW waves; every thread gets the totals (fixed order)
+template <int NV, int NW = 4>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int t = 0; t < NV; ++t) v[t] += __shfl_xor(v[t], o, 64);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
-    if (l == 0) {
-        sh[w] = a;
-        sh[4 + w] = b;
-    }
+    if (l == 0)
+#pragma unroll
+        for (int t = 0; t < NV; ++t) sh[NW * t + w] = v[t];
     __syncthreads();
-    a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+        double a = sh[NW * t];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) a += sh[NW * t + u];
+        v[t] = a;
+    }
 }
 
 template <typename T>
@@ -53,18 +67,6 @@ __device__ __forceinline__ T eK(uint32_t c, int ax, const T* __restrict__ ck, T 
 // from the compact table, an edge inside one medium takes h*eps of that medium.  The table
 // is always read (slot 0 for uncut edges) and the result is blended arithmetically, so the
 // load is never turned into a branch whose join would wait on every load in flight.
-template <typename T>
-__device__ __forceinline__ T edgeK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
-{
-    const bool cut = (c & (C_CUTX << ax)) != 0;
-    const int64_t ix = cut ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0;
-    const T v = ck[ix];
-    const T base = (c & C_SOLUTE) ? kin : kout;
-    const T m = cut ? (T)1 : (T)0;
-    return v * m + base * ((T)1 - m);
-}
-
-// the same split in two: the table index (any edge; slot 0 when uncut) and the blend
 __device__ __forceinline__ int64_t ck_index(uint32_t c, int ax)
 {
     return (c & (C_CUTX << ax)) ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0;
@@ -79,9 +81,14 @@ __device__ __forceinline__ T ck_blend(T v, uint32_t c, int ax, T kin, T kout)
 }
 
 template <typename T>
-struct Raw {   // what one node contributes to p_new = D^-1 r + beta p_old
-    T r, po;
-    float di;
+__device__ __forceinline__ T edgeK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
+{
+    return ck_blend(ck[ck_index(c, ax)], c, ax, kin, kout);
+}
+
+template <typename T>
+struct Old {   // the old vectors of one node, from which its new z and p follow
+    T z, w, p;
     uint32_t c;
 };
 
@@ -90,45 +97,62 @@ struct K3 {    // coefficients of the +x, +y, +z edges of a node
     T x, y, z;
 };
 
+// diagonal of the operator at a node from its six edge coefficients and the ionic term, in
+// one fixed order: every kernel that needs D sums it this way, so all agree bit for bit
 template <typename T>
-__device__ __forceinline__ void stencil_body(const Grid& g, const TileShape& ts, const CGBufs<T>& B, const Coef& cf,
-                                             const int bid)
+__device__ __forceinline__ T diag_sum(T kxm, T kxp, T kym, T kyp, T kzm, T kzp, T mt)
 {
-    constexpr int RY = TY / 4;
-    __shared__ double sh[8];
-    __shared__ T sp[TY + 2][66];   // p_new of plane i: rows j0-1..j0+TY, cols k0-1..k0+64
-    __shared__ T sky[TY + 1][64];  // K of the +y edge: rows j0-1..j0+TY-1, cols k0..k0+63
-    __shared__ T skz[TY][65];      // K of the +z edge: own rows, cols k0-1..k0+63
-    CGState* st = B.st;
-    if (st->status != 0) return;
-    const int par = st->iter_count & 1;
+    return ((kxm + kxp) + (kym + kyp)) + ((kzm + kzp) + mt);
+}
 
-    double rz = 0.0, rr = 0.0;
-    for (int t = threadIdx.x; t < B.nb2; t += 256) {
-        rz += B.part2[t];
-        rr += B.part2[B.nb2 + t];
-    }
-    block_sum2(rz, rr, sh);
-    const bool first = bid == 0 && threadIdx.x == 0;
-    if (rr <= st->stop2) {
-        if (first) {
-            st->status = st->stop_status;
-            st->iters = st->iter_count;
-            st->rr = rr;
-        }
-        return;
-    }
-    if (!isfinite(rz) || !isfinite(rr)) {
-        if (first) st->status = 2;
-        return;
-    }
-    const double beta = rz / st->rz[par ^ 1];
-    if (first) {
-        st->rz[par] = rz;
-        st->rr = rr;
-        st->par = par;
-    }
-    const T bT = (T)beta;
+template <typename T>
+__device__ __forceinline__ T node_diag(const Grid& g, const uint32_t* __restrict__ code, const T* __restrict__ ck,
+                                       T kin, T kout, T mass, int64_t e)
+{
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    const uint32_t c = code[e];
+    return diag_sum(edgeK(code[e - sx], 0, ck, kin, kout), edgeK(c, 0, ck, kin, kout),
+                    edgeK(code[e - sy], 1, ck, kin, kout), edgeK(c, 1, ck, kin, kout),
+                    edgeK(code[e - 1], 2, ck, kin, kout), edgeK(c, 2, ck, kin, kout),
+                    (c & C_SOLUTE) ? (T)0 : mass);
+}
+
+// element e of an array through a 32-bit byte offset from a uniform base (the grid is limited
+// so that every offset fits), which lets every load and store use one offset register
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t e)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t e)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * (uint32_t)sizeof(T));
+}
+
+// One iteration over one tile.  The preconditioned residual z = D^-1 r and w = D^-1 q are
+// kept instead of r and q, so a node's new p = (z - alpha w) + beta p_old needs no D^-1; the
+// tile computes D of its own nodes from the edge coefficients it has for q = A p, and forms
+// r = D z and q = D w there.
+//
+// Software pipeline along x: the old vectors of plane i+3 with their halo, and x of plane
+// i+2, are loaded while plane i is computed, into register slots numbered by plane modulo 4;
+// the loop body is unrolled four times so that every slot keeps its registers and no load in
+// flight is ever copied (a copy would wait for it).  Two LDS buffers alternate by plane, so
+// one barrier per plane suffices.
+template <typename T>
+__device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, const CGBufs<T>& B, const Coef& cf,
+                                          const int bid)
+{
+    constexpr int RY = TY / NWV;
+    __shared__ double sh[5 * NWV];
+    __shared__ T sp[2][TY + 2][66];   // p of plane i: rows j0-1..j0+TY, cols k0-1..k0+64
+    __shared__ T sky[2][TY + 1][64];  // K of the +y edge: rows j0-1..j0+TY-1, cols k0..k0+63
+    __shared__ T skz[2][TY][65];      // K of the +z edge: own rows, cols k0-1..k0+63
+    const CGState* st = B.st;
+    if (st->status != 0) return;
+    const int nw = st->iter_count & 1, od = nw ^ 1;
+    const T aT = (T)st->alpha, bT = (T)st->beta;
     const T kin = (T)cf.kin, kout = (T)cf.kout, mass = (T)cf.mass;
 
     // XCD-aware bijective block -> tile map (blocks are dealt round-robin to 8 XCDs)
@@ -144,160 +168,257 @@ __device__ __forceinline__ void stencil_body(const Grid& g, const TileShape& ts,
     const int ie = (ib + ts.LX < g.nx - 1) ? ib + ts.LX : g.nx - 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    const T* __restrict__ r = B.r;
-    const T* __restrict__ pold = B.p[par ^ 1];
-    T* __restrict__ pnew = B.p[par];
-    const float* __restrict__ dinv = B.dinv;
+    const T* __restrict__ z_o = B.z[od];
+    const T* __restrict__ w_o = B.w[od];
+    const T* __restrict__ p_o = B.p[od];
+    T* __restrict__ z_n = B.z[nw];
+    T* __restrict__ w_n = B.w[nw];
+    T* __restrict__ p_n = B.p[nw];
+    T* __restrict__ x = B.x;
     const uint32_t* __restrict__ code = B.code;
     const T* __restrict__ ck = B.ck;
-    const int64_t sx = (int64_t)g.ny * g.S;
+    const uint32_t sx = (uint32_t)g.ny * (uint32_t)g.S;
 
-    // Out-of-interior positions are clamped onto box nodes, where r = p = D^-1 = 0: every
-    // load below is unconditional and in bounds, and a clamped node contributes p_new = 0.
+    // Out-of-interior positions are clamped onto box nodes, where every vector is 0: every
+    // load below is unconditional and in bounds, and a clamped node has z = p = 0.
     auto clampj = [&](int j) { return j < 0 ? 0 : (j > g.ny - 1 ? g.ny - 1 : j); };
     auto clampk = [&](int k) { return k < 0 ? 0 : (k > g.nz - 1 ? g.nz - 1 : k); };
-    auto load = [&](int64_t e) {
-        Raw<T> v;
-        v.r = r[e];
-        v.po = pold[e];
-        v.di = dinv[e];
-        v.c = code[e];
+    auto load = [&](uint32_t e) {
+        Old<T> v;
+        v.z = at(z_o, e);
+        v.w = at(w_o, e);
+        v.p = at(p_o, e);
+        v.c = at(code, e);
         return v;
     };
-    auto pval = [&](const Raw<T>& v) { return (T)v.di * v.r + bT * v.po; };
+    auto znew = [&](const Old<T>& v) { return v.z - aT * v.w; };
+    auto pnew = [&](const Old<T>& v) { return znew(v) + bT * v.p; };
 
     // own columns (z = k0 + lane, rows j0 + wv*RY + q) and this thread's halo point
     const int k = k0 + lane;
     const int kc = clampk(k);
-    int64_t eo[RY];
+    uint32_t eo[RY];
     bool valid[RY];
 #pragma unroll
     for (int q = 0; q < RY; ++q) {
         const int j = j0 + wv * RY + q;
         valid[q] = j <= g.ny - 2 && k <= g.nz - 2;
-        eo[q] = g.idx(0, clampj(j), kc);
+        eo[q] = (uint32_t)g.idx(0, clampj(j), kc);
     }
     // halo: wave 0 row j0-1 (needs p and K+y), wave 1 row j0+TY (p), wave 2 column k0-1
-    // (p and K+z), wave 3 column k0+64 (p); waves 2 and 3 use their first TY lanes
+    // (p and K+z), wave 3 column k0+64 (p); waves 2 and 3 use their first TY lanes, further
+    // waves have no halo point (they load a node of their own tile and never use it)
     int hj, hk;
     bool hact = true;
     if (wv == 0) { hj = j0 - 1; hk = k0 + lane; }
     else if (wv == 1) { hj = j0 + TY; hk = k0 + lane; }
-    else { hact = lane < TY; hj = j0 + (lane < TY ? lane : TY - 1); hk = (wv == 2) ? k0 - 1 : k0 + 64; }
-    const int64_t eh = g.idx(0, clampj(hj), clampk(hk));
+    else if (wv <= 3) { hact = lane < TY; hj = j0 + (lane < TY ? lane : TY - 1); hk = (wv == 2) ? k0 - 1 : k0 + 64; }
+    else { hact = false; hj = j0; hk = k0; }
+    const uint32_t eh = (uint32_t)g.idx(0, clampj(hj), clampk(hk));
     const int hax = wv == 0 ? 1 : 2;
 
-    // prologue: plane ib-1 (p, K+x), ib (p, K), ib+1 (p, K), halo of ib (p, K)
-    T pm[RY], pc[RY], px[RY], kxm[RY];
-    uint32_t cc[RY], cxn[RY];   // node codes of planes i and i+1
-    K3<T> kr[RY];               // raw table reads for the edge coefficients of plane i
-    Raw<T> nxt[RY];
+    Old<T> rb[4][RY];   // old vectors of own planes, slot (plane - ib) % 4
+    Old<T> hb[4];       // halo, same slots
+    T xb[4][RY];        // x of own planes, same slots
+    K3<T> kr[2][RY];    // coefficient-table reads of own planes, slot (plane - ib) % 2
+    T hr[2];            // same for the halo
+    T pm[RY], pc[RY], kxm[RY];   // p of planes i-1 and i, K of the -x edges of plane i
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // p.q, r.z, r.r, z.q, q.D^-1 q (as D z w, D w w)
+
+    // prologue: plane ib-1 (p, K+x), planes ib..ib+2 and their halo, x of ib and ib+1
+    {
+        const uint32_t i1 = (uint32_t)(ib + 1 < ie ? ib + 1 : ie), i2 = (uint32_t)(ib + 2 < ie ? ib + 2 : ie);
+        const uint32_t h1 = (uint32_t)(ib + 1 < ie ? ib + 1 : ie - 1), h2 = (uint32_t)(ib + 2 < ie ? ib + 2 : ie - 1);
 #pragma unroll
-    for (int q = 0; q < RY; ++q) {
-        const Raw<T> a = load(eo[q] + (int64_t)(ib - 1) * sx);
-        const Raw<T> c0 = load(eo[q] + (int64_t)ib * sx);
-        const Raw<T> c1 = load(eo[q] + (int64_t)(ib + 1) * sx);
-        pm[q] = pval(a);
-        kxm[q] = edgeK(a.c, 0, ck, kin, kout);
-        pc[q] = pval(c0);
-        cc[q] = c0.c;
-        kr[q].x = ck[ck_index(c0.c, 0)];
-        kr[q].y = ck[ck_index(c0.c, 1)];
-        kr[q].z = ck[ck_index(c0.c, 2)];
-        px[q] = pval(c1);
-        cxn[q] = c1.c;
+        for (int q = 0; q < RY; ++q) {
+            const Old<T> a = load(eo[q] + (uint32_t)(ib - 1) * sx);
+            rb[0][q] = load(eo[q] + (uint32_t)ib * sx);
+            rb[1][q] = load(eo[q] + i1 * sx);
+            rb[2][q] = load(eo[q] + i2 * sx);
+            xb[0][q] = at(x, eo[q] + (uint32_t)ib * sx);
+            xb[1][q] = at(x, eo[q] + h1 * sx);
+            pm[q] = pnew(a);
+            kxm[q] = edgeK(a.c, 0, ck, kin, kout);
+            pc[q] = pnew(rb[0][q]);
+            kr[0][q].x = ck[ck_index(rb[0][q].c, 0)];
+            kr[0][q].y = ck[ck_index(rb[0][q].c, 1)];
+            kr[0][q].z = ck[ck_index(rb[0][q].c, 2)];
+        }
+        hb[0] = load(eh + (uint32_t)ib * sx);
+        hb[1] = load(eh + h1 * sx);
+        hb[2] = load(eh + h2 * sx);
+        hr[0] = ck[ck_index(hb[0].c, hax)];
     }
-    Raw<T> hraw = load(eh + (int64_t)ib * sx);
-    T hv = pval(hraw);
-    uint32_t hc = hraw.c;
-    T hr = ck[ck_index(hc, hax)];
 
-    T acc = (T)0;
-    for (int i = ib; i < ie; ++i) {
-        // prefetch: own plane i+2 (never past plane ie, the last one this chunk needs) and
-        // the halo of plane i+1
-        const int i2 = (i + 2 < ie) ? i + 2 : ie;
+    // Load distances: own planes and halo 3 planes ahead, x 2 planes ahead, table reads
+    // 1 plane ahead.  Loads complete in issue order as far as the wait counter is concerned,
+    // so each step first issues what the next step needs (the table reads of plane i+1),
+    // then the far prefetch.
+    auto step = [&](const int i, auto slot) {
+        constexpr int S0 = decltype(slot)::value;
+        constexpr int S1 = (S0 + 1) & 3, S2 = (S0 + 2) & 3, S3 = (S0 + 3) & 3;
+        constexpr int L = S0 & 1;
+        // plane i+1 has arrived: its p, and its table reads
+        T px[RY];
 #pragma unroll
-        for (int q = 0; q < RY; ++q) nxt[q] = load(eo[q] + (int64_t)i2 * sx);
-        const Raw<T> hn = load(eh + (int64_t)(i + 1) * sx);
+        for (int q = 0; q < RY; ++q) {
+            px[q] = pnew(rb[S1][q]);
+            kr[L ^ 1][q].x = ck[ck_index(rb[S1][q].c, 0)];
+            kr[L ^ 1][q].y = ck[ck_index(rb[S1][q].c, 1)];
+            kr[L ^ 1][q].z = ck[ck_index(rb[S1][q].c, 2)];
+        }
+        hr[L ^ 1] = ck[ck_index(hb[S1].c, hax)];
+        __builtin_amdgcn_sched_barrier(0);   // keep the issue order: table reads, then prefetch
+        // prefetch: own plane i+3 (never past plane ie, the last one this chunk needs), its
+        // halo and x of plane i+2 (never past ie-1)
+        {
+            const uint32_t i3 = (uint32_t)(i + 3 < ie ? i + 3 : ie);
+            const uint32_t h3 = (uint32_t)(i + 3 < ie ? i + 3 : ie - 1);
+            const uint32_t i2 = (uint32_t)(i + 2 < ie ? i + 2 : ie - 1);
+#pragma unroll
+            for (int q = 0; q < RY; ++q) {
+                rb[S3][q] = load(eo[q] + i3 * sx);
+                xb[S2][q] = at(x, eo[q] + i2 * sx);
+            }
+            hb[S3] = load(eh + h3 * sx);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 
-        // stage plane i in LDS: p_new and the +y/+z edge coefficients
+        // stage plane i in LDS: p and the +y/+z edge coefficients
         K3<T> kc3[RY];
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             const int row = wv * RY + q;
-            kc3[q].x = ck_blend(kr[q].x, cc[q], 0, kin, kout);
-            kc3[q].y = ck_blend(kr[q].y, cc[q], 1, kin, kout);
-            kc3[q].z = ck_blend(kr[q].z, cc[q], 2, kin, kout);
-            sp[1 + row][1 + lane] = pc[q];
-            sky[1 + row][lane] = kc3[q].y;
-            skz[row][1 + lane] = kc3[q].z;
+            const uint32_t cc = rb[S0][q].c;
+            kc3[q].x = ck_blend(kr[L][q].x, cc, 0, kin, kout);
+            kc3[q].y = ck_blend(kr[L][q].y, cc, 1, kin, kout);
+            kc3[q].z = ck_blend(kr[L][q].z, cc, 2, kin, kout);
+            sp[L][1 + row][1 + lane] = pc[q];
+            sky[L][1 + row][lane] = kc3[q].y;
+            skz[L][row][1 + lane] = kc3[q].z;
         }
-        const T hK = ck_blend(hr, hc, hax, kin, kout);
-        if (wv == 0) {
-            sp[0][1 + lane] = hv;
-            sky[0][lane] = hK;
-        } else if (wv == 1) {
-            sp[TY + 1][1 + lane] = hv;
-        } else if (hact) {
-            if (wv == 2) {
-                sp[1 + lane][0] = hv;
-                skz[lane][0] = hK;
-            } else {
-                sp[1 + lane][65] = hv;
+        {
+            const T hv = pnew(hb[S0]);
+            const T hK = ck_blend(hr[L], hb[S0].c, hax, kin, kout);
+            if (wv == 0) {
+                sp[L][0][1 + lane] = hv;
+                sky[L][0][lane] = hK;
+            } else if (wv == 1) {
+                sp[L][TY + 1][1 + lane] = hv;
+            } else if (hact) {   // waves 2 and 3
+                if (wv == 2) {
+                    sp[L][1 + lane][0] = hv;
+                    skz[L][lane][0] = hK;
+                } else {
+                    sp[L][1 + lane][65] = hv;
+                }
             }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < RY; ++q) {
             const int row = wv * RY + q;
-            const T Kym = sky[row][lane], Kyp = sky[1 + row][lane];
-            const T Kzm = skz[row][lane], Kzp = skz[row][1 + lane];
+            const Old<T>& o = rb[S0][q];
+            const T Kym = sky[L][row][lane], Kyp = sky[L][1 + row][lane];
+            const T Kzm = skz[L][row][lane], Kzp = skz[L][row][1 + lane];
             const T Kxp = kc3[q].x;
-            const T D = ((kxm[q] + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((cc[q] & C_SOLUTE) ? (T)0 : mass));
+            const T D = diag_sum(kxm[q], Kxp, Kym, Kyp, Kzm, Kzp, (o.c & C_SOLUTE) ? (T)0 : mass);
             const T p0 = pc[q];
-            const T nbs = kxm[q] * pm[q] + Kxp * px[q] + Kym * sp[row][1 + lane] +
-                          Kyp * sp[row + 2][1 + lane] + Kzm * sp[1 + row][lane] + Kzp * sp[1 + row][2 + lane];
+            const T nbs = kxm[q] * pm[q] + Kxp * px[q] + Kym * sp[L][row][1 + lane] +
+                          Kyp * sp[L][row + 2][1 + lane] + Kzm * sp[L][1 + row][lane] + Kzp * sp[L][1 + row][2 + lane];
             const T qv = D * p0 - nbs;
-            // a lane outside the interior was clamped onto a box node, whose p and q stay
+            const T zv = znew(o);
+            const T wv_ = qv / D;
+            const T xv = xb[S0][q] + aT * o.p;
+            // a lane outside the interior was clamped onto a box node, whose vectors stay
             // 0: it stores zeros there, so the stores need no branch
-            const int64_t e = eo[q] + (int64_t)i * sx;
-            pnew[e] = valid[q] ? p0 : (T)0;
-            B.q[e] = valid[q] ? qv : (T)0;
-            acc += valid[q] ? p0 * qv : (T)0;
-        }
-        __syncthreads();
-        // rotate.  The coefficient lookups of plane i+1 are issued last, straight into the
-        // registers that consume them, so no register copy waits on a load in flight and
-        // the next step's prefetch loads are never waited for before they are needed.
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            pm[q] = pc[q];
-            kxm[q] = kc3[q].x;
+            const bool ok = valid[q] && i < ie;
+            const uint32_t e = eo[q] + (uint32_t)(i < ie ? i : g.nx - 1) * sx;
+            at(z_n, e) = ok ? zv : (T)0;
+            at(w_n, e) = ok ? wv_ : (T)0;
+            at(p_n, e) = ok ? p0 : (T)0;
+            at(x, e) = ok ? xv : (T)0;
+            const double dD = ok ? (double)D : 0.0;
+            const double dz = (double)zv, dw = (double)wv_, dq = (double)qv, dzD = dD * dz, dwD = dD * dw;
+            acc[0] += ok ? (double)p0 * dq : 0.0;
+            acc[1] += dzD * dz;
+            acc[2] += dzD * dzD;
+            acc[3] += dzD * dw;
+            acc[4] += dwD * dw;
+            kxm[q] = Kxp;
+            pm[q] = p0;
             pc[q] = px[q];
-            cc[q] = cxn[q];
-            px[q] = pval(nxt[q]);
-            cxn[q] = nxt[q].c;
         }
-        hv = pval(hn);
-        hc = hn.c;
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            kr[q].x = ck[ck_index(cc[q], 0)];
-            kr[q].y = ck[ck_index(cc[q], 1)];
-            kr[q].z = ck[ck_index(cc[q], 2)];
-        }
-        hr = ck[ck_index(hc, hax)];
+    };
+
+    // Whole groups of four planes, so the loop body has no branch: a plane past the chunk's
+    // last one (only in the last chunk along x, when its length is not a multiple of four)
+    // is computed from clamped loads and stores its zeros onto the box face x = nx-1, whose
+    // vectors are 0, like a lane outside the interior.
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
+    using C3 = std::integral_constant<int, 3>;
+    for (int i = ib; i < ie; i += 4) {
+        step(i, C0{});
+        step(i + 1, C1{});
+        step(i + 2, C2{});
+        step(i + 3, C3{});
     }
-    double a = (double)acc, dummy = 0.0;
-    block_sum2(a, dummy, sh);
-    if (threadIdx.x == 0) B.part1[bid] = a;
+    block_sum<5, NWV>(acc, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int u = 0; u < 5; ++u) B.part[(int64_t)u * B.nb + bid] = acc[u];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_stencil(Grid g, TileShape ts, CGBufs<T> B, Coef cf)
+__global__ void __launch_bounds__(64 * NWV) k_cg_iter(Grid g, TileShape ts, CGBufs<T> B, Coef cf)
 {
-    stencil_body(g, ts, B, cf, (int)blockIdx.x);
+    iter_body(g, ts, B, cf, (int)blockIdx.x);
+}
+
+// one block: reduce the iteration's partial sums and set the scalars of the next iteration
+__device__ __forceinline__ void tail_body(const double* __restrict__ part, int nb, CGState* st)
+{
+    __shared__ double sh[20];
+    if (st->status != 0) return;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nb; t += 256)
+#pragma unroll
+        for (int u = 0; u < 5; ++u) v[u] += part[(int64_t)u * nb + t];
+    block_sum<5>(v, sh);
+    if (threadIdx.x != 0) return;
+    const double pq = v[0], gm = v[1], rr = v[2], zq = v[3], qq = v[4];
+    const int it = st->iter_count;
+    st->iter_count = it + 1;
+    st->rr = rr;
+    st->pq = pq;
+    if (!isfinite(pq) || !isfinite(gm) || !isfinite(rr) || !isfinite(zq) || !isfinite(qq)) {
+        st->status = 2;
+        st->iters = it;
+        return;
+    }
+    double alpha = 0.0, beta = 0.0;
+    if (pq > 0.0 && gm > 0.0) {
+        alpha = gm / pq;
+        const double gn = (gm - 2.0 * alpha * zq) + alpha * alpha * qq;
+        beta = gn > 0.0 ? gn / gm : 0.0;
+    }
+    st->alpha = alpha;
+    st->beta = beta;
+    st->gamma = gm;
+    if (rr <= st->stop2) {
+        st->status = st->stop_status;
+        st->iters = it;
+    } else if (!(pq > 0.0)) {
+        st->status = 2;
+        st->iters = it;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg_tail(const double* __restrict__ part, int nb, CGState* st)
+{
+    tail_body(part, nb, st);
 }
 
 template <typename T>
@@ -311,111 +432,45 @@ struct Vec4<float> {
     using type = float4;
 };
 
+// z_old = D^-1 b (the buffer the first iteration reads), x = 0, the other z and w, p of both
+// parities = 0 (box and padding nodes are never written by the iteration and must read 0),
+// partial sums of ||b||^2
 template <typename T>
-__device__ __forceinline__ void update_body(int64_t n4, const CGBufs<T>& B, const int bid, const int nblk)
+__global__ void __launch_bounds__(256) k_cg_init(Grid g, CGBufs<T> B, Coef cf, const double* b64, const T* bT)
 {
-    __shared__ double sh[8];
-    CGState* st = B.st;
-    if (st->status != 0) return;
-    const int par = st->par;
-    double pq = 0.0, dummy = 0.0;
-    for (int t = threadIdx.x; t < B.nb1; t += 256) pq += B.part1[t];
-    block_sum2(pq, dummy, sh);
-    const bool first = bid == 0 && threadIdx.x == 0;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-        if (first) {
-            st->status = 2;
-            st->pq = pq;
-        }
-        return;
-    }
-    const T aT = (T)(st->rz[par] / pq);
-    using V = typename Vec4<T>::type;
-    V* __restrict__ x = reinterpret_cast<V*>(B.x);
-    V* __restrict__ r = reinterpret_cast<V*>(B.r);
-    const V* __restrict__ p = reinterpret_cast<const V*>(B.p[par]);
-    const V* __restrict__ q = reinterpret_cast<const V*>(B.q);
-    const float4* __restrict__ dv = reinterpret_cast<const float4*>(B.dinv);
-    T rz = (T)0, rr = (T)0;
-    const int64_t stride = (int64_t)nblk * 256;
-    for (int64_t v = (int64_t)bid * 256 + threadIdx.x; v < n4; v += stride) {
-        V xv = x[v], rv = r[v];
-        const V pv = p[v], qv = q[v];
-        const float4 d = dv[v];
-        xv.x += aT * pv.x; xv.y += aT * pv.y; xv.z += aT * pv.z; xv.w += aT * pv.w;
-        rv.x -= aT * qv.x; rv.y -= aT * qv.y; rv.z -= aT * qv.z; rv.w -= aT * qv.w;
-        x[v] = xv;
-        r[v] = rv;
-        rz += rv.x * ((T)d.x * rv.x) + rv.y * ((T)d.y * rv.y) + rv.z * ((T)d.z * rv.z) + rv.w * ((T)d.w * rv.w);
-        rr += rv.x * rv.x + rv.y * rv.y + rv.z * rv.z + rv.w * rv.w;
-    }
-    double a = (double)rz, c = (double)rr;
-    block_sum2(a, c, sh);
-    if (threadIdx.x == 0) {
-        B.part2[bid] = a;
-        B.part2[B.nb2 + bid] = c;
-    }
-    if (first) st->iter_count += 1;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_update(int64_t n4, CGBufs<T> B)
-{
-    update_body(n4, B, (int)blockIdx.x, (int)gridDim.x);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_init(int64_t n4, CGBufs<T> B, const double* b64, const T* bT)
-{
-    __shared__ double sh[8];
-    using V = typename Vec4<T>::type;
-    T rz = (T)0, rr = (T)0;
+    __shared__ double sh[4];
+    const T kin = (T)cf.kin, kout = (T)cf.kout, mass = (T)cf.mass;
+    double rr = 0.0;
     const int64_t stride = (int64_t)gridDim.x * 256;
-    V* x = reinterpret_cast<V*>(B.x);
-    V* r = reinterpret_cast<V*>(B.r);
-    V* p0 = reinterpret_cast<V*>(B.p[0]);
-    V* p1 = reinterpret_cast<V*>(B.p[1]);
-    V* q = reinterpret_cast<V*>(B.q);
-    const float4* dv = reinterpret_cast<const float4*>(B.dinv);
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n4; v += stride) {
-        V bv;
-        if (b64) {
-            const double4 t = reinterpret_cast<const double4*>(b64)[v];
-            bv.x = (T)t.x; bv.y = (T)t.y; bv.z = (T)t.z; bv.w = (T)t.w;
-        } else {
-            bv = reinterpret_cast<const V*>(bT)[v];
-        }
-        const float4 d = dv[v];
-        V z0;
-        z0.x = 0; z0.y = 0; z0.z = 0; z0.w = 0;
-        x[v] = z0;
-        p0[v] = z0;
-        p1[v] = z0;
-        q[v] = z0;
-        r[v] = bv;
-        rz += bv.x * ((T)d.x * bv.x) + bv.y * ((T)d.y * bv.y) + bv.z * ((T)d.z * bv.z) + bv.w * ((T)d.w * bv.w);
-        rr += bv.x * bv.x + bv.y * bv.y + bv.z * bv.z + bv.w * bv.w;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += stride) {
+        const T bv = b64 ? (T)b64[e] : bT[e];
+        T zv = (T)0;
+        if (!(B.code[e] & C_BOX)) zv = bv / node_diag(g, B.code, B.ck, kin, kout, mass, e);
+        B.x[e] = (T)0;
+        B.z[0][e] = (T)0;
+        B.z[1][e] = zv;
+        B.w[0][e] = (T)0;
+        B.w[1][e] = (T)0;
+        B.p[0][e] = (T)0;
+        B.p[1][e] = (T)0;
+        rr += (double)bv * (double)bv;
     }
-    double a = (double)rz, c = (double)rr;
-    block_sum2(a, c, sh);
-    if (threadIdx.x == 0) {
-        B.part2[blockIdx.x] = a;
-        B.part2[B.nb2 + blockIdx.x] = c;
-    }
+    double a[1] = {rr};
+    block_sum<1>(a, sh);
+    if (threadIdx.x == 0) B.part[blockIdx.x] = a[0];
 }
 
-__global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CGState* st, double rtol2)
+__global__ void __launch_bounds__(256) k_cg_fin(const double* part, int nb, CGState* st, double rtol2)
 {
-    __shared__ double sh[8];
-    double rz = 0.0, rr = 0.0;
-    for (int t = threadIdx.x; t < nb2; t += 256) {
-        rz += part2[t];
-        rr += part2[nb2 + t];
-    }
-    block_sum2(rz, rr, sh);
+    __shared__ double sh[4];
+    double a[1] = {0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) a[0] += part[t];
+    block_sum<1>(a, sh);
     if (threadIdx.x == 0) {
-        st->rz[0] = rz;
-        st->rz[1] = INFINITY;  // first iteration: beta = rz / inf = 0
+        const double rr = a[0];
+        st->alpha = 0.0;
+        st->beta = 0.0;
+        st->gamma = 0.0;
         st->bnorm2 = rr;
         st->rr = rr;
         st->pq = 0.0;
@@ -424,57 +479,69 @@ __global__ void __launch_bounds__(256) k_cg_fin(const double* part2, int nb2, CG
         st->delta2 = 0.0;
         st->goal64 = 0.0;
         st->rr64 = 0.0;
-        st->status = 0;
+        st->status = rr > 0.0 ? 0 : 1;
         st->stop_status = 1;
         st->iters = 0;
         st->iter_count = 0;
-        st->par = 0;
         st->ru = 0;
         st->n_ru = 0;
-        st->pad = 0;
     }
 }
 
 // ---- mixed precision: FP32 CG with FP64 reliable updates ------------------------------------
-// The FP32 iteration runs on; a reliable update folds the FP32 correction into the FP64
-// solution and replaces the FP32 residual by the FP64 true residual b - A x64 (FP64 operator,
-// exact coefficients), keeping the search direction.  An update runs at a chunk end once the
-// recursive residual has dropped by delta since the last one, or when the recursive residual
-// reaches the target (the stencil kernel then stops with status 3).
+// The FP32 iteration runs on; a reliable update takes the pending step of the last
+// iteration, folds the FP32 correction into the FP64 solution and replaces the FP32
+// residual by the FP64 true residual b - A x64 (FP64 operator, exact coefficients; stored as
+// z = D^-1 r), keeping the search direction: the next iteration then continues with
+// alpha = 0 and beta = r_true.z_true / r.z.  An update runs at a chunk end once the recursive residual has
+// dropped by delta since the last one, or when the recursive residual reaches the target
+// (the tail then stops with status 3).
 
-__device__ __forceinline__ void ru_add_body(int64_t n4, CGState* st, double* x, float* d, int force, const int bid,
+__device__ __forceinline__ void ru_add_body(int64_t n4, CGState* st, double* __restrict__ x, float* __restrict__ d,
+                                            const float* p0, const float* p1, int force, const int bid,
                                             const int nblk)
 {
     const int s0 = st->status;
     const bool go = (s0 == 3) || (s0 == 0 && (force || st->rr <= st->trig2));
     if (!go) return;
+    const double a = st->alpha;
+    const float4* __restrict__ p = reinterpret_cast<const float4*>(((st->iter_count - 1) & 1) ? p1 : p0);
     const int64_t stride = (int64_t)nblk * 256;
     for (int64_t v = (int64_t)bid * 256 + threadIdx.x; v < n4; v += stride) {
         double4 xv = reinterpret_cast<double4*>(x)[v];
         const float4 dv = reinterpret_cast<const float4*>(d)[v];
-        xv.x += (double)dv.x; xv.y += (double)dv.y; xv.z += (double)dv.z; xv.w += (double)dv.w;
+        const float4 pv = p[v];
+        xv.x += (double)dv.x + a * (double)pv.x;
+        xv.y += (double)dv.y + a * (double)pv.y;
+        xv.z += (double)dv.z + a * (double)pv.z;
+        xv.w += (double)dv.w + a * (double)pv.w;
         reinterpret_cast<double4*>(x)[v] = xv;
         reinterpret_cast<float4*>(d)[v] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     if (bid == 0 && threadIdx.x == 0) st->ru = 1;
 }
 
-__global__ void __launch_bounds__(256) k_ru_add(int64_t n4, CGState* st, double* x, float* d, int force)
+__global__ void __launch_bounds__(256) k_ru_add(int64_t n4, CGState* st, double* x, float* d, float* p0, float* p1,
+                                                int force)
 {
-    ru_add_body(n4, st, x, d, force, (int)blockIdx.x, (int)gridDim.x);
+    ru_add_body(n4, st, x, d, p0, p1, force, (int)blockIdx.x, (int)gridDim.x);
 }
 
+// r_true = b - A x64 in FP64; z = r_true / D (D of the FP32 operator, as the iteration forms
+// it) stored as FP32 into the buffer the next iteration reads; partial sums of ||r_true||^2
+// (FP64) and of r.z, r.r as the FP32 iteration sees them (r = D z)
 __device__ __forceinline__ void ru_residual_body(const Grid& g, const uint32_t* __restrict__ code,
-                                                 const double* __restrict__ ck, const Coef& cf,
-                                                 const double* __restrict__ b, const double* __restrict__ x,
-                                                 const float* __restrict__ dinv, float* __restrict__ r32,
-                                                 double* __restrict__ part3, CGState* st, const int bid, const int nblk)
+                                                 const double* __restrict__ ck, const float* __restrict__ ck32,
+                                                 const Coef& cf, const double* __restrict__ b,
+                                                 const double* __restrict__ x, float* z0, float* z1,
+                                                 double* __restrict__ part3, const CGState* st, const int bid,
+                                                 const int nblk)
 {
-    __shared__ double sh[8];
+    __shared__ double sh[12];
     if (!st->ru) return;
+    float* __restrict__ zout = ((st->iter_count - 1) & 1) ? z1 : z0;
     const int64_t e = (int64_t)bid * 256 + threadIdx.x;
-    double rr64 = 0.0;
-    float rz32 = 0.0f, rr32 = 0.0f;
+    double v[3] = {0.0, 0.0, 0.0};
     if (e < g.N) {
         const uint32_t c = code[e];
         float out = 0.0f;
@@ -490,61 +557,54 @@ __device__ __forceinline__ void ru_residual_body(const Grid& g, const uint32_t* 
             const double ax = D * x[e] - (Kxm * x[e - sx] + Kxp * x[e + sx] + Kym * x[e - sy] +
                                           Kyp * x[e + sy] + Kzm * x[e - 1] + Kzp * x[e + 1]);
             const double rv = b[e] - ax;
-            rr64 = rv * rv;
-            out = (float)rv;
-            rz32 = out * (dinv[e] * out);
-            rr32 = out * out;
+            v[0] = rv * rv;
+            const float D32 = node_diag(g, code, ck32, (float)cf.kin, (float)cf.kout, (float)cf.mass, e);
+            out = (float)rv / D32;
+            const double dz = (double)out, dzD = (double)D32 * dz;
+            v[1] = dzD * dz;
+            v[2] = dzD * dzD;
         }
-        r32[e] = out;
+        zout[e] = out;
     }
-    double a = (double)rz32, c2 = (double)rr32;
-    block_sum2(a, c2, sh);
-    double dummy = 0.0;
-    block_sum2(rr64, dummy, sh);
+    block_sum<3>(v, sh);
     if (threadIdx.x == 0) {
-        part3[bid] = rr64;
-        part3[nblk + bid] = a;
-        part3[2 * nblk + bid] = c2;
+        part3[bid] = v[0];
+        part3[nblk + bid] = v[1];
+        part3[2 * nblk + bid] = v[2];
     }
 }
 
 __global__ void __launch_bounds__(256) k_ru_residual(Grid g, const uint32_t* __restrict__ code,
-                                                     const double* __restrict__ ck, Coef cf,
-                                                     const double* __restrict__ b, const double* __restrict__ x,
-                                                     const float* __restrict__ dinv, float* __restrict__ r32,
-                                                     double* __restrict__ part3, CGState* st)
+                                                     const double* __restrict__ ck, const float* __restrict__ ck32,
+                                                     Coef cf, const double* __restrict__ b,
+                                                     const double* __restrict__ x, float* z0, float* z1,
+                                                     double* __restrict__ part3, const CGState* st)
 {
-    ru_residual_body(g, code, ck, cf, b, x, dinv, r32, part3, st, (int)blockIdx.x, (int)gridDim.x);
+    ru_residual_body(g, code, ck, ck32, cf, b, x, z0, z1, part3, st, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __global__ void k_ru_begin(CGState* st)
 {
     st->status = 0;
+    st->iter_count = 0;
     st->ru = 1;
 }
 
 // one block: finish a reliable update (or, with init, set up the mixed iteration)
-__device__ __forceinline__ void ru_fin_body(CGState* st, const double* part3, int nbres, double* part2, int nb2,
-                                            int init, double rtol2, double delta2)
+__device__ __forceinline__ void ru_fin_body(CGState* st, const double* part3, int nbres, int init, double rtol2,
+                                            double delta2)
 {
-    __shared__ double sh[8];
+    __shared__ double sh[12];
     if (!st->ru) return;
-    double rr64 = 0.0, rz = 0.0, rr = 0.0, dummy = 0.0;
-    for (int t = threadIdx.x; t < nbres; t += 256) {
-        rr64 += part3[t];
-        rz += part3[nbres + t];
-        rr += part3[2 * nbres + t];
-    }
-    block_sum2(rz, rr, sh);
-    block_sum2(rr64, dummy, sh);
-    for (int t = threadIdx.x; t < nb2; t += 256) {
-        part2[t] = t == 0 ? rz : 0.0;
-        part2[nb2 + t] = t == 0 ? rr : 0.0;
-    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nbres; t += 256)
+#pragma unroll
+        for (int u = 0; u < 3; ++u) v[u] += part3[(int64_t)u * nbres + t];
+    block_sum<3>(v, sh);
     if (threadIdx.x == 0) {
+        const double rr64 = v[0], gm = v[1], rr = v[2];
         if (init) {
-            st->rz[0] = rz;
-            st->rz[1] = INFINITY;
+            st->beta = 0.0;
             st->bnorm2 = rr;
             st->pq = 0.0;
             st->stop2 = rtol2 * rr;
@@ -553,12 +613,13 @@ __device__ __forceinline__ void ru_fin_body(CGState* st, const double* part3, in
             st->stop_status = 3;
             st->iters = 0;
             st->iter_count = 0;
-            st->par = 0;
             st->n_ru = 0;
-            st->pad = 0;
         } else {
+            st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
             st->n_ru += 1;
         }
+        st->alpha = 0.0;
+        st->gamma = gm;
         st->rr = rr;
         st->rr64 = rr64;
         st->trig2 = st->delta2 * rr;
@@ -572,10 +633,10 @@ __device__ __forceinline__ void ru_fin_body(CGState* st, const double* part3, in
     }
 }
 
-__global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3, int nbres, double* part2,
-                                                int nb2, int init, double rtol2, double delta2)
+__global__ void __launch_bounds__(256) k_ru_fin(CGState* st, const double* part3, int nbres, int init, double rtol2,
+                                                double delta2)
 {
-    ru_fin_body(st, part3, nbres, part2, nb2, init, rtol2, delta2);
+    ru_fin_body(st, part3, nbres, init, rtol2, delta2);
 }
 
 // plain streaming copy with non-temporal accesses: the attainable-bandwidth reference (and the
@@ -607,26 +668,24 @@ __device__ __forceinline__ int find_prob(const int* __restrict__ off, int P, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) kb_stencil(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
+__global__ void __launch_bounds__(64 * NWV) kb_iter(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
 {
     const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
     const ProbDev<T>& d = D[p];
-    stencil_body(d.g, d.ts, d.B, d.cf, (int)blockIdx.x - off[p]);
+    iter_body(d.g, d.ts, d.B, d.cf, (int)blockIdx.x - off[p]);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) kb_update(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
+__global__ void __launch_bounds__(256) kb_tail(const ProbDev<float>* __restrict__ D)
 {
-    const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
-    const ProbDev<T>& d = D[p];
-    update_body(d.g.N / 4, d.B, (int)blockIdx.x - off[p], d.B.nb2);
+    const ProbDev<float>& d = D[blockIdx.x];
+    tail_body(d.B.part, d.B.nb, d.B.st);
 }
 
 __global__ void __launch_bounds__(256) kb_ru_add(const ProbDev<float>* __restrict__ D, const int* __restrict__ off, int P)
 {
     const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
     const ProbDev<float>& d = D[p];
-    ru_add_body(d.g.N / 4, d.B.st, d.x64, d.B.x, 0, (int)blockIdx.x - off[p], d.nadd);
+    ru_add_body(d.g.N / 4, d.B.st, d.x64, d.B.x, d.B.p[0], d.B.p[1], 0, (int)blockIdx.x - off[p], d.nadd);
 }
 
 __global__ void __launch_bounds__(256) kb_ru_residual(const ProbDev<float>* __restrict__ D, const int* __restrict__ off,
@@ -634,14 +693,14 @@ __global__ void __launch_bounds__(256) kb_ru_residual(const ProbDev<float>* __re
 {
     const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
     const ProbDev<float>& d = D[p];
-    ru_residual_body(d.g, d.B.code, d.ck64, d.cf, d.rhs, d.x64, d.B.dinv, d.B.r, d.part3, d.B.st,
+    ru_residual_body(d.g, d.B.code, d.ck64, d.B.ck, d.cf, d.rhs, d.x64, d.B.z[0], d.B.z[1], d.part3, d.B.st,
                      (int)blockIdx.x - off[p], d.nbres);
 }
 
 __global__ void __launch_bounds__(256) kb_ru_fin(const ProbDev<float>* __restrict__ D)
 {
     const ProbDev<float>& d = D[blockIdx.x];
-    ru_fin_body(d.B.st, d.part3, d.nbres, d.B.part2, d.B.nb2, 0, 0.0, 0.0);
+    ru_fin_body(d.B.st, d.part3, d.nbres, 0, 0.0, 0.0);
 }
 
 __global__ void kb_gather(const ProbDev<float>* __restrict__ D, int P, CGState* out)
@@ -656,14 +715,13 @@ hipError_t launch_batch_chunk(hipStream_t s, const ProbDev<float>* D, const int*
                               int iters, CGState* gather_out, hipEvent_t* ev)
 {
     const int* off_st = off;
-    const int* off_up = off + (P + 1);
-    const int* off_add = off + 2 * (P + 1);
-    const int* off_res = off + 3 * (P + 1);
+    const int* off_add = off + (P + 1);
+    const int* off_res = off + 2 * (P + 1);
     for (int it = 0; it < iters; ++it) {
         if (ev) (void)hipEventRecord(ev[2 * it], s);
-        kb_stencil<float><<<t.st, 256, 0, s>>>(D, off_st, P);
+        kb_iter<float><<<t.st, 64 * NWV, 0, s>>>(D, off_st, P);
         if (ev) (void)hipEventRecord(ev[2 * it + 1], s);
-        kb_update<float><<<t.up, 256, 0, s>>>(D, off_up, P);
+        kb_tail<<<P, 256, 0, s>>>(D);
     }
     kb_ru_add<<<t.add, 256, 0, s>>>(D, off_add, P);
     kb_ru_residual<<<t.res, 256, 0, s>>>(D, off_res, P);
@@ -700,52 +758,38 @@ TileShape make_tiles(const Grid& g)
     return t;
 }
 
-int update_blocks(const Grid& g)
-{
-    const int64_t n4 = g.N / 4;
-    int64_t b = (n4 + 255) / 256;
-    if (b > 512) b = 512;
-    if (b < 1) b = 1;
-    return (int)b;
-}
-
 template <typename T>
-hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, const double* b64, const T* bT)
+hipError_t launch_cg_init(hipStream_t s, const Grid& g, const CGBufs<T>& B, Coef c, const double* b64, const T* bT)
 {
-    k_cg_init<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B, b64, bT);
+    k_cg_init<T><<<B.nb, 256, 0, s>>>(g, B, c, b64, bT);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_fin(hipStream_t s, double* part2, int nb2, CGState* st, double rtol2)
+hipError_t launch_cg_fin(hipStream_t s, const double* part, int nb, CGState* st, double rtol2)
 {
-    k_cg_fin<<<1, 256, 0, s>>>(part2, nb2, st, rtol2);
+    k_cg_fin<<<1, 256, 0, s>>>(part, nb, st, rtol2);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cg_stencil(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c)
+hipError_t launch_cg_iter(hipStream_t s, const Grid& g, const TileShape& ts, const CGBufs<T>& B, Coef c)
 {
-    k_cg_stencil<T><<<ts.items, 256, 0, s>>>(g, ts, B, c);
+    k_cg_iter<T><<<ts.items, 64 * NWV, 0, s>>>(g, ts, B, c);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_cg_update(hipStream_t s, const Grid& g, const CGBufs<T>& B)
+hipError_t launch_cg_tail(hipStream_t s, const double* part, int nb, CGState* st)
 {
-    k_cg_update<T><<<B.nb2, 256, 0, s>>>(g.N / 4, B);
+    k_cg_tail<<<1, 256, 0, s>>>(part, nb, st);
     return hipGetLastError();
 }
 
-template hipError_t launch_cg_init<double>(hipStream_t, const Grid&, const CGBufs<double>&, const double*,
+template hipError_t launch_cg_init<double>(hipStream_t, const Grid&, const CGBufs<double>&, Coef, const double*,
                                            const double*);
-template hipError_t launch_cg_init<float>(hipStream_t, const Grid&, const CGBufs<float>&, const double*,
+template hipError_t launch_cg_init<float>(hipStream_t, const Grid&, const CGBufs<float>&, Coef, const double*,
                                           const float*);
-template hipError_t launch_cg_stencil<double>(hipStream_t, const Grid&, const TileShape&,
-                                              const CGBufs<double>&, Coef);
-template hipError_t launch_cg_stencil<float>(hipStream_t, const Grid&, const TileShape&, const CGBufs<float>&,
-                                             Coef);
-template hipError_t launch_cg_update<double>(hipStream_t, const Grid&, const CGBufs<double>&);
-template hipError_t launch_cg_update<float>(hipStream_t, const Grid&, const CGBufs<float>&);
+template hipError_t launch_cg_iter<double>(hipStream_t, const Grid&, const TileShape&, const CGBufs<double>&, Coef);
+template hipError_t launch_cg_iter<float>(hipStream_t, const Grid&, const TileShape&, const CGBufs<float>&, Coef);
 
 int residual_blocks(const Grid& g) { return (int)((g.N + 255) / 256); }
 
@@ -755,17 +799,18 @@ int add_blocks(const Grid& g)
     return (int)(nb > 4096 ? 4096 : (nb < 1 ? 1 : nb));
 }
 
-hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, int force)
+hipError_t launch_ru_add(hipStream_t s, const Grid& g, CGState* st, double* x64, float* d32, float* const* p32,
+                         int force)
 {
-    k_ru_add<<<(unsigned)add_blocks(g), 256, 0, s>>>(g.N / 4, st, x64, d32, force);
+    k_ru_add<<<(unsigned)add_blocks(g), 256, 0, s>>>(g.N / 4, st, x64, d32, p32[0], p32[1], force);
     return hipGetLastError();
 }
 
-hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, Coef c,
-                              const double* b, const double* x64, const float* dinv, float* r32, double* part3,
-                              CGState* st)
+hipError_t launch_ru_residual(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64, const float* ck32,
+                              Coef c, const double* b, const double* x64, float* const* z32, double* part3, CGState* st)
 {
-    k_ru_residual<<<(unsigned)residual_blocks(g), 256, 0, s>>>(g, code, ck64, c, b, x64, dinv, r32, part3, st);
+    k_ru_residual<<<(unsigned)residual_blocks(g), 256, 0, s>>>(g, code, ck64, ck32, c, b, x64, z32[0], z32[1], part3,
+                                                               st);
     return hipGetLastError();
 }
 
@@ -775,10 +820,10 @@ hipError_t launch_ru_begin(hipStream_t s, CGState* st)
     return hipGetLastError();
 }
 
-hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, double* part2, int nb2,
-                         int init, double rtol2, double delta2)
+hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nbres, int init, double rtol2,
+                         double delta2)
 {
-    k_ru_fin<<<1, 256, 0, s>>>(st, part3, nbres, part2, nb2, init, rtol2, delta2);
+    k_ru_fin<<<1, 256, 0, s>>>(st, part3, nbres, init, rtol2, delta2);
     return hipGetLastError();
 }
 
