@@ -89,6 +89,13 @@ typedef struct {
     double inner_rtol;      /* PB_MIXED: reliable-update factor: the FP32 recursive residual
                                may drop by this factor before an FP64 true-residual update */
     int32_t max_iter;       /* bound on launched CG iterations */
+    int32_t tile_planes;    /* planes per x-chunk of the iteration kernel's tiles: 0 = chosen
+                               from the grid (short chunks on small grids, so that a solve
+                               alone still spreads over the GPU; the serving loop takes 32
+                               instead, as its launches hold many problems), else a multiple
+                               of 4 in [4, 128].  It changes only the summation order of the
+                               reductions: a problem gives bit-identical results with the
+                               same value alone or in the serving loop. */
 } pb_params;
 
 /* Build the coefficient maps of a problem on the device (paper Sect. 2.1 and 3.1-3.2):

@@ -33,7 +33,7 @@ class PbParams(C.Structure):
         ("temperature_K", C.c_double), ("h", C.c_double), ("n", C.c_int32 * 3),
         ("origin", C.c_double * 3), ("bc", C.c_int32), ("bc_values", C.c_void_p),
         ("precision", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
-        ("max_iter", C.c_int32),
+        ("max_iter", C.c_int32), ("tile_planes", C.c_int32),
     ]
 
 
@@ -175,6 +175,7 @@ def make_params(grid) -> PbParams:
     p.precision = int(grid.precision)
     p.rtol, p.inner_rtol = float(grid.rtol), float(grid.inner_rtol)
     p.max_iter = int(grid.max_iter)
+    p.tile_planes = int(grid.tile_planes)
     return p
 
 

@@ -94,6 +94,8 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (p->precision == PB_MIXED && (!finite(p->inner_rtol) || p->inner_rtol <= 0 || p->inner_rtol >= 1))
         return fail(PB_EINVAL, "inner_rtol must be in (0, 1)");
     if (p->max_iter <= 0) return fail(PB_EINVAL, "max_iter must be > 0");
+    if (p->tile_planes != 0 && (p->tile_planes < 4 || p->tile_planes > 128 || p->tile_planes % 4))
+        return fail(PB_EINVAL, "tile_planes must be 0 or a multiple of 4 in [4, 128]");
     if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
     if (na > 0 && (!xyz || !rad || !chg)) return fail(PB_EINVAL, "atom arrays are NULL");
     for (int64_t a = 0; a < na; ++a) {
@@ -514,7 +516,7 @@ int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     g.ox = prm->origin[0];
     g.oy = prm->origin[1];
     g.oz = prm->origin[2];
-    pb->ts = make_tiles(g);
+    pb->ts = make_tiles(g, prm->tile_planes);
     double kd2 = 0;
     reduced_constants(prm->temperature_K, prm->ionic_strength_M, prm->eps_out, &pb->lB, &kd2);
     pb->kD = std::sqrt(kd2);

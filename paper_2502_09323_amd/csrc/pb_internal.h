@@ -124,7 +124,7 @@ hipError_t launch_export_phi(hipStream_t s, const Grid& g, const double* x, cons
                              double* out);
 
 // ---- solver kernels (pb_solve.hip) ------------------------------------------------------
-TileShape make_tiles(const Grid& g);
+TileShape make_tiles(const Grid& g, int planes);   // planes = 0: chosen from the grid
 
 template <typename T>
 struct CGBufs {

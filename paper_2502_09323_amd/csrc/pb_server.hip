@@ -32,6 +32,7 @@ using namespace pbk;
 namespace {
 
 constexpr int kChunkIters = 16;   // same chunk length as a solo mixed solve
+constexpr int kServerTilePlanes = 32;   // long x-chunks: a batched launch has blocks to spare
 
 struct Request {
     pb_params prm;
@@ -301,6 +302,7 @@ int admit(pb_server* s)
         if (s->budget && s->in_use + q.est_bytes > s->budget) break;  // wait for memory
         pb_params prm = q.prm;
         prm.bc_values = q.bc.empty() ? nullptr : q.bc.data();
+        if (prm.tile_planes == 0) prm.tile_planes = kServerTilePlanes;
         pb_problem* pb = nullptr;
         const int rc = pbi_build_begin(s->bctx, &prm, (int64_t)q.rad.size(), q.xyz.data(), q.rad.data(),
                                        q.chg.data(), &pb);

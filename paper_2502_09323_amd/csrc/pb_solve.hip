@@ -737,21 +737,20 @@ hipError_t launch_stream_copy(hipStream_t s, const void* a, void* b, size_t byte
     return hipGetLastError();
 }
 
-TileShape make_tiles(const Grid& g)
+TileShape make_tiles(const Grid& g, int planes)
 {
     TileShape t;
     t.njt = (g.ny - 2 + TY - 1) / TY;
     t.nkt = (g.nz - 2 + 63) / 64;
     const int tiles = t.njt * t.nkt;
-#ifdef PB_FORCE_LX
-    int lx = PB_FORCE_LX;
-#else
-    // chunk length along x: every chunk re-reads the planes next to it, so chunks stay long;
-    // they are shortened (down to 8 planes) while the grid would give fewer than 4096 tiles,
-    // so that the 256 CUs have several blocks each
-    int lx = 32;
-    while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 4096) lx >>= 1;
-#endif
+    int lx = planes;
+    if (lx <= 0) {
+        // chunk length along x: every chunk re-reads the planes next to it, so chunks stay
+        // long; they are shortened (down to 8 planes) while the grid would give fewer than
+        // 4096 tiles, so that the 256 CUs have several blocks each
+        lx = 32;
+        while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 4096) lx >>= 1;
+    }
     t.LX = lx;
     t.nxc = (g.nx - 2 + lx - 1) / lx;
     t.items = tiles * t.nxc;

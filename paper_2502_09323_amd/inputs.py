@@ -47,6 +47,7 @@ class GridSpec:
     bc: int = BC_DH
     rtol: float = 1e-10
     max_iter: int = 20000
+    tile_planes: int = 0      # planes per x-chunk of the GPU iteration tiles (0 = automatic)
     precision: int = FP64
     inner_rtol: float = 1e-4
     bc_values: np.ndarray | None = field(default=None, repr=False)  # BC_USER: full grid

@@ -1,9 +1,11 @@
 """Serving loop on the GPU: continuous batching must not change any result.
 
 Each request's energies and iteration count in the mix are compared bit for bit with the
-same request solved alone through pb_solve; admission honours the memory budget; requests
-are not admitted before their arrival time."""
+same request solved alone through pb_solve (with the tile layout the serving loop uses,
+32-plane x-chunks); admission honours the memory budget; requests are not admitted before
+their arrival time."""
 import time
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -63,7 +65,7 @@ def test_mix_equals_alone_bitwise(ctxs):
     for i, (mol, grid) in enumerate(reqs):
         r = served[i]
         assert r["code"] == 0
-        alone = B.solve(mol, grid, main)
+        alone = B.solve(mol, replace(grid, tile_planes=32), main)
         for k in ("e_pol", "e_ion", "e_coul", "q_pol_total", "area_total"):
             assert r[k] == alone[k], (i, k, r[k], alone[k])
         assert r["iters"] == alone["iters"] and r["outer_iters"] == alone["outer_iters"]
