@@ -76,8 +76,8 @@ typedef struct {
     double ionic_strength_M;/* 1:1 salt, mol/L (e.g. 0.145) */
     double temperature_K;   /* e.g. 298 */
     double h;               /* grid spacing, Angstrom */
-    int32_t n[3];           /* nodes per axis, each in [3, 4096]; n[0]*n[1]*(n[2] padded to
-                               a multiple of 8 after 7 leading pad nodes) < 2^29 */
+    int32_t n[3];           /* nodes per axis, each in [3, 4096]; n[0]*n[1]*(n[2] + 31
+                               pad nodes, rounded up to a multiple of 32) < 2^29 */
     double origin[3];       /* coordinates of node (0,0,0) */
     int32_t bc;             /* PB_BC_ZERO | PB_BC_DH | PB_BC_USER */
     const double* bc_values;/* PB_BC_USER: host array over the full grid; only box-face

@@ -83,7 +83,7 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     }
     {
         // the iteration kernel addresses FP64 vectors with 32-bit byte offsets
-        const int64_t S = ((int64_t)p->n[2] + Z0 + 7) / 8 * 8;
+        const int64_t S = row_stride(p->n[2]);
         if ((int64_t)p->n[0] * p->n[1] * S >= ((int64_t)1 << 29))
             return fail(PB_EINVAL, "grid of %d x %d x %d nodes exceeds 2^29 stored nodes", p->n[0], p->n[1], p->n[2]);
     }
@@ -510,7 +510,7 @@ int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     g.nx = prm->n[0];
     g.ny = prm->n[1];
     g.nz = prm->n[2];
-    g.S = ((g.nz + Z0) + 7) / 8 * 8;
+    g.S = (int)row_stride(g.nz);
     g.N = (int64_t)g.nx * g.ny * g.S;
     g.h = prm->h;
     g.ox = prm->origin[0];

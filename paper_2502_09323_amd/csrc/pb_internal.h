@@ -1,9 +1,10 @@
 // pb_internal.h -- device data layout and kernel launchers of libpb (gfx950).
 //
 // Node arrays live in a padded z-contiguous layout: node (i,j,k) is element
-// ((i*ny + j)*S + k + Z0) with Z0 = 7 and S a multiple of 8, so that the first interior
-// node of every z-row (k = 1) starts a 64-byte line for FP64 data.  Padding elements are
-// treated as Dirichlet nodes with value 0.
+// ((i*ny + j)*S + k + Z0) with Z0 = 31 and S a multiple of 32, so that the first interior
+// node of every z-row (k = 1) starts a 128-byte line for FP32 and FP64 data, and so does
+// every 32-node tile row after it.  Padding elements are treated as Dirichlet nodes with
+// value 0.
 //
 // Per node the solver keeps one 32-bit code instead of three edge coefficients:
 //   bit 0      solute (node strictly inside an atom ball)
@@ -26,7 +27,11 @@ constexpr uint32_t C_SOLUTE = 1u;
 constexpr uint32_t C_BOX = 2u;
 constexpr uint32_t C_CUTX = 4u;
 constexpr int C_SLOT_SHIFT = 5;
-constexpr int Z0 = 7;
+constexpr int Z0 = 31;
+constexpr int ZALIGN = 32;
+
+// z-row stride of a grid with nz nodes along z
+inline int64_t row_stride(int64_t nz) { return (nz + Z0 + ZALIGN - 1) / ZALIGN * ZALIGN; }
 
 struct Grid {
     int nx, ny, nz;   // nodes per axis
@@ -84,15 +89,13 @@ struct TileShape {     // tiling of the interior for the stencil kernel
     int items;         // nxc*njt*nkt
 };
 
-#ifndef PB_TILE_ROWS
-#define PB_TILE_ROWS 8
-#endif
 #ifndef PB_TILE_WAVES
 #define PB_TILE_WAVES 8
 #endif
-constexpr int TY = PB_TILE_ROWS;   // rows (y) per tile of the iteration kernel
-constexpr int NWV = PB_TILE_WAVES; // waves per block of the iteration kernel, TY/NWV rows each
-static_assert(TY % NWV == 0 && NWV >= 4 && TY <= 64, "tile shape");
+constexpr int ZW = 32;              // z-extent of a tile of the iteration kernel (lanes per row)
+constexpr int NWV = PB_TILE_WAVES;  // waves per block of the iteration kernel, two rows each
+constexpr int TY = 2 * NWV;         // y-extent of a tile
+static_assert(NWV >= 2 && TY <= 32, "tile shape");
 
 // ---- build kernels (pb_build.hip) -----------------------------------------------------
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,

@@ -154,7 +154,7 @@ int ensure_slot(pb_server* s, int k, int P)
 
 size_t estimate_bytes(const pb_params& p, int64_t na)
 {
-    const int64_t S = ((p.n[2] + Z0) + 7) / 8 * 8;
+    const int64_t S = row_stride(p.n[2]);
     const int64_t N = (int64_t)p.n[0] * p.n[1] * S;
     // node data of the mixed form (code, b, g, x64, seven FP32 vectors) + build scratch
     return (size_t)N * 60 + (size_t)na * 64 + ((size_t)1 << 20);

@@ -19,11 +19,11 @@
 // vectors of its neighbours.  The scalars never leave the device and all reductions run in
 // a fixed order, so a solve is run-to-run deterministic.
 //
-// The iteration kernel tiles the interior into 64 (z, one wave) x TY (y, NWV waves x TY/NWV
-// rows) columns and marches along x over a chunk of planes, carrying the x-neighbours in
-// registers and staging the current plane with its y/z halo in LDS.  Tiles are numbered
-// z-fastest and handed out so that each XCD gets one contiguous range of tiles, which keeps
-// the halo rows of neighbouring tiles in the same L2.
+// The iteration kernel tiles the interior into columns of ZW (z) x TY (y) nodes and marches
+// along x over a chunk of planes, carrying the x-neighbours in registers and staging the
+// current plane with its y/z halo in LDS.  Tiles are numbered z-fastest and handed out so
+// that each XCD gets one contiguous range of tiles, which keeps the halo rows of
+// neighbouring tiles in the same L2.
 #include "pb_internal.h"
 
 #include <cmath>
@@ -135,6 +135,9 @@ __device__ __forceinline__ T& at(T* base, uint32_t e)
 // tile computes D of its own nodes from the edge coefficients it has for q = A p, and forms
 // r = D z and q = D w there.
 //
+// A tile is ZW = 32 nodes along z (one 128-byte line of FP32 values: rows start on a line)
+// by TY = 2*NWV rows along y; each wave holds two rows, each lane one node of a plane.
+//
 // Software pipeline along x: the old vectors of plane i+3 with their halo, and x of plane
 // i+2, are loaded while plane i is computed, into register slots numbered by plane modulo 4;
 // the loop body is unrolled four times so that every slot keeps its registers and no load in
@@ -144,11 +147,10 @@ template <typename T>
 __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, const CGBufs<T>& B, const Coef& cf,
                                           const int bid)
 {
-    constexpr int RY = TY / NWV;
     __shared__ double sh[5 * NWV];
-    __shared__ T sp[2][TY + 2][66];   // p of plane i: rows j0-1..j0+TY, cols k0-1..k0+64
-    __shared__ T sky[2][TY + 1][64];  // K of the +y edge: rows j0-1..j0+TY-1, cols k0..k0+63
-    __shared__ T skz[2][TY][65];      // K of the +z edge: own rows, cols k0-1..k0+63
+    __shared__ T sp[2][TY + 2][ZW + 2];   // p of plane i: rows j0-1..j0+TY, cols k0-1..k0+ZW
+    __shared__ T sky[2][TY + 1][ZW];      // K of the +y edge: rows j0-1..j0+TY-1, cols k0..k0+ZW-1
+    __shared__ T skz[2][TY][ZW + 1];      // K of the +z edge: own rows, cols k0-1..k0+ZW-1
     const CGState* st = B.st;
     if (st->status != 0) return;
     const int nw = st->iter_count & 1, od = nw ^ 1;
@@ -163,10 +165,11 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
     const int t2 = item / ts.nkt;
     const int jt = t2 % ts.njt;
     const int xc = t2 / ts.njt;
-    const int k0 = 1 + kt * 64, j0 = 1 + jt * TY;
+    const int k0 = 1 + kt * ZW, j0 = 1 + jt * TY;
     const int ib = 1 + xc * ts.LX;
     const int ie = (ib + ts.LX < g.nx - 1) ? ib + ts.LX : g.nx - 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kl = lane & (ZW - 1), row = 2 * wv + (lane >> 5);
 
     const T* __restrict__ z_o = B.z[od];
     const T* __restrict__ w_o = B.w[od];
@@ -194,59 +197,53 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
     auto znew = [&](const Old<T>& v) { return v.z - aT * v.w; };
     auto pnew = [&](const Old<T>& v) { return znew(v) + bT * v.p; };
 
-    // own columns (z = k0 + lane, rows j0 + wv*RY + q) and this thread's halo point
-    const int k = k0 + lane;
-    const int kc = clampk(k);
-    uint32_t eo[RY];
-    bool valid[RY];
-#pragma unroll
-    for (int q = 0; q < RY; ++q) {
-        const int j = j0 + wv * RY + q;
-        valid[q] = j <= g.ny - 2 && k <= g.nz - 2;
-        eo[q] = (uint32_t)g.idx(0, clampj(j), kc);
+    // own node (z = k0 + kl, y = j0 + row) and this thread's halo point
+    const int k = k0 + kl, j = j0 + row;
+    const bool valid = j <= g.ny - 2 && k <= g.nz - 2;
+    const uint32_t eo = (uint32_t)g.idx(0, clampj(j), clampk(k));
+    // halo: wave 0 holds rows j0-1 (lanes 0-31; needs p and K+y) and j0+TY (lanes 32-63; p),
+    // wave 1 columns k0-1 (lanes 0..TY-1; p and K+z) and k0+ZW (lanes 32..32+TY-1; p); the
+    // other lanes have no halo point (they load a node of their own tile and never use it)
+    int hj = j0, hk = k0, hsel = 0;   // hsel: 1 row below, 2 row above, 3 column before, 4 column after
+    if (wv == 0) {
+        hsel = lane < 32 ? 1 : 2;
+        hj = lane < 32 ? j0 - 1 : j0 + TY;
+        hk = k0 + kl;
+    } else if (wv == 1 && kl < TY) {
+        hsel = lane < 32 ? 3 : 4;
+        hj = j0 + kl;
+        hk = lane < 32 ? k0 - 1 : k0 + ZW;
     }
-    // halo: wave 0 row j0-1 (needs p and K+y), wave 1 row j0+TY (p), wave 2 column k0-1
-    // (p and K+z), wave 3 column k0+64 (p); waves 2 and 3 use their first TY lanes, further
-    // waves have no halo point (they load a node of their own tile and never use it)
-    int hj, hk;
-    bool hact = true;
-    if (wv == 0) { hj = j0 - 1; hk = k0 + lane; }
-    else if (wv == 1) { hj = j0 + TY; hk = k0 + lane; }
-    else if (wv <= 3) { hact = lane < TY; hj = j0 + (lane < TY ? lane : TY - 1); hk = (wv == 2) ? k0 - 1 : k0 + 64; }
-    else { hact = false; hj = j0; hk = k0; }
     const uint32_t eh = (uint32_t)g.idx(0, clampj(hj), clampk(hk));
-    const int hax = wv == 0 ? 1 : 2;
+    const int hax = hsel == 1 ? 1 : 2;
 
-    Old<T> rb[4][RY];   // old vectors of own planes, slot (plane - ib) % 4
-    Old<T> hb[4];       // halo, same slots
-    T xb[4][RY];        // x of own planes, same slots
-    K3<T> kr[2][RY];    // coefficient-table reads of own planes, slot (plane - ib) % 2
-    T hr[2];            // same for the halo
-    T pm[RY], pc[RY], kxm[RY];   // p of planes i-1 and i, K of the -x edges of plane i
+    Old<T> rb[4];   // old vectors of the own node in planes, slot (plane - ib) % 4
+    Old<T> hb[4];   // halo, same slots
+    T xb[4];        // x of the own node, same slots
+    K3<T> kr[2];    // coefficient-table reads of the own node, slot (plane - ib) % 2
+    T hr[2];        // same for the halo
+    T pm, pc, kxm;  // p of planes i-1 and i, K of the -x edge of plane i
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // p.q, r.z, r.r, z.q, q.D^-1 q (as D z w, D w w)
 
     // prologue: plane ib-1 (p, K+x), planes ib..ib+2 and their halo, x of ib and ib+1
     {
         const uint32_t i1 = (uint32_t)(ib + 1 < ie ? ib + 1 : ie), i2 = (uint32_t)(ib + 2 < ie ? ib + 2 : ie);
         const uint32_t h1 = (uint32_t)(ib + 1 < ie ? ib + 1 : ie - 1), h2 = (uint32_t)(ib + 2 < ie ? ib + 2 : ie - 1);
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            const Old<T> a = load(eo[q] + (uint32_t)(ib - 1) * sx);
-            rb[0][q] = load(eo[q] + (uint32_t)ib * sx);
-            rb[1][q] = load(eo[q] + i1 * sx);
-            rb[2][q] = load(eo[q] + i2 * sx);
-            xb[0][q] = at(x, eo[q] + (uint32_t)ib * sx);
-            xb[1][q] = at(x, eo[q] + h1 * sx);
-            pm[q] = pnew(a);
-            kxm[q] = edgeK(a.c, 0, ck, kin, kout);
-            pc[q] = pnew(rb[0][q]);
-            kr[0][q].x = ck[ck_index(rb[0][q].c, 0)];
-            kr[0][q].y = ck[ck_index(rb[0][q].c, 1)];
-            kr[0][q].z = ck[ck_index(rb[0][q].c, 2)];
-        }
+        const Old<T> a = load(eo + (uint32_t)(ib - 1) * sx);
+        rb[0] = load(eo + (uint32_t)ib * sx);
+        rb[1] = load(eo + i1 * sx);
+        rb[2] = load(eo + i2 * sx);
+        xb[0] = at(x, eo + (uint32_t)ib * sx);
+        xb[1] = at(x, eo + h1 * sx);
         hb[0] = load(eh + (uint32_t)ib * sx);
         hb[1] = load(eh + h1 * sx);
         hb[2] = load(eh + h2 * sx);
+        pm = pnew(a);
+        kxm = edgeK(a.c, 0, ck, kin, kout);
+        pc = pnew(rb[0]);
+        kr[0].x = ck[ck_index(rb[0].c, 0)];
+        kr[0].y = ck[ck_index(rb[0].c, 1)];
+        kr[0].z = ck[ck_index(rb[0].c, 2)];
         hr[0] = ck[ck_index(hb[0].c, hax)];
     }
 
@@ -259,14 +256,10 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
         constexpr int S1 = (S0 + 1) & 3, S2 = (S0 + 2) & 3, S3 = (S0 + 3) & 3;
         constexpr int L = S0 & 1;
         // plane i+1 has arrived: its p, and its table reads
-        T px[RY];
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            px[q] = pnew(rb[S1][q]);
-            kr[L ^ 1][q].x = ck[ck_index(rb[S1][q].c, 0)];
-            kr[L ^ 1][q].y = ck[ck_index(rb[S1][q].c, 1)];
-            kr[L ^ 1][q].z = ck[ck_index(rb[S1][q].c, 2)];
-        }
+        const T px = pnew(rb[S1]);
+        kr[L ^ 1].x = ck[ck_index(rb[S1].c, 0)];
+        kr[L ^ 1].y = ck[ck_index(rb[S1].c, 1)];
+        kr[L ^ 1].z = ck[ck_index(rb[S1].c, 2)];
         hr[L ^ 1] = ck[ck_index(hb[S1].c, hax)];
         __builtin_amdgcn_sched_barrier(0);   // keep the issue order: table reads, then prefetch
         // prefetch: own plane i+3 (never past plane ie, the last one this chunk needs), its
@@ -275,80 +268,64 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
             const uint32_t i3 = (uint32_t)(i + 3 < ie ? i + 3 : ie);
             const uint32_t h3 = (uint32_t)(i + 3 < ie ? i + 3 : ie - 1);
             const uint32_t i2 = (uint32_t)(i + 2 < ie ? i + 2 : ie - 1);
-#pragma unroll
-            for (int q = 0; q < RY; ++q) {
-                rb[S3][q] = load(eo[q] + i3 * sx);
-                xb[S2][q] = at(x, eo[q] + i2 * sx);
-            }
+            rb[S3] = load(eo + i3 * sx);
+            xb[S2] = at(x, eo + i2 * sx);
             hb[S3] = load(eh + h3 * sx);
         }
         __builtin_amdgcn_sched_barrier(0);
 
         // stage plane i in LDS: p and the +y/+z edge coefficients
-        K3<T> kc3[RY];
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            const int row = wv * RY + q;
-            const uint32_t cc = rb[S0][q].c;
-            kc3[q].x = ck_blend(kr[L][q].x, cc, 0, kin, kout);
-            kc3[q].y = ck_blend(kr[L][q].y, cc, 1, kin, kout);
-            kc3[q].z = ck_blend(kr[L][q].z, cc, 2, kin, kout);
-            sp[L][1 + row][1 + lane] = pc[q];
-            sky[L][1 + row][lane] = kc3[q].y;
-            skz[L][row][1 + lane] = kc3[q].z;
-        }
+        const uint32_t cc = rb[S0].c;
+        const T Kxp = ck_blend(kr[L].x, cc, 0, kin, kout);
+        sp[L][1 + row][1 + kl] = pc;
+        sky[L][1 + row][kl] = ck_blend(kr[L].y, cc, 1, kin, kout);
+        skz[L][row][1 + kl] = ck_blend(kr[L].z, cc, 2, kin, kout);
         {
             const T hv = pnew(hb[S0]);
             const T hK = ck_blend(hr[L], hb[S0].c, hax, kin, kout);
-            if (wv == 0) {
-                sp[L][0][1 + lane] = hv;
-                sky[L][0][lane] = hK;
-            } else if (wv == 1) {
-                sp[L][TY + 1][1 + lane] = hv;
-            } else if (hact) {   // waves 2 and 3
-                if (wv == 2) {
-                    sp[L][1 + lane][0] = hv;
-                    skz[L][lane][0] = hK;
-                } else {
-                    sp[L][1 + lane][65] = hv;
-                }
+            if (hsel == 1) {
+                sp[L][0][1 + kl] = hv;
+                sky[L][0][kl] = hK;
+            } else if (hsel == 2) {
+                sp[L][TY + 1][1 + kl] = hv;
+            } else if (hsel == 3) {
+                sp[L][1 + kl][0] = hv;
+                skz[L][kl][0] = hK;
+            } else if (hsel == 4) {
+                sp[L][1 + kl][ZW + 1] = hv;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < RY; ++q) {
-            const int row = wv * RY + q;
-            const Old<T>& o = rb[S0][q];
-            const T Kym = sky[L][row][lane], Kyp = sky[L][1 + row][lane];
-            const T Kzm = skz[L][row][lane], Kzp = skz[L][row][1 + lane];
-            const T Kxp = kc3[q].x;
-            const T D = diag_sum(kxm[q], Kxp, Kym, Kyp, Kzm, Kzp, (o.c & C_SOLUTE) ? (T)0 : mass);
-            const T p0 = pc[q];
-            const T nbs = kxm[q] * pm[q] + Kxp * px[q] + Kym * sp[L][row][1 + lane] +
-                          Kyp * sp[L][row + 2][1 + lane] + Kzm * sp[L][1 + row][lane] + Kzp * sp[L][1 + row][2 + lane];
-            const T qv = D * p0 - nbs;
-            const T zv = znew(o);
-            const T wv_ = qv / D;
-            const T xv = xb[S0][q] + aT * o.p;
-            // a lane outside the interior was clamped onto a box node, whose vectors stay
-            // 0: it stores zeros there, so the stores need no branch
-            const bool ok = valid[q] && i < ie;
-            const uint32_t e = eo[q] + (uint32_t)(i < ie ? i : g.nx - 1) * sx;
-            at(z_n, e) = ok ? zv : (T)0;
-            at(w_n, e) = ok ? wv_ : (T)0;
-            at(p_n, e) = ok ? p0 : (T)0;
-            at(x, e) = ok ? xv : (T)0;
-            const double dD = ok ? (double)D : 0.0;
-            const double dz = (double)zv, dw = (double)wv_, dq = (double)qv, dzD = dD * dz, dwD = dD * dw;
-            acc[0] += ok ? (double)p0 * dq : 0.0;
-            acc[1] += dzD * dz;
-            acc[2] += dzD * dzD;
-            acc[3] += dzD * dw;
-            acc[4] += dwD * dw;
-            kxm[q] = Kxp;
-            pm[q] = p0;
-            pc[q] = px[q];
-        }
+        const Old<T>& o = rb[S0];
+        const T Kym = sky[L][row][kl], Kyp = sky[L][1 + row][kl];
+        const T Kzm = skz[L][row][kl], Kzp = skz[L][row][1 + kl];
+        const T D = diag_sum(kxm, Kxp, Kym, Kyp, Kzm, Kzp, (cc & C_SOLUTE) ? (T)0 : mass);
+        const T p0 = pc;
+        const T nbs = kxm * pm + Kxp * px + Kym * sp[L][row][1 + kl] + Kyp * sp[L][row + 2][1 + kl] +
+                      Kzm * sp[L][1 + row][kl] + Kzp * sp[L][1 + row][2 + kl];
+        const T qv = D * p0 - nbs;
+        const T zv = znew(o);
+        const T wq = qv / D;
+        const T xv = xb[S0] + aT * o.p;
+        // a lane outside the interior was clamped onto a box node, and a plane past the
+        // chunk's last one stores onto the box face x = nx-1: the vectors there stay 0, so
+        // the stores need no branch
+        const bool ok = valid && i < ie;
+        const uint32_t e = eo + (uint32_t)(i < ie ? i : g.nx - 1) * sx;
+        at(z_n, e) = ok ? zv : (T)0;
+        at(w_n, e) = ok ? wq : (T)0;
+        at(p_n, e) = ok ? p0 : (T)0;
+        at(x, e) = ok ? xv : (T)0;
+        const double dD = ok ? (double)D : 0.0;
+        const double dz = (double)zv, dw = (double)wq, dq = (double)qv, dzD = dD * dz, dwD = dD * dw;
+        acc[0] += ok ? (double)p0 * dq : 0.0;
+        acc[1] += dzD * dz;
+        acc[2] += dzD * dzD;
+        acc[3] += dzD * dw;
+        acc[4] += dwD * dw;
+        kxm = Kxp;
+        pm = p0;
+        pc = px;
     };
 
     // Whole groups of four planes, so the loop body has no branch: a plane past the chunk's
@@ -741,7 +718,7 @@ TileShape make_tiles(const Grid& g, int planes)
 {
     TileShape t;
     t.njt = (g.ny - 2 + TY - 1) / TY;
-    t.nkt = (g.nz - 2 + 63) / 64;
+    t.nkt = (g.nz - 2 + ZW - 1) / ZW;
     const int tiles = t.njt * t.nkt;
     int lx = planes;
     if (lx <= 0) {
