@@ -724,9 +724,9 @@ TileShape make_tiles(const Grid& g, int planes)
     if (lx <= 0) {
         // chunk length along x: every chunk re-reads the planes next to it, so chunks stay
         // long; they are shortened (down to 8 planes) while the grid would give fewer than
-        // 4096 tiles, so that the 256 CUs have several blocks each
+        // 2048 tiles, so that the 256 CUs have several 8-wave blocks each
         lx = 32;
-        while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 4096) lx >>= 1;
+        while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 2048) lx >>= 1;
     }
     t.LX = lx;
     t.nxc = (g.nx - 2 + lx - 1) / lx;
