@@ -792,6 +792,73 @@ double orc_coulomb(int64_t na, const double* xyz, const double* q, double eps_in
     return s;
 }
 
+/* ------------------------------------------------------------------------- */
+/* local refinement: which coarse cells are split into 2x2x2 fine cells        */
+/* ------------------------------------------------------------------------- */
+
+/* Coarse cell c (index per axis in [0, n-2]) covers the closed box
+ * [origin + H c, origin + H (c+1)].  It is flagged when a surface crossing point lies
+ * within distance delta of that box; flags are then rounded up to aligned bricks of
+ * brick^3 cells (a brick is refined as a whole when any of its cells is flagged).
+ * refined[] is indexed ((ci*(n1-1) + cj)*(n2-1) + ck).  Returns the number of refined
+ * cells. */
+int64_t orc_refine_cells(const int32_t* n, const double* origin, double H, double delta,
+                         int32_t brick, int64_t np, const double* rp, uint8_t* refined)
+{
+    const int64_t nc[3] = {n[0] - 1, n[1] - 1, n[2] - 1};
+    const int64_t ncell = nc[0] * nc[1] * nc[2];
+    uint8_t* flag = (uint8_t*)calloc((size_t)ncell, 1);
+    if (!flag) return -1;
+    const double d2max = delta * delta;
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            double a = floor((rp[3 * p + d] - delta - origin[d]) / H) - 1;
+            double b = floor((rp[3 * p + d] + delta - origin[d]) / H) + 1;
+            lo[d] = a < 0 ? 0 : (int64_t)a;
+            hi[d] = b > nc[d] - 1 ? nc[d] - 1 : (int64_t)b;
+        }
+        for (int64_t i = lo[0]; i <= hi[0]; ++i)
+            for (int64_t j = lo[1]; j <= hi[1]; ++j)
+                for (int64_t k = lo[2]; k <= hi[2]; ++k) {
+                    const int64_t c[3] = {i, j, k};
+                    double dd[3];
+                    for (int d = 0; d < 3; ++d) {
+                        double blo = origin[d] + H * (double)c[d];
+                        double bhi = origin[d] + H * (double)(c[d] + 1);
+                        double x = rp[3 * p + d];
+                        double e = blo - x > x - bhi ? blo - x : x - bhi;
+                        dd[d] = e > 0.0 ? e : 0.0;
+                    }
+                    double d2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+                    if (d2 <= d2max) flag[(i * nc[1] + j) * nc[2] + k] = 1;
+                }
+    }
+    /* bricks */
+    const int64_t nb[3] = {(nc[0] + brick - 1) / brick, (nc[1] + brick - 1) / brick, (nc[2] + brick - 1) / brick};
+    uint8_t* bf = (uint8_t*)calloc((size_t)(nb[0] * nb[1] * nb[2]), 1);
+    if (!bf) {
+        free(flag);
+        return -1;
+    }
+    for (int64_t i = 0; i < nc[0]; ++i)
+        for (int64_t j = 0; j < nc[1]; ++j)
+            for (int64_t k = 0; k < nc[2]; ++k)
+                if (flag[(i * nc[1] + j) * nc[2] + k])
+                    bf[((i / brick) * nb[1] + j / brick) * nb[2] + k / brick] = 1;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < nc[0]; ++i)
+        for (int64_t j = 0; j < nc[1]; ++j)
+            for (int64_t k = 0; k < nc[2]; ++k) {
+                uint8_t r = bf[((i / brick) * nb[1] + j / brick) * nb[2] + k / brick];
+                refined[(i * nc[1] + j) * nc[2] + k] = r;
+                cnt += r;
+            }
+    free(flag);
+    free(bf);
+    return cnt;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
