@@ -96,6 +96,19 @@ typedef struct {
                                of 4 in [4, 128].  It changes only the summation order of the
                                reductions: a problem gives bit-identical results with the
                                same value alone or in the serving loop. */
+    int32_t refine;         /* 0: uniform grid.  1: one level of 2:1 local refinement (the
+                               paper's octree restricted to one level, Sect. 3): a coarse cell
+                               of size h is split into 8 cells of size h/2 when a crossing
+                               point of the surface with the h/2 lattice lies within
+                               refine_shell_A of it (distance to the closed cell), rounded up
+                               to aligned bricks of refine_brick^3 coarse cells.  Nodes of the
+                               fine cells that lie on a face or edge of an unrefined cell are
+                               hanging: they take the mean of the 2 or 4 coarse nodes of that
+                               edge or face (P), and the operator is P^T K P over cell-wise
+                               assembled K.  Needs PB_FP64, at least one atom, and refined
+                               cells away from the box faces (PB_EINVAL otherwise). */
+    double refine_shell_A;  /* refine: distance in Angstrom (e.g. 3.0) */
+    int32_t refine_brick;   /* refine: brick edge in coarse cells, 1..64 (e.g. 4) */
 } pb_params;
 
 /* Build the coefficient maps of a problem on the device (paper Sect. 2.1 and 3.1-3.2):
@@ -156,6 +169,28 @@ int pb_copy_potential(const pb_problem* pb, double* host_phi);
 
 /* Release all device memory of a problem (waits for its stream). */
 void pb_problem_free(pb_problem* pb);
+
+/* Locally refined problems (refine = 1).  The fine cells live on a sub-lattice of the h/2
+ * lattice: fine node (a,b,c) of it is node (a,b,c) + fine_offset of the lattice with the
+ * problem's origin and spacing h/2 (coarse node (i,j,k) is lattice node (2i,2j,2k)). */
+typedef struct {
+    int32_t fine_n[3];        /* nodes of the fine sub-lattice per axis */
+    int32_t fine_offset[3];
+    int64_t refined_cells;    /* coarse cells split into fine cells */
+    int64_t hanging_nodes;
+    int64_t unknowns_coarse;  /* unknowns on the coarse grid and on the fine sub-lattice */
+    int64_t unknowns_fine;
+} pb_refine_stats;
+
+/* Fills *out (all zero for a uniform problem). */
+int pb_refine_info(const pb_problem* pb, pb_refine_stats* out);
+/* Refinement flags of the coarse cells: host uint8[(n0-1)*(n1-1)*(n2-1)], cell (i,j,k) at
+ * ((i*(n1-1) + j)*(n2-1) + k).  PB_EINVAL for a uniform problem. */
+int pb_copy_refined_cells(const pb_problem* pb, uint8_t* host);
+/* Potential (kT/e) on the fine sub-lattice after pb_solve, host doubles over fine_n in the
+ * order ((a*fine_n[1] + b)*fine_n[2] + c); nodes of no fine cell hold 0.  pb_copy_potential
+ * returns the coarse grid.  PB_EINVAL for a uniform problem. */
+int pb_copy_fine_potential(const pb_problem* pb, double* host_phi);
 
 /* --- inspection (used by the parity tests) ------------------------------------- */
 

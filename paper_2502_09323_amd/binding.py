@@ -23,7 +23,7 @@ EXPORTED = [
     "pb_copy_potential", "pb_problem_free", "pb_copy_coeffs", "pb_num_cut", "pb_copy_cut",
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
-    "pb_server_times", "pb_server_profile",
+    "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
 ]
 
 
@@ -34,7 +34,13 @@ class PbParams(C.Structure):
         ("origin", C.c_double * 3), ("bc", C.c_int32), ("bc_values", C.c_void_p),
         ("precision", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
         ("max_iter", C.c_int32), ("tile_planes", C.c_int32),
+        ("refine", C.c_int32), ("refine_shell_A", C.c_double), ("refine_brick", C.c_int32),
     ]
+
+
+class PbRefineStats(C.Structure):
+    _fields_ = [("fine_n", C.c_int32 * 3), ("fine_offset", C.c_int32 * 3), ("refined_cells", C.c_int64),
+                ("hanging_nodes", C.c_int64), ("unknowns_coarse", C.c_int64), ("unknowns_fine", C.c_int64)]
 
 
 class PbSolveStats(C.Structure):
@@ -66,6 +72,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libpb HIP library not found at {path}; run __graft_entry__.build()")
+    # PyTorch brings up the HIP runtime first (its allocator and streams are the ones the
+    # library is given), then the library is loaded into the same process
+    import torch
+
+    torch.cuda.is_available()
     L = C.CDLL(path)
     P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.pb_ctx_create.argtypes = [C.c_int, P, ALLOC_FN, FREE_FN, P, C.c_size_t, C.POINTER(P)]
@@ -98,6 +109,9 @@ def load(path: str = LIB_PATH):
     L.pb_server_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
     L.pb_server_destroy.argtypes = [P]
     L.pb_server_destroy.restype = None
+    L.pb_refine_info.argtypes = [P, C.POINTER(PbRefineStats)]
+    L.pb_copy_refined_cells.argtypes = [P, P]
+    L.pb_copy_fine_potential.argtypes = [P, P]
     _lib = L
     return L
 
@@ -176,6 +190,9 @@ def make_params(grid) -> PbParams:
     p.rtol, p.inner_rtol = float(grid.rtol), float(grid.inner_rtol)
     p.max_iter = int(grid.max_iter)
     p.tile_planes = int(grid.tile_planes)
+    p.refine = int(grid.refine)
+    p.refine_shell_A = float(grid.refine_shell)
+    p.refine_brick = int(grid.refine_brick)
     return p
 
 
@@ -227,6 +244,30 @@ class Problem:
     def potential(self) -> np.ndarray:
         phi = np.zeros(self.shape)
         rc = _lib.pb_copy_potential(self.h, _ptr(phi))
+        if rc != PB_OK:
+            raise _err(rc)
+        return phi
+
+    def refine_info(self) -> dict:
+        st = PbRefineStats()
+        rc = _lib.pb_refine_info(self.h, C.byref(st))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(fine_n=tuple(st.fine_n), fine_offset=tuple(st.fine_offset), refined_cells=st.refined_cells,
+                    hanging_nodes=st.hanging_nodes, unknowns_coarse=st.unknowns_coarse,
+                    unknowns_fine=st.unknowns_fine)
+
+    def refined_cells(self) -> np.ndarray:
+        out = np.zeros(tuple(int(v) - 1 for v in self.shape), dtype=np.uint8)
+        rc = _lib.pb_copy_refined_cells(self.h, _ptr(out))
+        if rc != PB_OK:
+            raise _err(rc)
+        return out
+
+    def fine_potential(self) -> np.ndarray:
+        info = self.refine_info()
+        phi = np.zeros(info["fine_n"])
+        rc = _lib.pb_copy_fine_potential(self.h, _ptr(phi))
         if rc != PB_OK:
             raise _err(rc)
         return phi

@@ -96,6 +96,13 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (p->max_iter <= 0) return fail(PB_EINVAL, "max_iter must be > 0");
     if (p->tile_planes != 0 && (p->tile_planes < 4 || p->tile_planes > 128 || p->tile_planes % 4))
         return fail(PB_EINVAL, "tile_planes must be 0 or a multiple of 4 in [4, 128]");
+    if (p->refine != 0 && p->refine != 1) return fail(PB_EINVAL, "refine must be 0 or 1");
+    if (p->refine) {
+        if (!finite(p->refine_shell_A) || p->refine_shell_A < 0) return fail(PB_EINVAL, "refine_shell_A must be >= 0");
+        if (p->refine_brick < 1 || p->refine_brick > 64) return fail(PB_EINVAL, "refine_brick must be in [1, 64]");
+        if (p->precision != PB_FP64) return fail(PB_EINVAL, "a refined problem is solved in FP64");
+        if (na <= 0) return fail(PB_EINVAL, "refinement needs atoms");
+    }
     if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
     if (na > 0 && (!xyz || !rad || !chg)) return fail(PB_EINVAL, "atom arrays are NULL");
     for (int64_t a = 0; a < na; ++a) {
@@ -474,6 +481,11 @@ void pbi_problem_destroy(pb_problem* pb, bool sync)
     (void)hipSetDevice(pb->ctx->device);
     if (sync) (void)hipStreamSynchronize(pb->ctx->stream);
     release_tmp(pb);
+    if (pb->ref) {
+        pbi_problem_destroy(pb->ref->fine, false);
+        delete pb->ref;
+        pb->ref = nullptr;
+    }
     if (pb->hout) (void)hipHostFree(pb->hout);
     if (pb->ev) (void)hipEventDestroy(pb->ev);
     pb->mem.release();
@@ -488,12 +500,38 @@ int pbi_event_done(pb_problem* pb)
     return fail(PB_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
 }
 
+namespace {
+int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                const double* chg, const int* off, pb_problem** out);
+}
+
 int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
                     const double* chg, pb_problem** out)
 {
+    return build_begin(ctx, prm, na, xyz, rad, chg, nullptr, out);
+}
+
+int pbi_build_begin_sub(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                        const double* chg, const int* off, pb_problem** out)
+{
+    return build_begin(ctx, prm, na, xyz, rad, chg, off, out);
+}
+
+namespace {
+int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                const double* chg, const int* off, pb_problem** out)
+{
     if (!ctx || !out) return fail(PB_EINVAL, "ctx/out is NULL");
     *out = nullptr;
-    int rc = validate(prm, na, xyz, rad, chg);
+    int rc;
+    if (off) {
+        // a sub-lattice: the atoms must lie inside it, whose first node sits at origin + h*off
+        pb_params vp = *prm;
+        for (int d = 0; d < 3; ++d) vp.origin[d] = prm->origin[d] + prm->h * (double)off[d];
+        rc = validate(&vp, na, xyz, rad, chg);
+    } else {
+        rc = validate(prm, na, xyz, rad, chg);
+    }
     if (rc) return rc;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
@@ -516,6 +554,8 @@ int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     g.ox = prm->origin[0];
     g.oy = prm->origin[1];
     g.oz = prm->origin[2];
+    if (off)
+        for (int d = 0; d < 3; ++d) g.off[d] = off[d];
     pb->ts = make_tiles(g, prm->tile_planes);
     double kd2 = 0;
     reduced_constants(prm->temperature_K, prm->ionic_strength_M, prm->eps_out, &pb->lB, &kd2);
@@ -624,6 +664,7 @@ int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
     *out = pb;
     return PB_OK;
 }
+}  // namespace
 
 int pbi_build_continue(pb_problem* pb)
 {
@@ -721,6 +762,10 @@ int pb_build_coeffs(pb_ctx* ctx, const pb_params* prm, int64_t na, const double*
         return rc;
     }
     pbi_build_end(pb);
+    if (prm->refine && (rc = pbi_refine_build(pb, xyz, rad, chg))) {
+        pbi_problem_destroy(pb, true);
+        return rc;
+    }
     *out = pb;
     return PB_OK;
 }
@@ -738,9 +783,19 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     pb->prof_n = 0;
     int rc = PB_OK;
     const pb_params& P = pb->prm;
-    if (P.precision == PB_FP64 && (rc = ensure_cg64(pb))) return rc;
     int status = PB_OK;
     CGState st;
+    if (pb->ref) {
+        if ((rc = pbi_refine_solve(pb, &st))) return rc;
+        stats->iters = st.status == 1 ? st.iters : st.iter_count;
+        stats->relres = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
+        status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
+        stats->status = status;
+        stats->t_solve_s = now_s() - t0;
+        pb->solved = pb->ref->fine->solved = status == PB_OK || status == PB_ENOCONV;
+        return status;
+    }
+    if (P.precision == PB_FP64 && (rc = ensure_cg64(pb))) return rc;
     if (P.precision == PB_FP64) {
         CGBufs<double> B = bufs<double>(pb);
         HIPCHK(launch_cg_init<double>(s, pb->g, B, pb->cf, pb->rhs, nullptr));
@@ -781,6 +836,7 @@ int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac)
 {
     if (!pb || !out) return fail(PB_EINVAL, "NULL argument");
     if (!pb->solved) return fail(PB_EINVAL, "pb_energy before a successful pb_solve");
+    if (pb->ref) pb = pb->ref->fine;   // the cut edges all lie on the fine sub-lattice
     HIPCHK(hipSetDevice(pb->ctx->device));
     const double t0 = now_s();
     int rc = pbi_energy_begin(pb, 0);
@@ -890,6 +946,7 @@ int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, d
 int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms)
 {
     if (!pb || !avg_ms || reps <= 0) return fail(PB_EINVAL, "bad argument");
+    if (pb->ref) return fail(PB_EINVAL, "pb_time_stencil times the uniform-grid iteration kernel");
     HIPCHK(hipSetDevice(pb->ctx->device));
     hipStream_t s = pb->ctx->stream;
     int rc = fp32 ? ensure_cg32(pb) : ensure_cg64(pb);
@@ -960,5 +1017,42 @@ int pb_stream_copy(pb_ctx* ctx, size_t bytes, int32_t reps, double* gbps)
 size_t pb_problem_bytes(const pb_problem* pb) { return pb ? pb->mem.bytes : 0; }
 
 void pb_problem_free(pb_problem* pb) { pbi_problem_destroy(pb, true); }
+
+int pb_refine_info(const pb_problem* pb, pb_refine_stats* out)
+{
+    if (!pb || !out) return fail(PB_EINVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    if (!pb->ref) return PB_OK;
+    const RefineData* R = pb->ref;
+    const Grid& gf = R->fine->g;
+    out->fine_n[0] = gf.nx;
+    out->fine_n[1] = gf.ny;
+    out->fine_n[2] = gf.nz;
+    for (int d = 0; d < 3; ++d) out->fine_offset[d] = gf.off[d];
+    out->refined_cells = R->n_refined;
+    out->hanging_nodes = R->nhang;
+    out->unknowns_coarse = R->nunk_c;
+    out->unknowns_fine = R->nunk_f;
+    return PB_OK;
+}
+
+int pb_copy_refined_cells(const pb_problem* pb, uint8_t* host)
+{
+    if (!pb || !host) return fail(PB_EINVAL, "NULL argument");
+    if (!pb->ref) return fail(PB_EINVAL, "not a refined problem");
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    const RefineData* R = pb->ref;
+    const size_t n = (size_t)R->nc[0] * R->nc[1] * R->nc[2];
+    HIPCHK(hipMemcpyAsync(host, R->cells, n, hipMemcpyDeviceToHost, pb->ctx->stream));
+    HIPCHK(hipStreamSynchronize(pb->ctx->stream));
+    return PB_OK;
+}
+
+int pb_copy_fine_potential(const pb_problem* pb, double* host_phi)
+{
+    if (!pb || !host_phi) return fail(PB_EINVAL, "NULL argument");
+    if (!pb->ref) return fail(PB_EINVAL, "not a refined problem");
+    return pb_copy_potential(pb->ref->fine, host_phi);
+}
 
 }  // extern "C"

@@ -37,7 +37,7 @@ __device__ __forceinline__ double node_x(const Grid& g, int ax, int i)
 {
 #pragma clang fp contract(off)
     double o = ax == 0 ? g.ox : ax == 1 ? g.oy : g.oz;
-    return o + g.h * (double)i;
+    return o + g.h * (double)(i + g.off[ax]);
 }
 
 // range of bins to visit around point p (clamped); false when no atom can be within bs
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, doubl
                         double w = 1.0;
                         bool corner = true;
                         for (int d = 0; d < 3; ++d) {
-                            double f = (a[d] - org[d]) / g.h;
+                            double f = (a[d] - org[d]) / g.h - (double)g.off[d];
                             double fl = floor(f);
                             if (fl < 0) fl = 0;
                             if (fl > nn[d] - 2) fl = nn[d] - 2;

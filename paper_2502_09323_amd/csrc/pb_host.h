@@ -68,6 +68,34 @@ struct BuildTmp {
     double* full = nullptr;   // device copy of user boundary values
 };
 
+struct pb_problem;
+
+// one level of 2:1 refinement: the fine sub-lattice problem and the composite operator
+struct RefineData {
+    pb_problem* fine = nullptr;   // fine sub-lattice: geometry, cut list, energy read-back
+    int nc[3] = {0, 0, 0};        // coarse cells per axis
+    int brick = 4;
+    double delta = 3.0;
+    uint8_t* cells = nullptr;     // refinement flags of the coarse cells
+    int64_t n_refined = 0;
+    double* Kc = nullptr;         // coarse grid: K of the +x, +y, +z edges, lumped term [4][Nc]
+    double* Kf = nullptr;         // fine sub-lattice, the same [4][Nf]
+    uint8_t* rolec = nullptr;     // 1: coarse unknown
+    uint8_t* rolef = nullptr;     // 1: fine unknown, 2: coincides with a coarse unknown, 3: hanging
+    int64_t ng = 0;               // derived fine nodes (roles 2, 3)
+    int64_t* gfine = nullptr;     // their fine element index
+    int64_t* gpar = nullptr;      // [4*ng] coarse parents (unused slots repeat the first)
+    int32_t* gnp = nullptr;       // parent counts 1, 2 or 4
+    int64_t nr = 0;               // coarse nodes receiving rows of derived fine nodes
+    int64_t *rnode = nullptr, *rptr = nullptr, *rsrc = nullptr;
+    double* rw = nullptr;
+    double *bc = nullptr, *rc = nullptr, *zc = nullptr, *pc = nullptr, *qc = nullptr, *dc = nullptr;
+    double *bf = nullptr, *rf = nullptr, *zf = nullptr, *pf = nullptr, *qf = nullptr, *df = nullptr;
+    double* part = nullptr;
+    int nbc = 0, nbf = 0;
+    int64_t nunk_c = 0, nunk_f = 0, nhang = 0;
+};
+
 struct pb_problem {
     pb_ctx* ctx;
     pb_params prm;
@@ -106,6 +134,7 @@ struct pb_problem {
     int nb = 0, nbres = 0;
     bool solved = false;
     BuildTmp* bt = nullptr;      // set while a build is in progress
+    RefineData* ref = nullptr;   // set for a locally refined problem
     hipEvent_t ev = nullptr;     // marks the end of the last asynchronous phase
     double* hout = nullptr;      // pinned: energy sums and the final CG state
     double* e_tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // energy temporaries
@@ -121,6 +150,10 @@ struct pb_problem {
 int pbi_build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
                     const double* chg, pb_problem** out);
 int pbi_build_continue(pb_problem* pb);
+// the same for a sub-lattice whose node (i,j,k) is node (i,j,k) + off of the lattice given by
+// prm's origin and spacing (atoms need only lie inside the sub-lattice)
+int pbi_build_begin_sub(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
+                        const double* chg, const int* off, pb_problem** out);
 void pbi_build_end(pb_problem* pb);
 int pbi_event_done(pb_problem* pb);
 void pbi_problem_destroy(pb_problem* pb, bool sync);   // sync=false: its event has completed
@@ -130,3 +163,7 @@ int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* st);
 // mixed-form solve split in steps for the serving loop (all work on the problem's stream)
 int pbi_mixed_begin(pb_problem* pb);                              // buffers + first update
 pbk::ProbDev<float> pbi_probdev(pb_problem* pb);
+
+// locally refined problems (pb_refine.hip)
+int pbi_refine_build(pb_problem* coarse, const double* xyz, const double* rad, const double* chg);
+int pbi_refine_solve(pb_problem* pb, pbk::CGState* out);

@@ -38,6 +38,8 @@ struct Grid {
     int S;            // z-row stride in elements
     int64_t N;        // storage elements nx*ny*S
     double h, ox, oy, oz;
+    int off[3] = {0, 0, 0};   // node (i,j,k) sits at origin + h*(i + off[0], ...): a sub-lattice
+                              // of a lattice with the same origin and spacing
     __host__ __device__ int64_t idx(int i, int j, int k) const
     {
         return ((int64_t)i * ny + j) * S + k + Z0;

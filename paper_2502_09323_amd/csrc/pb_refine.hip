@@ -1,0 +1,829 @@
+// pb_refine.hip -- one level of 2:1 local refinement with hanging nodes.
+//
+// The paper computes on a Cartesian octree with hierarchical refinement and handles its
+// non-conforming (hanging) nodes as in its references (Sect. 3, before Sect. 3.1); the
+// condensed operator of Sect. 3.1 is assembled cell by cell, every cell of size s adding
+// (s/4) eps_e per edge and (s^3/8) kbar^2 per vertex.  This file builds and solves that
+// operator for coarse cells of size H, some of which are split into 2x2x2 fine cells of size
+// h = H/2:
+//
+//   refinement  a coarse cell is split when a crossing point of the surface with the fine
+//               lattice lies within delta of it; the flags are rounded up to aligned bricks
+//   grids       the coarse grid (all coarse nodes) and a fine sub-lattice covering the
+//               refined bricks, each with explicit per-node coefficients: K of the +x, +y,
+//               +z edges (the number of incident cells of that grid times s/4 eps_e) and the
+//               lumped ionic term (incident cells times s^3/8 kbar^2)
+//   unknowns    coarse nodes with an unrefined incident cell; fine nodes with a refined
+//               incident cell, except those that coincide with a coarse unknown and the
+//               hanging nodes (not coarse nodes, on the boundary of an unrefined coarse cell),
+//               which take the mean of the 2 or 4 coarse nodes of the coarse edge or face
+//               they lie on
+//   operator    A = P^T K P: fill the derived fine values from the coarse ones (P), apply
+//               each grid's cell contributions, and add the rows of the derived fine nodes
+//               back to their coarse nodes (P^T)
+//
+// The solve is Jacobi-preconditioned CG over the unknowns of both grids (the diagonal of K
+// at each unknown), with device-resident scalars and fixed-order reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pb_host.h"
+#include "pb_internal.h"
+
+using namespace pbk;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+#define RCHK(expr)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return pbi_fail(PB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__device__ __forceinline__ void decode(const Grid& g, int64_t e, int& i, int& j, int& k)
+{
+    const int64_t row = e / g.S;
+    k = (int)(e - row * g.S) - Z0;
+    j = (int)(row % g.ny);
+    i = (int)(row / g.ny);
+}
+
+struct Cells {             // refinement flags of the coarse cells
+    const uint8_t* f;
+    int nc[3];
+    __device__ bool refined(int i, int j, int k) const
+    {
+        return f[((int64_t)i * nc[1] + j) * nc[2] + k] != 0;
+    }
+    __device__ bool valid(int i, int j, int k) const
+    {
+        return i >= 0 && j >= 0 && k >= 0 && i < nc[0] && j < nc[1] && k < nc[2];
+    }
+};
+
+// ---- refinement rule ---------------------------------------------------------------------
+
+// every coarse cell within delta of a crossing point is flagged (all writers store 1)
+__global__ void __launch_bounds__(256) k_mark(Grid gc, int64_t ncut, const double* __restrict__ rp, double delta,
+                                              uint8_t* flag, int nc0, int nc1, int nc2)
+{
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= ncut) return;
+    const double org[3] = {gc.ox, gc.oy, gc.oz};
+    const int nc[3] = {nc0, nc1, nc2};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        const double a = floor((rp[3 * p + d] - delta - org[d]) / gc.h) - 1.0;
+        const double b = floor((rp[3 * p + d] + delta - org[d]) / gc.h) + 1.0;
+        lo[d] = a < 0.0 ? 0 : (int)a;
+        hi[d] = b > (double)(nc[d] - 1) ? nc[d] - 1 : (int)b;
+    }
+    const double d2max = delta * delta;
+    for (int i = lo[0]; i <= hi[0]; ++i)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                const int c[3] = {i, j, k};
+                double dd[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double blo = org[d] + gc.h * (double)c[d];
+                    const double bhi = org[d] + gc.h * (double)(c[d] + 1);
+                    const double x = rp[3 * p + d];
+                    const double e = blo - x > x - bhi ? blo - x : x - bhi;
+                    dd[d] = e > 0.0 ? e : 0.0;
+                }
+                const double d2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+                if (d2 <= d2max) flag[((int64_t)i * nc1 + j) * nc2 + k] = 1;
+            }
+}
+
+// brick flags: a brick is refined when any of its cells is flagged
+__global__ void __launch_bounds__(256) k_bricks(const uint8_t* flag, int nc0, int nc1, int nc2, int B, int nb0,
+                                                int nb1, int nb2, uint8_t* bf)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)nb0 * nb1 * nb2) return;
+    const int bk = (int)(t % nb2), bj = (int)((t / nb2) % nb1), bi = (int)(t / ((int64_t)nb1 * nb2));
+    uint8_t r = 0;
+    for (int i = bi * B; i < min((bi + 1) * B, nc0) && !r; ++i)
+        for (int j = bj * B; j < min((bj + 1) * B, nc1) && !r; ++j)
+            for (int k = bk * B; k < min((bk + 1) * B, nc2) && !r; ++k)
+                r |= flag[((int64_t)i * nc1 + j) * nc2 + k];
+    bf[t] = r;
+}
+
+__global__ void __launch_bounds__(256) k_cells_from_bricks(const uint8_t* bf, int nc0, int nc1, int nc2, int B,
+                                                           int nb1, int nb2, uint8_t* cell)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)nc0 * nc1 * nc2) return;
+    const int k = (int)(t % nc2), j = (int)((t / nc2) % nc1), i = (int)(t / ((int64_t)nc1 * nc2));
+    cell[t] = bf[((int64_t)(i / B) * nb1 + j / B) * nb2 + k / B];
+}
+
+// ---- coefficients ------------------------------------------------------------------------
+
+__device__ __forceinline__ double edgeK(uint32_t c, int ax, const double* ck, const Coef& cf)
+{
+    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
+    return (c & C_SOLUTE) ? cf.kin : cf.kout;
+}
+
+// coarse grid: K of the +axis edges and the lumped term from the unrefined incident cells;
+// role 1 for a non-box node with an unrefined incident cell
+__global__ void __launch_bounds__(256) k_coarse_coef(Grid g, Cells cl, const uint32_t* __restrict__ code, Coef cf,
+                                                     double* __restrict__ K, uint8_t* __restrict__ role)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    double kx = 0.0, ky = 0.0, kz = 0.0, m = 0.0;
+    uint8_t r = 0;
+    if (k >= 0 && k < g.nz) {
+        const uint32_t c = code[e];
+        const double ke = (c & C_SOLUTE) ? cf.kin : cf.kout;
+        const int n[3] = {i, j, k};
+        double kk[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+            int cnt = 0;
+            for (int s1 = 0; s1 < 2; ++s1)
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    int cc[3] = {n[0], n[1], n[2]};
+                    cc[o1] -= s1;
+                    cc[o2] -= s2;
+                    if (cl.valid(cc[0], cc[1], cc[2]) && !cl.refined(cc[0], cc[1], cc[2])) ++cnt;
+                }
+            kk[ax] = 0.25 * (double)cnt * ke;
+        }
+        int c8 = 0;
+        for (int a = 0; a < 8; ++a) {
+            const int ci = i - (a & 1), cj = j - ((a >> 1) & 1), ck2 = k - ((a >> 2) & 1);
+            if (cl.valid(ci, cj, ck2) && !cl.refined(ci, cj, ck2)) ++c8;
+        }
+        kx = kk[0];
+        ky = kk[1];
+        kz = kk[2];
+        m = (c & C_SOLUTE) ? 0.0 : 0.125 * (double)c8 * cf.mass;
+        r = (!(c & C_BOX) && c8 > 0) ? 1 : 0;
+    }
+    K[e] = kx;
+    K[g.N + e] = ky;
+    K[2 * g.N + e] = kz;
+    K[3 * g.N + e] = m;
+    role[e] = r;
+}
+
+// fine sub-lattice: the same from the refined incident fine cells (a fine cell is refined when
+// its coarse parent is); roles 1 unknown, 2 coincident with a coarse unknown, 3 hanging
+__global__ void __launch_bounds__(256) k_fine_coef(Grid g, Grid gc, Cells cl, const uint32_t* __restrict__ code,
+                                                   const double* __restrict__ ck, Coef cf,
+                                                   const uint8_t* __restrict__ rolec, double* __restrict__ K,
+                                                   uint8_t* __restrict__ role)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    double kk[3] = {0.0, 0.0, 0.0}, m = 0.0;
+    uint8_t r = 0;
+    if (k >= 0 && k < g.nz) {
+        const uint32_t c = code[e];
+        const int F[3] = {i + g.off[0], j + g.off[1], k + g.off[2]};   // global fine lattice
+        auto fref = [&](int a, int b, int d) {   // fine cell (global) refined?
+            if (a < 0 || b < 0 || d < 0) return false;
+            const int ci = a >> 1, cj = b >> 1, ck2 = d >> 1;
+            return cl.valid(ci, cj, ck2) && cl.refined(ci, cj, ck2);
+        };
+        for (int ax = 0; ax < 3; ++ax) {
+            const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+            int cnt = 0;
+            for (int s1 = 0; s1 < 2; ++s1)
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    int cc[3] = {F[0], F[1], F[2]};
+                    cc[o1] -= s1;
+                    cc[o2] -= s2;
+                    if (fref(cc[0], cc[1], cc[2])) ++cnt;
+                }
+            kk[ax] = cnt ? 0.25 * (double)cnt * edgeK(c, ax, ck, cf) : 0.0;
+        }
+        int c8 = 0;
+        for (int a = 0; a < 8; ++a)
+            if (fref(F[0] - (a & 1), F[1] - ((a >> 1) & 1), F[2] - ((a >> 2) & 1))) ++c8;
+        m = (c & C_SOLUTE) ? 0.0 : 0.125 * (double)c8 * cf.mass;
+        if (c8 > 0) {
+            const bool even = !((F[0] | F[1] | F[2]) & 1);
+            if (even) {
+                r = rolec[gc.idx(F[0] >> 1, F[1] >> 1, F[2] >> 1)] ? 2 : 1;
+            } else {
+                // coarse cells whose closed box holds the node: an odd coordinate has one
+                // candidate, an even one two
+                bool hang = false;
+                for (int s = 0; s < 8 && !hang; ++s) {
+                    int cc[3];
+                    bool ok = true;
+                    for (int d = 0; d < 3; ++d) {
+                        const int side = (s >> d) & 1;
+                        if (F[d] & 1) {
+                            if (side) ok = false;
+                            cc[d] = (F[d] - 1) >> 1;
+                        } else {
+                            cc[d] = (F[d] >> 1) - 1 + side;
+                        }
+                    }
+                    if (ok && cl.valid(cc[0], cc[1], cc[2]) && !cl.refined(cc[0], cc[1], cc[2])) hang = true;
+                }
+                r = hang ? 3 : 1;
+            }
+        }
+    }
+    K[e] = kk[0];
+    K[g.N + e] = kk[1];
+    K[2 * g.N + e] = kk[2];
+    K[3 * g.N + e] = m;
+    role[e] = r;
+}
+
+// own-grid diagonal: the six edge coefficients and the lumped term
+__device__ __forceinline__ double own_diag(const Grid& g, const double* __restrict__ K, int64_t e)
+{
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    return ((K[e] + K[e - sx]) + (K[g.N + e] + K[g.N + e - sy])) + ((K[2 * g.N + e] + K[2 * g.N + e - 1]) + K[3 * g.N + e]);
+}
+
+__global__ void __launch_bounds__(256) k_diag(Grid g, const double* __restrict__ K, const uint8_t* __restrict__ role,
+                                              double* __restrict__ D)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    D[e] = role[e] ? own_diag(g, K, e) : 0.0;
+}
+
+// a coarse unknown with a coincident fine node also carries that node's fine diagonal
+__global__ void __launch_bounds__(256) k_diag_fix(int64_t ng, const int64_t* gfine, const int64_t* gpar,
+                                                  const int32_t* gnp, const double* Df, double* Dc)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ng || gnp[t] != 1) return;
+    Dc[gpar[4 * t]] += Df[gfine[t]];
+}
+
+__global__ void __launch_bounds__(256) k_invert(int64_t n, const uint8_t* __restrict__ role, double* __restrict__ D)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    D[e] = (role[e] == 1 && D[e] > 0.0) ? 1.0 / D[e] : 0.0;
+}
+
+// Dirichlet lift on the coarse grid: b += K g over the edges to box nodes
+__global__ void __launch_bounds__(256) k_lift(Grid g, const double* __restrict__ K, const uint8_t* __restrict__ role,
+                                              const uint32_t* __restrict__ code, const double* __restrict__ gb,
+                                              double* __restrict__ b)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N || role[e] != 1) return;
+    const int64_t st[3] = {(int64_t)g.ny * g.S, g.S, 1};
+    double lift = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (code[e + st[ax]] & C_BOX) lift += K[ax * g.N + e] * gb[e + st[ax]];
+        if (code[e - st[ax]] & C_BOX) lift += K[ax * g.N + e - st[ax]] * gb[e - st[ax]];
+    }
+    b[e] += lift;
+}
+
+// ---- operator and CG ---------------------------------------------------------------------
+
+// derived fine values from the coarse ones
+__global__ void __launch_bounds__(256) k_fill(int64_t ng, const int64_t* __restrict__ gfine,
+                                              const int64_t* __restrict__ gpar, const int32_t* __restrict__ gnp,
+                                              const double* __restrict__ vc, double* __restrict__ vf)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ng) return;
+    const int np = gnp[t];
+    double s = 0.0;
+    for (int u = 0; u < np; ++u) s += vc[gpar[4 * t + u]];
+    vf[gfine[t]] = s / (double)np;
+}
+
+// q = (cell contributions of this grid) p at every node with a role; 0 elsewhere
+__global__ void __launch_bounds__(256) k_apply(Grid g, const double* __restrict__ K, const uint8_t* __restrict__ role,
+                                               const double* __restrict__ p, double* __restrict__ q)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.N) return;
+    if (!role[e]) {
+        q[e] = 0.0;
+        return;
+    }
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    const double kxp = K[e], kxm = K[e - sx], kyp = K[g.N + e], kym = K[g.N + e - sy];
+    const double kzp = K[2 * g.N + e], kzm = K[2 * g.N + e - 1];
+    const double D = ((kxp + kxm) + (kyp + kym)) + ((kzp + kzm) + K[3 * g.N + e]);
+    q[e] = D * p[e] - (((kxm * p[e - sx] + kxp * p[e + sx]) + (kym * p[e - sy] + kyp * p[e + sy])) +
+                       (kzm * p[e - 1] + kzp * p[e + 1]));
+}
+
+// the rows of the derived fine nodes go to their coarse nodes (one thread per coarse node)
+__global__ void __launch_bounds__(256) k_restrict(int64_t nr, const int64_t* __restrict__ rnode,
+                                                  const int64_t* __restrict__ rptr, const int64_t* __restrict__ rsrc,
+                                                  const double* __restrict__ rw, const int64_t* __restrict__ gfine,
+                                                  const double* __restrict__ vf, double* __restrict__ vc)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nr) return;
+    double s = 0.0;
+    for (int64_t u = rptr[t]; u < rptr[t + 1]; ++u) s += rw[u] * vf[gfine[rsrc[u]]];
+    vc[rnode[t]] += s;
+}
+
+__device__ __forceinline__ void bsum(double* v, int nv, double* sh)
+{
+    for (int t = 0; t < nv; ++t)
+        for (int o = 32; o > 0; o >>= 1) v[t] += __shfl_xor(v[t], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+        for (int t = 0; t < nv; ++t) sh[4 * t + w] = v[t];
+    __syncthreads();
+    for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
+}
+
+// partial sums of a.b over the unknowns of both grids: blocks [0, nbc) coarse, then fine
+__global__ void __launch_bounds__(256) k_dot(int64_t Nc, int64_t Nf, int nbc, const uint8_t* rc, const uint8_t* rf,
+                                             const double* ac, const double* bc, const double* af, const double* bf,
+                                             double* part, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const bool coarse = (int)blockIdx.x < nbc;
+    const int64_t b0 = coarse ? blockIdx.x : blockIdx.x - nbc;
+    const int64_t nblocks = coarse ? nbc : (int64_t)gridDim.x - nbc;
+    const int64_t N = coarse ? Nc : Nf;
+    const uint8_t* role = coarse ? rc : rf;
+    const double* a = coarse ? ac : af;
+    const double* b = coarse ? bc : bf;
+    double v[1] = {0.0};
+    for (int64_t e = b0 * 256 + threadIdx.x; e < N; e += nblocks * 256)
+        if (role[e] == 1) v[0] += a[e] * b[e];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[t];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) {
+        const double pq = v[0];
+        st->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else {
+            st->alpha = st->gamma / pq;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, z = D^-1 r; partial sums of r.z and r.r
+__global__ void __launch_bounds__(256) k_update(int64_t Nc, int64_t Nf, int nbc, const uint8_t* rc, const uint8_t* rf,
+                                                double* xc, double* rrc, double* zc, const double* pc, const double* qc,
+                                                const double* dc, double* xf, double* rrf, double* zf, const double* pf,
+                                                const double* qf, const double* df, double* part, int nb,
+                                                const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const bool coarse = (int)blockIdx.x < nbc;
+    const int64_t b0 = coarse ? blockIdx.x : blockIdx.x - nbc;
+    const int64_t nblocks = coarse ? nbc : (int64_t)gridDim.x - nbc;
+    const int64_t N = coarse ? Nc : Nf;
+    const uint8_t* role = coarse ? rc : rf;
+    double* x = coarse ? xc : xf;
+    double* r = coarse ? rrc : rrf;
+    double* z = coarse ? zc : zf;
+    const double* p = coarse ? pc : pf;
+    const double* q = coarse ? qc : qf;
+    const double* d = coarse ? dc : df;
+    const double a = st->alpha;
+    double v[2] = {0.0, 0.0};
+    for (int64_t e = b0 * 256 + threadIdx.x; e < N; e += nblocks * 256) {
+        if (role[e] != 1) continue;
+        x[e] += a * p[e];
+        const double rv = r[e] - a * q[e];
+        r[e] = rv;
+        const double zv = d[e] * rv;
+        z[e] = zv;
+        v[0] += rv * zv;
+        v[1] += rv * rv;
+    }
+    bsum(v, 2, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[nb + blockIdx.x] = v[1];
+    }
+}
+
+// beta = r.z / r.z_old, convergence test; init: the first residual (no beta)
+__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int init, double rtol2)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    double v[2] = {0.0, 0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) {
+        v[0] += part[t];
+        v[1] += part[nb + t];
+    }
+    bsum(v, 2, sh);
+    if (threadIdx.x == 0) {
+        const double gm = v[0], rr = v[1];
+        if (init) {
+            st->bnorm2 = rr;
+            st->stop2 = rtol2 * rr;
+            st->iter_count = 0;
+            st->beta = 0.0;
+        } else {
+            st->iter_count += 1;
+            st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
+        }
+        st->gamma = gm;
+        st->rr = rr;
+        if (!isfinite(gm) || !isfinite(rr)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else if (rr <= st->stop2) {
+            st->status = 1;
+            st->iters = st->iter_count;
+        }
+    }
+}
+
+// p = z + beta p over the unknowns of one grid (init: beta = 0)
+__global__ void __launch_bounds__(256) k_pupd(int64_t N, const uint8_t* role, const double* z, double* p,
+                                              const CGState* st)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N || st->status != 0) return;
+    p[e] = role[e] == 1 ? z[e] + st->beta * p[e] : 0.0;
+}
+
+__global__ void k_state_init(CGState* st)
+{
+    st->alpha = st->beta = st->gamma = st->bnorm2 = st->rr = st->pq = 0.0;
+    st->stop2 = st->trig2 = st->delta2 = st->goal64 = st->rr64 = 0.0;
+    st->status = 0;
+    st->stop_status = 1;
+    st->iters = st->iter_count = st->ru = st->n_ru = 0;
+}
+
+// coarse nodes inside the refined region take the value of their fine node (for export)
+__global__ void __launch_bounds__(256) k_sync_coarse(Grid gc, Grid gf, const uint8_t* rolec, const uint32_t* codec,
+                                                     const double* xf, double* xc)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= gc.N || rolec[e] || (codec[e] & C_BOX)) return;
+    int i, j, k;
+    decode(gc, e, i, j, k);
+    if (k < 0 || k >= gc.nz) return;
+    const int a = 2 * i - gf.off[0], b = 2 * j - gf.off[1], c = 2 * k - gf.off[2];
+    if (a < 0 || b < 0 || c < 0 || a >= gf.nx || b >= gf.ny || c >= gf.nz) return;
+    xc[e] = xf[gf.idx(a, b, c)];
+}
+
+}  // namespace
+
+// ---- host side -----------------------------------------------------------------------------
+
+int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const double* chg)
+{
+    const pb_params& P = pb->prm;
+    const Grid& gc = pb->g;
+    hipStream_t s = pb->ctx->stream;
+    RefineData* R = new RefineData();
+    pb->ref = R;
+    R->delta = P.refine_shell_A;
+    R->brick = P.refine_brick;
+    for (int d = 0; d < 3; ++d) R->nc[d] = P.n[d] - 1;
+    const int64_t na = pb->na;
+    if (na <= 0) return pbi_fail(PB_EINVAL, "refinement needs atoms");
+
+    // fine sub-lattice: the bricks that can hold a cell within delta of the surface, plus one
+    // coarse cell on every side
+    const double H = P.h, o[3] = {P.origin[0], P.origin[1], P.origin[2]};
+    int cl[3], ch[3];
+    for (int d = 0; d < 3; ++d) {
+        double lo = 1e300, hi = -1e300;
+        for (int64_t a = 0; a < na; ++a) {
+            lo = std::min(lo, xyz[3 * a + d] - rad[a]);
+            hi = std::max(hi, xyz[3 * a + d] + rad[a]);
+        }
+        const int c0 = (int)std::floor((lo - R->delta - o[d]) / H) - 1;
+        const int c1 = (int)std::floor((hi + R->delta - o[d]) / H) + 2;   // one past the last cell
+        const int B = R->brick;
+        cl[d] = (c0 / B) * B - 1;
+        ch[d] = ((c1 + B - 1) / B) * B + 1;
+        cl[d] = std::max(cl[d], 0);
+        ch[d] = std::min(ch[d], R->nc[d]);
+    }
+    pb_params pf = P;
+    pf.bc = PB_BC_ZERO;
+    pf.bc_values = nullptr;
+    pf.h = H / 2.0;
+    pf.refine = 0;
+    pf.precision = PB_FP64;
+    int off[3];
+    for (int d = 0; d < 3; ++d) {
+        pf.n[d] = 2 * (ch[d] - cl[d]) + 1;
+        off[d] = 2 * cl[d];
+    }
+    pb_problem* fp = nullptr;
+    int rc = pbi_build_begin_sub(pb->ctx, &pf, na, xyz, rad, chg, off, &fp);
+    if (rc) return rc;
+    R->fine = fp;
+    if (hipEventSynchronize(fp->ev) != hipSuccess) return pbi_fail(PB_EDEVICE, "fine build: counting failed");
+    if ((rc = pbi_build_continue(fp))) return rc;
+    if (hipEventSynchronize(fp->ev) != hipSuccess) return pbi_fail(PB_EDEVICE, "fine build failed");
+    pbi_build_end(fp);
+    const Grid& gf = fp->g;
+
+    // refinement flags
+    const int64_t ncell = (int64_t)R->nc[0] * R->nc[1] * R->nc[2];
+    const int B = R->brick;
+    const int nb[3] = {(R->nc[0] + B - 1) / B, (R->nc[1] + B - 1) / B, (R->nc[2] + B - 1) / B};
+    R->cells = (uint8_t*)pb->mem.get((size_t)ncell);
+    uint8_t* flag = (uint8_t*)pb->mem.get((size_t)ncell);
+    uint8_t* bf = (uint8_t*)pb->mem.get((size_t)nb[0] * nb[1] * nb[2]);
+    if (!R->cells || !flag || !bf) return pbi_fail(PB_ENOMEM, "refinement flags");
+    RCHK(launch_fill(s, flag, (size_t)ncell));
+    if (fp->ncut > 0)
+        k_mark<<<nblk(fp->ncut, 256), 256, 0, s>>>(gc, fp->ncut, fp->rp, R->delta, flag, R->nc[0], R->nc[1], R->nc[2]);
+    k_bricks<<<nblk((int64_t)nb[0] * nb[1] * nb[2], 256), 256, 0, s>>>(flag, R->nc[0], R->nc[1], R->nc[2], B, nb[0], nb[1],
+                                                                       nb[2], bf);
+    k_cells_from_bricks<<<nblk(ncell, 256), 256, 0, s>>>(bf, R->nc[0], R->nc[1], R->nc[2], B, nb[1], nb[2], R->cells);
+    RCHK(hipGetLastError());
+    std::vector<uint8_t> hcell((size_t)ncell);
+    RCHK(hipMemcpyAsync(hcell.data(), R->cells, (size_t)ncell, hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    pb->mem.put(flag);
+    pb->mem.put(bf);
+    R->n_refined = 0;
+    for (int i = 0; i < R->nc[0]; ++i)
+        for (int j = 0; j < R->nc[1]; ++j)
+            for (int k = 0; k < R->nc[2]; ++k) {
+                if (!hcell[((size_t)i * R->nc[1] + j) * R->nc[2] + k]) continue;
+                ++R->n_refined;
+                const int c[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d) {
+                    if (c[d] == 0 || c[d] == R->nc[d] - 1)
+                        return pbi_fail(PB_EINVAL, "refined cells touch the box boundary layer");
+                    if (c[d] < cl[d] + 1 || c[d] >= ch[d] - 1)
+                        return pbi_fail(PB_EINVAL, "refined cell outside the fine sub-lattice");
+                }
+            }
+
+    // coefficients and roles
+    Cells cells{R->cells, {R->nc[0], R->nc[1], R->nc[2]}};
+    R->Kc = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)gc.N);
+    R->Kf = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)gf.N);
+    R->rolec = (uint8_t*)pb->mem.get((size_t)gc.N);
+    R->rolef = (uint8_t*)pb->mem.get((size_t)gf.N);
+    if (!R->Kc || !R->Kf || !R->rolec || !R->rolef) return pbi_fail(PB_ENOMEM, "refined coefficients");
+    k_coarse_coef<<<nblk(gc.N, 256), 256, 0, s>>>(gc, cells, pb->code, pb->cf, R->Kc, R->rolec);
+    k_fine_coef<<<nblk(gf.N, 256), 256, 0, s>>>(gf, gc, cells, fp->code, fp->ck64, fp->cf, R->rolec, R->Kf, R->rolef);
+    RCHK(hipGetLastError());
+    std::vector<uint8_t> hrolef((size_t)gf.N), hrolec((size_t)gc.N);
+    RCHK(hipMemcpyAsync(hrolef.data(), R->rolef, (size_t)gf.N, hipMemcpyDeviceToHost, s));
+    RCHK(hipMemcpyAsync(hrolec.data(), R->rolec, (size_t)gc.N, hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+
+    // derived fine nodes and their coarse parents; the gather lists of the coarse parents
+    std::vector<int64_t> gfine, gpar;
+    std::vector<int32_t> gnp;
+    R->nunk_c = R->nunk_f = R->nhang = 0;
+    for (int64_t e = 0; e < gc.N; ++e) R->nunk_c += hrolec[(size_t)e] == 1;
+    for (int i = 0; i < gf.nx; ++i)
+        for (int j = 0; j < gf.ny; ++j)
+            for (int k = 0; k < gf.nz; ++k) {
+                const int64_t e = gf.idx(i, j, k);
+                const uint8_t r = hrolef[(size_t)e];
+                if (r == 1) ++R->nunk_f;
+                if (r < 2) continue;
+                const int F[3] = {i + off[0], j + off[1], k + off[2]};
+                int lo[3], hi[3];
+                int cnt = 1;
+                for (int d = 0; d < 3; ++d) {
+                    if (F[d] & 1) {
+                        lo[d] = (F[d] - 1) / 2;
+                        hi[d] = (F[d] + 1) / 2;
+                        cnt *= 2;
+                    } else {
+                        lo[d] = hi[d] = F[d] / 2;
+                    }
+                }
+                if (r == 3) ++R->nhang;
+                gfine.push_back(e);
+                gnp.push_back(cnt);
+                int u = 0;
+                int64_t first = -1;
+                for (int a = lo[0]; a <= hi[0]; ++a)
+                    for (int b = lo[1]; b <= hi[1]; ++b)
+                        for (int c = lo[2]; c <= hi[2]; ++c) {
+                            const int64_t pe = gc.idx(a, b, c);
+                            if (hrolec[(size_t)pe] != 1) return pbi_fail(PB_EINVAL, "a derived fine node has a parent that is not an unknown");
+                            if (first < 0) first = pe;
+                            gpar.push_back(pe);
+                            ++u;
+                        }
+                for (; u < 4; ++u) gpar.push_back(first);
+            }
+    R->ng = (int64_t)gfine.size();
+    // gather lists: for each coarse parent, (derived entry, weight) in entry order
+    std::vector<std::vector<std::pair<int64_t, double>>> tmp;
+    std::vector<int64_t> rnode;
+    {
+        std::vector<int64_t> slot((size_t)gc.N, -1);
+        for (int64_t t = 0; t < R->ng; ++t)
+            for (int u = 0; u < gnp[(size_t)t]; ++u) {
+                const int64_t pe = gpar[4 * (size_t)t + u];
+                if (slot[(size_t)pe] < 0) {
+                    slot[(size_t)pe] = (int64_t)rnode.size();
+                    rnode.push_back(pe);
+                    tmp.emplace_back();
+                }
+                tmp[(size_t)slot[(size_t)pe]].emplace_back(t, 1.0 / gnp[(size_t)t]);
+            }
+    }
+    R->nr = (int64_t)rnode.size();
+    std::vector<int64_t> rptr(1, 0), rsrc;
+    std::vector<double> rw;
+    for (auto& v : tmp) {
+        for (auto& pr : v) {
+            rsrc.push_back(pr.first);
+            rw.push_back(pr.second);
+        }
+        rptr.push_back((int64_t)rsrc.size());
+    }
+    auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+        *dst = pb->mem.get(std::max<size_t>(bytes, 8));
+        if (!*dst) return pbi_fail(PB_ENOMEM, "refinement lists");
+        if (bytes && hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return pbi_fail(PB_EDEVICE, "refinement lists upload");
+        return PB_OK;
+    };
+    if ((rc = up((void**)&R->gfine, gfine.data(), sizeof(int64_t) * gfine.size()))) return rc;
+    if ((rc = up((void**)&R->gpar, gpar.data(), sizeof(int64_t) * gpar.size()))) return rc;
+    if ((rc = up((void**)&R->gnp, gnp.data(), sizeof(int32_t) * gnp.size()))) return rc;
+    if ((rc = up((void**)&R->rnode, rnode.data(), sizeof(int64_t) * rnode.size()))) return rc;
+    if ((rc = up((void**)&R->rptr, rptr.data(), sizeof(int64_t) * rptr.size()))) return rc;
+    if ((rc = up((void**)&R->rsrc, rsrc.data(), sizeof(int64_t) * rsrc.size()))) return rc;
+    if ((rc = up((void**)&R->rw, rw.data(), sizeof(double) * rw.size()))) return rc;
+
+    // load: each charge on the corners of the cell that holds it (the fine cell inside a
+    // refined coarse cell), 4 pi q trilinear; derived fine entries go to their parents
+    std::vector<double> hbc((size_t)gc.N, 0.0), hbf((size_t)gf.N, 0.0);
+    for (int64_t a = 0; a < na; ++a) {
+        int c[3];
+        for (int d = 0; d < 3; ++d) {
+            const double f = (xyz[3 * a + d] - o[d]) / H;
+            double fl = std::floor(f);
+            fl = std::min(std::max(fl, 0.0), (double)(P.n[d] - 2));
+            c[d] = (int)fl;
+        }
+        const bool fine = hcell[((size_t)c[0] * R->nc[1] + c[1]) * R->nc[2] + c[2]] != 0;
+        int base[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            if (fine) {
+                const double f = (xyz[3 * a + d] - o[d]) / (H / 2.0);
+                double fl = std::floor(f);
+                fl = std::min(std::max(fl, (double)(2 * c[d])), (double)(2 * c[d] + 1));
+                base[d] = (int)fl - off[d];
+                t[d] = f - fl;
+            } else {
+                const double f = (xyz[3 * a + d] - o[d]) / H;
+                base[d] = c[d];
+                t[d] = f - (double)c[d];
+            }
+        }
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y)
+                for (int z = 0; z < 2; ++z) {
+                    const double w = (x ? t[0] : 1.0 - t[0]) * (y ? t[1] : 1.0 - t[1]) * (z ? t[2] : 1.0 - t[2]);
+                    const double v = 4.0 * kPi * chg[a] * w;
+                    if (fine)
+                        hbf[(size_t)gf.idx(base[0] + x, base[1] + y, base[2] + z)] += v;
+                    else
+                        hbc[(size_t)gc.idx(base[0] + x, base[1] + y, base[2] + z)] += v;
+                }
+    }
+    for (int64_t t = 0; t < R->ng; ++t) {
+        const double v = hbf[(size_t)gfine[(size_t)t]];
+        if (v == 0.0) continue;
+        for (int u = 0; u < gnp[(size_t)t]; ++u) hbc[(size_t)gpar[4 * (size_t)t + u]] += v / gnp[(size_t)t];
+        hbf[(size_t)gfine[(size_t)t]] = 0.0;
+    }
+    // solver vectors: b, r, z, p, q, D^-1 of each grid (x: the problems' own x)
+    const size_t Nc = (size_t)gc.N, Nf = (size_t)gf.N;
+    double** vc[6] = {&R->bc, &R->rc, &R->zc, &R->pc, &R->qc, &R->dc};
+    double** vf[6] = {&R->bf, &R->rf, &R->zf, &R->pf, &R->qf, &R->df};
+    for (int v = 0; v < 6; ++v) {
+        *vc[v] = (double*)pb->mem.get(sizeof(double) * Nc);
+        *vf[v] = (double*)pb->mem.get(sizeof(double) * Nf);
+        if (!*vc[v] || !*vf[v]) return pbi_fail(PB_ENOMEM, "refined solver vectors");
+        RCHK(launch_fill(s, *vc[v], sizeof(double) * Nc));
+        RCHK(launch_fill(s, *vf[v], sizeof(double) * Nf));
+    }
+    RCHK(hipMemcpyAsync(R->bc, hbc.data(), sizeof(double) * Nc, hipMemcpyHostToDevice, s));
+    RCHK(hipMemcpyAsync(R->bf, hbf.data(), sizeof(double) * Nf, hipMemcpyHostToDevice, s));
+    k_lift<<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, pb->code, pb->gb, R->bc);
+    k_diag<<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, R->dc);
+    k_diag<<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, R->df);
+    if (R->ng) k_diag_fix<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, R->df, R->dc);
+    k_invert<<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, R->dc);
+    k_invert<<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->rolef, R->df);
+    RCHK(hipGetLastError());
+    R->nbc = (int)std::min<int64_t>(1024, (int64_t)nblk(gc.N, 256));
+    R->nbf = (int)std::min<int64_t>(1024, (int64_t)nblk(gf.N, 256));
+    R->part = (double*)pb->mem.get(sizeof(double) * 2 * (size_t)(R->nbc + R->nbf));
+    if (!R->part) return pbi_fail(PB_ENOMEM, "refined partial sums");
+    RCHK(hipStreamSynchronize(s));
+    return PB_OK;
+}
+
+// composite Jacobi-CG; fills the derived fine values of the solution at the end
+int pbi_refine_solve(pb_problem* pb, CGState* out)
+{
+    RefineData* R = pb->ref;
+    pb_problem* fp = R->fine;
+    const Grid& gc = pb->g;
+    const Grid& gf = fp->g;
+    hipStream_t s = pb->ctx->stream;
+    const pb_params& P = pb->prm;
+    const int nb = R->nbc + R->nbf;
+    CGState* st = pb->st;
+    const unsigned bc = nblk(gc.N, 256), bfn = nblk(gf.N, 256);
+    // x = 0, r = b, z = D^-1 r, p = z
+    RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)gc.N));
+    RCHK(launch_fill(s, fp->x, sizeof(double) * (size_t)gf.N));
+    RCHK(hipMemcpyAsync(R->rc, R->bc, sizeof(double) * (size_t)gc.N, hipMemcpyDeviceToDevice, s));
+    RCHK(hipMemcpyAsync(R->rf, R->bf, sizeof(double) * (size_t)gf.N, hipMemcpyDeviceToDevice, s));
+    k_state_init<<<1, 1, 0, s>>>(st);
+    // the first update with alpha = 0 and p = q = 0 leaves x, r and forms z and the norms
+    RCHK(launch_fill(s, R->pc, sizeof(double) * (size_t)gc.N));
+    RCHK(launch_fill(s, R->pf, sizeof(double) * (size_t)gf.N));
+    RCHK(launch_fill(s, R->qc, sizeof(double) * (size_t)gc.N));
+    RCHK(launch_fill(s, R->qf, sizeof(double) * (size_t)gf.N));
+    k_update<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, pb->x, R->rc, R->zc, R->pc, R->qc, R->dc, fp->x,
+                                R->rf, R->zf, R->pf, R->qf, R->df, R->part, nb, st);
+    k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 1, P.rtol * P.rtol);
+    k_pupd<<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
+    k_pupd<<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
+    RCHK(hipGetLastError());
+    const int M = 16;
+    int launched = 0;
+    CGState h;
+    for (;;) {
+        const int n = std::min(M, P.max_iter - launched);
+        for (int it = 0; it < n; ++it) {
+            if (R->ng) k_fill<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, R->pc, R->pf);
+            k_apply<<<bc, 256, 0, s>>>(gc, R->Kc, R->rolec, R->pc, R->qc);
+            k_apply<<<bfn, 256, 0, s>>>(gf, R->Kf, R->rolef, R->pf, R->qf);
+            if (R->nr)
+                k_restrict<<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, R->qf,
+                                                            R->qc);
+            k_dot<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, R->pc, R->qc, R->pf, R->qf, R->part, st);
+            k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
+            k_update<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, pb->x, R->rc, R->zc, R->pc, R->qc, R->dc,
+                                        fp->x, R->rf, R->zf, R->pf, R->qf, R->df, R->part, nb, st);
+            k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 0, 0.0);
+            k_pupd<<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
+            k_pupd<<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
+        }
+        RCHK(hipGetLastError());
+        launched += n;
+        RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        RCHK(hipStreamSynchronize(s));
+        if (h.status != 0 || launched >= P.max_iter) break;
+    }
+    // derived fine values of the solution, and the coarse copies of the fine-owned nodes
+    if (R->ng) k_fill<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, pb->x, fp->x);
+    k_sync_coarse<<<bc, 256, 0, s>>>(gc, gf, R->rolec, pb->code, fp->x, pb->x);
+    RCHK(hipGetLastError());
+    RCHK(hipMemcpyAsync(out, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    return PB_OK;
+}

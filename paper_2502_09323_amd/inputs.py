@@ -48,6 +48,9 @@ class GridSpec:
     rtol: float = 1e-10
     max_iter: int = 20000
     tile_planes: int = 0      # planes per x-chunk of the GPU iteration tiles (0 = automatic)
+    refine: int = 0           # 1: one level of 2:1 local refinement near the surface
+    refine_shell: float = 3.0 # refine coarse cells within this distance of a crossing point
+    refine_brick: int = 4     # ... rounded up to aligned bricks of this many cells per edge
     precision: int = FP64
     inner_rtol: float = 1e-4
     bc_values: np.ndarray | None = field(default=None, repr=False)  # BC_USER: full grid
@@ -140,8 +143,12 @@ def protein_c2(seed: int = 2502, **kw):
 
 
 def refined_c3(seed: int = 2503, **kw):
-    """20,000-atom molecule in a 45 A ball; coarse 193^3 nodes at 1.0 A."""
+    """20,000-atom molecule in a 45 A ball; coarse 193^3 nodes at 1.0 A, refined to 0.5 A
+    within 3 A of the surface (bricks of 4^3 coarse cells)."""
     mol = random_molecule(20000, 45.0, seed)
+    kw.setdefault("refine", 1)
+    kw.setdefault("refine_shell", 3.0)
+    kw.setdefault("refine_brick", 4)
     return mol, cubic_grid(193, 1.0, **kw)
 
 

@@ -39,11 +39,29 @@ def test_every_declared_symbol_is_exported(lib):
         assert n in declared_functions(), n
 
 
-def test_struct_sizes_match_binding():
-    # pb_params: 5 doubles, 3 int32 (+pad), 3 doubles, int32 (+pad), ptr, int32 (+pad), 2 doubles, int32 (+pad)
-    assert C.sizeof(B.PbParams) == 5 * 8 + 16 + 24 + 8 + 8 + 8 + 16 + 8
-    assert C.sizeof(B.PbSolveStats) == 32
-    assert C.sizeof(B.PbEnergyOut) == 72
+def test_struct_sizes_match_binding(tmp_path):
+    """The ctypes structures have the size and field offsets of the C header (compiled here)."""
+    import subprocess
+    structs = {"pb_params": B.PbParams, "pb_solve_stats": B.PbSolveStats, "pb_energy_out": B.PbEnergyOut,
+               "pb_refine_stats": B.PbRefineStats}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pb.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            src.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, v = line.split()
+        got[(cname, field)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_null_arguments_are_rejected_without_a_gpu(lib):
