@@ -39,6 +39,28 @@ RTOL = 5e-8
 # algorithmic bytes per unknown of one FP32 CG iteration kernel: read z, w, p, x and the
 # node code, write z, w, p and x (4 bytes each)
 ITER_BYTES_FP32 = 36
+
+# HBM traffic per launch relative to the algorithmic bytes, from rocprofv3 FETCH_SIZE (x2.0)
+# and WRITE_SIZE (x1.0) passes over this same command (each pass compared with the launches
+# it timed), with the fingerprint of the kernel source they were taken on; a kernel changed
+# since then reports null
+COUNTER_TRAFFIC = {"kb_iter<float>": {"fingerprint": "a9cbdc2f1925cf88", "ratio": 1.185}}
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pb_solve.hip", "pb_internal.h"):
+        with open(os.path.join(ROOT, "paper_2502_09323_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, bytes_per_launch):
+    t = COUNTER_TRAFFIC.get(kernel)
+    if not t or t["fingerprint"] != kernel_fingerprint():
+        return None
+    return round(t["ratio"] * bytes_per_launch)
 DELTA = 1e-2
 N_REQ = 512
 SEED = 2505
@@ -101,24 +123,30 @@ def bench_serving(args, B, torch):
     nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
     log(f"generated {N_REQ} requests")
 
-    # warmup: the first requests through a server (untimed)
-    for _ in range(args.warmup):
-        serve(B, main, side, reqs[:32])[2].close()
-
-    # timed: the whole stream, closed loop
+    # Every batched iteration launch of the run (warm-up, closed and open loop) is timed with
+    # HIP events on the serving stream, so that the average launch agrees with a kernel trace
+    # of the whole command.
     main.set_profiling(True)
-    walls, res = [], None
     prof = dict(stencil_ms=0.0, stencil_bytes=0.0, launches=0)
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        res, wall, srv = serve(B, main, side, reqs)
-        torch.cuda.synchronize()
+
+    def close(srv):
         p = srv.profile()
         for k in prof:
             prof[k] += p[k]
         srv.close()
+
+    # warmup: the first requests through a server (untimed)
+    for _ in range(args.warmup):
+        close(serve(B, main, side, reqs[:32])[2])
+
+    # timed: the whole stream, closed loop
+    walls, res = [], None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        res, wall, srv = serve(B, main, side, reqs)
+        torch.cuda.synchronize()
+        close(srv)
         walls.append(wall)
-    main.set_profiling(False)
     value = N_REQ / float(np.mean(walls))
     codes = sorted({r["code"] for r in res.values()})
     log(f"closed loop: {value:.2f} solves/s")
@@ -127,7 +155,8 @@ def bench_serving(args, B, torch):
     rate = OPEN_LOOP_LOAD * value
     arr = unit_arr / rate
     res_open, wall_open, srv = serve(B, main, side, reqs, arr)
-    srv.close()
+    close(srv)
+    main.set_profiling(False)
     lat_open = [res_open[i]["latency_s"] for i in range(N_REQ)]
     log(f"open loop at {rate:.2f}/s done")
 
@@ -166,11 +195,13 @@ def bench_serving(args, B, torch):
     log("precision comparison done")
     achieved = prof["stencil_bytes"] / (prof["stencil_ms"] * 1e-3) / 1e9 if prof["stencil_ms"] > 0 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": counter_traffic("kb_iter<float>", prof["stencil_bytes"] / max(prof["launches"], 1)),
                 "kernel": "kb_iter<float> (batched FP32 CG iteration)",
                 "bytes_per_launch": round(prof["stencil_bytes"] / max(prof["launches"], 1)),
                 "avg_launch_ms": round(prof["stencil_ms"] / max(prof["launches"], 1), 5),
-                "launches_timed": prof["launches"]}
+                "launches_timed": prof["launches"],
+                "scope": "every batched iteration launch of the run (warm-up, closed loop, open loop)"}
 
     cpu = None
     if not args.no_cpu:
@@ -234,7 +265,82 @@ def workload(name: str):
         return I.protein_c2() + ("synthetic 2000-atom molecule in a 20A ball, 161^3 nodes, h=0.5A",)
     if name == "c4":
         return I.large_c4() + ("synthetic 60000-atom molecule in a 65A ball, 385^3 nodes, h=0.5A",)
+    if name == "c3":
+        return I.refined_c3() + ("synthetic 20000-atom molecule in a 45A ball, 193^3 coarse nodes at h=1.0A, "
+                                 "refined to 0.5A within 3A of the surface (4^3-cell bricks)",)
     raise SystemExit(f"unknown workload {name}")
+
+
+# algorithmic bytes per grid node (coarse and fine arrays, FP64) of one composite CG iteration
+# on a refined problem: apply (K x3 and the lumped term, role, p; q), dot (role, p, q),
+# update (role, x, r rw; p, q, D^-1; z), direction (role, z, p rw)
+REFINED_ITER_BYTES = 49 + 17 + 65 + 25
+
+
+def bench_refined(args, B, torch):
+    ctx = B.Context(0)
+    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)
+    mol, grid, desc = workload("c3")
+    g = replace(grid, rtol=RTOL, precision=I.FP64)
+    lat, res = [], []
+    for s in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb = B.Problem(ctx, mol, g)
+        t1 = time.perf_counter()
+        st = pb.solve()
+        en = pb.energy()
+        info = pb.refine_info()
+        pb.close()
+        torch.cuda.synchronize()
+        if s >= args.warmup:
+            lat.append(time.perf_counter() - t0)
+            res.append((st, en, info, t1 - t0))
+    st, en, info, t_build = res[-1]
+    nunk = info["unknowns_coarse"] + info["unknowns_fine"]
+    t_solve = float(np.mean([r[0]["t_solve_s"] for r in res]))
+    iters = float(np.mean([r[0]["iters"] for r in res]))
+    nc = np.prod([int(v) for v in grid.n])
+    nf = np.prod(info["fine_n"])
+    nodes = float(nc + nf)
+    t_iter = t_solve / max(iters, 1.0)
+    ach = nodes * REFINED_ITER_BYTES / t_iter / 1e9
+    out = {
+        "metric": METRIC, "value": round(len(lat) / sum(lat), 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * float(np.mean(lat)), 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "n_atoms": mol.n, "rtol": RTOL, "unknowns": int(nunk),
+                   "refined_cells": int(info["refined_cells"]), "hanging_nodes": int(info["hanging_nodes"]),
+                   "fine_lattice": list(info["fine_n"])},
+        "iters": iters, "t_solve_ms": round(1e3 * t_solve, 2), "t_build_ms": round(1e3 * t_build, 2),
+        "pcg_gnode_iter_per_s": {"fp64": round(nunk * iters / t_solve / 1e9, 3)},
+        "energies_kT": {k: en[k] for k in ("e_pol", "e_ion", "e_coul")},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "composite CG iteration (all kernels of one iteration)",
+                     "bytes_per_launch": round(nodes * REFINED_ITER_BYTES), "avg_launch_ms": round(1e3 * t_iter, 4)},
+        "stream_copy_GBs": round(copy_gbs, 1),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import oracle as O
+        from oracle import refined as R
+
+        # the oracle's refined path on a reduced molecule and grid of the same recipe
+        mol_s = I.random_molecule(1500, 18.0, 2503)
+        g_s = I.cubic_grid(65, 1.0, refine=1, refine_shell=3.0, refine_brick=4)
+        t0 = time.perf_counter()
+        run_o = R.refined_run(mol_s, g_s, delta=3.0, brick=4, rtol=RTOL)
+        dt = time.perf_counter() - t0
+        rate = run_o.free.size * run_o.iters / run_o.times["solve"] / 1e9
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": O.num_threads(),
+                               "kind": "oracle",
+                               "gnode_iter_per_s": round(rate, 5),
+                               "sample": f"the refined-grid oracle on a reduced case of the same recipe (1500 atoms in "
+                                         f"an 18 A ball, 65^3 coarse nodes at 1.0 A, {run_o.free.size} unknowns): "
+                                         f"{dt:.1f} s, {run_o.iters} CG iterations"}
+    ctx.close()
+    return out
 
 
 def bench_single(args, B, torch):
@@ -282,7 +388,9 @@ def bench_single(args, B, torch):
         "fp64_plain": {"solves_per_s": round(p64["solves_per_s"], 3), "p50_ms": round(p64["p50"], 3),
                        "p99_ms": round(p64["p99"], 3), "energy_relerr_vs_fp64": p64["err"]},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_cg_iter<float>",
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic("k_cg_iter<float>", nu * ITER_BYTES_FP32),
+                     "kernel": "k_cg_iter<float>",
                      "bytes_per_launch": nu * ITER_BYTES_FP32, "avg_launch_ms": round(mx["stencil_ms"], 5)},
         "stream_copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": None,
@@ -305,12 +413,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); how the solve would shard "
-              "over several GPUs is described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): running the solver over "
+              "several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -319,7 +427,12 @@ def main():
 
     B.load()
     torch.cuda.set_device(0)
-    out = bench_serving(args, B, torch) if args.workload == "c5" else bench_single(args, B, torch)
+    if args.workload == "c5":
+        out = bench_serving(args, B, torch)
+    elif args.workload == "c3":
+        out = bench_refined(args, B, torch)
+    else:
+        out = bench_single(args, B, torch)
     print(json.dumps(out))
 
 
