@@ -88,9 +88,9 @@ def stream(n):
     return [(m, g) for _, m, g in reqs], unit_arrivals
 
 
-def serve(B, main, side, reqs, arrivals=None):
+def serve(B, main, side, reqs, arrivals=None, max_resident=MAX_RESIDENT):
     """Run requests through a fresh server; returns (results by id, wall seconds, server)."""
-    srv = B.Server(main, side, max_resident=MAX_RESIDENT)
+    srv = B.Server(main, side, max_resident=max_resident)
     t0 = srv.now()
     for i, (mol, g) in enumerate(reqs):
         srv.submit(mol, g, i, t0 if arrivals is None else t0 + float(arrivals[i]))
@@ -137,13 +137,13 @@ def bench_serving(args, B, torch):
 
     # warmup: the first requests through a server (untimed)
     for _ in range(args.warmup):
-        close(serve(B, main, side, reqs[:32])[2])
+        close(serve(B, main, side, reqs[:32], max_resident=args.max_resident)[2])
 
     # timed: the whole stream, closed loop
     walls, res = [], None
     for _ in range(args.steps):
         torch.cuda.synchronize()
-        res, wall, srv = serve(B, main, side, reqs)
+        res, wall, srv = serve(B, main, side, reqs, max_resident=args.max_resident)
         torch.cuda.synchronize()
         close(srv)
         walls.append(wall)
@@ -154,7 +154,7 @@ def bench_serving(args, B, torch):
     # open loop: Poisson arrivals at OPEN_LOOP_LOAD x the closed-loop rate
     rate = OPEN_LOOP_LOAD * value
     arr = unit_arr / rate
-    res_open, wall_open, srv = serve(B, main, side, reqs, arr)
+    res_open, wall_open, srv = serve(B, main, side, reqs, arr, max_resident=args.max_resident)
     close(srv)
     main.set_profiling(False)
     lat_open = [res_open[i]["latency_s"] for i in range(N_REQ)]
@@ -216,7 +216,7 @@ def bench_serving(args, B, torch):
         "config": {"workload": f"serving stream: {N_REQ} synthetic molecules (200-20000 atoms, log-uniform), "
                                f"grids 65^3-257^3, h in {{0.5,0.75,1.0}} A, mixed precision",
                    "n_requests": N_REQ, "seed": SEED, "rtol": RTOL, "reliable_update_factor": DELTA,
-                   "max_resident": MAX_RESIDENT, "unknowns_total": float(nu.sum()),
+                   "max_resident": args.max_resident, "unknowns_total": float(nu.sum()),
                    "atoms_total": int(sum(m.n for m, _ in reqs))},
         "served_closed_loop": {"solves_per_s": round(value, 3), "p50_s": round(pct(lat_closed, 50), 3),
                                "p99_s": round(pct(lat_closed, 99), 3), "codes": codes},
@@ -415,6 +415,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--max-resident", type=int, default=MAX_RESIDENT,
+                    help="serving stream: problems resident at once")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): running the solver over "

@@ -83,7 +83,9 @@ typedef struct {
     const double* bc_values;/* PB_BC_USER: host array over the full grid; only box-face
                                entries are read.  Ignored otherwise. */
     int32_t precision;      /* PB_FP64, or PB_MIXED: FP32 coefficients, vectors and CG with
-                               FP64 reliable updates (true residual, solution accumulation) */
+                               FP64 reliable updates (true residual, solution accumulation);
+                               the Debye-Hueckel box values then use FP32 exponentials and
+                               inverse distances with FP64 sums */
     double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64 path: CG
                                recursive residual; mixed: the FP64 true residual) */
     double inner_rtol;      /* PB_MIXED: reliable-update factor: the FP32 recursive residual

@@ -723,7 +723,10 @@ int pbi_build_continue(pb_problem* pb)
     HIPCHK(launch_fill(s, pb->gb, sizeof(double) * N));
     HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
     if (prm->bc == PB_BC_DH && pb->na > 0) {
-        HIPCHK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
+        if (prm->precision == PB_MIXED)
+            HIPCHK(launch_bc_dh32(s, g, at, pb->kD, prm->eps_out, pb->gb));
+        else
+            HIPCHK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
     } else if (prm->bc == PB_BC_USER) {
         HIPCHK(launch_bc_user(s, g, T.full, pb->gb));
     }

@@ -434,6 +434,45 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, doub
     if (act) gb[g.idx(i, j, k)] = s;
 }
 
+// The same sum for the mixed-precision form: distances from FP64 coordinate differences,
+// then the exponential and the inverse distance in FP32 (a few units in the last place,
+// about 1e-7 relative per term), accumulated in FP64.  The box is tens of Angstrom from the
+// surface, so these errors reach the surface potential screened by exp(-kD d) and stay far
+// below the FP32 iteration's own rounding.
+__global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, double eps_out, double* gb)
+{
+    __shared__ double sa[256 * 4];
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool act = t < n_box(g);
+    int i = 0, j = 0, k = 0;
+    if (act) box_node(g, t, i, j, k);
+    const double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
+    double s = 0.0;
+    for (int base = 0; base < at.n; base += 256) {
+        int a = base + threadIdx.x;
+        __syncthreads();
+        if (a < at.n) {
+            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
+            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
+            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
+            sa[4 * threadIdx.x + 3] = at.q[a];
+        }
+        __syncthreads();
+        int m = at.n - base < 256 ? at.n - base : 256;
+        if (act)
+            for (int u = 0; u < m; ++u) {
+                const float dx = (float)(p[0] - sa[4 * u]), dy = (float)(p[1] - sa[4 * u + 1]),
+                            dz = (float)(p[2] - sa[4 * u + 2]);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float ri = __frsqrt_rn(r2);
+                const float e = exp2f(mk * (r2 * ri));
+                s += (double)((float)sa[4 * u + 3] * e * ri);
+            }
+    }
+    if (act) gb[g.idx(i, j, k)] = s / eps_out;
+}
+
 __global__ void __launch_bounds__(256) k_bc_user(Grid g, const double* full, double* gb)
 {
     int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -755,6 +794,13 @@ hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD
 {
     int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
     k_bc_dh<<<nblk(nbx, 256), 256, 0, s>>>(g, at, kD, eps_out, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb)
+{
+    int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
+    k_bc_dh32<<<nblk(nbx, 256), 256, 0, s>>>(g, at, kD, eps_out, gb);
     return hipGetLastError();
 }
 

@@ -116,6 +116,7 @@ hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const At
 hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* rhs);
 hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
                         double* gb);
+hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb);
 hipError_t launch_bc_user(hipStream_t s, const Grid& g, const double* full, double* gb);
 hipError_t launch_diag_lift(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
                             Coef c, const double* gb, double* rhs, float* dinv, double* diag);
