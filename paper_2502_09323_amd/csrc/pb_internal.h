@@ -92,7 +92,7 @@ struct TileShape {     // tiling of the interior for the stencil kernel
 };
 
 #ifndef PB_TILE_WAVES
-#define PB_TILE_WAVES 8
+#define PB_TILE_WAVES 4
 #endif
 constexpr int ZW = 32;              // z-extent of a tile of the iteration kernel (lanes per row)
 constexpr int NWV = PB_TILE_WAVES;  // waves per block of the iteration kernel, two rows each

@@ -312,10 +312,12 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
         // the stores need no branch
         const bool ok = valid && i < ie;
         const uint32_t e = eo + (uint32_t)(i < ie ? i : g.nx - 1) * sx;
-        at(z_n, e) = ok ? zv : (T)0;
-        at(w_n, e) = ok ? wq : (T)0;
-        at(p_n, e) = ok ? p0 : (T)0;
-        at(x, e) = ok ? xv : (T)0;
+        // streaming stores: the new vectors are read again only in the next iteration,
+        // after the whole grid has passed through the caches
+        __builtin_nontemporal_store(ok ? zv : (T)0, &at(z_n, e));
+        __builtin_nontemporal_store(ok ? wq : (T)0, &at(w_n, e));
+        __builtin_nontemporal_store(ok ? p0 : (T)0, &at(p_n, e));
+        __builtin_nontemporal_store(ok ? xv : (T)0, &at(x, e));
         const double dD = ok ? (double)D : 0.0;
         const double dz = (double)zv, dw = (double)wq, dq = (double)qv, dzD = dD * dz, dwD = dD * dw;
         acc[0] += ok ? (double)p0 * dq : 0.0;
@@ -724,7 +726,7 @@ TileShape make_tiles(const Grid& g, int planes)
     if (lx <= 0) {
         // chunk length along x: every chunk re-reads the planes next to it, so chunks stay
         // long; they are shortened (down to 8 planes) while the grid would give fewer than
-        // 2048 tiles, so that the 256 CUs have several 8-wave blocks each
+        // 2048 tiles, so that the 256 CUs have several blocks each
         lx = 32;
         while (lx > 8 && (long)tiles * ((g.nx - 2 + lx - 1) / lx) < 2048) lx >>= 1;
     }
