@@ -333,6 +333,7 @@ int launch_chunk(pb_server* s, int k)
     for (int p = 0; p < P; ++p) {
         const ProbDev<float> d = pbi_probdev(mem[p]->pb);
         s->hdesc[k][p] = d;
+        t.st = (t.st + 7) & ~7;   // block b of each problem on XCD b % 8, as in a solo launch
         o[p] = t.st;
         o[(P + 1) + p] = t.add;
         o[2 * (P + 1) + p] = t.res;

@@ -171,12 +171,12 @@ __device__ __forceinline__ void iter_body(const Grid& g, const TileShape& ts, co
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int kl = lane & (ZW - 1), row = 2 * wv + (lane >> 5);
 
-    const T* __restrict__ z_o = B.z[od];
-    const T* __restrict__ w_o = B.w[od];
-    const T* __restrict__ p_o = B.p[od];
-    T* __restrict__ z_n = B.z[nw];
-    T* __restrict__ w_n = B.w[nw];
-    T* __restrict__ p_n = B.p[nw];
+    const T* __restrict__ z_o = od ? B.z[1] : B.z[0];
+    const T* __restrict__ w_o = od ? B.w[1] : B.w[0];
+    const T* __restrict__ p_o = od ? B.p[1] : B.p[0];
+    T* __restrict__ z_n = nw ? B.z[1] : B.z[0];
+    T* __restrict__ w_n = nw ? B.w[1] : B.w[0];
+    T* __restrict__ p_n = nw ? B.p[1] : B.p[0];
     T* __restrict__ x = B.x;
     const uint32_t* __restrict__ code = B.code;
     const T* __restrict__ ck = B.ck;
@@ -633,7 +633,7 @@ __global__ void __launch_bounds__(256) k_stream_copy(const f4v* __restrict__ a, 
 // ---- batched launches: one launch advances every resident problem ---------------------------
 // Block b of a batched launch belongs to the problem p with off[p] <= b < off[p+1] and acts as
 // block b - off[p] of that problem's own launch, so each problem computes exactly what it
-// computes when solved alone.
+// computes when solved alone.  In the iteration launch off[p] is a multiple of 8.
 
 __device__ __forceinline__ int find_prob(const int* __restrict__ off, int P, int b)
 {
@@ -650,8 +650,12 @@ template <typename T>
 __global__ void __launch_bounds__(64 * NWV) kb_iter(const ProbDev<T>* __restrict__ D, const int* __restrict__ off, int P)
 {
     const int p = __builtin_amdgcn_readfirstlane(find_prob(off, P, (int)blockIdx.x));
-    const ProbDev<T>& d = D[p];
-    iter_body(d.g, d.ts, d.B, d.cf, (int)blockIdx.x - off[p]);
+    const ProbDev<T> d = D[p];   // a uniform copy (scalar registers)
+    // each problem's range starts at a multiple of 8, so its block b runs on XCD b % 8 as in
+    // its own launch; the blocks that pad a range to the next multiple of 8 do nothing
+    const int bid = (int)blockIdx.x - off[p];
+    if (bid >= d.ts.items) return;
+    iter_body(d.g, d.ts, d.B, d.cf, bid);
 }
 
 __global__ void __launch_bounds__(256) kb_tail(const ProbDev<float>* __restrict__ D)
