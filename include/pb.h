@@ -107,8 +107,11 @@ typedef struct {
                                fine cells that lie on a face or edge of an unrefined cell are
                                hanging: they take the mean of the 2 or 4 coarse nodes of that
                                edge or face (P), and the operator is P^T K P over cell-wise
-                               assembled K.  Needs PB_FP64, at least one atom, and refined
-                               cells away from the box faces (PB_EINVAL otherwise). */
+                               assembled K.  Solved by Jacobi-CG over the unknowns of both
+                               grids, in FP64 or, with PB_MIXED, in FP32 with FP64 reliable
+                               updates (the refined-grid solution and energies are FP64 in
+                               both).  Needs at least one atom and refined cells away from
+                               the box faces (PB_EINVAL otherwise). */
     double refine_shell_A;  /* refine: distance in Angstrom (e.g. 3.0) */
     int32_t refine_brick;   /* refine: brick edge in coarse cells, 1..64 (e.g. 4) */
 } pb_params;

@@ -100,7 +100,6 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (p->refine) {
         if (!finite(p->refine_shell_A) || p->refine_shell_A < 0) return fail(PB_EINVAL, "refine_shell_A must be >= 0");
         if (p->refine_brick < 1 || p->refine_brick > 64) return fail(PB_EINVAL, "refine_brick must be in [1, 64]");
-        if (p->precision != PB_FP64) return fail(PB_EINVAL, "a refined problem is solved in FP64");
         if (na <= 0) return fail(PB_EINVAL, "refinement needs atoms");
     }
     if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
@@ -791,7 +790,9 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     if (pb->ref) {
         if ((rc = pbi_refine_solve(pb, &st))) return rc;
         stats->iters = st.status == 1 ? st.iters : st.iter_count;
-        stats->relres = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
+        const double rr = P.precision == PB_MIXED ? st.rr64 : st.rr;
+        stats->relres = st.bnorm2 > 0 ? std::sqrt(rr / st.bnorm2) : 0.0;
+        stats->outer_iters = P.precision == PB_MIXED ? st.n_ru : 0;
         status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
         stats->status = status;
         stats->t_solve_s = now_s() - t0;

@@ -91,7 +91,12 @@ struct RefineData {
     double* rw = nullptr;
     double *bc = nullptr, *rc = nullptr, *zc = nullptr, *pc = nullptr, *qc = nullptr, *dc = nullptr;
     double *bf = nullptr, *rf = nullptr, *zf = nullptr, *pf = nullptr, *qf = nullptr, *df = nullptr;
-    double* part = nullptr;
+    // mixed precision: FP32 copies of K and D^-1 and the FP32 solver vectors (x: correction);
+    // the FP64 r and q above then hold the true residual and the FP64 product
+    float *Kc32 = nullptr, *Kf32 = nullptr;
+    float *xc32 = nullptr, *rc32 = nullptr, *zc32 = nullptr, *pc32 = nullptr, *qc32 = nullptr, *dc32 = nullptr;
+    float *xf32 = nullptr, *rf32 = nullptr, *zf32 = nullptr, *pf32 = nullptr, *qf32 = nullptr, *df32 = nullptr;
+    double* part = nullptr;       // [3 * (nbc + nbf)] block partial sums
     int nbc = 0, nbf = 0;
     int64_t nunk_c = 0, nunk_f = 0, nhang = 0;
 };

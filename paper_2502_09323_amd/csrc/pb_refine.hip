@@ -304,46 +304,49 @@ __global__ void __launch_bounds__(256) k_lift(Grid g, const double* __restrict__
 // ---- operator and CG ---------------------------------------------------------------------
 
 // derived fine values from the coarse ones
+template <typename T>
 __global__ void __launch_bounds__(256) k_fill(int64_t ng, const int64_t* __restrict__ gfine,
                                               const int64_t* __restrict__ gpar, const int32_t* __restrict__ gnp,
-                                              const double* __restrict__ vc, double* __restrict__ vf)
+                                              const T* __restrict__ vc, T* __restrict__ vf, const CGState* st)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= ng) return;
+    if (t >= ng || (st && st->status != 0)) return;
     const int np = gnp[t];
-    double s = 0.0;
+    T s = (T)0;
     for (int u = 0; u < np; ++u) s += vc[gpar[4 * t + u]];
-    vf[gfine[t]] = s / (double)np;
+    vf[gfine[t]] = s / (T)np;
 }
 
 // q = (cell contributions of this grid) p at every node with a role; 0 elsewhere
-__global__ void __launch_bounds__(256) k_apply(Grid g, const double* __restrict__ K, const uint8_t* __restrict__ role,
-                                               const double* __restrict__ p, double* __restrict__ q)
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply(Grid g, const T* __restrict__ K, const uint8_t* __restrict__ role,
+                                               const T* __restrict__ p, T* __restrict__ q, const CGState* st)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= g.N) return;
+    if (e >= g.N || (st && st->status != 0)) return;
     if (!role[e]) {
-        q[e] = 0.0;
+        q[e] = (T)0;
         return;
     }
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    const double kxp = K[e], kxm = K[e - sx], kyp = K[g.N + e], kym = K[g.N + e - sy];
-    const double kzp = K[2 * g.N + e], kzm = K[2 * g.N + e - 1];
-    const double D = ((kxp + kxm) + (kyp + kym)) + ((kzp + kzm) + K[3 * g.N + e]);
+    const T kxp = K[e], kxm = K[e - sx], kyp = K[g.N + e], kym = K[g.N + e - sy];
+    const T kzp = K[2 * g.N + e], kzm = K[2 * g.N + e - 1];
+    const T D = ((kxp + kxm) + (kyp + kym)) + ((kzp + kzm) + K[3 * g.N + e]);
     q[e] = D * p[e] - (((kxm * p[e - sx] + kxp * p[e + sx]) + (kym * p[e - sy] + kyp * p[e + sy])) +
                        (kzm * p[e - 1] + kzp * p[e + 1]));
 }
 
 // the rows of the derived fine nodes go to their coarse nodes (one thread per coarse node)
+template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(int64_t nr, const int64_t* __restrict__ rnode,
                                                   const int64_t* __restrict__ rptr, const int64_t* __restrict__ rsrc,
                                                   const double* __restrict__ rw, const int64_t* __restrict__ gfine,
-                                                  const double* __restrict__ vf, double* __restrict__ vc)
+                                                  const T* __restrict__ vf, T* __restrict__ vc, const CGState* st)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= nr) return;
-    double s = 0.0;
-    for (int64_t u = rptr[t]; u < rptr[t + 1]; ++u) s += rw[u] * vf[gfine[rsrc[u]]];
+    if (t >= nr || (st && st->status != 0)) return;
+    T s = (T)0;
+    for (int64_t u = rptr[t]; u < rptr[t + 1]; ++u) s += (T)rw[u] * vf[gfine[rsrc[u]]];
     vc[rnode[t]] += s;
 }
 
@@ -359,23 +362,32 @@ __device__ __forceinline__ void bsum(double* v, int nv, double* sh)
     for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
 }
 
-// partial sums of a.b over the unknowns of both grids: blocks [0, nbc) coarse, then fine
-__global__ void __launch_bounds__(256) k_dot(int64_t Nc, int64_t Nf, int nbc, const uint8_t* rc, const uint8_t* rf,
-                                             const double* ac, const double* bc, const double* af, const double* bf,
+// The vector kernels run over both grids in one launch: blocks [0, nbc) take the coarse
+// grid, the others the fine sub-lattice.
+struct Split {
+    int64_t Nc, Nf;
+    int nbc;
+    const uint8_t *rc, *rf;
+    __device__ bool coarse() const { return (int)blockIdx.x < nbc; }
+    __device__ int64_t first() const { return (coarse() ? blockIdx.x : blockIdx.x - nbc) * (int64_t)256 + threadIdx.x; }
+    __device__ int64_t stride() const { return (coarse() ? nbc : (int64_t)gridDim.x - nbc) * (int64_t)256; }
+    __device__ int64_t n() const { return coarse() ? Nc : Nf; }
+    __device__ const uint8_t* role() const { return coarse() ? rc : rf; }
+};
+
+// partial sums of a.b over the unknowns of both grids
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot(Split sp, const T* ac, const T* bc, const T* af, const T* bf,
                                              double* part, const CGState* st)
 {
     __shared__ double sh[8];
     if (st->status != 0) return;
-    const bool coarse = (int)blockIdx.x < nbc;
-    const int64_t b0 = coarse ? blockIdx.x : blockIdx.x - nbc;
-    const int64_t nblocks = coarse ? nbc : (int64_t)gridDim.x - nbc;
-    const int64_t N = coarse ? Nc : Nf;
-    const uint8_t* role = coarse ? rc : rf;
-    const double* a = coarse ? ac : af;
-    const double* b = coarse ? bc : bf;
+    const uint8_t* role = sp.role();
+    const T* a = sp.coarse() ? ac : af;
+    const T* b = sp.coarse() ? bc : bf;
     double v[1] = {0.0};
-    for (int64_t e = b0 * 256 + threadIdx.x; e < N; e += nblocks * 256)
-        if (role[e] == 1) v[0] += a[e] * b[e];
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
+        if (role[e] == 1) v[0] += (double)a[e] * (double)b[e];
     bsum(v, 1, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -400,36 +412,32 @@ __global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGSta
 }
 
 // x += alpha p, r -= alpha q, z = D^-1 r; partial sums of r.z and r.r
-__global__ void __launch_bounds__(256) k_update(int64_t Nc, int64_t Nf, int nbc, const uint8_t* rc, const uint8_t* rf,
-                                                double* xc, double* rrc, double* zc, const double* pc, const double* qc,
-                                                const double* dc, double* xf, double* rrf, double* zf, const double* pf,
-                                                const double* qf, const double* df, double* part, int nb,
-                                                const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_update(Split sp, T* xc, T* rrc, T* zc, const T* pc, const T* qc, const T* dc,
+                                                T* xf, T* rrf, T* zf, const T* pf, const T* qf, const T* df,
+                                                double* part, int nb, const CGState* st)
 {
     __shared__ double sh[8];
     if (st->status != 0) return;
-    const bool coarse = (int)blockIdx.x < nbc;
-    const int64_t b0 = coarse ? blockIdx.x : blockIdx.x - nbc;
-    const int64_t nblocks = coarse ? nbc : (int64_t)gridDim.x - nbc;
-    const int64_t N = coarse ? Nc : Nf;
-    const uint8_t* role = coarse ? rc : rf;
-    double* x = coarse ? xc : xf;
-    double* r = coarse ? rrc : rrf;
-    double* z = coarse ? zc : zf;
-    const double* p = coarse ? pc : pf;
-    const double* q = coarse ? qc : qf;
-    const double* d = coarse ? dc : df;
-    const double a = st->alpha;
+    const bool coarse = sp.coarse();
+    const uint8_t* role = sp.role();
+    T* x = coarse ? xc : xf;
+    T* r = coarse ? rrc : rrf;
+    T* z = coarse ? zc : zf;
+    const T* p = coarse ? pc : pf;
+    const T* q = coarse ? qc : qf;
+    const T* d = coarse ? dc : df;
+    const T a = (T)st->alpha;
     double v[2] = {0.0, 0.0};
-    for (int64_t e = b0 * 256 + threadIdx.x; e < N; e += nblocks * 256) {
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride()) {
         if (role[e] != 1) continue;
         x[e] += a * p[e];
-        const double rv = r[e] - a * q[e];
+        const T rv = r[e] - a * q[e];
         r[e] = rv;
-        const double zv = d[e] * rv;
+        const T zv = d[e] * rv;
         z[e] = zv;
-        v[0] += rv * zv;
-        v[1] += rv * rv;
+        v[0] += (double)rv * (double)zv;
+        v[1] += (double)rv * (double)rv;
     }
     bsum(v, 2, sh);
     if (threadIdx.x == 0) {
@@ -438,11 +446,14 @@ __global__ void __launch_bounds__(256) k_update(int64_t Nc, int64_t Nf, int nbc,
     }
 }
 
-// beta = r.z / r.z_old, convergence test; init: the first residual (no beta)
-__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int init, double rtol2)
+// beta = r.z / r.z_old and the stop test: status = stop_status once r.r falls to stop2 (the
+// FP64 solve's goal; in mixed precision the FP32 goal) or to trig2 (mixed precision: the
+// point at which the true residual is computed again); with mode 1 the first residual sets
+// the reference norm (no beta)
+__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode, double rtol2)
 {
     __shared__ double sh[8];
-    if (st->status != 0) return;
+    if (mode == 0 && st->status != 0) return;
     double v[2] = {0.0, 0.0};
     for (int t = threadIdx.x; t < nb; t += 256) {
         v[0] += part[t];
@@ -451,34 +462,163 @@ __global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGStat
     bsum(v, 2, sh);
     if (threadIdx.x == 0) {
         const double gm = v[0], rr = v[1];
-        if (init) {
+        if (mode == 1) {          // init
             st->bnorm2 = rr;
             st->stop2 = rtol2 * rr;
             st->iter_count = 0;
             st->beta = 0.0;
-        } else {
+        } else if (mode == 0) {   // an iteration
             st->iter_count += 1;
             st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
         }
+        st->status = 0;
         st->gamma = gm;
         st->rr = rr;
         if (!isfinite(gm) || !isfinite(rr)) {
             st->status = 2;
             st->iters = st->iter_count;
-        } else if (rr <= st->stop2) {
-            st->status = 1;
+        } else if (rr <= st->stop2 || rr <= st->trig2) {
+            st->status = st->stop_status;
             st->iters = st->iter_count;
         }
     }
 }
 
 // p = z + beta p over the unknowns of one grid (init: beta = 0)
-__global__ void __launch_bounds__(256) k_pupd(int64_t N, const uint8_t* role, const double* z, double* p,
-                                              const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_pupd(int64_t N, const uint8_t* role, const T* z, T* p, const CGState* st)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= N || st->status != 0) return;
-    p[e] = role[e] == 1 ? z[e] + st->beta * p[e] : 0.0;
+    p[e] = role[e] == 1 ? z[e] + (T)st->beta * p[e] : (T)0;
+}
+
+// ---- mixed precision: reliable updates ------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) b[e] = (float)a[e];
+}
+
+// x64 += x32, x32 = 0 over both grids
+__global__ void __launch_bounds__(256) k_fold(Split sp, double* xc, float* dc, double* xf, float* df)
+{
+    double* x = sp.coarse() ? xc : xf;
+    float* d = sp.coarse() ? dc : df;
+    const uint8_t* role = sp.role();
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
+        if (role[e] == 1) {
+            x[e] += (double)d[e];
+            d[e] = 0.0f;
+        }
+}
+
+// r64 = b - q64 on the unknowns (q64 = A x64 with the FP64 operator); partial sums of r.r
+__global__ void __launch_bounds__(256) k_true_res(Split sp, const double* bc, const double* qc, double* rc,
+                                                  const double* bf, const double* qf, double* rf, double* part)
+{
+    __shared__ double sh[8];
+    const bool coarse = sp.coarse();
+    const uint8_t* role = sp.role();
+    const double* b = coarse ? bc : bf;
+    const double* q = coarse ? qc : qf;
+    double* r = coarse ? rc : rf;
+    double v[1] = {0.0};
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride()) {
+        const double rv = role[e] == 1 ? b[e] - q[e] : 0.0;
+        r[e] = rv;
+        v[0] += rv * rv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_to(const double* part, int nb, double* out)
+{
+    __shared__ double sh[8];
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[t];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) *out = v[0];
+}
+
+// r32 = r64, z32 = D^-1 r32; partial sums of r.z and r.r
+__global__ void __launch_bounds__(256) k_replace(Split sp, const double* r64c, float* rc, float* zc, const float* dc,
+                                                 const double* r64f, float* rf, float* zf, const float* df,
+                                                 double* part, int nb)
+{
+    __shared__ double sh[8];
+    const bool coarse = sp.coarse();
+    const uint8_t* role = sp.role();
+    const double* r64 = coarse ? r64c : r64f;
+    float* r = coarse ? rc : rf;
+    float* z = coarse ? zc : zf;
+    const float* d = coarse ? dc : df;
+    double v[2] = {0.0, 0.0};
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride()) {
+        const float rv = role[e] == 1 ? (float)r64[e] : 0.0f;
+        const float zv = d[e] * rv;
+        r[e] = rv;
+        z[e] = zv;
+        v[0] += (double)rv * (double)zv;
+        v[1] += (double)rv * (double)rv;
+    }
+    bsum(v, 2, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[nb + blockIdx.x] = v[1];
+    }
+}
+
+// after a residual replacement: part holds [r.z | r.r] of the FP32 residual and, after them,
+// the FP64 r.r; the FP64 norm decides convergence.  With init the first replacement (x = 0,
+// r = b) sets the goals.  A replacement follows a step whose direction update was skipped
+// (status 3 stops the launches after beta), so the next direction update takes beta from the
+// replaced residual.
+__global__ void __launch_bounds__(256) k_ru_fin(const double* part, int nb, CGState* st, int init, double rtol2,
+                                                double delta2)
+{
+    __shared__ double sh[12];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) {
+        v[0] += part[t];
+        v[1] += part[nb + t];
+        v[2] += part[2 * nb + t];
+    }
+    bsum(v, 3, sh);
+    if (threadIdx.x == 0) {
+        const double gm = v[0], rr = v[1], rr64 = v[2];
+        if (init) {
+            st->bnorm2 = rr64;
+            st->goal64 = rtol2 * rr64;
+            st->stop2 = rtol2 * rr;
+            st->delta2 = delta2;
+            st->stop_status = 3;
+            st->iter_count = 0;
+            st->n_ru = 0;
+            st->beta = 0.0;
+        } else {
+            // the direction continues from the replaced residual: its step was cut before
+            // p was updated, so beta = r'.z' over r.z of the step before (gamma / beta)
+            st->n_ru += 1;
+            st->beta = (st->gamma > 0.0 && st->beta > 0.0) ? gm * (st->beta / st->gamma) : 0.0;
+        }
+        st->alpha = 0.0;
+        st->gamma = gm;
+        st->rr = rr;
+        st->rr64 = rr64;
+        st->trig2 = st->delta2 * rr;
+        if (!isfinite(rr64) || !isfinite(gm)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else if (rr64 <= st->goal64) {
+            st->status = 1;
+            st->iters = st->iter_count;
+        } else {
+            st->status = 0;
+        }
+    }
 }
 
 __global__ void k_state_init(CGState* st)
@@ -758,13 +898,89 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
     RCHK(hipGetLastError());
     R->nbc = (int)std::min<int64_t>(1024, (int64_t)nblk(gc.N, 256));
     R->nbf = (int)std::min<int64_t>(1024, (int64_t)nblk(gf.N, 256));
-    R->part = (double*)pb->mem.get(sizeof(double) * 2 * (size_t)(R->nbc + R->nbf));
+    R->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)(R->nbc + R->nbf));
     if (!R->part) return pbi_fail(PB_ENOMEM, "refined partial sums");
+    if (P.precision == PB_MIXED) {
+        // FP32 operator and preconditioner, rounded once from the FP64 ones
+        R->Kc32 = (float*)pb->mem.get(sizeof(float) * 4 * Nc);
+        R->Kf32 = (float*)pb->mem.get(sizeof(float) * 4 * Nf);
+        if (!R->Kc32 || !R->Kf32) return pbi_fail(PB_ENOMEM, "refined FP32 coefficients");
+        float** wc[6] = {&R->xc32, &R->rc32, &R->zc32, &R->pc32, &R->qc32, &R->dc32};
+        float** wf[6] = {&R->xf32, &R->rf32, &R->zf32, &R->pf32, &R->qf32, &R->df32};
+        for (int v = 0; v < 6; ++v) {
+            *wc[v] = (float*)pb->mem.get(sizeof(float) * Nc);
+            *wf[v] = (float*)pb->mem.get(sizeof(float) * Nf);
+            if (!*wc[v] || !*wf[v]) return pbi_fail(PB_ENOMEM, "refined FP32 solver vectors");
+            RCHK(launch_fill(s, *wc[v], sizeof(float) * Nc));
+            RCHK(launch_fill(s, *wf[v], sizeof(float) * Nf));
+        }
+        k_to_f32<<<nblk(4 * gc.N, 256), 256, 0, s>>>(4 * gc.N, R->Kc, R->Kc32);
+        k_to_f32<<<nblk(4 * gf.N, 256), 256, 0, s>>>(4 * gf.N, R->Kf, R->Kf32);
+        k_to_f32<<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->dc, R->dc32);
+        k_to_f32<<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->df, R->df32);
+        RCHK(hipGetLastError());
+    }
     RCHK(hipStreamSynchronize(s));
     return PB_OK;
 }
 
-// composite Jacobi-CG; fills the derived fine values of the solution at the end
+namespace {
+
+// the solver vectors of one grid in one precision
+template <typename T>
+struct GridVecs {
+    T *x, *r, *z, *p, *q;
+    const T *d, *K;
+};
+
+// one composite CG iteration: q = P^T K P p, alpha, x and r, z = D^-1 r, beta, p
+template <typename T>
+void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, const Split& sp,
+                      const GridVecs<T>& c, const GridVecs<T>& f, CGState* st)
+{
+    const int nb = R->nbc + R->nbf;
+    if (R->ng) k_fill<T><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, c.p, f.p, st);
+    k_apply<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc, c.K, R->rolec, c.p, c.q, st);
+    k_apply<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf, f.K, R->rolef, f.p, f.q, st);
+    if (R->nr)
+        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, f.q, c.q,
+                                                       st);
+    k_dot<T><<<nb, 256, 0, s>>>(sp, c.p, c.q, f.p, f.q, R->part, st);
+    k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
+    k_update<T><<<nb, 256, 0, s>>>(sp, c.x, c.r, c.z, c.p, c.q, c.d, f.x, f.r, f.z, f.p, f.q, f.d, R->part, nb, st);
+    k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 0, 0.0);
+    k_pupd<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, c.z, c.p, st);
+    k_pupd<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->rolef, f.z, f.p, st);
+}
+
+// mixed precision: fold the FP32 correction into x, r = b - A x with the FP64 operator, and
+// restart the FP32 recurrence from it (the direction p is kept)
+void launch_reliable_update(hipStream_t s, pb_problem* pb, const Split& sp, int init, double rtol2, double delta2)
+{
+    RefineData* R = pb->ref;
+    pb_problem* fp = R->fine;
+    const Grid& gc = pb->g;
+    const Grid& gf = fp->g;
+    const int nb = R->nbc + R->nbf;
+    k_fold<<<nb, 256, 0, s>>>(sp, pb->x, R->xc32, fp->x, R->xf32);
+    if (R->ng)
+        k_fill<double><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, pb->x, fp->x, nullptr);
+    k_apply<double><<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, pb->x, R->qc, nullptr);
+    k_apply<double><<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, fp->x, R->qf, nullptr);
+    if (R->nr)
+        k_restrict<double><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, R->qf,
+                                                            R->qc, nullptr);
+    k_true_res<<<nb, 256, 0, s>>>(sp, R->bc, R->qc, R->rc, R->bf, R->qf, R->rf, R->part + 2 * nb);
+    k_replace<<<nb, 256, 0, s>>>(sp, R->rc, R->rc32, R->zc32, R->dc32, R->rf, R->rf32, R->zf32, R->df32, R->part, nb);
+    k_ru_fin<<<1, 256, 0, s>>>(R->part, nb, pb->st, init, rtol2, delta2);
+}
+
+}  // namespace
+
+// composite Jacobi-CG; fills the derived fine values of the solution at the end.  In mixed
+// precision the iterations run in FP32 on a correction to the FP64 solution, and a reliable
+// update (fold, FP64 true residual, restart) follows each time the FP32 residual norm falls by
+// inner_rtol or reaches the goal; the FP64 residual decides convergence.
 int pbi_refine_solve(pb_problem* pb, CGState* out)
 {
     RefineData* R = pb->ref;
@@ -773,57 +989,80 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
     const Grid& gf = fp->g;
     hipStream_t s = pb->ctx->stream;
     const pb_params& P = pb->prm;
+    const bool mixed = P.precision == PB_MIXED;
     const int nb = R->nbc + R->nbf;
     CGState* st = pb->st;
+    const Split sp{gc.N, gf.N, R->nbc, R->rolec, R->rolef};
     const unsigned bc = nblk(gc.N, 256), bfn = nblk(gf.N, 256);
-    // x = 0, r = b, z = D^-1 r, p = z
+    const GridVecs<double> c64{pb->x, R->rc, R->zc, R->pc, R->qc, R->dc, R->Kc};
+    const GridVecs<double> f64{fp->x, R->rf, R->zf, R->pf, R->qf, R->df, R->Kf};
+    const GridVecs<float> c32{R->xc32, R->rc32, R->zc32, R->pc32, R->qc32, R->dc32, R->Kc32};
+    const GridVecs<float> f32{R->xf32, R->rf32, R->zf32, R->pf32, R->qf32, R->df32, R->Kf32};
     RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)gc.N));
     RCHK(launch_fill(s, fp->x, sizeof(double) * (size_t)gf.N));
-    RCHK(hipMemcpyAsync(R->rc, R->bc, sizeof(double) * (size_t)gc.N, hipMemcpyDeviceToDevice, s));
-    RCHK(hipMemcpyAsync(R->rf, R->bf, sizeof(double) * (size_t)gf.N, hipMemcpyDeviceToDevice, s));
     k_state_init<<<1, 1, 0, s>>>(st);
-    // the first update with alpha = 0 and p = q = 0 leaves x, r and forms z and the norms
-    RCHK(launch_fill(s, R->pc, sizeof(double) * (size_t)gc.N));
-    RCHK(launch_fill(s, R->pf, sizeof(double) * (size_t)gf.N));
-    RCHK(launch_fill(s, R->qc, sizeof(double) * (size_t)gc.N));
-    RCHK(launch_fill(s, R->qf, sizeof(double) * (size_t)gf.N));
-    k_update<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, pb->x, R->rc, R->zc, R->pc, R->qc, R->dc, fp->x,
-                                R->rf, R->zf, R->pf, R->qf, R->df, R->part, nb, st);
-    k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 1, P.rtol * P.rtol);
-    k_pupd<<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
-    k_pupd<<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
+    if (mixed) {
+        // x32 = 0; r = b, z = D^-1 r from the first reliable update; p = z
+        RCHK(launch_fill(s, R->xc32, sizeof(float) * (size_t)gc.N));
+        RCHK(launch_fill(s, R->xf32, sizeof(float) * (size_t)gf.N));
+        launch_reliable_update(s, pb, sp, 1, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol);
+        k_pupd<float><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc32, R->pc32, st);
+        k_pupd<float><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf32, R->pf32, st);
+    } else {
+        // x = 0, r = b; the first update with alpha = 0 and p = q = 0 leaves x, r and forms z
+        // and the norms; p = z
+        RCHK(hipMemcpyAsync(R->rc, R->bc, sizeof(double) * (size_t)gc.N, hipMemcpyDeviceToDevice, s));
+        RCHK(hipMemcpyAsync(R->rf, R->bf, sizeof(double) * (size_t)gf.N, hipMemcpyDeviceToDevice, s));
+        RCHK(launch_fill(s, R->pc, sizeof(double) * (size_t)gc.N));
+        RCHK(launch_fill(s, R->pf, sizeof(double) * (size_t)gf.N));
+        RCHK(launch_fill(s, R->qc, sizeof(double) * (size_t)gc.N));
+        RCHK(launch_fill(s, R->qf, sizeof(double) * (size_t)gf.N));
+        k_update<double><<<nb, 256, 0, s>>>(sp, c64.x, c64.r, c64.z, c64.p, c64.q, c64.d, f64.x, f64.r, f64.z, f64.p,
+                                            f64.q, f64.d, R->part, nb, st);
+        k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 1, P.rtol * P.rtol);
+        k_pupd<double><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
+        k_pupd<double><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
+    }
     RCHK(hipGetLastError());
     const int M = 16;
     int launched = 0;
+    bool breakdown = false;
     CGState h;
-    for (;;) {
+    RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    while (h.status == 0 && launched < P.max_iter) {
         const int n = std::min(M, P.max_iter - launched);
         for (int it = 0; it < n; ++it) {
-            if (R->ng) k_fill<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, R->pc, R->pf);
-            k_apply<<<bc, 256, 0, s>>>(gc, R->Kc, R->rolec, R->pc, R->qc);
-            k_apply<<<bfn, 256, 0, s>>>(gf, R->Kf, R->rolef, R->pf, R->qf);
-            if (R->nr)
-                k_restrict<<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, R->qf,
-                                                            R->qc);
-            k_dot<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, R->pc, R->qc, R->pf, R->qf, R->part, st);
-            k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
-            k_update<<<nb, 256, 0, s>>>(gc.N, gf.N, R->nbc, R->rolec, R->rolef, pb->x, R->rc, R->zc, R->pc, R->qc, R->dc,
-                                        fp->x, R->rf, R->zf, R->pf, R->qf, R->df, R->part, nb, st);
-            k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 0, 0.0);
-            k_pupd<<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
-            k_pupd<<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
+            if (mixed)
+                launch_iteration<float>(s, R, gc, gf, sp, c32, f32, st);
+            else
+                launch_iteration<double>(s, R, gc, gf, sp, c64, f64, st);
         }
         RCHK(hipGetLastError());
         launched += n;
         RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
-        if (h.status != 0 || launched >= P.max_iter) break;
+        if (mixed && (h.status != 0 || launched >= P.max_iter)) {
+            // status 3: the FP32 residual reached its goal or fell by inner_rtol
+            breakdown = h.status == 2;
+            launch_reliable_update(s, pb, sp, 0, 0.0, 0.0);
+            if (!breakdown && launched < P.max_iter) {
+                k_pupd<float><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc32, R->pc32, st);
+                k_pupd<float><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf32, R->pf32, st);
+            }
+            RCHK(hipGetLastError());
+            RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+            RCHK(hipStreamSynchronize(s));
+            if (breakdown) break;
+        }
     }
     // derived fine values of the solution, and the coarse copies of the fine-owned nodes
-    if (R->ng) k_fill<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, pb->x, fp->x);
+    if (R->ng)
+        k_fill<double><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, pb->x, fp->x, nullptr);
     k_sync_coarse<<<bc, 256, 0, s>>>(gc, gf, R->rolec, pb->code, fp->x, pb->x);
     RCHK(hipGetLastError());
     RCHK(hipMemcpyAsync(out, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
+    if (breakdown && out->status != 1) out->status = 2;
     return PB_OK;
 }

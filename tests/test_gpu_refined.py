@@ -6,6 +6,7 @@ relative).  At the 193^3 / 20,000-atom size the flags are compared with the orac
 and the solve is checked against the discrete Gauss law.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -116,11 +117,56 @@ def test_refined_patch_test_on_gpu(ctx):
         pb.close()
 
 
+@pytest.mark.parametrize("name,mol,grid", _cases()[1:], ids=[c[0] for c in _cases()[1:]])
+def test_refined_mixed_parity(ctx, name, mol, grid):
+    """FP32 composite CG with FP64 reliable updates: the FP64 true residual reaches the same
+    goal, so energies and potentials agree with the FP64 oracle to 1e-6 (the Debye-Hueckel
+    box values are FP32-evaluated in this mode)."""
+    grid = replace(grid, precision=I.MIXED, rtol=1e-10, inner_rtol=1e-3)
+    ref = R.refined_run(mol, grid, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12)
+    pb = B.Problem(ctx, mol, grid)
+    try:
+        st = pb.solve()
+        assert st["status"] == 0 and st["relres"] <= 1e-10 and st["outer_iters"] >= 1
+        en = pb.energy()
+        for k in ("e_pol", "e_ion", "q_pol_total"):
+            assert abs(en[k] - ref.energy[k]) <= 1e-6 * abs(ref.energy[k]), (k, en[k], ref.energy[k])
+        assert en["e_coul"] == pytest.approx(ref.energy["e_coul"], rel=1e-12)
+        info = pb.refine_info()
+        o, n = info["fine_offset"], info["fine_n"]
+        want = ref.lB * ref.phi[o[0]:o[0] + n[0], o[1]:o[1] + n[1], o[2]:o[2] + n[2]]
+        m = fine_cell_vertices(ref.refined)[o[0]:o[0] + n[0], o[1]:o[1] + n[1], o[2]:o[2] + n[2]]
+        assert np.abs(pb.fine_potential()[m] - want[m]).max() <= 1e-6 * np.abs(want[m]).max()
+        want_c = ref.lB * ref.phi[::2, ::2, ::2]
+        assert np.abs(pb.potential() - want_c).max() <= 1e-6 * np.abs(want_c).max()
+    finally:
+        pb.close()
+
+
+def test_refined_mixed_matches_fp64_iterations(ctx):
+    """The mixed solve takes about as many iterations as the FP64 one on the same problem."""
+    mol = I.random_molecule(40, 3.0, 11)
+    g64 = I.cubic_grid(33, 0.5, refine=1, refine_shell=1.0, refine_brick=2, rtol=1e-8)
+    a = B.Problem(ctx, mol, g64)
+    b = B.Problem(ctx, mol, replace(g64, precision=I.MIXED, inner_rtol=1e-3))
+    try:
+        sa, sb = a.solve(), b.solve()
+        assert sa["status"] == 0 and sb["status"] == 0
+        assert sb["iters"] <= 1.3 * sa["iters"] + 16
+        ea, eb = a.energy(), b.energy()
+        assert abs(ea["e_pol"] - eb["e_pol"]) <= 1e-6 * abs(ea["e_pol"])
+    finally:
+        a.close()
+        b.close()
+
+
 def test_refined_invalid(ctx):
     mol = I.random_molecule(10, 2.0, 1)
-    g = I.cubic_grid(33, 0.5, refine=1, precision=I.MIXED)
+    # no atoms
+    g = I.cubic_grid(33, 0.5, refine=1)
+    empty = I.Molecule(xyz=np.zeros((0, 3)), radius=np.zeros(0), charge=np.zeros(0))
     with pytest.raises(B.PbError) as e:
-        B.Problem(ctx, mol, g)
+        B.Problem(ctx, empty, g)
     assert e.value.code == B.PB_EINVAL
     # a shell reaching the box faces
     g = I.cubic_grid(21, 0.5, refine=1, refine_shell=3.0)
