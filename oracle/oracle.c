@@ -454,6 +454,40 @@ int orc_assemble(const int32_t* n, double h, double eps_in, double eps_out, doub
     return missing ? -4 : 0;
 }
 
+/*
+ * The assembled operator as node fields over the full grid: K[ax] at node (i,j,k) is the
+ * total weight of the edge to the next node along ax (4 cells x (h/4) eps_e = h eps_e, the
+ * same eps_e as the assembly), zero on the last layer where that edge leaves the box;
+ * m at node v is its total mass (8 cells x (h^3/8) kbar2(v)).  For every interior node,
+ * the assembled row is diagonal sum(K of its 6 edges) + m and -K towards each neighbour.
+ */
+int orc_edge_coeffs(const int32_t* n, double h, double eps_in, double eps_out, double kbar2_out,
+                    const uint8_t* solute, int64_t ncut, const int64_t* key, const double* alpha,
+                    double* Kx, double* Ky, double* Kz, double* m)
+{
+    int missing = 0;
+    const int64_t N = (int64_t)n[0] * n[1] * n[2];
+#pragma omp parallel for schedule(static) reduction(| : missing)
+    for (int64_t v = 0; v < N; ++v) {
+        int64_t k = v % n[2], j = (v / n[2]) % n[1], i = v / ((int64_t)n[1] * n[2]);
+        double* out[3] = {Kx, Ky, Kz};
+        int64_t idx[3] = {i, j, k};
+        for (int ax = 0; ax < 3; ++ax) {
+            if (idx[ax] + 1 >= n[ax]) {
+                out[ax][v] = 0.0;
+                continue;
+            }
+            int64_t o = nid(n, i + (ax == 0), j + (ax == 1), k + (ax == 2));
+            int miss = 0;
+            double eps = edge_eps(solute, v, o, 3 * v + ax, key, alpha, ncut, eps_in, eps_out, &miss);
+            missing |= miss;
+            out[ax][v] = 4.0 * (0.25 * h) * eps;
+        }
+        m[v] = 8.0 * (h * h * h / 8.0) * (solute[v] ? 0.0 : kbar2_out);
+    }
+    return missing ? -4 : 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* 3. load vector and boundary values                                          */
 /* ------------------------------------------------------------------------- */

@@ -57,6 +57,7 @@ def lib():
         L.orc_mc_weights.argtypes = [P, P, i64, P, P, P]
         L.orc_edge_fields.argtypes = [P, d, d, d, P, i64, P, P, P, P, P]
         L.orc_surface_sums.argtypes = [i64, P, P, i64, P, P, P, P, P, P, P]
+        L.orc_edge_coeffs.argtypes = [P, d, d, d, d, P, i64, P, P, P, P, P, P]
         L.orc_coulomb.argtypes = [i64, P, P, d]
         L.orc_coulomb.restype = d
         L.orc_num_threads.restype = C.c_int
@@ -182,6 +183,21 @@ def assemble(grid, solute, cut: CutEdges, g_full, kbar2_out: float):
     k = int(nnz[0])
     A = sp.csr_matrix((val[:k].copy(), col[:k].copy(), rowptr), shape=(nu, nu))
     return A, lift
+
+
+def edge_coeffs(grid, solute, cut: CutEdges, kbar2_out: float):
+    """The assembled operator as full-grid fields (Kx, Ky, Kz, m): K[ax] at a node is the
+    weight of its edge to the next node along ax, m its lumped ionic term."""
+    shape = tuple(int(v) for v in grid.n)
+    K = [np.zeros(shape) for _ in range(3)]
+    m = np.zeros(shape)
+    sol = np.ascontiguousarray(solute, dtype=np.uint8)
+    rc = lib().orc_edge_coeffs(_p(_n(grid)), float(grid.h), float(grid.eps_in), float(grid.eps_out),
+                               float(kbar2_out), _p(sol), cut.m, _p(cut.key), _p(cut.alpha),
+                               _p(K[0]), _p(K[1]), _p(K[2]), _p(m))
+    if rc != 0:
+        raise RuntimeError(f"orc_edge_coeffs failed ({rc})")
+    return K[0], K[1], K[2], m
 
 
 def interior(a_full: np.ndarray) -> np.ndarray:
