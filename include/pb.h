@@ -47,6 +47,7 @@ enum {
 
 enum { PB_BC_ZERO = 0, PB_BC_DH = 1, PB_BC_USER = 2 };
 enum { PB_FP64 = 0, PB_MIXED = 1 };
+enum { PB_PRECOND_JACOBI = 0, PB_PRECOND_MG = 1 };
 
 typedef struct pb_ctx pb_ctx;
 typedef struct pb_problem pb_problem;
@@ -114,6 +115,22 @@ typedef struct {
                                the box faces (PB_EINVAL otherwise). */
     double refine_shell_A;  /* refine: distance in Angstrom (e.g. 3.0) */
     int32_t refine_brick;   /* refine: brick edge in coarse cells, 1..64 (e.g. 4) */
+    int32_t precond;        /* PB_PRECOND_JACOBI: diagonal (the default).  PB_PRECOND_MG:
+                               one geometric-multigrid V-cycle per CG step, smoothed by
+                               red-black symmetric Gauss-Seidel (the paper's SSOR preconditioner
+                               with omega = 1, Sect. 4, in an order a GPU can sweep in
+                               parallel): levels take every second node while n-1 is even on
+                               every axis (with one level the preconditioner is red-black
+                               symmetric Gauss-Seidel itself); coarse edges combine the fine
+                               ones in series along the edge and averaged across it; trilinear
+                               interpolation and its transpose.  Uniform grids only (PB_EINVAL
+                               with refine). */
+    int32_t mg_smooth;      /* PB_PRECOND_MG: red-black sweeps before and after the coarse
+                               correction on each level, 1..8 (0 = 1) */
+    int32_t mg_coarse_sweeps; /* PB_PRECOND_MG: symmetric sweeps on the coarsest level,
+                               1..64 (0 = 4) */
+    int32_t mg_levels;      /* PB_PRECOND_MG: at most this many levels, 0..12 (0 = as many as
+                               the grid allows, up to 12) */
 } pb_params;
 
 /* Build the coefficient maps of a problem on the device (paper Sect. 2.1 and 3.1-3.2):
@@ -174,6 +191,16 @@ int pb_copy_potential(const pb_problem* pb, double* host_phi);
 
 /* Release all device memory of a problem (waits for its stream). */
 void pb_problem_free(pb_problem* pb);
+
+/* One V-cycle of the multigrid preconditioner of a PB_PRECOND_MG problem on a given vector
+ * (parity tests; builds the level hierarchy on first use).
+ *   r_host : host, nx*ny*nz doubles (z contiguous); values on box nodes are ignored
+ *   z_host : host, nx*ny*nz doubles, written; box nodes 0.  In PB_MIXED the V-cycle runs in
+ *            FP32 (r rounded to FP32 on the way in).
+ *   levels : optional, receives the number of levels
+ * Overwrites the solver's CG work vectors (not the solution).  PB_EINVAL for a problem
+ * without the multigrid preconditioner. */
+int pb_mg_vcycle(pb_problem* pb, const double* r_host, double* z_host, int32_t* levels);
 
 /* Locally refined problems (refine = 1).  The fine cells live on a sub-lattice of the h/2
  * lattice: fine node (a,b,c) of it is node (a,b,c) + fine_offset of the lattice with the

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpb.so")
 PB_OK, PB_EINVAL, PB_ENOMEM, PB_ENOCONV, PB_EBREAKDOWN, PB_EDEVICE = 0, -1, -2, -3, -4, -5
 PB_BC_ZERO, PB_BC_DH, PB_BC_USER = 0, 1, 2
 PB_FP64, PB_MIXED = 0, 1
+PB_PRECOND_JACOBI, PB_PRECOND_MG = 0, 1
 
 EXPORTED = [
     "pb_ctx_create", "pb_ctx_destroy", "pb_last_error", "pb_build_coeffs", "pb_solve", "pb_energy",
@@ -24,6 +25,7 @@ EXPORTED = [
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
+    "pb_mg_vcycle",
 ]
 
 
@@ -35,6 +37,8 @@ class PbParams(C.Structure):
         ("precision", C.c_int32), ("rtol", C.c_double), ("inner_rtol", C.c_double),
         ("max_iter", C.c_int32), ("tile_planes", C.c_int32),
         ("refine", C.c_int32), ("refine_shell_A", C.c_double), ("refine_brick", C.c_int32),
+        ("precond", C.c_int32), ("mg_smooth", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
+        ("mg_levels", C.c_int32),
     ]
 
 
@@ -112,6 +116,7 @@ def load(path: str = LIB_PATH):
     L.pb_refine_info.argtypes = [P, C.POINTER(PbRefineStats)]
     L.pb_copy_refined_cells.argtypes = [P, P]
     L.pb_copy_fine_potential.argtypes = [P, P]
+    L.pb_mg_vcycle.argtypes = [P, P, P, C.POINTER(i32)]
     _lib = L
     return L
 
@@ -193,6 +198,10 @@ def make_params(grid) -> PbParams:
     p.refine = int(grid.refine)
     p.refine_shell_A = float(grid.refine_shell)
     p.refine_brick = int(grid.refine_brick)
+    p.precond = int(grid.precond)
+    p.mg_smooth = int(grid.mg_smooth)
+    p.mg_coarse_sweeps = int(grid.mg_coarse_sweeps)
+    p.mg_levels = int(grid.mg_levels)
     return p
 
 
@@ -271,6 +280,16 @@ class Problem:
         if rc != PB_OK:
             raise _err(rc)
         return phi
+
+    def mg_vcycle(self, r: np.ndarray):
+        """One V-cycle of the multigrid preconditioner on r (full grid); (z, levels)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros(self.shape)
+        lv = C.c_int32(0)
+        rc = _lib.pb_mg_vcycle(self.h, _ptr(r), _ptr(z), C.byref(lv))
+        if rc != PB_OK:
+            raise _err(rc)
+        return z, int(lv.value)
 
     def coeffs(self) -> dict:
         sh = self.shape

@@ -102,6 +102,15 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
         if (p->refine_brick < 1 || p->refine_brick > 64) return fail(PB_EINVAL, "refine_brick must be in [1, 64]");
         if (na <= 0) return fail(PB_EINVAL, "refinement needs atoms");
     }
+    if (p->precond != PB_PRECOND_JACOBI && p->precond != PB_PRECOND_MG)
+        return fail(PB_EINVAL, "precond must be PB_PRECOND_JACOBI or PB_PRECOND_MG");
+    if (p->precond == PB_PRECOND_MG) {
+        if (p->refine) return fail(PB_EINVAL, "the multigrid preconditioner is for uniform grids");
+        if (p->mg_smooth < 0 || p->mg_smooth > 8) return fail(PB_EINVAL, "mg_smooth must be in [0, 8]");
+        if (p->mg_coarse_sweeps < 0 || p->mg_coarse_sweeps > 64)
+            return fail(PB_EINVAL, "mg_coarse_sweeps must be in [0, 64]");
+        if (p->mg_levels < 0 || p->mg_levels > 12) return fail(PB_EINVAL, "mg_levels must be in [0, 12]");
+    }
     if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
     if (na > 0 && (!xyz || !rad || !chg)) return fail(PB_EINVAL, "atom arrays are NULL");
     for (int64_t a = 0; a < na; ++a) {
@@ -485,6 +494,8 @@ void pbi_problem_destroy(pb_problem* pb, bool sync)
         delete pb->ref;
         pb->ref = nullptr;
     }
+    delete pb->mg;   // its arrays are held by pb->mem
+    pb->mg = nullptr;
     if (pb->hout) (void)hipHostFree(pb->hout);
     if (pb->ev) (void)hipEventDestroy(pb->ev);
     pb->mem.release();
@@ -799,6 +810,18 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
         pb->solved = pb->ref->fine->solved = status == PB_OK || status == PB_ENOCONV;
         return status;
     }
+    if (P.precond == PB_PRECOND_MG) {
+        if ((rc = pbi_mg_solve(pb, &st))) return rc;
+        stats->iters = st.status == 1 ? st.iters : st.iter_count;
+        const double rr = P.precision == PB_MIXED ? st.rr64 : st.rr;
+        stats->relres = st.bnorm2 > 0 ? std::sqrt(rr / st.bnorm2) : 0.0;
+        stats->outer_iters = P.precision == PB_MIXED ? st.n_ru : 0;
+        status = st.status == 1 ? PB_OK : st.status == 2 ? PB_EBREAKDOWN : PB_ENOCONV;
+        stats->status = status;
+        stats->t_solve_s = now_s() - t0;
+        pb->solved = status == PB_OK || status == PB_ENOCONV;
+        return status;
+    }
     if (P.precision == PB_FP64 && (rc = ensure_cg64(pb))) return rc;
     if (P.precision == PB_FP64) {
         CGBufs<double> B = bufs<double>(pb);
@@ -944,6 +967,26 @@ int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, d
         if (key) key[c] = 3 * ((i * g.ny + j) * g.nz + k) + ax;
         if (owner) owner[c] = ow[c];
     }
+    return PB_OK;
+}
+
+int pb_mg_vcycle(pb_problem* pb, const double* r_host, double* z_host, int32_t* levels)
+{
+    if (!pb || !r_host || !z_host) return fail(PB_EINVAL, "NULL argument");
+    if (pb->prm.precond != PB_PRECOND_MG) return fail(PB_EINVAL, "not a multigrid-preconditioned problem");
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    const Grid& g = pb->g;
+    std::vector<double> r((size_t)g.N, 0.0), z((size_t)g.N, 0.0);
+    for (int i = 1; i < g.nx - 1; ++i)
+        for (int j = 1; j < g.ny - 1; ++j)
+            for (int k = 1; k < g.nz - 1; ++k)
+                r[(size_t)g.idx(i, j, k)] = r_host[((size_t)i * g.ny + j) * g.nz + k];
+    const int rc = pbi_mg_vcycle_test(pb, r.data(), z.data());
+    if (rc) return rc;
+    for (int i = 0; i < g.nx; ++i)
+        for (int j = 0; j < g.ny; ++j)
+            for (int k = 0; k < g.nz; ++k) z_host[((size_t)i * g.ny + j) * g.nz + k] = z[(size_t)g.idx(i, j, k)];
+    if (levels) *levels = pbi_mg_levels(pb);
     return PB_OK;
 }
 

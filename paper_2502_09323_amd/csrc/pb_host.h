@@ -101,6 +101,23 @@ struct RefineData {
     int64_t nunk_c = 0, nunk_f = 0, nhang = 0;
 };
 
+// multigrid preconditioner of a uniform problem (pb_mg.hip); level 0 is the problem's grid
+constexpr int PB_MG_MAX_LEVELS = 12;
+struct MGData {
+    int nlev = 0;               // levels in use
+    int nu = 1, cs = 4;         // sweeps per level and side, symmetric sweeps on the coarsest
+    pbk::Grid g[PB_MG_MAX_LEVELS];
+    void* K[PB_MG_MAX_LEVELS][3] = {};   // levels >= 1: K of the +x, +y, +z edges (element type)
+    void* dinv[PB_MG_MAX_LEVELS] = {};   // levels >= 1: 1 / diagonal
+    void* x[PB_MG_MAX_LEVELS] = {};      // iterate (level 0: the CG vector z)
+    void* b[PB_MG_MAX_LEVELS] = {};      // right-hand side (level 0: the CG residual)
+    void* r[PB_MG_MAX_LEVELS] = {};      // residual at the red nodes
+    void *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;   // CG r, z, p, q
+    void* cx = nullptr;         // CG x: the FP64 solution, or the FP32 correction (mixed)
+    double* part = nullptr;     // [3 * nb] block partial sums
+    int nb = 0;
+};
+
 struct pb_problem {
     pb_ctx* ctx;
     pb_params prm;
@@ -140,6 +157,7 @@ struct pb_problem {
     bool solved = false;
     BuildTmp* bt = nullptr;      // set while a build is in progress
     RefineData* ref = nullptr;   // set for a locally refined problem
+    MGData* mg = nullptr;        // set once a multigrid-preconditioned solve has run
     hipEvent_t ev = nullptr;     // marks the end of the last asynchronous phase
     double* hout = nullptr;      // pinned: energy sums and the final CG state
     double* e_tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // energy temporaries
@@ -172,3 +190,9 @@ pbk::ProbDev<float> pbi_probdev(pb_problem* pb);
 // locally refined problems (pb_refine.hip)
 int pbi_refine_build(pb_problem* coarse, const double* xyz, const double* rad, const double* chg);
 int pbi_refine_solve(pb_problem* pb, pbk::CGState* out);
+
+// multigrid-preconditioned CG (pb_mg.hip)
+int pbi_mg_solve(pb_problem* pb, pbk::CGState* out);
+int pbi_mg_levels(const pb_problem* pb);
+// one V-cycle on a vector over the padded level-0 layout (host arrays of g.N doubles)
+int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host);

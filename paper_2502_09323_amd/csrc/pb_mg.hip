@@ -1,0 +1,908 @@
+// pb_mg.hip -- CG preconditioned by one geometric-multigrid V-cycle (uniform grids).
+//
+// The paper solves with CG and an SSOR preconditioner (Sect. 4).  On a GPU a lexicographic
+// SSOR sweep is sequential, so this solver orders the nodes red-black (node (i,j,k) is red
+// when i+j+k is even; all neighbours of a red node are black) and uses symmetric red-black
+// Gauss-Seidel -- SSOR with omega = 1 in that order -- as the smoother of a V-cycle:
+//
+//   levels      node I of level l+1 is node 2I of level l, while n-1 is even on every axis
+//               (n >= 5); level 0 reads the operator from the node-code map, the coarser
+//               levels store K along +x, +y, +z and 1/diagonal per node
+//   coarse K    along a coarse edge the two fine edges are in series (K1 K2 / (K1 + K2));
+//               across it the 3 x 3 fine lines around it are averaged with weights
+//               (1/4, 1/2, 1/4) per axis, times 4 (a coarse dual face holds four fine ones);
+//               the coarse ionic term is P^T m
+//   transfers   P trilinear, R = P^T
+//   V-cycle     zero start; nu times (red, black); residual (zero on black nodes right after
+//               a black half-sweep, so only red nodes are formed); restrict; recurse; add P e;
+//               nu times (black, red); the coarsest level takes red, then (black, red) x cs.
+//               Pre- and post-smoothing are adjoint and R = P^T: the V-cycle is symmetric
+//               positive definite.  With one level it is red-black symmetric Gauss-Seidel.
+//   CG          standard PCG (z = V-cycle(r)) with device-resident scalars; FP64, or FP32
+//               with FP64 reliable updates (x64 += x32, r = b - A x64 in FP64, restart the
+//               recurrence from the true residual, keeping the direction)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pb_host.h"
+#include "pb_internal.h"
+#include "pb_stencil.h"
+
+using namespace pbk;
+
+namespace {
+
+#define RCHK(x)                                                                     \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess) return pbi_fail(PB_EDEVICE, "%s", hipGetErrorString(e_)); \
+    } while (0)
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// one level as the kernels see it
+template <typename T>
+struct Lev {
+    Grid g;
+    const T *kx, *ky, *kz;   // levels >= 1: K of the +x, +y, +z edges
+    const T* dinv;           // levels >= 1: 1 / diagonal
+    T* x;                    // iterate (level 0: the CG vector z)
+    const T* b;              // right-hand side (level 0: the CG residual r)
+    T* r;                    // residual, formed at red nodes (black entries stay 0)
+};
+
+// the level-0 operator from the node-code map
+template <typename T>
+struct Op0 {
+    const uint32_t* code;
+    const T* ck;
+    T kin, kout, mass;
+};
+
+// sum of K * x(neighbour) over the six edges of node e, and the diagonal there: level 0
+// gives D itself (inv = false), the coarser levels their stored 1 / D (inv = true)
+template <typename T, bool L0>
+__device__ __forceinline__ void nbr_sum(const Lev<T>& L, const Op0<T>& op, int64_t e, T& s, T& d)
+{
+    const Grid& g = L.g;
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    const T* x = L.x;
+    if constexpr (L0) {
+        const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
+        s = ((k.xm * x[e - sx] + k.xp * x[e + sx]) + (k.ym * x[e - sy] + k.yp * x[e + sy])) +
+            (k.zm * x[e - 1] + k.zp * x[e + 1]);
+        d = k.diag();
+    } else {
+        s = ((L.kx[e - sx] * x[e - sx] + L.kx[e] * x[e + sx]) + (L.ky[e - sy] * x[e - sy] + L.ky[e] * x[e + sy])) +
+            (L.kz[e - 1] * x[e - 1] + L.kz[e] * x[e + 1]);
+        d = L.dinv[e];
+    }
+}
+
+// Gauss-Seidel value (b + s) / D at a node
+template <typename T, bool L0>
+__device__ __forceinline__ T gs_value(T b, T s, T d)
+{
+    if constexpr (L0) return (b + s) / d;
+    return (b + s) * d;
+}
+
+// node of colour c (0 red, 1 black) handled by thread t, or -1
+__device__ __forceinline__ int64_t colour_node(const Grid& g, int c, int64_t t)
+{
+    const int M = (g.nz - 1) >> 1;   // at most this many nodes of one colour per interior z-row
+    const int64_t rows = (int64_t)(g.nx - 2) * (g.ny - 2);
+    if (M <= 0 || t >= rows * M) return -1;
+    const int row = (int)(t / M), m = (int)(t - (int64_t)row * M);
+    const int i = 1 + row / (g.ny - 2), j = 1 + row % (g.ny - 2);
+    const int k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
+    if (k > g.nz - 2) return -1;
+    return g.idx(i, j, k);
+}
+
+__host__ __device__ inline int64_t colour_threads(const Grid& g)
+{
+    return (int64_t)(g.nx - 2) * (g.ny - 2) * ((g.nz - 1) >> 1);
+}
+
+__host__ __device__ inline int64_t interior_count(const Grid& g)
+{
+    return (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+}
+
+__device__ __forceinline__ int64_t interior_node(const Grid& g, int64_t t)
+{
+    const int nzi = g.nz - 2, nyi = g.ny - 2;
+    const int64_t row = t / nzi;
+    const int k = 1 + (int)(t - row * nzi);
+    const int i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
+    return g.idx(i, j, k);
+}
+
+__device__ __forceinline__ bool halted(const CGState* st) { return st && st->status != 0; }
+
+// first half-sweep from a zero iterate: red nodes b / D, black nodes 0
+template <typename T, bool L0>
+__global__ void __launch_bounds__(256) k_first(Lev<T> L, Op0<T> op, const CGState* st)
+{
+    if (halted(st)) return;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= interior_count(L.g)) return;
+    const int64_t e = interior_node(L.g, t);
+    int i, j, k;
+    {
+        const int nzi = L.g.nz - 2, nyi = L.g.ny - 2;
+        const int64_t row = t / nzi;
+        k = 1 + (int)(t - row * nzi);
+        i = 1 + (int)(row / nyi);
+        j = 1 + (int)(row % nyi);
+    }
+    if ((i + j + k) & 1) {
+        L.x[e] = (T)0;
+        return;
+    }
+    if constexpr (L0) {
+        L.x[e] = L.b[e] / stencil::node_k(L.g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
+    } else {
+        L.x[e] = L.b[e] * L.dinv[e];
+    }
+}
+
+// Gauss-Seidel on the nodes of one colour
+template <typename T, bool L0>
+__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, const CGState* st)
+{
+    if (halted(st)) return;
+    const int64_t e = colour_node(L.g, c, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    if (e < 0) return;
+    T s, d;
+    nbr_sum<T, L0>(L, op, e, s, d);
+    L.x[e] = gs_value<T, L0>(L.b[e], s, d);
+}
+
+// residual b - A x at the red nodes (after a black half-sweep the black residual is zero)
+template <typename T, bool L0>
+__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, const CGState* st)
+{
+    if (halted(st)) return;
+    const int64_t e = colour_node(L.g, 0, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    if (e < 0) return;
+    T s, d;
+    nbr_sum<T, L0>(L, op, e, s, d);
+    const T ax = L0 ? d * L.x[e] - s : L.x[e] / d - s;
+    L.r[e] = L.b[e] - ax;
+}
+
+// coarse right-hand side P^T r: node 2I and its 12 red neighbours (two odd offsets, weight
+// 1/4); the other 14 of the 27 are black, where r is zero
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
+                                                  const CGState* st)
+{
+    if (halted(st)) return;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= interior_count(gc)) return;
+    const int nzi = gc.nz - 2, nyi = gc.ny - 2;
+    const int64_t row = t / nzi;
+    const int K = 1 + (int)(t - row * nzi), I = 1 + (int)(row / nyi), J = 1 + (int)(row % nyi);
+    const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
+    const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
+    const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
+    const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
+    const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
+    bc[gc.idx(I, J, K)] = r[f] + (T)0.25 * ((xy + xz) + yz);
+}
+
+// x += P e (trilinear from the coarse corners)
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
+                                                 const CGState* st)
+{
+    if (halted(st)) return;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= interior_count(gf)) return;
+    const int nzi = gf.nz - 2, nyi = gf.ny - 2;
+    const int64_t row = t / nzi;
+    const int k = 1 + (int)(t - row * nzi), i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+    const T v = ((ec[gc.idx(i0, j0, k0)] + ec[gc.idx(i0, j0, k1)]) + (ec[gc.idx(i0, j1, k0)] + ec[gc.idx(i0, j1, k1)])) +
+                ((ec[gc.idx(i1, j0, k0)] + ec[gc.idx(i1, j0, k1)]) + (ec[gc.idx(i1, j1, k0)] + ec[gc.idx(i1, j1, k1)]));
+    x[gf.idx(i, j, k)] += (T)0.125 * v;
+}
+
+// the coarsest level in one block: red from zero, then (black, red) x cs
+template <typename T, bool L0>
+__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, const CGState* st)
+{
+    if (halted(st)) return;
+    const Grid& g = L.g;
+    const int64_t n = interior_count(g), nc = colour_threads(g);
+    for (int64_t t = threadIdx.x; t < n; t += 256) {
+        const int64_t e = interior_node(g, t);
+        const int nzi = g.nz - 2, nyi = g.ny - 2;
+        const int64_t row = t / nzi;
+        const int k = 1 + (int)(t - row * nzi), i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
+        if ((i + j + k) & 1) {
+            L.x[e] = (T)0;
+        } else if constexpr (L0) {
+            L.x[e] = L.b[e] / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
+        } else {
+            L.x[e] = L.b[e] * L.dinv[e];
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < 2 * cs; ++s) {
+        const int c = (s & 1) ? 0 : 1;
+        for (int64_t t = threadIdx.x; t < nc; t += 256) {
+            const int64_t e = colour_node(g, c, t);
+            if (e < 0) continue;
+            T sum, d;
+            nbr_sum<T, L0>(L, op, e, sum, d);
+            L.x[e] = gs_value<T, L0>(L.b[e], sum, d);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- hierarchy set-up (FP64) ------------------------------------------------------------
+
+struct FineSrc {            // the operator of the level being coarsened
+    Grid g;
+    const uint32_t* code;   // level 0: node-code map (else nullptr)
+    const double* ck;
+    double kin, kout, mass;
+    const double *kx, *ky, *kz, *m;   // levels >= 1
+    __device__ double K(int ax, int64_t e) const
+    {
+        if (code) return stencil::edgeK(code[e], ax, ck, kin, kout);
+        return ax == 0 ? kx[e] : ax == 1 ? ky[e] : kz[e];
+    }
+    __device__ double M(int64_t e) const
+    {
+        if (code) return (code[e] & C_SOLUTE) ? 0.0 : mass;
+        return m[e];
+    }
+};
+
+__device__ __forceinline__ double series(double a, double b)
+{
+    const double t = a + b;
+    return t > 0.0 ? a * b / t : 0.0;
+}
+
+// coarse K along each axis and the coarse ionic term, one thread per coarse node
+__global__ void __launch_bounds__(256) k_coarsen(FineSrc F, Grid gc, double* kx, double* ky, double* kz, double* m)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    if (t >= n) return;
+    const int K = (int)(t % gc.nz), J = (int)((t / gc.nz) % gc.ny), I = (int)(t / ((int64_t)gc.nz * gc.ny));
+    const int64_t ec = gc.idx(I, J, K);
+    const int C[3] = {I, J, K};
+    const int nc[3] = {gc.nx, gc.ny, gc.nz};
+    const double w3[3] = {0.25, 0.5, 0.25};
+    double* out[3] = {kx, ky, kz};
+    for (int ax = 0; ax < 3; ++ax) {
+        const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+        bool ok = C[ax] <= nc[ax] - 2;
+        ok = ok && C[t1] >= 1 && C[t1] <= nc[t1] - 2 && C[t2] >= 1 && C[t2] <= nc[t2] - 2;
+        double acc = 0.0;
+        if (ok) {
+            for (int a = -1; a <= 1; ++a)
+                for (int b = -1; b <= 1; ++b) {
+                    int f[3] = {2 * I, 2 * J, 2 * K};
+                    f[t1] += a;
+                    f[t2] += b;
+                    const int64_t e1 = F.g.idx(f[0], f[1], f[2]);
+                    f[ax] += 1;
+                    const int64_t e2 = F.g.idx(f[0], f[1], f[2]);
+                    acc += w3[a + 1] * w3[b + 1] * series(F.K(ax, e1), F.K(ax, e2));
+                }
+        }
+        out[ax][ec] = 4.0 * acc;
+    }
+    double mm = 0.0;
+    if (I >= 1 && I <= gc.nx - 2 && J >= 1 && J <= gc.ny - 2 && K >= 1 && K <= gc.nz - 2) {
+        for (int a = -1; a <= 1; ++a)
+            for (int b = -1; b <= 1; ++b)
+                for (int c = -1; c <= 1; ++c) {
+                    const double w = (a ? 0.5 : 1.0) * (b ? 0.5 : 1.0) * (c ? 0.5 : 1.0);
+                    mm += w * F.M(F.g.idx(2 * I + a, 2 * J + b, 2 * K + c));
+                }
+    }
+    m[ec] = mm;
+}
+
+// 1 / diagonal at the interior nodes of a coarse level, and the element-type copies
+template <typename T>
+__global__ void __launch_bounds__(256) k_level_diag(Grid g, const double* kx, const double* ky, const double* kz,
+                                                    const double* m, T* kxT, T* kyT, T* kzT, T* dinvT)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    if (t >= n) return;
+    const int k = (int)(t % g.nz), j = (int)((t / g.nz) % g.ny), i = (int)(t / ((int64_t)g.nz * g.ny));
+    const int64_t e = g.idx(i, j, k);
+    kxT[e] = (T)kx[e];
+    kyT[e] = (T)ky[e];
+    kzT[e] = (T)kz[e];
+    double d = 0.0;
+    if (i >= 1 && i <= g.nx - 2 && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2) {
+        const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+        const double D = ((kx[e - sx] + kx[e]) + (ky[e - sy] + ky[e])) + ((kz[e - 1] + kz[e]) + m[e]);
+        d = 1.0 / D;
+    }
+    dinvT[e] = (T)d;
+}
+
+// ---- CG over the level-0 unknowns ----------------------------------------------------------
+
+__device__ __forceinline__ void bsum(double* v, int nv, double* sh)
+{
+    for (int t = 0; t < nv; ++t)
+        for (int o = 32; o > 0; o >>= 1) v[t] += __shfl_xor(v[t], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+        for (int t = 0; t < nv; ++t) sh[4 * t + w] = v[t];
+    __syncthreads();
+    for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
+}
+
+// p = z + beta p at the unknowns
+template <typename T>
+__global__ void __launch_bounds__(256) k_pupd(Grid g, const uint32_t* __restrict__ code, const T* __restrict__ z,
+                                              T* __restrict__ p, const CGState* st)
+{
+    if (st->status != 0) return;
+    const T beta = (T)st->beta;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
+        if (!(code[e] & C_BOX)) p[e] = z[e] + beta * p[e];
+}
+
+// q = A p at the unknowns; partial sums of p.q
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply(Grid g, Op0<T> op, const T* __restrict__ p, T* __restrict__ q,
+                                               double* part, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
+        if (op.code[e] & C_BOX) continue;
+        const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
+        const T s = ((k.xm * p[e - sx] + k.xp * p[e + sx]) + (k.ym * p[e - sy] + k.yp * p[e + sy])) +
+                    (k.zm * p[e - 1] + k.zp * p[e + 1]);
+        const T qe = k.diag() * p[e] - s;
+        q[e] = qe;
+        v[0] += (double)p[e] * (double)qe;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[t];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) {
+        const double pq = v[0];
+        st->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else {
+            st->alpha = st->gamma / pq;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q; partial sums of r.r (after the r.z slots)
+template <typename T>
+__global__ void __launch_bounds__(256) k_update(Grid g, const uint32_t* __restrict__ code, T* __restrict__ x,
+                                                T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                                                double* part, int nb, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const T a = (T)st->alpha;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
+        if (code[e] & C_BOX) continue;
+        x[e] += a * p[e];
+        const T rv = r[e] - a * q[e];
+        r[e] = rv;
+        v[0] += (double)rv * (double)rv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[nb + blockIdx.x] = v[0];
+}
+
+// partial sums of r.z
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot(Grid g, const uint32_t* __restrict__ code, const T* __restrict__ r,
+                                             const T* __restrict__ z, double* part, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
+        if (!(code[e] & C_BOX)) v[0] += (double)r[e] * (double)z[e];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
+// recursive r.r (status = stop_status once r.r <= stop2, or <= trig2 in mixed precision);
+// mode 1 (first residual): beta = 0; mode 2 (after a residual replacement): the direction
+// update that the stopped step skipped takes beta = r'.z' / (r.z of the step before)
+__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    double v[2] = {0.0, 0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) {
+        v[0] += part[t];
+        if (mode == 0) v[1] += part[nb + t];
+    }
+    bsum(v, 2, sh);
+    if (threadIdx.x == 0) {
+        const double gm = v[0];
+        if (mode == 0) {
+            const double rr = v[1];
+            st->iter_count += 1;
+            st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
+            st->rr = rr;
+            if (!isfinite(gm) || !isfinite(rr)) {
+                st->status = 2;
+                st->iters = st->iter_count;
+            } else if (rr <= st->stop2 || rr <= st->trig2) {
+                st->status = st->stop_status;
+                st->iters = st->iter_count;
+            }
+        } else if (mode == 1) {
+            st->beta = 0.0;
+        } else {
+            st->beta = (st->gamma > 0.0 && st->beta > 0.0) ? gm * (st->beta / st->gamma) : 0.0;
+        }
+        st->gamma = gm;
+        // the V-cycle is positive definite: r.z > 0 unless r = 0
+        if (st->status == 0 && (!isfinite(gm) || !(gm > 0.0))) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        }
+    }
+}
+
+// mixed precision: x64 += x32, x32 = 0
+__global__ void __launch_bounds__(256) k_fold(Grid g, const uint32_t* __restrict__ code, double* __restrict__ x64,
+                                              float* __restrict__ x32)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
+        if (!(code[e] & C_BOX)) {
+            x64[e] += (double)x32[e];
+            x32[e] = 0.0f;
+        }
+}
+
+// r = b - A x in FP64 (the FP64 code-map operator), stored in the element type; partial sums
+// of the FP64 r.r in the third slot range
+template <typename T>
+__global__ void __launch_bounds__(256) k_true_res(Grid g, Op0<double> op, const double* __restrict__ x,
+                                                  const double* __restrict__ b, T* __restrict__ r, double* part, int nb)
+{
+    __shared__ double sh[8];
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
+        if (op.code[e] & C_BOX) continue;
+        const stencil::NodeK<double> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
+        const double s = ((k.xm * x[e - sx] + k.xp * x[e + sx]) + (k.ym * x[e - sy] + k.yp * x[e + sy])) +
+                         (k.zm * x[e - 1] + k.zp * x[e + 1]);
+        const double rv = b[e] - (k.diag() * x[e] - s);
+        r[e] = (T)rv;
+        v[0] += rv * rv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = v[0];
+}
+
+// after a true residual: the FP64 norm decides convergence; with init it sets the goals
+__global__ void __launch_bounds__(256) k_ru_fin(const double* part, int nb, CGState* st, int init, int mixed,
+                                                double rtol2, double delta2)
+{
+    __shared__ double sh[8];
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[2 * nb + t];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) {
+        const double rr64 = v[0];
+        if (init) {
+            st->alpha = st->beta = st->gamma = st->pq = 0.0;
+            st->bnorm2 = rr64;
+            st->goal64 = rtol2 * rr64;
+            st->stop2 = rtol2 * rr64;
+            st->delta2 = mixed ? delta2 : 0.0;
+            st->stop_status = mixed ? 3 : 1;
+            st->iters = st->iter_count = st->ru = st->n_ru = 0;
+        } else {
+            st->n_ru += 1;
+        }
+        st->rr = rr64;
+        st->rr64 = rr64;
+        st->trig2 = st->delta2 * rr64;
+        if (!isfinite(rr64)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else if (rr64 <= st->goal64) {
+            st->status = 1;
+            st->iters = st->iter_count;
+        } else {
+            st->status = 0;
+        }
+    }
+}
+
+}  // namespace
+
+// ---- host side -----------------------------------------------------------------------------
+
+namespace {
+
+Grid coarse_grid(const Grid& f)
+{
+    Grid c = f;
+    c.nx = (f.nx - 1) / 2 + 1;
+    c.ny = (f.ny - 1) / 2 + 1;
+    c.nz = (f.nz - 1) / 2 + 1;
+    c.S = (int)row_stride(c.nz);
+    c.N = (int64_t)c.nx * c.ny * c.S;
+    c.h = 2.0 * f.h;
+    return c;
+}
+
+bool can_coarsen(const Grid& g)
+{
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d)
+        if ((n[d] - 1) % 2 != 0 || (n[d] - 1) / 2 + 1 < 3) return false;
+    return true;
+}
+
+// a coarsest level of at most this many unknowns runs in one block
+constexpr int64_t kOneBlockCoarse = 32768;
+
+template <typename T>
+Lev<T> level(const MGData* G, int l)
+{
+    Lev<T> L;
+    L.g = G->g[l];
+    L.kx = (const T*)G->K[l][0];
+    L.ky = (const T*)G->K[l][1];
+    L.kz = (const T*)G->K[l][2];
+    L.dinv = (const T*)G->dinv[l];
+    L.x = (T*)G->x[l];
+    L.b = (const T*)G->b[l];
+    L.r = (T*)G->r[l];
+    return L;
+}
+
+template <typename T>
+Op0<T> op0(const pb_problem* pb)
+{
+    Op0<T> o;
+    o.code = pb->code;
+    if constexpr (sizeof(T) == 8)
+        o.ck = (const T*)pb->ck64;
+    else
+        o.ck = (const T*)pb->ck32;
+    o.kin = (T)pb->cf.kin;
+    o.kout = (T)pb->cf.kout;
+    o.mass = (T)pb->cf.mass;
+    return o;
+}
+
+template <typename T, bool L0>
+void launch_smooth_first(hipStream_t s, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+{
+    k_first<T, L0><<<nblk(interior_count(L.g), 256), 256, 0, s>>>(L, op, st);
+}
+
+template <typename T, bool L0>
+void launch_sweep(hipStream_t s, const Lev<T>& L, const Op0<T>& op, int c, const CGState* st)
+{
+    const int64_t n = colour_threads(L.g);
+    if (n > 0) k_sweep<T, L0><<<nblk(n, 256), 256, 0, s>>>(L, op, c, st);
+}
+
+// pre-smoothing (red, black) x nu from zero, residual, restriction to level l+1
+template <typename T, bool L0>
+void launch_down(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+{
+    launch_smooth_first<T, L0>(s, L, op, st);
+    launch_sweep<T, L0>(s, L, op, 1, st);
+    for (int v = 1; v < G->nu; ++v) {
+        launch_sweep<T, L0>(s, L, op, 0, st);
+        launch_sweep<T, L0>(s, L, op, 1, st);
+    }
+    const int64_t n = colour_threads(L.g);
+    if (n > 0) k_resid<T, L0><<<nblk(n, 256), 256, 0, s>>>(L, op, st);
+}
+
+template <typename T, bool L0>
+void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+{
+    if (interior_count(L.g) <= kOneBlockCoarse) {
+        k_coarse<T, L0><<<1, 256, 0, s>>>(L, op, G->cs, st);
+        return;
+    }
+    launch_smooth_first<T, L0>(s, L, op, st);
+    for (int v = 0; v < G->cs; ++v) {
+        launch_sweep<T, L0>(s, L, op, 1, st);
+        launch_sweep<T, L0>(s, L, op, 0, st);
+    }
+}
+
+// z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r)
+template <typename T>
+void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st)
+{
+    const MGData* G = pb->mg;
+    const Op0<T> op = op0<T>(pb);
+    const int L = G->nlev;
+    if (L == 1) {
+        launch_coarsest<T, true>(s, G, level<T>(G, 0), op, st);
+        return;
+    }
+    for (int l = 0; l + 1 < L; ++l) {
+        const Lev<T> lv = level<T>(G, l);
+        if (l == 0)
+            launch_down<T, true>(s, G, lv, op, st);
+        else
+            launch_down<T, false>(s, G, lv, op, st);
+        const Grid& gc = G->g[l + 1];
+        k_restrict<T><<<nblk(interior_count(gc), 256), 256, 0, s>>>(lv.g, lv.r, gc, (T*)G->b[l + 1], st);
+    }
+    launch_coarsest<T, false>(s, G, level<T>(G, L - 1), op, st);
+    for (int l = L - 2; l >= 0; --l) {
+        const Lev<T> lv = level<T>(G, l);
+        k_prolong<T><<<nblk(interior_count(lv.g), 256), 256, 0, s>>>(lv.g, lv.x, G->g[l + 1], (const T*)G->x[l + 1],
+                                                                      st);
+        for (int v = 0; v < G->nu; ++v) {
+            if (l == 0) {
+                launch_sweep<T, true>(s, lv, op, 1, st);
+                launch_sweep<T, true>(s, lv, op, 0, st);
+            } else {
+                launch_sweep<T, false>(s, lv, op, 1, st);
+                launch_sweep<T, false>(s, lv, op, 0, st);
+            }
+        }
+    }
+}
+
+template <typename T>
+int setup_levels(pb_problem* pb, MGData* G)
+{
+    hipStream_t s = pb->ctx->stream;
+    const pb_params& P = pb->prm;
+    G->g[0] = pb->g;
+    G->nlev = 1;
+    const int maxl = P.mg_levels > 0 ? std::min(P.mg_levels, PB_MG_MAX_LEVELS) : PB_MG_MAX_LEVELS;
+    while (G->nlev < maxl && can_coarsen(G->g[G->nlev - 1])) {
+        G->g[G->nlev] = coarse_grid(G->g[G->nlev - 1]);
+        ++G->nlev;
+    }
+    // FP64 coefficients of every coarse level, then the element-type copies
+    std::vector<double*> tmp;
+    auto get64 = [&](int64_t n) -> double* {
+        double* p = (double*)pb->mem.get(sizeof(double) * (size_t)n);
+        if (p) tmp.push_back(p);
+        return p;
+    };
+    const double *pkx = nullptr, *pky = nullptr, *pkz = nullptr, *pm = nullptr;
+    for (int l = 1; l < G->nlev; ++l) {
+        const Grid& gc = G->g[l];
+        double *kx = get64(gc.N), *ky = get64(gc.N), *kz = get64(gc.N), *m = get64(gc.N);
+        if (!kx || !ky || !kz || !m) return pbi_fail(PB_ENOMEM, "multigrid levels");
+        RCHK(launch_fill(s, kx, sizeof(double) * (size_t)gc.N));
+        RCHK(launch_fill(s, ky, sizeof(double) * (size_t)gc.N));
+        RCHK(launch_fill(s, kz, sizeof(double) * (size_t)gc.N));
+        RCHK(launch_fill(s, m, sizeof(double) * (size_t)gc.N));
+        FineSrc F;
+        F.g = G->g[l - 1];
+        F.code = l == 1 ? pb->code : nullptr;
+        F.ck = pb->ck64;
+        F.kin = pb->cf.kin;
+        F.kout = pb->cf.kout;
+        F.mass = pb->cf.mass;
+        F.kx = pkx;
+        F.ky = pky;
+        F.kz = pkz;
+        F.m = pm;
+        const int64_t nn = (int64_t)gc.nx * gc.ny * gc.nz;
+        k_coarsen<<<nblk(nn, 256), 256, 0, s>>>(F, gc, kx, ky, kz, m);
+        T* kT[3];
+        for (int d = 0; d < 3; ++d) {
+            kT[d] = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
+            if (!kT[d]) return pbi_fail(PB_ENOMEM, "multigrid levels");
+            RCHK(launch_fill(s, kT[d], sizeof(T) * (size_t)gc.N));
+            G->K[l][d] = kT[d];
+        }
+        T* dT = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
+        if (!dT) return pbi_fail(PB_ENOMEM, "multigrid levels");
+        RCHK(launch_fill(s, dT, sizeof(T) * (size_t)gc.N));
+        G->dinv[l] = dT;
+        k_level_diag<T><<<nblk(nn, 256), 256, 0, s>>>(gc, kx, ky, kz, m, kT[0], kT[1], kT[2], dT);
+        RCHK(hipGetLastError());
+        pkx = kx;
+        pky = ky;
+        pkz = kz;
+        pm = m;
+    }
+    RCHK(hipStreamSynchronize(s));
+    for (double* p : tmp) pb->mem.put(p);
+    // level vectors (level 0: x and b are the CG vectors z and r)
+    for (int l = 0; l < G->nlev; ++l) {
+        const Grid& g = G->g[l];
+        const int nv = l == 0 ? 1 : 3;
+        void** dst[3] = {&G->r[l], &G->x[l], &G->b[l]};
+        for (int v = 0; v < nv; ++v) {
+            *dst[v] = pb->mem.get(sizeof(T) * (size_t)g.N);
+            if (!*dst[v]) return pbi_fail(PB_ENOMEM, "multigrid vectors");
+            RCHK(launch_fill(s, *dst[v], sizeof(T) * (size_t)g.N));
+        }
+    }
+    const Grid& g0 = pb->g;
+    void** cg[5] = {&G->cr, &G->cz, &G->cp, &G->cq, &G->cx};
+    const int ncg = sizeof(T) == 4 ? 5 : 4;
+    for (int v = 0; v < ncg; ++v) {
+        *cg[v] = pb->mem.get(sizeof(T) * (size_t)g0.N);
+        if (!*cg[v]) return pbi_fail(PB_ENOMEM, "multigrid CG vectors");
+        RCHK(launch_fill(s, *cg[v], sizeof(T) * (size_t)g0.N));
+    }
+    if (sizeof(T) == 8) G->cx = pb->x;
+    G->x[0] = G->cz;
+    G->b[0] = G->cr;
+    G->nb = (int)std::min<int64_t>(2048, (int64_t)nblk(g0.N, 256));
+    G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
+    if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
+    RCHK(hipStreamSynchronize(s));
+    return PB_OK;
+}
+
+template <typename T>
+void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st)
+{
+    const MGData* G = pb->mg;
+    const Grid& g = pb->g;
+    const Op0<T> op = op0<T>(pb);
+    T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p = (T*)G->cp, *q = (T*)G->cq;
+    k_pupd<T><<<G->nb, 256, 0, s>>>(g, pb->code, z, p, st);
+    k_apply<T><<<G->nb, 256, 0, s>>>(g, op, p, q, G->part, st);
+    k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
+    k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p, q, G->part, G->nb, st);
+    launch_vcycle<T>(s, pb, st);
+    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, st);
+    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0);
+}
+
+// true residual from the FP64 solution (mixed: after folding the FP32 correction into it),
+// then z = V-cycle(r) and r.z; mode 1 starts the recurrence, mode 2 restarts it
+template <typename T>
+void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init)
+{
+    const MGData* G = pb->mg;
+    const Grid& g = pb->g;
+    const pb_params& P = pb->prm;
+    const bool mixed = sizeof(T) == 4;
+    if (mixed) k_fold<<<G->nb, 256, 0, s>>>(g, pb->code, pb->x, (float*)G->cx);
+    const Op0<double> op64 = op0<double>(pb);
+    k_true_res<T><<<G->nb, 256, 0, s>>>(g, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb);
+    k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol,
+                               P.inner_rtol * P.inner_rtol);
+    launch_vcycle<T>(s, pb, st);
+    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, st);
+    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2);
+}
+
+template <typename T>
+int solve_t(pb_problem* pb, CGState* out)
+{
+    hipStream_t s = pb->ctx->stream;
+    const pb_params& P = pb->prm;
+    const bool mixed = sizeof(T) == 4;
+    if (!pb->mg) {
+        pb->mg = new MGData();
+        pb->mg->nu = P.mg_smooth > 0 ? P.mg_smooth : 1;
+        pb->mg->cs = P.mg_coarse_sweeps > 0 ? P.mg_coarse_sweeps : 4;
+        const int rc = setup_levels<T>(pb, pb->mg);
+        if (rc) return rc;
+    }
+    MGData* G = pb->mg;
+    CGState* st = pb->st;
+    RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
+    if (mixed) RCHK(launch_fill(s, G->cx, sizeof(float) * (size_t)pb->g.N));
+    RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)pb->g.N));
+    RCHK(launch_fill(s, st, sizeof(CGState)));
+    launch_restart<T>(s, pb, st, 1);
+    RCHK(hipGetLastError());
+    CGState h;
+    RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    const int M = 8;
+    int launched = 0;
+    bool breakdown = false;
+    while (h.status == 0 && launched < P.max_iter) {
+        const int n = std::min(M, P.max_iter - launched);
+        for (int it = 0; it < n; ++it) launch_iteration<T>(s, pb, st);
+        RCHK(hipGetLastError());
+        launched += n;
+        RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        RCHK(hipStreamSynchronize(s));
+        if (mixed && (h.status != 0 || launched >= P.max_iter)) {
+            // status 3: the FP32 residual reached its goal or fell by inner_rtol
+            breakdown = h.status == 2;
+            launch_restart<T>(s, pb, st, 0);
+            RCHK(hipGetLastError());
+            RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+            RCHK(hipStreamSynchronize(s));
+            if (breakdown) break;
+        }
+    }
+    RCHK(hipMemcpyAsync(out, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    if (breakdown && out->status != 1) out->status = 2;
+    return PB_OK;
+}
+
+}  // namespace
+
+int pbi_mg_solve(pb_problem* pb, CGState* out)
+{
+    if (pb->prm.precision == PB_MIXED) return solve_t<float>(pb, out);
+    return solve_t<double>(pb, out);
+}
+
+int pbi_mg_levels(const pb_problem* pb) { return pb->mg ? pb->mg->nlev : 0; }
+
+int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
+{
+    // one V-cycle on a host vector over the padded level-0 layout (test hook)
+    hipStream_t s = pb->ctx->stream;
+    const Grid& g = pb->g;
+    const bool mixed = pb->prm.precision == PB_MIXED;
+    if (!pb->mg) {
+        pb->mg = new MGData();
+        pb->mg->nu = pb->prm.mg_smooth > 0 ? pb->prm.mg_smooth : 1;
+        pb->mg->cs = pb->prm.mg_coarse_sweeps > 0 ? pb->prm.mg_coarse_sweeps : 4;
+        const int rc = mixed ? setup_levels<float>(pb, pb->mg) : setup_levels<double>(pb, pb->mg);
+        if (rc) return rc;
+    }
+    MGData* G = pb->mg;
+    CGState* st = pb->st;
+    RCHK(launch_fill(s, st, sizeof(CGState)));
+    std::vector<float> tmp;
+    if (mixed) {
+        tmp.resize((size_t)g.N);
+        for (int64_t e = 0; e < g.N; ++e) tmp[(size_t)e] = (float)r_host[e];
+        RCHK(hipMemcpyAsync(G->cr, tmp.data(), sizeof(float) * (size_t)g.N, hipMemcpyHostToDevice, s));
+        launch_vcycle<float>(s, pb, st);
+        RCHK(hipMemcpyAsync(tmp.data(), G->cz, sizeof(float) * (size_t)g.N, hipMemcpyDeviceToHost, s));
+        RCHK(hipStreamSynchronize(s));
+        for (int64_t e = 0; e < g.N; ++e) z_host[e] = tmp[(size_t)e];
+    } else {
+        RCHK(hipMemcpyAsync(G->cr, r_host, sizeof(double) * (size_t)g.N, hipMemcpyHostToDevice, s));
+        launch_vcycle<double>(s, pb, st);
+        RCHK(hipMemcpyAsync(z_host, G->cz, sizeof(double) * (size_t)g.N, hipMemcpyDeviceToHost, s));
+        RCHK(hipStreamSynchronize(s));
+    }
+    RCHK(hipGetLastError());
+    return PB_OK;
+}

@@ -406,6 +406,7 @@ int pb_submit(pb_server* s, const pb_params* prm, int64_t n_atoms, const double*
     if (!s || !prm) return pbi_fail(PB_EINVAL, "NULL argument");
     if (prm->precision != PB_MIXED) return pbi_fail(PB_EINVAL, "the serving loop runs the mixed form only");
     if (prm->refine) return pbi_fail(PB_EINVAL, "the serving loop runs uniform grids only");
+    if (prm->precond != PB_PRECOND_JACOBI) return pbi_fail(PB_EINVAL, "the serving loop runs Jacobi-CG only");
     if (n_atoms < 0 || (n_atoms > 0 && (!xyz || !radius || !charge))) return pbi_fail(PB_EINVAL, "bad atoms");
     Request q;
     q.prm = *prm;

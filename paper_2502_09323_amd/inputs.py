@@ -22,6 +22,7 @@ import numpy as np
 # Boundary-condition codes and precision codes (same values as the C header).
 BC_ZERO, BC_DH, BC_USER = 0, 1, 2
 FP64, MIXED = 0, 1
+JACOBI, MG = 0, 1            # preconditioners
 
 
 @dataclass
@@ -53,6 +54,10 @@ class GridSpec:
     refine_brick: int = 4     # ... rounded up to aligned bricks of this many cells per edge
     precision: int = FP64
     inner_rtol: float = 1e-4
+    precond: int = 0          # 0: Jacobi, 1: multigrid V-cycle (red-black Gauss-Seidel smoothing)
+    mg_smooth: int = 1        # multigrid: sweeps before and after the coarse correction
+    mg_coarse_sweeps: int = 4 # multigrid: symmetric sweeps on the coarsest level
+    mg_levels: int = 0        # multigrid: level cap (0 = as many as the grid allows)
     bc_values: np.ndarray | None = field(default=None, repr=False)  # BC_USER: full grid
 
     @property
