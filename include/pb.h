@@ -254,7 +254,9 @@ int pb_time_stencil(pb_problem* pb, int32_t reps, int32_t fp32, double* avg_ms);
 int pb_ctx_set_profiling(pb_ctx* ctx, int on);
 
 /* Average durations (ms) of the sampled stencil and update launches of the last pb_solve
- * (only iterations that did work are counted), and the number of samples. */
+ * (only iterations that did work are counted), and the number of samples.  For a
+ * PB_PRECOND_MG solve with more than one level: the first level-0 black half-sweep after the
+ * coarse correction, and the whole V-cycle. */
 int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples);
 
 /* Attainable-bandwidth reference: `reps` launches of a plain streaming copy of `bytes`

@@ -108,10 +108,11 @@ struct MGData {
     int nu = 1, cs = 4;         // sweeps per level and side, symmetric sweeps on the coarsest
     pbk::Grid g[PB_MG_MAX_LEVELS];
     void* K[PB_MG_MAX_LEVELS][3] = {};   // levels >= 1: K of the +x, +y, +z edges (element type)
-    void* dinv[PB_MG_MAX_LEVELS] = {};   // levels >= 1: 1 / diagonal
+    void* diag[PB_MG_MAX_LEVELS] = {};   // levels >= 1: diagonal
+    void* dinv[PB_MG_MAX_LEVELS] = {};   // 1 / diagonal (level 0 too)
     void* x[PB_MG_MAX_LEVELS] = {};      // iterate (level 0: the CG vector z)
     void* b[PB_MG_MAX_LEVELS] = {};      // right-hand side (level 0: the CG residual)
-    void* r[PB_MG_MAX_LEVELS] = {};      // residual at the red nodes
+    void* r[PB_MG_MAX_LEVELS] = {};      // residual at the red nodes (black entries 0)
     void *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;   // CG r, z, p, q
     void* cx = nullptr;         // CG x: the FP64 solution, or the FP32 correction (mixed)
     double* part = nullptr;     // [3 * nb] block partial sums

@@ -48,10 +48,10 @@ template <typename T>
 struct Lev {
     Grid g;
     const T *kx, *ky, *kz;   // levels >= 1: K of the +x, +y, +z edges
-    const T* dinv;           // levels >= 1: 1 / diagonal
+    const T* diag;           // levels >= 1: diagonal
+    const T* dinv;           // 1 / diagonal (every level)
     T* x;                    // iterate (level 0: the CG vector z)
     const T* b;              // right-hand side (level 0: the CG residual r)
-    T* r;                    // residual, formed at red nodes (black entries stay 0)
 };
 
 // the level-0 operator from the node-code map
@@ -62,44 +62,75 @@ struct Op0 {
     T kin, kout, mass;
 };
 
-// sum of K * x(neighbour) over the six edges of node e, and the diagonal there: level 0
-// gives D itself (inv = false), the coarser levels their stored 1 / D (inv = true)
-template <typename T, bool L0>
-__device__ __forceinline__ void nbr_sum(const Lev<T>& L, const Op0<T>& op, int64_t e, T& s, T& d)
+// sum over the six edges of node e of K * v(neighbour), and optionally the diagonal there
+template <typename T, bool L0, typename F>
+__device__ __forceinline__ T nsum(const Lev<T>& L, const Op0<T>& op, int64_t e, F v, T* D = nullptr)
 {
     const Grid& g = L.g;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    const T* x = L.x;
     if constexpr (L0) {
         const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-        s = ((k.xm * x[e - sx] + k.xp * x[e + sx]) + (k.ym * x[e - sy] + k.yp * x[e + sy])) +
-            (k.zm * x[e - 1] + k.zp * x[e + 1]);
-        d = k.diag();
+        if (D) *D = k.diag();
+        return ((k.xm * v(e - sx) + k.xp * v(e + sx)) + (k.ym * v(e - sy) + k.yp * v(e + sy))) +
+               (k.zm * v(e - 1) + k.zp * v(e + 1));
     } else {
-        s = ((L.kx[e - sx] * x[e - sx] + L.kx[e] * x[e + sx]) + (L.ky[e - sy] * x[e - sy] + L.ky[e] * x[e + sy])) +
-            (L.kz[e - 1] * x[e - 1] + L.kz[e] * x[e + 1]);
-        d = L.dinv[e];
+        if (D) *D = L.diag[e];
+        return ((L.kx[e - sx] * v(e - sx) + L.kx[e] * v(e + sx)) + (L.ky[e - sy] * v(e - sy) + L.ky[e] * v(e + sy))) +
+               (L.kz[e - 1] * v(e - 1) + L.kz[e] * v(e + 1));
     }
 }
 
-// Gauss-Seidel value (b + s) / D at a node
-template <typename T, bool L0>
-__device__ __forceinline__ T gs_value(T b, T s, T d)
+// Per-node kernels run on a 3-D grid of 256-thread blocks, 64 lanes along z by 4 rows along
+// y, one block layer per x-plane, so that no thread divides to find its node.  A colour
+// kernel gives lane m the m-th node of its colour in the row.
+inline dim3 node_grid(const Grid& g, bool colour)
 {
-    if constexpr (L0) return (b + s) / d;
-    return (b + s) * d;
+    const int nzl = colour ? (g.nz - 1) / 2 : g.nz - 2;   // nodes per interior row
+    return dim3((unsigned)std::max(1, (nzl + 63) / 64), (unsigned)((g.ny - 2 + 3) / 4), (unsigned)(g.nx - 2));
 }
 
-// node of colour c (0 red, 1 black) handled by thread t, or -1
-__device__ __forceinline__ int64_t colour_node(const Grid& g, int c, int64_t t)
+// interior node of this thread (all nodes), or -1; red tells its colour
+__device__ __forceinline__ int64_t this_node(const Grid& g, bool& red)
 {
-    const int M = (g.nz - 1) >> 1;   // at most this many nodes of one colour per interior z-row
-    const int64_t rows = (int64_t)(g.nx - 2) * (g.ny - 2);
+    const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int i = 1 + (int)blockIdx.z;
+    if (k > g.nz - 2 || j > g.ny - 2) return -1;
+    red = ((i + j + k) & 1) == 0;
+    return g.idx(i, j, k);
+}
+
+// interior node of colour c (0 red, 1 black) of this thread, or -1
+__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c)
+{
+    const int m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int i = 1 + (int)blockIdx.z;
+    const int k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
+    if (k > g.nz - 2 || j > g.ny - 2) return -1;
+    return g.idx(i, j, k);
+}
+
+// the same for the one-block coarsest solve: node t of colour c in (i, j, m) order
+__device__ __forceinline__ int64_t colour_node(const Grid& g, int c, int t)
+{
+    const int M = (g.nz - 1) >> 1;
+    const int rows = (g.nx - 2) * (g.ny - 2);
     if (M <= 0 || t >= rows * M) return -1;
-    const int row = (int)(t / M), m = (int)(t - (int64_t)row * M);
+    const int row = t / M, m = t - row * M;
     const int i = 1 + row / (g.ny - 2), j = 1 + row % (g.ny - 2);
     const int k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
     if (k > g.nz - 2) return -1;
+    return g.idx(i, j, k);
+}
+
+__device__ __forceinline__ int64_t interior_node(const Grid& g, int t, bool& red)
+{
+    const int nzi = g.nz - 2, nyi = g.ny - 2;
+    const int row = t / nzi;
+    const int k = 1 + (t - row * nzi);
+    const int i = 1 + row / nyi, j = 1 + row % nyi;
+    red = ((i + j + k) & 1) == 0;
     return g.idx(i, j, k);
 }
 
@@ -113,42 +144,25 @@ __host__ __device__ inline int64_t interior_count(const Grid& g)
     return (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
 }
 
-__device__ __forceinline__ int64_t interior_node(const Grid& g, int64_t t)
-{
-    const int nzi = g.nz - 2, nyi = g.ny - 2;
-    const int64_t row = t / nzi;
-    const int k = 1 + (int)(t - row * nzi);
-    const int i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
-    return g.idx(i, j, k);
-}
-
 __device__ __forceinline__ bool halted(const CGState* st) { return st && st->status != 0; }
 
-// first half-sweep from a zero iterate: red nodes b / D, black nodes 0
+// the first smoothing step from a zero iterate in one pass: red x = b / D, then black
+// x = (b + sum K x_red) / D with the red values formed on the fly
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_first(Lev<T> L, Op0<T> op, const CGState* st)
+__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, const CGState* st)
 {
     if (halted(st)) return;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= interior_count(L.g)) return;
-    const int64_t e = interior_node(L.g, t);
-    int i, j, k;
-    {
-        const int nzi = L.g.nz - 2, nyi = L.g.ny - 2;
-        const int64_t row = t / nzi;
-        k = 1 + (int)(t - row * nzi);
-        i = 1 + (int)(row / nyi);
-        j = 1 + (int)(row % nyi);
-    }
-    if ((i + j + k) & 1) {
-        L.x[e] = (T)0;
+    bool red;
+    const int64_t e = this_node(L.g, red);
+    if (e < 0) return;
+    const T* __restrict__ b = L.b;
+    const T* __restrict__ dinv = L.dinv;
+    if (red) {
+        L.x[e] = b[e] * dinv[e];
         return;
     }
-    if constexpr (L0) {
-        L.x[e] = L.b[e] / stencil::node_k(L.g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
-    } else {
-        L.x[e] = L.b[e] * L.dinv[e];
-    }
+    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return b[n] * dinv[n]; });
+    L.x[e] = (b[e] + s) * dinv[e];
 }
 
 // Gauss-Seidel on the nodes of one colour
@@ -156,38 +170,38 @@ template <typename T, bool L0>
 __global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, const CGState* st)
 {
     if (halted(st)) return;
-    const int64_t e = colour_node(L.g, c, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    const int64_t e = this_colour_node(L.g, c);
     if (e < 0) return;
-    T s, d;
-    nbr_sum<T, L0>(L, op, e, s, d);
-    L.x[e] = gs_value<T, L0>(L.b[e], s, d);
+    const T* __restrict__ x = L.x;
+    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; });
+    L.x[e] = (L.b[e] + s) * L.dinv[e];
 }
 
-// residual b - A x at the red nodes (after a black half-sweep the black residual is zero)
+// residual b - A x at the red nodes (after a black half-sweep the black residual is zero,
+// and the black entries of r stay 0)
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, const CGState* st)
+__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restrict__ r, const CGState* st)
 {
     if (halted(st)) return;
-    const int64_t e = colour_node(L.g, 0, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    const int64_t e = this_colour_node(L.g, 0);
     if (e < 0) return;
-    T s, d;
-    nbr_sum<T, L0>(L, op, e, s, d);
-    const T ax = L0 ? d * L.x[e] - s : L.x[e] / d - s;
-    L.r[e] = L.b[e] - ax;
+    const T* __restrict__ x = L.x;
+    T D;
+    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; }, &D);
+    r[e] = L.b[e] - (D * x[e] - s);
 }
 
-// coarse right-hand side P^T r: node 2I and its 12 red neighbours (two odd offsets, weight
-// 1/4); the other 14 of the 27 are black, where r is zero
+// coarse right-hand side P^T r: fine node 2I and its 12 red neighbours (two odd offsets,
+// weight 1/4); the other 14 of the 27 are black, where r is zero
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
                                                   const CGState* st)
 {
     if (halted(st)) return;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= interior_count(gc)) return;
-    const int nzi = gc.nz - 2, nyi = gc.ny - 2;
-    const int64_t row = t / nzi;
-    const int K = 1 + (int)(t - row * nzi), I = 1 + (int)(row / nyi), J = 1 + (int)(row % nyi);
+    const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int I = 1 + (int)blockIdx.z;
+    if (K > gc.nz - 2 || J > gc.ny - 2) return;
     const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
     const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
     const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
@@ -196,21 +210,27 @@ __global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__
     bc[gc.idx(I, J, K)] = r[f] + (T)0.25 * ((xy + xz) + yz);
 }
 
-// x += P e (trilinear from the coarse corners)
+// P e at fine node (i, j, k): trilinear from the coarse corners of its coarse cell
+template <typename T>
+__device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec, int i, int j, int k)
+{
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+    const T v = ((ec[gc.idx(i0, j0, k0)] + ec[gc.idx(i0, j0, k1)]) + (ec[gc.idx(i0, j1, k0)] + ec[gc.idx(i0, j1, k1)])) +
+                ((ec[gc.idx(i1, j0, k0)] + ec[gc.idx(i1, j0, k1)]) + (ec[gc.idx(i1, j1, k0)] + ec[gc.idx(i1, j1, k1)]));
+    return (T)0.125 * v;
+}
+
+// x += P e
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
                                                  const CGState* st)
 {
     if (halted(st)) return;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= interior_count(gf)) return;
-    const int nzi = gf.nz - 2, nyi = gf.ny - 2;
-    const int64_t row = t / nzi;
-    const int k = 1 + (int)(t - row * nzi), i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
-    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-    const T v = ((ec[gc.idx(i0, j0, k0)] + ec[gc.idx(i0, j0, k1)]) + (ec[gc.idx(i0, j1, k0)] + ec[gc.idx(i0, j1, k1)])) +
-                ((ec[gc.idx(i1, j0, k0)] + ec[gc.idx(i1, j0, k1)]) + (ec[gc.idx(i1, j1, k0)] + ec[gc.idx(i1, j1, k1)]));
-    x[gf.idx(i, j, k)] += (T)0.125 * v;
+    const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int i = 1 + (int)blockIdx.z;
+    if (k > gf.nz - 2 || j > gf.ny - 2) return;
+    x[gf.idx(i, j, k)] += prolong_at(gc, ec, i, j, k);
 }
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
@@ -219,32 +239,33 @@ __global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, con
 {
     if (halted(st)) return;
     const Grid& g = L.g;
-    const int64_t n = interior_count(g), nc = colour_threads(g);
-    for (int64_t t = threadIdx.x; t < n; t += 256) {
-        const int64_t e = interior_node(g, t);
-        const int nzi = g.nz - 2, nyi = g.ny - 2;
-        const int64_t row = t / nzi;
-        const int k = 1 + (int)(t - row * nzi), i = 1 + (int)(row / nyi), j = 1 + (int)(row % nyi);
-        if ((i + j + k) & 1) {
-            L.x[e] = (T)0;
-        } else if constexpr (L0) {
-            L.x[e] = L.b[e] / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
-        } else {
-            L.x[e] = L.b[e] * L.dinv[e];
-        }
+    const int n = (int)interior_count(g), nc = (int)colour_threads(g);
+    for (int t = threadIdx.x; t < n; t += 256) {
+        bool red;
+        const int64_t e = interior_node(g, t, red);
+        L.x[e] = red ? L.b[e] * L.dinv[e] : (T)0;
     }
     __syncthreads();
+    const T* __restrict__ x = L.x;
     for (int s = 0; s < 2 * cs; ++s) {
         const int c = (s & 1) ? 0 : 1;
-        for (int64_t t = threadIdx.x; t < nc; t += 256) {
+        for (int t = threadIdx.x; t < nc; t += 256) {
             const int64_t e = colour_node(g, c, t);
             if (e < 0) continue;
-            T sum, d;
-            nbr_sum<T, L0>(L, op, e, sum, d);
-            L.x[e] = gs_value<T, L0>(L.b[e], sum, d);
+            const T sum = nsum<T, L0>(L, op, e, [&](int64_t m) { return x[m]; });
+            L.x[e] = (L.b[e] + sum) * L.dinv[e];
         }
         __syncthreads();
     }
+}
+
+// 1 / diagonal of the level-0 unknowns (0 elsewhere)
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag0(Grid g, Op0<T> op, T* __restrict__ dinv)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
+        dinv[e] = (op.code[e] & C_BOX) ? (T)0
+                                       : (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
 }
 
 // ---- hierarchy set-up (FP64) ------------------------------------------------------------
@@ -319,7 +340,7 @@ __global__ void __launch_bounds__(256) k_coarsen(FineSrc F, Grid gc, double* kx,
 // 1 / diagonal at the interior nodes of a coarse level, and the element-type copies
 template <typename T>
 __global__ void __launch_bounds__(256) k_level_diag(Grid g, const double* kx, const double* ky, const double* kz,
-                                                    const double* m, T* kxT, T* kyT, T* kzT, T* dinvT)
+                                                    const double* m, T* kxT, T* kyT, T* kzT, T* diagT, T* dinvT)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -329,12 +350,13 @@ __global__ void __launch_bounds__(256) k_level_diag(Grid g, const double* kx, co
     kxT[e] = (T)kx[e];
     kyT[e] = (T)ky[e];
     kzT[e] = (T)kz[e];
-    double d = 0.0;
+    double D = 0.0, d = 0.0;
     if (i >= 1 && i <= g.nx - 2 && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2) {
         const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-        const double D = ((kx[e - sx] + kx[e]) + (ky[e - sy] + ky[e])) + ((kz[e - 1] + kz[e]) + m[e]);
+        D = ((kx[e - sx] + kx[e]) + (ky[e - sy] + ky[e])) + ((kz[e - 1] + kz[e]) + m[e]);
         d = 1.0 / D;
     }
+    diagT[e] = (T)D;
     dinvT[e] = (T)d;
 }
 
@@ -587,10 +609,10 @@ Lev<T> level(const MGData* G, int l)
     L.kx = (const T*)G->K[l][0];
     L.ky = (const T*)G->K[l][1];
     L.kz = (const T*)G->K[l][2];
+    L.diag = (const T*)G->diag[l];
     L.dinv = (const T*)G->dinv[l];
     L.x = (T*)G->x[l];
     L.b = (const T*)G->b[l];
-    L.r = (T*)G->r[l];
     return L;
 }
 
@@ -610,30 +632,36 @@ Op0<T> op0(const pb_problem* pb)
 }
 
 template <typename T, bool L0>
-void launch_smooth_first(hipStream_t s, const Lev<T>& L, const Op0<T>& op, const CGState* st)
-{
-    k_first<T, L0><<<nblk(interior_count(L.g), 256), 256, 0, s>>>(L, op, st);
-}
-
-template <typename T, bool L0>
 void launch_sweep(hipStream_t s, const Lev<T>& L, const Op0<T>& op, int c, const CGState* st)
 {
-    const int64_t n = colour_threads(L.g);
-    if (n > 0) k_sweep<T, L0><<<nblk(n, 256), 256, 0, s>>>(L, op, c, st);
+    if (colour_threads(L.g) > 0) k_sweep<T, L0><<<node_grid(L.g, true), 256, 0, s>>>(L, op, c, st);
 }
 
-// pre-smoothing (red, black) x nu from zero, residual, restriction to level l+1
+// pre-smoothing (red, black) x nu from zero
 template <typename T, bool L0>
-void launch_down(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const CGState* st)
 {
-    launch_smooth_first<T, L0>(s, L, op, st);
-    launch_sweep<T, L0>(s, L, op, 1, st);
-    for (int v = 1; v < G->nu; ++v) {
+    k_down1<T, L0><<<node_grid(L.g, false), 256, 0, s>>>(L, op, st);
+    for (int v = 1; v < nu; ++v) {
         launch_sweep<T, L0>(s, L, op, 0, st);
         launch_sweep<T, L0>(s, L, op, 1, st);
     }
-    const int64_t n = colour_threads(L.g);
-    if (n > 0) k_resid<T, L0><<<nblk(n, 256), 256, 0, s>>>(L, op, st);
+}
+
+// coarse correction and post-smoothing (black, red) x nu
+template <typename T, bool L0>
+void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const Grid& gc, const T* ec,
+                 const CGState* st, hipEvent_t* ev = nullptr)
+{
+    k_prolong<T><<<node_grid(L.g, false), 256, 0, s>>>(L.g, L.x, gc, ec, st);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    launch_sweep<T, L0>(s, L, op, 1, st);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    launch_sweep<T, L0>(s, L, op, 0, st);
+    for (int v = 1; v < nu; ++v) {
+        launch_sweep<T, L0>(s, L, op, 1, st);
+        launch_sweep<T, L0>(s, L, op, 0, st);
+    }
 }
 
 template <typename T, bool L0>
@@ -643,16 +671,20 @@ void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<
         k_coarse<T, L0><<<1, 256, 0, s>>>(L, op, G->cs, st);
         return;
     }
-    launch_smooth_first<T, L0>(s, L, op, st);
-    for (int v = 0; v < G->cs; ++v) {
+    // red, black in one pass, then red, then (black, red) x (cs - 1)
+    launch_pre<T, L0>(s, 1, L, op, st);
+    launch_sweep<T, L0>(s, L, op, 0, st);
+    for (int v = 1; v < G->cs; ++v) {
         launch_sweep<T, L0>(s, L, op, 1, st);
         launch_sweep<T, L0>(s, L, op, 0, st);
     }
 }
 
-// z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r)
+// z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r); with ev, events around
+// the whole V-cycle (ev[0], ev[3]) and around the first level-0 black half-sweep after the
+// coarse correction (ev[1], ev[2])
 template <typename T>
-void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st)
+void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
     const Op0<T> op = op0<T>(pb);
@@ -661,30 +693,30 @@ void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st)
         launch_coarsest<T, true>(s, G, level<T>(G, 0), op, st);
         return;
     }
+    if (ev) (void)hipEventRecord(ev[0], s);
     for (int l = 0; l + 1 < L; ++l) {
         const Lev<T> lv = level<T>(G, l);
-        if (l == 0)
-            launch_down<T, true>(s, G, lv, op, st);
-        else
-            launch_down<T, false>(s, G, lv, op, st);
         const Grid& gc = G->g[l + 1];
-        k_restrict<T><<<nblk(interior_count(gc), 256), 256, 0, s>>>(lv.g, lv.r, gc, (T*)G->b[l + 1], st);
+        T* r = (T*)G->r[l];
+        if (l == 0) {
+            launch_pre<T, true>(s, G->nu, lv, op, st);
+            k_resid<T, true><<<node_grid(lv.g, true), 256, 0, s>>>(lv, op, r, st);
+        } else {
+            launch_pre<T, false>(s, G->nu, lv, op, st);
+            k_resid<T, false><<<node_grid(lv.g, true), 256, 0, s>>>(lv, op, r, st);
+        }
+        k_restrict<T><<<node_grid(gc, false), 256, 0, s>>>(lv.g, r, gc, (T*)G->b[l + 1], st);
     }
     launch_coarsest<T, false>(s, G, level<T>(G, L - 1), op, st);
     for (int l = L - 2; l >= 0; --l) {
         const Lev<T> lv = level<T>(G, l);
-        k_prolong<T><<<nblk(interior_count(lv.g), 256), 256, 0, s>>>(lv.g, lv.x, G->g[l + 1], (const T*)G->x[l + 1],
-                                                                      st);
-        for (int v = 0; v < G->nu; ++v) {
-            if (l == 0) {
-                launch_sweep<T, true>(s, lv, op, 1, st);
-                launch_sweep<T, true>(s, lv, op, 0, st);
-            } else {
-                launch_sweep<T, false>(s, lv, op, 1, st);
-                launch_sweep<T, false>(s, lv, op, 0, st);
-            }
-        }
+        const T* ec = (const T*)G->x[l + 1];
+        if (l == 0)
+            launch_post<T, true>(s, G->nu, lv, op, G->g[1], ec, st, ev);
+        else
+            launch_post<T, false>(s, G->nu, lv, op, G->g[l + 1], ec, st);
     }
+    if (ev) (void)hipEventRecord(ev[3], s);
 }
 
 template <typename T>
@@ -736,10 +768,13 @@ int setup_levels(pb_problem* pb, MGData* G)
             G->K[l][d] = kT[d];
         }
         T* dT = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
-        if (!dT) return pbi_fail(PB_ENOMEM, "multigrid levels");
+        T* DT = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
+        if (!dT || !DT) return pbi_fail(PB_ENOMEM, "multigrid levels");
         RCHK(launch_fill(s, dT, sizeof(T) * (size_t)gc.N));
+        RCHK(launch_fill(s, DT, sizeof(T) * (size_t)gc.N));
         G->dinv[l] = dT;
-        k_level_diag<T><<<nblk(nn, 256), 256, 0, s>>>(gc, kx, ky, kz, m, kT[0], kT[1], kT[2], dT);
+        G->diag[l] = DT;
+        k_level_diag<T><<<nblk(nn, 256), 256, 0, s>>>(gc, kx, ky, kz, m, kT[0], kT[1], kT[2], DT, dT);
         RCHK(hipGetLastError());
         pkx = kx;
         pky = ky;
@@ -751,13 +786,20 @@ int setup_levels(pb_problem* pb, MGData* G)
     // level vectors (level 0: x and b are the CG vectors z and r)
     for (int l = 0; l < G->nlev; ++l) {
         const Grid& g = G->g[l];
-        const int nv = l == 0 ? 1 : 3;
         void** dst[3] = {&G->r[l], &G->x[l], &G->b[l]};
-        for (int v = 0; v < nv; ++v) {
+        for (int v = 0; v < (l == 0 ? 1 : 3); ++v) {
             *dst[v] = pb->mem.get(sizeof(T) * (size_t)g.N);
             if (!*dst[v]) return pbi_fail(PB_ENOMEM, "multigrid vectors");
             RCHK(launch_fill(s, *dst[v], sizeof(T) * (size_t)g.N));
         }
+    }
+    // 1 / diagonal of level 0
+    {
+        T* d0 = (T*)pb->mem.get(sizeof(T) * (size_t)pb->g.N);
+        if (!d0) return pbi_fail(PB_ENOMEM, "multigrid vectors");
+        k_diag0<T><<<(unsigned)std::min<int64_t>(65536, nblk(pb->g.N, 256)), 256, 0, s>>>(pb->g, op0<T>(pb), d0);
+        RCHK(hipGetLastError());
+        G->dinv[0] = d0;
     }
     const Grid& g0 = pb->g;
     void** cg[5] = {&G->cr, &G->cz, &G->cp, &G->cq, &G->cx};
@@ -770,7 +812,7 @@ int setup_levels(pb_problem* pb, MGData* G)
     if (sizeof(T) == 8) G->cx = pb->x;
     G->x[0] = G->cz;
     G->b[0] = G->cr;
-    G->nb = (int)std::min<int64_t>(2048, (int64_t)nblk(g0.N, 256));
+    G->nb = (int)std::min<int64_t>(8192, (int64_t)nblk(g0.N, 256));
     G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
     if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
     RCHK(hipStreamSynchronize(s));
@@ -778,7 +820,7 @@ int setup_levels(pb_problem* pb, MGData* G)
 }
 
 template <typename T>
-void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st)
+void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
     const Grid& g = pb->g;
@@ -788,7 +830,7 @@ void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st)
     k_apply<T><<<G->nb, 256, 0, s>>>(g, op, p, q, G->part, st);
     k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
     k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p, q, G->part, G->nb, st);
-    launch_vcycle<T>(s, pb, st);
+    launch_vcycle<T>(s, pb, st, ev);
     k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, st);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0);
 }
@@ -839,9 +881,26 @@ int solve_t(pb_problem* pb, CGState* out)
     const int M = 8;
     int launched = 0;
     bool breakdown = false;
+    // sampled timings (context profiling on): every 4th iteration while the V-cycle has
+    // more than one level
+    const bool prof = pb->ctx->profile != 0 && G->nlev > 1;
+    std::vector<hipEvent_t> evs;
+    std::vector<int> ev_it;
     while (h.status == 0 && launched < P.max_iter) {
         const int n = std::min(M, P.max_iter - launched);
-        for (int it = 0; it < n; ++it) launch_iteration<T>(s, pb, st);
+        for (int it = 0; it < n; ++it) {
+            hipEvent_t* ev = nullptr;
+            if (prof && (launched + it) % 4 == 0 && evs.size() < 4 * 128) {
+                for (int e = 0; e < 4; ++e) {
+                    hipEvent_t x;
+                    RCHK(hipEventCreate(&x));
+                    evs.push_back(x);
+                }
+                ev_it.push_back(h.iter_count + it);
+                ev = &evs[evs.size() - 4];
+            }
+            launch_iteration<T>(s, pb, st, ev);
+        }
         RCHK(hipGetLastError());
         launched += n;
         RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -859,6 +918,20 @@ int solve_t(pb_problem* pb, CGState* out)
     RCHK(hipMemcpyAsync(out, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
     if (breakdown && out->status != 1) out->status = 2;
+    if (prof) {
+        // only iterations that ran: the sampled iteration count is below the final one
+        const int done = out->iter_count;
+        for (size_t k = 0; k < ev_it.size(); ++k) {
+            if (ev_it[k] >= done) continue;
+            float a = 0, b = 0;
+            RCHK(hipEventElapsedTime(&a, evs[4 * k + 1], evs[4 * k + 2]));
+            RCHK(hipEventElapsedTime(&b, evs[4 * k], evs[4 * k + 3]));
+            pb->prof_stencil_ms += a;
+            pb->prof_update_ms += b;
+            pb->prof_n += 1;
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
+    }
     return PB_OK;
 }
 

@@ -11,11 +11,16 @@
 namespace pbk {
 namespace stencil {
 
+// The table is read for every edge (entry 0 for an uncut one) and the result blended
+// arithmetically, so that no load sits behind a branch.
 template <typename T>
 __device__ __forceinline__ T edgeK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
 {
-    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
-    return (c & C_SOLUTE) ? kin : kout;
+    const bool cut = (c & (C_CUTX << ax)) != 0;
+    const T v = ck[cut ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0];
+    const T base = (c & C_SOLUTE) ? kin : kout;
+    const T m = cut ? (T)1 : (T)0;
+    return v * m + base * ((T)1 - m);
 }
 
 // the six edge weights of node e (x-, x+, y-, y+, z-, z+) and its ionic term
