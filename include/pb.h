@@ -275,14 +275,16 @@ size_t pb_problem_bytes(const pb_problem* pb);
  * stream, coefficient builds and energy read-backs on build_ctx's stream (same device).
  * Requests are admitted first-come first-served once arrived, while at most max_resident
  * problems are resident and ctx's hbm_budget_bytes (if non-zero) is not exceeded; all
- * resident problems advance together, 16 CG iterations per batched chunk.
+ * resident problems advance together, 16 CG iterations per batched chunk.  Requests with
+ * precond = PB_PRECOND_MG run their 16 iterations as their own launches after the batched
+ * ones (the results equal those of a solve of the same request alone).
  * Errors: PB_EINVAL, PB_EDEVICE. */
 int pb_server_create(pb_ctx* ctx, pb_ctx* build_ctx, int32_t max_resident, pb_server** out);
 
 /* Seconds since the server was created (the clock of arrival and completion times). */
 double pb_server_now(const pb_server* srv);
 
-/* Queue a request (copied; params->precision must be PB_MIXED).  It becomes eligible for
+/* Queue a request (copied; params->precision must be PB_MIXED, refine 0).  It becomes eligible for
  * admission once pb_server_now() >= arrival_time_s.  A request whose estimated memory
  * exceeds the whole budget completes with code PB_ENOMEM. */
 int pb_submit(pb_server* srv, const pb_params* params, int64_t n_atoms, const double* xyz,

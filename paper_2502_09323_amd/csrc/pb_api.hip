@@ -334,7 +334,9 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     if (!rc) pb->e_tmp[2] = dalloc<double>(pb, na1, &rc);                      // reaction potentials
     if (!rc) pb->e_tmp[3] = dalloc<double>(pb, 16, &rc);                       // energy sums
     if (rc) return rc;
-    if (finish_mixed) {
+    if (finish_mixed && pb->mg) {
+        if ((rc = pbi_mg_finish(pb, s))) return rc;
+    } else if (finish_mixed) {
         HIPCHK(launch_ru_add(s, pb->g, pb->st, pb->x, pb->d32, pb->p32, 1));
         HIPCHK(launch_ru_residual(s, pb->g, pb->code, pb->ck64, pb->ck32, pb->cf, pb->rhs, pb->x, pb->z32,
                                   pb->part_res, pb->st));

@@ -194,6 +194,13 @@ int pbi_refine_solve(pb_problem* pb, pbk::CGState* out);
 
 // multigrid-preconditioned CG (pb_mg.hip)
 int pbi_mg_solve(pb_problem* pb, pbk::CGState* out);
+// the same in steps for the serving loop, all enqueued on stream s: the level hierarchy,
+// then chunks of n iterations (first: x = 0 and the first residual before them), each
+// followed by the restart from the true residual where one is due; finish folds a leftover
+// FP32 correction into the solution
+int pbi_mg_begin(pb_problem* pb, hipStream_t s);
+int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first);
+int pbi_mg_finish(pb_problem* pb, hipStream_t s);
 int pbi_mg_levels(const pb_problem* pb);
 // one V-cycle on a vector over the padded level-0 layout (host arrays of g.N doubles)
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host);

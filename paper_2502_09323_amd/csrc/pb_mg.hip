@@ -144,12 +144,20 @@ __host__ __device__ inline int64_t interior_count(const Grid& g)
     return (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
 }
 
-__device__ __forceinline__ bool halted(const CGState* st) { return st && st->status != 0; }
+// which kernels of a chain run: those of a CG iteration (ru = 0) while the solve is running,
+// those of a restart from the true residual (ru = 1) only while one is in progress; with no
+// state (a V-cycle applied on its own) always
+struct Gate {
+    const CGState* st;
+    int ru;
+};
+
+__device__ __forceinline__ bool halted(const Gate& g) { return g.st && (g.st->status != 0 || g.st->ru != g.ru); }
 
 // the first smoothing step from a zero iterate in one pass: red x = b / D, then black
 // x = (b + sum K x_red) / D with the red values formed on the fly
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, const CGState* st)
+__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, Gate st)
 {
     if (halted(st)) return;
     bool red;
@@ -167,7 +175,7 @@ __global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, const CGStat
 
 // Gauss-Seidel on the nodes of one colour
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, const CGState* st)
+__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, Gate st)
 {
     if (halted(st)) return;
     const int64_t e = this_colour_node(L.g, c);
@@ -180,7 +188,7 @@ __global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, const
 // residual b - A x at the red nodes (after a black half-sweep the black residual is zero,
 // and the black entries of r stay 0)
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restrict__ r, const CGState* st)
+__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restrict__ r, Gate st)
 {
     if (halted(st)) return;
     const int64_t e = this_colour_node(L.g, 0);
@@ -195,7 +203,7 @@ __global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restric
 // weight 1/4); the other 14 of the 27 are black, where r is zero
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
-                                                  const CGState* st)
+                                                  Gate st)
 {
     if (halted(st)) return;
     const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
@@ -223,7 +231,7 @@ __device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec
 // x += P e
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
-                                                 const CGState* st)
+                                                 Gate st)
 {
     if (halted(st)) return;
     const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
@@ -235,7 +243,7 @@ __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Gri
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
 template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, const CGState* st)
+__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, Gate st)
 {
     if (halted(st)) return;
     const Grid& g = L.g;
@@ -450,10 +458,10 @@ __global__ void __launch_bounds__(256) k_update(Grid g, const uint32_t* __restri
 // partial sums of r.z
 template <typename T>
 __global__ void __launch_bounds__(256) k_dot(Grid g, const uint32_t* __restrict__ code, const T* __restrict__ r,
-                                             const T* __restrict__ z, double* part, const CGState* st)
+                                             const T* __restrict__ z, double* part, Gate st)
 {
     __shared__ double sh[8];
-    if (st->status != 0) return;
+    if (halted(st)) return;
     double v[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
         if (!(code[e] & C_BOX)) v[0] += (double)r[e] * (double)z[e];
@@ -468,7 +476,7 @@ __global__ void __launch_bounds__(256) k_dot(Grid g, const uint32_t* __restrict_
 __global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode)
 {
     __shared__ double sh[8];
-    if (st->status != 0) return;
+    if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
     double v[2] = {0.0, 0.0};
     for (int t = threadIdx.x; t < nb; t += 256) {
         v[0] += part[t];
@@ -491,12 +499,14 @@ __global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGStat
             }
         } else if (mode == 1) {
             st->beta = 0.0;
+            st->ru = 0;
         } else {
             st->beta = (st->gamma > 0.0 && st->beta > 0.0) ? gm * (st->beta / st->gamma) : 0.0;
+            st->ru = 0;
         }
         st->gamma = gm;
         // the V-cycle is positive definite: r.z > 0 unless r = 0
-        if (st->status == 0 && (!isfinite(gm) || !(gm > 0.0))) {
+        if (!isfinite(gm) || !(gm > 0.0)) {
             st->status = 2;
             st->iters = st->iter_count;
         }
@@ -505,8 +515,9 @@ __global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGStat
 
 // mixed precision: x64 += x32, x32 = 0
 __global__ void __launch_bounds__(256) k_fold(Grid g, const uint32_t* __restrict__ code, double* __restrict__ x64,
-                                              float* __restrict__ x32)
+                                              float* __restrict__ x32, const CGState* st, int force)
 {
+    if (!force && st->status != 3) return;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
         if (!(code[e] & C_BOX)) {
             x64[e] += (double)x32[e];
@@ -518,9 +529,11 @@ __global__ void __launch_bounds__(256) k_fold(Grid g, const uint32_t* __restrict
 // of the FP64 r.r in the third slot range
 template <typename T>
 __global__ void __launch_bounds__(256) k_true_res(Grid g, Op0<double> op, const double* __restrict__ x,
-                                                  const double* __restrict__ b, T* __restrict__ r, double* part, int nb)
+                                                  const double* __restrict__ b, T* __restrict__ r, double* part, int nb,
+                                                  const CGState* st, int force)
 {
     __shared__ double sh[8];
+    if (!force && st->status != 3) return;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
     double v[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
@@ -536,11 +549,13 @@ __global__ void __launch_bounds__(256) k_true_res(Grid g, Op0<double> op, const 
     if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = v[0];
 }
 
-// after a true residual: the FP64 norm decides convergence; with init it sets the goals
+// after a true residual: the FP64 norm decides convergence; with init it sets the goals.  A
+// restart that goes on sets ru, which lets the V-cycle, r.z and beta of the restart run.
 __global__ void __launch_bounds__(256) k_ru_fin(const double* part, int nb, CGState* st, int init, int mixed,
-                                                double rtol2, double delta2)
+                                                double rtol2, double delta2, int force)
 {
     __shared__ double sh[8];
+    if (!force && st->status != 3) return;
     double v[1] = {0.0};
     for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[2 * nb + t];
     bsum(v, 1, sh);
@@ -569,6 +584,7 @@ __global__ void __launch_bounds__(256) k_ru_fin(const double* part, int nb, CGSt
         } else {
             st->status = 0;
         }
+        st->ru = st->status == 0 ? 1 : 0;
     }
 }
 
@@ -632,14 +648,14 @@ Op0<T> op0(const pb_problem* pb)
 }
 
 template <typename T, bool L0>
-void launch_sweep(hipStream_t s, const Lev<T>& L, const Op0<T>& op, int c, const CGState* st)
+void launch_sweep(hipStream_t s, const Lev<T>& L, const Op0<T>& op, int c, Gate st)
 {
     if (colour_threads(L.g) > 0) k_sweep<T, L0><<<node_grid(L.g, true), 256, 0, s>>>(L, op, c, st);
 }
 
 // pre-smoothing (red, black) x nu from zero
 template <typename T, bool L0>
-void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, Gate st)
 {
     k_down1<T, L0><<<node_grid(L.g, false), 256, 0, s>>>(L, op, st);
     for (int v = 1; v < nu; ++v) {
@@ -651,7 +667,7 @@ void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const 
 // coarse correction and post-smoothing (black, red) x nu
 template <typename T, bool L0>
 void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const Grid& gc, const T* ec,
-                 const CGState* st, hipEvent_t* ev = nullptr)
+                 Gate st, hipEvent_t* ev = nullptr)
 {
     k_prolong<T><<<node_grid(L.g, false), 256, 0, s>>>(L.g, L.x, gc, ec, st);
     if (ev) (void)hipEventRecord(ev[1], s);
@@ -665,7 +681,7 @@ void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const
 }
 
 template <typename T, bool L0>
-void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, const CGState* st)
+void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, Gate st)
 {
     if (interior_count(L.g) <= kOneBlockCoarse) {
         k_coarse<T, L0><<<1, 256, 0, s>>>(L, op, G->cs, st);
@@ -684,7 +700,7 @@ void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<
 // the whole V-cycle (ev[0], ev[3]) and around the first level-0 black half-sweep after the
 // coarse correction (ev[1], ev[2])
 template <typename T>
-void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st, hipEvent_t* ev = nullptr)
+void launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
     const Op0<T> op = op0<T>(pb);
@@ -719,10 +735,11 @@ void launch_vcycle(hipStream_t s, const pb_problem* pb, const CGState* st, hipEv
     if (ev) (void)hipEventRecord(ev[3], s);
 }
 
+// the level hierarchy and the solver vectors, enqueued on stream s (no host wait); the FP64
+// coefficients the element-type copies are rounded from stay allocated with the problem
 template <typename T>
-int setup_levels(pb_problem* pb, MGData* G)
+int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
 {
-    hipStream_t s = pb->ctx->stream;
     const pb_params& P = pb->prm;
     G->g[0] = pb->g;
     G->nlev = 1;
@@ -781,8 +798,6 @@ int setup_levels(pb_problem* pb, MGData* G)
         pkz = kz;
         pm = m;
     }
-    RCHK(hipStreamSynchronize(s));
-    for (double* p : tmp) pb->mem.put(p);
     // level vectors (level 0: x and b are the CG vectors z and r)
     for (int l = 0; l < G->nlev; ++l) {
         const Grid& g = G->g[l];
@@ -815,7 +830,7 @@ int setup_levels(pb_problem* pb, MGData* G)
     G->nb = (int)std::min<int64_t>(8192, (int64_t)nblk(g0.N, 256));
     G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
     if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
-    RCHK(hipStreamSynchronize(s));
+    RCHK(hipGetLastError());
     return PB_OK;
 }
 
@@ -826,100 +841,130 @@ void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent
     const Grid& g = pb->g;
     const Op0<T> op = op0<T>(pb);
     T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p = (T*)G->cp, *q = (T*)G->cq;
+    const Gate gate{st, 0};
     k_pupd<T><<<G->nb, 256, 0, s>>>(g, pb->code, z, p, st);
     k_apply<T><<<G->nb, 256, 0, s>>>(g, op, p, q, G->part, st);
     k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
     k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p, q, G->part, G->nb, st);
-    launch_vcycle<T>(s, pb, st, ev);
-    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, st);
+    launch_vcycle<T>(s, pb, gate, ev);
+    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, gate);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0);
 }
 
-// true residual from the FP64 solution (mixed: after folding the FP32 correction into it),
-// then z = V-cycle(r) and r.z; mode 1 starts the recurrence, mode 2 restarts it
+// restart from the true residual: fold the FP32 correction into the FP64 solution (mixed),
+// r = b - A x in FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the
+// state (init: the first residual, x = 0); otherwise only where the iteration stopped with
+// status 3 (the FP32 residual reached its goal or fell by inner_rtol).
 template <typename T>
-void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init)
+void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init, int force)
 {
     const MGData* G = pb->mg;
     const Grid& g = pb->g;
     const pb_params& P = pb->prm;
     const bool mixed = sizeof(T) == 4;
-    if (mixed) k_fold<<<G->nb, 256, 0, s>>>(g, pb->code, pb->x, (float*)G->cx);
+    if (mixed) k_fold<<<G->nb, 256, 0, s>>>(g, pb->code, pb->x, (float*)G->cx, st, force);
     const Op0<double> op64 = op0<double>(pb);
-    k_true_res<T><<<G->nb, 256, 0, s>>>(g, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb);
-    k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol,
-                               P.inner_rtol * P.inner_rtol);
-    launch_vcycle<T>(s, pb, st);
-    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, st);
+    k_true_res<T><<<G->nb, 256, 0, s>>>(g, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb, st, force);
+    k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol,
+                               force);
+    const Gate gate{st, 1};
+    launch_vcycle<T>(s, pb, gate);
+    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, gate);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2);
 }
 
 template <typename T>
-int solve_t(pb_problem* pb, CGState* out)
+int begin_t(pb_problem* pb, hipStream_t s)
 {
-    hipStream_t s = pb->ctx->stream;
     const pb_params& P = pb->prm;
-    const bool mixed = sizeof(T) == 4;
     if (!pb->mg) {
         pb->mg = new MGData();
         pb->mg->nu = P.mg_smooth > 0 ? P.mg_smooth : 1;
         pb->mg->cs = P.mg_coarse_sweeps > 0 ? P.mg_coarse_sweeps : 4;
-        const int rc = setup_levels<T>(pb, pb->mg);
+        const int rc = setup_levels<T>(pb, pb->mg, s);
         if (rc) return rc;
     }
+    return PB_OK;
+}
+
+// x = 0 and the first residual, enqueued on s
+template <typename T>
+int start_t(pb_problem* pb, hipStream_t s)
+{
     MGData* G = pb->mg;
-    CGState* st = pb->st;
     RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
-    if (mixed) RCHK(launch_fill(s, G->cx, sizeof(float) * (size_t)pb->g.N));
+    if (sizeof(T) == 4) RCHK(launch_fill(s, G->cx, sizeof(float) * (size_t)pb->g.N));
     RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)pb->g.N));
-    RCHK(launch_fill(s, st, sizeof(CGState)));
-    launch_restart<T>(s, pb, st, 1);
+    RCHK(launch_fill(s, pb->st, sizeof(CGState)));
+    launch_restart<T>(s, pb, pb->st, 1, 1);
     RCHK(hipGetLastError());
-    CGState h;
-    RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-    RCHK(hipStreamSynchronize(s));
+    return PB_OK;
+}
+
+// n iterations and the restart that follows them where one is due, enqueued on s
+template <typename T>
+int chunk_t(pb_problem* pb, hipStream_t s, int n, int first_it, std::vector<hipEvent_t>* evs, std::vector<int>* ev_it)
+{
+    for (int it = 0; it < n; ++it) {
+        hipEvent_t* ev = nullptr;
+        if (evs && (first_it + it) % 4 == 0 && evs->size() < 4 * 128) {
+            for (int e = 0; e < 4; ++e) {
+                hipEvent_t x;
+                RCHK(hipEventCreate(&x));
+                evs->push_back(x);
+            }
+            ev_it->push_back(first_it + it);
+            ev = &(*evs)[evs->size() - 4];
+        }
+        launch_iteration<T>(s, pb, pb->st, ev);
+    }
+    if (sizeof(T) == 4) launch_restart<T>(s, pb, pb->st, 0, 0);
+    RCHK(hipGetLastError());
+    return PB_OK;
+}
+
+// Pipelined like the Jacobi solve: chunks of iterations (each followed by the restart where
+// one is due) are enqueued while the state of the previous chunk is read back.
+template <typename T>
+int solve_t(pb_problem* pb, CGState* out)
+{
+    pb_ctx* ctx = pb->ctx;
+    hipStream_t s = ctx->stream;
+    const pb_params& P = pb->prm;
+    int rc = begin_t<T>(pb, s);
+    if (!rc) rc = start_t<T>(pb, s);
+    if (rc) return rc;
     const int M = 8;
-    int launched = 0;
-    bool breakdown = false;
+    int launched = 0, c = 0;
     // sampled timings (context profiling on): every 4th iteration while the V-cycle has
     // more than one level
-    const bool prof = pb->ctx->profile != 0 && G->nlev > 1;
+    const bool prof = ctx->profile != 0 && pb->mg->nlev > 1;
     std::vector<hipEvent_t> evs;
     std::vector<int> ev_it;
-    while (h.status == 0 && launched < P.max_iter) {
+    auto enqueue = [&](int slot) -> int {
         const int n = std::min(M, P.max_iter - launched);
-        for (int it = 0; it < n; ++it) {
-            hipEvent_t* ev = nullptr;
-            if (prof && (launched + it) % 4 == 0 && evs.size() < 4 * 128) {
-                for (int e = 0; e < 4; ++e) {
-                    hipEvent_t x;
-                    RCHK(hipEventCreate(&x));
-                    evs.push_back(x);
-                }
-                ev_it.push_back(h.iter_count + it);
-                ev = &evs[evs.size() - 4];
-            }
-            launch_iteration<T>(s, pb, st, ev);
-        }
-        RCHK(hipGetLastError());
+        const int r = chunk_t<T>(pb, s, n, launched, prof ? &evs : nullptr, &ev_it);
+        if (r) return r;
         launched += n;
-        RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-        RCHK(hipStreamSynchronize(s));
-        if (mixed && (h.status != 0 || launched >= P.max_iter)) {
-            // status 3: the FP32 residual reached its goal or fell by inner_rtol
-            breakdown = h.status == 2;
-            launch_restart<T>(s, pb, st, 0);
-            RCHK(hipGetLastError());
-            RCHK(hipMemcpyAsync(&h, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-            RCHK(hipStreamSynchronize(s));
-            if (breakdown) break;
-        }
+        RCHK(hipMemcpyAsync(&ctx->host_state[slot], pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        RCHK(hipEventRecord(ctx->ev[slot], s));
+        return PB_OK;
+    };
+    if ((rc = enqueue(0))) return rc;
+    for (;;) {
+        const bool more = launched < P.max_iter;
+        if (more && (rc = enqueue((c + 1) & 1))) return rc;
+        RCHK(hipEventSynchronize(ctx->ev[c & 1]));
+        const CGState snap = ctx->host_state[c & 1];
+        if (snap.status == 1 || snap.status == 2 || !more) break;
+        ++c;
     }
-    RCHK(hipMemcpyAsync(out, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    // a correction left over by a stop without convergence
+    if (sizeof(T) == 4) k_fold<<<pb->mg->nb, 256, 0, s>>>(pb->g, pb->code, pb->x, (float*)pb->mg->cx, pb->st, 1);
+    RCHK(hipMemcpyAsync(out, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
-    if (breakdown && out->status != 1) out->status = 2;
     if (prof) {
-        // only iterations that ran: the sampled iteration count is below the final one
+        // only iterations that ran: the sampled iteration index is below the final count
         const int done = out->iter_count;
         for (size_t k = 0; k < ev_it.size(); ++k) {
             if (ev_it[k] >= done) continue;
@@ -943,6 +988,33 @@ int pbi_mg_solve(pb_problem* pb, CGState* out)
     return solve_t<double>(pb, out);
 }
 
+int pbi_mg_begin(pb_problem* pb, hipStream_t s)
+{
+    if (pb->prm.precision == PB_MIXED) return begin_t<float>(pb, s);
+    return begin_t<double>(pb, s);
+}
+
+int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first)
+{
+    int rc = PB_OK;
+    if (pb->prm.precision == PB_MIXED) {
+        if (first) rc = start_t<float>(pb, s);
+        if (!rc) rc = chunk_t<float>(pb, s, n, 0, nullptr, nullptr);
+    } else {
+        if (first) rc = start_t<double>(pb, s);
+        if (!rc) rc = chunk_t<double>(pb, s, n, 0, nullptr, nullptr);
+    }
+    return rc;
+}
+
+int pbi_mg_finish(pb_problem* pb, hipStream_t s)
+{
+    if (pb->prm.precision != PB_MIXED || !pb->mg) return PB_OK;
+    k_fold<<<pb->mg->nb, 256, 0, s>>>(pb->g, pb->code, pb->x, (float*)pb->mg->cx, pb->st, 1);
+    RCHK(hipGetLastError());
+    return PB_OK;
+}
+
 int pbi_mg_levels(const pb_problem* pb) { return pb->mg ? pb->mg->nlev : 0; }
 
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
@@ -951,28 +1023,22 @@ int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
     hipStream_t s = pb->ctx->stream;
     const Grid& g = pb->g;
     const bool mixed = pb->prm.precision == PB_MIXED;
-    if (!pb->mg) {
-        pb->mg = new MGData();
-        pb->mg->nu = pb->prm.mg_smooth > 0 ? pb->prm.mg_smooth : 1;
-        pb->mg->cs = pb->prm.mg_coarse_sweeps > 0 ? pb->prm.mg_coarse_sweeps : 4;
-        const int rc = mixed ? setup_levels<float>(pb, pb->mg) : setup_levels<double>(pb, pb->mg);
-        if (rc) return rc;
-    }
+    int rc = pbi_mg_begin(pb, s);
+    if (rc) return rc;
     MGData* G = pb->mg;
-    CGState* st = pb->st;
-    RCHK(launch_fill(s, st, sizeof(CGState)));
+    const Gate gate{nullptr, 0};
     std::vector<float> tmp;
     if (mixed) {
         tmp.resize((size_t)g.N);
         for (int64_t e = 0; e < g.N; ++e) tmp[(size_t)e] = (float)r_host[e];
         RCHK(hipMemcpyAsync(G->cr, tmp.data(), sizeof(float) * (size_t)g.N, hipMemcpyHostToDevice, s));
-        launch_vcycle<float>(s, pb, st);
+        launch_vcycle<float>(s, pb, gate);
         RCHK(hipMemcpyAsync(tmp.data(), G->cz, sizeof(float) * (size_t)g.N, hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
         for (int64_t e = 0; e < g.N; ++e) z_host[e] = tmp[(size_t)e];
     } else {
         RCHK(hipMemcpyAsync(G->cr, r_host, sizeof(double) * (size_t)g.N, hipMemcpyHostToDevice, s));
-        launch_vcycle<double>(s, pb, st);
+        launch_vcycle<double>(s, pb, gate);
         RCHK(hipMemcpyAsync(z_host, G->cz, sizeof(double) * (size_t)g.N, hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
     }

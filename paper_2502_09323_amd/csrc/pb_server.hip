@@ -13,7 +13,10 @@
 //      budget allow;
 //   5. launches one chunk for every resident problem: 16 CG iterations as batched launches
 //      (each launch covers the tiles of all problems), then the batched reliable-update
-//      kernels and a gather of all problem states.
+//      kernels and a gather of all problem states.  Requests with the multigrid
+//      preconditioner (worth it on large grids, where Jacobi-CG needs hundreds of iterations)
+//      run their 16 iterations as their own launches after the batched ones, each followed by
+//      its restart from the true residual where one is due, on the same stream.
 // Every problem's blocks run the code and block numbering of its own solo launch, so a result
 // does not depend on which other problems shared the batch.
 #include <hip/hip_runtime.h>
@@ -49,6 +52,7 @@ struct Active {
     int launched;       // CG iterations launched for it
     int last_chunk;     // the last chunk that included it
     bool finished;      // converged, broke down or out of iterations; no more chunks
+    bool mg;            // multigrid-preconditioned: its own launches after the batched ones
     CGState snap;
 };
 
@@ -156,8 +160,11 @@ size_t estimate_bytes(const pb_params& p, int64_t na)
 {
     const int64_t S = row_stride(p.n[2]);
     const int64_t N = (int64_t)p.n[0] * p.n[1] * S;
-    // node data of the mixed form (code, b, g, x64, seven FP32 vectors) + build scratch
-    return (size_t)N * 60 + (size_t)na * 64 + ((size_t)1 << 20);
+    // node data of the mixed form (code, b, g, x64, seven FP32 vectors) + build scratch; the
+    // multigrid form keeps six FP32 vectors and 1/D on level 0 and about 1/7 of that again
+    // (with the FP64 coefficients) on the coarser levels
+    const size_t per_node = p.precond == PB_PRECOND_MG ? 80 : 60;
+    return (size_t)N * per_node + (size_t)na * 64 + ((size_t)1 << 20);
 }
 
 // wait for the chunk in slot k and record every member's state
@@ -178,7 +185,7 @@ int complete_slot(pb_server* s, int k)
     for (size_t m = 0; m < s->members[k].size(); ++m) {
         for (auto& a : s->act) {
             if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
-            if (s->prof_slot[k]) {
+            if (s->prof_slot[k] && !a.mg) {
                 // algorithmic bytes of the FP32 iteration kernel per unknown: read z, w, p, x
                 // and the node code, write z, w, p, x
                 const int done = s->hgather[k][m].iter_count - a.snap.iter_count;
@@ -218,7 +225,8 @@ int progress(pb_server* s)
         int rc = PB_OK;
         if (p.phase == 1) {
             rc = pbi_build_continue(p.pb);
-            if (!rc) rc = pbi_mixed_begin(p.pb);
+            if (!rc)
+                rc = p.pb->prm.precond == PB_PRECOND_MG ? pbi_mg_begin(p.pb, p.pb->ctx->stream) : pbi_mixed_begin(p.pb);
             if (!rc && hipEventRecord(p.pb->ev, p.pb->ctx->stream) != hipSuccess) rc = PB_EDEVICE;
             if (!rc) {
                 p.phase = 2;
@@ -237,6 +245,7 @@ int progress(pb_server* s)
             a.launched = 0;
             a.last_chunk = -1;
             a.finished = false;
+            a.mg = p.pb->prm.precond == PB_PRECOND_MG;
             s->act.push_back(a);
             s->pend.erase(s->pend.begin() + (long)i);
             continue;
@@ -320,13 +329,15 @@ int admit(pb_server* s)
 
 int launch_chunk(pb_server* s, int k)
 {
-    std::vector<Active*> mem;
+    // Jacobi members first (one batched chunk), then the multigrid members (their own
+    // launches); the gathered states follow the same order
+    std::vector<Active*> mem, mgm;
     for (auto& a : s->act)
-        if (!a.finished) mem.push_back(&a);
-    const int P = (int)mem.size();
+        if (!a.finished) (a.mg ? mgm : mem).push_back(&a);
+    const int P = (int)mem.size(), Q = (int)mgm.size();
     s->members[k].clear();
-    if (P == 0) return PB_OK;
-    int rc = ensure_slot(s, k, P);
+    if (P + Q == 0) return PB_OK;
+    int rc = ensure_slot(s, k, P + Q);
     if (rc) return rc;
     BatchTotals t{0, 0, 0};
     int* o = s->hoff[k];
@@ -342,11 +353,12 @@ int launch_chunk(pb_server* s, int k)
         t.res += d.nbres;
         s->members[k].push_back(mem[p]->id);
     }
+    for (auto* a : mgm) s->members[k].push_back(a->id);
     o[P] = t.st;
     o[(P + 1) + P] = t.add;
     o[2 * (P + 1) + P] = t.res;
     hipStream_t st = s->ctx->stream;
-    s->prof_slot[k] = s->ctx->profile != 0;
+    s->prof_slot[k] = s->ctx->profile != 0 && P > 0;
     if (s->prof_slot[k] && !s->pev_made) {
         for (int a = 0; a < 2; ++a)
             for (int e = 0; e < 2 * kChunkIters; ++e) SCHK(hipEventCreate(&s->pev[a][e]));
@@ -357,15 +369,27 @@ int launch_chunk(pb_server* s, int k)
         const Grid& g = mem[p]->pb->g;
         s->prof_nu[k].push_back((int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2));
     }
-    SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
-    SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 3 * (P + 1), hipMemcpyHostToDevice, st));
-    SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
-                            s->prof_slot[k] ? s->pev[k] : nullptr));
-    SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * P, hipMemcpyDeviceToHost, st));
+    for (int q = 0; q < Q; ++q) s->prof_nu[k].push_back(0);
+    if (P > 0) {
+        SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
+        SCHK(hipMemcpyAsync(s->doff[k], s->hoff[k], sizeof(int) * 3 * (P + 1), hipMemcpyHostToDevice, st));
+        SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
+                                s->prof_slot[k] ? s->pev[k] : nullptr));
+    }
+    for (int q = 0; q < Q; ++q) {
+        pb_problem* pb = mgm[q]->pb;
+        if ((rc = pbi_mg_chunk(pb, st, kChunkIters, mgm[q]->launched == 0))) return rc;
+        SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, st));
+    }
+    SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * (P + Q), hipMemcpyDeviceToHost, st));
     SCHK(hipEventRecord(s->ev[k], st));
     s->inflight[k] = true;
     s->slot_chunk[k] = s->chunk_id;
     for (auto* a : mem) {
+        a->launched += kChunkIters;
+        a->last_chunk = s->chunk_id;
+    }
+    for (auto* a : mgm) {
         a->launched += kChunkIters;
         a->last_chunk = s->chunk_id;
     }
@@ -406,7 +430,6 @@ int pb_submit(pb_server* s, const pb_params* prm, int64_t n_atoms, const double*
     if (!s || !prm) return pbi_fail(PB_EINVAL, "NULL argument");
     if (prm->precision != PB_MIXED) return pbi_fail(PB_EINVAL, "the serving loop runs the mixed form only");
     if (prm->refine) return pbi_fail(PB_EINVAL, "the serving loop runs uniform grids only");
-    if (prm->precond != PB_PRECOND_JACOBI) return pbi_fail(PB_EINVAL, "the serving loop runs Jacobi-CG only");
     if (n_atoms < 0 || (n_atoms > 0 && (!xyz || !radius || !charge))) return pbi_fail(PB_EINVAL, "bad atoms");
     Request q;
     q.prm = *prm;

@@ -71,6 +71,30 @@ def test_mix_equals_alone_bitwise(ctxs):
         assert r["iters"] == alone["iters"] and r["outer_iters"] == alone["outer_iters"]
 
 
+def test_multigrid_requests_in_the_mix_equal_alone_bitwise(ctxs):
+    """Requests with the multigrid preconditioner run their own launches between the batched
+    chunks; each result equals the same request solved alone, bit for bit."""
+    main, side = ctxs
+    reqs = small_stream(n=8, seed=11)
+    reqs = [(mol, replace(grid, precond=I.MG) if i % 2 == 0 else grid) for i, (mol, grid) in enumerate(reqs)]
+    # one request on a grid with n - 1 even, so that its V-cycle has several levels
+    mol = I.random_molecule(150, 5.0, 77)
+    reqs.append((mol, I.cubic_grid(41, 0.5, precision=I.MIXED, rtol=1e-8, inner_rtol=1e-2, precond=I.MG)))
+    srv = B.Server(main, side, max_resident=4)
+    served = run_server(srv, reqs)
+    srv.close()
+    for i, (mol, grid) in enumerate(reqs):
+        r = served[i]
+        assert r["code"] == 0
+        alone = B.solve(mol, replace(grid, tile_planes=32), main)
+        for k in ("e_pol", "e_ion", "e_coul", "q_pol_total", "area_total"):
+            assert r[k] == alone[k], (i, k, r[k], alone[k])
+        assert r["iters"] == alone["iters"] and r["outer_iters"] == alone["outer_iters"]
+    # the 41^3 request has four levels (41, 21, 11, 6); the others' n - 1 is mostly odd, where
+    # the preconditioner is red-black symmetric Gauss-Seidel alone
+    assert served[len(reqs) - 1]["iters"] < 30
+
+
 def test_served_energies_match_fp64_oracle(ctxs):
     main, side = ctxs
     reqs = small_stream(n=4, seed=11)
