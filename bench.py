@@ -63,6 +63,7 @@ def counter_traffic(kernel, bytes_per_launch):
     return round(t["ratio"] * bytes_per_launch)
 DELTA = 1e-2
 DELTA_MG = 1e-3   # reliable-update factor of the multigrid-preconditioned mixed solve
+MG_MIN_N = 129    # serving: grids from this many nodes per axis use the multigrid preconditioner
 N_REQ = 512
 SEED = 2505
 MAX_RESIDENT = 32
@@ -83,10 +84,18 @@ def pct(x, q):
 
 # ---- serving stream ---------------------------------------------------------------------------
 
-def stream(n):
+def stream(n, precond="auto"):
+    """The serving stream; with precond "auto" the requests on grids of at least MG_MIN_N nodes
+    per axis take the multigrid preconditioner (Jacobi-CG needs hundreds of iterations there),
+    the smaller ones Jacobi-CG in the batched launches."""
     reqs = I.serving_stream_c5(n_req=n, seed=SEED, rate_hz=1.0, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA)
     unit_arrivals = np.array([r[0] for r in reqs])  # Poisson process at 1 request/s
-    return [(m, g) for _, m, g in reqs], unit_arrivals
+    out = []
+    for _, m, g in reqs:
+        if precond == "mg" or (precond == "auto" and min(g.n) >= MG_MIN_N):
+            g = replace(g, precond=I.MG, inner_rtol=DELTA_MG)
+        out.append((m, g))
+    return out, unit_arrivals
 
 
 def serve(B, main, side, reqs, arrivals=None, max_resident=MAX_RESIDENT):
@@ -120,8 +129,9 @@ def bench_serving(args, B, torch):
     main = B.Context(0)
     side = B.Context(0, stream=torch.cuda.Stream(0))
     copy_gbs = main.stream_copy_gbps(1 << 30, 20)
-    reqs, unit_arr = stream(N_REQ)
+    reqs, unit_arr = stream(N_REQ, args.serve_precond)
     nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
+    n_mg = sum(1 for _, g in reqs if g.precond == I.MG)
     log(f"generated {N_REQ} requests")
 
     # Every batched iteration launch of the run (warm-up, closed and open loop) is timed with
@@ -167,7 +177,7 @@ def bench_serving(args, B, torch):
     t0 = time.perf_counter()
     for mol, g in reqs:
         t = time.perf_counter()
-        r = B.solve(mol, replace(g, precision=I.FP64), main)
+        r = B.solve(mol, replace(g, precision=I.FP64, precond=I.JACOBI), main)
         svc.append(time.perf_counter() - t)
         e64.append(r)
     t_fp64 = time.perf_counter() - t0
@@ -180,7 +190,7 @@ def bench_serving(args, B, torch):
     err_ref = 0.0
     for i in sample:
         mol, g = reqs[i]
-        ref = B.solve(mol, replace(g, precision=I.FP64, rtol=1e-12), main)
+        ref = B.solve(mol, replace(g, precision=I.FP64, rtol=1e-12, precond=I.JACOBI), main)
         err_ref = max(err_ref, max(relerr(res[i][k], ref[k]) for k in ("e_pol", "e_ion")))
 
     # precision comparison on the 385^3 single solve
@@ -217,6 +227,9 @@ def bench_serving(args, B, torch):
         "config": {"workload": f"serving stream: {N_REQ} synthetic molecules (200-20000 atoms, log-uniform), "
                                f"grids 65^3-257^3, h in {{0.5,0.75,1.0}} A, mixed precision",
                    "n_requests": N_REQ, "seed": SEED, "rtol": RTOL, "reliable_update_factor": DELTA,
+                   "preconditioner": {"auto": f"multigrid V-cycle on grids >= {MG_MIN_N}^3, Jacobi below",
+                                      "mg": "multigrid V-cycle", "jacobi": "Jacobi"}[args.serve_precond],
+                   "multigrid_requests": n_mg,
                    "max_resident": args.max_resident, "unknowns_total": float(nu.sum()),
                    "atoms_total": int(sum(m.n for m, _ in reqs))},
         "served_closed_loop": {"solves_per_s": round(value, 3), "p50_s": round(pct(lat_closed, 50), 3),
@@ -457,6 +470,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--max-resident", type=int, default=MAX_RESIDENT,
                     help="serving stream: problems resident at once")
+    ap.add_argument("--serve-precond", default="auto", choices=["auto", "mg", "jacobi"],
+                    help="serving stream: preconditioner policy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): running the solver over "

@@ -15,8 +15,9 @@
 //      (each launch covers the tiles of all problems), then the batched reliable-update
 //      kernels and a gather of all problem states.  Requests with the multigrid
 //      preconditioner (worth it on large grids, where Jacobi-CG needs hundreds of iterations)
-//      run their 16 iterations as their own launches after the batched ones, each followed by
-//      its restart from the true residual where one is due, on the same stream.
+//      run their 16 iterations as their own launches, each followed by its restart from the
+//      true residual where one is due, on side streams that start with the chunk and that
+//      the gather waits for.
 // Every problem's blocks run the code and block numbering of its own solo launch, so a result
 // does not depend on which other problems shared the batch.
 #include <hip/hip_runtime.h>
@@ -36,6 +37,7 @@ namespace {
 
 constexpr int kChunkIters = 16;   // same chunk length as a solo mixed solve
 constexpr int kServerTilePlanes = 32;   // long x-chunks: a batched launch has blocks to spare
+constexpr int kMgStreams = 4;          // streams the multigrid problems are spread over
 
 struct Request {
     pb_params prm;
@@ -52,7 +54,8 @@ struct Active {
     int launched;       // CG iterations launched for it
     int last_chunk;     // the last chunk that included it
     bool finished;      // converged, broke down or out of iterations; no more chunks
-    bool mg;            // multigrid-preconditioned: its own launches after the batched ones
+    bool mg;            // multigrid-preconditioned: its own launches on one of the side streams
+    int lane;           // ... which one
     CGState snap;
 };
 
@@ -100,7 +103,13 @@ struct pb_server {
     CGState* hgather[2] = {nullptr, nullptr};
     int cap[2] = {0, 0};
     std::vector<uint64_t> members[2];
-    hipEvent_t ev[2];
+    hipEvent_t ev[2] = {};
+    // multigrid problems run on side streams (a V-cycle is many small dependent launches;
+    // several problems' launches overlap there); each chunk starts them after the chunk start
+    // on the main stream and the main stream waits for them before the gather copy
+    hipStream_t mgs[kMgStreams] = {};
+    hipEvent_t start_ev[2] = {}, mg_ev[2][kMgStreams] = {};
+    int next_lane = 0;
     bool inflight[2] = {false, false};
     int slot_chunk[2] = {-1, -1};
     int next = 0;
@@ -246,6 +255,7 @@ int progress(pb_server* s)
             a.last_chunk = -1;
             a.finished = false;
             a.mg = p.pb->prm.precond == PB_PRECOND_MG;
+            a.lane = a.mg ? (s->next_lane++ % kMgStreams) : 0;
             s->act.push_back(a);
             s->pend.erase(s->pend.begin() + (long)i);
             continue;
@@ -358,6 +368,7 @@ int launch_chunk(pb_server* s, int k)
     o[(P + 1) + P] = t.add;
     o[2 * (P + 1) + P] = t.res;
     hipStream_t st = s->ctx->stream;
+    SCHK(hipEventRecord(s->start_ev[k], st));
     s->prof_slot[k] = s->ctx->profile != 0 && P > 0;
     if (s->prof_slot[k] && !s->pev_made) {
         for (int a = 0; a < 2; ++a)
@@ -376,11 +387,21 @@ int launch_chunk(pb_server* s, int k)
         SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
                                 s->prof_slot[k] ? s->pev[k] : nullptr));
     }
+    bool used[kMgStreams] = {};
+    for (int q = 0; q < Q; ++q) used[mgm[q]->lane] = true;
+    for (int j = 0; j < kMgStreams; ++j)
+        if (used[j]) SCHK(hipStreamWaitEvent(s->mgs[j], s->start_ev[k], 0));
     for (int q = 0; q < Q; ++q) {
         pb_problem* pb = mgm[q]->pb;
-        if ((rc = pbi_mg_chunk(pb, st, kChunkIters, mgm[q]->launched == 0))) return rc;
-        SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, st));
+        hipStream_t ms = s->mgs[mgm[q]->lane];
+        if ((rc = pbi_mg_chunk(pb, ms, kChunkIters, mgm[q]->launched == 0))) return rc;
+        SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, ms));
     }
+    for (int j = 0; j < kMgStreams; ++j)
+        if (used[j]) {
+            SCHK(hipEventRecord(s->mg_ev[k][j], s->mgs[j]));
+            SCHK(hipStreamWaitEvent(st, s->mg_ev[k][j], 0));
+        }
     SCHK(hipMemcpyAsync(s->hgather[k], s->dgather[k], sizeof(CGState) * (P + Q), hipMemcpyDeviceToHost, st));
     SCHK(hipEventRecord(s->ev[k], st));
     s->inflight[k] = true;
@@ -413,11 +434,18 @@ int pb_server_create(pb_ctx* ctx, pb_ctx* build_ctx, int32_t max_resident, pb_se
     s->max_resident = max_resident;
     s->budget = ctx->budget;
     s->t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < 2; ++k)
-        if (hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) != hipSuccess) {
-            delete s;
-            return pbi_fail(PB_EDEVICE, "hipEventCreate failed");
-        }
+    bool ok = true;
+    for (int k = 0; k < 2; ++k) {
+        ok = ok && hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&s->start_ev[k], hipEventDisableTiming) == hipSuccess;
+        for (int j = 0; j < kMgStreams; ++j)
+            ok = ok && hipEventCreateWithFlags(&s->mg_ev[k][j], hipEventDisableTiming) == hipSuccess;
+    }
+    for (int j = 0; j < kMgStreams; ++j) ok = ok && hipStreamCreate(&s->mgs[j]) == hipSuccess;
+    if (!ok) {
+        pb_server_destroy(s);
+        return pbi_fail(PB_EDEVICE, "server streams or events");
+    }
     *out = s;
     return PB_OK;
 }
@@ -526,11 +554,18 @@ void pb_server_destroy(pb_server* s)
     (void)hipSetDevice(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
     (void)hipStreamSynchronize(s->bctx->stream);
+    for (int j = 0; j < kMgStreams; ++j)
+        if (s->mgs[j]) (void)hipStreamSynchronize(s->mgs[j]);
     for (auto& a : s->act) pb_problem_free(a.pb);
     for (auto& p : s->pend) pb_problem_free(p.pb);
+    for (int j = 0; j < kMgStreams; ++j)
+        if (s->mgs[j]) (void)hipStreamDestroy(s->mgs[j]);
     for (int k = 0; k < 2; ++k) {
         free_slot(s, k);
-        (void)hipEventDestroy(s->ev[k]);
+        if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+        if (s->start_ev[k]) (void)hipEventDestroy(s->start_ev[k]);
+        for (int j = 0; j < kMgStreams; ++j)
+            if (s->mg_ev[k][j]) (void)hipEventDestroy(s->mg_ev[k][j]);
         if (s->pev_made)
             for (int e = 0; e < 2 * kChunkIters; ++e) (void)hipEventDestroy(s->pev[k][e]);
     }
