@@ -25,7 +25,7 @@ EXPORTED = [
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
-    "pb_mg_vcycle",
+    "pb_mg_vcycle", "pb_server_profile_mg",
 ]
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
     L.pb_poll.argtypes = [P, P, P, P, P, P, i32, C.POINTER(i32)]
     L.pb_server_times.argtypes = [P, P]
     L.pb_server_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
+    L.pb_server_profile_mg.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(i64)]
     L.pb_server_destroy.argtypes = [P]
     L.pb_server_destroy.restype = None
     L.pb_refine_info.argtypes = [P, C.POINTER(PbRefineStats)]
@@ -406,7 +408,13 @@ class Server:
         rc = _lib.pb_server_profile(self.h, C.byref(a), C.byref(b), C.byref(n))
         if rc != PB_OK:
             raise _err(rc)
-        return dict(stencil_ms=a.value, stencil_bytes=b.value, launches=n.value)
+        out = dict(stencil_ms=a.value, stencil_bytes=b.value, launches=n.value)
+        c, d, e, m = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        rc = _lib.pb_server_profile_mg(self.h, C.byref(c), C.byref(d), C.byref(e), C.byref(m))
+        if rc != PB_OK:
+            raise _err(rc)
+        out.update(mg_sweep_ms=c.value, mg_sweep_bytes=d.value, mg_vcycle_ms=e.value, mg_samples=m.value)
+        return out
 
     def times(self) -> dict:
         v = np.zeros(4)

@@ -199,7 +199,8 @@ int pbi_mg_solve(pb_problem* pb, pbk::CGState* out);
 // followed by the restart from the true residual where one is due; finish folds a leftover
 // FP32 correction into the solution
 int pbi_mg_begin(pb_problem* pb, hipStream_t s);
-int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first);
+// (sample: four events for the first iteration's V-cycle, or nullptr; see pb_get_profile)
+int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample);
 int pbi_mg_finish(pb_problem* pb, hipStream_t s);
 int pbi_mg_levels(const pb_problem* pb);
 // one V-cycle on a vector over the padded level-0 layout (host arrays of g.N doubles)

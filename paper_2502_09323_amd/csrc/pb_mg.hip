@@ -14,8 +14,10 @@
 //               the coarse ionic term is P^T m
 //   transfers   P trilinear, R = P^T
 //   V-cycle     zero start; nu times (red, black); residual (zero on black nodes right after
-//               a black half-sweep, so only red nodes are formed); restrict; recurse; add P e;
+//               a black half-sweep, so only red nodes are formed); restrict; recurse; add P e
+//               (at the red nodes: the black half-sweep that follows replaces the black ones);
 //               nu times (black, red); the coarsest level takes red, then (black, red) x cs.
+//               Levels of at most 8192 unknowns run in one block (one launch).
 //               Pre- and post-smoothing are adjoint and R = P^T: the V-cycle is symmetric
 //               positive definite.  With one level it is red-black symmetric Gauss-Seidel.
 //   CG          standard PCG (z = V-cycle(r)) with device-resident scalars; FP64, or FP32
@@ -100,15 +102,21 @@ __device__ __forceinline__ int64_t this_node(const Grid& g, bool& red)
     return g.idx(i, j, k);
 }
 
-// interior node of colour c (0 red, 1 black) of this thread, or -1
-__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c)
+// interior node of colour c (0 red, 1 black) of this thread, or -1; with its indices
+__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int& i, int& j, int& k)
 {
     const int m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int i = 1 + (int)blockIdx.z;
-    const int k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
+    j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    i = 1 + (int)blockIdx.z;
+    k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
     if (k > g.nz - 2 || j > g.ny - 2) return -1;
     return g.idx(i, j, k);
+}
+
+__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c)
+{
+    int i, j, k;
+    return this_colour_node(g, c, i, j, k);
 }
 
 // the same for the one-block coarsest solve: node t of colour c in (i, j, m) order
@@ -228,17 +236,17 @@ __device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec
     return (T)0.125 * v;
 }
 
-// x += P e
+// x += P e at the red nodes: post-smoothing starts with a black half-sweep, which replaces
+// every black value from its red neighbours, so the correction of the black ones is unused
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
                                                  Gate st)
 {
     if (halted(st)) return;
-    const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int i = 1 + (int)blockIdx.z;
-    if (k > gf.nz - 2 || j > gf.ny - 2) return;
-    x[gf.idx(i, j, k)] += prolong_at(gc, ec, i, j, k);
+    int i, j, k;
+    const int64_t e = this_colour_node(gf, 0, i, j, k);
+    if (e < 0) return;
+    x[e] += prolong_at(gc, ec, i, j, k);
 }
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
@@ -264,6 +272,121 @@ __global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, Gat
             L.x[e] = (L.b[e] + sum) * L.dinv[e];
         }
         __syncthreads();
+    }
+}
+
+// ---- the small levels of a V-cycle in one block ------------------------------------------
+// Levels of at most kSubcycleNodes unknowns would each cost several launches of a few
+// microseconds that do little work; one block of kSubThreads threads runs the part of the
+// V-cycle below the first such level (its right-hand side given) in one launch, with a block
+// barrier between phases.  Same steps and order as the multi-launch path.
+constexpr int kSubcycleNodes = 8192;
+constexpr int kSubThreads = 1024;
+
+template <typename T>
+struct SubLevels {
+    int nl;                          // levels, the last is the coarsest
+    int nu, cs;
+    Lev<T> lv[PB_MG_MAX_LEVELS];
+    T* r[PB_MG_MAX_LEVELS];
+};
+
+template <typename T>
+__device__ __forceinline__ void blk_sweep(const Lev<T>& L, int c)
+{
+    const Op0<T> op{};
+    const int nc = (int)colour_threads(L.g);
+    const T* __restrict__ x = L.x;
+    for (int t = threadIdx.x; t < nc; t += kSubThreads) {
+        const int64_t e = colour_node(L.g, c, t);
+        if (e < 0) continue;
+        const T s = nsum<T, false>(L, op, e, [&](int64_t m) { return x[m]; });
+        L.x[e] = (L.b[e] + s) * L.dinv[e];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void blk_red_from_zero(const Lev<T>& L)
+{
+    const int nc = (int)colour_threads(L.g);
+    for (int t = threadIdx.x; t < nc; t += kSubThreads) {
+        const int64_t e = colour_node(L.g, 0, t);
+        if (e >= 0) L.x[e] = L.b[e] * L.dinv[e];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate st)
+{
+    if (halted(st)) return;
+    const Op0<T> op{};
+    // down: pre-smoothing, residual at the red nodes, restriction
+    for (int l = 0; l + 1 < S.nl; ++l) {
+        const Lev<T>& L = S.lv[l];
+        blk_red_from_zero(L);
+        blk_sweep(L, 1);
+        for (int v = 1; v < S.nu; ++v) {
+            blk_sweep(L, 0);
+            blk_sweep(L, 1);
+        }
+        const int nc = (int)colour_threads(L.g);
+        const T* __restrict__ x = L.x;
+        for (int t = threadIdx.x; t < nc; t += kSubThreads) {
+            const int64_t e = colour_node(L.g, 0, t);
+            if (e < 0) continue;
+            T D;
+            const T s = nsum<T, false>(L, op, e, [&](int64_t m) { return x[m]; }, &D);
+            S.r[l][e] = L.b[e] - (D * x[e] - s);
+        }
+        __syncthreads();
+        const Grid& gf = L.g;
+        const Grid& gc = S.lv[l + 1].g;
+        const T* __restrict__ r = S.r[l];
+        T* bc = const_cast<T*>(S.lv[l + 1].b);
+        const int n = (int)interior_count(gc);
+        const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
+        for (int t = threadIdx.x; t < n; t += kSubThreads) {
+            bool red;
+            const int64_t ec = interior_node(gc, t, red);
+            const int64_t q = ec - Z0;
+            const int K = (int)(q % gc.S), J = (int)((q / gc.S) % gc.ny), I = (int)(q / ((int64_t)gc.ny * gc.S));
+            const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
+            const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
+            const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
+            const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
+            bc[ec] = r[f] + (T)0.25 * ((xy + xz) + yz);
+        }
+        __syncthreads();
+    }
+    // coarsest: red from zero, then (black, red) x cs
+    {
+        const Lev<T>& L = S.lv[S.nl - 1];
+        blk_red_from_zero(L);
+        for (int v = 0; v < S.cs; ++v) {
+            blk_sweep(L, 1);
+            blk_sweep(L, 0);
+        }
+    }
+    // up: coarse correction, post-smoothing
+    for (int l = S.nl - 2; l >= 0; --l) {
+        const Lev<T>& L = S.lv[l];
+        const Grid& gc = S.lv[l + 1].g;
+        const T* __restrict__ ec = S.lv[l + 1].x;
+        const int n = (int)colour_threads(L.g);
+        for (int t = threadIdx.x; t < n; t += kSubThreads) {
+            const int64_t e = colour_node(L.g, 0, t);   // red nodes only, as in k_prolong
+            if (e < 0) continue;
+            const int64_t q = e - Z0;
+            const int k = (int)(q % L.g.S), j = (int)((q / L.g.S) % L.g.ny), i = (int)(q / ((int64_t)L.g.ny * L.g.S));
+            L.x[e] += prolong_at(gc, ec, i, j, k);
+        }
+        __syncthreads();
+        for (int v = 0; v < S.nu; ++v) {
+            blk_sweep(L, 1);
+            blk_sweep(L, 0);
+        }
     }
 }
 
@@ -669,7 +792,7 @@ template <typename T, bool L0>
 void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const Grid& gc, const T* ec,
                  Gate st, hipEvent_t* ev = nullptr)
 {
-    k_prolong<T><<<node_grid(L.g, false), 256, 0, s>>>(L.g, L.x, gc, ec, st);
+    k_prolong<T><<<node_grid(L.g, true), 256, 0, s>>>(L.g, L.x, gc, ec, st);
     if (ev) (void)hipEventRecord(ev[1], s);
     launch_sweep<T, L0>(s, L, op, 1, st);
     if (ev) (void)hipEventRecord(ev[2], s);
@@ -710,7 +833,12 @@ void launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev 
         return;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
-    for (int l = 0; l + 1 < L; ++l) {
+    // the first level from which every level has at most kSubcycleNodes unknowns (not 0)
+    int ls = L;
+    while (ls - 1 >= 1 && interior_count(G->g[ls - 1]) <= kSubcycleNodes) --ls;
+    // pre-smoothing and restriction on the levels above the one-block part (or above the
+    // coarsest level)
+    for (int l = 0; l < std::min(ls, L - 1); ++l) {
         const Lev<T> lv = level<T>(G, l);
         const Grid& gc = G->g[l + 1];
         T* r = (T*)G->r[l];
@@ -723,8 +851,21 @@ void launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev 
         }
         k_restrict<T><<<node_grid(gc, false), 256, 0, s>>>(lv.g, r, gc, (T*)G->b[l + 1], st);
     }
-    launch_coarsest<T, false>(s, G, level<T>(G, L - 1), op, st);
-    for (int l = L - 2; l >= 0; --l) {
+    if (ls < L) {
+        // levels ls.. in one block; its right-hand side was restricted above
+        SubLevels<T> S;
+        S.nl = L - ls;
+        S.nu = G->nu;
+        S.cs = G->cs;
+        for (int l = ls; l < L; ++l) {
+            S.lv[l - ls] = level<T>(G, l);
+            S.r[l - ls] = (T*)G->r[l];
+        }
+        k_subcycle<T><<<1, kSubThreads, 0, s>>>(S, st);
+    } else {
+        launch_coarsest<T, false>(s, G, level<T>(G, L - 1), op, st);
+    }
+    for (int l = std::min(ls, L - 1) - 1; l >= 0; --l) {
         const Lev<T> lv = level<T>(G, l);
         const T* ec = (const T*)G->x[l + 1];
         if (l == 0)
@@ -901,23 +1042,12 @@ int start_t(pb_problem* pb, hipStream_t s)
     return PB_OK;
 }
 
-// n iterations and the restart that follows them where one is due, enqueued on s
+// n iterations and the restart that follows them where one is due, enqueued on s; ev[it],
+// where given, receives the four timing events of iteration it's V-cycle
 template <typename T>
-int chunk_t(pb_problem* pb, hipStream_t s, int n, int first_it, std::vector<hipEvent_t>* evs, std::vector<int>* ev_it)
+int chunk_t(pb_problem* pb, hipStream_t s, int n, hipEvent_t* const* ev)
 {
-    for (int it = 0; it < n; ++it) {
-        hipEvent_t* ev = nullptr;
-        if (evs && (first_it + it) % 4 == 0 && evs->size() < 4 * 128) {
-            for (int e = 0; e < 4; ++e) {
-                hipEvent_t x;
-                RCHK(hipEventCreate(&x));
-                evs->push_back(x);
-            }
-            ev_it->push_back(first_it + it);
-            ev = &(*evs)[evs->size() - 4];
-        }
-        launch_iteration<T>(s, pb, pb->st, ev);
-    }
+    for (int it = 0; it < n; ++it) launch_iteration<T>(s, pb, pb->st, ev ? ev[it] : nullptr);
     if (sizeof(T) == 4) launch_restart<T>(s, pb, pb->st, 0, 0);
     RCHK(hipGetLastError());
     return PB_OK;
@@ -943,7 +1073,23 @@ int solve_t(pb_problem* pb, CGState* out)
     std::vector<int> ev_it;
     auto enqueue = [&](int slot) -> int {
         const int n = std::min(M, P.max_iter - launched);
-        const int r = chunk_t<T>(pb, s, n, launched, prof ? &evs : nullptr, &ev_it);
+        hipEvent_t* ev[M] = {};
+        for (int it = 0; prof && it < n; ++it) {
+            if ((launched + it) % 4 != 0 || evs.size() >= 4 * 128) continue;
+            for (int e = 0; e < 4; ++e) {
+                hipEvent_t x;
+                RCHK(hipEventCreate(&x));
+                evs.push_back(x);
+            }
+            ev_it.push_back(launched + it);
+        }
+        // pointers into evs only once it has stopped growing for this chunk
+        for (size_t k = 0, it = 0; k < ev_it.size(); ++k)
+            if (ev_it[k] >= launched && ev_it[k] < launched + n) {
+                it = (size_t)(ev_it[k] - launched);
+                ev[it] = &evs[4 * k];
+            }
+        const int r = chunk_t<T>(pb, s, n, prof ? ev : nullptr);
         if (r) return r;
         launched += n;
         RCHK(hipMemcpyAsync(&ctx->host_state[slot], pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -994,15 +1140,17 @@ int pbi_mg_begin(pb_problem* pb, hipStream_t s)
     return begin_t<double>(pb, s);
 }
 
-int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first)
+int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample)
 {
     int rc = PB_OK;
+    std::vector<hipEvent_t*> ev((size_t)std::max(n, 1), nullptr);
+    ev[0] = sample;
     if (pb->prm.precision == PB_MIXED) {
         if (first) rc = start_t<float>(pb, s);
-        if (!rc) rc = chunk_t<float>(pb, s, n, 0, nullptr, nullptr);
+        if (!rc) rc = chunk_t<float>(pb, s, n, ev.data());
     } else {
         if (first) rc = start_t<double>(pb, s);
-        if (!rc) rc = chunk_t<double>(pb, s, n, 0, nullptr, nullptr);
+        if (!rc) rc = chunk_t<double>(pb, s, n, ev.data());
     }
     return rc;
 }

@@ -123,6 +123,17 @@ struct pb_server {
     std::vector<int64_t> prof_nu[2];     // interior unknowns of each member
     double prof_ms = 0, prof_bytes = 0;
     int64_t prof_launches = 0;
+    // multigrid members: the level-0 black half-sweep after the coarse correction and the
+    // whole V-cycle of each chunk's first iteration, timed with events from a pool
+    struct MgSample {
+        uint64_t id;
+        hipEvent_t e[4];
+        int64_t nu;
+    };
+    std::vector<MgSample> mg_samples[2];
+    std::vector<hipEvent_t> ev_pool;
+    double prof_mg_ms = 0, prof_mg_bytes = 0, prof_mg_vcycle_ms = 0;
+    int64_t prof_mg_n = 0;
 
     double now() const
     {
@@ -194,6 +205,19 @@ int complete_slot(pb_server* s, int k)
     for (size_t m = 0; m < s->members[k].size(); ++m) {
         for (auto& a : s->act) {
             if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
+            for (auto& smp : s->mg_samples[k]) {
+                // the sampled (first) iteration of the chunk ran if any iteration did
+                if (smp.id != a.id || s->hgather[k][m].iter_count <= a.snap.iter_count) continue;
+                float sw = 0, vc = 0;
+                SCHK(hipEventElapsedTime(&sw, smp.e[1], smp.e[2]));
+                SCHK(hipEventElapsedTime(&vc, smp.e[0], smp.e[3]));
+                s->prof_mg_ms += sw;
+                s->prof_mg_vcycle_ms += vc;
+                // algorithmic bytes per unknown of the FP32 half-sweep: x and the node code of
+                // every node, b and 1/D of the swept colour read, x of that colour written
+                s->prof_mg_bytes += 14.0 * (double)smp.nu;
+                s->prof_mg_n += 1;
+            }
             if (s->prof_slot[k] && !a.mg) {
                 // algorithmic bytes of the FP32 iteration kernel per unknown: read z, w, p, x
                 // and the node code, write z, w, p, x
@@ -205,6 +229,9 @@ int complete_slot(pb_server* s, int k)
             if (stt == 1 || stt == 2 || a.launched >= a.pb->prm.max_iter) a.finished = true;
         }
     }
+    for (auto& smp : s->mg_samples[k])
+        for (int e = 0; e < 4; ++e) s->ev_pool.push_back(smp.e[e]);
+    s->mg_samples[k].clear();
     return PB_OK;
 }
 
@@ -394,7 +421,25 @@ int launch_chunk(pb_server* s, int k)
     for (int q = 0; q < Q; ++q) {
         pb_problem* pb = mgm[q]->pb;
         hipStream_t ms = s->mgs[mgm[q]->lane];
-        if ((rc = pbi_mg_chunk(pb, ms, kChunkIters, mgm[q]->launched == 0))) return rc;
+        hipEvent_t* sample = nullptr;
+        if (s->ctx->profile && pb->mg && pb->mg->nlev > 1) {
+            pb_server::MgSample smp;
+            smp.id = mgm[q]->id;
+            for (int e = 0; e < 4; ++e) {
+                if (s->ev_pool.empty()) {
+                    hipEvent_t x;
+                    SCHK(hipEventCreate(&x));
+                    s->ev_pool.push_back(x);
+                }
+                smp.e[e] = s->ev_pool.back();
+                s->ev_pool.pop_back();
+            }
+            const Grid& g = pb->g;
+            smp.nu = (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+            s->mg_samples[k].push_back(smp);
+            sample = s->mg_samples[k].back().e;
+        }
+        if ((rc = pbi_mg_chunk(pb, ms, kChunkIters, mgm[q]->launched == 0, sample))) return rc;
         SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, ms));
     }
     for (int j = 0; j < kMgStreams; ++j)
@@ -538,6 +583,17 @@ int pb_server_profile(const pb_server* s, double* stencil_ms_total, double* sten
     return PB_OK;
 }
 
+int pb_server_profile_mg(const pb_server* s, double* sweep_ms_total, double* sweep_bytes_total,
+                         double* vcycle_ms_total, int64_t* samples)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    if (sweep_ms_total) *sweep_ms_total = s->prof_mg_ms;
+    if (sweep_bytes_total) *sweep_bytes_total = s->prof_mg_bytes;
+    if (vcycle_ms_total) *vcycle_ms_total = s->prof_mg_vcycle_ms;
+    if (samples) *samples = s->prof_mg_n;
+    return PB_OK;
+}
+
 int pb_server_times(const pb_server* s, double* out4)
 {
     if (!s || !out4) return pbi_fail(PB_EINVAL, "NULL argument");
@@ -560,6 +616,10 @@ void pb_server_destroy(pb_server* s)
     for (auto& p : s->pend) pb_problem_free(p.pb);
     for (int j = 0; j < kMgStreams; ++j)
         if (s->mgs[j]) (void)hipStreamDestroy(s->mgs[j]);
+    for (int k = 0; k < 2; ++k)
+        for (auto& smp : s->mg_samples[k])
+            for (int e = 0; e < 4; ++e) (void)hipEventDestroy(smp.e[e]);
+    for (auto e : s->ev_pool) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k) {
         free_slot(s, k);
         if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
