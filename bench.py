@@ -64,6 +64,7 @@ def counter_traffic(kernel, bytes_per_launch):
 DELTA = 1e-2
 DELTA_MG = 1e-3   # reliable-update factor of the multigrid-preconditioned mixed solve
 MG_MIN_N = 129    # serving: grids from this many nodes per axis use the multigrid preconditioner
+BIND_COMPLEXES, BIND_DISP, BIND_H = 6, 30, 0.5   # binding workload: complexes, displacements, spacing
 N_REQ = 512
 SEED = 2505
 MAX_RESIDENT = 32
@@ -84,15 +85,16 @@ def pct(x, q):
 
 # ---- serving stream ---------------------------------------------------------------------------
 
-def stream(n, precond="auto"):
+def stream(n, precond="auto", mg_min_n=None):
     """The serving stream; with precond "auto" the requests on grids of at least MG_MIN_N nodes
     per axis take the multigrid preconditioner (Jacobi-CG needs hundreds of iterations there),
     the smaller ones Jacobi-CG in the batched launches."""
     reqs = I.serving_stream_c5(n_req=n, seed=SEED, rate_hz=1.0, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA)
     unit_arrivals = np.array([r[0] for r in reqs])  # Poisson process at 1 request/s
+    mg_min_n = MG_MIN_N if mg_min_n is None else mg_min_n
     out = []
     for _, m, g in reqs:
-        if precond == "mg" or (precond == "auto" and min(g.n) >= MG_MIN_N):
+        if precond == "mg" or (precond == "auto" and min(g.n) >= mg_min_n):
             g = replace(g, precond=I.MG, inner_rtol=DELTA_MG)
         out.append((m, g))
     return out, unit_arrivals
@@ -135,7 +137,7 @@ def bench_serving(args, B, torch):
     main = B.Context(0)
     side = B.Context(0, stream=torch.cuda.Stream(0))
     copy_gbs = main.stream_copy_gbps(1 << 30, 20)
-    reqs, unit_arr = stream(N_REQ, args.serve_precond)
+    reqs, unit_arr = stream(N_REQ, args.serve_precond, args.mg_min_n)
     nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
     n_mg = sum(1 for _, g in reqs if g.precond == I.MG)
     log(f"generated {N_REQ} requests")
@@ -256,7 +258,7 @@ def bench_serving(args, B, torch):
         "config": {"workload": f"serving stream: {N_REQ} synthetic molecules (200-20000 atoms, log-uniform), "
                                f"grids 65^3-257^3, h in {{0.5,0.75,1.0}} A, mixed precision",
                    "n_requests": N_REQ, "seed": SEED, "rtol": RTOL, "reliable_update_factor": DELTA,
-                   "preconditioner": {"auto": f"multigrid V-cycle on grids >= {MG_MIN_N}^3, Jacobi below",
+                   "preconditioner": {"auto": f"multigrid V-cycle on grids >= {args.mg_min_n}^3, Jacobi below",
                                       "mg": "multigrid V-cycle", "jacobi": "Jacobi"}[args.serve_precond],
                    "multigrid_requests": n_mg,
                    "max_resident": args.max_resident, "unknowns_total": float(nu.sum()),
@@ -491,17 +493,97 @@ def bench_single(args, B, torch):
     return out
 
 
+def bench_binding(args, B, torch):
+    """Binding energies of synthetic complexes by the paper's protocol (30 displacements of
+    the solute within a cube of half the grid spacing, three solves each: complex, receptor,
+    ligand, all on one grid per complex), served through the serving loop."""
+    main = B.Context(0)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    copy_gbs = main.stream_copy_gbps(1 << 30, 20)
+    w = I.binding_workload(n_complex=BIND_COMPLEXES, n_disp=BIND_DISP, h=BIND_H, precision=I.MIXED, rtol=RTOL,
+                           inner_rtol=DELTA_MG, precond=I.MG)
+    reqs = [(m, g) for _, _, _, m, g in w]
+    main.set_profiling(True)
+    for _ in range(args.warmup):
+        serve(B, main, side, reqs[:3 * 6], max_resident=args.max_resident)[2].close()
+    walls, res = [], None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        res, wall, srv = serve(B, main, side, reqs, max_resident=args.max_resident)
+        torch.cuda.synchronize()
+        prof = srv.profile()
+        srv.close()
+        walls.append(wall)
+    main.set_profiling(False)
+    value = len(reqs) / float(np.mean(walls))
+    # ddG per complex over the displacements
+    per = {}
+    for idx, (c, k, part, _, _) in enumerate(w):
+        per.setdefault(c, {}).setdefault(k, {})[part] = res[idx]
+    table = []
+    for c in sorted(per):
+        dd = [B.binding_ddg(v["c"], v["1"], v["2"]) for v in per[c].values()]
+        row = {"complex": c}
+        for key in ("ddg_total", "ddg_coul", "ddg_pol", "ddg_ion"):
+            xs = np.array([d[key] for d in dd])
+            row[key] = [round(float(xs.mean()), 4), round(float(xs.std()), 4)]
+        table.append(row)
+    # accuracy: the first displacement of the first complex against tight FP64 Jacobi solves
+    ref = [B.solve(m, replace(g, precision=I.FP64, precond=I.JACOBI, rtol=1e-12), main) for _, _, _, m, g in w[:3]]
+    d_srv = B.binding_ddg(res[0], res[1], res[2])
+    d_ref = B.binding_ddg(ref[0], ref[1], ref[2])
+    n = max(prof["mg_samples"], 1)
+    a_mg = prof["mg_sweep_bytes"] / (prof["mg_sweep_ms"] * 1e-3) / 1e9 if prof["mg_sweep_ms"] > 0 else None
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * float(np.mean(walls)), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 CG + f64 reliable updates/energy", "data": "synthetic",
+        "config": {"workload": f"binding energies: {BIND_COMPLEXES} synthetic complexes (1500 + 250 atoms) x "
+                               f"{BIND_DISP} displacements x 3 solves (complex, receptor, ligand), "
+                               f"h = {BIND_H} A, one grid per complex",
+                   "requests": len(reqs), "grid": list(w[0][4].n), "rtol": RTOL,
+                   "preconditioner": "multigrid V-cycle", "max_resident": args.max_resident},
+        "ddg_kT_mean_std_per_complex": table,
+        "ddg_served_vs_fp64_rtol1e-12": {k: abs(d_srv[k] - d_ref[k]) for k in d_ref},
+        "roofline": {"bound": "hbm", "achieved": round(a_mg, 1) if a_mg else None, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(a_mg / HBM_PEAK_GBS, 4) if a_mg else None, "traffic": None,
+                     "kernel": "k_sweep<float, true> (level-0 red-black half-sweep of the multigrid V-cycle)",
+                     "bytes_per_launch": round(prof["mg_sweep_bytes"] / n),
+                     "avg_launch_ms": round(prof["mg_sweep_ms"] / n, 5), "launches_timed": prof["mg_samples"],
+                     "avg_vcycle_ms": round(prof["mg_vcycle_ms"] / n, 5),
+                     "scope": "the first iteration of every chunk of every request (timed run)"},
+        "stream_copy_GBs": round(copy_gbs, 1),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        _, _, _, m, g = w[0]
+        t0 = time.perf_counter()
+        run_o = O.run(m, replace(g, precision=I.FP64), rtol=RTOL)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": O.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"one FP64 oracle solve (Jacobi-CG) of the first complex on its grid at rtol "
+                                         f"{RTOL}: {dt:.1f} s, {run_o.iters} CG iterations"}
+    main.close()
+    side.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4", "binding"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--max-resident", type=int, default=MAX_RESIDENT,
                     help="serving stream: problems resident at once")
     ap.add_argument("--serve-precond", default="auto", choices=["auto", "mg", "jacobi"],
                     help="serving stream: preconditioner policy")
+    ap.add_argument("--mg-min-n", type=int, default=MG_MIN_N,
+                    help="serving stream, policy auto: smallest grid (nodes per axis) given the multigrid preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): running the solver over "
@@ -518,6 +600,8 @@ def main():
         out = bench_serving(args, B, torch)
     elif args.workload == "c3":
         out = bench_refined(args, B, torch)
+    elif args.workload == "binding":
+        out = bench_binding(args, B, torch)
     else:
         out = bench_single(args, B, torch)
     print(json.dumps(out))

@@ -180,6 +180,22 @@ typedef struct {
     double t_energy_s;      /* wall time of pb_energy */
 } pb_energy_out;
 
+/* Binding energy of a complex from its two parts (paper Sect. 5.2, binding energy
+ * calculation): ddG = dG_complex - dG_1 - dG_2, with dG the total electrostatic energy
+ * e_coul + e_pol + e_ion (eq. energyPart), and the same difference for each component.  The
+ * three energies must come from solves on the same grid (box, spacing and origin), so that
+ * discretization errors largely cancel.  Host-only arithmetic; no device work.
+ * Errors: PB_EINVAL (NULL argument). */
+typedef struct {
+    double ddg_total;
+    double ddg_coul;
+    double ddg_pol;
+    double ddg_ion;
+} pb_binding_out;
+
+int pb_binding_ddg(const pb_energy_out* complex_e, const pb_energy_out* part1, const pb_energy_out* part2,
+                   pb_binding_out* out);
+
 /* Energy read-back after pb_solve.  phi_reac_per_atom (optional, host, n_atoms doubles)
  * receives phi_pol + phi_ion at each atom centre in kT/e.  Errors: PB_EINVAL (not
  * solved), PB_EDEVICE. */
@@ -307,10 +323,18 @@ int pb_poll(pb_server* srv, uint64_t* ids, pb_energy_out* results, pb_solve_stat
 int pb_server_times(const pb_server* srv, double* out4);
 
 /* With profiling on in ctx (pb_ctx_set_profiling): total HIP-event time (ms) of the batched
- * stencil launches, their algorithmic bytes (24 per interior unknown per CG iteration actually
+ * stencil launches, their algorithmic bytes (36 per interior unknown per CG iteration actually
  * performed), and the number of launches timed. */
 int pb_server_profile(const pb_server* srv, double* stencil_ms_total, double* stencil_bytes_total,
                       int64_t* stencil_launches);
+
+/* The same for the multigrid requests: for the first iteration of every chunk of each such
+ * request (more than one level, iteration performed), the HIP-event time (ms) of the level-0
+ * black half-sweep after the coarse correction and its algorithmic bytes (14 per interior
+ * unknown: x and the node code of every node read, b and 1/D of the swept colour read, x of
+ * that colour written), the time of the whole V-cycle, and the number of samples. */
+int pb_server_profile_mg(const pb_server* srv, double* sweep_ms_total, double* sweep_bytes_total,
+                         double* vcycle_ms_total, int64_t* samples);
 
 /* Wait for the device, release every resident problem and the server. */
 void pb_server_destroy(pb_server* srv);

@@ -25,7 +25,7 @@ EXPORTED = [
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
-    "pb_mg_vcycle", "pb_server_profile_mg",
+    "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg",
 ]
 
 
@@ -56,6 +56,11 @@ class PbEnergyOut(C.Structure):
     _fields_ = [("e_coul", C.c_double), ("e_pol", C.c_double), ("e_ion", C.c_double),
                 ("e_solv", C.c_double), ("e_total", C.c_double), ("q_pol_total", C.c_double),
                 ("area_total", C.c_double), ("n_cut", C.c_int64), ("t_energy_s", C.c_double)]
+
+
+class PbBindingOut(C.Structure):
+    _fields_ = [("ddg_total", C.c_double), ("ddg_coul", C.c_double), ("ddg_pol", C.c_double),
+                ("ddg_ion", C.c_double)]
 
 
 class PbError(RuntimeError):
@@ -119,6 +124,8 @@ def load(path: str = LIB_PATH):
     L.pb_copy_refined_cells.argtypes = [P, P]
     L.pb_copy_fine_potential.argtypes = [P, P]
     L.pb_mg_vcycle.argtypes = [P, P, P, C.POINTER(i32)]
+    L.pb_binding_ddg.argtypes = [C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut),
+                                 C.POINTER(PbBindingOut)]
     _lib = L
     return L
 
@@ -182,6 +189,23 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _energy_struct(e: dict) -> PbEnergyOut:
+    out = PbEnergyOut()
+    for k, _ in PbEnergyOut._fields_:
+        setattr(out, k, e.get(k, 0))
+    return out
+
+
+def binding_ddg(e_complex: dict, e_part1: dict, e_part2: dict) -> dict:
+    """ddG of a complex from the energies of it and its two parts (pb_binding_ddg)."""
+    out = PbBindingOut()
+    a, b, c = _energy_struct(e_complex), _energy_struct(e_part1), _energy_struct(e_part2)
+    rc = _lib.pb_binding_ddg(C.byref(a), C.byref(b), C.byref(c), C.byref(out))
+    if rc != PB_OK:
+        raise _err(rc)
+    return {k: getattr(out, k) for k, _ in PbBindingOut._fields_}
 
 
 def make_params(grid) -> PbParams:

@@ -972,6 +972,16 @@ int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, d
     return PB_OK;
 }
 
+int pb_binding_ddg(const pb_energy_out* c, const pb_energy_out* a, const pb_energy_out* b, pb_binding_out* out)
+{
+    if (!c || !a || !b || !out) return fail(PB_EINVAL, "NULL argument");
+    out->ddg_coul = c->e_coul - a->e_coul - b->e_coul;
+    out->ddg_pol = c->e_pol - a->e_pol - b->e_pol;
+    out->ddg_ion = c->e_ion - a->e_ion - b->e_ion;
+    out->ddg_total = c->e_total - a->e_total - b->e_total;
+    return PB_OK;
+}
+
 int pb_mg_vcycle(pb_problem* pb, const double* r_host, double* z_host, int32_t* levels)
 {
     if (!pb || !r_host || !z_host) return fail(PB_EINVAL, "NULL argument");

@@ -83,40 +83,47 @@ __device__ __forceinline__ T nsum(const Lev<T>& L, const Op0<T>& op, int64_t e, 
 }
 
 // Per-node kernels run on a 3-D grid of 256-thread blocks, 64 lanes along z by 4 rows along
-// y, one block layer per x-plane, so that no thread divides to find its node.  A colour
-// kernel gives lane m the m-th node of its colour in the row.
+// y, each block layer covering kPlanes x-planes (a thread takes the same (j, k) slot in each),
+// so that no thread divides to find its node and a launch has few enough blocks that one
+// which finds the iteration stopped costs little.  A colour kernel gives lane m the m-th node
+// of its colour in the row.
+constexpr int kPlanes = 4;
+
 inline dim3 node_grid(const Grid& g, bool colour)
 {
     const int nzl = colour ? (g.nz - 1) / 2 : g.nz - 2;   // nodes per interior row
-    return dim3((unsigned)std::max(1, (nzl + 63) / 64), (unsigned)((g.ny - 2 + 3) / 4), (unsigned)(g.nx - 2));
+    return dim3((unsigned)std::max(1, (nzl + 63) / 64), (unsigned)((g.ny - 2 + 3) / 4),
+                (unsigned)((g.nx - 2 + kPlanes - 1) / kPlanes));
 }
 
-// interior node of this thread (all nodes), or -1; red tells its colour
-__device__ __forceinline__ int64_t this_node(const Grid& g, bool& red)
+// interior node of this thread in plane r of its block layer (all nodes), or -1; red tells
+// its colour
+__device__ __forceinline__ int64_t this_node(const Grid& g, int r, bool& red)
 {
     const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
     const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int i = 1 + (int)blockIdx.z;
-    if (k > g.nz - 2 || j > g.ny - 2) return -1;
+    const int i = 1 + (int)blockIdx.z * kPlanes + r;
+    if (k > g.nz - 2 || j > g.ny - 2 || i > g.nx - 2) return -1;
     red = ((i + j + k) & 1) == 0;
     return g.idx(i, j, k);
 }
 
-// interior node of colour c (0 red, 1 black) of this thread, or -1; with its indices
-__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int& i, int& j, int& k)
+// interior node of colour c (0 red, 1 black) of this thread in plane r of its block layer,
+// or -1; with its indices
+__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int r, int& i, int& j, int& k)
 {
     const int m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
     j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    i = 1 + (int)blockIdx.z;
+    i = 1 + (int)blockIdx.z * kPlanes + r;
     k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
-    if (k > g.nz - 2 || j > g.ny - 2) return -1;
+    if (k > g.nz - 2 || j > g.ny - 2 || i > g.nx - 2) return -1;
     return g.idx(i, j, k);
 }
 
-__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c)
+__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int r)
 {
     int i, j, k;
-    return this_colour_node(g, c, i, j, k);
+    return this_colour_node(g, c, r, i, j, k);
 }
 
 // the same for the one-block coarsest solve: node t of colour c in (i, j, m) order
@@ -168,17 +175,20 @@ template <typename T, bool L0>
 __global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, Gate st)
 {
     if (halted(st)) return;
-    bool red;
-    const int64_t e = this_node(L.g, red);
-    if (e < 0) return;
     const T* __restrict__ b = L.b;
     const T* __restrict__ dinv = L.dinv;
-    if (red) {
-        L.x[e] = b[e] * dinv[e];
-        return;
+#pragma unroll
+    for (int r = 0; r < kPlanes; ++r) {
+        bool red;
+        const int64_t e = this_node(L.g, r, red);
+        if (e < 0) continue;
+        if (red) {
+            L.x[e] = b[e] * dinv[e];
+        } else {
+            const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return b[n] * dinv[n]; });
+            L.x[e] = (b[e] + s) * dinv[e];
+        }
     }
-    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return b[n] * dinv[n]; });
-    L.x[e] = (b[e] + s) * dinv[e];
 }
 
 // Gauss-Seidel on the nodes of one colour
@@ -186,11 +196,14 @@ template <typename T, bool L0>
 __global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, Gate st)
 {
     if (halted(st)) return;
-    const int64_t e = this_colour_node(L.g, c);
-    if (e < 0) return;
     const T* __restrict__ x = L.x;
-    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; });
-    L.x[e] = (L.b[e] + s) * L.dinv[e];
+#pragma unroll
+    for (int r = 0; r < kPlanes; ++r) {
+        const int64_t e = this_colour_node(L.g, c, r);
+        if (e < 0) continue;
+        const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; });
+        L.x[e] = (L.b[e] + s) * L.dinv[e];
+    }
 }
 
 // residual b - A x at the red nodes (after a black half-sweep the black residual is zero,
@@ -199,12 +212,15 @@ template <typename T, bool L0>
 __global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restrict__ r, Gate st)
 {
     if (halted(st)) return;
-    const int64_t e = this_colour_node(L.g, 0);
-    if (e < 0) return;
     const T* __restrict__ x = L.x;
-    T D;
-    const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; }, &D);
-    r[e] = L.b[e] - (D * x[e] - s);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        const int64_t e = this_colour_node(L.g, 0, p);
+        if (e < 0) continue;
+        T D;
+        const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; }, &D);
+        r[e] = L.b[e] - (D * x[e] - s);
+    }
 }
 
 // coarse right-hand side P^T r: fine node 2I and its 12 red neighbours (two odd offsets,
@@ -214,16 +230,21 @@ __global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__
                                                   Gate st)
 {
     if (halted(st)) return;
-    const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int I = 1 + (int)blockIdx.z;
-    if (K > gc.nz - 2 || J > gc.ny - 2) return;
-    const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
     const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
-    const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
-    const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
-    const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
-    bc[gc.idx(I, J, K)] = r[f] + (T)0.25 * ((xy + xz) + yz);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        bool red;
+        const int64_t ec = this_node(gc, p, red);
+        if (ec < 0) continue;
+        const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+        const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+        const int I = 1 + (int)blockIdx.z * kPlanes + p;
+        const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
+        const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
+        const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
+        const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
+        bc[ec] = r[f] + (T)0.25 * ((xy + xz) + yz);
+    }
 }
 
 // P e at fine node (i, j, k): trilinear from the coarse corners of its coarse cell
@@ -243,10 +264,13 @@ __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Gri
                                                  Gate st)
 {
     if (halted(st)) return;
-    int i, j, k;
-    const int64_t e = this_colour_node(gf, 0, i, j, k);
-    if (e < 0) return;
-    x[e] += prolong_at(gc, ec, i, j, k);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, k;
+        const int64_t e = this_colour_node(gf, 0, p, i, j, k);
+        if (e < 0) continue;
+        x[e] += prolong_at(gc, ec, i, j, k);
+    }
 }
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
@@ -1077,8 +1101,10 @@ int solve_t(pb_problem* pb, CGState* out)
         for (int it = 0; prof && it < n; ++it) {
             if ((launched + it) % 4 != 0 || evs.size() >= 4 * 128) continue;
             for (int e = 0; e < 4; ++e) {
+                // timing only: no system-scope fence, whose cache writeback of the data the
+                // sampled kernels wrote would otherwise be counted in their time
                 hipEvent_t x;
-                RCHK(hipEventCreate(&x));
+                RCHK(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
                 evs.push_back(x);
             }
             ev_it.push_back(launched + it);

@@ -427,8 +427,9 @@ int launch_chunk(pb_server* s, int k)
             smp.id = mgm[q]->id;
             for (int e = 0; e < 4; ++e) {
                 if (s->ev_pool.empty()) {
+                    // timing only: no system-scope fence (its cache writeback would count)
                     hipEvent_t x;
-                    SCHK(hipEventCreate(&x));
+                    SCHK(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
                     s->ev_pool.push_back(x);
                 }
                 smp.e[e] = s->ev_pool.back();

@@ -190,3 +190,56 @@ def serving_stream_c5(n_req: int = 512, seed: int = 2505, rate_hz: float = 1.0, 
         mol = random_molecule(na, Rs, seed * 100003 + k)
         out.append((float(t[k]), mol, cubic_grid(n, float(hs[k]), **kw)))
     return out
+
+
+# --- binding energies (complex and parts) --------------------------------------
+
+def binding_complex(seed: int, n_rec: int = 1500, n_lig: int = 250, R_rec: float = 18.0, R_lig: float = 8.0,
+                    gap: float = 1.0):
+    """A synthetic receptor-ligand pair and their complex: two molecules generated in balls
+    whose centres are R_rec + R_lig + gap apart along x (atom centres of the two parts at
+    least gap apart; their spheres overlap across the interface), the complex being the union
+    of their atoms.  Returns (complex, receptor, ligand), centred on the complex's bounding
+    box."""
+    rec = random_molecule(n_rec, R_rec, 2 * seed + 1)
+    lig = random_molecule(n_lig, R_lig, 2 * seed + 2, center=(R_rec + R_lig + gap, 0.0, 0.0))
+    xyz = np.concatenate([rec.xyz, lig.xyz])
+    rad = np.concatenate([rec.radius, lig.radius])
+    lo = (xyz - rad[:, None]).min(axis=0)
+    hi = (xyz + rad[:, None]).max(axis=0)
+    shift = -0.5 * (lo + hi)
+    rec = Molecule(rec.xyz + shift, rec.radius, rec.charge)
+    lig = Molecule(lig.xyz + shift, lig.radius, lig.charge)
+    cpx = Molecule(np.ascontiguousarray(np.concatenate([rec.xyz, lig.xyz])), np.ascontiguousarray(rad),
+                   np.ascontiguousarray(np.concatenate([rec.charge, lig.charge])))
+    return cpx, rec, lig
+
+
+def shifted(mol: Molecule, d) -> Molecule:
+    return Molecule(np.ascontiguousarray(mol.xyz + np.asarray(d, dtype=np.float64)[None, :]), mol.radius, mol.charge)
+
+
+def binding_grid(cpx: Molecule, h: float, margin: float = 8.0, **kw) -> GridSpec:
+    """One cubic grid for a complex and its parts: the complex's extent plus a margin on every
+    side, cells rounded up to a multiple of 32."""
+    ext = float(((cpx.xyz + cpx.radius[:, None]).max(axis=0) - (cpx.xyz - cpx.radius[:, None]).min(axis=0)).max())
+    cells = 32 * math.ceil((ext + 2.0 * margin) / (32.0 * h))
+    return cubic_grid(cells + 1, h, **kw)
+
+
+def binding_workload(n_complex: int = 6, n_disp: int = 30, h: float = 0.5, seed: int = 2506, **kw):
+    """The binding-energy protocol of the paper on synthetic complexes: for each complex, the
+    solute's centroid is displaced n_disp times uniformly within a cube of half the grid
+    spacing (the same displacement for the complex and its parts, the grid fixed), and each
+    displacement needs three solves.  Returns a list of (complex index, displacement index,
+    part 'c' | '1' | '2', molecule, grid)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(n_complex):
+        cpx, rec, lig = binding_complex(seed * 1000 + c)
+        grid = binding_grid(cpx, h, **kw)
+        for k in range(n_disp):
+            d = rng.uniform(-0.25 * h, 0.25 * h, size=3)
+            for part, mol in (("c", cpx), ("1", rec), ("2", lig)):
+                out.append((c, k, part, shifted(mol, d), grid))
+    return out
