@@ -275,6 +275,11 @@ int pb_ctx_set_profiling(pb_ctx* ctx, int on);
  * coarse correction, and the whole V-cycle. */
 int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples);
 
+/* With profiling on in the problem's context: HIP-event time (ms) of the energy N-body
+ * kernel (atoms x cut points, FP64; a12) of the last pb_energy, and its number of pairs
+ * (n_atoms * n_cut); both 0 when it was not timed. */
+int pb_get_energy_profile(const pb_problem* pb, double* nbody_ms, double* pairs);
+
 /* Attainable-bandwidth reference: `reps` launches of a plain streaming copy of `bytes`
  * bytes between two buffers from the context allocator, timed with HIP events; *gbps is
  * (bytes read + bytes written) per second / 1e9. */
@@ -335,6 +340,11 @@ int pb_server_profile(const pb_server* srv, double* stencil_ms_total, double* st
  * that colour written), the time of the whole V-cycle, and the number of samples. */
 int pb_server_profile_mg(const pb_server* srv, double* sweep_ms_total, double* sweep_bytes_total,
                          double* vcycle_ms_total, int64_t* samples);
+
+/* With profiling on in build_ctx: the HIP-event time (ms) of the energy N-body kernel summed
+ * over every request read back, the pairs (n_atoms * n_cut) summed likewise, and the number
+ * of such read-backs. */
+int pb_server_profile_energy(const pb_server* srv, double* nbody_ms_total, double* pairs_total, int64_t* calls);
 
 /* Wait for the device, release every resident problem and the server. */
 void pb_server_destroy(pb_server* srv);

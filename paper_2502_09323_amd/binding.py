@@ -25,7 +25,7 @@ EXPORTED = [
     "pb_time_stencil", "pb_ctx_set_profiling", "pb_get_profile", "pb_problem_bytes", "pb_stream_copy",
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
-    "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg",
+    "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg", "pb_get_energy_profile", "pb_server_profile_energy",
 ]
 
 
@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH):
     L.pb_copy_refined_cells.argtypes = [P, P]
     L.pb_copy_fine_potential.argtypes = [P, P]
     L.pb_mg_vcycle.argtypes = [P, P, P, C.POINTER(i32)]
+    L.pb_get_energy_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.pb_server_profile_energy.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
     L.pb_binding_ddg.argtypes = [C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut),
                                  C.POINTER(PbBindingOut)]
     _lib = L
@@ -357,6 +359,13 @@ class Problem:
             raise _err(rc)
         return dict(stencil_ms=a.value, update_ms=b.value, samples=n.value)
 
+    def energy_profile(self) -> dict:
+        a, b = C.c_double(), C.c_double()
+        rc = _lib.pb_get_energy_profile(self.h, C.byref(a), C.byref(b))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(nbody_ms=a.value, nbody_pairs=b.value)
+
     def nbytes(self) -> int:
         return int(_lib.pb_problem_bytes(self.h))
 
@@ -438,6 +447,11 @@ class Server:
         if rc != PB_OK:
             raise _err(rc)
         out.update(mg_sweep_ms=c.value, mg_sweep_bytes=d.value, mg_vcycle_ms=e.value, mg_samples=m.value)
+        f, g, k = C.c_double(), C.c_double(), C.c_int64()
+        rc = _lib.pb_server_profile_energy(self.h, C.byref(f), C.byref(g), C.byref(k))
+        if rc != PB_OK:
+            raise _err(rc)
+        out.update(nbody_ms=f.value, nbody_pairs=g.value, nbody_calls=k.value)
         return out
 
     def times(self) -> dict:
@@ -468,6 +482,7 @@ def solve(mol, grid, ctx: Context | None = None, per_atom: bool = False) -> dict
         st = pb.solve()
         en = pb.energy(per_atom=per_atom)
         en.update(st)
+        en.update(pb.energy_profile())
         return en
     finally:
         pb.close()

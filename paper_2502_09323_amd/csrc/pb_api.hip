@@ -346,10 +346,16 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     HIPCHK(launch_fill(s, pb->e_tmp[3], 16 * sizeof(double)));
     HIPCHK(launch_edge_fields(s, pb->g, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
                               pb->kcut, pb->x, pb->gb, pb->wp, pb->F, pb->phip, pb->pts, pb->rp, pb->np));
+    pb->prof_nbody_ms = pb->prof_nbody_pairs = 0;
+    pb->nb_timed = pb->ctx->profile && pb->na > 0 && pb->ncut > 0;
+    if (pb->nb_timed && !pb->nb_ev[0])
+        for (int e = 0; e < 2; ++e) HIPCHK(hipEventCreateWithFlags(&pb->nb_ev[e], hipEventDisableSystemFence));
     if (pb->na > 0) {
-        if (pb->ncut > 0)
+        if (pb->ncut > 0) {
+            if (pb->nb_timed) HIPCHK(hipEventRecord(pb->nb_ev[0], s));
             HIPCHK(launch_nbody(s, at, pb->ncut, pb->pts, pb->e_tmp[0], pb->e_nchunk));
-        else
+            if (pb->nb_timed) HIPCHK(hipEventRecord(pb->nb_ev[1], s));
+        } else
             HIPCHK(launch_fill(s, pb->e_tmp[0], sizeof(double) * 2 * na1 * (size_t)pb->e_nchunk));
         HIPCHK(launch_coulomb(s, at, pb->e_tmp[1]));
         HIPCHK(launch_energy_reduce(s, at, pb->e_tmp[0], pb->e_nchunk, pb->e_tmp[1], pb->prm.eps_in, pb->prm.eps_out,
@@ -363,6 +369,14 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
 
 int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* stats)
 {
+    if (pb->nb_timed) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, pb->nb_ev[0], pb->nb_ev[1]) == hipSuccess) {
+            pb->prof_nbody_ms = ms;
+            pb->prof_nbody_pairs = (double)pb->na * (double)pb->ncut;
+        }
+        pb->nb_timed = false;
+    }
     for (int t = 0; t < 4; ++t)
         if (pb->e_tmp[t]) {
             pb->mem.put(pb->e_tmp[t]);
@@ -500,6 +514,8 @@ void pbi_problem_destroy(pb_problem* pb, bool sync)
     pb->mg = nullptr;
     if (pb->hout) (void)hipHostFree(pb->hout);
     if (pb->ev) (void)hipEventDestroy(pb->ev);
+    for (int e = 0; e < 2; ++e)
+        if (pb->nb_ev[e]) (void)hipEventDestroy(pb->nb_ev[e]);
     pb->mem.release();
     delete pb;
 }
@@ -849,6 +865,15 @@ int pb_solve(pb_problem* pb, pb_solve_stats* stats)
     stats->t_solve_s = now_s() - t0;
     pb->solved = status == PB_OK || status == PB_ENOCONV;
     return status;
+}
+
+int pb_get_energy_profile(const pb_problem* pb, double* nbody_ms, double* pairs)
+{
+    if (!pb) return fail(PB_EINVAL, "NULL problem");
+    const pb_problem* q = pb->ref ? pb->ref->fine : pb;   // a refined problem's energy runs on its fine lattice
+    if (nbody_ms) *nbody_ms = q->prof_nbody_ms;
+    if (pairs) *pairs = q->prof_nbody_pairs;
+    return PB_OK;
 }
 
 int pb_get_profile(const pb_problem* pb, double* stencil_ms_avg, double* update_ms_avg, int32_t* samples)

@@ -80,44 +80,76 @@ __global__ void __launch_bounds__(256) k_edge_fields(Grid g, double eps_in, doub
     o[7] = wp[c] * pp;
 }
 
-// grid (ceil(n_atoms/256), nchunk); partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} over the chunk
+// 1/sqrt(x) in FP64: the FP32 reciprocal square root as a start, then two Newton steps
+// y <- y (3 - x y^2) / 2, each of which squares the relative error (about 1e-7 -> 1e-14 ->
+// rounding level), in place of the library's FP64 square root and division
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = (double)rsqrtf((float)x);
+    y = y * (1.5 - 0.5 * (x * y * y));
+    y = y * (1.5 - 0.5 * (x * y * y));
+    return y;
+}
+
+// grid (ceil(n_atoms/512), nchunk), two atoms per thread (a and a + 256), so that each cut
+// point read from LDS serves two pairs; partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} over
+// the chunk
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
                                                double* __restrict__ partial, int64_t chunk_len)
 {
     __shared__ double sp[NB_TILE * 8];
-    const int a = blockIdx.x * 256 + threadIdx.x;
-    const bool act = a < at.n;
-    double xi = 0, yi = 0, zi = 0;
-    if (act) {
-        xi = at.xyzr[4 * a];
-        yi = at.xyzr[4 * a + 1];
-        zi = at.xyzr[4 * a + 2];
+    const int a0 = blockIdx.x * 512 + threadIdx.x, a1 = a0 + 256;
+    const bool act0 = a0 < at.n, act1 = a1 < at.n;
+    double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+    if (act0) {
+        x0 = at.xyzr[4 * a0];
+        y0 = at.xyzr[4 * a0 + 1];
+        z0 = at.xyzr[4 * a0 + 2];
+    }
+    if (act1) {
+        x1 = at.xyzr[4 * a1];
+        y1 = at.xyzr[4 * a1 + 1];
+        z1 = at.xyzr[4 * a1 + 2];
+    } else {
+        // an inactive slot evaluates the pairs of a far point, whose sums are discarded
+        x1 = x0 + 1e3;
+        y1 = y0;
+        z1 = z0;
     }
     const int64_t p0 = (int64_t)blockIdx.y * chunk_len;
     int64_t p1 = p0 + chunk_len;
     if (p1 > ncut) p1 = ncut;
-    double sf = 0.0, sd = 0.0;
+    double sf0 = 0.0, sd0 = 0.0, sf1 = 0.0, sd1 = 0.0;
     for (int64_t base = p0; base < p1; base += NB_TILE) {
         const int m = (int)((p1 - base) < NB_TILE ? (p1 - base) : NB_TILE);
         __syncthreads();
         for (int t = threadIdx.x; t < m * 8; t += 256) sp[t] = pts[base * 8 + t];
         __syncthreads();
-        if (act) {
+        if (act0) {
             for (int u = 0; u < m; ++u) {
                 const double* P = sp + 8 * u;
-                const double dx = P[0] - xi, dy = P[1] - yi, dz = P[2] - zi;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double ri = rsqrt(r2);
-                const double dn = dx * P[3] + dy * P[4] + dz * P[5];
-                sf += P[6] * ri;
-                sd += P[7] * dn * (ri * ri * ri);
+                const double dx0 = P[0] - x0, dy0 = P[1] - y0, dz0 = P[2] - z0;
+                const double dx1 = P[0] - x1, dy1 = P[1] - y1, dz1 = P[2] - z1;
+                const double r0 = rsqrt_nr(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+                const double r1 = rsqrt_nr(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+                const double dn0 = dx0 * P[3] + dy0 * P[4] + dz0 * P[5];
+                const double dn1 = dx1 * P[3] + dy1 * P[4] + dz1 * P[5];
+                sf0 += P[6] * r0;
+                sd0 += P[7] * dn0 * (r0 * r0 * r0);
+                sf1 += P[6] * r1;
+                sd1 += P[7] * dn1 * (r1 * r1 * r1);
             }
         }
     }
-    if (act) {
-        double* o = partial + ((int64_t)blockIdx.y * at.n + a) * 2;
-        o[0] = sf;
-        o[1] = sd;
+    if (act0) {
+        double* o = partial + ((int64_t)blockIdx.y * at.n + a0) * 2;
+        o[0] = sf0;
+        o[1] = sd0;
+    }
+    if (act1) {
+        double* o = partial + ((int64_t)blockIdx.y * at.n + a1) * 2;
+        o[0] = sf1;
+        o[1] = sd1;
     }
 }
 
@@ -202,7 +234,7 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 int nbody_chunks(int n_atoms, int64_t ncut)
 {
     // enough blocks to fill 256 CUs several times, each chunk at least a few LDS tiles
-    const int ab = (n_atoms + 255) / 256;
+    const int ab = (n_atoms + 511) / 512;   // blocks of k_nbody along the atoms
     int64_t want = (2048 + ab - 1) / ab;
     int64_t maxc = (ncut + 4 * NB_TILE - 1) / (4 * NB_TILE);
     if (want > maxc) want = maxc;
@@ -226,7 +258,7 @@ hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const doub
                         int nchunk)
 {
     const int64_t len = (ncut + nchunk - 1) / nchunk;
-    dim3 grid(nblk(at.n, 256), (unsigned)nchunk);
+    dim3 grid(nblk(at.n, 512), (unsigned)nchunk);
     k_nbody<<<grid, 256, 0, s>>>(at, ncut, pts, partial, len > 0 ? len : 1);
     return hipGetLastError();
 }

@@ -167,6 +167,10 @@ struct pb_problem {
     // sampled kernel timings of the last solve (iteration kernel, tail kernel)
     double prof_stencil_ms = 0, prof_update_ms = 0;
     int prof_n = 0;
+    // the energy N-body kernel of the last read-back, timed while profiling is on
+    hipEvent_t nb_ev[2] = {nullptr, nullptr};
+    bool nb_timed = false;
+    double prof_nbody_ms = 0, prof_nbody_pairs = 0;
 };
 
 

@@ -134,6 +134,9 @@ struct pb_server {
     std::vector<hipEvent_t> ev_pool;
     double prof_mg_ms = 0, prof_mg_bytes = 0, prof_mg_vcycle_ms = 0;
     int64_t prof_mg_n = 0;
+    // the energy N-body kernel of every request read back while build_ctx profiles
+    double prof_nb_ms = 0, prof_nb_pairs = 0;
+    int64_t prof_nb_n = 0;
 
     double now() const
     {
@@ -290,6 +293,11 @@ int progress(pb_server* s)
             pb_energy_out e;
             pb_solve_stats st;
             pbi_energy_end(p.pb, &e, &st);
+            if (p.pb->prof_nbody_pairs > 0) {
+                s->prof_nb_ms += p.pb->prof_nbody_ms;
+                s->prof_nb_pairs += p.pb->prof_nbody_pairs;
+                s->prof_nb_n += 1;
+            }
             add_result(s, p.id, st.status, &e, &st);
             s->in_use -= std::min(s->in_use, pb_problem_bytes(p.pb));
             pbi_problem_destroy(p.pb, false);  // its read-back event has completed
@@ -593,6 +601,15 @@ int pb_server_profile_mg(const pb_server* s, double* sweep_ms_total, double* swe
     if (sweep_bytes_total) *sweep_bytes_total = s->prof_mg_bytes;
     if (vcycle_ms_total) *vcycle_ms_total = s->prof_mg_vcycle_ms;
     if (samples) *samples = s->prof_mg_n;
+    return PB_OK;
+}
+
+int pb_server_profile_energy(const pb_server* s, double* nbody_ms_total, double* pairs_total, int64_t* calls)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    if (nbody_ms_total) *nbody_ms_total = s->prof_nb_ms;
+    if (pairs_total) *pairs_total = s->prof_nb_pairs;
+    if (calls) *calls = s->prof_nb_n;
     return PB_OK;
 }
 
