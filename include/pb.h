@@ -99,7 +99,14 @@ typedef struct {
                                of 4 in [4, 128].  It changes only the summation order of the
                                reductions: a problem gives bit-identical results with the
                                same value alone or in the serving loop. */
-    int32_t refine;         /* 0: uniform grid.  1: one level of 2:1 local refinement (the
+    int32_t refine;         /* 0: uniform grid.  2: de-refinement toward the box (the
+                               paper's treatment of the box, Sect. 4.1 on BCs, with one
+                               level): the grid given is the coarse far field, and every
+                               coarse cell that meets the solute's extent (atom centres -/+
+                               radii) widened by refine_shell_A on all three axes is split,
+                               rounded up to bricks as below; use with PB_BC_ZERO on a box
+                               far from the solute.  Otherwise as refine = 1.
+                               1: one level of 2:1 local refinement (the
                                paper's octree restricted to one level, Sect. 3): a coarse cell
                                of size h is split into 8 cells of size h/2 when a crossing
                                point of the surface with the h/2 lattice lies within

@@ -62,6 +62,38 @@ def refine_cells(grid, rp: np.ndarray, delta: float, brick: int) -> np.ndarray:
     return out
 
 
+def refine_cells_box(grid, lo, hi, delta: float, brick: int) -> np.ndarray:
+    """De-refinement toward the box (the paper's Sect. 4.1 on BCs): every coarse cell that
+    meets the box [lo - delta, hi + delta] on all three axes is split (lo, hi: the solute's
+    extent, atom centres -/+ radii), rounded up to aligned bricks like refine_cells; the rest
+    of the domain, out to the box where the null Dirichlet values are applied, stays coarse."""
+    nc = [int(v) - 1 for v in grid.n]
+    H = float(grid.h)
+    flag = np.ones(nc, bool)
+    for d in range(3):
+        c = np.arange(nc[d])
+        blo = grid.origin[d] + H * c
+        bhi = grid.origin[d] + H * (c + 1)
+        ok = (bhi >= lo[d] - delta) & (blo <= hi[d] + delta)
+        shape = [1, 1, 1]
+        shape[d] = nc[d]
+        flag &= ok.reshape(shape)
+    out = np.zeros(nc, np.uint8)
+    nb = [(v + brick - 1) // brick for v in nc]
+    bf = np.zeros(nb, bool)
+    idx = np.argwhere(flag)
+    bf[idx[:, 0] // brick, idx[:, 1] // brick, idx[:, 2] // brick] = True
+    I, J, K = np.meshgrid(*[np.arange(v) for v in nc], indexing="ij")
+    out[...] = bf[I // brick, J // brick, K // brick]
+    return out
+
+
+def solute_extent(mol):
+    lo = (mol.xyz - mol.radius[:, None]).min(axis=0)
+    hi = (mol.xyz + mol.radius[:, None]).max(axis=0)
+    return lo, hi
+
+
 _AX = np.eye(3, dtype=np.int64)
 
 
@@ -108,7 +140,7 @@ class RefinedRun:
 
 
 def refined_run(mol, grid, delta: float = 3.0, brick: int = 4, rtol: float = 1e-12, max_iter: int = 100000,
-                solver: str = "pcg", want_energy: bool = True) -> RefinedRun:
+                solver: str = "pcg", want_energy: bool = True, mode: str = "surface") -> RefinedRun:
     """Geometry -> refinement -> constrained assembly -> load -> solve -> energies."""
     t0 = time.perf_counter()
     lB, kD = O.constants(grid.temp_K, grid.ionic_M, grid.eps_out)
@@ -122,7 +154,11 @@ def refined_run(mol, grid, delta: float = 3.0, brick: int = 4, rtol: float = 1e-
 
     sol = O.classify(fg, mol)
     cut = O.cut_edges(fg, mol, sol)
-    ref = refine_cells(grid, cut.rp, delta, brick).astype(bool)
+    if mode == "box":
+        lo, hi = solute_extent(mol)
+        ref = refine_cells_box(grid, lo, hi, delta, brick).astype(bool)
+    else:
+        ref = refine_cells(grid, cut.rp, delta, brick).astype(bool)
     if ref[0].any() or ref[-1].any() or ref[:, 0].any() or ref[:, -1].any() or ref[:, :, 0].any() or ref[:, :, -1].any():
         raise ValueError("refined cells touch the box boundary layer")
 

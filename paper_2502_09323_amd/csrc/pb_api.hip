@@ -96,7 +96,7 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (p->max_iter <= 0) return fail(PB_EINVAL, "max_iter must be > 0");
     if (p->tile_planes != 0 && (p->tile_planes < 4 || p->tile_planes > 128 || p->tile_planes % 4))
         return fail(PB_EINVAL, "tile_planes must be 0 or a multiple of 4 in [4, 128]");
-    if (p->refine != 0 && p->refine != 1) return fail(PB_EINVAL, "refine must be 0 or 1");
+    if (p->refine < 0 || p->refine > 2) return fail(PB_EINVAL, "refine must be 0, 1 or 2");
     if (p->refine) {
         if (!finite(p->refine_shell_A) || p->refine_shell_A < 0) return fail(PB_EINVAL, "refine_shell_A must be >= 0");
         if (p->refine_brick < 1 || p->refine_brick > 64) return fail(PB_EINVAL, "refine_brick must be in [1, 64]");

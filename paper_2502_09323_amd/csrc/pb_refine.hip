@@ -73,6 +73,27 @@ struct Cells {             // refinement flags of the coarse cells
 // ---- refinement rule ---------------------------------------------------------------------
 
 // every coarse cell within delta of a crossing point is flagged (all writers store 1)
+// de-refinement toward the box: a coarse cell is flagged when it meets the box
+// [lo - delta, hi + delta] (the solute's extent widened by delta) on all three axes
+__global__ void __launch_bounds__(256) k_mark_box(Grid gc, double lox, double loy, double loz, double hix, double hiy,
+                                                  double hiz, double delta, uint8_t* flag, int nc0, int nc1, int nc2)
+{
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)nc0 * nc1 * nc2;
+    if (t >= n) return;
+    const int k = (int)(t % nc2), j = (int)((t / nc2) % nc1), i = (int)(t / ((int64_t)nc2 * nc1));
+    const int c[3] = {i, j, k};
+    const double org[3] = {gc.ox, gc.oy, gc.oz}, lo[3] = {lox, loy, loz}, hi[3] = {hix, hiy, hiz};
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+        const double blo = org[d] + gc.h * (double)c[d];
+        const double bhi = org[d] + gc.h * (double)(c[d] + 1);
+        in = in && bhi >= lo[d] - delta && blo <= hi[d] + delta;
+    }
+    flag[t] = in ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(256) k_mark(Grid gc, int64_t ncut, const double* __restrict__ rp, double delta,
                                               uint8_t* flag, int nc0, int nc1, int nc2)
 {
@@ -709,8 +730,21 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
     uint8_t* bf = (uint8_t*)pb->mem.get((size_t)nb[0] * nb[1] * nb[2]);
     if (!R->cells || !flag || !bf) return pbi_fail(PB_ENOMEM, "refinement flags");
     RCHK(launch_fill(s, flag, (size_t)ncell));
-    if (fp->ncut > 0)
+    if (P.refine == 2) {
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = 1e300;
+            hi[d] = -1e300;
+            for (int64_t a = 0; a < na; ++a) {
+                lo[d] = std::min(lo[d], xyz[3 * a + d] - rad[a]);
+                hi[d] = std::max(hi[d], xyz[3 * a + d] + rad[a]);
+            }
+        }
+        k_mark_box<<<nblk(ncell, 256), 256, 0, s>>>(gc, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], R->delta, flag,
+                                                    R->nc[0], R->nc[1], R->nc[2]);
+    } else if (fp->ncut > 0) {
         k_mark<<<nblk(fp->ncut, 256), 256, 0, s>>>(gc, fp->ncut, fp->rp, R->delta, flag, R->nc[0], R->nc[1], R->nc[2]);
+    }
     k_bricks<<<nblk((int64_t)nb[0] * nb[1] * nb[2], 256), 256, 0, s>>>(flag, R->nc[0], R->nc[1], R->nc[2], B, nb[0], nb[1],
                                                                        nb[2], bf);
     k_cells_from_bricks<<<nblk(ncell, 256), 256, 0, s>>>(bf, R->nc[0], R->nc[1], R->nc[2], B, nb[1], nb[2], R->cells);

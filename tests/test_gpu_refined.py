@@ -48,13 +48,20 @@ def _cases():
         ("ragged_zero_bc", I.random_molecule(25, 2.5, 4),
          I.GridSpec(n=(37, 29, 45), h=0.5, origin=(-9.0, -7.0, -11.0), bc=I.BC_ZERO, refine=1, refine_shell=0.8,
                     refine_brick=3)),
+        # de-refinement toward a far box with null Dirichlet values (refine = 2)
+        ("derefined_zero_bc", I.random_molecule(30, 3.0, 9),
+         I.cubic_grid(29, 1.0, bc=I.BC_ZERO, refine=2, refine_shell=1.5, refine_brick=2)),
     ]
+
+
+def _mode(grid):
+    return "box" if grid.refine == 2 else "surface"
 
 
 @pytest.mark.parametrize("name,mol,grid", _cases(), ids=[c[0] for c in _cases()])
 def test_refined_parity(ctx, name, mol, grid):
     grid.rtol = 1e-12
-    ref = R.refined_run(mol, grid, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12)
+    ref = R.refined_run(mol, grid, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12, mode=_mode(grid))
     pb = B.Problem(ctx, mol, grid)
     try:
         info = pb.refine_info()
@@ -123,7 +130,7 @@ def test_refined_mixed_parity(ctx, name, mol, grid):
     goal, so energies and potentials agree with the FP64 oracle to 1e-6 (the Debye-Hueckel
     box values are FP32-evaluated in this mode)."""
     grid = replace(grid, precision=I.MIXED, rtol=1e-10, inner_rtol=1e-3)
-    ref = R.refined_run(mol, grid, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12)
+    ref = R.refined_run(mol, grid, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12, mode=_mode(grid))
     pb = B.Problem(ctx, mol, grid)
     try:
         st = pb.solve()

@@ -138,3 +138,57 @@ def test_refined_close_to_uniform_fine_grid():
     # only the far field is coarser
     assert abs(r.energy["e_pol"] / u.energy["e_pol"] - 1.0) < 3e-3
     assert abs(r.energy["e_ion"] / u.energy["e_ion"] - 1.0) < 2e-2
+
+
+def test_box_rule_covers_the_widened_extent_in_aligned_bricks():
+    """De-refinement toward the box: the refined cells are whole aligned bricks, they hold every
+    cell that meets the solute's extent widened by delta, and every refined brick meets it."""
+    mol = I.random_molecule(20, 3.0, 23, center=(0.3, -0.4, 0.2))
+    grid = I.cubic_grid(33, 1.0, bc=I.BC_ZERO)
+    delta, brick = 1.5, 3
+    lo, hi = R.solute_extent(mol)
+    ref = R.refine_cells_box(grid, lo, hi, delta, brick).astype(bool)
+    nc = ref.shape
+    H, o = grid.h, grid.origin
+    meets = np.ones(nc, bool)
+    for d in range(3):
+        c = np.arange(nc[d])
+        ok = (o[d] + H * (c + 1) >= lo[d] - delta) & (o[d] + H * c <= hi[d] + delta)
+        sh = [1, 1, 1]
+        sh[d] = nc[d]
+        meets &= ok.reshape(sh)
+    assert meets.any() and np.all(ref[meets])
+    for bi in range(0, nc[0], brick):
+        for bj in range(0, nc[1], brick):
+            for bk in range(0, nc[2], brick):
+                blk = ref[bi:bi + brick, bj:bj + brick, bk:bk + brick]
+                assert blk.all() or not blk.any()
+                if blk.any():
+                    assert meets[bi:bi + brick, bj:bj + brick, bk:bk + brick].any()
+
+
+def test_derefined_zero_bc_kirkwood():
+    """The paper's box treatment with one level: a fine region around the sphere, a coarse far
+    field and null Dirichlet values on a far box.  E_pol is exact for any box (discrete Gauss
+    law); E_ion approaches the uniform fine grid on the same box and improves as the box grows."""
+    gold = {}
+    for line in open(GOLD):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            gold[k] = float(v)
+    mol = I.single_charge_sphere(2.0, center=(0.13, -0.07, 0.21))
+    lB, kD = O.constants(298.15, 0.145, 80.0)
+    e_pol = 0.5 * (1.0 / 80.0 - 1.0 / 2.0) / 2.0 * lB
+    e_ion = -0.5 / 80.0 * kD / (1.0 + kD * 2.0) * lB
+    errs = []
+    for n in (21, 41):
+        grid = I.cubic_grid(n, 1.0, temp_K=298.15, bc=I.BC_ZERO)
+        run = R.refined_run(mol, grid, delta=2.0, brick=2, rtol=1e-12, mode="box")
+        assert 0 < run.refined.sum() < run.refined.size
+        assert abs(run.energy["e_pol"] / e_pol - 1.0) < 1e-10
+        errs.append(abs(run.energy["e_ion"] / e_ion - 1.0))
+    assert errs[1] < 0.5 * errs[0] and errs[1] < 2.0 * gold["ngpb_relerr_ion"]
+    # against the uniform h = 0.5 grid on the same 40 A box
+    u = O.run(mol, I.cubic_grid(81, 0.5, temp_K=298.15, bc=I.BC_ZERO), rtol=1e-12)
+    assert abs(run.energy["e_ion"] / u.energy["e_ion"] - 1.0) < 0.02
