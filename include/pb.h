@@ -148,7 +148,7 @@ typedef struct {
  * 4 pi sum q_i w_n(r_i) (eq. RVop_), boundary values and their lift, and the Jacobi
  * diagonal.
  *   xyz    : host, 3*n_atoms doubles, atom centres (x0,y0,z0,x1,...)
- *   radius : host, n_atoms doubles, > 0
+ *   radius : host, n_atoms doubles, finite and >= 1e-6 A
  *   charge : host, n_atoms doubles
  * Every atom ball must lie strictly inside [origin + h, origin + (n-2) h] on each axis.
  * On success *out owns all device state of the problem.

@@ -114,7 +114,7 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (na < 0 || na > (int64_t)1 << 26) return fail(PB_EINVAL, "bad atom count");
     if (na > 0 && (!xyz || !rad || !chg)) return fail(PB_EINVAL, "atom arrays are NULL");
     for (int64_t a = 0; a < na; ++a) {
-        if (!finite(rad[a]) || rad[a] <= 0 || !finite(chg[a])) return fail(PB_EINVAL, "atom %lld: bad radius/charge", (long long)a);
+        if (!finite(rad[a]) || rad[a] < 1e-6 || !finite(chg[a])) return fail(PB_EINVAL, "atom %lld: bad radius/charge", (long long)a);
         for (int d = 0; d < 3; ++d) {
             double c = xyz[3 * a + d];
             if (!finite(c)) return fail(PB_EINVAL, "atom %lld: non-finite coordinate", (long long)a);
@@ -330,9 +330,10 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     if (!pb->ev) HIPCHK(hipEventCreateWithFlags(&pb->ev, hipEventDisableTiming));
     pb->e_nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
     pb->e_tmp[0] = dalloc<double>(pb, 2 * na1 * (size_t)pb->e_nchunk, &rc);   // partial sums
-    if (!rc) pb->e_tmp[1] = dalloc<double>(pb, na1, &rc);                      // Coulomb potentials
+    const int ncc = coulomb_chunks((int)std::max<int64_t>(pb->na, 1));
+    if (!rc) pb->e_tmp[1] = dalloc<double>(pb, na1 * (size_t)ncc, &rc);        // Coulomb potentials
     if (!rc) pb->e_tmp[2] = dalloc<double>(pb, na1, &rc);                      // reaction potentials
-    if (!rc) pb->e_tmp[3] = dalloc<double>(pb, 16, &rc);                       // energy sums
+    if (!rc) pb->e_tmp[3] = dalloc<double>(pb, ENERGY_OUT_DOUBLES, &rc);       // energy sums
     if (rc) return rc;
     if (finish_mixed && pb->mg) {
         if ((rc = pbi_mg_finish(pb, s))) return rc;
@@ -357,9 +358,9 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
             if (pb->nb_timed) HIPCHK(hipEventRecord(pb->nb_ev[1], s));
         } else
             HIPCHK(launch_fill(s, pb->e_tmp[0], sizeof(double) * 2 * na1 * (size_t)pb->e_nchunk));
-        HIPCHK(launch_coulomb(s, at, pb->e_tmp[1]));
-        HIPCHK(launch_energy_reduce(s, at, pb->e_tmp[0], pb->e_nchunk, pb->e_tmp[1], pb->prm.eps_in, pb->prm.eps_out,
-                                    pb->lB, pb->e_tmp[2], pb->e_tmp[3], pb->F, pb->ncut, pb->wp));
+        HIPCHK(launch_coulomb(s, at, pb->e_tmp[1], ncc));
+        HIPCHK(launch_energy_reduce(s, at, pb->e_tmp[0], pb->e_nchunk, pb->e_tmp[1], ncc, pb->prm.eps_in,
+                                    pb->prm.eps_out, pb->lB, pb->e_tmp[2], pb->e_tmp[3], pb->F, pb->ncut, pb->wp));
     }
     HIPCHK(hipMemcpyAsync(pb->hout, pb->e_tmp[3], 16 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(pb->hout + 16, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));

@@ -438,10 +438,14 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, doub
 // then the exponential and the inverse distance in FP32 (a few units in the last place,
 // about 1e-7 relative per term), accumulated in FP64.  The box is tens of Angstrom from the
 // surface, so these errors reach the surface potential screened by exp(-kD d) and stay far
-// below the FP32 iteration's own rounding.
+// below the FP32 iteration's own rounding.  The hardware reciprocal square root and base-2
+// exponential are used directly: r^2 leaves the FP32 normal range only for an atom centre
+// within 1e-19 A of a box node, where the sum is singular anyway, and an exponent below
+// -126 gives 0 in place of a term under 1e-38.
 __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, double eps_out, double* gb)
 {
-    __shared__ double sa[256 * 4];
+    __shared__ double sa[256 * 3];
+    __shared__ float sq[256];
     int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool act = t < n_box(g);
     int i = 0, j = 0, k = 0;
@@ -453,21 +457,21 @@ __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, do
         int a = base + threadIdx.x;
         __syncthreads();
         if (a < at.n) {
-            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
-            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
-            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
-            sa[4 * threadIdx.x + 3] = at.q[a];
+            sa[3 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
+            sa[3 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
+            sa[3 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
+            sq[threadIdx.x] = (float)at.q[a];
         }
         __syncthreads();
         int m = at.n - base < 256 ? at.n - base : 256;
         if (act)
             for (int u = 0; u < m; ++u) {
-                const float dx = (float)(p[0] - sa[4 * u]), dy = (float)(p[1] - sa[4 * u + 1]),
-                            dz = (float)(p[2] - sa[4 * u + 2]);
+                const float dx = (float)(p[0] - sa[3 * u]), dy = (float)(p[1] - sa[3 * u + 1]),
+                            dz = (float)(p[2] - sa[3 * u + 2]);
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const float ri = __frsqrt_rn(r2);
-                const float e = exp2f(mk * (r2 * ri));
-                s += (double)((float)sa[4 * u + 3] * e * ri);
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
+                s += (double)(sq[u] * e * ri);
             }
     }
     if (act) gb[g.idx(i, j, k)] = s / eps_out;

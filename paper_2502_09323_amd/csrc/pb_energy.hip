@@ -11,10 +11,11 @@
 //   E_coul = 1/2 lB sum_i q_i sum_{j != i} q_j /(eps_in r_ij)
 //
 // The atoms x cut-points sum is the FP64 vector-ALU hot spot: points are staged through
-// LDS in tiles, each thread owns one atom, and the cut list is split into chunks whose
+// LDS in tiles, each thread owns a few atoms, and the cut list is split into chunks whose
 // per-atom partials are summed in chunk order, so the result does not depend on timing.
 #include "pb_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pbk {
@@ -73,88 +74,104 @@ __global__ void __launch_bounds__(256) k_edge_fields(Grid g, double eps_in, doub
     o[0] = rp[3 * c];
     o[1] = rp[3 * c + 1];
     o[2] = rp[3 * c + 2];
-    o[3] = np[3 * c];
-    o[4] = np[3 * c + 1];
-    o[5] = np[3 * c + 2];
+    const double wphi = wp[c] * pp;
+    o[3] = wphi * np[3 * c];
+    o[4] = wphi * np[3 * c + 1];
+    o[5] = wphi * np[3 * c + 2];
     o[6] = f;
-    o[7] = wp[c] * pp;
+    o[7] = 0.0;
 }
 
-// 1/sqrt(x) in FP64: the FP32 reciprocal square root as a start, then two Newton steps
-// y <- y (3 - x y^2) / 2, each of which squares the relative error (about 1e-7 -> 1e-14 ->
-// rounding level), in place of the library's FP64 square root and division
+// 1/sqrt(x) in FP64: the hardware FP32 reciprocal square root y as a start (relative error
+// d of about 1e-7), then one step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., with
+// e = 1 - x y^2 = 2d + O(d^2): the first omitted term, 5e^3/16, is below FP64 rounding.
+// Five FP64 operations in place of the library's square root and division.  The raw
+// instruction takes no denormal inputs: x is a squared atom-to-surface distance, which is at
+// least the smallest atom radius squared, since every cut point lies outside or on every ball.
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
-    double y = (double)rsqrtf((float)x);
-    y = y * (1.5 - 0.5 * (x * y * y));
-    y = y * (1.5 - 0.5 * (x * y * y));
-    return y;
+    const double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double e = fma(-x, y * y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
-// grid (ceil(n_atoms/512), nchunk), two atoms per thread (a and a + 256), so that each cut
-// point read from LDS serves two pairs; partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} over
-// the chunk
+#ifndef PB_NB_ATOMS
+#define PB_NB_ATOMS 4
+#endif
+constexpr int NB_ATOMS = PB_NB_ATOMS;            // atoms per thread
+constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
+
+// grid (ceil(n_atoms/NB_BLOCK_ATOMS), nchunk); thread t of block b owns the atoms
+// b*NB_BLOCK_ATOMS + t + 256 k (k < NB_ATOMS), so that each cut point read from LDS serves
+// NB_ATOMS pairs.  A cut point is (r_p, w_p phi_p n_p, F_p): the surface-potential weight is
+// folded into the normal when the point is written.  partial[(chunk*n + i)*2 + {0,1}] =
+// {S_F, S_D} of atom i over the chunk.
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
                                                double* __restrict__ partial, int64_t chunk_len)
 {
     __shared__ double sp[NB_TILE * 8];
-    const int a0 = blockIdx.x * 512 + threadIdx.x, a1 = a0 + 256;
-    const bool act0 = a0 < at.n, act1 = a1 < at.n;
-    double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
-    if (act0) {
-        x0 = at.xyzr[4 * a0];
-        y0 = at.xyzr[4 * a0 + 1];
-        z0 = at.xyzr[4 * a0 + 2];
-    }
-    if (act1) {
-        x1 = at.xyzr[4 * a1];
-        y1 = at.xyzr[4 * a1 + 1];
-        z1 = at.xyzr[4 * a1 + 2];
+    const int a0 = blockIdx.x * NB_BLOCK_ATOMS + threadIdx.x;
+    double ax[NB_ATOMS], ay[NB_ATOMS], az[NB_ATOMS], sf[NB_ATOMS], sd[NB_ATOMS];
+    if (a0 < at.n) {
+        ax[0] = at.xyzr[4 * a0];
+        ay[0] = at.xyzr[4 * a0 + 1];
+        az[0] = at.xyzr[4 * a0 + 2];
     } else {
-        // an inactive slot evaluates the pairs of a far point, whose sums are discarded
-        x1 = x0 + 1e3;
-        y1 = y0;
-        z1 = z0;
+        ax[0] = ay[0] = az[0] = 0.0;
     }
+#pragma unroll
+    for (int k = 1; k < NB_ATOMS; ++k) {
+        const int a = a0 + 256 * k;
+        if (a < at.n) {
+            ax[k] = at.xyzr[4 * a];
+            ay[k] = at.xyzr[4 * a + 1];
+            az[k] = at.xyzr[4 * a + 2];
+        } else {
+            // an inactive slot evaluates the pairs of a far point, whose sums are discarded
+            ax[k] = ax[0] + 1e3 * k;
+            ay[k] = ay[0];
+            az[k] = az[0];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB_ATOMS; ++k) sf[k] = sd[k] = 0.0;
     const int64_t p0 = (int64_t)blockIdx.y * chunk_len;
     int64_t p1 = p0 + chunk_len;
     if (p1 > ncut) p1 = ncut;
-    double sf0 = 0.0, sd0 = 0.0, sf1 = 0.0, sd1 = 0.0;
     for (int64_t base = p0; base < p1; base += NB_TILE) {
         const int m = (int)((p1 - base) < NB_TILE ? (p1 - base) : NB_TILE);
         __syncthreads();
         for (int t = threadIdx.x; t < m * 8; t += 256) sp[t] = pts[base * 8 + t];
         __syncthreads();
-        if (act0) {
+        if (a0 < at.n) {
             for (int u = 0; u < m; ++u) {
                 const double* P = sp + 8 * u;
-                const double dx0 = P[0] - x0, dy0 = P[1] - y0, dz0 = P[2] - z0;
-                const double dx1 = P[0] - x1, dy1 = P[1] - y1, dz1 = P[2] - z1;
-                const double r0 = rsqrt_nr(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-                const double r1 = rsqrt_nr(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
-                const double dn0 = dx0 * P[3] + dy0 * P[4] + dz0 * P[5];
-                const double dn1 = dx1 * P[3] + dy1 * P[4] + dz1 * P[5];
-                sf0 += P[6] * r0;
-                sd0 += P[7] * dn0 * (r0 * r0 * r0);
-                sf1 += P[6] * r1;
-                sd1 += P[7] * dn1 * (r1 * r1 * r1);
+                const double px = P[0], py = P[1], pz = P[2], wx = P[3], wy = P[4], wz = P[5], f = P[6];
+#pragma unroll
+                for (int k = 0; k < NB_ATOMS; ++k) {
+                    const double dx = px - ax[k], dy = py - ay[k], dz = pz - az[k];
+                    const double r = rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+                    const double dn = fma(dx, wx, fma(dy, wy, dz * wz));
+                    sf[k] = fma(f, r, sf[k]);
+                    sd[k] = fma(dn, (r * r) * r, sd[k]);
+                }
             }
         }
     }
-    if (act0) {
-        double* o = partial + ((int64_t)blockIdx.y * at.n + a0) * 2;
-        o[0] = sf0;
-        o[1] = sd0;
-    }
-    if (act1) {
-        double* o = partial + ((int64_t)blockIdx.y * at.n + a1) * 2;
-        o[0] = sf1;
-        o[1] = sd1;
+#pragma unroll
+    for (int k = 0; k < NB_ATOMS; ++k) {
+        const int a = a0 + 256 * k;
+        if (a < at.n) {
+            double* o = partial + ((int64_t)blockIdx.y * at.n + a) * 2;
+            o[0] = sf[k];
+            o[1] = sd[k];
+        }
     }
 }
 
-// phi_coul(i) = sum_{j != i} q_j / r_ij  (divided by eps_in later)
-__global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* phic)
+// phic[c*n + i] = sum over j != i in chunk c of q_j / r_ij  (divided by eps_in later); grid
+// (ceil(n/256), nchunk), chunk c covering whole 256-atom tiles
+__global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* __restrict__ phic, int tiles_per_chunk)
 {
     __shared__ double sa[256 * 4];
     const int a = blockIdx.x * 256 + threadIdx.x;
@@ -166,7 +183,10 @@ __global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* phic)
         zi = at.xyzr[4 * a + 2];
     }
     double s = 0.0;
-    for (int base = 0; base < at.n; base += 256) {
+    const int b0 = blockIdx.y * tiles_per_chunk * 256;
+    int b1 = b0 + tiles_per_chunk * 256;
+    if (b1 > at.n) b1 = at.n;
+    for (int base = b0; base < b1; base += 256) {
         const int j = base + threadIdx.x;
         __syncthreads();
         if (j < at.n) {
@@ -176,54 +196,82 @@ __global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* phic)
             sa[4 * threadIdx.x + 3] = at.q[j];
         }
         __syncthreads();
-        const int m = at.n - base < 256 ? at.n - base : 256;
+        const int m = b1 - base < 256 ? b1 - base : 256;
         if (act)
             for (int u = 0; u < m; ++u) {
-                if (base + u == a) continue;
                 const double dx = sa[4 * u] - xi, dy = sa[4 * u + 1] - yi, dz = sa[4 * u + 2] - zi;
-                s += sa[4 * u + 3] * rsqrt(dx * dx + dy * dy + dz * dz);
+                const double t = sa[4 * u + 3] * rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+                s += (base + u == a) ? 0.0 : t;   // the self term (not finite) is dropped by the select
             }
     }
-    if (act) phic[a] = s;
+    if (act) phic[(int64_t)blockIdx.y * at.n + a] = s;
 }
 
-// single block of 1024: per-atom potentials and the energy sums, in fixed order
-__global__ void __launch_bounds__(1024) k_energy_reduce(Atoms at, const double* partial, int nchunk,
-                                                        const double* phic, double eps_in, double eps_out,
-                                                        double lB, double* phi_reac, double* out,
-                                                        const double* F, int64_t ncut, const double* wp)
+constexpr int ER_BLOCKS = 256;   // most blocks of the energy reduction
+
+// Energy reduction, first stage: each block takes the atoms and cut points b*256 + t +
+// k*gridDim.x*256; an atom's potentials are its chunk partials summed in chunk order.
+// part[5*b + {0..4}] = {sum q phi_pol, sum q phi_ion, sum q phi_coul, sum F, sum w} of block b.
+__global__ void __launch_bounds__(256) k_energy_part(Atoms at, const double* __restrict__ partial, int nchunk,
+                                                     const double* __restrict__ phic, int ncc, double eps_in,
+                                                     double eps_out, double lB, double* __restrict__ phi_reac,
+                                                     const double* __restrict__ F, int64_t ncut,
+                                                     const double* __restrict__ wp, double* __restrict__ part)
 {
     __shared__ double sh[32];
     const double fpi = 1.0 / (4.0 * kPi);
-    double e_pol = 0.0, e_ion = 0.0, e_coul = 0.0, dummy = 0.0;
-    for (int a = threadIdx.x; a < at.n; a += 1024) {
-        double sf = 0.0, sd = 0.0;
+    double e_pol = 0.0, e_ion = 0.0, e_coul = 0.0, fs = 0.0, ws = 0.0, dummy = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x; a < at.n; a += stride) {
+        double sf = 0.0, sd = 0.0, pc = 0.0;
         for (int c = 0; c < nchunk; ++c) {
             sf += partial[((int64_t)c * at.n + a) * 2];
             sd += partial[((int64_t)c * at.n + a) * 2 + 1];
         }
+        for (int c = 0; c < ncc; ++c) pc += phic[(int64_t)c * at.n + a];
         const double ppol = (1.0 / eps_out - 1.0 / eps_in) * sf * fpi;
         const double pion = sd * fpi - sf * fpi / eps_out;
         const double q = at.q[a];
         e_pol += q * ppol;
         e_ion += q * pion;
-        e_coul += q * phic[a] / eps_in;
+        e_coul += q * pc / eps_in;
         phi_reac[a] = lB * (ppol + pion);
     }
-    block_sum2(e_pol, e_ion, sh, 16);
-    block_sum2(e_coul, dummy, sh, 16);
-    double fs = 0.0, ws = 0.0;
-    for (int64_t c = threadIdx.x; c < ncut; c += 1024) {
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ncut; c += stride) {
         fs += F[c];
         ws += wp[c];
     }
-    block_sum2(fs, ws, sh, 16);
+    block_sum2(e_pol, e_ion, sh, 4);
+    block_sum2(e_coul, fs, sh, 4);
+    block_sum2(ws, dummy, sh, 4);
     if (threadIdx.x == 0) {
-        out[0] = 0.5 * lB * e_coul;
-        out[1] = 0.5 * lB * e_pol;
-        out[2] = 0.5 * lB * e_ion;
-        out[3] = (1.0 / eps_out - 1.0 / eps_in) * fs * fpi;
-        out[4] = ws;
+        double* o = part + 5 * blockIdx.x;
+        o[0] = e_pol;
+        o[1] = e_ion;
+        o[2] = e_coul;
+        o[3] = fs;
+        o[4] = ws;
+    }
+}
+
+// second stage, one block: the block sums in block order, and the energies
+__global__ void __launch_bounds__(256) k_energy_final(const double* __restrict__ part, int nb, double eps_in,
+                                                      double eps_out, double lB, double* __restrict__ out)
+{
+    __shared__ double sh[32];
+    const double fpi = 1.0 / (4.0 * kPi);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dummy = 0.0;
+    if (threadIdx.x < nb)
+        for (int k = 0; k < 5; ++k) v[k] = part[5 * threadIdx.x + k];
+    block_sum2(v[0], v[1], sh, 4);
+    block_sum2(v[2], v[3], sh, 4);
+    block_sum2(v[4], dummy, sh, 4);
+    if (threadIdx.x == 0) {
+        out[0] = 0.5 * lB * v[2];
+        out[1] = 0.5 * lB * v[0];
+        out[2] = 0.5 * lB * v[1];
+        out[3] = (1.0 / eps_out - 1.0 / eps_in) * v[3] * fpi;
+        out[4] = v[4];
     }
 }
 
@@ -233,10 +281,10 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 int nbody_chunks(int n_atoms, int64_t ncut)
 {
-    // enough blocks to fill 256 CUs several times, each chunk at least a few LDS tiles
-    const int ab = (n_atoms + 511) / 512;   // blocks of k_nbody along the atoms
+    // enough blocks to fill 256 CUs several times, each chunk at least one LDS tile
+    const int ab = (n_atoms + NB_BLOCK_ATOMS - 1) / NB_BLOCK_ATOMS;   // blocks of k_nbody along the atoms
     int64_t want = (2048 + ab - 1) / ab;
-    int64_t maxc = (ncut + 4 * NB_TILE - 1) / (4 * NB_TILE);
+    int64_t maxc = (ncut + NB_TILE - 1) / NB_TILE;
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
     if (want > 4096) want = 4096;
@@ -258,23 +306,37 @@ hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const doub
                         int nchunk)
 {
     const int64_t len = (ncut + nchunk - 1) / nchunk;
-    dim3 grid(nblk(at.n, 512), (unsigned)nchunk);
+    dim3 grid(nblk(at.n, NB_BLOCK_ATOMS), (unsigned)nchunk);
     k_nbody<<<grid, 256, 0, s>>>(at, ncut, pts, partial, len > 0 ? len : 1);
     return hipGetLastError();
 }
 
-hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic)
+int coulomb_chunks(int n_atoms)
 {
-    k_coulomb<<<nblk(at.n, 256), 256, 0, s>>>(at, phic);
+    const int ab = (n_atoms + 255) / 256, tiles = ab;
+    int want = (2048 + ab - 1) / ab;
+    if (want > tiles) want = tiles;
+    if (want < 1) want = 1;
+    return want;
+}
+
+hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic, int ncc)
+{
+    const int tiles = (at.n + 255) / 256;
+    const int tpc = (tiles + ncc - 1) / ncc;
+    k_coulomb<<<dim3(nblk(at.n, 256), (unsigned)ncc), 256, 0, s>>>(at, phic, tpc > 0 ? tpc : 1);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, const double* partial, int nchunk,
-                                const double* phic, double eps_in, double eps_out, double lB, double* phi_reac,
-                                double* out, const double* F, int64_t ncut, const double* wp)
+                                const double* phic, int ncc, double eps_in, double eps_out, double lB,
+                                double* phi_reac, double* out, const double* F, int64_t ncut, const double* wp)
 {
-    k_energy_reduce<<<1, 1024, 0, s>>>(at, partial, nchunk, phic, eps_in, eps_out, lB, phi_reac, out, F, ncut,
-                                       wp);
+    int64_t need = std::max<int64_t>(at.n, ncut);
+    int nb = (int)std::min<int64_t>(ER_BLOCKS, std::max<int64_t>(1, (need + 255) / 256));
+    k_energy_part<<<nb, 256, 0, s>>>(at, partial, nchunk, phic, ncc, eps_in, eps_out, lB, phi_reac, F, ncut, wp,
+                                     out + 16);
+    k_energy_final<<<1, 256, 0, s>>>(out + 16, nb, eps_in, eps_out, lB, out);
     return hipGetLastError();
 }
 

@@ -191,15 +191,19 @@ hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, doubl
                               int64_t ncut, const int64_t* cutkey, const uint32_t* code,
                               const double* alpha, const double* kcut, const double* x,
                               const double* gb, const double* wp, double* F, double* phip,
-                              double* pts /* 8 per cut: rp, np, F, w*phip */, const double* rp,
+                              double* pts /* 8 per cut: rp, w*phip*np, F, 0 */, const double* rp,
                               const double* np);
 hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const double* pts,
                         double* partial, int nchunk);
-hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic);
+// phic: n_atoms * ncc partial Coulomb potentials, ncc = coulomb_chunks(n_atoms)
+hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic, int ncc);
+// out: ENERGY_OUT_DOUBLES (the five results, then per-block partial sums)
+constexpr int ENERGY_OUT_DOUBLES = 16 + 5 * 256;
 hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, const double* partial, int nchunk,
-                                const double* phic, double eps_in, double eps_out, double lB,
-                                double* phi_reac, double* out /* 4 */, const double* F, int64_t ncut,
+                                const double* phic, int ncc, double eps_in, double eps_out, double lB,
+                                double* phi_reac, double* out, const double* F, int64_t ncut,
                                 const double* wp);
 int nbody_chunks(int n_atoms, int64_t ncut);
+int coulomb_chunks(int n_atoms);
 
 }  // namespace pbk
