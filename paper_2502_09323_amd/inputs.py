@@ -49,8 +49,10 @@ class GridSpec:
     rtol: float = 1e-10
     max_iter: int = 20000
     tile_planes: int = 0      # planes per x-chunk of the GPU iteration tiles (0 = automatic)
-    refine: int = 0           # 1: one level of 2:1 local refinement near the surface
+    refine: int = 0           # 1: one level of 2:1 local refinement near the surface;
+                              # 2: the grid is a coarse far field, refined around the solute
     refine_shell: float = 3.0 # refine coarse cells within this distance of a crossing point
+                              # (refine 1) or of the solute's extent (refine 2)
     refine_brick: int = 4     # ... rounded up to aligned bricks of this many cells per edge
     precision: int = FP64
     inner_rtol: float = 1e-4
