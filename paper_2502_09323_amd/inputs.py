@@ -123,6 +123,35 @@ def random_molecule(n_atoms: int, sphere_R: float, seed: int,
                     np.ascontiguousarray(charge))
 
 
+def sphere_cluster(n: int, seed: int, r_lo: float = 1.5, r_hi: float = 2.5, gap: float = 1.0,
+                   q_sigma: float = 1.0, n_neutral_top: int = 3) -> Molecule:
+    """Non-overlapping charged spheres grown as an aggregate without symmetry (the paper's
+    many-sphere benchmark, Sect. 5: one central charge per sphere, the spheres with the
+    largest z left uncharged).  Sphere 0 sits at the origin; each later sphere is placed next
+    to a randomly chosen earlier one, at a centre distance of the two radii plus
+    gap * U[1, 1.5] in a uniformly random direction, and is kept only if it stays at least
+    ``gap`` from every other sphere.  Draw order: all radii, then per attempt (parent index,
+    direction as three normals, distance factor), then the charges; the ``n_neutral_top``
+    spheres of largest z then get charge 0."""
+    rng = np.random.default_rng(seed)
+    radius = rng.uniform(r_lo, r_hi, size=n)
+    xyz = np.zeros((n, 3))
+    k = 1
+    while k < n:
+        par = int(rng.integers(0, k))
+        v = rng.normal(size=3)
+        f = rng.uniform(1.0, 1.5)
+        c = xyz[par] + v / np.linalg.norm(v) * (radius[par] + radius[k] + gap * f)
+        d = np.linalg.norm(xyz[:k] - c, axis=1)
+        if np.all(d >= radius[:k] + radius[k] + gap):
+            xyz[k] = c
+            k += 1
+    charge = rng.normal(0.0, q_sigma, size=n)
+    if n_neutral_top > 0:
+        charge[np.argsort(xyz[:, 2])[-n_neutral_top:]] = 0.0
+    return Molecule(np.ascontiguousarray(xyz), np.ascontiguousarray(radius), np.ascontiguousarray(charge))
+
+
 def single_charge_sphere(R: float = 2.0, q: float = 1.0, center=(0.0, 0.0, 0.0)) -> Molecule:
     return Molecule(np.array([center], dtype=np.float64), np.array([R]), np.array([q]))
 

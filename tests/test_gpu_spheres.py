@@ -1,0 +1,82 @@
+"""The GPU path against the analytic many-sphere solution (the paper's analytical benchmark,
+Sect. "An analytical benchmark"): a 30-sphere cluster without symmetry, 27 charged, the three
+highest spheres uncharged, in an 80 A box with Debye-Hueckel box values, h = 0.5 and 0.25 A.
+
+The analytic energies and reaction potentials come from ``tests/golden/spheres30_analytic.txt``
+(written by ``tests/golden/make_spheres30.py`` from the many-sphere reference); the surface
+potential is compared with the reference evaluated at every crossing point (degree 8, whose
+pointwise error is far below the grid's).  Errors are discretization errors of the method:
+bounded, and shrinking with h.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import spheres as S
+from paper_2502_09323_amd import binding as B
+from paper_2502_09323_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "spheres30_analytic.txt")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    B.load()
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cluster():
+    gold = {}
+    for line in open(GOLD):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            gold[k] = float(v)
+    m = I.sphere_cluster(30, 2506)
+    lB, kD = O.constants(298.15, 0.145, 80.0)
+    sol = S.solve(S.Spheres(m.xyz, m.radius, m.charge), 2.0, 80.0, kD, N=8)
+    return m, gold, sol
+
+
+def _errors(ctx, m, gold, sol, n, h, prec):
+    lo, hi = (m.xyz - m.radius[:, None]).min(0), (m.xyz + m.radius[:, None]).max(0)
+    g = I.cubic_grid(n, h, center=tuple(0.5 * (lo + hi)), temp_K=298.15, precond=I.MG, precision=prec,
+                     rtol=1e-10, inner_rtol=1e-2)
+    pb = B.Problem(ctx, m, g)
+    try:
+        st = pb.solve()
+        assert st["status"] == 0
+        en = pb.energy(per_atom=True)
+        c = pb.cut(fields=True)
+    finally:
+        pb.close()
+    ana = np.zeros(len(c["phip"]))
+    for i in range(len(m.radius)):
+        sel = c["owner"] == i
+        ana[sel] = S.interior_potential(sol, i, c["rp"][sel])
+    surf = np.abs(c["phip"] - ana) / np.abs(ana).max()
+    pr = np.array([gold[f"phi_reac_{i}"] for i in range(len(m.radius))])
+    return dict({k: abs(en[k] / gold[k] - 1.0) for k in ("e_pol", "e_ion", "e_coul", "e_total")},
+                phi_reac=np.abs(en["phi_reac"] - pr).max() / np.abs(pr).max(),
+                surf50=float(np.median(surf)), surf95=float(np.percentile(surf, 95)))
+
+
+@pytest.mark.parametrize("prec", [I.FP64, I.MIXED], ids=["fp64", "mixed"])
+def test_thirty_spheres_against_the_analytic_solution(ctx, cluster, prec):
+    m, gold, sol = cluster
+    e5 = _errors(ctx, m, gold, sol, 161, 0.5, prec)
+    e25 = _errors(ctx, m, gold, sol, 321, 0.25, prec)
+    print("h=0.5", e5, "h=0.25", e25, flush=True)
+    for e in (e5, e25):
+        assert e["e_coul"] < 1e-12
+        assert e["e_pol"] < 3e-4 and e["e_total"] < 2e-4 and e["phi_reac"] < 5e-4
+    assert e5["e_ion"] < 0.08 and e25["e_ion"] < 0.01 and e25["e_ion"] < 0.25 * e5["e_ion"]
+    assert e5["surf50"] < 0.01 and e5["surf95"] < 0.05
+    assert e25["surf50"] < 0.5 * e5["surf50"] and e25["surf95"] < 0.5 * e5["surf95"]
