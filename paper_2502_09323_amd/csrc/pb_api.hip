@@ -326,7 +326,10 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
         if (!rc) pb->pts = dalloc<double>(pb, 8 * nc1, &rc);
         if (rc) return rc;
     }
-    if (!pb->hout) HIPCHK(hipHostMalloc((void**)&pb->hout, 16 * sizeof(double) + sizeof(CGState), hipHostMallocDefault));
+    if (!pb->hout) {
+        pb->hout = (double*)pb->ctx->pinned.get(16 * sizeof(double) + sizeof(CGState), &pb->hout_cap);
+        if (!pb->hout) return fail(PB_EDEVICE, "pinned host allocation failed");
+    }
     if (!pb->ev) HIPCHK(hipEventCreateWithFlags(&pb->ev, hipEventDisableTiming));
     pb->e_nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
     pb->e_tmp[0] = dalloc<double>(pb, 2 * na1 * (size_t)pb->e_nchunk, &rc);   // partial sums
@@ -465,6 +468,7 @@ void pb_ctx_destroy(pb_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < 2; ++k) (void)hipEventDestroy(c->ev[k]);
     (void)hipHostFree(c->host_state);
+    c->pinned.release();
     delete c;
 }
 
@@ -493,7 +497,7 @@ void release_tmp(pb_problem* pb)
     for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->cls,
                     (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full})
         if (d) pb->mem.put(d);
-    if (t->hpin) (void)hipHostFree(t->hpin);
+    if (t->hpin) pb->ctx->pinned.put(t->hpin, t->hpin_cap);   // the build's copies have completed
     delete t;
     pb->bt = nullptr;
 }
@@ -513,7 +517,7 @@ void pbi_problem_destroy(pb_problem* pb, bool sync)
     }
     delete pb->mg;   // its arrays are held by pb->mem
     pb->mg = nullptr;
-    if (pb->hout) (void)hipHostFree(pb->hout);
+    if (pb->hout) pb->ctx->pinned.put(pb->hout, pb->hout_cap);   // no read-back is pending
     if (pb->ev) (void)hipEventDestroy(pb->ev);
     for (int e = 0; e < 2; ++e)
         if (pb->nb_ev[e]) (void)hipEventDestroy(pb->nb_ev[e]);
@@ -617,7 +621,8 @@ int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz
     pb->q = dalloc<double>(pb, na1, &rc);
     CK(rc);
     // pinned staging: atoms (x, y, z, R), charges, and the two counts read back later
-    HK(hipHostMalloc((void**)&T.hpin, sizeof(double) * 5 * na1 + 64, hipHostMallocDefault));
+    T.hpin = (double*)ctx->pinned.get(sizeof(double) * 5 * na1 + 64, &T.hpin_cap);
+    if (!T.hpin) return bail(fail(PB_EDEVICE, "pinned host allocation failed"));
     double* hx = T.hpin;
     double* hq = T.hpin + 4 * na1;
     T.htot = (int*)(T.hpin + 5 * na1);

@@ -11,6 +11,45 @@
 
 int pbi_fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 
+// Pinned host blocks kept for reuse: allocating and freeing pinned memory per problem costs
+// milliseconds of host time, and freeing it waits for the device.  Blocks come in
+// power-of-two sizes of at least 4 KiB; a block is handed back only once no copy that uses
+// it can still be pending.  One host thread uses a context at a time.
+struct PinnedPool {
+    std::vector<std::pair<void*, size_t>> free_list;   // (block, capacity)
+    static size_t capacity(size_t n)
+    {
+        size_t c = 4096;
+        while (c < n) c <<= 1;
+        return c;
+    }
+    // a block of at least n bytes and its capacity, or nullptr
+    void* get(size_t n, size_t* cap)
+    {
+        const size_t c = capacity(n);
+        for (size_t i = free_list.size(); i-- > 0;)
+            if (free_list[i].second == c) {
+                void* p = free_list[i].first;
+                free_list.erase(free_list.begin() + (long)i);
+                *cap = c;
+                return p;
+            }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+        *cap = c;
+        return p;
+    }
+    void put(void* p, size_t cap)
+    {
+        if (p) free_list.emplace_back(p, cap);
+    }
+    void release()
+    {
+        for (auto& b : free_list) (void)hipHostFree(b.first);
+        free_list.clear();
+    }
+};
+
 struct pb_ctx {
     int device;
     hipStream_t stream;
@@ -21,6 +60,7 @@ struct pb_ctx {
     int profile;
     pbk::CGState* host_state;  // pinned, 2 slots for pipelined polling
     hipEvent_t ev[2];
+    PinnedPool pinned;         // staging and read-back blocks of this context's problems
 };
 
 struct DevAlloc {
@@ -63,7 +103,8 @@ struct BuildTmp {
     uint32_t* cls = nullptr;
     int *bslots = nullptr, *bcuts = nullptr, *tot = nullptr;
     int nblk = 0;
-    double* hpin = nullptr;   // pinned: atoms, charges, then the two counts
+    double* hpin = nullptr;   // pinned (context pool): atoms, charges, then the two counts
+    size_t hpin_cap = 0;
     int* htot = nullptr;
     double* full = nullptr;   // device copy of user boundary values
 };
@@ -160,7 +201,8 @@ struct pb_problem {
     RefineData* ref = nullptr;   // set for a locally refined problem
     MGData* mg = nullptr;        // set once a multigrid-preconditioned solve has run
     hipEvent_t ev = nullptr;     // marks the end of the last asynchronous phase
-    double* hout = nullptr;      // pinned: energy sums and the final CG state
+    double* hout = nullptr;      // pinned (context pool): energy sums and the final CG state
+    size_t hout_cap = 0;
     double* e_tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // energy temporaries
     int e_nchunk = 0;
 

@@ -38,6 +38,12 @@ namespace {
 constexpr int kChunkIters = 16;   // same chunk length as a solo mixed solve
 constexpr int kServerTilePlanes = 32;   // long x-chunks: a batched launch has blocks to spare
 constexpr int kMgStreams = 4;          // streams the multigrid problems are spread over
+// Multigrid problems converge in a few dozen iterations, so a fixed 16-iteration chunk with
+// a second chunk in flight would launch many iterations that find the solve stopped.  Their
+// chunks are sized instead: kMgFirst iterations, kMgSecond while the first is in flight, then
+// the estimate from the residual decay seen so far (see mg_chunk_iters).
+constexpr int kMgFirst = 12;
+constexpr int kMgSecond = 6;
 
 struct Request {
     pb_params prm;
@@ -56,6 +62,8 @@ struct Active {
     bool finished;      // converged, broke down or out of iterations; no more chunks
     bool mg;            // multigrid-preconditioned: its own launches on one of the side streams
     int lane;           // ... which one
+    int pending;        // iterations launched in chunks not yet completed
+    bool seen;          // snap holds the state after a completed chunk
     CGState snap;
 };
 
@@ -103,6 +111,7 @@ struct pb_server {
     CGState* hgather[2] = {nullptr, nullptr};
     int cap[2] = {0, 0};
     std::vector<uint64_t> members[2];
+    std::vector<int> members_n[2];   // iterations each member was given in the chunk
     hipEvent_t ev[2] = {};
     // multigrid problems run on side streams (a V-cycle is many small dependent launches;
     // several problems' launches overlap there); each chunk starts them after the chunk start
@@ -228,6 +237,8 @@ int complete_slot(pb_server* s, int k)
                 s->prof_bytes += (double)s->prof_nu[k][m] * 36.0 * (done > 0 ? done : 0);
             }
             a.snap = s->hgather[k][m];
+            a.pending -= s->members_n[k][m];
+            a.seen = true;
             const int stt = a.snap.status;
             if (stt == 1 || stt == 2 || a.launched >= a.pb->prm.max_iter) a.finished = true;
         }
@@ -282,6 +293,8 @@ int progress(pb_server* s)
             a.id = p.id;
             a.arrival = p.arrival;
             a.launched = 0;
+            a.pending = 0;
+            a.seen = false;
             a.last_chunk = -1;
             a.finished = false;
             a.mg = p.pb->prm.precond == PB_PRECOND_MG;
@@ -372,15 +385,50 @@ int admit(pb_server* s)
     return PB_OK;
 }
 
+// Iterations to give a multigrid problem in the next chunk; 0 when the chunk in flight is
+// expected to finish it.  From the state after its last completed chunk: the squared residual
+// fell from ||b||^2 (the solve starts at x = 0) to rr in iter_count iterations; at that mean
+// rate it reaches the goal after `need` more, `pending` of which are already launched.  An
+// estimate that falls short only costs one more chunk; one that runs over, launches that
+// return at once.
+int mg_chunk_iters(const Active& a)
+{
+    if (!a.seen) return a.pending == 0 ? kMgFirst : kMgSecond;
+    const CGState& st = a.snap;
+    int need = kChunkIters;
+    if (st.rr <= st.goal64) {
+        need = 0;
+    } else if (st.iter_count > 0 && st.rr > 0.0 && st.rr < st.bnorm2 && st.goal64 > 0.0) {
+        const double rate = std::log(st.rr / st.bnorm2) / (double)st.iter_count;   // < 0
+        if (rate < -1e-3) need = (int)std::min<double>(kChunkIters, std::ceil(std::log(st.goal64 / st.rr) / rate));
+    }
+    int n = std::min(need + 1 - a.pending, kChunkIters);
+    if (n < 0) n = 0;
+    if (n == 0 && a.pending == 0) n = 1;   // nothing in flight: keep it moving
+    return n;
+}
+
 int launch_chunk(pb_server* s, int k)
 {
     // Jacobi members first (one batched chunk), then the multigrid members (their own
     // launches); the gathered states follow the same order
     std::vector<Active*> mem, mgm;
-    for (auto& a : s->act)
-        if (!a.finished) (a.mg ? mgm : mem).push_back(&a);
+    std::vector<int> mgn;
+    for (auto& a : s->act) {
+        if (a.finished) continue;
+        if (!a.mg) {
+            mem.push_back(&a);
+        } else {
+            const int n = mg_chunk_iters(a);
+            if (n > 0) {
+                mgm.push_back(&a);
+                mgn.push_back(n);
+            }
+        }
+    }
     const int P = (int)mem.size(), Q = (int)mgm.size();
     s->members[k].clear();
+    s->members_n[k].clear();
     if (P + Q == 0) return PB_OK;
     int rc = ensure_slot(s, k, P + Q);
     if (rc) return rc;
@@ -397,8 +445,12 @@ int launch_chunk(pb_server* s, int k)
         t.add += d.nadd;
         t.res += d.nbres;
         s->members[k].push_back(mem[p]->id);
+        s->members_n[k].push_back(kChunkIters);
     }
-    for (auto* a : mgm) s->members[k].push_back(a->id);
+    for (int q = 0; q < Q; ++q) {
+        s->members[k].push_back(mgm[q]->id);
+        s->members_n[k].push_back(mgn[q]);
+    }
     o[P] = t.st;
     o[(P + 1) + P] = t.add;
     o[2 * (P + 1) + P] = t.res;
@@ -449,7 +501,7 @@ int launch_chunk(pb_server* s, int k)
             s->mg_samples[k].push_back(smp);
             sample = s->mg_samples[k].back().e;
         }
-        if ((rc = pbi_mg_chunk(pb, ms, kChunkIters, mgm[q]->launched == 0, sample))) return rc;
+        if ((rc = pbi_mg_chunk(pb, ms, mgn[q], mgm[q]->launched == 0, sample))) return rc;
         SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, ms));
     }
     for (int j = 0; j < kMgStreams; ++j)
@@ -463,11 +515,13 @@ int launch_chunk(pb_server* s, int k)
     s->slot_chunk[k] = s->chunk_id;
     for (auto* a : mem) {
         a->launched += kChunkIters;
+        a->pending += kChunkIters;
         a->last_chunk = s->chunk_id;
     }
-    for (auto* a : mgm) {
-        a->launched += kChunkIters;
-        a->last_chunk = s->chunk_id;
+    for (int q = 0; q < Q; ++q) {
+        mgm[q]->launched += mgn[q];
+        mgm[q]->pending += mgn[q];
+        mgm[q]->last_chunk = s->chunk_id;
     }
     s->chunk_id++;
     return PB_OK;
