@@ -547,114 +547,133 @@ __device__ __forceinline__ double tri_area(const double* a, const double* b, con
     return 0.5 * sqrt(x * x + y * y + z * z);
 }
 
+// The surface in one cell as bit fields, so that nothing is indexed at run time from a
+// private array: sm holds the solute flags of the 8 corners, each cut edge has two link
+// slots (4-bit fields of lk[0], lk[1], 15 = empty) naming the cut edges it is joined to on
+// the two faces it lies on.
+__device__ __forceinline__ int nib(uint64_t w, int i) { return (int)((w >> (4 * i)) & 15u); }
+__device__ __forceinline__ void set_nib(uint64_t& w, int i, int v)
+{
+    w = (w & ~((uint64_t)15 << (4 * i))) | ((uint64_t)v << (4 * i));
+}
+__device__ __forceinline__ void add_link(uint64_t* lk, int a, int b)
+{
+    if (nib(lk[0], a) == 15) set_nib(lk[0], a, b); else set_nib(lk[1], a, b);
+    if (nib(lk[0], b) == 15) set_nib(lk[0], b, a); else set_nib(lk[1], b, a);
+}
+
+// index into the cut list of cut edge le of the cell whose corner codes are cc
+__device__ __forceinline__ int64_t cell_cut_index(const uint32_t* cc, int le, const int* cutbase)
+{
+    const int lax = le >> 2, u = le & 1, v = (le >> 1) & 1;
+    const int c0 = lax == 0 ? 2 * u + 4 * v : (lax == 1 ? u + 4 * v : u + 2 * v);
+    uint32_t cd = cc[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) cd = c0 == q ? cc[q] : cd;
+    const uint32_t bits = (cd >> 2) & 7u;
+    return (int64_t)cutbase[cd >> C_SLOT_SHIFT] + __popc(bits & ((1u << lax) - 1u));
+}
+
+// one thread per cut edge: its marching-cubes weight, the sum over its four cells of a third
+// of the area of every triangle that touches it, each closed polygon triangulated as the
+// average over all fan starting vertices
 __global__ void __launch_bounds__(128) k_mc_weights(Grid g, const uint32_t* code, const int* cutbase,
                                                     int64_t ncut, const int64_t* cutkey,
                                                     const double* rp, double* wp)
 {
     int64_t c = (int64_t)blockIdx.x * 128 + threadIdx.x;
     if (c >= ncut) return;
-    int64_t key = cutkey[c];
-    int64_t e = key >> 2;
-    int ax = (int)(key & 3);
-    int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+    // local edges: 0..3 along x at (y,z) = 00,10,01,11; 4..7 along y at (x,z); 8..11 along z at
+    // (x,y); corners x + 2y + 4z; the faces (axis fa, side sd) and their four edges
+    constexpr int kC0[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
+    constexpr int kC1[12] = {1, 3, 5, 7, 2, 3, 6, 7, 4, 5, 6, 7};
+    constexpr int kFace[6][4] = {{4, 6, 8, 10}, {5, 7, 9, 11},    // x = 0, x = 1
+                                 {0, 2, 8, 9},  {1, 3, 10, 11},   // y = 0, y = 1
+                                 {0, 1, 4, 5},  {2, 3, 6, 7}};    // z = 0, z = 1
+    const int64_t key = cutkey[c];
+    const int64_t e = key >> 2;
+    const int ax = (int)(key & 3);
+    const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
     const int64_t stride[3] = {(int64_t)g.ny * g.S, g.S, 1};
     double total = 0.0;
     for (int u = 0; u < 2; ++u)
         for (int v = 0; v < 2; ++v) {
-            int64_t base = e - u * stride[a1] - v * stride[a2];  // cell lower corner
+            const int64_t base = e - u * stride[a1] - v * stride[a2];   // cell lower corner
             uint32_t cc[8];
-            int sol[8];
+            unsigned sm = 0;
+#pragma unroll
             for (int q = 0; q < 8; ++q) {
-                int64_t nq = base + (q & 1) * stride[0] + ((q >> 1) & 1) * stride[1] + ((q >> 2) & 1) * stride[2];
-                cc[q] = code[nq];
-                sol[q] = (int)(cc[q] & C_SOLUTE);
+                cc[q] = code[base + (q & 1) * stride[0] + ((q >> 1) & 1) * stride[1] + ((q >> 2) & 1) * stride[2]];
+                sm |= (cc[q] & C_SOLUTE) << q;
             }
-            bool cut[12];
-            int64_t gi[12];
-            int link[12][2];
-            int me = -1;
-            for (int le = 0; le < 12; ++le) {
-                int lax, c0, c1;
-                cedge(le, lax, c0, c1);
-                cut[le] = sol[c0] != sol[c1];
-                link[le][0] = link[le][1] = -1;
-                gi[le] = -1;
-                if (cut[le]) {
-                    uint32_t cd = cc[c0];
-                    uint32_t bits = (cd >> 2) & 7u;
-                    gi[le] = cutbase[cd >> C_SLOT_SHIFT] + __popc(bits & ((1u << lax) - 1u));
-                    if (gi[le] == c) me = le;
-                }
-            }
-            for (int fa = 0; fa < 3; ++fa)
-                for (int sd = 0; sd < 2; ++sd) {
-                    int fe[4], nf = 0, ncf = 0;
-                    for (int le = 0; le < 12; ++le) {
-                        int lax, c0, c1;
-                        cedge(le, lax, c0, c1);
-                        if (lax == fa) continue;
-                        if (((c0 >> fa) & 1) == sd && ((c1 >> fa) & 1) == sd) fe[nf++] = le;
-                    }
-                    for (int t = 0; t < 4; ++t) ncf += cut[fe[t]] ? 1 : 0;
-                    int pr[2][2], npr = 0;
-                    if (ncf == 2) {
-                        int x = -1, y = -1;
-                        for (int t = 0; t < 4; ++t)
-                            if (cut[fe[t]]) { if (x < 0) x = fe[t]; else y = fe[t]; }
-                        pr[0][0] = x; pr[0][1] = y; npr = 1;
-                    } else if (ncf == 4) {
-                        for (int q = 0; q < 8; ++q) {
-                            if (((q >> fa) & 1) != sd || !sol[q]) continue;
-                            int x = -1, y = -1;
-                            for (int t = 0; t < 4; ++t) {
-                                int lax, c0, c1;
-                                cedge(fe[t], lax, c0, c1);
-                                if (c0 == q || c1 == q) { if (x < 0) x = fe[t]; else y = fe[t]; }
-                            }
-                            pr[npr][0] = x; pr[npr][1] = y; npr++;
+            unsigned cut = 0;
+#pragma unroll
+            for (int le = 0; le < 12; ++le) cut |= (((sm >> kC0[le]) ^ (sm >> kC1[le])) & 1u) << le;
+            // this cell's copy of edge c: along ax, its low corner has bit a1 = u, bit a2 = v
+            const int q0 = (u << a1) | (v << a2);
+            const int me = ax == 0 ? ((q0 >> 1) & 1) + 2 * ((q0 >> 2) & 1)
+                                   : (ax == 1 ? 4 + (q0 & 1) + 2 * ((q0 >> 2) & 1) : 8 + (q0 & 1) + 2 * ((q0 >> 1) & 1));
+            uint64_t lk[2] = {~(uint64_t)0, ~(uint64_t)0};
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int fa = f >> 1, sd = f & 1;
+                int ncf = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) ncf += (cut >> kFace[f][t]) & 1u;
+                if (ncf == 2) {
+                    int x = -1, y = -1;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if ((cut >> kFace[f][t]) & 1u) {
+                            if (x < 0) x = kFace[f][t]; else y = kFace[f][t];
                         }
-                    }
-                    for (int t = 0; t < npr; ++t) {
-                        int x = pr[t][0], y = pr[t][1];
-                        if (link[x][0] < 0) link[x][0] = y; else link[x][1] = y;
-                        if (link[y][0] < 0) link[y][0] = x; else link[y][1] = x;
+                    add_link(lk, x, y);
+                } else if (ncf == 4) {
+                    // join the two cuts incident to the same solute corner
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (((q >> fa) & 1) != sd || !((sm >> q) & 1u)) continue;
+                        int x = -1, y = -1;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int le = kFace[f][t];
+                            if (kC0[le] == q || kC1[le] == q) {
+                                if (x < 0) x = le; else y = le;
+                            }
+                        }
+                        add_link(lk, x, y);
                     }
                 }
-            // walk loops in ascending start order until the loop holding `me` is found
-            bool seen[12];
-            for (int le = 0; le < 12; ++le) seen[le] = false;
-            int loop[12], m = 0;
-            for (int e0 = 0; e0 < 12; ++e0) {
-                if (!cut[e0] || seen[e0]) continue;
-                m = 0;
-                int prev = -1, cur = e0;
-                bool hit = false;
-                for (;;) {
-                    loop[m++] = cur;
-                    seen[cur] = true;
-                    hit = hit || (cur == me);
-                    int nxt = (link[cur][0] != prev) ? link[cur][0] : link[cur][1];
-                    if (nxt == e0 || nxt < 0 || m >= 12) break;
-                    prev = cur;
-                    cur = nxt;
-                }
-                if (hit) break;
-                m = 0;
+            }
+            // the polygon through me, in the order of its links, me first
+            uint64_t loop = 0;
+            int m = 0, prev = 15, cur = me;
+            for (;;) {
+                loop |= (uint64_t)cur << (4 * m);
+                ++m;
+                const int a = nib(lk[0], cur), b = nib(lk[1], cur);
+                const int nxt = a != prev ? a : b;
+                if (nxt == me || nxt == 15 || m >= 12) break;
+                prev = cur;
+                cur = nxt;
             }
             if (m < 3) continue;
-            int pe = 0;
-            for (int t = 0; t < m; ++t)
-                if (loop[t] == me) pe = t;
-            // average over the m fans: every fan triangle touching `me` gives area/(3m)
+            // fans from every start, triangles touching vertex 0 (me): from start 0 the
+            // m - 2 triangles (0, t, t+1); from start s >= 1 the triangle (s, m-1, 0) when
+            // s <= m-2 and (s, 0, 1) when s >= 2
+            auto P = [&](int k) { return rp + 3 * cell_cut_index(cc, nib(loop, k), cutbase); };
+            const double* p0 = P(0);
+            const double* p1 = P(1);
+            const double* pl = P(m - 1);
             double acc = 0.0;
-            for (int st = 0; st < m; ++st) {
-                const double* v0 = rp + 3 * gi[loop[st]];
-                for (int t = 1; t + 1 < m; ++t) {
-                    int i1 = (st + t) % m, i2 = (st + t + 1) % m;
-                    if (st != pe && i1 != pe && i2 != pe) continue;
-                    acc += tri_area(v0, rp + 3 * gi[loop[i1]], rp + 3 * gi[loop[i2]]);
-                }
+            const double* pa = p1;
+            for (int t = 1; t + 1 < m; ++t) {
+                const double* pb = t + 1 == m - 1 ? pl : P(t + 1);
+                acc += tri_area(p0, pa, pb);
+                pa = pb;
             }
+            for (int st = 1; st + 1 < m; ++st) acc += tri_area(st == 1 ? p1 : P(st), pl, p0);
+            for (int st = 2; st < m; ++st) acc += tri_area(st == m - 1 ? pl : P(st), p0, p1);
             total += acc / (3.0 * (double)m);
         }
     wp[c] = total;
