@@ -495,7 +495,7 @@ void release_tmp(pb_problem* pb)
     BuildTmp* t = pb->bt;
     if (!t) return;
     for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->cls,
-                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full})
+                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full, (void*)t->acell})
         if (d) pb->mem.put(d);
     if (t->hpin) pb->ctx->pinned.put(t->hpin, t->hpin_cap);   // the build's copies have completed
     delete t;
@@ -753,7 +753,9 @@ int pbi_build_continue(pb_problem* pb)
     CK(rc);
     pb->x = dalloc<double>(pb, N, &rc);
     CK(rc);
-    HIPCHK(launch_deposit(s, g, T.bn, at, pb->rhs));
+    T.acell = dalloc<double>(pb, 6 * (size_t)std::max<int64_t>(pb->na, 1), &rc);
+    CK(rc);
+    HIPCHK(launch_deposit(s, g, T.bn, at, T.acell, pb->rhs));
     HIPCHK(launch_fill(s, pb->gb, sizeof(double) * N));
     HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
     if (prm->bc == PB_BC_DH && pb->na > 0) {

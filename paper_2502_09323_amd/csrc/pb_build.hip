@@ -328,7 +328,28 @@ __global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, doub
 
 // ---- load vector ------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, double* rhs)
+// per atom: the grid cell that receives its charge (floor of its grid coordinates, clamped
+// to the cells of the grid) and its offsets in that cell: ac[6a + d] = t_d, ac[6a + 3 + d] =
+// the cell index along d
+__global__ void __launch_bounds__(256) k_atom_cells(Grid g, Atoms at, double* ac)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= at.n) return;
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const double org[3] = {g.ox, g.oy, g.oz};
+    for (int d = 0; d < 3; ++d) {
+        const double f = (at.xyzr[4 * a + d] - org[d]) / g.h - (double)g.off[d];
+        double fl = floor(f);
+        if (fl < 0) fl = 0;
+        if (fl > nn[d] - 2) fl = nn[d] - 2;
+        ac[6 * a + d] = f - fl;
+        ac[6 * a + 3 + d] = fl;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const double* __restrict__ ac,
+                                                 double* rhs)
 {
 #pragma clang fp contract(off)
     int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -341,8 +362,6 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, doubl
     }
     double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
     const int nd[3] = {i, j, k};
-    const int nn[3] = {g.nx, g.ny, g.nz};
-    const double org[3] = {g.ox, g.oy, g.oz};
     double sum = 0.0;
     int lo[3], hi[3];
     if (bin_range(b, p, lo, hi)) {
@@ -352,16 +371,12 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, doubl
                     int bi = (x * b.nby + y) * b.nbz + z;
                     for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
                         int id = b.ids[u];
-                        const double* a = at.xyzr + 4 * id;
+                        const double* c6 = ac + 6 * id;
                         double w = 1.0;
                         bool corner = true;
                         for (int d = 0; d < 3; ++d) {
-                            double f = (a[d] - org[d]) / g.h - (double)g.off[d];
-                            double fl = floor(f);
-                            if (fl < 0) fl = 0;
-                            if (fl > nn[d] - 2) fl = nn[d] - 2;
-                            int cl = (int)fl;
-                            double t = f - fl;
+                            const int cl = (int)c6[3 + d];
+                            const double t = c6[d];
                             if (nd[d] == cl) w = w * (1.0 - t);
                             else if (nd[d] == cl + 1) w = w * t;
                             else corner = false;
@@ -806,9 +821,10 @@ hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const At
     return hipGetLastError();
 }
 
-hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* rhs)
+hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs)
 {
-    k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, rhs);
+    if (at.n > 0) k_atom_cells<<<nblk(at.n, 256), 256, 0, s>>>(g, at, ac);
+    k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, ac, rhs);
     return hipGetLastError();
 }
 

@@ -98,39 +98,16 @@ __device__ __forceinline__ double rsqrt_nr(double x)
 constexpr int NB_ATOMS = 4;                       // atoms per thread
 constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
 
-// the pairs of one LDS tile of m cut points with the first K atoms of the thread
-template <int K>
-__device__ __forceinline__ void nb_tile(const double* __restrict__ sp, int m, const double* ax, const double* ay,
-                                        const double* az, double* sf, double* sd)
-{
-    for (int u = 0; u < m; ++u) {
-        const double* P = sp + 8 * u;
-        const double px = P[0], py = P[1], pz = P[2], wx = P[3], wy = P[4], wz = P[5], f = P[6];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double dx = px - ax[k], dy = py - ay[k], dz = pz - az[k];
-            const double r = rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
-            const double dn = fma(dx, wx, fma(dy, wy, dz * wz));
-            sf[k] = fma(f, r, sf[k]);
-            sd[k] = fma(dn, (r * r) * r, sd[k]);
-        }
-    }
-}
-
 // grid (ceil(n_atoms/NB_BLOCK_ATOMS), nchunk); thread t of block b owns the atoms
 // b*NB_BLOCK_ATOMS + t + 256 k (k < NB_ATOMS), so that each cut point read from LDS serves
-// up to NB_ATOMS pairs.  A block whose atoms fill only nk < NB_ATOMS groups of 256 (a small
-// molecule, or the last block) computes nk pairs per point: the choice is uniform over the
-// block.  A cut point is (r_p, w_p phi_p n_p, F_p): the surface-potential weight is folded
-// into the normal when the point is written.  partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D}
-// of atom i over the chunk.
+// NB_ATOMS pairs.  A cut point is (r_p, w_p phi_p n_p, F_p): the surface-potential weight is
+// folded into the normal when the point is written.  partial[(chunk*n + i)*2 + {0,1}] =
+// {S_F, S_D} of atom i over the chunk.
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
                                                double* __restrict__ partial, int64_t chunk_len)
 {
     __shared__ double sp[NB_TILE * 8];
     const int a0 = blockIdx.x * NB_BLOCK_ATOMS + threadIdx.x;
-    const int left = at.n - blockIdx.x * NB_BLOCK_ATOMS;
-    const int nk = left >= NB_BLOCK_ATOMS ? NB_ATOMS : (left + 255) / 256;
     double ax[NB_ATOMS], ay[NB_ATOMS], az[NB_ATOMS], sf[NB_ATOMS], sd[NB_ATOMS];
     if (a0 < at.n) {
         ax[0] = at.xyzr[4 * a0];
@@ -164,14 +141,18 @@ __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const dou
         for (int t = threadIdx.x; t < m * 8; t += 256) sp[t] = pts[base * 8 + t];
         __syncthreads();
         if (a0 < at.n) {
-            if (nk == 4)
-                nb_tile<4>(sp, m, ax, ay, az, sf, sd);
-            else if (nk == 3)
-                nb_tile<3>(sp, m, ax, ay, az, sf, sd);
-            else if (nk == 2)
-                nb_tile<2>(sp, m, ax, ay, az, sf, sd);
-            else
-                nb_tile<1>(sp, m, ax, ay, az, sf, sd);
+            for (int u = 0; u < m; ++u) {
+                const double* P = sp + 8 * u;
+                const double px = P[0], py = P[1], pz = P[2], wx = P[3], wy = P[4], wz = P[5], f = P[6];
+#pragma unroll
+                for (int k = 0; k < NB_ATOMS; ++k) {
+                    const double dx = px - ax[k], dy = py - ay[k], dz = pz - az[k];
+                    const double r = rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+                    const double dn = fma(dx, wx, fma(dy, wy, dz * wz));
+                    sf[k] = fma(f, r, sf[k]);
+                    sd[k] = fma(dn, (r * r) * r, sd[k]);
+                }
+            }
         }
     }
 #pragma unroll

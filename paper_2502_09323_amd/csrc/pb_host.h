@@ -107,6 +107,7 @@ struct BuildTmp {
     size_t hpin_cap = 0;
     int* htot = nullptr;
     double* full = nullptr;   // device copy of user boundary values
+    double* acell = nullptr;  // per atom: its deposition cell and offsets (6 doubles)
 };
 
 struct pb_problem;
@@ -154,7 +155,7 @@ struct MGData {
     void* x[PB_MG_MAX_LEVELS] = {};      // iterate (level 0: the CG vector z)
     void* b[PB_MG_MAX_LEVELS] = {};      // right-hand side (level 0: the CG residual)
     void* r[PB_MG_MAX_LEVELS] = {};      // residual at the red nodes (black entries 0)
-    void *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;   // CG r, z, p, q
+    void *cr = nullptr, *cz = nullptr, *cp = nullptr, *cp2 = nullptr, *cq = nullptr;   // CG r, z, p (two), q
     void* cx = nullptr;         // CG x: the FP64 solution, or the FP32 correction (mixed)
     double* part = nullptr;     // [3 * nb] block partial sums
     int nb = 0;

@@ -113,7 +113,8 @@ hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const At
                            double eps_in, double eps_out, int64_t ncut, const int64_t* cutkey,
                            const uint32_t* code, double* alpha, double* kcut, double* rp,
                            double* np, int* owner, double* ck64, float* ck32);
-hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* rhs);
+// ac: scratch of 6 doubles per atom (the atom's cell and offsets)
+hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs);
 hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
                         double* gb);
 hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb);

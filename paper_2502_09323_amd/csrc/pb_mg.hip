@@ -529,34 +529,45 @@ __device__ __forceinline__ void bsum(double* v, int nv, double* sh)
     for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
 }
 
-// p = z + beta p at the unknowns
+// The search direction is double buffered: an iteration with iter_count = ic reads the old
+// direction from buffer ic & 1 and writes the new one to the other (iter_count counts the
+// iterations that ran, so a restart between two iterations keeps the pairing).
 template <typename T>
-__global__ void __launch_bounds__(256) k_pupd(Grid g, const uint32_t* __restrict__ code, const T* __restrict__ z,
-                                              T* __restrict__ p, const CGState* st)
+__device__ __forceinline__ const T* p_old(const CGState* st, const T* p0, const T* p1)
 {
-    if (st->status != 0) return;
-    const T beta = (T)st->beta;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
-        if (!(code[e] & C_BOX)) p[e] = z[e] + beta * p[e];
+    return (st->iter_count & 1) ? p1 : p0;
+}
+template <typename T>
+__device__ __forceinline__ T* p_new(const CGState* st, T* p0, T* p1)
+{
+    return (st->iter_count & 1) ? p0 : p1;
 }
 
-// q = A p at the unknowns; partial sums of p.q
+// p = z + beta p_old and q = A p at the unknowns in one pass (the new direction at the six
+// neighbours is formed on the fly from z and p_old, which box nodes hold as 0); partial
+// sums of p.q
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(Grid g, Op0<T> op, const T* __restrict__ p, T* __restrict__ q,
-                                               double* part, const CGState* st)
+__global__ void __launch_bounds__(256) k_apply(Grid g, Op0<T> op, const T* __restrict__ z, T* p0, T* p1,
+                                               T* __restrict__ q, double* part, const CGState* st)
 {
     __shared__ double sh[8];
     if (st->status != 0) return;
+    const T* __restrict__ po = p_old(st, (const T*)p0, (const T*)p1);
+    T* __restrict__ pn = p_new(st, p0, p1);
+    const T beta = (T)st->beta;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
     double v[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
         if (op.code[e] & C_BOX) continue;
         const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-        const T s = ((k.xm * p[e - sx] + k.xp * p[e + sx]) + (k.ym * p[e - sy] + k.yp * p[e + sy])) +
-                    (k.zm * p[e - 1] + k.zp * p[e + 1]);
-        const T qe = k.diag() * p[e] - s;
+        auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
+        const T pe = pd(e);
+        const T s = ((k.xm * pd(e - sx) + k.xp * pd(e + sx)) + (k.ym * pd(e - sy) + k.yp * pd(e + sy))) +
+                    (k.zm * pd(e - 1) + k.zp * pd(e + 1));
+        const T qe = k.diag() * pe - s;
+        pn[e] = pe;
         q[e] = qe;
-        v[0] += (double)p[e] * (double)qe;
+        v[0] += (double)pe * (double)qe;
     }
     bsum(v, 1, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -584,11 +595,12 @@ __global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGSta
 // x += alpha p, r -= alpha q; partial sums of r.r (after the r.z slots)
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(Grid g, const uint32_t* __restrict__ code, T* __restrict__ x,
-                                                T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                                                T* __restrict__ r, T* p0, T* p1, const T* __restrict__ q,
                                                 double* part, int nb, const CGState* st)
 {
     __shared__ double sh[8];
     if (st->status != 0) return;
+    const T* __restrict__ p = p_new(st, p0, p1);
     const T a = (T)st->alpha;
     double v[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
@@ -982,8 +994,8 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
         G->dinv[0] = d0;
     }
     const Grid& g0 = pb->g;
-    void** cg[5] = {&G->cr, &G->cz, &G->cp, &G->cq, &G->cx};
-    const int ncg = sizeof(T) == 4 ? 5 : 4;
+    void** cg[6] = {&G->cr, &G->cz, &G->cp, &G->cp2, &G->cq, &G->cx};
+    const int ncg = sizeof(T) == 4 ? 6 : 5;
     for (int v = 0; v < ncg; ++v) {
         *cg[v] = pb->mem.get(sizeof(T) * (size_t)g0.N);
         if (!*cg[v]) return pbi_fail(PB_ENOMEM, "multigrid CG vectors");
@@ -1005,12 +1017,11 @@ void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent
     const MGData* G = pb->mg;
     const Grid& g = pb->g;
     const Op0<T> op = op0<T>(pb);
-    T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p = (T*)G->cp, *q = (T*)G->cq;
+    T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p0 = (T*)G->cp, *p1 = (T*)G->cp2, *q = (T*)G->cq;
     const Gate gate{st, 0};
-    k_pupd<T><<<G->nb, 256, 0, s>>>(g, pb->code, z, p, st);
-    k_apply<T><<<G->nb, 256, 0, s>>>(g, op, p, q, G->part, st);
+    k_apply<T><<<G->nb, 256, 0, s>>>(g, op, z, p0, p1, q, G->part, st);
     k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
-    k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p, q, G->part, G->nb, st);
+    k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p0, p1, q, G->part, G->nb, st);
     launch_vcycle<T>(s, pb, gate, ev);
     k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, gate);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0);
@@ -1060,6 +1071,7 @@ int start_t(pb_problem* pb, hipStream_t s)
     RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
     if (sizeof(T) == 4) RCHK(launch_fill(s, G->cx, sizeof(float) * (size_t)pb->g.N));
     RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)pb->g.N));
+    RCHK(launch_fill(s, G->cp2, sizeof(T) * (size_t)pb->g.N));
     RCHK(launch_fill(s, pb->st, sizeof(CGState)));
     launch_restart<T>(s, pb, pb->st, 1, 1);
     RCHK(hipGetLastError());
