@@ -159,6 +159,8 @@ struct MGData {
     void* cx = nullptr;         // CG x: the FP64 solution, or the FP32 correction (mixed)
     double* part = nullptr;     // [3 * nb] block partial sums
     int nb = 0;
+    double* prz = nullptr;      // [nrz] r.z partial sums of the last half-sweep of a V-cycle
+    int nrz = 0;
 };
 
 struct pb_problem {

@@ -628,19 +628,57 @@ __global__ void __launch_bounds__(256) k_dot(Grid g, const uint32_t* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// the last red half-sweep of a V-cycle on level 0, and the partial sums of r.z = b.x over
+// all unknowns: lane m of a row updates its red node and adds the black node of the same pair
+// (k = 1 + 2m, 2 + 2m), final after the black half-sweep; partial sums per block in block
+// order (x, then y, then z)
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep_dot(Lev<T> L, Op0<T> op, Gate st, double* part)
+{
+    __shared__ double sh[8];
+    if (halted(st)) return;
+    const T* __restrict__ x = L.x;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int r = 0; r < kPlanes; ++r) {
+        int i, j, k;
+        const int64_t e = this_colour_node(L.g, 0, r, i, j, k);
+        if (e >= 0) {
+            const T s = nsum<T, true>(L, op, e, [&](int64_t n) { return x[n]; });
+            const T xn = (L.b[e] + s) * L.dinv[e];
+            L.x[e] = xn;
+            v[0] += (double)L.b[e] * (double)xn;
+        }
+        // the black node of the pair (k - 1 if k is even, else k + 1), which may exist when
+        // the red one lies past the row's end
+        const int kb = (k & 1) ? k + 1 : k - 1;
+        if (i <= L.g.nx - 2 && j <= L.g.ny - 2 && kb <= L.g.nz - 2) {
+            const int64_t eb = L.g.idx(i, j, kb);
+            v[0] += (double)L.b[eb] * (double)x[eb];
+        }
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = v[0];
+}
+
 // mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
 // recursive r.r (status = stop_status once r.r <= stop2, or <= trig2 in mixed precision);
 // mode 1 (first residual): beta = 0; mode 2 (after a residual replacement): the direction
 // update that the stopped step skipped takes beta = r'.z' / (r.z of the step before)
-__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode)
+// The r.z partials are prz[0 .. nrz) (those of the fused last half-sweep), or part[0 .. nb).
+__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode,
+                                              const double* prz, int nrz)
 {
     __shared__ double sh[8];
     if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
-    double v[2] = {0.0, 0.0};
-    for (int t = threadIdx.x; t < nb; t += 256) {
-        v[0] += part[t];
-        if (mode == 0) v[1] += part[nb + t];
+    if (!prz) {
+        prz = part;
+        nrz = nb;
     }
+    double v[2] = {0.0, 0.0};
+    for (int t = threadIdx.x; t < nrz; t += 256) v[0] += prz[t];
+    if (mode == 0)
+        for (int t = threadIdx.x; t < nb; t += 256) v[1] += part[nb + t];
     bsum(v, 2, sh);
     if (threadIdx.x == 0) {
         const double gm = v[0];
@@ -824,17 +862,22 @@ void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, Gate s
 }
 
 // coarse correction and post-smoothing (black, red) x nu
+// (level 0 with dot: the last red half-sweep also forms the r.z partial sums)
 template <typename T, bool L0>
 void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const Grid& gc, const T* ec,
-                 Gate st, hipEvent_t* ev = nullptr)
+                 Gate st, hipEvent_t* ev = nullptr, double* dot = nullptr)
 {
     k_prolong<T><<<node_grid(L.g, true), 256, 0, s>>>(L.g, L.x, gc, ec, st);
     if (ev) (void)hipEventRecord(ev[1], s);
-    launch_sweep<T, L0>(s, L, op, 1, st);
-    if (ev) (void)hipEventRecord(ev[2], s);
-    launch_sweep<T, L0>(s, L, op, 0, st);
-    for (int v = 1; v < nu; ++v) {
+    for (int v = 0; v < nu; ++v) {
         launch_sweep<T, L0>(s, L, op, 1, st);
+        if (v == 0 && ev) (void)hipEventRecord(ev[2], s);
+        if constexpr (L0) {
+            if (dot && v == nu - 1) {
+                if (colour_threads(L.g) > 0) k_sweep_dot<T><<<node_grid(L.g, true), 256, 0, s>>>(L, op, st, dot);
+                continue;
+            }
+        }
         launch_sweep<T, L0>(s, L, op, 0, st);
     }
 }
@@ -857,16 +900,17 @@ void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<
 
 // z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r); with ev, events around
 // the whole V-cycle (ev[0], ev[3]) and around the first level-0 black half-sweep after the
-// coarse correction (ev[1], ev[2])
+// coarse correction (ev[1], ev[2]).  With more than one level the last half-sweep also writes
+// the r.z partial sums to G->prz (G->nrz blocks); returns whether it did.
 template <typename T>
-void launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev = nullptr)
+bool launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
     const Op0<T> op = op0<T>(pb);
     const int L = G->nlev;
     if (L == 1) {
         launch_coarsest<T, true>(s, G, level<T>(G, 0), op, st);
-        return;
+        return false;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
     // the first level from which every level has at most kSubcycleNodes unknowns (not 0)
@@ -905,11 +949,12 @@ void launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev 
         const Lev<T> lv = level<T>(G, l);
         const T* ec = (const T*)G->x[l + 1];
         if (l == 0)
-            launch_post<T, true>(s, G->nu, lv, op, G->g[1], ec, st, ev);
+            launch_post<T, true>(s, G->nu, lv, op, G->g[1], ec, st, ev, G->prz);
         else
             launch_post<T, false>(s, G->nu, lv, op, G->g[l + 1], ec, st);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
+    return true;
 }
 
 // the level hierarchy and the solver vectors, enqueued on stream s (no host wait); the FP64
@@ -1007,6 +1052,12 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
     G->nb = (int)std::min<int64_t>(8192, (int64_t)nblk(g0.N, 256));
     G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
     if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
+    {
+        const dim3 ng = node_grid(g0, true);
+        G->nrz = (int)(ng.x * ng.y * ng.z);
+        G->prz = (double*)pb->mem.get(sizeof(double) * (size_t)G->nrz);
+        if (!G->prz) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
+    }
     RCHK(hipGetLastError());
     return PB_OK;
 }
@@ -1022,9 +1073,9 @@ void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent
     k_apply<T><<<G->nb, 256, 0, s>>>(g, op, z, p0, p1, q, G->part, st);
     k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
     k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p0, p1, q, G->part, G->nb, st);
-    launch_vcycle<T>(s, pb, gate, ev);
-    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, gate);
-    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0);
+    const bool fused = launch_vcycle<T>(s, pb, gate, ev);
+    if (!fused) k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, gate);
+    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0, fused ? G->prz : nullptr, G->nrz);
 }
 
 // restart from the true residual: fold the FP32 correction into the FP64 solution (mixed),
@@ -1044,9 +1095,9 @@ void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init, int fo
     k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol,
                                force);
     const Gate gate{st, 1};
-    launch_vcycle<T>(s, pb, gate);
-    k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, gate);
-    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2);
+    const bool fused = launch_vcycle<T>(s, pb, gate);
+    if (!fused) k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, gate);
+    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2, fused ? G->prz : nullptr, G->nrz);
 }
 
 template <typename T>
