@@ -312,6 +312,9 @@ def refined_run(mol, grid, delta: float = 3.0, brick: int = 4, rtol: float = 1e-
     if solver == "dense":
         xs = np.linalg.solve(A.toarray(), b)
         it, rr, st = 0, float(np.linalg.norm(b - A @ xs) / max(np.linalg.norm(b), 1e-300)), 0
+    elif solver == "mg":
+        pre = TwoLevel(A, grid, mol, free, nf)
+        xs, it, rr, st = pre.pcg(b, rtol, max_iter)
     else:
         xs, it, rr, st = O.pcg(A, b, rtol, max_iter)
     t2 = time.perf_counter()
@@ -323,3 +326,92 @@ def refined_run(mol, grid, delta: float = 3.0, brick: int = 4, rtol: float = 1e-
     t3 = time.perf_counter()
     return RefinedRun(lB, kD, ref, fg, sol, cut, A, b, free, hanging, phi, it, rr, st, en,
                       dict(build=t1 - t0, solve=t2 - t1, energy=t3 - t2))
+
+
+# ---- two-level preconditioner for the composite system ------------------------------------
+
+def coarse_interpolation(grid, free: np.ndarray, nf) -> "object":
+    """I_H: the trilinear interpolation of the coarse grid (all nodes, flat (i, j, k) order,
+    box nodes excluded) to the free vertices: a free vertex at fine-lattice coordinates F takes
+    coarse node F/2 with weight 1 along an even axis and nodes (F-1)/2, (F+1)/2 with weight
+    1/2 each along an odd one (the product over the axes)."""
+    import scipy.sparse as sp
+    n = np.array([int(v) for v in grid.n], np.int64)
+    nf = np.asarray(nf, np.int64)
+    F = np.stack([free // (nf[1] * nf[2]), (free // nf[2]) % nf[1], free % nf[2]], axis=1)
+    odd = (F % 2) == 1
+    rows, cols, vals = [], [], []
+    for s in range(8):
+        I = np.empty_like(F)
+        w = np.ones(F.shape[0])
+        ok = np.ones(F.shape[0], bool)
+        for d in range(3):
+            bit = (s >> d) & 1
+            I[:, d] = np.where(odd[:, d], (F[:, d] - 1) // 2 + bit, F[:, d] // 2)
+            ok &= odd[:, d] | (bit == 0)
+            w *= np.where(odd[:, d], 0.5, 1.0)
+        ok &= ((I > 0) & (I < n - 1)).all(axis=1)
+        rows.append(np.nonzero(ok)[0])
+        cols.append((I[ok, 0] * n[1] + I[ok, 1]) * n[2] + I[ok, 2])
+        vals.append(w[ok])
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(F.shape[0], int(n.prod()))).tocsr()
+
+
+class TwoLevel:
+    """Symmetric two-level preconditioner of the composite operator A (this implementation's,
+    like the uniform multigrid; the paper preconditions CG with SSOR, Sect. 4):
+
+        z1 = w D^-1 r,   z2 = z1 + I_H V(I_H^T (r - A z1)),   z = z2 + w D^-1 (r - A z2)
+
+    with D = diag(A), w = 0.8, and V one V-cycle of the uniform multigrid of the coarse grid
+    (its operator from the coarse-grid geometry, ``oracle.mg``; nu = grid.mg_smooth or 1,
+    coarse_sweeps = grid.mg_coarse_sweeps or 4, levels as grid.mg_levels).  It is
+    S + (I - S A) C (I - A S) + S (I - A S) with S = w D^-1 and C = I_H V I_H^T, symmetric,
+    and positive definite while w D^-1 A has spectral radius below 2 (about 1.6 here: the
+    composite operator is close to diagonally dominant, D^-1 A below 2)."""
+
+    OMEGA = 0.8
+
+    def __init__(self, A, grid, mol, free, nf):
+        from oracle import mg as M
+        self.M = M
+        self.A = A
+        self.dinv = 1.0 / A.diagonal()
+        self.IH = coarse_interpolation(grid, free, nf)
+        self.levels = M.hierarchy(M.fine_level(grid, mol), int(getattr(grid, "mg_levels", 0) or 0))
+        self.nu = int(getattr(grid, "mg_smooth", 0) or 1)
+        self.cs = int(getattr(grid, "mg_coarse_sweeps", 0) or 4)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        w = self.OMEGA
+        z = w * self.dinv * r
+        bc = (self.IH.T @ (r - self.A @ z)).reshape(self.levels[0].D.shape)
+        e = self.M.vcycle(self.levels, bc, self.nu, self.cs)
+        z = z + self.IH @ e.reshape(-1)
+        return z + w * self.dinv * (r - self.A @ z)
+
+    def pcg(self, b: np.ndarray, rtol: float, max_iter: int):
+        """PCG from x = 0, stopping on the recursive residual ||r|| <= rtol ||b||; returns
+        (x, iterations, relres, status 0 converged / 1 not)."""
+        x = np.zeros_like(b)
+        r = b.copy()
+        bn = float(np.linalg.norm(b))
+        if bn == 0.0:
+            return x, 0, 0.0, 0
+        z = self.apply(r)
+        p = z.copy()
+        gamma = float(r @ z)
+        for it in range(1, max_iter + 1):
+            q = self.A @ p
+            alpha = gamma / float(p @ q)
+            x += alpha * p
+            r -= alpha * q
+            rn = float(np.linalg.norm(r))
+            if rn <= rtol * bn:
+                return x, it, rn / bn, 0
+            z = self.apply(r)
+            g2 = float(r @ z)
+            p = z + (g2 / gamma) * p
+            gamma = g2
+        return x, max_iter, float(np.linalg.norm(r)) / bn, 1

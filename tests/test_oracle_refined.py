@@ -192,3 +192,37 @@ def test_derefined_zero_bc_kirkwood():
     # against the uniform h = 0.5 grid on the same 40 A box
     u = O.run(mol, I.cubic_grid(81, 0.5, temp_K=298.15, bc=I.BC_ZERO), rtol=1e-12)
     assert abs(run.energy["e_ion"] / u.energy["e_ion"] - 1.0) < 0.02
+
+
+def test_two_level_preconditioner_is_symmetric_positive_definite():
+    """The two-level preconditioner of the composite operator, as a dense matrix on a small
+    refined problem: symmetric, positive definite, and w D^-1 A inside the smoother's bound."""
+    mol = I.single_charge_sphere(1.5, center=(0.13, -0.07, 0.21))
+    grid = I.cubic_grid(13, 1.0, temp_K=298.15)
+    run = R.refined_run(mol, grid, delta=0.5, brick=2, rtol=1e-8)
+    pre = R.TwoLevel(run.A, grid, mol, run.free, run.fgrid.n)
+    n = run.A.shape[0]
+    assert 200 < n < 3000
+    Bm = np.column_stack([pre.apply(np.eye(n)[:, i]) for i in range(n)])
+    assert np.abs(Bm - Bm.T).max() <= 1e-12 * np.abs(Bm).max()
+    assert np.linalg.eigvalsh(0.5 * (Bm + Bm.T)).min() > 0.0
+    d = run.A.diagonal()
+    lam = np.linalg.eigvalsh((run.A.toarray() / np.sqrt(d)[:, None]) / np.sqrt(d)[None, :]).max()
+    assert pre.OMEGA * lam < 2.0
+
+
+@pytest.mark.parametrize("case", ["sphere", "molecule", "derefined"])
+def test_two_level_pcg_matches_jacobi_in_fewer_iterations(case):
+    if case == "sphere":
+        mol, grid, mode = I.single_charge_sphere(2.0, center=(0.13, -0.07, 0.21)), I.cubic_grid(25, 1.0, temp_K=298.15), "surface"
+    elif case == "molecule":
+        mol, grid, mode = I.random_molecule(30, 3.0, 7), I.cubic_grid(25, 1.0), "surface"
+    else:
+        mol, grid, mode = I.random_molecule(30, 3.0, 7), I.cubic_grid(29, 1.0, bc=I.BC_ZERO), "box"
+    a = R.refined_run(mol, grid, delta=1.5, brick=2, rtol=1e-12, mode=mode)
+    b = R.refined_run(mol, grid, delta=1.5, brick=2, rtol=1e-12, mode=mode, solver="mg")
+    assert b.status == 0 and 4 * b.iters <= a.iters
+    for k in ("e_pol", "e_ion"):
+        assert abs(b.energy[k] - a.energy[k]) <= 1e-10 * abs(a.energy[k]), k
+    ok = np.isfinite(a.phi)
+    assert np.abs(b.phi[ok] - a.phi[ok]).max() <= 1e-9 * np.abs(a.phi[ok]).max()
