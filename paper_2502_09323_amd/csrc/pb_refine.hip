@@ -514,6 +514,137 @@ __global__ void __launch_bounds__(256) k_pupd(int64_t N, const uint8_t* role, co
     p[e] = role[e] == 1 ? z[e] + (T)st->beta * p[e] : (T)0;
 }
 
+// ---- two-level preconditioner (FP64) ------------------------------------------------------
+// z = B r with B the symmetric two-level preconditioner: z1 = w D^-1 r, then the coarse-grid
+// correction z2 = z1 + I_H V(I_H^T (r - A z1)) with V one V-cycle of the coarse grid's own
+// multigrid (its operator from the coarse node-code map), then z = z2 + w D^-1 (r - A z2).
+// I_H interpolates the coarse grid trilinearly to the unknowns: a coarse unknown takes its own
+// node; a fine unknown at fine-lattice coordinates F takes coarse node F/2 along an even axis
+// and the two nodes (F -+ 1)/2 with weight 1/2 along an odd one.
+
+constexpr double kOmega = 0.8;   // smoother damping: w D^-1 A stays below 2 (SPD preconditioner)
+
+// z *= w at the unknowns
+__global__ void __launch_bounds__(256) k_zscale(Split sp, double* zc, double* zf, const CGState* st)
+{
+    if (st->status != 0) return;
+    const uint8_t* role = sp.role();
+    double* z = sp.coarse() ? zc : zf;
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
+        if (role[e] == 1) z[e] *= kOmega;
+}
+
+// q = r - q at the unknowns
+__global__ void __launch_bounds__(256) k_rsub(Split sp, const double* rc, const double* rf, double* qc, double* qf,
+                                              const CGState* st)
+{
+    if (st->status != 0) return;
+    const uint8_t* role = sp.role();
+    const double* r = sp.coarse() ? rc : rf;
+    double* q = sp.coarse() ? qc : qf;
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
+        if (role[e] == 1) q[e] = r[e] - q[e];
+}
+
+// bH = I_H^T w over the coarse grid (0 on the box and the pads): the node's own value where it
+// is a coarse unknown, plus the fine unknowns among the 27 fine nodes around it
+__global__ void __launch_bounds__(256) k_rest_h(Grid gc, Grid gf, const uint8_t* __restrict__ rolec,
+                                                const uint8_t* __restrict__ rolef, const double* __restrict__ wc,
+                                                const double* __restrict__ wf, double* __restrict__ bH,
+                                                const CGState* st)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= gc.N || st->status != 0) return;
+    int i, j, k;
+    decode(gc, e, i, j, k);
+    if (k < 1 || k > gc.nz - 2 || i < 1 || i > gc.nx - 2 || j < 1 || j > gc.ny - 2) {
+        bH[e] = 0.0;
+        return;
+    }
+    double v = rolec[e] == 1 ? wc[e] : 0.0;
+    const int F[3] = {2 * i - gf.off[0], 2 * j - gf.off[1], 2 * k - gf.off[2]};
+    const int nf[3] = {gf.nx, gf.ny, gf.nz};
+    bool near = true;
+    for (int d = 0; d < 3; ++d) near = near && F[d] >= -1 && F[d] <= nf[d];
+    if (near)
+        for (int a = -1; a <= 1; ++a)
+            for (int b = -1; b <= 1; ++b)
+                for (int c = -1; c <= 1; ++c) {
+                    const int f0 = F[0] + a, f1 = F[1] + b, f2 = F[2] + c;
+                    if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= nf[0] || f1 >= nf[1] || f2 >= nf[2]) continue;
+                    const int64_t ef = gf.idx(f0, f1, f2);
+                    if (rolef[ef] != 1) continue;
+                    const double w = (a ? 0.5 : 1.0) * (b ? 0.5 : 1.0) * (c ? 0.5 : 1.0);
+                    v += w * wf[ef];
+                }
+    bH[e] = v;
+}
+
+// z += I_H eH at the coarse unknowns
+__global__ void __launch_bounds__(256) k_prol_c(int64_t N, const uint8_t* __restrict__ rolec,
+                                                const double* __restrict__ eH, double* __restrict__ zc,
+                                                const CGState* st)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N || st->status != 0) return;
+    if (rolec[e] == 1) zc[e] += eH[e];
+}
+
+// z += I_H eH at the fine unknowns
+__global__ void __launch_bounds__(256) k_prol_f(Grid gf, Grid gc, const uint8_t* __restrict__ rolef,
+                                                const double* __restrict__ eH, double* __restrict__ zf,
+                                                const CGState* st)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= gf.N || st->status != 0) return;
+    if (rolef[e] != 1) return;
+    int i, j, k;
+    decode(gf, e, i, j, k);
+    const int F[3] = {i + gf.off[0], j + gf.off[1], k + gf.off[2]};
+    double v = 0.0;
+    for (int s3 = 0; s3 < 8; ++s3) {
+        int I[3];
+        double w = 1.0;
+        bool ok = true;
+        for (int d = 0; d < 3; ++d) {
+            const int bit = (s3 >> d) & 1;
+            if (F[d] & 1) {
+                I[d] = (F[d] - 1) / 2 + bit;
+                w *= 0.5;
+            } else {
+                I[d] = F[d] / 2;
+                ok = ok && bit == 0;
+            }
+        }
+        if (ok) v += w * eH[gc.idx(I[0], I[1], I[2])];
+    }
+    zf[e] += v;
+}
+
+// z += w D^-1 (r - q) at the unknowns; partial sums of r.z in part[0, nb)
+__global__ void __launch_bounds__(256) k_post(Split sp, double* zc, double* zf, const double* rc, const double* rf,
+                                              const double* qc, const double* qf, const double* dc, const double* df,
+                                              double* part, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const bool coarse = sp.coarse();
+    const uint8_t* role = sp.role();
+    double* z = coarse ? zc : zf;
+    const double* r = coarse ? rc : rf;
+    const double* q = coarse ? qc : qf;
+    const double* d = coarse ? dc : df;
+    double v[1] = {0.0};
+    for (int64_t e = sp.first(); e < sp.n(); e += sp.stride()) {
+        if (role[e] != 1) continue;
+        const double zv = z[e] + kOmega * d[e] * (r[e] - q[e]);
+        z[e] = zv;
+        v[0] += r[e] * zv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
 // ---- mixed precision: reliable updates ------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b)
@@ -968,9 +1099,43 @@ struct GridVecs {
 };
 
 // one composite CG iteration: q = P^T K P p, alpha, x and r, z = D^-1 r, beta, p
+// w = A v over both grids (v's derived fine values are filled in first)
+void launch_apply64(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, double* vc, double* vf,
+                    double* wc, double* wf, const CGState* st)
+{
+    if (R->ng) k_fill<double><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, vc, vf, st);
+    k_apply<double><<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, vc, wc, st);
+    k_apply<double><<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, vf, wf, st);
+    if (R->nr)
+        k_restrict<double><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, wf,
+                                                            wc, st);
+}
+
+// z = B r (FP64): on entry z = D^-1 r (from the update); the q vectors serve as scratch;
+// the r.z partial sums go to part[0, nb)
+void launch_two_level(hipStream_t s, pb_problem* pb, const Grid& gc, const Grid& gf, const Split& sp, CGState* st)
+{
+    RefineData* R = pb->ref;
+    pb_problem* fp = R->fine;
+    const int nb = R->nbc + R->nbf;
+    double* bH = pbi_mg_rhs0(pb);
+    double* eH = pbi_mg_sol0(pb);
+    k_zscale<<<nb, 256, 0, s>>>(sp, R->zc, R->zf, st);
+    launch_apply64(s, R, gc, gf, R->zc, R->zf, R->qc, R->qf, st);
+    k_rsub<<<nb, 256, 0, s>>>(sp, R->rc, R->rf, R->qc, R->qf, st);
+    k_rest_h<<<nblk(gc.N, 256), 256, 0, s>>>(gc, gf, R->rolec, R->rolef, R->qc, R->qf, bH, st);
+    pbi_mg_vcycle64(pb, s, st);
+    k_prol_c<<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, eH, R->zc, st);
+    k_prol_f<<<nblk(gf.N, 256), 256, 0, s>>>(gf, gc, R->rolef, eH, R->zf, st);
+    launch_apply64(s, R, gc, gf, R->zc, R->zf, R->qc, R->qf, st);
+    k_post<<<nb, 256, 0, s>>>(sp, R->zc, R->zf, R->rc, R->rf, R->qc, R->qf, R->dc, R->df, R->part, st);
+    (void)fp;
+}
+
 template <typename T>
+// (two_level: the problem whose two-level preconditioner replaces D^-1 r; FP64 only)
 void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, const Split& sp,
-                      const GridVecs<T>& c, const GridVecs<T>& f, CGState* st)
+                      const GridVecs<T>& c, const GridVecs<T>& f, CGState* st, pb_problem* two_level = nullptr)
 {
     const int nb = R->nbc + R->nbf;
     if (R->ng) k_fill<T><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, c.p, f.p, st);
@@ -982,6 +1147,9 @@ void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const 
     k_dot<T><<<nb, 256, 0, s>>>(sp, c.p, c.q, f.p, f.q, R->part, st);
     k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
     k_update<T><<<nb, 256, 0, s>>>(sp, c.x, c.r, c.z, c.p, c.q, c.d, f.x, f.r, f.z, f.p, f.q, f.d, R->part, nb, st);
+    if constexpr (sizeof(T) == 8) {
+        if (two_level) launch_two_level(s, two_level, gc, gf, sp, st);
+    }
     k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 0, 0.0);
     k_pupd<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, c.z, c.p, st);
     k_pupd<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->rolef, f.z, f.p, st);
@@ -1032,6 +1200,12 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
     const GridVecs<double> f64{fp->x, R->rf, R->zf, R->pf, R->qf, R->df, R->Kf};
     const GridVecs<float> c32{R->xc32, R->rc32, R->zc32, R->pc32, R->qc32, R->dc32, R->Kc32};
     const GridVecs<float> f32{R->xf32, R->rf32, R->zf32, R->pf32, R->qf32, R->df32, R->Kf32};
+    // the two-level preconditioner (FP64): the coarse grid's multigrid hierarchy, once
+    const bool two_level = P.precond == PB_PRECOND_MG;
+    if (two_level && !pb->mg) {
+        const int rc = pbi_mg_begin(pb, s);
+        if (rc) return rc;
+    }
     RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)gc.N));
     RCHK(launch_fill(s, fp->x, sizeof(double) * (size_t)gf.N));
     k_state_init<<<1, 1, 0, s>>>(st);
@@ -1053,6 +1227,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
         RCHK(launch_fill(s, R->qf, sizeof(double) * (size_t)gf.N));
         k_update<double><<<nb, 256, 0, s>>>(sp, c64.x, c64.r, c64.z, c64.p, c64.q, c64.d, f64.x, f64.r, f64.z, f64.p,
                                             f64.q, f64.d, R->part, nb, st);
+        if (two_level) launch_two_level(s, pb, gc, gf, sp, st);
         k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 1, P.rtol * P.rtol);
         k_pupd<double><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
         k_pupd<double><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
@@ -1070,7 +1245,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
             if (mixed)
                 launch_iteration<float>(s, R, gc, gf, sp, c32, f32, st);
             else
-                launch_iteration<double>(s, R, gc, gf, sp, c64, f64, st);
+                launch_iteration<double>(s, R, gc, gf, sp, c64, f64, st, two_level ? pb : nullptr);
         }
         RCHK(hipGetLastError());
         launched += n;
