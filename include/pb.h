@@ -130,8 +130,13 @@ typedef struct {
                                every axis (with one level the preconditioner is red-black
                                symmetric Gauss-Seidel itself); coarse edges combine the fine
                                ones in series along the edge and averaged across it; trilinear
-                               interpolation and its transpose.  Uniform grids only (PB_EINVAL
-                               with refine). */
+                               interpolation and its transpose.  With refine (FP64 only;
+                               PB_EINVAL in PB_MIXED): the symmetric two-level preconditioner
+                               of the composite system, z1 = w D^-1 r, z2 = z1 + I V(I^T (r -
+                               A z1)), z = z2 + w D^-1 (r - A z2), w = 0.8, V one V-cycle of
+                               the coarse grid's multigrid (from its own node-code map), I
+                               the trilinear interpolation of the coarse grid to the
+                               unknowns. */
     int32_t mg_smooth;      /* PB_PRECOND_MG: red-black sweeps before and after the coarse
                                correction on each level, 1..8 (0 = 1) */
     int32_t mg_coarse_sweeps; /* PB_PRECOND_MG: symmetric sweeps on the coarsest level,
@@ -166,7 +171,8 @@ typedef struct {
     double t_solve_s;       /* wall time of pb_solve */
 } pb_solve_stats;
 
-/* Solve A phi = b with Jacobi-preconditioned CG (the paper uses CG, Sect. 4), either in
+/* Solve A phi = b with preconditioned CG (the paper uses CG, Sect. 4; the preconditioner is
+ * pb_params.precond: Jacobi, or the multigrid / two-level preconditioner), either in
  * FP64 throughout or as FP32 CG with FP64 reliable updates: whenever the FP32 recursive
  * residual has dropped by inner_rtol, the FP32 correction is added to the FP64 solution and
  * the FP32 residual is replaced by the FP64 true residual b - A x (exact coefficients), with
