@@ -67,7 +67,7 @@ def counter_traffic(kernel, bytes_per_launch):
         return None
     return round(t["ratio"] * bytes_per_launch)
 DELTA = 1e-2
-DELTA_MG = 1e-3   # reliable-update factor of the multigrid-preconditioned mixed solve
+DELTA_MG = 1e-4   # reliable-update factor of the multigrid-preconditioned mixed solve
 MG_MIN_N = 129    # serving: grids from this many nodes per axis use the multigrid preconditioner
 BIND_COMPLEXES, BIND_DISP, BIND_H = 6, 30, 0.5   # binding workload: complexes, displacements, spacing
 N_REQ = 512
