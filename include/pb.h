@@ -130,8 +130,8 @@ typedef struct {
                                every axis (with one level the preconditioner is red-black
                                symmetric Gauss-Seidel itself); coarse edges combine the fine
                                ones in series along the edge and averaged across it; trilinear
-                               interpolation and its transpose.  With refine (FP64 only;
-                               PB_EINVAL in PB_MIXED): the symmetric two-level preconditioner
+                               interpolation and its transpose.  With refine: the symmetric
+                               two-level preconditioner
                                of the composite system, z1 = w D^-1 r, z2 = z1 + I V(I^T (r -
                                A z1)), z = z2 + w D^-1 (r - A z2), w = 0.8, V one V-cycle of
                                the coarse grid's multigrid (from its own node-code map), I

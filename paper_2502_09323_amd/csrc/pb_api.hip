@@ -105,8 +105,6 @@ int validate(const pb_params* p, int64_t na, const double* xyz, const double* ra
     if (p->precond != PB_PRECOND_JACOBI && p->precond != PB_PRECOND_MG)
         return fail(PB_EINVAL, "precond must be PB_PRECOND_JACOBI or PB_PRECOND_MG");
     if (p->precond == PB_PRECOND_MG) {
-        if (p->refine && p->precision != PB_FP64)
-            return fail(PB_EINVAL, "the two-level preconditioner of refined meshes is FP64 only");
         if (p->mg_smooth < 0 || p->mg_smooth > 8) return fail(PB_EINVAL, "mg_smooth must be in [0, 8]");
         if (p->mg_coarse_sweeps < 0 || p->mg_coarse_sweeps > 64)
             return fail(PB_EINVAL, "mg_coarse_sweeps must be in [0, 64]");

@@ -252,10 +252,11 @@ int pbi_mg_begin(pb_problem* pb, hipStream_t s);
 int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample);
 int pbi_mg_finish(pb_problem* pb, hipStream_t s);
 int pbi_mg_levels(const pb_problem* pb);
-// one FP64 V-cycle of pb's multigrid (set up by pbi_mg_begin) on level 0: right-hand side
-// pbi_mg_rhs0 (box nodes 0), correction in pbi_mg_sol0; gated on st running (status 0, ru 0)
-void pbi_mg_vcycle64(pb_problem* pb, hipStream_t s, const pbk::CGState* st);
-double* pbi_mg_rhs0(pb_problem* pb);
-double* pbi_mg_sol0(pb_problem* pb);
+// one V-cycle of pb's multigrid (set up by pbi_mg_begin, in pb's precision) on level 0:
+// right-hand side pbi_mg_rhs0 (box nodes 0), correction in pbi_mg_sol0 (element type of the
+// precision); gated on st running (status 0, ru 0) when st is given
+void pbi_mg_vcycle_on(pb_problem* pb, hipStream_t s, const pbk::CGState* st);
+void* pbi_mg_rhs0(pb_problem* pb);
+void* pbi_mg_sol0(pb_problem* pb);
 // one V-cycle on a vector over the padded level-0 layout (host arrays of g.N doubles)
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host);

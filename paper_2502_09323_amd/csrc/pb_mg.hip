@@ -1254,13 +1254,16 @@ int pbi_mg_finish(pb_problem* pb, hipStream_t s)
 
 int pbi_mg_levels(const pb_problem* pb) { return pb->mg ? pb->mg->nlev : 0; }
 
-void pbi_mg_vcycle64(pb_problem* pb, hipStream_t s, const CGState* st)
+void pbi_mg_vcycle_on(pb_problem* pb, hipStream_t s, const CGState* st)
 {
-    launch_vcycle<double>(s, pb, Gate{st, 0});
+    if (pb->prm.precision == PB_MIXED)
+        launch_vcycle<float>(s, pb, Gate{st, 0});
+    else
+        launch_vcycle<double>(s, pb, Gate{st, 0});
 }
 
-double* pbi_mg_rhs0(pb_problem* pb) { return pb->mg ? (double*)pb->mg->b[0] : nullptr; }
-double* pbi_mg_sol0(pb_problem* pb) { return pb->mg ? (double*)pb->mg->x[0] : nullptr; }
+void* pbi_mg_rhs0(pb_problem* pb) { return pb->mg ? pb->mg->b[0] : nullptr; }
+void* pbi_mg_sol0(pb_problem* pb) { return pb->mg ? pb->mg->x[0] : nullptr; }
 
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
 {

@@ -514,54 +514,58 @@ __global__ void __launch_bounds__(256) k_pupd(int64_t N, const uint8_t* role, co
     p[e] = role[e] == 1 ? z[e] + (T)st->beta * p[e] : (T)0;
 }
 
-// ---- two-level preconditioner (FP64) ------------------------------------------------------
+// ---- two-level preconditioner ----------------------------------------------------------------
 // z = B r with B the symmetric two-level preconditioner: z1 = w D^-1 r, then the coarse-grid
 // correction z2 = z1 + I_H V(I_H^T (r - A z1)) with V one V-cycle of the coarse grid's own
 // multigrid (its operator from the coarse node-code map), then z = z2 + w D^-1 (r - A z2).
 // I_H interpolates the coarse grid trilinearly to the unknowns: a coarse unknown takes its own
 // node; a fine unknown at fine-lattice coordinates F takes coarse node F/2 along an even axis
-// and the two nodes (F -+ 1)/2 with weight 1/2 along an odd one.
+// and the two nodes (F -+ 1)/2 with weight 1/2 along an odd one.  In the element type of the
+// CG (FP64, or FP32 in the mixed form, whose reliable updates apply it ungated: st = null).
 
 constexpr double kOmega = 0.8;   // smoother damping: w D^-1 A stays below 2 (SPD preconditioner)
 
+__device__ __forceinline__ bool stopped(const CGState* st) { return st && st->status != 0; }
+
 // z *= w at the unknowns
-__global__ void __launch_bounds__(256) k_zscale(Split sp, double* zc, double* zf, const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_zscale(Split sp, T* zc, T* zf, const CGState* st)
 {
-    if (st->status != 0) return;
+    if (stopped(st)) return;
     const uint8_t* role = sp.role();
-    double* z = sp.coarse() ? zc : zf;
+    T* z = sp.coarse() ? zc : zf;
     for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
-        if (role[e] == 1) z[e] *= kOmega;
+        if (role[e] == 1) z[e] *= (T)kOmega;
 }
 
 // q = r - q at the unknowns
-__global__ void __launch_bounds__(256) k_rsub(Split sp, const double* rc, const double* rf, double* qc, double* qf,
-                                              const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rsub(Split sp, const T* rc, const T* rf, T* qc, T* qf, const CGState* st)
 {
-    if (st->status != 0) return;
+    if (stopped(st)) return;
     const uint8_t* role = sp.role();
-    const double* r = sp.coarse() ? rc : rf;
-    double* q = sp.coarse() ? qc : qf;
+    const T* r = sp.coarse() ? rc : rf;
+    T* q = sp.coarse() ? qc : qf;
     for (int64_t e = sp.first(); e < sp.n(); e += sp.stride())
         if (role[e] == 1) q[e] = r[e] - q[e];
 }
 
 // bH = I_H^T w over the coarse grid (0 on the box and the pads): the node's own value where it
 // is a coarse unknown, plus the fine unknowns among the 27 fine nodes around it
+template <typename T>
 __global__ void __launch_bounds__(256) k_rest_h(Grid gc, Grid gf, const uint8_t* __restrict__ rolec,
-                                                const uint8_t* __restrict__ rolef, const double* __restrict__ wc,
-                                                const double* __restrict__ wf, double* __restrict__ bH,
-                                                const CGState* st)
+                                                const uint8_t* __restrict__ rolef, const T* __restrict__ wc,
+                                                const T* __restrict__ wf, T* __restrict__ bH, const CGState* st)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= gc.N || st->status != 0) return;
+    if (e >= gc.N || stopped(st)) return;
     int i, j, k;
     decode(gc, e, i, j, k);
     if (k < 1 || k > gc.nz - 2 || i < 1 || i > gc.nx - 2 || j < 1 || j > gc.ny - 2) {
-        bH[e] = 0.0;
+        bH[e] = (T)0;
         return;
     }
-    double v = rolec[e] == 1 ? wc[e] : 0.0;
+    T v = rolec[e] == 1 ? wc[e] : (T)0;
     const int F[3] = {2 * i - gf.off[0], 2 * j - gf.off[1], 2 * k - gf.off[2]};
     const int nf[3] = {gf.nx, gf.ny, gf.nz};
     bool near = true;
@@ -574,43 +578,43 @@ __global__ void __launch_bounds__(256) k_rest_h(Grid gc, Grid gf, const uint8_t*
                     if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= nf[0] || f1 >= nf[1] || f2 >= nf[2]) continue;
                     const int64_t ef = gf.idx(f0, f1, f2);
                     if (rolef[ef] != 1) continue;
-                    const double w = (a ? 0.5 : 1.0) * (b ? 0.5 : 1.0) * (c ? 0.5 : 1.0);
+                    const T w = (a ? (T)0.5 : (T)1) * (b ? (T)0.5 : (T)1) * (c ? (T)0.5 : (T)1);
                     v += w * wf[ef];
                 }
     bH[e] = v;
 }
 
 // z += I_H eH at the coarse unknowns
-__global__ void __launch_bounds__(256) k_prol_c(int64_t N, const uint8_t* __restrict__ rolec,
-                                                const double* __restrict__ eH, double* __restrict__ zc,
-                                                const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_prol_c(int64_t N, const uint8_t* __restrict__ rolec, const T* __restrict__ eH,
+                                                T* __restrict__ zc, const CGState* st)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= N || st->status != 0) return;
+    if (e >= N || stopped(st)) return;
     if (rolec[e] == 1) zc[e] += eH[e];
 }
 
 // z += I_H eH at the fine unknowns
+template <typename T>
 __global__ void __launch_bounds__(256) k_prol_f(Grid gf, Grid gc, const uint8_t* __restrict__ rolef,
-                                                const double* __restrict__ eH, double* __restrict__ zf,
-                                                const CGState* st)
+                                                const T* __restrict__ eH, T* __restrict__ zf, const CGState* st)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= gf.N || st->status != 0) return;
+    if (e >= gf.N || stopped(st)) return;
     if (rolef[e] != 1) return;
     int i, j, k;
     decode(gf, e, i, j, k);
     const int F[3] = {i + gf.off[0], j + gf.off[1], k + gf.off[2]};
-    double v = 0.0;
+    T v = (T)0;
     for (int s3 = 0; s3 < 8; ++s3) {
         int I[3];
-        double w = 1.0;
+        T w = (T)1;
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
             const int bit = (s3 >> d) & 1;
             if (F[d] & 1) {
                 I[d] = (F[d] - 1) / 2 + bit;
-                w *= 0.5;
+                w *= (T)0.5;
             } else {
                 I[d] = F[d] / 2;
                 ok = ok && bit == 0;
@@ -622,24 +626,24 @@ __global__ void __launch_bounds__(256) k_prol_f(Grid gf, Grid gc, const uint8_t*
 }
 
 // z += w D^-1 (r - q) at the unknowns; partial sums of r.z in part[0, nb)
-__global__ void __launch_bounds__(256) k_post(Split sp, double* zc, double* zf, const double* rc, const double* rf,
-                                              const double* qc, const double* qf, const double* dc, const double* df,
-                                              double* part, const CGState* st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_post(Split sp, T* zc, T* zf, const T* rc, const T* rf, const T* qc,
+                                              const T* qf, const T* dc, const T* df, double* part, const CGState* st)
 {
     __shared__ double sh[8];
-    if (st->status != 0) return;
+    if (stopped(st)) return;
     const bool coarse = sp.coarse();
     const uint8_t* role = sp.role();
-    double* z = coarse ? zc : zf;
-    const double* r = coarse ? rc : rf;
-    const double* q = coarse ? qc : qf;
-    const double* d = coarse ? dc : df;
+    T* z = coarse ? zc : zf;
+    const T* r = coarse ? rc : rf;
+    const T* q = coarse ? qc : qf;
+    const T* d = coarse ? dc : df;
     double v[1] = {0.0};
     for (int64_t e = sp.first(); e < sp.n(); e += sp.stride()) {
         if (role[e] != 1) continue;
-        const double zv = z[e] + kOmega * d[e] * (r[e] - q[e]);
+        const T zv = z[e] + (T)kOmega * d[e] * (r[e] - q[e]);
         z[e] = zv;
-        v[0] += r[e] * zv;
+        v[0] += (double)r[e] * (double)zv;
     }
     bsum(v, 1, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -1098,42 +1102,44 @@ struct GridVecs {
     const T *d, *K;
 };
 
-// one composite CG iteration: q = P^T K P p, alpha, x and r, z = D^-1 r, beta, p
-// w = A v over both grids (v's derived fine values are filled in first)
-void launch_apply64(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, double* vc, double* vf,
-                    double* wc, double* wf, const CGState* st)
+// w = A v over both grids with the operator of K arrays Kc, Kf (v's derived fine values are
+// filled in first)
+template <typename T>
+void launch_apply_comp(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, const T* Kc, const T* Kf,
+                       T* vc, T* vf, T* wc, T* wf, const CGState* st)
 {
-    if (R->ng) k_fill<double><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, vc, vf, st);
-    k_apply<double><<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, vc, wc, st);
-    k_apply<double><<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, vf, wf, st);
+    if (R->ng) k_fill<T><<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->gpar, R->gnp, vc, vf, st);
+    k_apply<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc, Kc, R->rolec, vc, wc, st);
+    k_apply<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf, Kf, R->rolef, vf, wf, st);
     if (R->nr)
-        k_restrict<double><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, wf,
-                                                            wc, st);
+        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, wf, wc,
+                                                       st);
 }
 
-// z = B r (FP64): on entry z = D^-1 r (from the update); the q vectors serve as scratch;
-// the r.z partial sums go to part[0, nb)
-void launch_two_level(hipStream_t s, pb_problem* pb, const Grid& gc, const Grid& gf, const Split& sp, CGState* st)
+// z = B r in the element type T: on entry z = D^-1 r; the q vectors serve as scratch; the r.z
+// partial sums go to part[0, nb).  st = null: ungated (inside a reliable update)
+template <typename T>
+void launch_two_level(hipStream_t s, pb_problem* pb, const Grid& gc, const Grid& gf, const Split& sp,
+                      const GridVecs<T>& c, const GridVecs<T>& f, const CGState* st)
 {
     RefineData* R = pb->ref;
-    pb_problem* fp = R->fine;
     const int nb = R->nbc + R->nbf;
-    double* bH = pbi_mg_rhs0(pb);
-    double* eH = pbi_mg_sol0(pb);
-    k_zscale<<<nb, 256, 0, s>>>(sp, R->zc, R->zf, st);
-    launch_apply64(s, R, gc, gf, R->zc, R->zf, R->qc, R->qf, st);
-    k_rsub<<<nb, 256, 0, s>>>(sp, R->rc, R->rf, R->qc, R->qf, st);
-    k_rest_h<<<nblk(gc.N, 256), 256, 0, s>>>(gc, gf, R->rolec, R->rolef, R->qc, R->qf, bH, st);
-    pbi_mg_vcycle64(pb, s, st);
-    k_prol_c<<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, eH, R->zc, st);
-    k_prol_f<<<nblk(gf.N, 256), 256, 0, s>>>(gf, gc, R->rolef, eH, R->zf, st);
-    launch_apply64(s, R, gc, gf, R->zc, R->zf, R->qc, R->qf, st);
-    k_post<<<nb, 256, 0, s>>>(sp, R->zc, R->zf, R->rc, R->rf, R->qc, R->qf, R->dc, R->df, R->part, st);
-    (void)fp;
+    T* bH = (T*)pbi_mg_rhs0(pb);
+    T* eH = (T*)pbi_mg_sol0(pb);
+    k_zscale<T><<<nb, 256, 0, s>>>(sp, c.z, f.z, st);
+    launch_apply_comp<T>(s, R, gc, gf, c.K, f.K, c.z, f.z, c.q, f.q, st);
+    k_rsub<T><<<nb, 256, 0, s>>>(sp, c.r, f.r, c.q, f.q, st);
+    k_rest_h<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc, gf, R->rolec, R->rolef, c.q, f.q, bH, st);
+    pbi_mg_vcycle_on(pb, s, st);
+    k_prol_c<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, eH, c.z, st);
+    k_prol_f<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf, gc, R->rolef, eH, f.z, st);
+    launch_apply_comp<T>(s, R, gc, gf, c.K, f.K, c.z, f.z, c.q, f.q, st);
+    k_post<T><<<nb, 256, 0, s>>>(sp, c.z, f.z, c.r, f.r, c.q, f.q, c.d, f.d, R->part, st);
 }
 
+// one composite CG iteration: q = P^T K P p, alpha, x and r, z = D^-1 r (or z = B r with
+// two_level, the problem whose two-level preconditioner is used), beta, p
 template <typename T>
-// (two_level: the problem whose two-level preconditioner replaces D^-1 r; FP64 only)
 void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const Grid& gf, const Split& sp,
                       const GridVecs<T>& c, const GridVecs<T>& f, CGState* st, pb_problem* two_level = nullptr)
 {
@@ -1147,9 +1153,7 @@ void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const 
     k_dot<T><<<nb, 256, 0, s>>>(sp, c.p, c.q, f.p, f.q, R->part, st);
     k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
     k_update<T><<<nb, 256, 0, s>>>(sp, c.x, c.r, c.z, c.p, c.q, c.d, f.x, f.r, f.z, f.p, f.q, f.d, R->part, nb, st);
-    if constexpr (sizeof(T) == 8) {
-        if (two_level) launch_two_level(s, two_level, gc, gf, sp, st);
-    }
+    if (two_level) launch_two_level<T>(s, two_level, gc, gf, sp, c, f, st);
     k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 0, 0.0);
     k_pupd<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc.N, R->rolec, c.z, c.p, st);
     k_pupd<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->rolef, f.z, f.p, st);
@@ -1157,7 +1161,9 @@ void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const 
 
 // mixed precision: fold the FP32 correction into x, r = b - A x with the FP64 operator, and
 // restart the FP32 recurrence from it (the direction p is kept)
-void launch_reliable_update(hipStream_t s, pb_problem* pb, const Split& sp, int init, double rtol2, double delta2)
+// (two_level: z = B r in place of D^-1 r after the replacement)
+void launch_reliable_update(hipStream_t s, pb_problem* pb, const Split& sp, int init, double rtol2, double delta2,
+                            bool two_level)
 {
     RefineData* R = pb->ref;
     pb_problem* fp = R->fine;
@@ -1174,6 +1180,11 @@ void launch_reliable_update(hipStream_t s, pb_problem* pb, const Split& sp, int 
                                                             R->qc, nullptr);
     k_true_res<<<nb, 256, 0, s>>>(sp, R->bc, R->qc, R->rc, R->bf, R->qf, R->rf, R->part + 2 * nb);
     k_replace<<<nb, 256, 0, s>>>(sp, R->rc, R->rc32, R->zc32, R->dc32, R->rf, R->rf32, R->zf32, R->df32, R->part, nb);
+    if (two_level) {
+        const GridVecs<float> c32{R->xc32, R->rc32, R->zc32, R->pc32, R->qc32, R->dc32, R->Kc32};
+        const GridVecs<float> f32{R->xf32, R->rf32, R->zf32, R->pf32, R->qf32, R->df32, R->Kf32};
+        launch_two_level<float>(s, pb, gc, gf, sp, c32, f32, nullptr);
+    }
     k_ru_fin<<<1, 256, 0, s>>>(R->part, nb, pb->st, init, rtol2, delta2);
 }
 
@@ -1213,7 +1224,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
         // x32 = 0; r = b, z = D^-1 r from the first reliable update; p = z
         RCHK(launch_fill(s, R->xc32, sizeof(float) * (size_t)gc.N));
         RCHK(launch_fill(s, R->xf32, sizeof(float) * (size_t)gf.N));
-        launch_reliable_update(s, pb, sp, 1, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol);
+        launch_reliable_update(s, pb, sp, 1, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol, two_level);
         k_pupd<float><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc32, R->pc32, st);
         k_pupd<float><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf32, R->pf32, st);
     } else {
@@ -1227,7 +1238,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
         RCHK(launch_fill(s, R->qf, sizeof(double) * (size_t)gf.N));
         k_update<double><<<nb, 256, 0, s>>>(sp, c64.x, c64.r, c64.z, c64.p, c64.q, c64.d, f64.x, f64.r, f64.z, f64.p,
                                             f64.q, f64.d, R->part, nb, st);
-        if (two_level) launch_two_level(s, pb, gc, gf, sp, st);
+        if (two_level) launch_two_level<double>(s, pb, gc, gf, sp, c64, f64, st);
         k_beta<<<1, 256, 0, s>>>(R->part, nb, st, 1, P.rtol * P.rtol);
         k_pupd<double><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc, R->pc, st);
         k_pupd<double><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf, R->pf, st);
@@ -1243,7 +1254,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
         const int n = std::min(M, P.max_iter - launched);
         for (int it = 0; it < n; ++it) {
             if (mixed)
-                launch_iteration<float>(s, R, gc, gf, sp, c32, f32, st);
+                launch_iteration<float>(s, R, gc, gf, sp, c32, f32, st, two_level ? pb : nullptr);
             else
                 launch_iteration<double>(s, R, gc, gf, sp, c64, f64, st, two_level ? pb : nullptr);
         }
@@ -1254,7 +1265,7 @@ int pbi_refine_solve(pb_problem* pb, CGState* out)
         if (mixed && (h.status != 0 || launched >= P.max_iter)) {
             // status 3: the FP32 residual reached its goal or fell by inner_rtol
             breakdown = h.status == 2;
-            launch_reliable_update(s, pb, sp, 0, 0.0, 0.0);
+            launch_reliable_update(s, pb, sp, 0, 0.0, 0.0, two_level);
             if (!breakdown && launched < P.max_iter) {
                 k_pupd<float><<<bc, 256, 0, s>>>(gc.N, R->rolec, R->zc32, R->pc32, st);
                 k_pupd<float><<<bfn, 256, 0, s>>>(gf.N, R->rolef, R->zf32, R->pf32, st);

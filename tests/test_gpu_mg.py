@@ -137,7 +137,7 @@ def test_mg_full_size_161(ctx):
 
 def test_mg_invalid(ctx):
     mol = I.random_molecule(10, 2.0, 1)
-    for g in (I.cubic_grid(33, 0.5, precond=2), I.cubic_grid(33, 0.5, precond=I.MG, refine=1, precision=I.MIXED),
+    for g in (I.cubic_grid(33, 0.5, precond=2),
               I.cubic_grid(33, 0.5, precond=I.MG, mg_smooth=9), I.cubic_grid(33, 0.5, precond=I.MG, mg_levels=13)):
         with pytest.raises(B.PbError) as e:
             B.Problem(ctx, mol, g)

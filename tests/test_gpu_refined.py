@@ -123,6 +123,33 @@ def test_refined_two_level_parity(ctx, name, mol, grid):
         jac.close()
 
 
+@pytest.mark.parametrize("name,mol,grid", _cases()[1:], ids=[c[0] for c in _cases()[1:]])
+def test_refined_two_level_mixed(ctx, name, mol, grid):
+    """The two-level preconditioner in the mixed form (FP32 CG and preconditioner, FP64
+    reliable updates): the FP64 true residual reaches the goal and the energies and potentials
+    agree with the FP64 oracle to 1e-6, in about the FP64 two-level iteration count."""
+    g64 = replace(grid, precond=I.MG, rtol=1e-10)
+    ref = R.refined_run(mol, g64, delta=grid.refine_shell, brick=grid.refine_brick, rtol=1e-12, mode=_mode(grid),
+                        solver="mg")
+    pb = B.Problem(ctx, mol, replace(g64, precision=I.MIXED, inner_rtol=1e-3))
+    p64 = B.Problem(ctx, mol, g64)
+    try:
+        st, s64 = pb.solve(), p64.solve()
+        assert st["status"] == 0 and st["relres"] <= 1e-10 and st["outer_iters"] >= 1
+        assert st["iters"] <= s64["iters"] + 5, (st["iters"], s64["iters"])
+        en = pb.energy()
+        for k in ("e_pol", "e_ion", "q_pol_total"):
+            assert abs(en[k] - ref.energy[k]) <= 1e-6 * abs(ref.energy[k]), (k, en[k], ref.energy[k])
+        info = pb.refine_info()
+        o, n = info["fine_offset"], info["fine_n"]
+        want = ref.lB * ref.phi[o[0]:o[0] + n[0], o[1]:o[1] + n[1], o[2]:o[2] + n[2]]
+        m = fine_cell_vertices(ref.refined)[o[0]:o[0] + n[0], o[1]:o[1] + n[1], o[2]:o[2] + n[2]]
+        assert np.abs(pb.fine_potential()[m] - want[m]).max() <= 1e-6 * np.abs(want[m]).max()
+    finally:
+        pb.close()
+        p64.close()
+
+
 def test_refined_patch_test_on_gpu(ctx):
     """One permittivity, no ions, no charge, linear box values: the solution is that linear
     function at every vertex, hanging nodes included."""
