@@ -218,6 +218,15 @@ def bench_serving(args, B, torch):
     close(srv)
     lat_open = [res_open[i]["latency_s"] for i in range(N_REQ)]
     log(f"open loop at {rate:.2f}/s done")
+    # the same at half and at the full closed-loop rate
+    sweep = {}
+    for load in (0.5, 1.0):
+        r_s, w_s, srv = serve(B, main, side, reqs, unit_arr / (load * value), max_resident=args.max_resident)
+        close(srv)
+        l_s = [r_s[i]["latency_s"] for i in range(N_REQ)]
+        sweep[f"{load:.1f}x"] = {"arrival_rate_hz": round(load * value, 3), "solves_per_s": round(N_REQ / w_s, 3),
+                                 "p50_ms": round(1e3 * pct(l_s, 50), 1), "p99_ms": round(1e3 * pct(l_s, 99), 1)}
+    log("open-loop sweep done")
 
     # baseline: one at a time, plain FP64, same tolerance (same energy error)
     svc, e64 = [], []
@@ -315,6 +324,11 @@ def bench_serving(args, B, torch):
                                "p99_s": round(pct(lat_closed, 99), 3), "codes": codes},
         "served_open_loop": {"arrival_rate_hz": round(rate, 3), "solves_per_s": round(N_REQ / wall_open, 3),
                              "p50_ms": round(1e3 * pct(lat_open, 50), 1), "p99_ms": round(1e3 * pct(lat_open, 99), 1)},
+        "served_open_loop_sweep": {"0.5x": sweep["0.5x"], "0.8x": {"arrival_rate_hz": round(rate, 3),
+                                                                  "solves_per_s": round(N_REQ / wall_open, 3),
+                                                                  "p50_ms": round(1e3 * pct(lat_open, 50), 1),
+                                                                  "p99_ms": round(1e3 * pct(lat_open, 99), 1)},
+                                   "1.0x": sweep["1.0x"]},
         "fp64_one_at_a_time": {"solves_per_s": round(N_REQ / t_fp64, 3), "mean_service_ms": round(1e3 * float(np.mean(svc)), 2),
                                "p50_ms_same_arrivals": round(1e3 * pct(lat64, 50), 1),
                                "p99_ms_same_arrivals": round(1e3 * pct(lat64, 99), 1)},
@@ -333,8 +347,52 @@ def bench_serving(args, B, torch):
     return out
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def oracle_single_thread(mol, g, timeout_s=90.0):
+    """Seconds the oracle takes for one request in a child process with one OpenMP thread."""
+    import subprocess
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "req.npz")
+        np.savez(path, xyz=mol.xyz, radius=mol.radius, charge=mol.charge, n=np.array(g.n), h=g.h,
+                 origin=np.array(g.origin), temp=g.temp_K, ionic=g.ionic_M, eps_in=g.eps_in, eps_out=g.eps_out,
+                 bc=g.bc)
+        code = (
+            "import sys, time, numpy as np\n"
+            f"sys.path.insert(0, {ROOT!r})\n"
+            "from paper_2502_09323_amd import inputs as I\n"
+            "from oracle import oracle as O\n"
+            f"z = np.load({path!r})\n"
+            "m = I.Molecule(z['xyz'], z['radius'], z['charge'])\n"
+            "g = I.GridSpec(n=tuple(int(v) for v in z['n']), h=float(z['h']), origin=tuple(float(v) for v in z['origin']),"
+            " eps_in=float(z['eps_in']), eps_out=float(z['eps_out']), ionic_M=float(z['ionic']),"
+            " temp_K=float(z['temp']), bc=int(z['bc']))\n"
+            "t = time.perf_counter()\n"
+            f"O.run(m, g, rtol={RTOL})\n"
+            "print(time.perf_counter() - t, O.num_threads())\n")
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=timeout_s)
+        dt, nt = out.stdout.split()[-2:]
+        return float(dt), int(nt)
+
+
 def cpu_baseline_stream(reqs, budget_s=15.0):
-    """The oracle (FP64, all host threads) on the first requests of the same stream."""
+    """The oracle (FP64, all host threads) on the first requests of the same stream, and on the
+    smallest of them with one thread."""
     from oracle import oracle as O
 
     t0 = time.perf_counter()
@@ -345,9 +403,17 @@ def cpu_baseline_stream(reqs, budget_s=15.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": round(n / dt, 4), "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"the first {n} requests of the same stream solved by the FP64 CPU oracle at rtol {RTOL} "
-                      f"({dt:.1f} s)"}
+    out = {"value": round(n / dt, 4), "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+           "sample": f"the first {n} requests of the same stream solved by the FP64 CPU oracle at rtol {RTOL} "
+                     f"({dt:.1f} s)", "host": host_cpu()}
+    k = min(range(n), key=lambda i: reqs[i][1].unknowns)
+    try:
+        t1, nt = oracle_single_thread(reqs[k][0], reqs[k][1])
+        out["single_thread"] = {"seconds": round(t1, 2), "threads": nt,
+                                "sample": f"request {k} of the stream ({reqs[k][1].n[0]}^3 nodes, {reqs[k][0].n} atoms)"}
+    except Exception as e:   # the single-thread figure is context only
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 # ---- single solves (c1, c2, c4) ---------------------------------------------------------------
