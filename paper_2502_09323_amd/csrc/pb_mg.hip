@@ -1131,10 +1131,15 @@ int start_t(pb_problem* pb, hipStream_t s)
 
 // n iterations and the restart that follows them where one is due, enqueued on s; ev[it],
 // where given, receives the four timing events of iteration it's V-cycle
+// (ran[it], where given: receives the state's status as iteration it starts; 0 means the
+// iteration runs, short of a breakdown in its alpha step: only its scalar steps change it)
 template <typename T>
-int chunk_t(pb_problem* pb, hipStream_t s, int n, hipEvent_t* const* ev)
+int chunk_t(pb_problem* pb, hipStream_t s, int n, hipEvent_t* const* ev, int* const* ran = nullptr)
 {
-    for (int it = 0; it < n; ++it) launch_iteration<T>(s, pb, pb->st, ev ? ev[it] : nullptr);
+    for (int it = 0; it < n; ++it) {
+        if (ran && ran[it]) RCHK(hipMemcpyAsync(ran[it], &pb->st->status, sizeof(int), hipMemcpyDeviceToDevice, s));
+        launch_iteration<T>(s, pb, pb->st, ev ? ev[it] : nullptr);
+    }
     if (sizeof(T) == 4) launch_restart<T>(s, pb, pb->st, 0, 0);
     RCHK(hipGetLastError());
     return PB_OK;
@@ -1158,11 +1163,18 @@ int solve_t(pb_problem* pb, CGState* out)
     const bool prof = ctx->profile != 0 && pb->mg->nlev > 1;
     std::vector<hipEvent_t> evs;
     std::vector<int> ev_it;
+    // per sample, the status as its iteration starts (a launch after a stop returns at once)
+    constexpr int kMaxSamples = 128;
+    int* ran_dev = nullptr;
+    if (prof) {
+        ran_dev = (int*)pb->mem.get(sizeof(int) * kMaxSamples);
+        if (!ran_dev) return pbi_fail(PB_ENOMEM, "profiling flags");
+    }
     auto enqueue = [&](int slot) -> int {
         const int n = std::min(M, P.max_iter - launched);
         hipEvent_t* ev[M] = {};
         for (int it = 0; prof && it < n; ++it) {
-            if ((launched + it) % 4 != 0 || evs.size() >= 4 * 128) continue;
+            if ((launched + it) % 4 != 0 || evs.size() >= 4 * kMaxSamples) continue;
             for (int e = 0; e < 4; ++e) {
                 // timing only: no system-scope fence, whose cache writeback of the data the
                 // sampled kernels wrote would otherwise be counted in their time
@@ -1173,12 +1185,14 @@ int solve_t(pb_problem* pb, CGState* out)
             ev_it.push_back(launched + it);
         }
         // pointers into evs only once it has stopped growing for this chunk
+        int* ran[M] = {};
         for (size_t k = 0, it = 0; k < ev_it.size(); ++k)
             if (ev_it[k] >= launched && ev_it[k] < launched + n) {
                 it = (size_t)(ev_it[k] - launched);
                 ev[it] = &evs[4 * k];
+                ran[it] = ran_dev + k;
             }
-        const int r = chunk_t<T>(pb, s, n, prof ? ev : nullptr);
+        const int r = chunk_t<T>(pb, s, n, prof ? ev : nullptr, prof ? ran : nullptr);
         if (r) return r;
         launched += n;
         RCHK(hipMemcpyAsync(&ctx->host_state[slot], pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -1199,10 +1213,13 @@ int solve_t(pb_problem* pb, CGState* out)
     RCHK(hipMemcpyAsync(out, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
     if (prof) {
-        // only iterations that ran: the sampled iteration index is below the final count
-        const int done = out->iter_count;
+        // only iterations that ran: the state was running as the sampled iteration started
+        std::vector<int> ran_h(ev_it.size(), 1);
+        if (!ev_it.empty())
+            RCHK(hipMemcpy(ran_h.data(), ran_dev, sizeof(int) * ev_it.size(), hipMemcpyDeviceToHost));
+        pb->mem.put(ran_dev);
         for (size_t k = 0; k < ev_it.size(); ++k) {
-            if (ev_it[k] >= done) continue;
+            if (ran_h[k] != 0) continue;
             float a = 0, b = 0;
             RCHK(hipEventElapsedTime(&a, evs[4 * k + 1], evs[4 * k + 2]));
             RCHK(hipEventElapsedTime(&b, evs[4 * k], evs[4 * k + 3]));
