@@ -262,12 +262,15 @@ int pb_copy_fine_potential(const pb_problem* pb, double* host_phi);
 int pb_copy_coeffs(const pb_problem* pb, uint8_t* solute, double* kx, double* ky, double* kz,
                    double* diag, double* rhs);
 
-/* Number of cut edges of a built problem (or a negative error code). */
+/* Number of cut edges of a built problem (or a negative error code).  For a refined problem:
+ * those of its fine sub-lattice, where the surface and the energy read-back are. */
 int64_t pb_num_cut(const pb_problem* pb);
 
 /* Cut-edge list in ascending key order, key = 3*((i*n1 + j)*n2 + k) + axis of the edge's
  * low end (i,j,k).  Host arrays of m = pb_num_cut entries (rp, np: 3*m), any may be NULL.
- * F (flux K_e (phi_s - phi_w)) and phip (eq. phi0) are valid after pb_energy. */
+ * F (flux K_e (phi_s - phi_w)) and phip (eq. phi0) are valid after pb_energy.  For a refined
+ * problem the list of the fine sub-lattice (i, j, k and n on the sub-lattice, whose node 0
+ * is fine-lattice node fine_offset of pb_refine_info). */
 int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, double* np,
                 int64_t* owner, double* wp, double* F, double* phip);
 

@@ -967,13 +967,15 @@ int pb_copy_coeffs(const pb_problem* pb, uint8_t* sol, double* kx, double* ky, d
 int64_t pb_num_cut(const pb_problem* pb)
 {
     if (!pb) return fail(PB_EINVAL, "NULL problem");
-    return pb->ncut;
+    return pb->ref ? pb->ref->fine->ncut : pb->ncut;
 }
 
 int pb_copy_cut(const pb_problem* pb, int64_t* key, double* alpha, double* rp, double* np, int64_t* owner,
                 double* wp, double* F, double* phip)
 {
     if (!pb) return fail(PB_EINVAL, "NULL problem");
+    // a refined problem's surface lies on its fine sub-lattice (the energy read-back's list)
+    if (pb->ref) return pb_copy_cut(pb->ref->fine, key, alpha, rp, np, owner, wp, F, phip);
     HIPCHK(hipSetDevice(pb->ctx->device));
     hipStream_t s = pb->ctx->stream;
     const size_t m = (size_t)pb->ncut;

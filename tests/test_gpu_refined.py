@@ -89,6 +89,15 @@ def test_refined_parity(ctx, name, mol, grid):
         phi_c = pb.potential()
         want_c = ref.lB * ref.phi[::2, ::2, ::2]
         assert np.abs(phi_c - want_c).max() <= 1e-9 * np.abs(want_c).max()
+        # the cut list of the fine sub-lattice: the oracle's fine-lattice crossings, bit for bit
+        cut = pb.cut(fields=True)
+        sub, ax = cut["key"] // 3, cut["key"] % 3
+        ijk = np.stack([sub // (n[1] * n[2]), (sub // n[2]) % n[1], sub % n[2]], axis=1) + np.asarray(o)
+        nfl = ref.fgrid.n
+        key = 3 * ((ijk[:, 0] * nfl[1] + ijk[:, 1]) * nfl[2] + ijk[:, 2]) + ax
+        np.testing.assert_array_equal(key, ref.cut.key)
+        assert np.abs(cut["wp"] - ref.energy["wp"]).max() <= 1e-12 * ref.energy["wp"].max()
+        assert np.abs(cut["F"] - ref.energy["F"]).max() <= 1e-9 * np.abs(ref.energy["F"]).max()
     finally:
         pb.close()
 

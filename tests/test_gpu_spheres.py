@@ -80,3 +80,38 @@ def test_thirty_spheres_against_the_analytic_solution(ctx, cluster, prec):
     assert e5["e_ion"] < 0.08 and e25["e_ion"] < 0.01 and e25["e_ion"] < 0.25 * e5["e_ion"]
     assert e5["surf50"] < 0.01 and e5["surf95"] < 0.05
     assert e25["surf50"] < 0.5 * e5["surf50"] and e25["surf95"] < 0.5 * e5["surf95"]
+
+
+def test_thirty_spheres_derefined_null_box(ctx, cluster):
+    """The paper's own box treatment on the same cluster: null Dirichlet values on a box five
+    times the cluster's extent (a 20 % fill), reached by one de-refinement level (0.5 A cells
+    within 2 A of the spheres, 1 A cells beyond), solved with the two-level preconditioner.
+    The errors against the analytic solution match those of the uniform 0.5 A grid with
+    Debye-Hueckel box values."""
+    m, gold, sol = cluster
+    lo, hi = (m.xyz - m.radius[:, None]).min(0), (m.xyz + m.radius[:, None]).max(0)
+    g = I.cubic_grid(181, 1.0, center=tuple(0.5 * (lo + hi)), temp_K=298.15, bc=I.BC_ZERO, refine=2,
+                     refine_shell=2.0, refine_brick=4, precond=I.MG, precision=I.MIXED, rtol=1e-10,
+                     inner_rtol=1e-4)
+    pb = B.Problem(ctx, m, g)
+    try:
+        st = pb.solve()
+        assert st["status"] == 0
+        en = pb.energy(per_atom=True)
+        c = pb.cut(fields=True)
+        info = pb.refine_info()
+    finally:
+        pb.close()
+    assert info["refined_cells"] > 0
+    ana = np.zeros(len(c["phip"]))
+    for i in range(len(m.radius)):
+        sel = c["owner"] == i
+        ana[sel] = S.interior_potential(sol, i, c["rp"][sel])
+    surf = np.abs(c["phip"] - ana) / np.abs(ana).max()
+    pr = np.array([gold[f"phi_reac_{i}"] for i in range(len(m.radius))])
+    err = {k: abs(en[k] / gold[k] - 1.0) for k in ("e_pol", "e_ion", "e_total")}
+    err["phi_reac"] = np.abs(en["phi_reac"] - pr).max() / np.abs(pr).max()
+    err["surf50"], err["surf95"] = float(np.median(surf)), float(np.percentile(surf, 95))
+    print("derefined null box", err, info, flush=True)
+    assert err["e_pol"] < 5e-4 and err["e_total"] < 5e-4 and err["phi_reac"] < 1e-3
+    assert err["e_ion"] < 0.08 and err["surf50"] < 0.01 and err["surf95"] < 0.05
