@@ -214,6 +214,17 @@ int pb_binding_ddg(const pb_energy_out* complex_e, const pb_energy_out* part1, c
  * solved), PB_EDEVICE. */
 int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac_per_atom);
 
+/* Grid energy after pb_solve (Sect. 3.3, electrostatic energy), in kT: half the sum over
+ * the interior grid nodes of the charge deposited there (trilinear weights of each atom's
+ * cell, the right-hand side's charge term) times the potential there; charge that the
+ * deposition would put on box nodes is left out, as in the right-hand side.  It includes the
+ * grid's self-energy, which cancels in the difference of two solves of the same geometry and
+ * grid: at the actual ionic strength and at zero ionic strength the difference estimates the
+ * ionic energy without a volume integral.  *e_grid is a host double.  Uniform grids only.
+ * Errors: PB_EINVAL (NULL argument, not solved, a locally refined problem), PB_ENOMEM,
+ * PB_EDEVICE. */
+int pb_grid_energy(pb_problem* pb, double* e_grid);
+
 /* Copy the potential on the full grid (kT/e, box nodes hold the boundary values) into a
  * host array of n[0]*n[1]*n[2] doubles. */
 int pb_copy_potential(const pb_problem* pb, double* host_phi);

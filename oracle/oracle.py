@@ -288,6 +288,16 @@ def energies(grid, mol, solute, cut: CutEdges, phi_full, lB: float, sel=None):
     return out
 
 
+def grid_energy(grid, mol, phi_full, lB: float) -> float:
+    """Grid energy in kT (Sect. 3.3, electrostatic energy): one half of the sum over the grid
+    nodes of the fixed charge mapped onto each node times the potential there.  The node
+    charges are the right-hand side's deposition divided by 4 pi, on the interior nodes only
+    (the right-hand side holds no charge on box nodes).  The difference of two solves of one
+    geometry, at the actual ionic strength and at zero, estimates the ionic energy."""
+    Q = interior(deposit(grid, mol)) / (4.0 * math.pi)
+    return 0.5 * lB * float(np.dot(Q, interior(phi_full)))
+
+
 # --- the whole pipeline -------------------------------------------------------------
 
 @dataclass

@@ -26,6 +26,7 @@ EXPORTED = [
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
     "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg", "pb_get_energy_profile", "pb_server_profile_energy",
+    "pb_grid_energy",
 ]
 
 
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.pb_solve.argtypes = [P, C.POINTER(PbSolveStats)]
     L.pb_energy.argtypes = [P, C.POINTER(PbEnergyOut), P]
     L.pb_copy_potential.argtypes = [P, P]
+    L.pb_grid_energy.argtypes = [P, C.POINTER(C.c_double)]
     L.pb_problem_free.argtypes = [P]
     L.pb_problem_free.restype = None
     L.pb_copy_coeffs.argtypes = [P, P, P, P, P, P, P]
@@ -277,6 +279,15 @@ class Problem:
         if per_atom:
             d["phi_reac"] = pa[: self.n_atoms]
         return d
+
+    def grid_energy(self) -> float:
+        """Half the sum of the deposited node charges times the potential (kT); the
+        difference of two solves of one geometry at two ionic strengths estimates E_ion."""
+        e = C.c_double(0.0)
+        rc = _lib.pb_grid_energy(self.h, C.byref(e))
+        if rc != PB_OK:
+            raise _err(rc)
+        return e.value
 
     def potential(self) -> np.ndarray:
         phi = np.zeros(self.shape)

@@ -915,6 +915,28 @@ int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac)
     return rc;
 }
 
+int pb_grid_energy(pb_problem* pb, double* e_grid)
+{
+    if (!pb || !e_grid) return fail(PB_EINVAL, "NULL argument");
+    if (!pb->solved) return fail(PB_EINVAL, "pb_grid_energy before a successful pb_solve");
+    if (pb->ref) return fail(PB_EINVAL, "pb_grid_energy: locally refined problems are not supported");
+    *e_grid = 0.0;
+    if (pb->na == 0) return PB_OK;
+    HIPCHK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    const Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    const int nb = grid_energy_blocks(at.n);
+    int rc = PB_OK;
+    double* part = dalloc<double>(pb, (size_t)nb + 1, &rc);
+    if (rc) return rc;
+    hipError_t e = launch_grid_energy(s, pb->g, at, pb->x, 0.5 * pb->lB, part);
+    if (e == hipSuccess) e = hipMemcpyAsync(e_grid, part + nb, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    pb->mem.put(part);
+    if (e != hipSuccess) return fail(PB_EDEVICE, "grid energy: %s", hipGetErrorString(e));
+    return PB_OK;
+}
+
 int pb_copy_potential(const pb_problem* pb, double* host_phi)
 {
     if (!pb || !host_phi) return fail(PB_EINVAL, "NULL argument");

@@ -331,21 +331,84 @@ __global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, doub
 // per atom: the grid cell that receives its charge (floor of its grid coordinates, clamped
 // to the cells of the grid) and its offsets in that cell: ac[6a + d] = t_d, ac[6a + 3 + d] =
 // the cell index along d
-__global__ void __launch_bounds__(256) k_atom_cells(Grid g, Atoms at, double* ac)
+// the grid cell holding atom a (its low corner, clamped into the grid) and the atom's
+// fractional position in it along each axis
+__device__ __forceinline__ void atom_cell(const Grid& g, const Atoms& at, int a, double* t, double* fl)
 {
 #pragma clang fp contract(off)
-    const int a = blockIdx.x * 256 + threadIdx.x;
-    if (a >= at.n) return;
     const int nn[3] = {g.nx, g.ny, g.nz};
     const double org[3] = {g.ox, g.oy, g.oz};
     for (int d = 0; d < 3; ++d) {
         const double f = (at.xyzr[4 * a + d] - org[d]) / g.h - (double)g.off[d];
-        double fl = floor(f);
-        if (fl < 0) fl = 0;
-        if (fl > nn[d] - 2) fl = nn[d] - 2;
-        ac[6 * a + d] = f - fl;
-        ac[6 * a + 3 + d] = fl;
+        double c = floor(f);
+        if (c < 0) c = 0;
+        if (c > nn[d] - 2) c = nn[d] - 2;
+        t[d] = f - c;
+        fl[d] = c;
     }
+}
+
+__global__ void __launch_bounds__(256) k_atom_cells(Grid g, Atoms at, double* ac)
+{
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= at.n) return;
+    double t[3], fl[3];
+    atom_cell(g, at, a, t, fl);
+    for (int d = 0; d < 3; ++d) {
+        ac[6 * a + d] = t[d];
+        ac[6 * a + 3 + d] = fl[d];
+    }
+}
+
+// sum of v over the 256 threads of a block, the same value in every thread
+__device__ __forceinline__ double block_total(double v, double* sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Grid energy (Sect. 3.3, electrostatic energy): half the sum over grid nodes of the charge
+// deposited there times the potential there.  Summed per atom instead of per node: atom a
+// contributes q_a times the potential at the eight corners of its cell with the deposition's
+// trilinear weights; box nodes hold no deposited charge and are left out.  part[b] = the
+// sum over the atoms of block b.
+__global__ void __launch_bounds__(256) k_grid_energy(Grid g, Atoms at, const double* __restrict__ x,
+                                                     double* __restrict__ part)
+{
+#pragma clang fp contract(off)
+    __shared__ double sh[4];
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (a < at.n) {
+        double t[3], fl[3];
+        atom_cell(g, at, a, t, fl);
+        const int c0[3] = {(int)fl[0], (int)fl[1], (int)fl[2]};
+        for (int c = 0; c < 8; ++c) {
+            const int i = c0[0] + ((c >> 2) & 1), j = c0[1] + ((c >> 1) & 1), k = c0[2] + (c & 1);
+            if (is_box(g, i, j, k)) continue;
+            double w = 1.0;
+            w = w * ((c & 4) ? t[0] : 1.0 - t[0]);
+            w = w * ((c & 2) ? t[1] : 1.0 - t[1]);
+            w = w * ((c & 1) ? t[2] : 1.0 - t[2]);
+            v += w * x[g.idx(i, j, k)];
+        }
+        v *= at.q[a];
+    }
+    v = block_total(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// one block: scale times the sum of part[0..nb), combined in a fixed order; written to part[nb]
+__global__ void __launch_bounds__(256) k_grid_energy_total(double* part, int nb, double scale)
+{
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[b];
+    v = block_total(v, sh);
+    if (threadIdx.x == 0) part[nb] = scale * v;
 }
 
 __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const double* __restrict__ ac,
@@ -825,6 +888,17 @@ hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Ato
 {
     if (at.n > 0) k_atom_cells<<<nblk(at.n, 256), 256, 0, s>>>(g, at, ac);
     k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, ac, rhs);
+    return hipGetLastError();
+}
+
+int grid_energy_blocks(int n_atoms) { return (int)nblk(n_atoms > 0 ? n_atoms : 1, 256); }
+
+hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, const double* x, double scale,
+                              double* part)
+{
+    const int nb = grid_energy_blocks(at.n);
+    k_grid_energy<<<nb, 256, 0, s>>>(g, at, x, part);
+    k_grid_energy_total<<<1, 256, 0, s>>>(part, nb, scale);
     return hipGetLastError();
 }
 

@@ -115,6 +115,11 @@ hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const At
                            double* np, int* owner, double* ck64, float* ck32);
 // ac: scratch of 6 doubles per atom (the atom's cell and offsets)
 hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs);
+// grid energy: part[nb] = scale * sum_a q_a sum_corners w x over interior nodes, with
+// nb = grid_energy_blocks(at.n) and part holding nb + 1 doubles
+int grid_energy_blocks(int n_atoms);
+hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, const double* x, double scale,
+                              double* part);
 hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
                         double* gb);
 hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb);

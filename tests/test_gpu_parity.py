@@ -91,6 +91,8 @@ def test_kirkwood_c1_full_parity(ctx):
     born = 0.5 * (1 / 80 - 1 / 2) / 2.0 * lB
     assert abs(en["e_pol"] - born) <= 1e-10 * abs(born)
     assert abs(en["phi_reac"][0] - 2 * (en["e_pol"] + en["e_ion"])) <= 1e-12 * abs(en["phi_reac"][0])
+    ge = O.grid_energy(grid, mol, run.phi, lB)
+    assert abs(pb.grid_energy() - ge) <= E_TOL64 * abs(ge)
     pb.close()
 
 
@@ -124,6 +126,8 @@ def test_small_molecule_parity(ctx, case):
     assert np.max(np.abs(en["phi_reac"] - pr)) <= 1e-9 * np.max(np.abs(pr))
     cut = pb.cut(fields=True)
     assert np.max(np.abs(cut["F"] - run.energy["F"])) <= 1e-8 * np.max(np.abs(run.energy["F"]))
+    ge = O.grid_energy(grid, mol, run.phi, run.lB)
+    assert abs(pb.grid_energy() - ge) <= E_TOL64 * abs(ge)
     pb.close()
 
 
@@ -137,6 +141,8 @@ def test_mixed_precision_matches_fp64_oracle(ctx):
     assert st["relres"] <= 1e-9
     en = pb.energy()
     compare_energy(en, run.energy, E_TOL_MIXED)
+    ge = O.grid_energy(grid, mol, run.phi, run.lB)
+    assert abs(pb.grid_energy() - ge) <= E_TOL_MIXED * abs(ge)
     pb.close()
 
 
@@ -184,6 +190,7 @@ def test_empty_molecule(ctx):
     en = pb.energy()
     assert en["n_cut"] == 0 and en["e_pol"] == 0.0 and en["e_ion"] == 0.0
     assert np.all(pb.potential() == 0.0)
+    assert pb.grid_energy() == 0.0
     pb.close()
 
 
@@ -197,4 +204,6 @@ def test_c2_full_size_parity(ctx):
     assert st["status"] == 0
     en = pb.energy()
     compare_energy(en, run.energy, E_TOL64)
+    ge = O.grid_energy(grid, mol, run.phi, run.lB)
+    assert abs(pb.grid_energy() - ge) <= E_TOL64 * abs(ge)
     pb.close()
