@@ -77,7 +77,7 @@ MG_MIN_N = 129    # serving: grids from this many nodes per axis use the multigr
 BIND_COMPLEXES, BIND_DISP, BIND_H = 6, 30, 0.5   # binding workload: complexes, displacements, spacing
 N_REQ = 512
 SEED = 2505
-MAX_RESIDENT = 32
+MAX_RESIDENT = 64
 OPEN_LOOP_LOAD = 0.8
 
 
@@ -178,7 +178,6 @@ def fifo_latency(arrivals, service):
 def bench_serving(args, B, torch):
     main = B.Context(0)
     side = B.Context(0, stream=torch.cuda.Stream(0))
-    copy_gbs = main.stream_copy_gbps(1 << 30, 20)
     reqs, unit_arr = stream(N_REQ, args.serve_precond, args.mg_min_n)
     nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
     n_mg = sum(1 for _, g in reqs if g.precond == I.MG)
@@ -344,7 +343,7 @@ def bench_serving(args, B, torch):
                                  "mixed": c4["mixed"], "fp64": c4["fp64"]},
         "roofline": roofline,
         "roofline_solver_kernels": other,
-        "stream_copy_GBs": round(copy_gbs, 1),
+        "stream_copy_GBs": round(main.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": cpu,
     }
     main.close()
@@ -439,10 +438,12 @@ def workload(name: str):
 # algorithmic bytes per grid node (coarse and fine arrays, FP64) of one composite CG iteration
 # on a refined problem: apply (K x3 and the lumped term, role, p; q), dot (role, p, q),
 # update (role, x, r rw; p, q, D^-1; z), direction (role, z, p rw)
-# FP64 flops per atom x cut-point pair of the energy N-body kernel as written (a fused
-# multiply-add counts two): the three differences, the squared distance (5), the correction of
+# FP64 flops per atom x cut-point pair of the energy N-body sum (a fused multiply-add counts
+# two), in the direct form: the three differences, the squared distance (5), the correction of
 # the FP32 reciprocal square root (8; the FP32 start and its two conversions are not counted),
-# the dot product with the weighted normal (5), F/r into its sum (2) and the r^-3 term (4)
+# the dot product with the weighted normal (5), F/r into its sum (2) and the r^-3 term (4).
+# The kernel's expanded form (squared distance and dot product from per-point and per-atom
+# terms) performs the same 27 in 16 instructions instead of 18.
 NBODY_FLOPS_PER_PAIR = 27
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic bytes per interior unknown of one level-0 red-black half-sweep of the V-cycle
@@ -455,7 +456,6 @@ REFINED_ITER_BYTES_FP32 = 25 + 9 + 33 + 13
 
 def bench_refined(args, B, torch):
     ctx = B.Context(0)
-    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)
     mol, grid, desc = workload("c3")
     ref = None
 
@@ -522,7 +522,7 @@ def bench_refined(args, B, torch):
                      "kernel": "composite CG iteration in FP32 (all kernels of one iteration, reliable updates "
                                "included)",
                      "bytes_per_launch": round(nodes * REFINED_ITER_BYTES_FP32), "avg_launch_ms": round(1e3 * t_iter, 4)},
-        "stream_copy_GBs": round(copy_gbs, 1),
+        "stream_copy_GBs": round(ctx.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": None,
     }
     if not args.no_cpu:
@@ -548,7 +548,6 @@ def bench_refined(args, B, torch):
 
 def bench_single(args, B, torch):
     ctx = B.Context(0)
-    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)
     mol, grid, desc = workload(args.workload)
     nu = grid.unknowns
     ref = B.solve(mol, replace(grid, rtol=1e-12, precision=I.FP64), ctx)
@@ -612,7 +611,7 @@ def bench_single(args, B, torch):
         "fp64_plain": {"solves_per_s": round(p64["solves_per_s"], 3), "p50_ms": round(p64["p50"], 3),
                        "p99_ms": round(p64["p99"], 3), "iters": p64["iters"], "energy_relerr_vs_fp64": p64["err"]},
         "roofline": None,
-        "stream_copy_GBs": round(copy_gbs, 1),
+        "stream_copy_GBs": round(ctx.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": None,
     }
     # the dominant kernel of the multigrid solve's step: the level-0 half-sweep (two per
@@ -648,7 +647,6 @@ def bench_binding(args, B, torch):
     ligand, all on one grid per complex), served through the serving loop."""
     main = B.Context(0)
     side = B.Context(0, stream=torch.cuda.Stream(0))
-    copy_gbs = main.stream_copy_gbps(1 << 30, 20)
     w = I.binding_workload(n_complex=BIND_COMPLEXES, n_disp=BIND_DISP, h=BIND_H, precision=I.MIXED, rtol=RTOL,
                            inner_rtol=DELTA_MG, precond=I.MG)
     reqs = [(m, g) for _, _, _, m, g in w]
@@ -706,7 +704,7 @@ def bench_binding(args, B, torch):
                      "avg_vcycle_ms": round(prof["mg_vcycle_ms"] / n, 5),
                      "scope": "the first iteration of every chunk of every request (timed run)"},
         "roofline_other": nbt.roofline("every energy read-back of the timed run"),
-        "stream_copy_GBs": round(copy_gbs, 1),
+        "stream_copy_GBs": round(main.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": None,
     }
     if not args.no_cpu:
@@ -731,7 +729,6 @@ def bench_derefine(args, B, torch):
     widened by 2 A) and 1 A cells beyond, against the tight uniform 161^3 grid at 0.5 A with
     Debye-Hueckel box values."""
     ctx = B.Context(0)
-    copy_gbs = ctx.stream_copy_gbps(1 << 30, 20)
     mol, g_dh = I.protein_c2()
     g_dr = I.cubic_grid(161, 1.0, bc=I.BC_ZERO, refine=2, refine_shell=2.0, refine_brick=4)
     ref_dh = B.solve(mol, replace(g_dh, precision=I.FP64, rtol=1e-10), ctx)
@@ -777,7 +774,7 @@ def bench_derefine(args, B, torch):
             "e_ion_relerr": abs(en["e_ion"] / ref_dh["e_ion"] - 1.0),
             "uniform_mixed_multigrid_solves_per_s": round(v_dh, 3)},
         "roofline": None,
-        "stream_copy_GBs": round(copy_gbs, 1),
+        "stream_copy_GBs": round(ctx.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": None,
     }
     ctx.close()

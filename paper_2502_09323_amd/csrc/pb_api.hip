@@ -322,7 +322,7 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     if (!pb->F) {
         pb->F = dalloc<double>(pb, nc1, &rc);
         if (!rc) pb->phip = dalloc<double>(pb, nc1, &rc);
-        if (!rc) pb->pts = dalloc<double>(pb, 8 * nc1, &rc);
+        if (!rc) pb->pts = dalloc<double>(pb, CUT_POINT_DOUBLES * nc1, &rc);
         if (rc) return rc;
     }
     if (!pb->hout) {

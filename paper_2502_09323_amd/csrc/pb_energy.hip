@@ -70,16 +70,20 @@ __global__ void __launch_bounds__(256) k_edge_fields(Grid g, double eps_in, doub
     (void)kcut;
     F[c] = f;
     phip[c] = pp;
-    double* o = pts + 8 * c;
-    o[0] = rp[3 * c];
-    o[1] = rp[3 * c + 1];
-    o[2] = rp[3 * c + 2];
+    double* o = pts + CUT_POINT_DOUBLES * c;
+    const double px = rp[3 * c], py = rp[3 * c + 1], pz = rp[3 * c + 2];
     const double wphi = wp[c] * pp;
-    o[3] = wphi * np[3 * c];
-    o[4] = wphi * np[3 * c + 1];
-    o[5] = wphi * np[3 * c + 2];
+    const double ux = wphi * np[3 * c], uy = wphi * np[3 * c + 1], uz = wphi * np[3 * c + 2];
+    o[0] = px;
+    o[1] = py;
+    o[2] = pz;
+    o[3] = ux;
+    o[4] = uy;
+    o[5] = uz;
     o[6] = f;
-    o[7] = 0.0;
+    o[7] = fma(px, px, fma(py, py, pz * pz));
+    o[8] = 2.0 * fma(px, ux, fma(py, uy, pz * uz));
+    o[9] = 0.0;
 }
 
 // 1/sqrt(x) in FP64: the hardware FP32 reciprocal square root y as a start (relative error
@@ -100,57 +104,63 @@ constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
 
 // grid (ceil(n_atoms/NB_BLOCK_ATOMS), nchunk); thread t of block b owns the atoms
 // b*NB_BLOCK_ATOMS + t + 256 k (k < NB_ATOMS), so that each cut point read from LDS serves
-// NB_ATOMS pairs.  A cut point is (r_p, w_p phi_p n_p, F_p): the surface-potential weight is
-// folded into the normal when the point is written.  partial[(chunk*n + i)*2 + {0,1}] =
-// {S_F, S_D} of atom i over the chunk.
+// NB_ATOMS pairs.  A cut point carries r_p, u_p = w_p phi_p n_p (the surface-potential weight
+// folded into the normal), F_p, |r_p|^2 and 2 r_p.u_p, so that a pair needs no difference
+// vector: with a = the atom centre,
+//   |r_p - a|^2 = |r_p|^2 + |a|^2 - 2 a.r_p   and   2 (r_p - a).u_p = 2 r_p.u_p - 2 a.u_p,
+// each one add or three fused multiply-adds with -2a held per atom.  The rounding error of the
+// first is about |r_p|^2 eps, far below the squared distance (at least the smallest atom
+// radius squared, as every cut point lies outside or on every ball) times 1e-10.
+// partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} of atom i over the chunk.
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
                                                double* __restrict__ partial, int64_t chunk_len)
 {
-    __shared__ double sp[NB_TILE * 8];
+    constexpr int PT = CUT_POINT_DOUBLES;
+    __shared__ double sp[NB_TILE * PT];
     const int a0 = blockIdx.x * NB_BLOCK_ATOMS + threadIdx.x;
-    double ax[NB_ATOMS], ay[NB_ATOMS], az[NB_ATOMS], sf[NB_ATOMS], sd[NB_ATOMS];
+    double mx[NB_ATOMS], my[NB_ATOMS], mz[NB_ATOMS], aa[NB_ATOMS], sf[NB_ATOMS], sd[NB_ATOMS];
+    double x0 = 0.0, y0 = 0.0, z0 = 0.0;
     if (a0 < at.n) {
-        ax[0] = at.xyzr[4 * a0];
-        ay[0] = at.xyzr[4 * a0 + 1];
-        az[0] = at.xyzr[4 * a0 + 2];
-    } else {
-        ax[0] = ay[0] = az[0] = 0.0;
+        x0 = at.xyzr[4 * a0];
+        y0 = at.xyzr[4 * a0 + 1];
+        z0 = at.xyzr[4 * a0 + 2];
     }
 #pragma unroll
-    for (int k = 1; k < NB_ATOMS; ++k) {
+    for (int k = 0; k < NB_ATOMS; ++k) {
         const int a = a0 + 256 * k;
-        if (a < at.n) {
-            ax[k] = at.xyzr[4 * a];
-            ay[k] = at.xyzr[4 * a + 1];
-            az[k] = at.xyzr[4 * a + 2];
-        } else {
-            // an inactive slot evaluates the pairs of a far point, whose sums are discarded
-            ax[k] = ax[0] + 1e3 * k;
-            ay[k] = ay[0];
-            az[k] = az[0];
+        // an inactive slot evaluates the pairs of a far point, whose sums are discarded
+        double x = x0 + 1e3 * k, y = y0, z = z0;
+        if (k > 0 && a < at.n) {
+            x = at.xyzr[4 * a];
+            y = at.xyzr[4 * a + 1];
+            z = at.xyzr[4 * a + 2];
         }
+        mx[k] = -2.0 * x;
+        my[k] = -2.0 * y;
+        mz[k] = -2.0 * z;
+        aa[k] = fma(x, x, fma(y, y, z * z));
+        sf[k] = sd[k] = 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < NB_ATOMS; ++k) sf[k] = sd[k] = 0.0;
     const int64_t p0 = (int64_t)blockIdx.y * chunk_len;
     int64_t p1 = p0 + chunk_len;
     if (p1 > ncut) p1 = ncut;
     for (int64_t base = p0; base < p1; base += NB_TILE) {
         const int m = (int)((p1 - base) < NB_TILE ? (p1 - base) : NB_TILE);
         __syncthreads();
-        for (int t = threadIdx.x; t < m * 8; t += 256) sp[t] = pts[base * 8 + t];
+        for (int t = threadIdx.x; t < m * PT; t += 256) sp[t] = pts[base * PT + t];
         __syncthreads();
         if (a0 < at.n) {
             for (int u = 0; u < m; ++u) {
-                const double* P = sp + 8 * u;
-                const double px = P[0], py = P[1], pz = P[2], wx = P[3], wy = P[4], wz = P[5], f = P[6];
+                const double* P = sp + PT * u;
+                const double px = P[0], py = P[1], pz = P[2], ux = P[3], uy = P[4], uz = P[5], f = P[6];
+                const double pp = P[7], pu2 = P[8];
 #pragma unroll
                 for (int k = 0; k < NB_ATOMS; ++k) {
-                    const double dx = px - ax[k], dy = py - ay[k], dz = pz - az[k];
-                    const double r = rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
-                    const double dn = fma(dx, wx, fma(dy, wy, dz * wz));
+                    const double r2 = fma(mx[k], px, fma(my[k], py, fma(mz[k], pz, pp + aa[k])));
+                    const double dn2 = fma(mx[k], ux, fma(my[k], uy, fma(mz[k], uz, pu2)));
+                    const double r = rsqrt_nr(r2);
                     sf[k] = fma(f, r, sf[k]);
-                    sd[k] = fma(dn, (r * r) * r, sd[k]);
+                    sd[k] = fma(dn2, (r * r) * r, sd[k]);
                 }
             }
         }
@@ -161,7 +171,7 @@ __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const dou
         if (a < at.n) {
             double* o = partial + ((int64_t)blockIdx.y * at.n + a) * 2;
             o[0] = sf[k];
-            o[1] = sd[k];
+            o[1] = 0.5 * sd[k];
         }
     }
 }

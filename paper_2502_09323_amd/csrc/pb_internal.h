@@ -193,11 +193,14 @@ hipError_t launch_ru_fin(hipStream_t s, CGState* st, const double* part3, int nb
 int residual_blocks(const Grid& g);
 
 // ---- energy kernels (pb_energy.hip) -------------------------------------------------------
+// a cut point as the N-body kernel reads it: r_p (3), the weighted normal u = w_p phi_p n_p
+// (3), F_p, |r_p|^2, 2 r_p.u, and one pad
+constexpr int CUT_POINT_DOUBLES = 10;
 hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, double eps_out,
                               int64_t ncut, const int64_t* cutkey, const uint32_t* code,
                               const double* alpha, const double* kcut, const double* x,
                               const double* gb, const double* wp, double* F, double* phip,
-                              double* pts /* 8 per cut: rp, w*phip*np, F, 0 */, const double* rp,
+                              double* pts /* CUT_POINT_DOUBLES per cut point */, const double* rp,
                               const double* np);
 hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const double* pts,
                         double* partial, int nchunk);
