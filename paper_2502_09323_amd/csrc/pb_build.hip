@@ -522,31 +522,37 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, doub
 // -126 gives 0 in place of a term under 1e-38.
 __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, double eps_out, double* gb)
 {
-    __shared__ double sa[256 * 3];
+    // squared distance in FP64 in the expanded form |p|^2 + |a|^2 - 2 a.p (one add and three
+    // fused multiply-adds from -2a and |a|^2 held in LDS; the box is far from every atom, so
+    // the cancellation costs nothing at FP32 precision), then the FP32 terms
+    __shared__ double sa[256 * 4];
     __shared__ float sq[256];
     int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool act = t < n_box(g);
     int i = 0, j = 0, k = 0;
     if (act) box_node(g, t, i, j, k);
     const double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    const double pp = fma(p[0], p[0], fma(p[1], p[1], p[2] * p[2]));
     const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
     double s = 0.0;
     for (int base = 0; base < at.n; base += 256) {
         int a = base + threadIdx.x;
         __syncthreads();
         if (a < at.n) {
-            sa[3 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
-            sa[3 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
-            sa[3 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
+            const double x = at.xyzr[4 * a + 0], y = at.xyzr[4 * a + 1], z = at.xyzr[4 * a + 2];
+            sa[4 * threadIdx.x + 0] = -2.0 * x;
+            sa[4 * threadIdx.x + 1] = -2.0 * y;
+            sa[4 * threadIdx.x + 2] = -2.0 * z;
+            sa[4 * threadIdx.x + 3] = fma(x, x, fma(y, y, z * z));
             sq[threadIdx.x] = (float)at.q[a];
         }
         __syncthreads();
         int m = at.n - base < 256 ? at.n - base : 256;
         if (act)
+#pragma unroll 4
             for (int u = 0; u < m; ++u) {
-                const float dx = (float)(p[0] - sa[3 * u]), dy = (float)(p[1] - sa[3 * u + 1]),
-                            dz = (float)(p[2] - sa[3 * u + 2]);
-                const float r2 = dx * dx + dy * dy + dz * dz;
+                const double* A = sa + 4 * u;
+                const float r2 = (float)fma(A[0], p[0], fma(A[1], p[1], fma(A[2], p[2], pp + A[3])));
                 const float ri = __builtin_amdgcn_rsqf(r2);
                 const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
                 s += (double)(sq[u] * e * ri);
