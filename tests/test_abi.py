@@ -74,3 +74,7 @@ def test_null_arguments_are_rejected_without_a_gpu(lib):
     st = B.PbSolveStats()
     assert lib.pb_solve(None, C.byref(st)) == B.PB_EINVAL
     assert lib.pb_num_cut(None) == B.PB_EINVAL
+    e = C.c_double(1.0)
+    assert lib.pb_grid_energy(None, C.byref(e)) == B.PB_EINVAL
+    assert lib.pb_grid_energy(None, None) == B.PB_EINVAL
+    assert b"NULL" in lib.pb_last_error()
