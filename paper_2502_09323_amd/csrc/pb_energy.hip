@@ -108,9 +108,10 @@ constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
 // folded into the normal), F_p, |r_p|^2 and 2 r_p.u_p, so that a pair needs no difference
 // vector: with a = the atom centre,
 //   |r_p - a|^2 = |r_p|^2 + |a|^2 - 2 a.r_p   and   2 (r_p - a).u_p = 2 r_p.u_p - 2 a.u_p,
-// each one add or three fused multiply-adds with -2a held per atom.  The rounding error of the
-// first is about |r_p|^2 eps, far below the squared distance (at least the smallest atom
-// radius squared, as every cut point lies outside or on every ball) times 1e-10.
+// the first in one add and three fused multiply-adds, the second in three, with -2a and |a|^2
+// held per atom.  The rounding error of the first is about (|r_p|^2 + |a|^2) eps, far below
+// 1e-10 times the squared distance (at least the smallest atom radius squared, as every cut
+// point lies outside or on every ball).
 // partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} of atom i over the chunk.
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
                                                double* __restrict__ partial, int64_t chunk_len)
