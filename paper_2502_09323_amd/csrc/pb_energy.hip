@@ -289,13 +289,14 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 int nbody_chunks(int n_atoms, int64_t ncut)
 {
-    // enough blocks to fill 256 CUs several times, each chunk at least one LDS tile
+    // about 8192 blocks, so that every SIMD holds several waves even for a few thousand atoms
+    // (whose launches are short), each chunk at least 64 cut points
     const int ab = (n_atoms + NB_BLOCK_ATOMS - 1) / NB_BLOCK_ATOMS;   // blocks of k_nbody along the atoms
-    int64_t want = (2048 + ab - 1) / ab;
-    int64_t maxc = (ncut + NB_TILE - 1) / NB_TILE;
+    int64_t want = (8192 + ab - 1) / ab;
+    int64_t maxc = (ncut + 63) / 64;
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
-    if (want > 4096) want = 4096;
+    if (want > 8192) want = 8192;
     return (int)want;
 }
 
