@@ -331,7 +331,7 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     }
     if (!pb->ev) HIPCHK(hipEventCreateWithFlags(&pb->ev, hipEventDisableTiming));
     pb->e_nchunk = nbody_chunks((int)std::max<int64_t>(pb->na, 1), pb->ncut);
-    pb->e_tmp[0] = dalloc<double>(pb, 2 * na1 * (size_t)pb->e_nchunk, &rc);   // partial sums
+    pb->e_tmp[0] = dalloc<double>(pb, (size_t)energy_partial_doubles((int)na1, pb->e_nchunk), &rc);   // partial sums
     const int ncc = coulomb_chunks((int)std::max<int64_t>(pb->na, 1));
     if (!rc) pb->e_tmp[1] = dalloc<double>(pb, na1 * (size_t)ncc, &rc);        // Coulomb potentials
     if (!rc) pb->e_tmp[2] = dalloc<double>(pb, na1, &rc);                      // reaction potentials

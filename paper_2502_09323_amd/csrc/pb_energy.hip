@@ -216,6 +216,25 @@ __global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* __restrict__ 
 }
 
 constexpr int ER_BLOCKS = 256;   // most blocks of the energy reduction
+constexpr int ER_FOLD = 16;      // chunk partials summed per group before the reduction
+
+// out[(g*n + a)*2 + {0,1}] = the partials of atom a summed over chunks g*ER_FOLD ..
+// g*ER_FOLD + ER_FOLD - 1 (those that exist), in chunk order; grid (ceil(n/256), groups)
+__global__ void __launch_bounds__(256) k_chunk_fold(const double* __restrict__ partial, int nchunk, int n,
+                                                    double* __restrict__ out)
+{
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= n) return;
+    const int c0 = blockIdx.y * ER_FOLD;
+    const int c1 = c0 + ER_FOLD < nchunk ? c0 + ER_FOLD : nchunk;
+    double sf = 0.0, sd = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        sf += partial[((int64_t)c * n + a) * 2];
+        sd += partial[((int64_t)c * n + a) * 2 + 1];
+    }
+    out[((int64_t)blockIdx.y * n + a) * 2] = sf;
+    out[((int64_t)blockIdx.y * n + a) * 2 + 1] = sd;
+}
 
 // Energy reduction, first stage: each block takes the atoms and cut points b*256 + t +
 // k*gridDim.x*256; an atom's potentials are its chunk partials summed in chunk order.
@@ -337,10 +356,25 @@ hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic, int ncc)
     return hipGetLastError();
 }
 
-hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, const double* partial, int nchunk,
+int fold_chunks(int nchunk) { return nchunk > ER_FOLD ? (nchunk + ER_FOLD - 1) / ER_FOLD : 0; }
+
+int64_t energy_partial_doubles(int n_atoms, int nchunk)
+{
+    return 2 * (int64_t)std::max(n_atoms, 1) * (nchunk + fold_chunks(nchunk));
+}
+
+hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, double* partial, int nchunk,
                                 const double* phic, int ncc, double eps_in, double eps_out, double lB,
                                 double* phi_reac, double* out, const double* F, int64_t ncut, const double* wp)
 {
+    const int nf = fold_chunks(nchunk);
+    if (nf > 0 && at.n > 0) {
+        // many chunks: sum them in groups first, so the per-atom loop below stays short
+        double* folded = partial + 2 * (int64_t)at.n * nchunk;
+        k_chunk_fold<<<dim3(nblk(at.n, 256), (unsigned)nf), 256, 0, s>>>(partial, nchunk, at.n, folded);
+        partial = folded;
+        nchunk = nf;
+    }
     int64_t need = std::max<int64_t>(at.n, ncut);
     int nb = (int)std::min<int64_t>(ER_BLOCKS, std::max<int64_t>(1, (need + 255) / 256));
     k_energy_part<<<nb, 256, 0, s>>>(at, partial, nchunk, phic, ncc, eps_in, eps_out, lB, phi_reac, F, ncut, wp,

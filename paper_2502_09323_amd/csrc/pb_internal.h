@@ -208,7 +208,10 @@ hipError_t launch_nbody(hipStream_t s, const Atoms& at, int64_t ncut, const doub
 hipError_t launch_coulomb(hipStream_t s, const Atoms& at, double* phic, int ncc);
 // out: ENERGY_OUT_DOUBLES (the five results, then per-block partial sums)
 constexpr int ENERGY_OUT_DOUBLES = 16 + 5 * 256;
-hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, const double* partial, int nchunk,
+// the N-body partials: nchunk chunks, then room for their sums in groups (the reduction folds
+// many chunks first); energy_partial_doubles gives the buffer's size
+int64_t energy_partial_doubles(int n_atoms, int nchunk);
+hipError_t launch_energy_reduce(hipStream_t s, const Atoms& at, double* partial, int nchunk,
                                 const double* phic, int ncc, double eps_in, double eps_out, double lB,
                                 double* phi_reac, double* out, const double* F, int64_t ncut,
                                 const double* wp);
