@@ -42,7 +42,9 @@ enum {
     PB_ENOMEM = -2,      /* allocation failed or a request exceeds the memory budget */
     PB_ENOCONV = -3,     /* max_iter reached; the last iterate and statistics are returned */
     PB_EBREAKDOWN = -4,  /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
-    PB_EDEVICE = -5      /* a HIP runtime call failed; see pb_last_error() */
+    PB_EDEVICE = -5,     /* a HIP runtime call failed; see pb_last_error() */
+    PB_ECANCELED = -6,   /* serving: the request was cancelled (pb_cancel) */
+    PB_ETIMEDOUT = -7    /* serving: the request did not complete within the server's time limit */
 };
 
 enum { PB_BC_ZERO = 0, PB_BC_DH = 1, PB_BC_USER = 2 };
@@ -346,9 +348,29 @@ int pb_server_step(pb_server* srv, int32_t* n_active, int32_t* n_queued);
 
 /* Move up to max finished requests out of the server: ids, energies, solve statistics,
  * completion times (server clock) and result codes (PB_OK, PB_ENOCONV, PB_EBREAKDOWN,
- * PB_ENOMEM, ...).  Any output array may be NULL. */
+ * PB_ENOMEM, PB_ECANCELED, PB_ETIMEDOUT, ...).  Any output array may be NULL. */
 int pb_poll(pb_server* srv, uint64_t* ids, pb_energy_out* results, pb_solve_stats* stats,
             double* done_time_s, int32_t* codes, int32_t max, int32_t* n_done);
+
+/* Cancel a queued or running request: it completes with code PB_ECANCELED (reported by
+ * pb_poll) and no energies.  A running problem stops iterating at once and its device memory
+ * is released when no launch in flight still uses it.  Errors: PB_EINVAL (NULL server, or the
+ * request is not queued or running: unknown, already finished or already cancelled). */
+int pb_cancel(pb_server* srv, uint64_t request_id);
+
+/* Time limit per request, in seconds from its arrival time (0, the default: none).  A request
+ * not finished within it completes with code PB_ETIMEDOUT and no energies, as if cancelled;
+ * the limit is checked at every pb_server_step.  Errors: PB_EINVAL (negative or non-finite). */
+int pb_server_set_timeout(pb_server* srv, double seconds);
+
+/* Device-memory accounting of the serving loop against ctx's hbm_budget_bytes.  A request
+ * holds an estimate from its atoms while it is queued for a build, an upper bound from its
+ * counted cut edges while the build allocates, and then exactly the bytes its problem holds
+ * plus those its energy read-back will allocate, until it completes.  in_use: the current
+ * sum; peak: its largest value so far; over_budget: builds let past the budget because
+ * nothing else running could free memory (a request that alone exceeds the budget fails with
+ * PB_ENOMEM instead).  Any output may be NULL. */
+int pb_server_memory(const pb_server* srv, size_t* in_use, size_t* peak, int64_t* over_budget);
 
 /* Host seconds spent so far in the four phases of pb_server_step: waiting for chunks,
  * retiring (energy read-back), admitting (coefficient builds), launching. */

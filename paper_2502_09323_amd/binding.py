@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpb.so")
 
 PB_OK, PB_EINVAL, PB_ENOMEM, PB_ENOCONV, PB_EBREAKDOWN, PB_EDEVICE = 0, -1, -2, -3, -4, -5
+PB_ECANCELED, PB_ETIMEDOUT = -6, -7
 PB_BC_ZERO, PB_BC_DH, PB_BC_USER = 0, 1, 2
 PB_FP64, PB_MIXED = 0, 1
 PB_PRECOND_JACOBI, PB_PRECOND_MG = 0, 1
@@ -26,7 +27,7 @@ EXPORTED = [
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
     "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg", "pb_get_energy_profile", "pb_server_profile_energy",
-    "pb_grid_energy",
+    "pb_grid_energy", "pb_cancel", "pb_server_set_timeout", "pb_server_memory",
 ]
 
 
@@ -122,6 +123,9 @@ def load(path: str = LIB_PATH):
                                        C.POINTER(i64)]
     L.pb_server_destroy.argtypes = [P]
     L.pb_server_destroy.restype = None
+    L.pb_cancel.argtypes = [P, C.c_uint64]
+    L.pb_server_set_timeout.argtypes = [P, C.c_double]
+    L.pb_server_memory.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(i64)]
     L.pb_refine_info.argtypes = [P, C.POINTER(PbRefineStats)]
     L.pb_copy_refined_cells.argtypes = [P, P]
     L.pb_copy_fine_potential.argtypes = [P, P]
@@ -464,6 +468,23 @@ class Server:
             raise _err(rc)
         out.update(nbody_ms=f.value, nbody_pairs=g.value, nbody_calls=k.value)
         return out
+
+    def cancel(self, request_id: int):
+        rc = _lib.pb_cancel(self.h, int(request_id))
+        if rc != PB_OK:
+            raise _err(rc)
+
+    def set_timeout(self, seconds: float):
+        rc = _lib.pb_server_set_timeout(self.h, float(seconds))
+        if rc != PB_OK:
+            raise _err(rc)
+
+    def memory(self) -> dict:
+        a, b, c = C.c_size_t(), C.c_size_t(), C.c_int64()
+        rc = _lib.pb_server_memory(self.h, C.byref(a), C.byref(b), C.byref(c))
+        if rc != PB_OK:
+            raise _err(rc)
+        return dict(in_use=int(a.value), peak=int(b.value), over_budget=int(c.value))
 
     def times(self) -> dict:
         v = np.zeros(4)

@@ -345,9 +345,9 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
                                   pb->part_res, pb->st));
         HIPCHK(launch_ru_fin(s, pb->st, pb->part_res, pb->nbres, 0, 0.0, 0.0));
     }
-    Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    const Atoms at = pbi_atoms(pb);
     HIPCHK(launch_fill(s, pb->e_tmp[3], 16 * sizeof(double)));
-    HIPCHK(launch_edge_fields(s, pb->g, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
+    HIPCHK(launch_edge_fields(s, pb->g, at, pb->prm.eps_in, pb->prm.eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
                               pb->kcut, pb->x, pb->gb, pb->wp, pb->F, pb->phip, pb->pts, pb->rp, pb->np));
     pb->prof_nbody_ms = pb->prof_nbody_pairs = 0;
     pb->nb_timed = pb->ctx->profile && pb->na > 0 && pb->ncut > 0;
@@ -368,6 +368,58 @@ int pbi_energy_begin(pb_problem* pb, int finish_mixed)
     HIPCHK(hipMemcpyAsync(pb->hout + 16, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(pb->ev, s));
     return PB_OK;
+}
+
+namespace {
+
+size_t rounded(size_t n) { return n == 0 ? 256 : (n + 255) & ~(size_t)255; }   // as DevAlloc::get
+
+// the energy read-back's buffers: F, phi_p and the N-body cut points (kept with the problem
+// once made), then the partial sums, Coulomb potentials, reaction potentials and sums
+size_t energy_bytes(int64_t na, int64_t ncut, bool with_cut_arrays)
+{
+    const size_t nc1 = (size_t)std::max<int64_t>(ncut, 1), na1 = (size_t)std::max<int64_t>(na, 1);
+    size_t b = 0;
+    if (with_cut_arrays) b += 2 * rounded(8 * nc1) + rounded(8 * (size_t)CUT_POINT_DOUBLES * nc1);
+    const int nchunk = nbody_chunks((int)na1, ncut);
+    const int ncc = coulomb_chunks((int)na1);
+    b += rounded(8 * (size_t)energy_partial_doubles((int)na1, nchunk)) + rounded(8 * na1 * (size_t)ncc) +
+         rounded(8 * na1) + rounded(8 * (size_t)ENERGY_OUT_DOUBLES);
+    return b;
+}
+
+}  // namespace
+
+size_t pbi_energy_bytes(const pb_problem* pb) { return energy_bytes(pb->na, pb->ncut, pb->F == nullptr); }
+
+size_t pbi_request_bytes(const pb_params& p, int64_t na, const double* radius, int64_t ncut)
+{
+    const int64_t N = (int64_t)p.n[0] * p.n[1] * row_stride(p.n[2]);
+    if (ncut < 0) {
+        // before the build counts them: a lattice line along one axis meets a ball of radius R
+        // at most twice and at most pi (R + h)^2 / h^2 such lines pass through it, so the cut
+        // edges are fewer than 6 pi (R + h)^2 / h^2 per atom; overlapping balls hide most of
+        // that (about a seventh at 0.5 A on the synthetic molecules), and a third of it is taken
+        double e = 0.0;
+        for (int64_t a = 0; a < na; ++a) {
+            const double r = radius[a] + p.h;
+            e += 2.0 * 3.14159265358979323846 * r * r / (p.h * p.h);
+        }
+        ncut = std::min<int64_t>((int64_t)e, 3 * N);
+    }
+    // per node: code, b, box values and the FP64 solution (28 B), the build's classes (4 B,
+    // until the build ends), and the solver: six FP32 CG vectors and the correction (28 B), or
+    // for the multigrid form six FP32 CG vectors, 1/D and the red residual on level 0 (32 B)
+    // and the coarser levels (64 B per stored node in FP64 and FP32 copies; with the z-row
+    // padding of small levels they hold up to a quarter of level 0's stored nodes)
+    const size_t per_node = p.precond == PB_PRECOND_MG ? 28 + 4 + 32 + 16 : 28 + 4 + 28;
+    // per cut edge: key, alpha, K, crossing point, normal, owner, area weight (84 B) and at
+    // most one slot of the compact coefficient tables (40 B)
+    const size_t per_cut = 124;
+    // per atom: coordinates and charge (40 B), bin ids and deposition cells (52 B)
+    const size_t per_atom = 92;
+    return (size_t)N * per_node + (size_t)std::max<int64_t>(ncut, 1) * per_cut + (size_t)std::max<int64_t>(na, 1) * per_atom +
+           energy_bytes(na, ncut, true) + ((size_t)1 << 20);
 }
 
 int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* stats)
@@ -642,7 +694,8 @@ int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz
     }
     HK(hipMemcpyAsync(pb->xyzr, hx, sizeof(double) * 4 * na1, hipMemcpyHostToDevice, s));
     HK(hipMemcpyAsync(pb->q, hq, sizeof(double) * na1, hipMemcpyHostToDevice, s));
-    Atoms at{(int)na, pb->xyzr, pb->q};
+    for (int d = 0; d < 3; ++d) pb->ctr[d] = na > 0 ? 0.5 * (lo[d] + hi[d]) : 0.0;
+    const Atoms at = pbi_atoms(pb);
 
     // bins of edge >= R_max + h (and >= 2h) so that the 27 bins around a node or an edge end
     // hold every atom whose ball can touch it
@@ -715,7 +768,7 @@ int pbi_build_continue(pb_problem* pb)
     pb->ncut = T.htot[1];
     const size_t N = (size_t)g.N;
     const size_t ns1 = (size_t)std::max<int64_t>(pb->nslot, 1), nc1 = (size_t)std::max<int64_t>(pb->ncut, 1);
-    Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    const Atoms at = pbi_atoms(pb);
 
     pb->code = dalloc<uint32_t>(pb, N, &rc);
     CK(rc);
@@ -783,6 +836,8 @@ int pbi_build_continue(pb_problem* pb)
 }
 
 void pbi_build_end(pb_problem* pb) { release_tmp(pb); }
+
+int64_t pbi_build_counted_cuts(const pb_problem* pb) { return pb->bt ? pb->bt->htot[1] : pb->ncut; }
 
 extern "C" {
 
@@ -924,7 +979,7 @@ int pb_grid_energy(pb_problem* pb, double* e_grid)
     if (pb->na == 0) return PB_OK;
     HIPCHK(hipSetDevice(pb->ctx->device));
     hipStream_t s = pb->ctx->stream;
-    const Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    const Atoms at = pbi_atoms(pb);
     const int nb = grid_energy_blocks(at.n);
     int rc = PB_OK;
     double* part = dalloc<double>(pb, (size_t)nb + 1, &rc);

@@ -523,15 +523,17 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, doub
 __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, double eps_out, double* gb)
 {
     // squared distance in FP64 in the expanded form |p|^2 + |a|^2 - 2 a.p (one add and three
-    // fused multiply-adds from -2a and |a|^2 held in LDS; the box is far from every atom, so
-    // the cancellation costs nothing at FP32 precision), then the FP32 terms
+    // fused multiply-adds from -2a and |a|^2 held in LDS), with p and a relative to the atoms'
+    // centre so that the cancellation does not grow with the molecule's distance from the
+    // coordinate origin (the box is far from every atom, so it costs nothing at FP32
+    // precision), then the FP32 terms
     __shared__ double sa[256 * 4];
     __shared__ float sq[256];
     int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool act = t < n_box(g);
     int i = 0, j = 0, k = 0;
     if (act) box_node(g, t, i, j, k);
-    const double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
+    const double p[3] = {node_x(g, 0, i) - at.cx, node_x(g, 1, j) - at.cy, node_x(g, 2, k) - at.cz};
     const double pp = fma(p[0], p[0], fma(p[1], p[1], p[2] * p[2]));
     const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
     double s = 0.0;
@@ -539,7 +541,8 @@ __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, do
         int a = base + threadIdx.x;
         __syncthreads();
         if (a < at.n) {
-            const double x = at.xyzr[4 * a + 0], y = at.xyzr[4 * a + 1], z = at.xyzr[4 * a + 2];
+            const double x = at.xyzr[4 * a + 0] - at.cx, y = at.xyzr[4 * a + 1] - at.cy,
+                         z = at.xyzr[4 * a + 2] - at.cz;
             sa[4 * threadIdx.x + 0] = -2.0 * x;
             sa[4 * threadIdx.x + 1] = -2.0 * y;
             sa[4 * threadIdx.x + 2] = -2.0 * z;

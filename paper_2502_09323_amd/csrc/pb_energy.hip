@@ -46,7 +46,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh, int
     }
 }
 
-__global__ void __launch_bounds__(256) k_edge_fields(Grid g, double eps_in, double eps_out, int64_t ncut,
+__global__ void __launch_bounds__(256) k_edge_fields(Grid g, Atoms at, double eps_in, double eps_out, int64_t ncut,
                                                      const int64_t* cutkey, const uint32_t* code,
                                                      const double* alpha, const double* kcut,
                                                      const double* x, const double* gb, const double* wp,
@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(256) k_edge_fields(Grid g, double eps_in, doub
     F[c] = f;
     phip[c] = pp;
     double* o = pts + CUT_POINT_DOUBLES * c;
-    const double px = rp[3 * c], py = rp[3 * c + 1], pz = rp[3 * c + 2];
+    // relative to the atoms' centre, as the N-body kernel takes the atoms
+    const double px = rp[3 * c] - at.cx, py = rp[3 * c + 1] - at.cy, pz = rp[3 * c + 2] - at.cz;
     const double wphi = wp[c] * pp;
     const double ux = wphi * np[3 * c], uy = wphi * np[3 * c + 1], uz = wphi * np[3 * c + 2];
     o[0] = px;
@@ -109,8 +110,11 @@ constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
 // vector: with a = the atom centre,
 //   |r_p - a|^2 = |r_p|^2 + |a|^2 - 2 a.r_p   and   2 (r_p - a).u_p = 2 r_p.u_p - 2 a.u_p,
 // the first in one add and three fused multiply-adds, the second in three, with -2a and |a|^2
-// held per atom.  The rounding error of the first is about (|r_p|^2 + |a|^2) eps, far below
-// 1e-10 times the squared distance (at least the smallest atom radius squared, as every cut
+// held per atom.  Both r_p and a are taken relative to the centre of the atoms' bounding box
+// (at.cx, at.cy, at.cz), so |r_p| and |a| are at most the molecule's half-diagonal plus an
+// atom radius wherever the molecule sits.  The rounding error of r^2 is about
+// (|r_p|^2 + |a|^2) eps: for a 65 A molecule (|r_p|, |a| < 115 A) below 3e-12 A^2, or 2e-12
+// of the smallest squared distance (an atom radius squared, at least 1.44 A^2, as every cut
 // point lies outside or on every ball).
 // partial[(chunk*n + i)*2 + {0,1}] = {S_F, S_D} of atom i over the chunk.
 __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const double* __restrict__ pts,
@@ -122,9 +126,9 @@ __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const dou
     double mx[NB_ATOMS], my[NB_ATOMS], mz[NB_ATOMS], aa[NB_ATOMS], sf[NB_ATOMS], sd[NB_ATOMS];
     double x0 = 0.0, y0 = 0.0, z0 = 0.0;
     if (a0 < at.n) {
-        x0 = at.xyzr[4 * a0];
-        y0 = at.xyzr[4 * a0 + 1];
-        z0 = at.xyzr[4 * a0 + 2];
+        x0 = at.xyzr[4 * a0] - at.cx;
+        y0 = at.xyzr[4 * a0 + 1] - at.cy;
+        z0 = at.xyzr[4 * a0 + 2] - at.cz;
     }
 #pragma unroll
     for (int k = 0; k < NB_ATOMS; ++k) {
@@ -132,9 +136,9 @@ __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const dou
         // an inactive slot evaluates the pairs of a far point, whose sums are discarded
         double x = x0 + 1e3 * k, y = y0, z = z0;
         if (k > 0 && a < at.n) {
-            x = at.xyzr[4 * a];
-            y = at.xyzr[4 * a + 1];
-            z = at.xyzr[4 * a + 2];
+            x = at.xyzr[4 * a] - at.cx;
+            y = at.xyzr[4 * a + 1] - at.cy;
+            z = at.xyzr[4 * a + 2] - at.cz;
         }
         mx[k] = -2.0 * x;
         my[k] = -2.0 * y;
@@ -319,13 +323,13 @@ int nbody_chunks(int n_atoms, int64_t ncut)
     return (int)want;
 }
 
-hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, double eps_out, int64_t ncut,
+hipError_t launch_edge_fields(hipStream_t s, const Grid& g, const Atoms& at, double eps_in, double eps_out, int64_t ncut,
                               const int64_t* cutkey, const uint32_t* code, const double* alpha,
                               const double* kcut, const double* x, const double* gb, const double* wp,
                               double* F, double* phip, double* pts, const double* rp, const double* np)
 {
     if (ncut == 0) return hipSuccess;
-    k_edge_fields<<<nblk(ncut, 256), 256, 0, s>>>(g, eps_in, eps_out, ncut, cutkey, code, alpha, kcut, x, gb,
+    k_edge_fields<<<nblk(ncut, 256), 256, 0, s>>>(g, at, eps_in, eps_out, ncut, cutkey, code, alpha, kcut, x, gb,
                                                    wp, F, phip, pts, rp, np);
     return hipGetLastError();
 }

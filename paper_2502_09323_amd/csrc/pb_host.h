@@ -171,6 +171,7 @@ struct pb_problem {
     pbk::TileShape ts;
     pbk::Coef cf;
     double lB, kD;
+    double ctr[3] = {0.0, 0.0, 0.0};   // centre of the atoms' bounding box (Atoms::cx, cy, cz)
     DevAlloc mem;
     // inputs
     double* xyzr = nullptr;
@@ -228,9 +229,16 @@ int pbi_build_continue(pb_problem* pb);
 int pbi_build_begin_sub(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz, const double* rad,
                         const double* chg, const int* off, pb_problem** out);
 void pbi_build_end(pb_problem* pb);
+// the cut edges counted by the first build phase (valid once its event has completed)
+int64_t pbi_build_counted_cuts(const pb_problem* pb);
 int pbi_event_done(pb_problem* pb);
 void pbi_problem_destroy(pb_problem* pb, bool sync);   // sync=false: its event has completed
 int pbi_energy_begin(pb_problem* pb, int finish_mixed);            // kernels + read-back
+// device bytes pbi_energy_begin allocates beyond what the problem holds
+size_t pbi_energy_bytes(const pb_problem* pb);
+// an upper estimate of the device bytes a mixed-form request holds at its peak (build,
+// solve and energy read-back); ncut < 0: not yet counted, estimated from the atom radii
+size_t pbi_request_bytes(const pb_params& p, int64_t na, const double* radius, int64_t ncut);
 int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* st);
 
 // mixed-form solve split in steps for the serving loop (all work on the problem's stream)
@@ -260,3 +268,13 @@ void* pbi_mg_rhs0(pb_problem* pb);
 void* pbi_mg_sol0(pb_problem* pb);
 // one V-cycle on a vector over the padded level-0 layout (host arrays of g.N doubles)
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host);
+
+// the problem's atoms as the kernels take them, with the centre of their bounding box
+inline pbk::Atoms pbi_atoms(const pb_problem* pb)
+{
+    pbk::Atoms at{(int)pb->na, pb->xyzr, pb->q};
+    at.cx = pb->ctr[0];
+    at.cy = pb->ctr[1];
+    at.cz = pb->ctr[2];
+    return at;
+}

@@ -57,6 +57,11 @@ struct Atoms {
     int n;
     const double* xyzr;  // 4 per atom: x, y, z, radius
     const double* q;
+    // a point near the molecule (the centre of the atoms' bounding box): kernels that form a
+    // squared distance in the expanded form |p|^2 + |a|^2 - 2 a.p take p and a relative to
+    // it, so that its rounding error does not grow with the distance of the molecule from
+    // the coordinate origin
+    double cx = 0.0, cy = 0.0, cz = 0.0;
 };
 
 struct Coef {          // what the operator needs on the device
@@ -196,7 +201,8 @@ int residual_blocks(const Grid& g);
 // a cut point as the N-body kernel reads it: r_p (3), the weighted normal u = w_p phi_p n_p
 // (3), F_p, |r_p|^2, 2 r_p.u, and one pad
 constexpr int CUT_POINT_DOUBLES = 10;
-hipError_t launch_edge_fields(hipStream_t s, const Grid& g, double eps_in, double eps_out,
+// the cut points are stored relative to the atoms' centre (at.cx, at.cy, at.cz)
+hipError_t launch_edge_fields(hipStream_t s, const Grid& g, const Atoms& at, double eps_in, double eps_out,
                               int64_t ncut, const int64_t* cutkey, const uint32_t* code,
                               const double* alpha, const double* kcut, const double* x,
                               const double* gb, const double* wp, double* F, double* phip,

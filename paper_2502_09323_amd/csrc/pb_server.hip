@@ -57,6 +57,8 @@ struct Active {
     pb_problem* pb;
     uint64_t id;
     double arrival;
+    size_t counted;     // bytes of the memory budget held for it (its device memory, read-back included)
+    int cancel;         // PB_ECANCELED or PB_ETIMEDOUT once cancelled: no more chunks, no read-back
     int launched;       // CG iterations launched for it
     int last_chunk;     // the last chunk that included it
     bool finished;      // converged, broke down or out of iterations; no more chunks
@@ -72,7 +74,8 @@ struct Pending {        // a problem being built or read back on the build strea
     uint64_t id;
     double arrival;
     int phase;          // 1 counting, 2 filling, 3 read-back
-    size_t reserved;    // budget reserved before the build knew its size
+    size_t counted;     // bytes of the memory budget held for it: an estimate until the build ends
+    int cancel;         // PB_ECANCELED or PB_ETIMEDOUT: dropped when its phase ends
 };
 
 struct Result {
@@ -96,7 +99,10 @@ struct pb_server {
     pb_ctx* ctx;     // batched iteration stream
     pb_ctx* bctx;    // build / energy stream
     int max_resident;
-    size_t budget = 0, in_use = 0;
+    size_t budget = 0, in_use = 0;   // in_use: sum of the `counted` bytes of all admitted requests
+    size_t in_use_peak = 0;
+    int64_t over_budget = 0;          // builds let past the budget (nothing else could free memory)
+    double timeout_s = 0.0;           // per request, from its arrival (0: none)
     std::deque<Request> queue;
     std::vector<Active> act;
     std::vector<Pending> pend;
@@ -188,15 +194,12 @@ int ensure_slot(pb_server* s, int k, int P)
     return PB_OK;
 }
 
-size_t estimate_bytes(const pb_params& p, int64_t na)
+// move a request's share of the budget count from `counted` to `bytes`
+void charge(pb_server* s, size_t& counted, size_t bytes)
 {
-    const int64_t S = row_stride(p.n[2]);
-    const int64_t N = (int64_t)p.n[0] * p.n[1] * S;
-    // node data of the mixed form (code, b, g, x64, seven FP32 vectors) + build scratch; the
-    // multigrid form keeps six FP32 vectors and 1/D on level 0 and about 1/7 of that again
-    // (with the FP64 coefficients) on the coarser levels
-    const size_t per_node = p.precond == PB_PRECOND_MG ? 80 : 60;
-    return (size_t)N * per_node + (size_t)na * 64 + ((size_t)1 << 20);
+    s->in_use = s->in_use - std::min(s->in_use, counted) + bytes;
+    counted = bytes;
+    s->in_use_peak = std::max(s->in_use_peak, s->in_use);
 }
 
 // wait for the chunk in slot k and record every member's state
@@ -261,6 +264,25 @@ void add_result(pb_server* s, uint64_t id, int code, const pb_energy_out* e, con
     s->done.push_back(r);
 }
 
+// something other than builds waiting for memory will release memory later
+bool others_progressing(const pb_server* s, const Pending* self)
+{
+    if (!s->act.empty()) return true;
+    for (const auto& p : s->pend)
+        if (&p != self && p.phase >= 2) return true;
+    return false;
+}
+
+// drop a pending problem (its phase event has completed) with a result code
+void drop_pending(pb_server* s, size_t i, int code)
+{
+    Pending& p = s->pend[i];
+    add_result(s, p.id, code, nullptr, nullptr);
+    charge(s, p.counted, 0);
+    pbi_problem_destroy(p.pb, false);
+    s->pend.erase(s->pend.begin() + (long)i);
+}
+
 // advance builds and read-backs whose last phase has finished (never blocks)
 int progress(pb_server* s)
 {
@@ -273,7 +295,27 @@ int progress(pb_server* s)
             continue;
         }
         int rc = PB_OK;
+        if (p.cancel) {
+            drop_pending(s, i, p.cancel);
+            continue;
+        }
         if (p.phase == 1) {
+            // the counts are known: hold the budget for the request's actual cut list before
+            // the build allocates it, or wait while other requests will free memory
+            const size_t need = pbi_request_bytes(p.pb->prm, p.pb->na, nullptr, pbi_build_counted_cuts(p.pb));
+            if (s->budget && need > s->budget) {
+                drop_pending(s, i, pbi_fail(PB_ENOMEM, "request %llu needs %zu bytes, budget %zu",
+                                            (unsigned long long)p.id, need, s->budget));
+                continue;
+            }
+            if (s->budget && need > p.counted && s->in_use - p.counted + need > s->budget) {
+                if (others_progressing(s, &p)) {
+                    ++i;
+                    continue;
+                }
+                ++s->over_budget;
+            }
+            charge(s, p.counted, need);
             rc = pbi_build_continue(p.pb);
             if (!rc)
                 rc = p.pb->prm.precond == PB_PRECOND_MG ? pbi_mg_begin(p.pb, p.pb->ctx->stream) : pbi_mixed_begin(p.pb);
@@ -285,13 +327,16 @@ int progress(pb_server* s)
             }
         } else if (p.phase == 2) {
             pbi_build_end(p.pb);
-            const size_t b = pb_problem_bytes(p.pb);
-            s->in_use = s->in_use - std::min(s->in_use, p.reserved) + b;
+            // from here on the count is exact: what the problem holds and what its read-back
+            // will allocate
+            charge(s, p.counted, pb_problem_bytes(p.pb) + pbi_energy_bytes(p.pb));
             Active a;
             memset(&a.snap, 0, sizeof a.snap);
             a.pb = p.pb;
             a.id = p.id;
             a.arrival = p.arrival;
+            a.counted = p.counted;
+            a.cancel = 0;
             a.launched = 0;
             a.pending = 0;
             a.seen = false;
@@ -312,14 +357,14 @@ int progress(pb_server* s)
                 s->prof_nb_n += 1;
             }
             add_result(s, p.id, st.status, &e, &st);
-            s->in_use -= std::min(s->in_use, pb_problem_bytes(p.pb));
+            charge(s, p.counted, 0);
             pbi_problem_destroy(p.pb, false);  // its read-back event has completed
             s->pend.erase(s->pend.begin() + (long)i);
             continue;
         }
         // a phase failed: report and drop the problem
         add_result(s, p.id, rc, nullptr, nullptr);
-        s->in_use -= std::min(s->in_use, std::max(p.reserved, pb_problem_bytes(p.pb)));
+        charge(s, p.counted, 0);
         pb_problem_free(p.pb);
         s->pend.erase(s->pend.begin() + (long)i);
     }
@@ -335,17 +380,41 @@ int retire(pb_server* s)
             ++i;
             continue;
         }
-        const int rc = pbi_energy_begin(a.pb, 1);
+        const int rc = a.cancel ? a.cancel : pbi_energy_begin(a.pb, 1);
         if (rc) {
             add_result(s, a.id, rc, nullptr, nullptr);
-            s->in_use -= std::min(s->in_use, pb_problem_bytes(a.pb));
-            pb_problem_free(a.pb);
+            charge(s, a.counted, 0);
+            pb_problem_free(a.pb);   // no chunk in flight touches it
         } else {
-            s->pend.push_back(Pending{a.pb, a.id, a.arrival, 3, 0});
+            s->pend.push_back(Pending{a.pb, a.id, a.arrival, 3, a.counted, 0});
         }
         s->act.erase(s->act.begin() + (long)i);
     }
     return PB_OK;
+}
+
+// requests past their time limit: queued ones complete at once, admitted ones are cancelled
+// (an admitted problem is released once no launch in flight touches it)
+void expire(pb_server* s)
+{
+    if (s->timeout_s <= 0.0) return;
+    const double t = s->now();
+    for (size_t i = 0; i < s->queue.size();) {
+        const Request& q = s->queue[i];
+        if (t - q.arrival > s->timeout_s) {
+            add_result(s, q.id, PB_ETIMEDOUT, nullptr, nullptr);
+            s->queue.erase(s->queue.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+    for (auto& a : s->act)
+        if (!a.cancel && t - a.arrival > s->timeout_s) {
+            a.cancel = PB_ETIMEDOUT;
+            a.finished = true;
+        }
+    for (auto& p : s->pend)
+        if (!p.cancel && t - p.arrival > s->timeout_s) p.cancel = PB_ETIMEDOUT;
 }
 
 int building(const pb_server* s)
@@ -362,7 +431,9 @@ int admit(pb_server* s)
            (int)s->act.size() + building(s) < s->max_resident) {
         Request& q = s->queue.front();
         if (s->budget && q.est_bytes > s->budget) {
-            add_result(s, q.id, PB_ENOMEM, nullptr, nullptr);
+            add_result(s, q.id, pbi_fail(PB_ENOMEM, "request %llu: estimated %zu bytes, budget %zu",
+                                         (unsigned long long)q.id, q.est_bytes, s->budget),
+                       nullptr, nullptr);
             s->queue.pop_front();
             continue;
         }
@@ -378,8 +449,9 @@ int admit(pb_server* s)
             s->queue.pop_front();
             continue;
         }
-        s->in_use += q.est_bytes;
-        s->pend.push_back(Pending{pb, q.id, q.arrival, 1, q.est_bytes});
+        size_t counted = 0;
+        charge(s, counted, q.est_bytes);
+        s->pend.push_back(Pending{pb, q.id, q.arrival, 1, counted, 0});
         s->queue.pop_front();
     }
     return PB_OK;
@@ -580,7 +652,7 @@ int pb_submit(pb_server* s, const pb_params* prm, int64_t n_atoms, const double*
     q.prm.bc_values = nullptr;
     q.id = request_id;
     q.arrival = arrival_time_s;
-    q.est_bytes = estimate_bytes(*prm, n_atoms);
+    q.est_bytes = pbi_request_bytes(*prm, n_atoms, radius, -1);
     s->queue.push_back(std::move(q));
     return PB_OK;
 }
@@ -593,6 +665,7 @@ int pb_server_step(pb_server* s, int32_t* n_active, int32_t* n_queued)
     double t = s->now(), t2;
     int rc = complete_slot(s, k);  // the slot about to be reused holds the older chunk
     t2 = s->now(); s->t_wait += t2 - t; t = t2;
+    expire(s);
     if (!rc) rc = progress(s);
     if (!rc) rc = retire(s);
     t2 = s->now(); s->t_retire += t2 - t; t = t2;
@@ -634,6 +707,45 @@ int pb_poll(pb_server* s, uint64_t* ids, pb_energy_out* results, pb_solve_stats*
     }
     s->done.erase(s->done.begin(), s->done.begin() + n);
     *n_done = n;
+    return PB_OK;
+}
+
+int pb_cancel(pb_server* s, uint64_t request_id)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    for (size_t i = 0; i < s->queue.size(); ++i)
+        if (s->queue[i].id == request_id) {
+            add_result(s, request_id, PB_ECANCELED, nullptr, nullptr);
+            s->queue.erase(s->queue.begin() + (long)i);
+            return PB_OK;
+        }
+    for (auto& a : s->act)
+        if (a.id == request_id && !a.cancel) {
+            a.cancel = PB_ECANCELED;
+            a.finished = true;
+            return PB_OK;
+        }
+    for (auto& p : s->pend)
+        if (p.id == request_id && !p.cancel) {
+            p.cancel = PB_ECANCELED;
+            return PB_OK;
+        }
+    return pbi_fail(PB_EINVAL, "request %llu is not queued or running", (unsigned long long)request_id);
+}
+
+int pb_server_set_timeout(pb_server* s, double seconds)
+{
+    if (!s || !(seconds >= 0.0) || !std::isfinite(seconds)) return pbi_fail(PB_EINVAL, "bad argument");
+    s->timeout_s = seconds;
+    return PB_OK;
+}
+
+int pb_server_memory(const pb_server* s, size_t* in_use, size_t* peak, int64_t* over_budget)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    if (in_use) *in_use = s->in_use;
+    if (peak) *peak = s->in_use_peak;
+    if (over_budget) *over_budget = s->over_budget;
     return PB_OK;
 }
 

@@ -78,3 +78,6 @@ def test_null_arguments_are_rejected_without_a_gpu(lib):
     assert lib.pb_grid_energy(None, C.byref(e)) == B.PB_EINVAL
     assert lib.pb_grid_energy(None, None) == B.PB_EINVAL
     assert b"NULL" in lib.pb_last_error()
+    assert lib.pb_cancel(None, 0) == B.PB_EINVAL
+    assert lib.pb_server_set_timeout(None, 1.0) == B.PB_EINVAL
+    assert lib.pb_server_memory(None, None, None, None) == B.PB_EINVAL

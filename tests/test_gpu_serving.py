@@ -134,3 +134,87 @@ def test_future_arrivals_wait(ctxs):
     for i in range(3):
         assert served[i]["code"] == 0
         assert served[i]["done_s"] >= arrivals[i]
+
+
+def test_long_stream_holds_the_budget_and_returns_it(ctxs):
+    """A stream eight times longer than the resident limit under a budget of a few requests:
+    the accounted memory never exceeds the budget, comes back to zero when the stream is done,
+    and waiting for memory changes no result."""
+    import torch
+
+    budget = 48 << 20
+    main_b = B.Context(0, hbm_budget_bytes=budget)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    reqs = small_stream(n=24, seed=13)
+    srv = B.Server(main_b, side, max_resident=3)
+    served = run_server(srv, reqs, timeout_s=120.0)
+    mem = srv.memory()
+    srv.close()
+    print("serving memory:", mem, flush=True)
+    assert all(served[i]["code"] == 0 for i in range(len(reqs)))
+    assert 0 < mem["peak"] <= budget
+    assert mem["in_use"] == 0 and mem["over_budget"] == 0
+    for i in (0, 11, 23):
+        mol, grid = reqs[i]
+        alone = B.solve(mol, replace(grid, tile_planes=32), ctxs[0])
+        assert served[i]["e_pol"] == alone["e_pol"] and served[i]["e_ion"] == alone["e_ion"]
+    main_b.close()
+    side.close()
+
+
+def test_cancel_and_time_limit(ctxs):
+    main, side = ctxs
+    reqs = small_stream(n=6, seed=17)
+    srv = B.Server(main, side, max_resident=2)
+    for i, (mol, grid) in enumerate(reqs):
+        srv.submit(mol, grid, i)
+    srv.step()                      # admits requests 0 and 1 (builds start)
+    srv.cancel(0)                   # being built
+    srv.cancel(5)                   # still queued
+    for _ in range(3):
+        srv.step()
+    srv.cancel(1)                   # being built, resident or read back
+    with pytest.raises(B.PbError) as e:
+        srv.cancel(1)               # already cancelled
+    assert e.value.code == B.PB_EINVAL
+    with pytest.raises(B.PbError):
+        srv.cancel(99)              # unknown
+    out = {}
+    t0 = time.time()
+    while len(out) < len(reqs):
+        srv.step()
+        for r in srv.poll():
+            out[r["id"]] = r
+        assert time.time() - t0 < 60, "serving loop did not finish"
+    mem = srv.memory()
+    srv.close()
+    assert [out[i]["code"] for i in range(6)] == [B.PB_ECANCELED, B.PB_ECANCELED, 0, 0, 0, B.PB_ECANCELED]
+    assert mem["in_use"] == 0
+    mol, grid = reqs[3]
+    alone = B.solve(mol, replace(grid, tile_planes=32), main)
+    assert out[3]["e_pol"] == alone["e_pol"] and out[3]["iters"] == alone["iters"]
+    # a time limit: requests that arrived a second ago and requests already admitted expire
+    srv = B.Server(main, side, max_resident=2)
+    t = srv.now()
+    for i, (mol, grid) in enumerate(reqs[:4]):
+        srv.submit(mol, grid, i, t if i < 2 else t - 1.0)
+    srv.set_timeout(30.0)
+    srv.step()                      # admits requests 0 and 1
+    srv.set_timeout(1e-6)
+    out = {}
+    t0 = time.time()
+    while len(out) < 4:
+        srv.step()
+        for r in srv.poll():
+            out[r["id"]] = r
+        assert time.time() - t0 < 60, "serving loop did not finish"
+    mem = srv.memory()
+    srv.close()
+    assert all(out[i]["code"] == B.PB_ETIMEDOUT for i in range(4))
+    assert mem["in_use"] == 0
+    with pytest.raises(B.PbError):
+        srv2 = B.Server(main, side, max_resident=2)
+        try:
+            srv2.set_timeout(-1.0)
+        finally:
+            srv2.close()
