@@ -216,6 +216,27 @@ int pb_binding_ddg(const pb_energy_out* complex_e, const pb_energy_out* part1, c
  * solved), PB_EDEVICE. */
 int pb_energy(pb_problem* pb, pb_energy_out* out, double* phi_reac_per_atom);
 
+/* pb_energy for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and results, with no
+ * device, pinned or pageable allocation.  The read-back's buffers (per cut edge: flux, surface
+ * potential and the N-body point, 96 bytes; per atom: the N-body partial sums, Coulomb and
+ * reaction potentials; the sums) live in one static device array of
+ * pb_energy_noalloc_limit() bytes (128 MiB), which every device the library runs on holds
+ * until the process ends; its address is taken when the first context on the device is
+ * created.  When the N-body sum in pb_energy's chunking does not fit, fewer chunks are used
+ * (only the order of the FP64 additions changes).  The energies go to *out, the reaction
+ * potentials (kT/e, optional) to the caller's host array phi_reac_per_atom[n_atoms]; the
+ * call returns when they are there.  Unlike pb_energy it leaves nothing with the problem, so
+ * pb_copy_cut's F and phip stay those of the last pb_energy.  Every call on one device shares
+ * the array: calls that overlap on one device (other host threads, other streams) race and
+ * must be serialized by the caller.
+ * Errors: PB_EINVAL (NULL argument, not solved), PB_ENOMEM (the problem needs more than the
+ * limit even in one chunk: about 1.3M cut edges; use pb_energy), PB_EDEVICE. */
+int pb_energy_noalloc(pb_problem* pb, pb_energy_out* out, double* phi_reac_per_atom);
+
+/* Size in bytes of pb_energy_noalloc's static scratch array. */
+size_t pb_energy_noalloc_limit(void);
+
 /* Grid energy after pb_solve (Sect. 3.3, electrostatic energy), in kT: half the sum over
  * the interior grid nodes of the charge deposited there (trilinear weights of each atom's
  * cell, the right-hand side's charge term) times the potential there; charge that the

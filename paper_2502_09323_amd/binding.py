@@ -27,7 +27,8 @@ EXPORTED = [
     "pb_server_create", "pb_server_now", "pb_submit", "pb_server_step", "pb_poll", "pb_server_destroy",
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
     "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg", "pb_get_energy_profile", "pb_server_profile_energy",
-    "pb_grid_energy", "pb_cancel", "pb_server_set_timeout", "pb_server_memory",
+    "pb_grid_energy", "pb_cancel", "pb_server_set_timeout", "pb_server_memory", "pb_energy_noalloc",
+    "pb_energy_noalloc_limit",
 ]
 
 
@@ -97,6 +98,9 @@ def load(path: str = LIB_PATH):
     L.pb_build_coeffs.argtypes = [P, C.POINTER(PbParams), i64, P, P, P, C.POINTER(P)]
     L.pb_solve.argtypes = [P, C.POINTER(PbSolveStats)]
     L.pb_energy.argtypes = [P, C.POINTER(PbEnergyOut), P]
+    L.pb_energy_noalloc.argtypes = [P, C.POINTER(PbEnergyOut), P]
+    L.pb_energy_noalloc_limit.argtypes = []
+    L.pb_energy_noalloc_limit.restype = C.c_size_t
     L.pb_copy_potential.argtypes = [P, P]
     L.pb_grid_energy.argtypes = [P, C.POINTER(C.c_double)]
     L.pb_problem_free.argtypes = [P]
@@ -277,6 +281,19 @@ class Problem:
         out = PbEnergyOut()
         pa = np.zeros(max(self.n_atoms, 1)) if per_atom else None
         rc = _lib.pb_energy(self.h, C.byref(out), _ptr(pa))
+        if rc != PB_OK:
+            raise _err(rc)
+        d = {k: getattr(out, k) for k, _ in PbEnergyOut._fields_}
+        if per_atom:
+            d["phi_reac"] = pa[: self.n_atoms]
+        return d
+
+    def energy_noalloc(self, per_atom: bool = False) -> dict:
+        """pb_energy without any allocation (the read-back's buffers in the library's static
+        scratch array); per-atom potentials go to a host array allocated here, before the call."""
+        out = PbEnergyOut()
+        pa = np.zeros(max(self.n_atoms, 1)) if per_atom else None
+        rc = _lib.pb_energy_noalloc(self.h, C.byref(out), _ptr(pa))
         if rc != PB_OK:
             raise _err(rc)
         d = {k: getattr(out, k) for k, _ in PbEnergyOut._fields_}

@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["pb_api.hip", "pb_build.hip", "pb_solve.hip", "pb_energy.hip", "pb_server.hip", "pb_refine.hip", "pb_mg.hip"]
+SRC = ["pb_api.hip", "pb_build.hip", "pb_solve.hip", "pb_energy.hip", "pb_server.hip", "pb_refine.hip", "pb_mg.hip",
+       "pb_noalloc.hip"]
 LIB = os.path.join(HERE, "libpb.so")
 
 

@@ -491,6 +491,11 @@ int pb_ctx_create(int device, void* hip_stream, pb_alloc_fn alloc, pb_free_fn fr
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(PB_EINVAL, "device %d out of range (%d devices)", device, ndev);
     HIPCHK(hipSetDevice(device));
+    {
+        // the allocation-free energy read-back's scratch array: its address on this device
+        const int rc = pbi_scratch_setup(device);
+        if (rc) return rc;
+    }
     pb_ctx* c = new pb_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;

@@ -234,6 +234,9 @@ int64_t pbi_build_counted_cuts(const pb_problem* pb);
 int pbi_event_done(pb_problem* pb);
 void pbi_problem_destroy(pb_problem* pb, bool sync);   // sync=false: its event has completed
 int pbi_energy_begin(pb_problem* pb, int finish_mixed);            // kernels + read-back
+// take the device address of the allocation-free read-back's scratch array on `device` (the
+// current device), once per device (pb_noalloc.hip)
+int pbi_scratch_setup(int device);
 // device bytes pbi_energy_begin allocates beyond what the problem holds
 size_t pbi_energy_bytes(const pb_problem* pb);
 // an upper estimate of the device bytes a mixed-form request holds at its peak (build,
