@@ -40,9 +40,11 @@ def build() -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        # PB_ORACLE_LIB names another build of oracle.c (the sanitizer test's)
+        path = os.environ.get("PB_ORACLE_LIB") or _SO
+        if path == _SO and not os.path.exists(_SO):
             build()
-        L = C.CDLL(_SO)
+        L = C.CDLL(path)
         P = C.c_void_p
         i64, i32, d = C.c_int64, C.c_int32, C.c_double
         L.orc_constants.argtypes = [d, d, d, P, P]

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpb.so")
+# PB_LIB_PATH names another build of the library (the host-code sanitizer test's)
+LIB_PATH = os.environ.get("PB_LIB_PATH") or os.path.join(_HERE, "libpb.so")
 
 PB_OK, PB_EINVAL, PB_ENOMEM, PB_ENOCONV, PB_EBREAKDOWN, PB_EDEVICE = 0, -1, -2, -3, -4, -5
 PB_ECANCELED, PB_ETIMEDOUT = -6, -7
