@@ -102,7 +102,8 @@ typedef struct {
                                reductions: a problem gives bit-identical results with the
                                same value alone or in the serving loop. */
     int32_t refine;         /* 0: uniform grid.  2: de-refinement toward the box (the
-                               paper's treatment of the box, Sect. 4.1 on BCs, with one
+                               paper's treatment of the box, Sect. 3.4, exploiting
+                               de-refinement for more efficient BCs, with one
                                level): the grid given is the coarse far field, and every
                                coarse cell that meets the solute's extent (atom centres -/+
                                radii) widened by refine_shell_A on all three axes is split,
@@ -195,7 +196,7 @@ typedef struct {
     double t_energy_s;      /* wall time of pb_energy */
 } pb_energy_out;
 
-/* Binding energy of a complex from its two parts (paper Sect. 5.2, binding energy
+/* Binding energy of a complex from its two parts (paper Sect. 6.2, binding energy
  * calculation): ddG = dG_complex - dG_1 - dG_2, with dG the total electrostatic energy
  * e_coul + e_pol + e_ion (eq. energyPart), and the same difference for each component.  The
  * three energies must come from solves on the same grid (box, spacing and origin), so that
@@ -342,8 +343,9 @@ size_t pb_problem_bytes(const pb_problem* pb);
 
 /* A serving loop for a stream of requests in the mixed form (the paper treats one molecule
  * at a time; solving many molecules, e.g. for binding free energies over complexes and
- * their parts, Sect. 5.2, is the workload this serves).  Iteration kernels run on ctx's
- * stream, coefficient builds and energy read-backs on build_ctx's stream (same device).
+ * their parts, Sect. 6.2 (binding energy calculation), is the workload this serves).
+ * Iteration kernels run on ctx's stream, coefficient builds and energy read-backs on
+ * build_ctx's stream (same device).
  * Requests are admitted first-come first-served once arrived, while at most max_resident
  * problems are resident and ctx's hbm_budget_bytes (if non-zero) is not exceeded; all
  * resident problems advance together, 16 CG iterations per batched chunk.  Requests with

@@ -63,7 +63,7 @@ def refine_cells(grid, rp: np.ndarray, delta: float, brick: int) -> np.ndarray:
 
 
 def refine_cells_box(grid, lo, hi, delta: float, brick: int) -> np.ndarray:
-    """De-refinement toward the box (the paper's Sect. 4.1 on BCs): every coarse cell that
+    """De-refinement toward the box (the paper's Sect. 3.4, exploiting de-refinement for more efficient BCs): every coarse cell that
     meets the box [lo - delta, hi + delta] on all three axes is split (lo, hi: the solute's
     extent, atom centres -/+ radii), rounded up to aligned bricks like refine_cells; the rest
     of the domain, out to the box where the null Dirichlet values are applied, stays coarse."""

@@ -1,4 +1,4 @@
-"""Binding energies ddG = dG_complex - dG_1 - dG_2 (paper Sect. 5.2): CPU pins.
+"""Binding energies ddG = dG_complex - dG_1 - dG_2 (paper Sect. 6.2, binding energy calculation): CPU pins.
 
 * the Coulomb part: the oracle's pair sum is additive, so ddG_coul is exactly the sum over
   the pairs that straddle the two parts, and for two point charges it is the closed form

@@ -8,7 +8,7 @@ of the salt contribution built on it.
 - A charge on a node sees only that node.
 - Kirkwood sphere with the exact box values at both ionic strengths: the polarization energy
   of a central charge does not depend on the salt, so G(I) - G(0) is the closed-form ionic
-  energy of Sect. 5.1.1 up to a discretization error that falls at second order in h.
+  energy of Sect. 6.1.1 (the Kirkwood sphere) up to a discretization error that falls at second order in h.
 - A molecule: G(I) - G(0) is the change of the solvation energy with the salt, and agrees
   with the same change from the surface read-back (E_pol + E_ion at I, minus E_pol at 0) to
   within the two methods' discretization errors.

@@ -38,7 +38,7 @@ def _golden():
 
 
 def born_kirkwood(lB, kD, R=2.0, q=1.0, ei=2.0, eo=80.0):
-    """Closed forms of Sect. 5.1.1 in reduced units (times lB -> kT)."""
+    """Closed forms of Sect. 6.1.1 (the Kirkwood sphere) in reduced units (times lB -> kT)."""
     e_pol = 0.5 * (1.0 / eo - 1.0 / ei) * q * q / R * lB
     e_ion = -0.5 * q * q / eo * kD / (1.0 + kD * R) * lB
     return e_pol, e_ion
