@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -179,6 +180,9 @@ class Context:
         if rc != PB_OK:
             raise _err(rc)
         self.h = h
+        # problems and servers made on this context: released before it, whatever order the
+        # interpreter collects them in
+        self._users = weakref.WeakSet()
 
     def set_profiling(self, on: bool):
         rc = _lib.pb_ctx_set_profiling(self.h, 1 if on else 0)
@@ -194,6 +198,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for u in list(getattr(self, "_users", ())):
+                u.close()
             _lib.pb_ctx_destroy(self.h)
             self.h = None
 
@@ -265,6 +271,7 @@ class Problem:
         if rc != PB_OK:
             raise _err(rc)
         self.h = h
+        ctx._users.add(self)
 
     @property
     def shape(self):
@@ -426,6 +433,8 @@ class Server:
         if rc != PB_OK:
             raise _err(rc)
         self.h = h
+        ctx._users.add(self)
+        build_ctx._users.add(self)
 
     def now(self) -> float:
         return float(_lib.pb_server_now(self.h))

@@ -11,6 +11,7 @@
 // classification is bit-identical to the plain definition x = origin + h*i,
 // d2 = (dx*dx + dy*dy) + dz*dz, solute iff d2 < R*R.
 #include "pb_internal.h"
+#include "pb_stencil.h"
 
 #include <cmath>
 
@@ -577,8 +578,7 @@ __global__ void __launch_bounds__(256) k_bc_user(Grid g, const double* full, dou
 
 __device__ __forceinline__ double edgeK(uint32_t c, int ax, const double* ck, const Coef& cf)
 {
-    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
-    return (c & C_SOLUTE) ? cf.kin : cf.kout;
+    return stencil::edgeK(c, ax, ck, cf.kin, cf.kout);
 }
 
 __global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code, const double* ck,
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code,
     K[3] = edgeK(c, 1, ck, cf);
     K[4] = edgeK(code[e - 1], 2, ck, cf);
     K[5] = edgeK(c, 2, ck, cf);
-    double D = K[0] + K[1] + K[2] + K[3] + K[4] + K[5] + ((c & C_SOLUTE) ? 0.0 : cf.mass);
+    const double D = stencil::diag_sum(K[0], K[1], K[2], K[3], K[4], K[5], (c & C_SOLUTE) ? 0.0 : cf.mass);
     double lift = 0.0;
     for (int q = 0; q < 6; ++q)
         if (code[nb[q]] & C_BOX) lift += K[q] * gb[nb[q]];
@@ -792,10 +792,7 @@ __global__ void __launch_bounds__(256) k_export_coeffs(Grid g, const uint32_t* c
     if (diag || b) {
         double D = 0.0, bv = 0.0;
         if (!(c & C_BOX)) {
-            const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-            D = edgeK(code[e - sx], 0, ck, cf) + edgeK(c, 0, ck, cf) + edgeK(code[e - sy], 1, ck, cf) +
-                edgeK(c, 1, ck, cf) + edgeK(code[e - 1], 2, ck, cf) + edgeK(c, 2, ck, cf) +
-                ((c & C_SOLUTE) ? 0.0 : cf.mass);
+            D = stencil::node_diag(g, code, ck, cf.kin, cf.kout, cf.mass, e);
             bv = rhs[e];
         }
         if (diag) diag[u] = D;

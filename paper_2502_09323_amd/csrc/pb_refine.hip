@@ -33,6 +33,7 @@
 
 #include "pb_host.h"
 #include "pb_internal.h"
+#include "pb_stencil.h"
 
 using namespace pbk;
 
@@ -155,8 +156,7 @@ __global__ void __launch_bounds__(256) k_cells_from_bricks(const uint8_t* bf, in
 
 __device__ __forceinline__ double edgeK(uint32_t c, int ax, const double* ck, const Coef& cf)
 {
-    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
-    return (c & C_SOLUTE) ? cf.kin : cf.kout;
+    return stencil::edgeK(c, ax, ck, cf.kin, cf.kout);
 }
 
 // coarse grid: K of the +axis edges and the lumped term from the unrefined incident cells;

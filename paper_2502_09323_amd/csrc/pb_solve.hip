@@ -25,6 +25,7 @@
 // that each XCD gets one contiguous range of tiles, which keeps the halo rows of
 // neighbouring tiles in the same L2.
 #include "pb_internal.h"
+#include "pb_stencil.h"
 
 #include <cmath>
 #include <type_traits>
@@ -32,6 +33,8 @@
 namespace pbk {
 
 namespace {
+
+using namespace stencil;
 
 // sum of NV doubles over a block of NW waves; every thread gets the totals (fixed order)
 template <int NV, int NW = 4>
@@ -57,36 +60,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh)
 }
 
 template <typename T>
-__device__ __forceinline__ T eK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
-{
-    if (c & (C_CUTX << ax)) return ck[3 * (int64_t)(c >> C_SLOT_SHIFT) + ax];
-    return (c & C_SOLUTE) ? kin : kout;
-}
-
-// K of the edge from a node along +axis without a branch: a cut edge reads its WHA value
-// from the compact table, an edge inside one medium takes h*eps of that medium.  The table
-// is always read (slot 0 for uncut edges) and the result is blended arithmetically, so the
-// load is never turned into a branch whose join would wait on every load in flight.
-__device__ __forceinline__ int64_t ck_index(uint32_t c, int ax)
-{
-    return (c & (C_CUTX << ax)) ? 3 * (int64_t)(c >> C_SLOT_SHIFT) + ax : 0;
-}
-
-template <typename T>
-__device__ __forceinline__ T ck_blend(T v, uint32_t c, int ax, T kin, T kout)
-{
-    const T base = (c & C_SOLUTE) ? kin : kout;
-    const T m = (c & (C_CUTX << ax)) ? (T)1 : (T)0;
-    return v * m + base * ((T)1 - m);
-}
-
-template <typename T>
-__device__ __forceinline__ T edgeK(uint32_t c, int ax, const T* __restrict__ ck, T kin, T kout)
-{
-    return ck_blend(ck[ck_index(c, ax)], c, ax, kin, kout);
-}
-
-template <typename T>
 struct Old {   // the old vectors of one node, from which its new z and p follow
     T z, w, p;
     uint32_t c;
@@ -96,26 +69,6 @@ template <typename T>
 struct K3 {    // coefficients of the +x, +y, +z edges of a node
     T x, y, z;
 };
-
-// diagonal of the operator at a node from its six edge coefficients and the ionic term, in
-// one fixed order: every kernel that needs D sums it this way, so all agree bit for bit
-template <typename T>
-__device__ __forceinline__ T diag_sum(T kxm, T kxp, T kym, T kyp, T kzm, T kzp, T mt)
-{
-    return ((kxm + kxp) + (kym + kyp)) + ((kzm + kzp) + mt);
-}
-
-template <typename T>
-__device__ __forceinline__ T node_diag(const Grid& g, const uint32_t* __restrict__ code, const T* __restrict__ ck,
-                                       T kin, T kout, T mass, int64_t e)
-{
-    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    const uint32_t c = code[e];
-    return diag_sum(edgeK(code[e - sx], 0, ck, kin, kout), edgeK(c, 0, ck, kin, kout),
-                    edgeK(code[e - sy], 1, ck, kin, kout), edgeK(c, 1, ck, kin, kout),
-                    edgeK(code[e - 1], 2, ck, kin, kout), edgeK(c, 2, ck, kin, kout),
-                    (c & C_SOLUTE) ? (T)0 : mass);
-}
 
 // element e of an array through a 32-bit byte offset from a uniform base (the grid is limited
 // so that every offset fits), which lets every load and store use one offset register
@@ -526,12 +479,12 @@ __device__ __forceinline__ void ru_residual_body(const Grid& g, const uint32_t* 
         float out = 0.0f;
         if (!(c & C_BOX)) {
             const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-            const double Kxm = eK(code[e - sx], 0, ck, cf.kin, cf.kout);
-            const double Kxp = eK(c, 0, ck, cf.kin, cf.kout);
-            const double Kym = eK(code[e - sy], 1, ck, cf.kin, cf.kout);
-            const double Kyp = eK(c, 1, ck, cf.kin, cf.kout);
-            const double Kzm = eK(code[e - 1], 2, ck, cf.kin, cf.kout);
-            const double Kzp = eK(c, 2, ck, cf.kin, cf.kout);
+            const double Kxm = edgeK(code[e - sx], 0, ck, cf.kin, cf.kout);
+            const double Kxp = edgeK(c, 0, ck, cf.kin, cf.kout);
+            const double Kym = edgeK(code[e - sy], 1, ck, cf.kin, cf.kout);
+            const double Kyp = edgeK(c, 1, ck, cf.kin, cf.kout);
+            const double Kzm = edgeK(code[e - 1], 2, ck, cf.kin, cf.kout);
+            const double Kzp = edgeK(c, 2, ck, cf.kin, cf.kout);
             const double D = ((Kxm + Kxp) + (Kym + Kyp)) + ((Kzm + Kzp) + ((c & C_SOLUTE) ? 0.0 : cf.mass));
             const double ax = D * x[e] - (Kxm * x[e - sx] + Kxp * x[e + sx] + Kym * x[e - sy] +
                                           Kyp * x[e + sy] + Kzm * x[e - 1] + Kzp * x[e + 1]);
