@@ -1,0 +1,166 @@
+"""GPU parity against the FP64 oracle at the full sizes of the benchmark workloads.
+
+The oracle's values were computed once on the CPU by ``tests/golden/make_full_size.py``
+(which calls only ``oracle/`` and the seeded input generators) and stored as JSON: the
+energies of the energy read-back (Sect. 3.3), SHA-256 digests of the solute flags, cut-edge
+keys and owners, and seeded samples of per-atom, per-cut-edge and per-node values.
+
+Bar: integer results (flags, keys, owners, counts) bit-exact; FP64 solves 1e-10 relative on
+the energies; the mixed form (FP32 CG with FP64 reliable updates) 1e-6; sampled values as in
+the small-size parity tests (coefficients 1e-13 relative, crossing geometry 1e-12, area
+weights 1e-12 relative to the largest, fluxes 1e-8, potentials 1e-9 of their largest value).
+The 385^3 problem is compared through the same launch configuration ``bench.py --workload
+c4`` times; the serving-stream sample goes through the serving loop at the benchmark's
+tolerances."""
+import hashlib
+import json
+import os
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import bench
+from paper_2502_09323_amd import binding as B
+from paper_2502_09323_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+E_TOL64 = 1e-10
+E_TOL_MIXED = 1e-6
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    B.load()
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def check_energies(en, ref, tol, keys=("e_pol", "e_ion", "e_coul")):
+    for k in keys:
+        r = ref["energy"][k]
+        assert abs(en[k] - r) <= tol * abs(r), (k, en[k], r, abs(en[k] - r) / abs(r))
+
+
+def check_build(pb, ref, coeffs=True):
+    cut = pb.cut()
+    assert cut["key"].shape[0] == ref["n_cut"]
+    assert sha(cut["key"]) == ref["sha256_cut_key"], "cut-edge keys differ"
+    assert sha(cut["owner"]) == ref["sha256_cut_owner"], "cut-edge owners differ"
+    ci = np.asarray(ref["cuts"]["idx"], dtype=np.int64)
+    c = ref["cuts"]
+    assert np.max(np.abs(cut["alpha"][ci] - np.asarray(c["alpha"])), initial=0) <= 1e-13
+    assert np.max(np.abs(cut["rp"][ci] - np.asarray(c["rp"])), initial=0) <= 1e-12
+    assert np.max(np.abs(cut["np"][ci] - np.asarray(c["np"])), initial=0) <= 1e-12
+    wp = np.asarray(c["wp"])
+    assert np.max(np.abs(cut["wp"][ci] - wp), initial=0) <= 1e-12 * max(np.max(wp, initial=0), 1.0)
+    if coeffs:
+        co = pb.coeffs()
+        assert sha(co["solute"]) == ref["sha256_solute"], "solute flags differ"
+        ijk = np.asarray(ref["nodes"]["ijk"])
+        d = co["diag"][ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+        assert np.max(np.abs(d - np.asarray(ref["nodes"]["diag"])) / np.asarray(ref["nodes"]["diag"])) <= 1e-13
+        b = co["rhs"][ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+        rb = np.asarray(ref["nodes"]["rhs"])
+        assert np.max(np.abs(b - rb)) <= 1e-13 * max(np.max(np.abs(rb)), 1e-300)
+        del co
+    return cut
+
+
+def check_solution(pb, ref, cut, tol_phi, tol_f):
+    ci = np.asarray(ref["cuts"]["idx"], dtype=np.int64)
+    assert np.max(np.abs(cut["F"][ci] - np.asarray(ref["cuts"]["F"])), initial=0) <= tol_f * ref["F_absmax"]
+    phi = pb.potential()
+    ijk = np.asarray(ref["nodes"]["ijk"])
+    got = phi[ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+    assert np.max(np.abs(got - np.asarray(ref["nodes"]["phi"]))) <= tol_phi * ref["phi_absmax"]
+
+
+def test_c4_385_full_size_parity(ctx):
+    """60,000 atoms, 385^3 nodes (56.2M unknowns): the multigrid and Jacobi FP64 solves at
+    1e-10, the mixed multigrid solve of the benchmark at 1e-6, every cut key bit-exact."""
+    ref = golden("c4_oracle.json")
+    mol, grid = I.large_c4()
+    print("C4 parity: FP64 multigrid, rtol 1e-12", flush=True)
+    pb = B.Problem(ctx, mol, replace(grid, precision=I.FP64, precond=I.MG, rtol=1e-12))
+    check_build(pb, ref)
+    st = pb.solve()
+    assert st["status"] == 0
+    en = pb.energy(per_atom=True)
+    check_energies(en, ref, E_TOL64)
+    assert abs(en["q_pol_total"] - ref["energy"]["q_pol_total"]) <= 1e-10 * abs(ref["energy"]["q_pol_total"])
+    assert abs(en["area_total"] - ref["energy"]["area_total"]) <= 1e-12 * ref["energy"]["area_total"]
+    ai = np.asarray(ref["atoms"]["idx"], dtype=np.int64)
+    assert np.max(np.abs(en["phi_reac"][ai] - np.asarray(ref["atoms"]["phi_reac"]))) <= 1e-9 * ref["phi_reac_absmax"]
+    cut = pb.cut(fields=True)
+    check_solution(pb, ref, cut, 1e-9, 1e-8)
+    pb.close()
+    print("C4 parity: FP64 Jacobi, rtol 1e-11", flush=True)
+    pb = B.Problem(ctx, mol, replace(grid, precision=I.FP64, precond=I.JACOBI, rtol=1e-11))
+    st = pb.solve()
+    assert st["status"] == 0
+    check_energies(pb.energy(), ref, E_TOL64)
+    pb.close()
+    print("C4 parity: mixed multigrid at the benchmark's tolerances", flush=True)
+    g = replace(grid, precision=I.MIXED, precond=I.MG, rtol=bench.RTOL, inner_rtol=bench.DELTA_MG)
+    pb = B.Problem(ctx, mol, g)
+    st = pb.solve()
+    assert st["status"] == 0
+    check_energies(pb.energy(), ref, E_TOL_MIXED)
+    pb.close()
+
+
+def test_c5_stream_sample_parity(ctx):
+    """Sixteen requests of the serving stream (65^3 ... 257^3): each built and solved alone in
+    FP64 (multigrid, 1e-10, cut keys bit-exact), and all of them through the serving loop with
+    the benchmark's preconditioner policy and tolerances (1e-6)."""
+    import torch
+
+    doc = golden("c5_sample_oracle.json")
+    reqs, _ = bench.stream(512)
+    side = B.Context(0, stream=torch.cuda.Stream(0))
+    srv = B.Server(ctx, side, max_resident=bench.MAX_RESIDENT)
+    for rec in doc["requests"]:
+        k = rec["request"]
+        mol, g = reqs[k]
+        assert mol.n == rec["n_atoms"] and list(g.n) == rec["n"]
+        srv.submit(mol, g, k, srv.now())
+    served = {}
+    while len(served) < len(doc["requests"]):
+        srv.step()
+        for r in srv.poll():
+            served[r["id"]] = r
+    srv.close()
+    side.close()
+    for rec in doc["requests"]:
+        k = rec["request"]
+        mol, g = reqs[k]
+        print(f"C5 request {k}: n {g.n[0]}, {mol.n} atoms", flush=True)
+        r = served[k]
+        assert r["code"] == 0 and r["n_cut"] == rec["n_cut"]
+        check_energies(r, rec, E_TOL_MIXED)
+        pb = B.Problem(ctx, mol, replace(g, precision=I.FP64, precond=I.MG, rtol=1e-12))
+        check_build(pb, rec, coeffs=False)
+        st = pb.solve()
+        assert st["status"] == 0
+        en = pb.energy(per_atom=True)
+        check_energies(en, rec, E_TOL64)
+        ai = np.asarray(rec["atoms"]["idx"], dtype=np.int64)
+        pr = np.asarray(rec["atoms"]["phi_reac"])
+        assert np.max(np.abs(en["phi_reac"][ai] - pr)) <= 1e-9 * max(np.max(np.abs(pr)), 1e-300)
+        pb.close()
