@@ -409,10 +409,11 @@ size_t pbi_request_bytes(const pb_params& p, int64_t na, const double* radius, i
     }
     // per node: code, b, box values and the FP64 solution (28 B), the build's classes (4 B,
     // until the build ends), and the solver: six FP32 CG vectors and the correction (28 B), or
-    // for the multigrid form six FP32 CG vectors, 1/D and the red residual on level 0 (32 B)
-    // and the coarser levels (64 B per stored node in FP64 and FP32 copies; with the z-row
-    // padding of small levels they hold up to a quarter of level 0's stored nodes)
-    const size_t per_node = p.precond == PB_PRECOND_MG ? 28 + 4 + 32 + 16 : 28 + 4 + 28;
+    // for the multigrid form eight FP32 vectors and the codes of level 0 in the red-black
+    // layout (36 B, up to 40 B with its segment padding) and the coarser levels (64 B per
+    // stored node in FP64 and FP32 copies; with the z-row padding of small levels they hold up
+    // to a quarter of level 0's stored nodes)
+    const size_t per_node = p.precond == PB_PRECOND_MG ? 28 + 4 + 40 + 16 : 28 + 4 + 28;
     // per cut edge: key, alpha, K, crossing point, normal, owner, area weight (84 B) and at
     // most one slot of the compact coefficient tables (40 B)
     const size_t per_cut = 124;

@@ -161,6 +161,14 @@ struct MGData {
     int nb = 0;
     double* prz = nullptr;      // [nrz] r.z partial sums of the last half-sweep of a V-cycle
     int nrz = 0;
+    // level 0 and the CG vectors are kept in the red-black layout (pb_mg.hip): Sh positions per
+    // colour segment, Nrb elements per vector, and the node codes in that layout
+    int Sh = 0;
+    int64_t Nrb = 0;
+    uint32_t* code_rb = nullptr;
+    // natural-layout right-hand side and solution of level 0 for callers that work in that
+    // layout (the two-level preconditioner of refined grids); made on first use
+    void *nat_b = nullptr, *nat_x = nullptr;
 };
 
 struct pb_problem {

@@ -64,22 +64,16 @@ struct Op0 {
     T kin, kout, mass;
 };
 
-// sum over the six edges of node e of K * v(neighbour), and optionally the diagonal there
-template <typename T, bool L0, typename F>
-__device__ __forceinline__ T nsum(const Lev<T>& L, const Op0<T>& op, int64_t e, F v, T* D = nullptr)
+// sum over the six edges of node e of a coarse level of K * v(neighbour), and optionally
+// the diagonal there
+template <typename T, typename F>
+__device__ __forceinline__ T nsum(const Lev<T>& L, int64_t e, F v, T* D = nullptr)
 {
     const Grid& g = L.g;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    if constexpr (L0) {
-        const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-        if (D) *D = k.diag();
-        return ((k.xm * v(e - sx) + k.xp * v(e + sx)) + (k.ym * v(e - sy) + k.yp * v(e + sy))) +
-               (k.zm * v(e - 1) + k.zp * v(e + 1));
-    } else {
-        if (D) *D = L.diag[e];
-        return ((L.kx[e - sx] * v(e - sx) + L.kx[e] * v(e + sx)) + (L.ky[e - sy] * v(e - sy) + L.ky[e] * v(e + sy))) +
-               (L.kz[e - 1] * v(e - 1) + L.kz[e] * v(e + 1));
-    }
+    if (D) *D = L.diag[e];
+    return ((L.kx[e - sx] * v(e - sx) + L.kx[e] * v(e + sx)) + (L.ky[e - sy] * v(e - sy) + L.ky[e] * v(e + sy))) +
+           (L.kz[e - 1] * v(e - 1) + L.kz[e] * v(e + 1));
 }
 
 // Per-node kernels run on a 3-D grid of 256-thread blocks, 64 lanes along z by 4 rows along
@@ -171,8 +165,8 @@ __device__ __forceinline__ bool halted(const Gate& g) { return g.st && (g.st->st
 
 // the first smoothing step from a zero iterate in one pass: red x = b / D, then black
 // x = (b + sum K x_red) / D with the red values formed on the fly
-template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, Gate st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Gate st)
 {
     if (halted(st)) return;
     const T* __restrict__ b = L.b;
@@ -185,15 +179,15 @@ __global__ void __launch_bounds__(256) k_down1(Lev<T> L, Op0<T> op, Gate st)
         if (red) {
             L.x[e] = b[e] * dinv[e];
         } else {
-            const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return b[n] * dinv[n]; });
+            const T s = nsum<T>(L, e, [&](int64_t n) { return b[n] * dinv[n]; });
             L.x[e] = (b[e] + s) * dinv[e];
         }
     }
 }
 
 // Gauss-Seidel on the nodes of one colour
-template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, Gate st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, int c, Gate st)
 {
     if (halted(st)) return;
     const T* __restrict__ x = L.x;
@@ -201,15 +195,15 @@ __global__ void __launch_bounds__(256) k_sweep(Lev<T> L, Op0<T> op, int c, Gate 
     for (int r = 0; r < kPlanes; ++r) {
         const int64_t e = this_colour_node(L.g, c, r);
         if (e < 0) continue;
-        const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; });
+        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; });
         L.x[e] = (L.b[e] + s) * L.dinv[e];
     }
 }
 
 // residual b - A x at the red nodes (after a black half-sweep the black residual is zero,
 // and the black entries of r stay 0)
-template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restrict__ r, Gate st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_resid(Lev<T> L, T* __restrict__ r, Gate st)
 {
     if (halted(st)) return;
     const T* __restrict__ x = L.x;
@@ -218,7 +212,7 @@ __global__ void __launch_bounds__(256) k_resid(Lev<T> L, Op0<T> op, T* __restric
         const int64_t e = this_colour_node(L.g, 0, p);
         if (e < 0) continue;
         T D;
-        const T s = nsum<T, L0>(L, op, e, [&](int64_t n) { return x[n]; }, &D);
+        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; }, &D);
         r[e] = L.b[e] - (D * x[e] - s);
     }
 }
@@ -274,8 +268,8 @@ __global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Gri
 }
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
-template <typename T, bool L0>
-__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, Gate st)
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, int cs, Gate st)
 {
     if (halted(st)) return;
     const Grid& g = L.g;
@@ -292,7 +286,7 @@ __global__ void __launch_bounds__(256) k_coarse(Lev<T> L, Op0<T> op, int cs, Gat
         for (int t = threadIdx.x; t < nc; t += 256) {
             const int64_t e = colour_node(g, c, t);
             if (e < 0) continue;
-            const T sum = nsum<T, L0>(L, op, e, [&](int64_t m) { return x[m]; });
+            const T sum = nsum<T>(L, e, [&](int64_t m) { return x[m]; });
             L.x[e] = (L.b[e] + sum) * L.dinv[e];
         }
         __syncthreads();
@@ -318,13 +312,12 @@ struct SubLevels {
 template <typename T>
 __device__ __forceinline__ void blk_sweep(const Lev<T>& L, int c)
 {
-    const Op0<T> op{};
     const int nc = (int)colour_threads(L.g);
     const T* __restrict__ x = L.x;
     for (int t = threadIdx.x; t < nc; t += kSubThreads) {
         const int64_t e = colour_node(L.g, c, t);
         if (e < 0) continue;
-        const T s = nsum<T, false>(L, op, e, [&](int64_t m) { return x[m]; });
+        const T s = nsum<T>(L, e, [&](int64_t m) { return x[m]; });
         L.x[e] = (L.b[e] + s) * L.dinv[e];
     }
     __syncthreads();
@@ -345,7 +338,6 @@ template <typename T>
 __global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate st)
 {
     if (halted(st)) return;
-    const Op0<T> op{};
     // down: pre-smoothing, residual at the red nodes, restriction
     for (int l = 0; l + 1 < S.nl; ++l) {
         const Lev<T>& L = S.lv[l];
@@ -361,7 +353,7 @@ __global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate s
             const int64_t e = colour_node(L.g, 0, t);
             if (e < 0) continue;
             T D;
-            const T s = nsum<T, false>(L, op, e, [&](int64_t m) { return x[m]; }, &D);
+            const T s = nsum<T>(L, e, [&](int64_t m) { return x[m]; }, &D);
             S.r[l][e] = L.b[e] - (D * x[e] - s);
         }
         __syncthreads();
@@ -412,15 +404,6 @@ __global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate s
             blk_sweep(L, 0);
         }
     }
-}
-
-// 1 / diagonal of the level-0 unknowns (0 elsewhere)
-template <typename T>
-__global__ void __launch_bounds__(256) k_diag0(Grid g, Op0<T> op, T* __restrict__ dinv)
-{
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
-        dinv[e] = (op.code[e] & C_BOX) ? (T)0
-                                       : (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e).diag();
 }
 
 // ---- hierarchy set-up (FP64) ------------------------------------------------------------
@@ -543,34 +526,438 @@ __device__ __forceinline__ T* p_new(const CGState* st, T* p0, T* p1)
     return (st->iter_count & 1) ? p0 : p1;
 }
 
-// p = z + beta p_old and q = A p at the unknowns in one pass (the new direction at the six
-// neighbours is formed on the fly from z and p_old, which box nodes hold as 0); partial
-// sums of p.q
+// ---- level 0 in the red-black layout ----------------------------------------------------
+// The vectors of level 0 (the CG vectors, the level's iterate, right-hand side, red residual
+// and 1/D) and a copy of the node codes keep the two colours apart: row (i, j) holds its red
+// nodes in one segment of Sh positions and its black nodes in the next, node k at position
+// k >> 1.  A half-sweep then moves only lines of the colour it updates and of the other
+// colour it reads, instead of whole lines of both.  Box and padding positions hold 0 in every
+// vector (their codes carry C_BOX), so neighbour loads need no branch.  The neighbours of a
+// node are all of the other colour: along x and y at the same position of the adjacent rows,
+// along z at positions (k - 1) >> 1 and (k + 1) >> 1 of its own row.
+
+struct RB {
+    int nx, ny, nz;
+    int Sh;        // positions per colour segment (a multiple of 32: 128-byte aligned segments)
+    int64_t N;     // elements per vector: nx * ny * 2 * Sh
+    __host__ __device__ int64_t at(int i, int j, int c, int m) const
+    {
+        return (((int64_t)i * ny + j) * 2 + c) * Sh + m;
+    }
+    __host__ __device__ int64_t idx(int i, int j, int k) const { return at(i, j, (i + j + k) & 1, k >> 1); }
+};
+
+inline RB rb_of(const Grid& g)
+{
+    RB r;
+    r.nx = g.nx;
+    r.ny = g.ny;
+    r.nz = g.nz;
+    r.Sh = ((g.nz + 1) / 2 + 31) / 32 * 32;
+    r.N = (int64_t)g.nx * g.ny * 2 * r.Sh;
+    return r;
+}
+
+// the level-0 operator read from the codes in the red-black layout
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(Grid g, Op0<T> op, const T* __restrict__ z, T* p0, T* p1,
-                                               T* __restrict__ q, double* part, const CGState* st)
+struct OpRB {
+    const uint32_t* code;
+    const T* ck;
+    T kin, kout, mass;
+};
+
+// element indices of a node and of its six neighbours (x-, x+, y-, y+, z-, z+)
+struct RBNb {
+    int64_t e, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ RBNb rb_nb(const RB& r, int i, int j, int c, int m, int k)
+{
+    RBNb n;
+    n.e = r.at(i, j, c, m);
+    const int64_t eo = r.at(i, j, 1 - c, m);
+    const int64_t sx = (int64_t)r.ny * 2 * r.Sh, sy = 2 * (int64_t)r.Sh;
+    n.xm = eo - sx;
+    n.xp = eo + sx;
+    n.ym = eo - sy;
+    n.yp = eo + sy;
+    n.zm = eo - ((k & 1) ? 0 : 1);
+    n.zp = eo + ((k & 1) ? 1 : 0);
+    return n;
+}
+
+template <typename T>
+__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const RBNb& n)
+{
+    const uint32_t c = op.code[n.e];
+    stencil::NodeK<T> k;
+    k.xm = stencil::edgeK(op.code[n.xm], 0, op.ck, op.kin, op.kout);
+    k.xp = stencil::edgeK(c, 0, op.ck, op.kin, op.kout);
+    k.ym = stencil::edgeK(op.code[n.ym], 1, op.ck, op.kin, op.kout);
+    k.yp = stencil::edgeK(c, 1, op.ck, op.kin, op.kout);
+    k.zm = stencil::edgeK(op.code[n.zm], 2, op.ck, op.kin, op.kout);
+    k.zp = stencil::edgeK(c, 2, op.ck, op.kin, op.kout);
+    k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
+    return k;
+}
+
+// sum over the six edges of K * v(neighbour), in the order of the natural-layout kernels
+template <typename T, typename F>
+__device__ __forceinline__ T rb_sum(const stencil::NodeK<T>& k, const RBNb& n, F v)
+{
+    return ((k.xm * v(n.xm) + k.xp * v(n.xp)) + (k.ym * v(n.ym) + k.yp * v(n.yp))) + (k.zm * v(n.zm) + k.zp * v(n.zp));
+}
+
+// 3-D launch over (position, row, x-plane group): 64 positions by 4 rows per block, kPlanes
+// x-planes per thread
+inline dim3 rb_grid(const RB& r)
+{
+    const int mh = (r.nz + 1) / 2;
+    return dim3((unsigned)((mh + 63) / 64), (unsigned)((r.ny - 2 + 3) / 4), (unsigned)((r.nx - 2 + kPlanes - 1) / kPlanes));
+}
+
+// this thread's row and position in plane p of its block layer; false outside the interior rows
+__device__ __forceinline__ bool rb_slot(const RB& r, int p, int& i, int& j, int& m)
+{
+    m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    i = 1 + (int)blockIdx.z * kPlanes + p;
+    return i <= r.nx - 2 && j <= r.ny - 2;
+}
+
+// z index of the node of colour c at position m of row (i, j), or -1 if it is not interior
+__device__ __forceinline__ int rb_node(const RB& r, int i, int j, int c, int m)
+{
+    const int k = 2 * m + ((i + j + c) & 1);
+    return (k >= 1 && k <= r.nz - 2) ? k : -1;
+}
+
+__device__ __forceinline__ unsigned block_linear() { return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x; }
+
+// codes in the red-black layout (C_BOX on box and padding positions)
+__global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* __restrict__ code, uint32_t* __restrict__ out)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < r.N; t += (int64_t)gridDim.x * 256) {
+        const int m = (int)(t % r.Sh);
+        const int64_t q = t / r.Sh;
+        const int c = (int)(q & 1);
+        const int64_t row = q >> 1;
+        const int j = (int)(row % r.ny), i = (int)(row / r.ny);
+        const int k = 2 * m + ((i + j + c) & 1);
+        out[t] = k < r.nz ? code[g.idx(i, j, k)] : C_BOX;
+    }
+}
+
+// 1 / diagonal of the level-0 unknowns in the red-black layout (0 elsewhere)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_diag0(Grid g, RB r, Op0<T> op, T* __restrict__ dinv)
+{
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            dinv[r.at(i, j, c, m)] =
+                (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, g.idx(i, j, k)).diag();
+        }
+    }
+}
+
+// level-0 right-hand side b and iterate x (the CG vectors r and z), with 1/D
+template <typename T>
+struct Lev0 {
+    RB r;
+    const T* b;
+    const T* dinv;
+    T* x;
+};
+
+// the first smoothing step from a zero iterate: red x = b / D, then black
+// x = (b + sum K x_red) / D with the red values formed on the fly
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_down1(Lev0<T> L, OpRB<T> op, Gate st)
+{
+    if (halted(st)) return;
+    const T* __restrict__ b = L.b;
+    const T* __restrict__ dinv = L.dinv;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(L.r, p, i, j, m)) continue;
+        if (rb_node(L.r, i, j, 0, m) >= 0) {
+            const int64_t e = L.r.at(i, j, 0, m);
+            L.x[e] = b[e] * dinv[e];
+        }
+        const int k = rb_node(L.r, i, j, 1, m);
+        if (k >= 0) {
+            const RBNb n = rb_nb(L.r, i, j, 1, m, k);
+            const stencil::NodeK<T> K = rb_k(op, n);
+            const T s = rb_sum(K, n, [&](int64_t f) { return b[f] * dinv[f]; });
+            L.x[n.e] = (b[n.e] + s) * dinv[n.e];
+        }
+    }
+}
+
+// Gauss-Seidel on the nodes of colour c
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_sweep(Lev0<T> L, OpRB<T> op, int c, Gate st)
+{
+    if (halted(st)) return;
+    const T* __restrict__ x = L.x;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(L.r, p, i, j, m)) continue;
+        const int k = rb_node(L.r, i, j, c, m);
+        if (k < 0) continue;
+        const RBNb n = rb_nb(L.r, i, j, c, m, k);
+        const stencil::NodeK<T> K = rb_k(op, n);
+        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
+        L.x[n.e] = (L.b[n.e] + s) * L.dinv[n.e];
+    }
+}
+
+// residual b - A x at the red nodes (the black residual is zero right after a black
+// half-sweep), in the red segments of rr
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_resid(Lev0<T> L, OpRB<T> op, T* __restrict__ rr, Gate st)
+{
+    if (halted(st)) return;
+    const T* __restrict__ x = L.x;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(L.r, p, i, j, m)) continue;
+        const int k = rb_node(L.r, i, j, 0, m);
+        if (k < 0) continue;
+        const RBNb n = rb_nb(L.r, i, j, 0, m, k);
+        const stencil::NodeK<T> K = rb_k(op, n);
+        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
+        rr[n.e] = L.b[n.e] - (K.diag() * x[n.e] - s);
+    }
+}
+
+// coarse right-hand side P^T r from the red residual of level 0: fine node 2I and its 12
+// red neighbours (two odd offsets, weight 1/4); the other 14 of the 27 are black
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_restrict(RB rf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
+                                                     Gate st)
+{
+    if (halted(st)) return;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        bool red;
+        const int64_t ec = this_node(gc, p, red);
+        if (ec < 0) continue;
+        const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+        const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+        const int I = 1 + (int)blockIdx.z * kPlanes + p;
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        auto R = [&](int a, int b, int c) { return r[rf.idx(i + a, j + b, k + c)]; };
+        const T xy = (R(-1, -1, 0) + R(-1, 1, 0)) + (R(1, -1, 0) + R(1, 1, 0));
+        const T xz = (R(-1, 0, -1) + R(-1, 0, 1)) + (R(1, 0, -1) + R(1, 0, 1));
+        const T yz = (R(0, -1, -1) + R(0, -1, 1)) + (R(0, 1, -1) + R(0, 1, 1));
+        bc[ec] = R(0, 0, 0) + (T)0.25 * ((xy + xz) + yz);
+    }
+}
+
+// x += P e at the red nodes of level 0 (the black half-sweep that follows replaces the black ones)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_prolong(RB rf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
+                                                    Gate st)
+{
+    if (halted(st)) return;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(rf, p, i, j, m)) continue;
+        const int k = rb_node(rf, i, j, 0, m);
+        if (k < 0) continue;
+        x[rf.at(i, j, 0, m)] += prolong_at(gc, ec, i, j, k);
+    }
+}
+
+// the last red half-sweep of a V-cycle on level 0 and the partial sums of r.z = b.x over all
+// unknowns (the black ones are final after the black half-sweep), one per block
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_sweep_dot(Lev0<T> L, OpRB<T> op, Gate st, double* part)
+{
+    __shared__ double sh[8];
+    if (halted(st)) return;
+    const T* __restrict__ x = L.x;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(L.r, p, i, j, m)) continue;
+        const int k = rb_node(L.r, i, j, 0, m);
+        if (k >= 0) {
+            const RBNb n = rb_nb(L.r, i, j, 0, m, k);
+            const stencil::NodeK<T> K = rb_k(op, n);
+            const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
+            const T xn = (L.b[n.e] + s) * L.dinv[n.e];
+            L.x[n.e] = xn;
+            v[0] += (double)L.b[n.e] * (double)xn;
+        }
+        if (rb_node(L.r, i, j, 1, m) >= 0) {
+            const int64_t eb = L.r.at(i, j, 1, m);
+            v[0] += (double)L.b[eb] * (double)x[eb];
+        }
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[block_linear()] = v[0];
+}
+
+// the single-level case (no coarser grid): red from zero, black, then (red, black) ... as the
+// coarsest level runs, over the red-black level 0
+// (k_rb_down1 gives red + black; the sweeps follow on the host side)
+
+// ---- CG over the level-0 unknowns (red-black layout) ---------------------------------------
+
+// p = z + beta p_old and q = A p at both nodes of each position in one pass (the new direction
+// at the neighbours is formed on the fly from z and p_old, which box positions hold as 0);
+// partial sums of p.q, one per block
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_apply(RB r, OpRB<T> op, const T* __restrict__ z, T* p0, T* p1,
+                                                  T* __restrict__ q, double* part, const CGState* st)
 {
     __shared__ double sh[8];
     if (st->status != 0) return;
     const T* __restrict__ po = p_old(st, (const T*)p0, (const T*)p1);
     T* __restrict__ pn = p_new(st, p0, p1);
     const T beta = (T)st->beta;
-    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
     double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
-        if (op.code[e] & C_BOX) continue;
-        const stencil::NodeK<T> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-        auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
-        const T pe = pd(e);
-        const T s = ((k.xm * pd(e - sx) + k.xp * pd(e + sx)) + (k.ym * pd(e - sy) + k.yp * pd(e + sy))) +
-                    (k.zm * pd(e - 1) + k.zp * pd(e + 1));
-        const T qe = k.diag() * pe - s;
-        pn[e] = pe;
-        q[e] = qe;
-        v[0] += (double)pe * (double)qe;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            const RBNb n = rb_nb(r, i, j, c, m, k);
+            const stencil::NodeK<T> K = rb_k(op, n);
+            const T pe = pd(n.e);
+            const T qe = K.diag() * pe - rb_sum(K, n, pd);
+            pn[n.e] = pe;
+            q[n.e] = qe;
+            v[0] += (double)pe * (double)qe;
+        }
     }
     bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[block_linear()] = v[0];
+}
+
+// x += alpha p, r -= alpha q over every element (box and padding positions hold 0 in p, q and
+// r); partial sums of r.r (after the nb slots of the p.q sums)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_update(int64_t N, T* __restrict__ x, T* __restrict__ r, T* p0, T* p1,
+                                                   const T* __restrict__ q, double* part, int nb, const CGState* st)
+{
+    __shared__ double sh[8];
+    if (st->status != 0) return;
+    const T* __restrict__ p = p_new(st, p0, p1);
+    const T a = (T)st->alpha;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
+        x[e] += a * p[e];
+        const T rv = r[e] - a * q[e];
+        r[e] = rv;
+        v[0] += (double)rv * (double)rv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[nb + blockIdx.x] = v[0];
+}
+
+// partial sums of r.z over every element
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_dot(int64_t N, const T* __restrict__ r, const T* __restrict__ z,
+                                                double* part, Gate st)
+{
+    __shared__ double sh[8];
+    if (halted(st)) return;
+    double v[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256)
+        v[0] += (double)r[e] * (double)z[e];
+    bsum(v, 1, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// the FP64 solution (natural layout) += the correction in the red-black layout, which is then
+// cleared
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_fold(Grid g, RB r, double* __restrict__ x64, T* __restrict__ xc,
+                                                 const CGState* st, int force)
+{
+    if (!force && st->status != 3) return;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            const int64_t e = r.at(i, j, c, m);
+            x64[g.idx(i, j, k)] += (double)xc[e];
+            xc[e] = (T)0;
+        }
+    }
+}
+
+// r = b - A x in FP64 from the natural-layout solution, right-hand side and codes, stored in
+// the element type in the red-black layout; partial sums of the FP64 r.r in the third slot
+// range, one per block
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_true_res(Grid g, RB r, Op0<double> op, const double* __restrict__ x,
+                                                     const double* __restrict__ b, T* __restrict__ res, double* part,
+                                                     int nb, const CGState* st, int force)
+{
+    __shared__ double sh[8];
+    if (!force && st->status != 3) return;
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            const int64_t e = g.idx(i, j, k);
+            const stencil::NodeK<double> K = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
+            const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
+                             (K.zm * x[e - 1] + K.zp * x[e + 1]);
+            const double rv = b[e] - (K.diag() * x[e] - s);
+            res[r.at(i, j, c, m)] = (T)rv;
+            v[0] += rv * rv;
+        }
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) part[2 * nb + block_linear()] = v[0];
+}
+
+// natural-layout level-0 vector <-> red-black layout (interior nodes; the two-level
+// preconditioner of refined grids hands its coarse right-hand side over in the natural layout)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_convert(Grid g, RB r, T* __restrict__ nat, T* __restrict__ rbv, int to_rb,
+                                                    Gate st)
+{
+    if (halted(st)) return;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            if (to_rb)
+                rbv[r.at(i, j, c, m)] = nat[g.idx(i, j, k)];
+            else
+                nat[g.idx(i, j, k)] = rbv[r.at(i, j, c, m)];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGState* st)
@@ -590,75 +977,6 @@ __global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGSta
             st->alpha = st->gamma / pq;
         }
     }
-}
-
-// x += alpha p, r -= alpha q; partial sums of r.r (after the r.z slots)
-template <typename T>
-__global__ void __launch_bounds__(256) k_update(Grid g, const uint32_t* __restrict__ code, T* __restrict__ x,
-                                                T* __restrict__ r, T* p0, T* p1, const T* __restrict__ q,
-                                                double* part, int nb, const CGState* st)
-{
-    __shared__ double sh[8];
-    if (st->status != 0) return;
-    const T* __restrict__ p = p_new(st, p0, p1);
-    const T a = (T)st->alpha;
-    double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
-        if (code[e] & C_BOX) continue;
-        x[e] += a * p[e];
-        const T rv = r[e] - a * q[e];
-        r[e] = rv;
-        v[0] += (double)rv * (double)rv;
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[nb + blockIdx.x] = v[0];
-}
-
-// partial sums of r.z
-template <typename T>
-__global__ void __launch_bounds__(256) k_dot(Grid g, const uint32_t* __restrict__ code, const T* __restrict__ r,
-                                             const T* __restrict__ z, double* part, Gate st)
-{
-    __shared__ double sh[8];
-    if (halted(st)) return;
-    double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
-        if (!(code[e] & C_BOX)) v[0] += (double)r[e] * (double)z[e];
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-}
-
-// the last red half-sweep of a V-cycle on level 0, and the partial sums of r.z = b.x over
-// all unknowns: lane m of a row updates its red node and adds the black node of the same pair
-// (k = 1 + 2m, 2 + 2m), final after the black half-sweep; partial sums per block in block
-// order (x, then y, then z)
-template <typename T>
-__global__ void __launch_bounds__(256) k_sweep_dot(Lev<T> L, Op0<T> op, Gate st, double* part)
-{
-    __shared__ double sh[8];
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-    double v[1] = {0.0};
-#pragma unroll
-    for (int r = 0; r < kPlanes; ++r) {
-        int i, j, k;
-        const int64_t e = this_colour_node(L.g, 0, r, i, j, k);
-        if (e >= 0) {
-            const T s = nsum<T, true>(L, op, e, [&](int64_t n) { return x[n]; });
-            const T xn = (L.b[e] + s) * L.dinv[e];
-            L.x[e] = xn;
-            v[0] += (double)L.b[e] * (double)xn;
-        }
-        // the black node of the pair (k - 1 if k is even, else k + 1), which may exist when
-        // the red one lies past the row's end
-        const int kb = (k & 1) ? k + 1 : k - 1;
-        if (i <= L.g.nx - 2 && j <= L.g.ny - 2 && kb <= L.g.nz - 2) {
-            const int64_t eb = L.g.idx(i, j, kb);
-            v[0] += (double)L.b[eb] * (double)x[eb];
-        }
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = v[0];
 }
 
 // mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
@@ -708,42 +1026,6 @@ __global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGStat
             st->iters = st->iter_count;
         }
     }
-}
-
-// mixed precision: x64 += x32, x32 = 0
-__global__ void __launch_bounds__(256) k_fold(Grid g, const uint32_t* __restrict__ code, double* __restrict__ x64,
-                                              float* __restrict__ x32, const CGState* st, int force)
-{
-    if (!force && st->status != 3) return;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256)
-        if (!(code[e] & C_BOX)) {
-            x64[e] += (double)x32[e];
-            x32[e] = 0.0f;
-        }
-}
-
-// r = b - A x in FP64 (the FP64 code-map operator), stored in the element type; partial sums
-// of the FP64 r.r in the third slot range
-template <typename T>
-__global__ void __launch_bounds__(256) k_true_res(Grid g, Op0<double> op, const double* __restrict__ x,
-                                                  const double* __restrict__ b, T* __restrict__ r, double* part, int nb,
-                                                  const CGState* st, int force)
-{
-    __shared__ double sh[8];
-    if (!force && st->status != 3) return;
-    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < g.N; e += (int64_t)gridDim.x * 256) {
-        if (op.code[e] & C_BOX) continue;
-        const stencil::NodeK<double> k = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-        const double s = ((k.xm * x[e - sx] + k.xp * x[e + sx]) + (k.ym * x[e - sy] + k.yp * x[e + sy])) +
-                         (k.zm * x[e - 1] + k.zp * x[e + 1]);
-        const double rv = b[e] - (k.diag() * x[e] - s);
-        r[e] = (T)rv;
-        v[0] += rv * rv;
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = v[0];
 }
 
 // after a true residual: the FP64 norm decides convergence; with init it sets the goals.  A
@@ -844,58 +1126,72 @@ Op0<T> op0(const pb_problem* pb)
     return o;
 }
 
-template <typename T, bool L0>
-void launch_sweep(hipStream_t s, const Lev<T>& L, const Op0<T>& op, int c, Gate st)
+// ---- launches on the coarse levels (natural layout) --------------------------------------
+
+template <typename T>
+void launch_sweep(hipStream_t s, const Lev<T>& L, int c, Gate st)
 {
-    if (colour_threads(L.g) > 0) k_sweep<T, L0><<<node_grid(L.g, true), 256, 0, s>>>(L, op, c, st);
+    if (colour_threads(L.g) > 0) k_sweep<T><<<node_grid(L.g, true), 256, 0, s>>>(L, c, st);
 }
 
 // pre-smoothing (red, black) x nu from zero
-template <typename T, bool L0>
-void launch_pre(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, Gate st)
+template <typename T>
+void launch_pre(hipStream_t s, int nu, const Lev<T>& L, Gate st)
 {
-    k_down1<T, L0><<<node_grid(L.g, false), 256, 0, s>>>(L, op, st);
+    k_down1<T><<<node_grid(L.g, false), 256, 0, s>>>(L, st);
     for (int v = 1; v < nu; ++v) {
-        launch_sweep<T, L0>(s, L, op, 0, st);
-        launch_sweep<T, L0>(s, L, op, 1, st);
+        launch_sweep<T>(s, L, 0, st);
+        launch_sweep<T>(s, L, 1, st);
     }
 }
 
 // coarse correction and post-smoothing (black, red) x nu
-// (level 0 with dot: the last red half-sweep also forms the r.z partial sums)
-template <typename T, bool L0>
-void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Op0<T>& op, const Grid& gc, const T* ec,
-                 Gate st, hipEvent_t* ev = nullptr, double* dot = nullptr)
+template <typename T>
+void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Grid& gc, const T* ec, Gate st)
 {
     k_prolong<T><<<node_grid(L.g, true), 256, 0, s>>>(L.g, L.x, gc, ec, st);
-    if (ev) (void)hipEventRecord(ev[1], s);
     for (int v = 0; v < nu; ++v) {
-        launch_sweep<T, L0>(s, L, op, 1, st);
-        if (v == 0 && ev) (void)hipEventRecord(ev[2], s);
-        if constexpr (L0) {
-            if (dot && v == nu - 1) {
-                if (colour_threads(L.g) > 0) k_sweep_dot<T><<<node_grid(L.g, true), 256, 0, s>>>(L, op, st, dot);
-                continue;
-            }
-        }
-        launch_sweep<T, L0>(s, L, op, 0, st);
+        launch_sweep<T>(s, L, 1, st);
+        launch_sweep<T>(s, L, 0, st);
     }
 }
 
-template <typename T, bool L0>
-void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, const Op0<T>& op, Gate st)
+template <typename T>
+void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, Gate st)
 {
     if (interior_count(L.g) <= kOneBlockCoarse) {
-        k_coarse<T, L0><<<1, 256, 0, s>>>(L, op, G->cs, st);
+        k_coarse<T><<<1, 256, 0, s>>>(L, G->cs, st);
         return;
     }
     // red, black in one pass, then red, then (black, red) x (cs - 1)
-    launch_pre<T, L0>(s, 1, L, op, st);
-    launch_sweep<T, L0>(s, L, op, 0, st);
+    launch_pre<T>(s, 1, L, st);
+    launch_sweep<T>(s, L, 0, st);
     for (int v = 1; v < G->cs; ++v) {
-        launch_sweep<T, L0>(s, L, op, 1, st);
-        launch_sweep<T, L0>(s, L, op, 0, st);
+        launch_sweep<T>(s, L, 1, st);
+        launch_sweep<T>(s, L, 0, st);
     }
+}
+
+// ---- launches on level 0 (red-black layout) ------------------------------------------------
+
+template <typename T>
+OpRB<T> oprb(const pb_problem* pb)
+{
+    const Op0<T> o = op0<T>(pb);
+    return OpRB<T>{pb->mg->code_rb, o.ck, o.kin, o.kout, o.mass};
+}
+
+template <typename T>
+Lev0<T> lev0(const pb_problem* pb)
+{
+    const MGData* G = pb->mg;
+    return Lev0<T>{rb_of(pb->g), (const T*)G->cr, (const T*)G->dinv[0], (T*)G->cz};
+}
+
+template <typename T>
+void launch_rb_sweep(hipStream_t s, const Lev0<T>& L, const OpRB<T>& op, int c, Gate st)
+{
+    k_rb_sweep<T><<<rb_grid(L.r), 256, 0, s>>>(L, op, c, st);
 }
 
 // z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r); with ev, events around
@@ -906,29 +1202,40 @@ template <typename T>
 bool launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
-    const Op0<T> op = op0<T>(pb);
+    const OpRB<T> op = oprb<T>(pb);
+    const Lev0<T> L0 = lev0<T>(pb);
+    const dim3 grid0 = rb_grid(L0.r);
     const int L = G->nlev;
     if (L == 1) {
-        launch_coarsest<T, true>(s, G, level<T>(G, 0), op, st);
+        // one level: red from zero and black, then red, then (black, red) x (cs - 1)
+        k_rb_down1<T><<<grid0, 256, 0, s>>>(L0, op, st);
+        launch_rb_sweep<T>(s, L0, op, 0, st);
+        for (int v = 1; v < G->cs; ++v) {
+            launch_rb_sweep<T>(s, L0, op, 1, st);
+            launch_rb_sweep<T>(s, L0, op, 0, st);
+        }
         return false;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
+    // level 0: pre-smoothing, red residual, restriction to level 1
+    k_rb_down1<T><<<grid0, 256, 0, s>>>(L0, op, st);
+    for (int v = 1; v < G->nu; ++v) {
+        launch_rb_sweep<T>(s, L0, op, 0, st);
+        launch_rb_sweep<T>(s, L0, op, 1, st);
+    }
+    k_rb_resid<T><<<grid0, 256, 0, s>>>(L0, op, (T*)G->r[0], st);
+    k_rb_restrict<T><<<node_grid(G->g[1], false), 256, 0, s>>>(L0.r, (const T*)G->r[0], G->g[1], (T*)G->b[1], st);
     // the first level from which every level has at most kSubcycleNodes unknowns (not 0)
     int ls = L;
     while (ls - 1 >= 1 && interior_count(G->g[ls - 1]) <= kSubcycleNodes) --ls;
-    // pre-smoothing and restriction on the levels above the one-block part (or above the
-    // coarsest level)
-    for (int l = 0; l < std::min(ls, L - 1); ++l) {
+    // pre-smoothing and restriction on the coarse levels above the one-block part (or above
+    // the coarsest level)
+    for (int l = 1; l < std::min(ls, L - 1); ++l) {
         const Lev<T> lv = level<T>(G, l);
         const Grid& gc = G->g[l + 1];
         T* r = (T*)G->r[l];
-        if (l == 0) {
-            launch_pre<T, true>(s, G->nu, lv, op, st);
-            k_resid<T, true><<<node_grid(lv.g, true), 256, 0, s>>>(lv, op, r, st);
-        } else {
-            launch_pre<T, false>(s, G->nu, lv, op, st);
-            k_resid<T, false><<<node_grid(lv.g, true), 256, 0, s>>>(lv, op, r, st);
-        }
+        launch_pre<T>(s, G->nu, lv, st);
+        k_resid<T><<<node_grid(lv.g, true), 256, 0, s>>>(lv, r, st);
         k_restrict<T><<<node_grid(gc, false), 256, 0, s>>>(lv.g, r, gc, (T*)G->b[l + 1], st);
     }
     if (ls < L) {
@@ -943,15 +1250,21 @@ bool launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev 
         }
         k_subcycle<T><<<1, kSubThreads, 0, s>>>(S, st);
     } else {
-        launch_coarsest<T, false>(s, G, level<T>(G, L - 1), op, st);
+        launch_coarsest<T>(s, G, level<T>(G, L - 1), st);
     }
-    for (int l = std::min(ls, L - 1) - 1; l >= 0; --l) {
-        const Lev<T> lv = level<T>(G, l);
-        const T* ec = (const T*)G->x[l + 1];
-        if (l == 0)
-            launch_post<T, true>(s, G->nu, lv, op, G->g[1], ec, st, ev, G->prz);
+    for (int l = std::min(ls, L - 1) - 1; l >= 1; --l)
+        launch_post<T>(s, G->nu, level<T>(G, l), G->g[l + 1], (const T*)G->x[l + 1], st);
+    // level 0: coarse correction at the red nodes, post-smoothing; the last red half-sweep
+    // also forms the r.z partial sums
+    k_rb_prolong<T><<<grid0, 256, 0, s>>>(L0.r, L0.x, G->g[1], (const T*)G->x[1], st);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    for (int v = 0; v < G->nu; ++v) {
+        launch_rb_sweep<T>(s, L0, op, 1, st);
+        if (v == 0 && ev) (void)hipEventRecord(ev[2], s);
+        if (v == G->nu - 1)
+            k_rb_sweep_dot<T><<<grid0, 256, 0, s>>>(L0, op, st, G->prz);
         else
-            launch_post<T, false>(s, G->nu, lv, op, G->g[l + 1], ec, st);
+            launch_rb_sweep<T>(s, L0, op, 0, st);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     return true;
@@ -1020,44 +1333,44 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
         pkz = kz;
         pm = m;
     }
-    // level vectors (level 0: x and b are the CG vectors z and r)
-    for (int l = 0; l < G->nlev; ++l) {
+    // coarse-level vectors (natural layout)
+    for (int l = 1; l < G->nlev; ++l) {
         const Grid& g = G->g[l];
         void** dst[3] = {&G->r[l], &G->x[l], &G->b[l]};
-        for (int v = 0; v < (l == 0 ? 1 : 3); ++v) {
+        for (int v = 0; v < 3; ++v) {
             *dst[v] = pb->mem.get(sizeof(T) * (size_t)g.N);
             if (!*dst[v]) return pbi_fail(PB_ENOMEM, "multigrid vectors");
             RCHK(launch_fill(s, *dst[v], sizeof(T) * (size_t)g.N));
         }
     }
-    // 1 / diagonal of level 0
-    {
-        T* d0 = (T*)pb->mem.get(sizeof(T) * (size_t)pb->g.N);
-        if (!d0) return pbi_fail(PB_ENOMEM, "multigrid vectors");
-        k_diag0<T><<<(unsigned)std::min<int64_t>(65536, nblk(pb->g.N, 256)), 256, 0, s>>>(pb->g, op0<T>(pb), d0);
-        RCHK(hipGetLastError());
-        G->dinv[0] = d0;
-    }
+    // level 0 in the red-black layout: the codes, 1 / diagonal, the red residual and the CG
+    // vectors r, z, p (two), q and the correction x (x and b of level 0 are z and r)
     const Grid& g0 = pb->g;
-    void** cg[6] = {&G->cr, &G->cz, &G->cp, &G->cp2, &G->cq, &G->cx};
-    const int ncg = sizeof(T) == 4 ? 6 : 5;
-    for (int v = 0; v < ncg; ++v) {
-        *cg[v] = pb->mem.get(sizeof(T) * (size_t)g0.N);
-        if (!*cg[v]) return pbi_fail(PB_ENOMEM, "multigrid CG vectors");
-        RCHK(launch_fill(s, *cg[v], sizeof(T) * (size_t)g0.N));
+    const RB rb = rb_of(g0);
+    G->Sh = rb.Sh;
+    G->Nrb = rb.N;
+    G->code_rb = (uint32_t*)pb->mem.get(sizeof(uint32_t) * (size_t)rb.N);
+    if (!G->code_rb) return pbi_fail(PB_ENOMEM, "multigrid codes");
+    k_rb_code<<<(unsigned)std::min<int64_t>(65536, nblk(rb.N, 256)), 256, 0, s>>>(g0, rb, pb->code, G->code_rb);
+    void** v0[8] = {&G->dinv[0], &G->r[0], &G->cr, &G->cz, &G->cp, &G->cp2, &G->cq, &G->cx};
+    for (int v = 0; v < 8; ++v) {
+        *v0[v] = pb->mem.get(sizeof(T) * (size_t)rb.N);
+        if (!*v0[v]) return pbi_fail(PB_ENOMEM, "multigrid level-0 vectors");
+        RCHK(launch_fill(s, *v0[v], sizeof(T) * (size_t)rb.N));
     }
-    if (sizeof(T) == 8) G->cx = pb->x;
+    k_rb_diag0<T><<<rb_grid(rb), 256, 0, s>>>(g0, rb, op0<T>(pb), (T*)G->dinv[0]);
     G->x[0] = G->cz;
     G->b[0] = G->cr;
-    G->nb = (int)std::min<int64_t>(8192, (int64_t)nblk(g0.N, 256));
+    {
+        // one partial sum per block of the level-0 launches; the streaming kernels use as many
+        const dim3 ng = rb_grid(rb);
+        G->nb = (int)(ng.x * ng.y * ng.z);
+        G->nrz = G->nb;
+    }
     G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
     if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
-    {
-        const dim3 ng = node_grid(g0, true);
-        G->nrz = (int)(ng.x * ng.y * ng.z);
-        G->prz = (double*)pb->mem.get(sizeof(double) * (size_t)G->nrz);
-        if (!G->prz) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
-    }
+    G->prz = (double*)pb->mem.get(sizeof(double) * (size_t)G->nrz);
+    if (!G->prz) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
     RCHK(hipGetLastError());
     return PB_OK;
 }
@@ -1066,37 +1379,37 @@ template <typename T>
 void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent_t* ev = nullptr)
 {
     const MGData* G = pb->mg;
-    const Grid& g = pb->g;
-    const Op0<T> op = op0<T>(pb);
+    const RB rb = rb_of(pb->g);
     T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p0 = (T*)G->cp, *p1 = (T*)G->cp2, *q = (T*)G->cq;
     const Gate gate{st, 0};
-    k_apply<T><<<G->nb, 256, 0, s>>>(g, op, z, p0, p1, q, G->part, st);
+    k_rb_apply<T><<<rb_grid(rb), 256, 0, s>>>(rb, oprb<T>(pb), z, p0, p1, q, G->part, st);
     k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
-    k_update<T><<<G->nb, 256, 0, s>>>(g, pb->code, x, r, p0, p1, q, G->part, G->nb, st);
+    k_rb_update<T><<<G->nb, 256, 0, s>>>(rb.N, x, r, p0, p1, q, G->part, G->nb, st);
     const bool fused = launch_vcycle<T>(s, pb, gate, ev);
-    if (!fused) k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, r, z, G->part, gate);
+    if (!fused) k_rb_dot<T><<<G->nb, 256, 0, s>>>(rb.N, r, z, G->part, gate);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0, fused ? G->prz : nullptr, G->nrz);
 }
 
-// restart from the true residual: fold the FP32 correction into the FP64 solution (mixed),
-// r = b - A x in FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the
-// state (init: the first residual, x = 0); otherwise only where the iteration stopped with
-// status 3 (the FP32 residual reached its goal or fell by inner_rtol).
+// restart from the true residual: fold the correction into the FP64 solution, r = b - A x in
+// FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the state (init: the
+// first residual, x = 0); otherwise only where the iteration stopped with status 3 (the FP32
+// residual reached its goal or fell by inner_rtol).
 template <typename T>
 void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init, int force)
 {
     const MGData* G = pb->mg;
     const Grid& g = pb->g;
+    const RB rb = rb_of(g);
     const pb_params& P = pb->prm;
     const bool mixed = sizeof(T) == 4;
-    if (mixed) k_fold<<<G->nb, 256, 0, s>>>(g, pb->code, pb->x, (float*)G->cx, st, force);
+    k_rb_fold<T><<<rb_grid(rb), 256, 0, s>>>(g, rb, pb->x, (T*)G->cx, st, force);
     const Op0<double> op64 = op0<double>(pb);
-    k_true_res<T><<<G->nb, 256, 0, s>>>(g, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb, st, force);
+    k_rb_true_res<T><<<rb_grid(rb), 256, 0, s>>>(g, rb, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb, st, force);
     k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol,
                                force);
     const Gate gate{st, 1};
     const bool fused = launch_vcycle<T>(s, pb, gate);
-    if (!fused) k_dot<T><<<G->nb, 256, 0, s>>>(g, pb->code, (const T*)G->cr, (const T*)G->cz, G->part, gate);
+    if (!fused) k_rb_dot<T><<<G->nb, 256, 0, s>>>(rb.N, (const T*)G->cr, (const T*)G->cz, G->part, gate);
     k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2, fused ? G->prz : nullptr, G->nrz);
 }
 
@@ -1120,9 +1433,9 @@ int start_t(pb_problem* pb, hipStream_t s)
 {
     MGData* G = pb->mg;
     RCHK(launch_fill(s, pb->x, sizeof(double) * (size_t)pb->g.N));
-    if (sizeof(T) == 4) RCHK(launch_fill(s, G->cx, sizeof(float) * (size_t)pb->g.N));
-    RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)pb->g.N));
-    RCHK(launch_fill(s, G->cp2, sizeof(T) * (size_t)pb->g.N));
+    RCHK(launch_fill(s, G->cx, sizeof(T) * (size_t)G->Nrb));
+    RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)G->Nrb));
+    RCHK(launch_fill(s, G->cp2, sizeof(T) * (size_t)G->Nrb));
     RCHK(launch_fill(s, pb->st, sizeof(CGState)));
     launch_restart<T>(s, pb, pb->st, 1, 1);
     RCHK(hipGetLastError());
@@ -1208,8 +1521,12 @@ int solve_t(pb_problem* pb, CGState* out)
         if (snap.status == 1 || snap.status == 2 || !more) break;
         ++c;
     }
-    // a correction left over by a stop without convergence
-    if (sizeof(T) == 4) k_fold<<<pb->mg->nb, 256, 0, s>>>(pb->g, pb->code, pb->x, (float*)pb->mg->cx, pb->st, 1);
+    // the correction into the FP64 solution (all of it in FP64; in the mixed form what is left
+    // after the last restart)
+    {
+        const RB rb = rb_of(pb->g);
+        k_rb_fold<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (T*)pb->mg->cx, pb->st, 1);
+    }
     RCHK(hipMemcpyAsync(out, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
     if (prof) {
@@ -1263,50 +1580,89 @@ int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* s
 
 int pbi_mg_finish(pb_problem* pb, hipStream_t s)
 {
-    if (pb->prm.precision != PB_MIXED || !pb->mg) return PB_OK;
-    k_fold<<<pb->mg->nb, 256, 0, s>>>(pb->g, pb->code, pb->x, (float*)pb->mg->cx, pb->st, 1);
+    if (!pb->mg) return PB_OK;
+    const RB rb = rb_of(pb->g);
+    if (pb->prm.precision == PB_MIXED)
+        k_rb_fold<float><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (float*)pb->mg->cx, pb->st, 1);
+    else
+        k_rb_fold<double><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (double*)pb->mg->cx, pb->st, 1);
     RCHK(hipGetLastError());
     return PB_OK;
 }
 
 int pbi_mg_levels(const pb_problem* pb) { return pb->mg ? pb->mg->nlev : 0; }
 
+namespace {
+
+template <typename T>
+void vcycle_natural(pb_problem* pb, hipStream_t s, const CGState* st)
+{
+    MGData* G = pb->mg;
+    const RB rb = rb_of(pb->g);
+    const Gate gate{st, 0};
+    k_rb_convert<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, (T*)G->nat_b, (T*)G->cr, 1, gate);
+    launch_vcycle<T>(s, pb, gate);
+    k_rb_convert<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, (T*)G->nat_x, (T*)G->cz, 0, gate);
+}
+
+void* natural_buffer(pb_problem* pb, void** slot)
+{
+    if (!pb->mg) return nullptr;
+    if (!*slot) {
+        const size_t bytes = (pb->prm.precision == PB_MIXED ? sizeof(float) : sizeof(double)) * (size_t)pb->g.N;
+        *slot = pb->mem.get(bytes);
+        if (*slot && launch_fill(pb->ctx->stream, *slot, bytes) != hipSuccess) return nullptr;
+    }
+    return *slot;
+}
+
+}  // namespace
+
 void pbi_mg_vcycle_on(pb_problem* pb, hipStream_t s, const CGState* st)
 {
     if (pb->prm.precision == PB_MIXED)
-        launch_vcycle<float>(s, pb, Gate{st, 0});
+        vcycle_natural<float>(pb, s, st);
     else
-        launch_vcycle<double>(s, pb, Gate{st, 0});
+        vcycle_natural<double>(pb, s, st);
 }
 
-void* pbi_mg_rhs0(pb_problem* pb) { return pb->mg ? pb->mg->b[0] : nullptr; }
-void* pbi_mg_sol0(pb_problem* pb) { return pb->mg ? pb->mg->x[0] : nullptr; }
+void* pbi_mg_rhs0(pb_problem* pb) { return natural_buffer(pb, &pb->mg->nat_b); }
+void* pbi_mg_sol0(pb_problem* pb) { return natural_buffer(pb, &pb->mg->nat_x); }
 
 int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
 {
-    // one V-cycle on a host vector over the padded level-0 layout (test hook)
+    // one V-cycle on a host vector over the padded natural level-0 layout (test hook); the
+    // conversion to and from the red-black layout is done here on the host
     hipStream_t s = pb->ctx->stream;
     const Grid& g = pb->g;
     const bool mixed = pb->prm.precision == PB_MIXED;
     int rc = pbi_mg_begin(pb, s);
     if (rc) return rc;
     MGData* G = pb->mg;
+    const RB rb = rb_of(g);
     const Gate gate{nullptr, 0};
-    std::vector<float> tmp;
+    std::vector<double> r64((size_t)rb.N, 0.0), z64((size_t)rb.N, 0.0);
+    for (int i = 1; i < g.nx - 1; ++i)
+        for (int j = 1; j < g.ny - 1; ++j)
+            for (int k = 1; k < g.nz - 1; ++k) r64[(size_t)rb.idx(i, j, k)] = r_host[g.idx(i, j, k)];
     if (mixed) {
-        tmp.resize((size_t)g.N);
-        for (int64_t e = 0; e < g.N; ++e) tmp[(size_t)e] = (float)r_host[e];
-        RCHK(hipMemcpyAsync(G->cr, tmp.data(), sizeof(float) * (size_t)g.N, hipMemcpyHostToDevice, s));
+        std::vector<float> tmp((size_t)rb.N);
+        for (size_t e = 0; e < tmp.size(); ++e) tmp[e] = (float)r64[e];
+        RCHK(hipMemcpyAsync(G->cr, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice, s));
         launch_vcycle<float>(s, pb, gate);
-        RCHK(hipMemcpyAsync(tmp.data(), G->cz, sizeof(float) * (size_t)g.N, hipMemcpyDeviceToHost, s));
+        RCHK(hipMemcpyAsync(tmp.data(), G->cz, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
-        for (int64_t e = 0; e < g.N; ++e) z_host[e] = tmp[(size_t)e];
+        for (size_t e = 0; e < tmp.size(); ++e) z64[e] = tmp[e];
     } else {
-        RCHK(hipMemcpyAsync(G->cr, r_host, sizeof(double) * (size_t)g.N, hipMemcpyHostToDevice, s));
+        RCHK(hipMemcpyAsync(G->cr, r64.data(), sizeof(double) * r64.size(), hipMemcpyHostToDevice, s));
         launch_vcycle<double>(s, pb, gate);
-        RCHK(hipMemcpyAsync(z_host, G->cz, sizeof(double) * (size_t)g.N, hipMemcpyDeviceToHost, s));
+        RCHK(hipMemcpyAsync(z64.data(), G->cz, sizeof(double) * z64.size(), hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
     }
+    for (int64_t e = 0; e < g.N; ++e) z_host[e] = 0.0;
+    for (int i = 1; i < g.nx - 1; ++i)
+        for (int j = 1; j < g.ny - 1; ++j)
+            for (int k = 1; k < g.nz - 1; ++k) z_host[g.idx(i, j, k)] = z64[(size_t)rb.idx(i, j, k)];
     RCHK(hipGetLastError());
     return PB_OK;
 }
