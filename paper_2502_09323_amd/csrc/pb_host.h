@@ -169,6 +169,26 @@ struct MGData {
     // natural-layout right-hand side and solution of level 0 for callers that work in that
     // layout (the two-level preconditioner of refined grids); made on first use
     void *nat_b = nullptr, *nat_x = nullptr;
+    int ls = 0;                 // first level of the part of the V-cycle run in one block
+    // the hierarchy's device descriptor, read by every kernel, and the launch tables of the
+    // problem solved alone (device; solo_host holds what was copied there)
+    void* dev = nullptr;
+    void* solo_desc = nullptr;
+    int* solo_off = nullptr;
+    std::vector<char> solo_host;
+};
+
+// most problems of one batched multigrid launch
+constexpr int PB_MG_MAX_BATCH = 64;
+
+// launch tables of batched multigrid chunks: pinned staging and device memory, grown on demand
+struct MGBatch {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    pb_alloc_fn alloc = nullptr;
+    pb_free_fn free_fn = nullptr;
+    void* user = nullptr;
 };
 
 struct pb_problem {
@@ -271,6 +291,18 @@ int pbi_mg_begin(pb_problem* pb, hipStream_t s);
 int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample);
 int pbi_mg_finish(pb_problem* pb, hipStream_t s);
 int pbi_mg_levels(const pb_problem* pb);
+// x = 0 and the first residual of a multigrid problem, enqueued on s
+int pbi_mg_start(pb_problem* pb, hipStream_t s);
+// whether a problem can join batched multigrid chunks (more than one level, and no large
+// coarsest level run in launches of its own)
+bool pbi_mg_batchable(const pb_problem* pb);
+// n iterations of every problem of pbs (at most PB_MG_MAX_BATCH, batchable, one precision and
+// the same smoothing counts) in batched launches, then the restart where one is due, and the
+// problems' states into gather[0 .. pbs.size()) (device); ev (optional): 4 events per
+// iteration around its V-cycle and the first level-0 black half-sweep after the coarse
+// correction
+int pbi_mg_batch_chunk(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGBatch* bb, pbk::CGState* gather,
+                       hipEvent_t* ev);
 // one V-cycle of pb's multigrid (set up by pbi_mg_begin, in pb's precision) on level 0:
 // right-hand side pbi_mg_rhs0 (box nodes 0), correction in pbi_mg_sol0 (element type of the
 // precision); gated on st running (status 0, ru 0) when st is given

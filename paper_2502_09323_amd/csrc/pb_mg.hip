@@ -6,7 +6,7 @@
 // Gauss-Seidel -- SSOR with omega = 1 in that order -- as the smoother of a V-cycle:
 //
 //   levels      node I of level l+1 is node 2I of level l, while n-1 is even on every axis
-//               (n >= 5); level 0 reads the operator from the node-code map, the coarser
+//               (n >= 5); level 0 reads the operator from the node codes, the coarser
 //               levels store K along +x, +y, +z and 1/diagonal per node
 //   coarse K    along a coarse edge the two fine edges are in series (K1 K2 / (K1 + K2));
 //               across it the 3 x 3 fine lines around it are averaged with weights
@@ -23,10 +23,19 @@
 //   CG          standard PCG (z = V-cycle(r)) with device-resident scalars; FP64, or FP32
 //               with FP64 reliable updates (x64 += x32, r = b - A x64 in FP64, restart the
 //               recurrence from the true residual, keeping the direction)
+//
+// Level 0 and the CG vectors use a red-black layout (each colour of a z-row in its own
+// segment), the coarser levels the padded natural layout.  Every kernel is a batched launch:
+// a table of block offsets maps each block to one problem of a set (its hierarchy described
+// by a device-resident MGDev) and to a block of that problem's own launch, so one launch per
+// pass serves every problem of the serving loop's multigrid requests, and a solo solve is a
+// set of one.  A problem's blocks do the same work in the same order whatever the set, so a
+// result does not depend on what it was batched with.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "pb_host.h"
@@ -45,18 +54,18 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// one level as the kernels see it
+// one coarse level as the kernels see it
 template <typename T>
 struct Lev {
     Grid g;
-    const T *kx, *ky, *kz;   // levels >= 1: K of the +x, +y, +z edges
-    const T* diag;           // levels >= 1: diagonal
-    const T* dinv;           // 1 / diagonal (every level)
-    T* x;                    // iterate (level 0: the CG vector z)
-    const T* b;              // right-hand side (level 0: the CG residual r)
+    const T *kx, *ky, *kz;   // K of the +x, +y, +z edges
+    const T* diag;           // diagonal
+    const T* dinv;           // 1 / diagonal
+    T* x;                    // iterate
+    const T* b;              // right-hand side
 };
 
-// the level-0 operator from the node-code map
+// the level-0 operator from the natural-layout node codes
 template <typename T>
 struct Op0 {
     const uint32_t* code;
@@ -64,8 +73,211 @@ struct Op0 {
     T kin, kout, mass;
 };
 
-// sum over the six edges of node e of a coarse level of K * v(neighbour), and optionally
-// the diagonal there
+// ---- level 0 in the red-black layout ----------------------------------------------------
+// The vectors of level 0 (the CG vectors, the level's iterate, right-hand side, red residual
+// and 1/D) and a copy of the node codes keep the two colours apart: row (i, j) holds its red
+// nodes in one segment of Sh positions and its black nodes in the next, node k at position
+// k >> 1.  A half-sweep then moves only lines of the colour it updates and of the other
+// colour it reads, instead of whole lines of both.  Box and padding positions hold 0 in every
+// vector (their codes carry C_BOX), so neighbour loads need no branch.  The neighbours of a
+// node are all of the other colour: along x and y at the same position of the adjacent rows,
+// along z at positions (k - 1) >> 1 and (k + 1) >> 1 of its own row.
+
+struct RB {
+    int nx, ny, nz;
+    int Sh;        // positions per colour segment (a multiple of 32: 128-byte aligned segments)
+    int64_t N;     // elements per vector: nx * ny * 2 * Sh
+    __host__ __device__ int64_t at(int i, int j, int c, int m) const
+    {
+        return (((int64_t)i * ny + j) * 2 + c) * Sh + m;
+    }
+    __host__ __device__ int64_t idx(int i, int j, int k) const { return at(i, j, (i + j + k) & 1, k >> 1); }
+};
+
+inline RB rb_of(const Grid& g)
+{
+    RB r;
+    r.nx = g.nx;
+    r.ny = g.ny;
+    r.nz = g.nz;
+    r.Sh = ((g.nz + 1) / 2 + 31) / 32 * 32;
+    r.N = (int64_t)g.nx * g.ny * 2 * r.Sh;
+    return r;
+}
+
+template <typename T>
+struct OpRB {
+    const uint32_t* code;   // red-black layout
+    const T* ck;
+    T kin, kout, mass;
+};
+
+// one problem's hierarchy, solver vectors and state, as every kernel reads it (written once
+// into device memory when the hierarchy is built)
+template <typename T>
+struct MGDev {
+    RB rb;
+    Grid g0;                     // level 0 in the natural layout (solution, right-hand side)
+    OpRB<T> op;
+    Op0<double> op64;            // FP64 operator from the natural codes (true residual)
+    T *cr, *cz, *cp, *cp2, *cq, *cx, *dinv0, *r0;   // level 0: CG r, z, p (two), q, correction x; 1/D; red residual
+    double* x64;                 // FP64 solution (natural layout)
+    const double* rhs;           // FP64 right-hand side (natural layout)
+    int nlev, ls, nu, cs;        // levels, first level of the one-block part (ls == nlev: none)
+    Lev<T> lv[PB_MG_MAX_LEVELS]; // levels >= 1
+    T* r[PB_MG_MAX_LEVELS];      // red residual of levels >= 1
+    CGState* st;
+    double* part;                // [3 * nb] block partial sums
+    double* prz;                 // [nb] r.z partial sums of the last half-sweep
+    int nb;                      // blocks of a level-0 pass
+    int mixed;
+    double rtol2, delta2;
+};
+
+// A batched launch: the problems, and the offsets of their blocks in this pass (P + 1; a
+// problem may have none).
+template <typename T>
+struct Bt {
+    const MGDev<T>* const* d;
+    const int* off;
+    int P;
+};
+
+// the problem of this block and the block's index in that problem's own launch
+__device__ __forceinline__ int bt_find(const int* off, int P, int& local)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = P;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    local = b - off[lo];
+    return lo;
+}
+
+// which kernels run: those of a CG iteration (ru = 0) while the solve is running, those of a
+// restart from the true residual (ru = 1) only while one is in progress; ungated (a V-cycle
+// on its own); or gated on another state (the two-level preconditioner of refined grids)
+struct GateSpec {
+    const CGState* ext;
+    int mode;   // 0 iteration, 1 restart, 2 none, 3 ext (running, ru 0; null: none)
+};
+
+__device__ __forceinline__ bool gated_out(const GateSpec& g, const CGState* st)
+{
+    if (g.mode == 2) return false;
+    if (g.mode == 3) return g.ext && (g.ext->status != 0 || g.ext->ru != 0);
+    return st->status != 0 || st->ru != g.mode;
+}
+
+// The block shape of the per-node passes: 64 lanes along z by 4 rows along y, each thread
+// taking kPlanes x-planes, so that no thread divides to find its node and a launch has few
+// enough blocks that one which finds the iteration stopped costs little.
+constexpr int kPlanes = 4;
+
+struct VB {   // a block of a problem's own 3-D launch
+    int x, y, z;
+};
+
+__device__ __forceinline__ VB vb_of(int local, int gx, int gy)
+{
+    VB v;
+    v.x = local % gx;
+    const int t = local / gx;
+    v.y = t % gy;
+    v.z = t / gy;
+    return v;
+}
+
+__host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz + 1) / 2 + 63) / 64; }
+__host__ __device__ inline int rows_gy(int ny) { return (ny - 2 + 3) / 4; }
+
+inline int rb_blocks(const RB& r) { return rb_gx(r) * rows_gy(r.ny) * ((r.nx - 2 + kPlanes - 1) / kPlanes); }
+
+__device__ __forceinline__ VB vb_rb(const RB& r, int local) { return vb_of(local, rb_gx(r), rows_gy(r.ny)); }
+
+// blocks along z of a coarse-level pass over all interior nodes or over the nodes of one colour
+__host__ __device__ inline int lev_gx(const Grid& g, bool colour)
+{
+    const int nzl = colour ? (g.nz - 1) / 2 : g.nz - 2;
+    return nzl > 0 ? (nzl + 63) / 64 : 1;
+}
+
+inline int lev_blocks(const Grid& g, bool colour)
+{
+    return lev_gx(g, colour) * rows_gy(g.ny) * ((g.nx - 2 + kPlanes - 1) / kPlanes);
+}
+
+__device__ __forceinline__ VB vb_lev(const Grid& g, bool colour, int local)
+{
+    return vb_of(local, lev_gx(g, colour), rows_gy(g.ny));
+}
+
+// red-black: this thread's row and position in plane p of its block; false outside the rows
+__device__ __forceinline__ bool rb_slot(const VB& b, const RB& r, int p, int& i, int& j, int& m)
+{
+    m = b.x * 64 + (int)(threadIdx.x & 63);
+    j = 1 + b.y * 4 + (int)(threadIdx.x >> 6);
+    i = 1 + b.z * kPlanes + p;
+    return i <= r.nx - 2 && j <= r.ny - 2;
+}
+
+// z index of the node of colour c at position m of row (i, j), or -1 if it is not interior
+__device__ __forceinline__ int rb_node(const RB& r, int i, int j, int c, int m)
+{
+    const int k = 2 * m + ((i + j + c) & 1);
+    return (k >= 1 && k <= r.nz - 2) ? k : -1;
+}
+
+// element indices of a node and of its six neighbours (x-, x+, y-, y+, z-, z+)
+struct RBNb {
+    int64_t e, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ RBNb rb_nb(const RB& r, int i, int j, int c, int m, int k)
+{
+    RBNb n;
+    n.e = r.at(i, j, c, m);
+    const int64_t eo = r.at(i, j, 1 - c, m);
+    const int64_t sx = (int64_t)r.ny * 2 * r.Sh, sy = 2 * (int64_t)r.Sh;
+    n.xm = eo - sx;
+    n.xp = eo + sx;
+    n.ym = eo - sy;
+    n.yp = eo + sy;
+    n.zm = eo - ((k & 1) ? 0 : 1);
+    n.zp = eo + ((k & 1) ? 1 : 0);
+    return n;
+}
+
+template <typename T>
+__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const RBNb& n)
+{
+    const uint32_t c = op.code[n.e];
+    stencil::NodeK<T> k;
+    k.xm = stencil::edgeK(op.code[n.xm], 0, op.ck, op.kin, op.kout);
+    k.xp = stencil::edgeK(c, 0, op.ck, op.kin, op.kout);
+    k.ym = stencil::edgeK(op.code[n.ym], 1, op.ck, op.kin, op.kout);
+    k.yp = stencil::edgeK(c, 1, op.ck, op.kin, op.kout);
+    k.zm = stencil::edgeK(op.code[n.zm], 2, op.ck, op.kin, op.kout);
+    k.zp = stencil::edgeK(c, 2, op.ck, op.kin, op.kout);
+    k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
+    return k;
+}
+
+// sum over the six edges of K * v(neighbour)
+template <typename T, typename F>
+__device__ __forceinline__ T rb_sum(const stencil::NodeK<T>& k, const RBNb& n, F v)
+{
+    return ((k.xm * v(n.xm) + k.xp * v(n.xp)) + (k.ym * v(n.ym) + k.yp * v(n.yp))) + (k.zm * v(n.zm) + k.zp * v(n.zp));
+}
+
+// ---- coarse levels (natural layout) ------------------------------------------------------
+
+// sum over the six edges of node e of K * v(neighbour), and optionally the diagonal there
 template <typename T, typename F>
 __device__ __forceinline__ T nsum(const Lev<T>& L, int64_t e, F v, T* D = nullptr)
 {
@@ -76,51 +288,29 @@ __device__ __forceinline__ T nsum(const Lev<T>& L, int64_t e, F v, T* D = nullpt
            (L.kz[e - 1] * v(e - 1) + L.kz[e] * v(e + 1));
 }
 
-// Per-node kernels run on a 3-D grid of 256-thread blocks, 64 lanes along z by 4 rows along
-// y, each block layer covering kPlanes x-planes (a thread takes the same (j, k) slot in each),
-// so that no thread divides to find its node and a launch has few enough blocks that one
-// which finds the iteration stopped costs little.  A colour kernel gives lane m the m-th node
-// of its colour in the row.
-constexpr int kPlanes = 4;
-
-inline dim3 node_grid(const Grid& g, bool colour)
+// interior node of this thread in plane r of its block (all nodes), or -1; red tells its colour
+__device__ __forceinline__ int64_t this_node(const VB& b, const Grid& g, int r, bool& red)
 {
-    const int nzl = colour ? (g.nz - 1) / 2 : g.nz - 2;   // nodes per interior row
-    return dim3((unsigned)std::max(1, (nzl + 63) / 64), (unsigned)((g.ny - 2 + 3) / 4),
-                (unsigned)((g.nx - 2 + kPlanes - 1) / kPlanes));
-}
-
-// interior node of this thread in plane r of its block layer (all nodes), or -1; red tells
-// its colour
-__device__ __forceinline__ int64_t this_node(const Grid& g, int r, bool& red)
-{
-    const int k = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int i = 1 + (int)blockIdx.z * kPlanes + r;
+    const int k = 1 + b.x * 64 + (int)(threadIdx.x & 63);
+    const int j = 1 + b.y * 4 + (int)(threadIdx.x >> 6);
+    const int i = 1 + b.z * kPlanes + r;
     if (k > g.nz - 2 || j > g.ny - 2 || i > g.nx - 2) return -1;
     red = ((i + j + k) & 1) == 0;
     return g.idx(i, j, k);
 }
 
-// interior node of colour c (0 red, 1 black) of this thread in plane r of its block layer,
-// or -1; with its indices
-__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int r, int& i, int& j, int& k)
+// interior node of colour c (0 red, 1 black) of this thread in plane r, or -1; with its indices
+__device__ __forceinline__ int64_t this_colour_node(const VB& b, const Grid& g, int c, int r, int& i, int& j, int& k)
 {
-    const int m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    i = 1 + (int)blockIdx.z * kPlanes + r;
+    const int m = b.x * 64 + (int)(threadIdx.x & 63);
+    j = 1 + b.y * 4 + (int)(threadIdx.x >> 6);
+    i = 1 + b.z * kPlanes + r;
     k = 1 + ((i + j + 1 + c) & 1) + 2 * m;
     if (k > g.nz - 2 || j > g.ny - 2 || i > g.nx - 2) return -1;
     return g.idx(i, j, k);
 }
 
-__device__ __forceinline__ int64_t this_colour_node(const Grid& g, int c, int r)
-{
-    int i, j, k;
-    return this_colour_node(g, c, r, i, j, k);
-}
-
-// the same for the one-block coarsest solve: node t of colour c in (i, j, m) order
+// node t of colour c in (i, j, m) order (one-block passes)
 __device__ __forceinline__ int64_t colour_node(const Grid& g, int c, int t)
 {
     const int M = (g.nz - 1) >> 1;
@@ -153,94 +343,6 @@ __host__ __device__ inline int64_t interior_count(const Grid& g)
     return (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
 }
 
-// which kernels of a chain run: those of a CG iteration (ru = 0) while the solve is running,
-// those of a restart from the true residual (ru = 1) only while one is in progress; with no
-// state (a V-cycle applied on its own) always
-struct Gate {
-    const CGState* st;
-    int ru;
-};
-
-__device__ __forceinline__ bool halted(const Gate& g) { return g.st && (g.st->status != 0 || g.st->ru != g.ru); }
-
-// the first smoothing step from a zero iterate in one pass: red x = b / D, then black
-// x = (b + sum K x_red) / D with the red values formed on the fly
-template <typename T>
-__global__ void __launch_bounds__(256) k_down1(Lev<T> L, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ b = L.b;
-    const T* __restrict__ dinv = L.dinv;
-#pragma unroll
-    for (int r = 0; r < kPlanes; ++r) {
-        bool red;
-        const int64_t e = this_node(L.g, r, red);
-        if (e < 0) continue;
-        if (red) {
-            L.x[e] = b[e] * dinv[e];
-        } else {
-            const T s = nsum<T>(L, e, [&](int64_t n) { return b[n] * dinv[n]; });
-            L.x[e] = (b[e] + s) * dinv[e];
-        }
-    }
-}
-
-// Gauss-Seidel on the nodes of one colour
-template <typename T>
-__global__ void __launch_bounds__(256) k_sweep(Lev<T> L, int c, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-#pragma unroll
-    for (int r = 0; r < kPlanes; ++r) {
-        const int64_t e = this_colour_node(L.g, c, r);
-        if (e < 0) continue;
-        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; });
-        L.x[e] = (L.b[e] + s) * L.dinv[e];
-    }
-}
-
-// residual b - A x at the red nodes (after a black half-sweep the black residual is zero,
-// and the black entries of r stay 0)
-template <typename T>
-__global__ void __launch_bounds__(256) k_resid(Lev<T> L, T* __restrict__ r, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        const int64_t e = this_colour_node(L.g, 0, p);
-        if (e < 0) continue;
-        T D;
-        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; }, &D);
-        r[e] = L.b[e] - (D * x[e] - s);
-    }
-}
-
-// coarse right-hand side P^T r: fine node 2I and its 12 red neighbours (two odd offsets,
-// weight 1/4); the other 14 of the 27 are black, where r is zero
-template <typename T>
-__global__ void __launch_bounds__(256) k_restrict(Grid gf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
-                                                  Gate st)
-{
-    if (halted(st)) return;
-    const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        bool red;
-        const int64_t ec = this_node(gc, p, red);
-        if (ec < 0) continue;
-        const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-        const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-        const int I = 1 + (int)blockIdx.z * kPlanes + p;
-        const int64_t f = gf.idx(2 * I, 2 * J, 2 * K);
-        const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
-        const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
-        const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
-        bc[ec] = r[f] + (T)0.25 * ((xy + xz) + yz);
-    }
-}
-
 // P e at fine node (i, j, k): trilinear from the coarse corners of its coarse cell
 template <typename T>
 __device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec, int i, int j, int k)
@@ -251,27 +353,152 @@ __device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec
     return (T)0.125 * v;
 }
 
-// x += P e at the red nodes: post-smoothing starts with a black half-sweep, which replaces
-// every black value from its red neighbours, so the correction of the black ones is unused
+// the level of a coarse-level pass: l, or the problem's coarsest for l < 0
 template <typename T>
-__global__ void __launch_bounds__(256) k_prolong(Grid gf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
-                                                 Gate st)
+__device__ __forceinline__ int lev_index(const MGDev<T>& D, int l)
 {
-    if (halted(st)) return;
+    return l < 0 ? D.nlev - 1 : l;
+}
+
+// the first smoothing step of coarse level l from a zero iterate: red x = b / D, then black
+// x = (b + sum K x_red) / D with the red values formed on the fly (all interior nodes)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_down1(Bt<T> B, int l, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Lev<T>& L = D.lv[lev_index(D, l)];
+    const VB vb = vb_lev(L.g, false, local);
+    const T* __restrict__ b = L.b;
+    const T* __restrict__ dinv = L.dinv;
+#pragma unroll
+    for (int r = 0; r < kPlanes; ++r) {
+        bool red;
+        const int64_t e = this_node(vb, L.g, r, red);
+        if (e < 0) continue;
+        if (red) {
+            L.x[e] = b[e] * dinv[e];
+        } else {
+            const T s = nsum<T>(L, e, [&](int64_t n) { return b[n] * dinv[n]; });
+            L.x[e] = (b[e] + s) * dinv[e];
+        }
+    }
+}
+
+// Gauss-Seidel on the nodes of colour c of coarse level l
+template <typename T>
+__global__ void __launch_bounds__(256) kb_sweep(Bt<T> B, int l, int c, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Lev<T>& L = D.lv[lev_index(D, l)];
+    const VB vb = vb_lev(L.g, true, local);
+    const T* __restrict__ x = L.x;
+#pragma unroll
+    for (int r = 0; r < kPlanes; ++r) {
+        int i, j, k;
+        const int64_t e = this_colour_node(vb, L.g, c, r, i, j, k);
+        if (e < 0) continue;
+        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; });
+        L.x[e] = (L.b[e] + s) * L.dinv[e];
+    }
+}
+
+// residual b - A x at the red nodes of coarse level l (after a black half-sweep the black
+// residual is zero, and the black entries of r stay 0)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_resid(Bt<T> B, int l, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Lev<T>& L = D.lv[l];
+    T* __restrict__ r = D.r[l];
+    const VB vb = vb_lev(L.g, true, local);
+    const T* __restrict__ x = L.x;
 #pragma unroll
     for (int p = 0; p < kPlanes; ++p) {
         int i, j, k;
-        const int64_t e = this_colour_node(gf, 0, p, i, j, k);
+        const int64_t e = this_colour_node(vb, L.g, 0, p, i, j, k);
         if (e < 0) continue;
-        x[e] += prolong_at(gc, ec, i, j, k);
+        T Dg;
+        const T s = nsum<T>(L, e, [&](int64_t n) { return x[n]; }, &Dg);
+        r[e] = L.b[e] - (Dg * x[e] - s);
+    }
+}
+
+// coarse right-hand side P^T r on level l from the red residual of level l - 1: fine node 2I
+// and its 12 red neighbours (two odd offsets, weight 1/4); the other 14 of the 27 are black.
+// Level 0's residual is in the red-black layout.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_restrict(Bt<T> B, int l, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Grid& gc = D.lv[l].g;
+    T* __restrict__ bc = const_cast<T*>(D.lv[l].b);
+    const VB vb = vb_lev(gc, false, local);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        bool red;
+        const int64_t ec = this_node(vb, gc, p, red);
+        if (ec < 0) continue;
+        const int K = 1 + vb.x * 64 + (int)(threadIdx.x & 63);
+        const int J = 1 + vb.y * 4 + (int)(threadIdx.x >> 6);
+        const int I = 1 + vb.z * kPlanes + p;
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        if (l == 1) {
+            const T* __restrict__ r = D.r0;
+            auto R = [&](int a, int b, int c) { return r[D.rb.idx(i + a, j + b, k + c)]; };
+            const T xy = (R(-1, -1, 0) + R(-1, 1, 0)) + (R(1, -1, 0) + R(1, 1, 0));
+            const T xz = (R(-1, 0, -1) + R(-1, 0, 1)) + (R(1, 0, -1) + R(1, 0, 1));
+            const T yz = (R(0, -1, -1) + R(0, -1, 1)) + (R(0, 1, -1) + R(0, 1, 1));
+            bc[ec] = R(0, 0, 0) + (T)0.25 * ((xy + xz) + yz);
+        } else {
+            const Grid& gf = D.lv[l - 1].g;
+            const T* __restrict__ r = D.r[l - 1];
+            const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
+            const int64_t f = gf.idx(i, j, k);
+            const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
+            const T xz = (r[f - sx - 1] + r[f - sx + 1]) + (r[f + sx - 1] + r[f + sx + 1]);
+            const T yz = (r[f - sy - 1] + r[f - sy + 1]) + (r[f + sy - 1] + r[f + sy + 1]);
+            bc[ec] = r[f] + (T)0.25 * ((xy + xz) + yz);
+        }
+    }
+}
+
+// x += P e at the red nodes of coarse level l from level l + 1: post-smoothing starts with a
+// black half-sweep, which replaces every black value from its red neighbours
+template <typename T>
+__global__ void __launch_bounds__(256) kb_prolong(Bt<T> B, int l, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Lev<T>& L = D.lv[l];
+    const Grid& gc = D.lv[l + 1].g;
+    const T* __restrict__ ec = D.lv[l + 1].x;
+    const VB vb = vb_lev(L.g, true, local);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, k;
+        const int64_t e = this_colour_node(vb, L.g, 0, p, i, j, k);
+        if (e < 0) continue;
+        L.x[e] += prolong_at(gc, ec, i, j, k);
     }
 }
 
 // the coarsest level in one block: red from zero, then (black, red) x cs
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse(Lev<T> L, int cs, Gate st)
+__global__ void __launch_bounds__(256) kb_coarse(Bt<T> B, GateSpec gs)
 {
-    if (halted(st)) return;
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const Lev<T>& L = D.lv[D.nlev - 1];
     const Grid& g = L.g;
     const int n = (int)interior_count(g), nc = (int)colour_threads(g);
     for (int t = threadIdx.x; t < n; t += 256) {
@@ -281,7 +508,7 @@ __global__ void __launch_bounds__(256) k_coarse(Lev<T> L, int cs, Gate st)
     }
     __syncthreads();
     const T* __restrict__ x = L.x;
-    for (int s = 0; s < 2 * cs; ++s) {
+    for (int s = 0; s < 2 * D.cs; ++s) {
         const int c = (s & 1) ? 0 : 1;
         for (int t = threadIdx.x; t < nc; t += 256) {
             const int64_t e = colour_node(g, c, t);
@@ -296,18 +523,10 @@ __global__ void __launch_bounds__(256) k_coarse(Lev<T> L, int cs, Gate st)
 // ---- the small levels of a V-cycle in one block ------------------------------------------
 // Levels of at most kSubcycleNodes unknowns would each cost several launches of a few
 // microseconds that do little work; one block of kSubThreads threads runs the part of the
-// V-cycle below the first such level (its right-hand side given) in one launch, with a block
-// barrier between phases.  Same steps and order as the multi-launch path.
+// V-cycle from level ls down (its right-hand side given) in one launch, with a block barrier
+// between phases.  Same steps and order as the multi-launch path.
 constexpr int kSubcycleNodes = 8192;
 constexpr int kSubThreads = 1024;
-
-template <typename T>
-struct SubLevels {
-    int nl;                          // levels, the last is the coarsest
-    int nu, cs;
-    Lev<T> lv[PB_MG_MAX_LEVELS];
-    T* r[PB_MG_MAX_LEVELS];
-};
 
 template <typename T>
 __device__ __forceinline__ void blk_sweep(const Lev<T>& L, int c)
@@ -335,32 +554,36 @@ __device__ __forceinline__ void blk_red_from_zero(const Lev<T>& L)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate st)
+__global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
 {
-    if (halted(st)) return;
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const int l0 = D.ls, nl = D.nlev;
     // down: pre-smoothing, residual at the red nodes, restriction
-    for (int l = 0; l + 1 < S.nl; ++l) {
-        const Lev<T>& L = S.lv[l];
+    for (int l = l0; l + 1 < nl; ++l) {
+        const Lev<T>& L = D.lv[l];
         blk_red_from_zero(L);
         blk_sweep(L, 1);
-        for (int v = 1; v < S.nu; ++v) {
+        for (int v = 1; v < D.nu; ++v) {
             blk_sweep(L, 0);
             blk_sweep(L, 1);
         }
         const int nc = (int)colour_threads(L.g);
         const T* __restrict__ x = L.x;
+        T* __restrict__ rl = D.r[l];
         for (int t = threadIdx.x; t < nc; t += kSubThreads) {
             const int64_t e = colour_node(L.g, 0, t);
             if (e < 0) continue;
-            T D;
-            const T s = nsum<T>(L, e, [&](int64_t m) { return x[m]; }, &D);
-            S.r[l][e] = L.b[e] - (D * x[e] - s);
+            T Dg;
+            const T s = nsum<T>(L, e, [&](int64_t m) { return x[m]; }, &Dg);
+            rl[e] = L.b[e] - (Dg * x[e] - s);
         }
         __syncthreads();
         const Grid& gf = L.g;
-        const Grid& gc = S.lv[l + 1].g;
-        const T* __restrict__ r = S.r[l];
-        T* bc = const_cast<T*>(S.lv[l + 1].b);
+        const Grid& gc = D.lv[l + 1].g;
+        const T* __restrict__ r = rl;
+        T* bc = const_cast<T*>(D.lv[l + 1].b);
         const int n = (int)interior_count(gc);
         const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
         for (int t = threadIdx.x; t < n; t += kSubThreads) {
@@ -378,30 +601,515 @@ __global__ void __launch_bounds__(kSubThreads) k_subcycle(SubLevels<T> S, Gate s
     }
     // coarsest: red from zero, then (black, red) x cs
     {
-        const Lev<T>& L = S.lv[S.nl - 1];
+        const Lev<T>& L = D.lv[nl - 1];
         blk_red_from_zero(L);
-        for (int v = 0; v < S.cs; ++v) {
+        for (int v = 0; v < D.cs; ++v) {
             blk_sweep(L, 1);
             blk_sweep(L, 0);
         }
     }
     // up: coarse correction, post-smoothing
-    for (int l = S.nl - 2; l >= 0; --l) {
-        const Lev<T>& L = S.lv[l];
-        const Grid& gc = S.lv[l + 1].g;
-        const T* __restrict__ ec = S.lv[l + 1].x;
+    for (int l = nl - 2; l >= l0; --l) {
+        const Lev<T>& L = D.lv[l];
+        const Grid& gc = D.lv[l + 1].g;
+        const T* __restrict__ ec = D.lv[l + 1].x;
         const int n = (int)colour_threads(L.g);
         for (int t = threadIdx.x; t < n; t += kSubThreads) {
-            const int64_t e = colour_node(L.g, 0, t);   // red nodes only, as in k_prolong
+            const int64_t e = colour_node(L.g, 0, t);   // red nodes only, as in kb_prolong
             if (e < 0) continue;
             const int64_t q = e - Z0;
             const int k = (int)(q % L.g.S), j = (int)((q / L.g.S) % L.g.ny), i = (int)(q / ((int64_t)L.g.ny * L.g.S));
             L.x[e] += prolong_at(gc, ec, i, j, k);
         }
         __syncthreads();
-        for (int v = 0; v < S.nu; ++v) {
+        for (int v = 0; v < D.nu; ++v) {
             blk_sweep(L, 1);
             blk_sweep(L, 0);
+        }
+    }
+}
+
+// ---- level 0 (red-black layout) ------------------------------------------------------------
+
+__device__ __forceinline__ void bsum(double* v, int nv, double* sh)
+{
+    for (int t = 0; t < nv; ++t)
+        for (int o = 32; o > 0; o >>= 1) v[t] += __shfl_xor(v[t], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+        for (int t = 0; t < nv; ++t) sh[4 * t + w] = v[t];
+    __syncthreads();
+    for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
+}
+
+// the first smoothing step from a zero iterate: red x = b / D, then black
+// x = (b + sum K x_red) / D with the red values formed on the fly
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_down1(Bt<T> B, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+    const T* __restrict__ b = D.cr;
+    const T* __restrict__ dinv = D.dinv0;
+    T* __restrict__ x = D.cz;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        if (rb_node(R, i, j, 0, m) >= 0) {
+            const int64_t e = R.at(i, j, 0, m);
+            x[e] = b[e] * dinv[e];
+        }
+        const int k = rb_node(R, i, j, 1, m);
+        if (k >= 0) {
+            const RBNb n = rb_nb(R, i, j, 1, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, n);
+            const T s = rb_sum(K, n, [&](int64_t f) { return b[f] * dinv[f]; });
+            x[n.e] = (b[n.e] + s) * dinv[n.e];
+        }
+    }
+}
+
+// Gauss-Seidel on the level-0 nodes of colour c; with dot (the last red half-sweep of a
+// V-cycle) also the partial sums of r.z = b.x over all unknowns (the black ones are final
+// after the black half-sweep), one per block
+template <typename T, bool Dot>
+__global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+    const T* __restrict__ b = D.cr;
+    const T* __restrict__ x = D.cz;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        const int k = rb_node(R, i, j, c, m);
+        if (k >= 0) {
+            const RBNb n = rb_nb(R, i, j, c, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, n);
+            const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
+            const T xn = (b[n.e] + s) * D.dinv0[n.e];
+            D.cz[n.e] = xn;
+            if constexpr (Dot) v[0] += (double)b[n.e] * (double)xn;
+        }
+        if constexpr (Dot) {
+            if (rb_node(R, i, j, 1 - c, m) >= 0) {
+                const int64_t eb = R.at(i, j, 1 - c, m);
+                v[0] += (double)b[eb] * (double)x[eb];
+            }
+        }
+    }
+    if constexpr (Dot) {
+        bsum(v, 1, sh);
+        if (threadIdx.x == 0) D.prz[local] = v[0];
+    }
+}
+
+// residual b - A x at the red nodes of level 0 (the black residual is zero right after a
+// black half-sweep), in the red segments of r0
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_resid(Bt<T> B, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+    const T* __restrict__ x = D.cz;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        const int k = rb_node(R, i, j, 0, m);
+        if (k < 0) continue;
+        const RBNb n = rb_nb(R, i, j, 0, m, k);
+        const stencil::NodeK<T> K = rb_k(D.op, n);
+        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
+        D.r0[n.e] = D.cr[n.e] - (K.diag() * x[n.e] - s);
+    }
+}
+
+// x += P e at the red nodes of level 0 from level 1 (the black half-sweep that follows
+// replaces the black ones)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_prolong(Bt<T> B, GateSpec gs)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+    const Grid& gc = D.lv[1].g;
+    const T* __restrict__ ec = D.lv[1].x;
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        const int k = rb_node(R, i, j, 0, m);
+        if (k < 0) continue;
+        D.cz[R.at(i, j, 0, m)] += prolong_at(gc, ec, i, j, k);
+    }
+}
+
+// ---- CG over the level-0 unknowns ----------------------------------------------------------
+
+// The search direction is double buffered: an iteration with iter_count = ic reads the old
+// direction from buffer ic & 1 and writes the new one to the other (iter_count counts the
+// iterations that ran, so a restart between two iterations keeps the pairing).
+template <typename T>
+__device__ __forceinline__ const T* p_old(const CGState* st, const T* p0, const T* p1)
+{
+    return (st->iter_count & 1) ? p1 : p0;
+}
+template <typename T>
+__device__ __forceinline__ T* p_new(const CGState* st, T* p0, T* p1)
+{
+    return (st->iter_count & 1) ? p0 : p1;
+}
+
+// p = z + beta p_old and q = A p at both nodes of each position in one pass (the new direction
+// at the neighbours is formed on the fly from z and p_old, which box positions hold as 0);
+// partial sums of p.q, one per block
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const CGState* st = D.st;
+    if (st->status != 0) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+    const T* __restrict__ z = D.cz;
+    const T* __restrict__ po = p_old(st, (const T*)D.cp, (const T*)D.cp2);
+    T* __restrict__ pn = p_new(st, D.cp, D.cp2);
+    const T beta = (T)st->beta;
+    auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
+    double v[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(R, i, j, c, m);
+            if (k < 0) continue;
+            const RBNb n = rb_nb(R, i, j, c, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, n);
+            const T pe = pd(n.e);
+            const T qe = K.diag() * pe - rb_sum(K, n, pd);
+            pn[n.e] = pe;
+            D.cq[n.e] = qe;
+            v[0] += (double)pe * (double)qe;
+        }
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) D.part[local] = v[0];
+}
+
+// x += alpha p, r -= alpha q over every element (box and padding positions hold 0 in p, q and
+// r); partial sums of r.r (after the nb slots of the p.q sums)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const CGState* st = D.st;
+    if (st->status != 0) return;
+    const T* __restrict__ p = p_new(st, D.cp, D.cp2);
+    T* __restrict__ x = D.cx;
+    T* __restrict__ r = D.cr;
+    const T* __restrict__ q = D.cq;
+    const T a = (T)st->alpha;
+    double v[1] = {0.0};
+    const int64_t step = (int64_t)D.nb * 256;
+    for (int64_t e = (int64_t)local * 256 + threadIdx.x; e < D.rb.N; e += step) {
+        x[e] += a * p[e];
+        const T rv = r[e] - a * q[e];
+        r[e] = rv;
+        v[0] += (double)rv * (double)rv;
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) D.part[D.nb + local] = v[0];
+}
+
+// partial sums of r.z over every element (a single-level V-cycle forms no r.z itself)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_dot(Bt<T> B, GateSpec gs)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (gated_out(gs, D.st)) return;
+    double v[1] = {0.0};
+    const int64_t step = (int64_t)D.nb * 256;
+    for (int64_t e = (int64_t)local * 256 + threadIdx.x; e < D.rb.N; e += step)
+        v[0] += (double)D.cr[e] * (double)D.cz[e];
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) D.part[local] = v[0];
+}
+
+// the FP64 solution (natural layout) += the correction in the red-black layout, which is then
+// cleared (with force, or where the iteration stopped for a restart)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_fold(Bt<T> B, int force)
+{
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (!force && D.st->status != 3) return;
+    const RB& R = D.rb;
+    const VB vb = vb_rb(R, local);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(R, i, j, c, m);
+            if (k < 0) continue;
+            const int64_t e = R.at(i, j, c, m);
+            D.x64[D.g0.idx(i, j, k)] += (double)D.cx[e];
+            D.cx[e] = (T)0;
+        }
+    }
+}
+
+// r = b - A x in FP64 from the natural-layout solution, right-hand side and codes, stored in
+// the element type in the red-black layout; partial sums of the FP64 r.r in the third slot
+// range, one per block
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (!force && D.st->status != 3) return;
+    const RB& R = D.rb;
+    const Grid& g = D.g0;
+    const VB vb = vb_rb(R, local);
+    const double* __restrict__ x = D.x64;
+    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, R, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(R, i, j, c, m);
+            if (k < 0) continue;
+            const int64_t e = g.idx(i, j, k);
+            const stencil::NodeK<double> K =
+                stencil::node_k(g, D.op64.code, D.op64.ck, D.op64.kin, D.op64.kout, D.op64.mass, e);
+            const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
+                             (K.zm * x[e - 1] + K.zp * x[e + 1]);
+            const double rv = D.rhs[e] - (K.diag() * x[e] - s);
+            D.cr[R.at(i, j, c, m)] = (T)rv;
+            v[0] += rv * rv;
+        }
+    }
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) D.part[2 * D.nb + local] = v[0];
+}
+
+// ---- the scalar steps, one block per problem ------------------------------------------------
+
+// sum of n partials in a fixed order (eight interleaved accumulators per thread keep many
+// loads in flight)
+__device__ __forceinline__ double psum(const double* __restrict__ a, int n)
+{
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int t = threadIdx.x;
+    for (; t + 7 * 256 < n; t += 8 * 256)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += a[t + u * 256];
+    for (int u = 0; t < n; t += 256, ++u) s[u & 7] += a[t];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_alpha(Bt<T> B)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    CGState* st = D.st;
+    if (st->status != 0) return;
+    double v[1] = {psum(D.part, D.nb)};
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) {
+        const double pq = v[0];
+        st->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else {
+            st->alpha = st->gamma / pq;
+        }
+    }
+}
+
+// mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
+// recursive r.r (status = stop_status once r.r <= stop2, or <= trig2 in mixed precision);
+// mode 1 (first residual): beta = 0; mode 2 (after a residual replacement): the direction
+// update that the stopped step skipped takes beta = r'.z' / (r.z of the step before).
+// The r.z partials are those of the fused last half-sweep (prz), or of the dot pass (part)
+// for a single-level V-cycle.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_beta(Bt<T> B, int mode)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    CGState* st = D.st;
+    if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
+    double v[2] = {psum(D.nlev > 1 ? D.prz : D.part, D.nb), mode == 0 ? psum(D.part + D.nb, D.nb) : 0.0};
+    bsum(v, 2, sh);
+    if (threadIdx.x == 0) {
+        const double gm = v[0];
+        if (mode == 0) {
+            const double rr = v[1];
+            st->iter_count += 1;
+            st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
+            st->rr = rr;
+            if (!isfinite(gm) || !isfinite(rr)) {
+                st->status = 2;
+                st->iters = st->iter_count;
+            } else if (rr <= st->stop2 || rr <= st->trig2) {
+                st->status = st->stop_status;
+                st->iters = st->iter_count;
+            }
+        } else if (mode == 1) {
+            st->beta = 0.0;
+            st->ru = 0;
+        } else {
+            st->beta = (st->gamma > 0.0 && st->beta > 0.0) ? gm * (st->beta / st->gamma) : 0.0;
+            st->ru = 0;
+        }
+        st->gamma = gm;
+        // the V-cycle is positive definite: r.z > 0 unless r = 0
+        if (!isfinite(gm) || !(gm > 0.0)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        }
+    }
+}
+
+// after a true residual: the FP64 norm decides convergence; with init it sets the goals.  A
+// restart that goes on sets ru, which lets the V-cycle, r.z and beta of the restart run.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_ru_fin(Bt<T> B, int init, int force)
+{
+    __shared__ double sh[8];
+    int local;
+    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    CGState* st = D.st;
+    if (!force && st->status != 3) return;
+    double v[1] = {psum(D.part + 2 * D.nb, D.nb)};
+    bsum(v, 1, sh);
+    if (threadIdx.x == 0) {
+        const double rr64 = v[0];
+        if (init) {
+            st->alpha = st->beta = st->gamma = st->pq = 0.0;
+            st->bnorm2 = rr64;
+            st->goal64 = D.rtol2 * rr64;
+            st->stop2 = D.rtol2 * rr64;
+            st->delta2 = D.mixed ? D.delta2 : 0.0;
+            st->stop_status = D.mixed ? 3 : 1;
+            st->iters = st->iter_count = st->ru = st->n_ru = 0;
+        } else {
+            st->n_ru += 1;
+        }
+        st->rr = rr64;
+        st->rr64 = rr64;
+        st->trig2 = st->delta2 * rr64;
+        if (!isfinite(rr64)) {
+            st->status = 2;
+            st->iters = st->iter_count;
+        } else if (rr64 <= st->goal64) {
+            st->status = 1;
+            st->iters = st->iter_count;
+        } else {
+            st->status = 0;
+        }
+        st->ru = st->status == 0 ? 1 : 0;
+    }
+}
+
+// every problem's state into one array (the serving loop reads them back in one copy)
+template <typename T>
+__global__ void __launch_bounds__(64) kb_gather(Bt<T> B, CGState* out)
+{
+    int local;
+    const int p = bt_find(B.off, B.P, local);
+    const MGDev<T>& D = *B.d[p];
+    const int n = (int)(sizeof(CGState) / sizeof(int));
+    const int* s = (const int*)D.st;
+    int* o = (int*)(out + p);
+    for (int t = threadIdx.x; t < n; t += 64) o[t] = s[t];
+}
+
+// ---- set-up and test helpers (one problem) ------------------------------------------------
+
+// codes in the red-black layout (C_BOX on box and padding positions)
+__global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* __restrict__ code, uint32_t* __restrict__ out)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < r.N; t += (int64_t)gridDim.x * 256) {
+        const int m = (int)(t % r.Sh);
+        const int64_t q = t / r.Sh;
+        const int c = (int)(q & 1);
+        const int64_t row = q >> 1;
+        const int j = (int)(row % r.ny), i = (int)(row / r.ny);
+        const int k = 2 * m + ((i + j + c) & 1);
+        out[t] = k < r.nz ? code[g.idx(i, j, k)] : C_BOX;
+    }
+}
+
+// 1 / diagonal of the level-0 unknowns in the red-black layout (0 elsewhere)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_diag0(Grid g, RB r, Op0<T> op, T* __restrict__ dinv)
+{
+    const VB vb = vb_rb(r, (int)blockIdx.x);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            dinv[r.at(i, j, c, m)] =
+                (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, g.idx(i, j, k)).diag();
+        }
+    }
+}
+
+// natural-layout level-0 vector <-> red-black layout (interior nodes; the two-level
+// preconditioner of refined grids hands its coarse right-hand side over in the natural layout)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rb_convert(Grid g, RB r, T* __restrict__ nat, T* __restrict__ rbv, int to_rb,
+                                                    GateSpec gs, const CGState* st)
+{
+    if (gated_out(gs, st)) return;
+    const VB vb = vb_rb(r, (int)blockIdx.x);
+#pragma unroll
+    for (int p = 0; p < kPlanes; ++p) {
+        int i, j, m;
+        if (!rb_slot(vb, r, p, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int k = rb_node(r, i, j, c, m);
+            if (k < 0) continue;
+            if (to_rb)
+                rbv[r.at(i, j, c, m)] = nat[g.idx(i, j, k)];
+            else
+                nat[g.idx(i, j, k)] = rbv[r.at(i, j, c, m)];
         }
     }
 }
@@ -498,575 +1206,6 @@ __global__ void __launch_bounds__(256) k_level_diag(Grid g, const double* kx, co
     dinvT[e] = (T)d;
 }
 
-// ---- CG over the level-0 unknowns ----------------------------------------------------------
-
-__device__ __forceinline__ void bsum(double* v, int nv, double* sh)
-{
-    for (int t = 0; t < nv; ++t)
-        for (int o = 32; o > 0; o >>= 1) v[t] += __shfl_xor(v[t], o, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0)
-        for (int t = 0; t < nv; ++t) sh[4 * t + w] = v[t];
-    __syncthreads();
-    for (int t = 0; t < nv; ++t) v[t] = (sh[4 * t] + sh[4 * t + 1]) + (sh[4 * t + 2] + sh[4 * t + 3]);
-}
-
-// The search direction is double buffered: an iteration with iter_count = ic reads the old
-// direction from buffer ic & 1 and writes the new one to the other (iter_count counts the
-// iterations that ran, so a restart between two iterations keeps the pairing).
-template <typename T>
-__device__ __forceinline__ const T* p_old(const CGState* st, const T* p0, const T* p1)
-{
-    return (st->iter_count & 1) ? p1 : p0;
-}
-template <typename T>
-__device__ __forceinline__ T* p_new(const CGState* st, T* p0, T* p1)
-{
-    return (st->iter_count & 1) ? p0 : p1;
-}
-
-// ---- level 0 in the red-black layout ----------------------------------------------------
-// The vectors of level 0 (the CG vectors, the level's iterate, right-hand side, red residual
-// and 1/D) and a copy of the node codes keep the two colours apart: row (i, j) holds its red
-// nodes in one segment of Sh positions and its black nodes in the next, node k at position
-// k >> 1.  A half-sweep then moves only lines of the colour it updates and of the other
-// colour it reads, instead of whole lines of both.  Box and padding positions hold 0 in every
-// vector (their codes carry C_BOX), so neighbour loads need no branch.  The neighbours of a
-// node are all of the other colour: along x and y at the same position of the adjacent rows,
-// along z at positions (k - 1) >> 1 and (k + 1) >> 1 of its own row.
-
-struct RB {
-    int nx, ny, nz;
-    int Sh;        // positions per colour segment (a multiple of 32: 128-byte aligned segments)
-    int64_t N;     // elements per vector: nx * ny * 2 * Sh
-    __host__ __device__ int64_t at(int i, int j, int c, int m) const
-    {
-        return (((int64_t)i * ny + j) * 2 + c) * Sh + m;
-    }
-    __host__ __device__ int64_t idx(int i, int j, int k) const { return at(i, j, (i + j + k) & 1, k >> 1); }
-};
-
-inline RB rb_of(const Grid& g)
-{
-    RB r;
-    r.nx = g.nx;
-    r.ny = g.ny;
-    r.nz = g.nz;
-    r.Sh = ((g.nz + 1) / 2 + 31) / 32 * 32;
-    r.N = (int64_t)g.nx * g.ny * 2 * r.Sh;
-    return r;
-}
-
-// the level-0 operator read from the codes in the red-black layout
-template <typename T>
-struct OpRB {
-    const uint32_t* code;
-    const T* ck;
-    T kin, kout, mass;
-};
-
-// element indices of a node and of its six neighbours (x-, x+, y-, y+, z-, z+)
-struct RBNb {
-    int64_t e, xm, xp, ym, yp, zm, zp;
-};
-
-__device__ __forceinline__ RBNb rb_nb(const RB& r, int i, int j, int c, int m, int k)
-{
-    RBNb n;
-    n.e = r.at(i, j, c, m);
-    const int64_t eo = r.at(i, j, 1 - c, m);
-    const int64_t sx = (int64_t)r.ny * 2 * r.Sh, sy = 2 * (int64_t)r.Sh;
-    n.xm = eo - sx;
-    n.xp = eo + sx;
-    n.ym = eo - sy;
-    n.yp = eo + sy;
-    n.zm = eo - ((k & 1) ? 0 : 1);
-    n.zp = eo + ((k & 1) ? 1 : 0);
-    return n;
-}
-
-template <typename T>
-__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const RBNb& n)
-{
-    const uint32_t c = op.code[n.e];
-    stencil::NodeK<T> k;
-    k.xm = stencil::edgeK(op.code[n.xm], 0, op.ck, op.kin, op.kout);
-    k.xp = stencil::edgeK(c, 0, op.ck, op.kin, op.kout);
-    k.ym = stencil::edgeK(op.code[n.ym], 1, op.ck, op.kin, op.kout);
-    k.yp = stencil::edgeK(c, 1, op.ck, op.kin, op.kout);
-    k.zm = stencil::edgeK(op.code[n.zm], 2, op.ck, op.kin, op.kout);
-    k.zp = stencil::edgeK(c, 2, op.ck, op.kin, op.kout);
-    k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
-    return k;
-}
-
-// sum over the six edges of K * v(neighbour), in the order of the natural-layout kernels
-template <typename T, typename F>
-__device__ __forceinline__ T rb_sum(const stencil::NodeK<T>& k, const RBNb& n, F v)
-{
-    return ((k.xm * v(n.xm) + k.xp * v(n.xp)) + (k.ym * v(n.ym) + k.yp * v(n.yp))) + (k.zm * v(n.zm) + k.zp * v(n.zp));
-}
-
-// 3-D launch over (position, row, x-plane group): 64 positions by 4 rows per block, kPlanes
-// x-planes per thread
-inline dim3 rb_grid(const RB& r)
-{
-    const int mh = (r.nz + 1) / 2;
-    return dim3((unsigned)((mh + 63) / 64), (unsigned)((r.ny - 2 + 3) / 4), (unsigned)((r.nx - 2 + kPlanes - 1) / kPlanes));
-}
-
-// this thread's row and position in plane p of its block layer; false outside the interior rows
-__device__ __forceinline__ bool rb_slot(const RB& r, int p, int& i, int& j, int& m)
-{
-    m = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    j = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    i = 1 + (int)blockIdx.z * kPlanes + p;
-    return i <= r.nx - 2 && j <= r.ny - 2;
-}
-
-// z index of the node of colour c at position m of row (i, j), or -1 if it is not interior
-__device__ __forceinline__ int rb_node(const RB& r, int i, int j, int c, int m)
-{
-    const int k = 2 * m + ((i + j + c) & 1);
-    return (k >= 1 && k <= r.nz - 2) ? k : -1;
-}
-
-__device__ __forceinline__ unsigned block_linear() { return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x; }
-
-// codes in the red-black layout (C_BOX on box and padding positions)
-__global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* __restrict__ code, uint32_t* __restrict__ out)
-{
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < r.N; t += (int64_t)gridDim.x * 256) {
-        const int m = (int)(t % r.Sh);
-        const int64_t q = t / r.Sh;
-        const int c = (int)(q & 1);
-        const int64_t row = q >> 1;
-        const int j = (int)(row % r.ny), i = (int)(row / r.ny);
-        const int k = 2 * m + ((i + j + c) & 1);
-        out[t] = k < r.nz ? code[g.idx(i, j, k)] : C_BOX;
-    }
-}
-
-// 1 / diagonal of the level-0 unknowns in the red-black layout (0 elsewhere)
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_diag0(Grid g, RB r, Op0<T> op, T* __restrict__ dinv)
-{
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(r, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(r, i, j, c, m);
-            if (k < 0) continue;
-            dinv[r.at(i, j, c, m)] =
-                (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, g.idx(i, j, k)).diag();
-        }
-    }
-}
-
-// level-0 right-hand side b and iterate x (the CG vectors r and z), with 1/D
-template <typename T>
-struct Lev0 {
-    RB r;
-    const T* b;
-    const T* dinv;
-    T* x;
-};
-
-// the first smoothing step from a zero iterate: red x = b / D, then black
-// x = (b + sum K x_red) / D with the red values formed on the fly
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_down1(Lev0<T> L, OpRB<T> op, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ b = L.b;
-    const T* __restrict__ dinv = L.dinv;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(L.r, p, i, j, m)) continue;
-        if (rb_node(L.r, i, j, 0, m) >= 0) {
-            const int64_t e = L.r.at(i, j, 0, m);
-            L.x[e] = b[e] * dinv[e];
-        }
-        const int k = rb_node(L.r, i, j, 1, m);
-        if (k >= 0) {
-            const RBNb n = rb_nb(L.r, i, j, 1, m, k);
-            const stencil::NodeK<T> K = rb_k(op, n);
-            const T s = rb_sum(K, n, [&](int64_t f) { return b[f] * dinv[f]; });
-            L.x[n.e] = (b[n.e] + s) * dinv[n.e];
-        }
-    }
-}
-
-// Gauss-Seidel on the nodes of colour c
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_sweep(Lev0<T> L, OpRB<T> op, int c, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(L.r, p, i, j, m)) continue;
-        const int k = rb_node(L.r, i, j, c, m);
-        if (k < 0) continue;
-        const RBNb n = rb_nb(L.r, i, j, c, m, k);
-        const stencil::NodeK<T> K = rb_k(op, n);
-        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
-        L.x[n.e] = (L.b[n.e] + s) * L.dinv[n.e];
-    }
-}
-
-// residual b - A x at the red nodes (the black residual is zero right after a black
-// half-sweep), in the red segments of rr
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_resid(Lev0<T> L, OpRB<T> op, T* __restrict__ rr, Gate st)
-{
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(L.r, p, i, j, m)) continue;
-        const int k = rb_node(L.r, i, j, 0, m);
-        if (k < 0) continue;
-        const RBNb n = rb_nb(L.r, i, j, 0, m, k);
-        const stencil::NodeK<T> K = rb_k(op, n);
-        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
-        rr[n.e] = L.b[n.e] - (K.diag() * x[n.e] - s);
-    }
-}
-
-// coarse right-hand side P^T r from the red residual of level 0: fine node 2I and its 12
-// red neighbours (two odd offsets, weight 1/4); the other 14 of the 27 are black
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_restrict(RB rf, const T* __restrict__ r, Grid gc, T* __restrict__ bc,
-                                                     Gate st)
-{
-    if (halted(st)) return;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        bool red;
-        const int64_t ec = this_node(gc, p, red);
-        if (ec < 0) continue;
-        const int K = 1 + (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-        const int J = 1 + (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-        const int I = 1 + (int)blockIdx.z * kPlanes + p;
-        const int i = 2 * I, j = 2 * J, k = 2 * K;
-        auto R = [&](int a, int b, int c) { return r[rf.idx(i + a, j + b, k + c)]; };
-        const T xy = (R(-1, -1, 0) + R(-1, 1, 0)) + (R(1, -1, 0) + R(1, 1, 0));
-        const T xz = (R(-1, 0, -1) + R(-1, 0, 1)) + (R(1, 0, -1) + R(1, 0, 1));
-        const T yz = (R(0, -1, -1) + R(0, -1, 1)) + (R(0, 1, -1) + R(0, 1, 1));
-        bc[ec] = R(0, 0, 0) + (T)0.25 * ((xy + xz) + yz);
-    }
-}
-
-// x += P e at the red nodes of level 0 (the black half-sweep that follows replaces the black ones)
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_prolong(RB rf, T* __restrict__ x, Grid gc, const T* __restrict__ ec,
-                                                    Gate st)
-{
-    if (halted(st)) return;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(rf, p, i, j, m)) continue;
-        const int k = rb_node(rf, i, j, 0, m);
-        if (k < 0) continue;
-        x[rf.at(i, j, 0, m)] += prolong_at(gc, ec, i, j, k);
-    }
-}
-
-// the last red half-sweep of a V-cycle on level 0 and the partial sums of r.z = b.x over all
-// unknowns (the black ones are final after the black half-sweep), one per block
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_sweep_dot(Lev0<T> L, OpRB<T> op, Gate st, double* part)
-{
-    __shared__ double sh[8];
-    if (halted(st)) return;
-    const T* __restrict__ x = L.x;
-    double v[1] = {0.0};
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(L.r, p, i, j, m)) continue;
-        const int k = rb_node(L.r, i, j, 0, m);
-        if (k >= 0) {
-            const RBNb n = rb_nb(L.r, i, j, 0, m, k);
-            const stencil::NodeK<T> K = rb_k(op, n);
-            const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
-            const T xn = (L.b[n.e] + s) * L.dinv[n.e];
-            L.x[n.e] = xn;
-            v[0] += (double)L.b[n.e] * (double)xn;
-        }
-        if (rb_node(L.r, i, j, 1, m) >= 0) {
-            const int64_t eb = L.r.at(i, j, 1, m);
-            v[0] += (double)L.b[eb] * (double)x[eb];
-        }
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[block_linear()] = v[0];
-}
-
-// the single-level case (no coarser grid): red from zero, black, then (red, black) ... as the
-// coarsest level runs, over the red-black level 0
-// (k_rb_down1 gives red + black; the sweeps follow on the host side)
-
-// ---- CG over the level-0 unknowns (red-black layout) ---------------------------------------
-
-// p = z + beta p_old and q = A p at both nodes of each position in one pass (the new direction
-// at the neighbours is formed on the fly from z and p_old, which box positions hold as 0);
-// partial sums of p.q, one per block
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_apply(RB r, OpRB<T> op, const T* __restrict__ z, T* p0, T* p1,
-                                                  T* __restrict__ q, double* part, const CGState* st)
-{
-    __shared__ double sh[8];
-    if (st->status != 0) return;
-    const T* __restrict__ po = p_old(st, (const T*)p0, (const T*)p1);
-    T* __restrict__ pn = p_new(st, p0, p1);
-    const T beta = (T)st->beta;
-    auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
-    double v[1] = {0.0};
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(r, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(r, i, j, c, m);
-            if (k < 0) continue;
-            const RBNb n = rb_nb(r, i, j, c, m, k);
-            const stencil::NodeK<T> K = rb_k(op, n);
-            const T pe = pd(n.e);
-            const T qe = K.diag() * pe - rb_sum(K, n, pd);
-            pn[n.e] = pe;
-            q[n.e] = qe;
-            v[0] += (double)pe * (double)qe;
-        }
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[block_linear()] = v[0];
-}
-
-// x += alpha p, r -= alpha q over every element (box and padding positions hold 0 in p, q and
-// r); partial sums of r.r (after the nb slots of the p.q sums)
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_update(int64_t N, T* __restrict__ x, T* __restrict__ r, T* p0, T* p1,
-                                                   const T* __restrict__ q, double* part, int nb, const CGState* st)
-{
-    __shared__ double sh[8];
-    if (st->status != 0) return;
-    const T* __restrict__ p = p_new(st, p0, p1);
-    const T a = (T)st->alpha;
-    double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-        x[e] += a * p[e];
-        const T rv = r[e] - a * q[e];
-        r[e] = rv;
-        v[0] += (double)rv * (double)rv;
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[nb + blockIdx.x] = v[0];
-}
-
-// partial sums of r.z over every element
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_dot(int64_t N, const T* __restrict__ r, const T* __restrict__ z,
-                                                double* part, Gate st)
-{
-    __shared__ double sh[8];
-    if (halted(st)) return;
-    double v[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256)
-        v[0] += (double)r[e] * (double)z[e];
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-}
-
-// the FP64 solution (natural layout) += the correction in the red-black layout, which is then
-// cleared
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_fold(Grid g, RB r, double* __restrict__ x64, T* __restrict__ xc,
-                                                 const CGState* st, int force)
-{
-    if (!force && st->status != 3) return;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(r, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(r, i, j, c, m);
-            if (k < 0) continue;
-            const int64_t e = r.at(i, j, c, m);
-            x64[g.idx(i, j, k)] += (double)xc[e];
-            xc[e] = (T)0;
-        }
-    }
-}
-
-// r = b - A x in FP64 from the natural-layout solution, right-hand side and codes, stored in
-// the element type in the red-black layout; partial sums of the FP64 r.r in the third slot
-// range, one per block
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_true_res(Grid g, RB r, Op0<double> op, const double* __restrict__ x,
-                                                     const double* __restrict__ b, T* __restrict__ res, double* part,
-                                                     int nb, const CGState* st, int force)
-{
-    __shared__ double sh[8];
-    if (!force && st->status != 3) return;
-    const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
-    double v[1] = {0.0};
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(r, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(r, i, j, c, m);
-            if (k < 0) continue;
-            const int64_t e = g.idx(i, j, k);
-            const stencil::NodeK<double> K = stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, e);
-            const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
-                             (K.zm * x[e - 1] + K.zp * x[e + 1]);
-            const double rv = b[e] - (K.diag() * x[e] - s);
-            res[r.at(i, j, c, m)] = (T)rv;
-            v[0] += rv * rv;
-        }
-    }
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) part[2 * nb + block_linear()] = v[0];
-}
-
-// natural-layout level-0 vector <-> red-black layout (interior nodes; the two-level
-// preconditioner of refined grids hands its coarse right-hand side over in the natural layout)
-template <typename T>
-__global__ void __launch_bounds__(256) k_rb_convert(Grid g, RB r, T* __restrict__ nat, T* __restrict__ rbv, int to_rb,
-                                                    Gate st)
-{
-    if (halted(st)) return;
-#pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
-        int i, j, m;
-        if (!rb_slot(r, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(r, i, j, c, m);
-            if (k < 0) continue;
-            if (to_rb)
-                rbv[r.at(i, j, c, m)] = nat[g.idx(i, j, k)];
-            else
-                nat[g.idx(i, j, k)] = rbv[r.at(i, j, c, m)];
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_alpha(const double* part, int nb, CGState* st)
-{
-    __shared__ double sh[8];
-    if (st->status != 0) return;
-    double v[1] = {0.0};
-    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[t];
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) {
-        const double pq = v[0];
-        st->pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            st->status = 2;
-            st->iters = st->iter_count;
-        } else {
-            st->alpha = st->gamma / pq;
-        }
-    }
-}
-
-// mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
-// recursive r.r (status = stop_status once r.r <= stop2, or <= trig2 in mixed precision);
-// mode 1 (first residual): beta = 0; mode 2 (after a residual replacement): the direction
-// update that the stopped step skipped takes beta = r'.z' / (r.z of the step before)
-// The r.z partials are prz[0 .. nrz) (those of the fused last half-sweep), or part[0 .. nb).
-__global__ void __launch_bounds__(256) k_beta(const double* part, int nb, CGState* st, int mode,
-                                              const double* prz, int nrz)
-{
-    __shared__ double sh[8];
-    if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
-    if (!prz) {
-        prz = part;
-        nrz = nb;
-    }
-    double v[2] = {0.0, 0.0};
-    for (int t = threadIdx.x; t < nrz; t += 256) v[0] += prz[t];
-    if (mode == 0)
-        for (int t = threadIdx.x; t < nb; t += 256) v[1] += part[nb + t];
-    bsum(v, 2, sh);
-    if (threadIdx.x == 0) {
-        const double gm = v[0];
-        if (mode == 0) {
-            const double rr = v[1];
-            st->iter_count += 1;
-            st->beta = st->gamma > 0.0 ? gm / st->gamma : 0.0;
-            st->rr = rr;
-            if (!isfinite(gm) || !isfinite(rr)) {
-                st->status = 2;
-                st->iters = st->iter_count;
-            } else if (rr <= st->stop2 || rr <= st->trig2) {
-                st->status = st->stop_status;
-                st->iters = st->iter_count;
-            }
-        } else if (mode == 1) {
-            st->beta = 0.0;
-            st->ru = 0;
-        } else {
-            st->beta = (st->gamma > 0.0 && st->beta > 0.0) ? gm * (st->beta / st->gamma) : 0.0;
-            st->ru = 0;
-        }
-        st->gamma = gm;
-        // the V-cycle is positive definite: r.z > 0 unless r = 0
-        if (!isfinite(gm) || !(gm > 0.0)) {
-            st->status = 2;
-            st->iters = st->iter_count;
-        }
-    }
-}
-
-// after a true residual: the FP64 norm decides convergence; with init it sets the goals.  A
-// restart that goes on sets ru, which lets the V-cycle, r.z and beta of the restart run.
-__global__ void __launch_bounds__(256) k_ru_fin(const double* part, int nb, CGState* st, int init, int mixed,
-                                                double rtol2, double delta2, int force)
-{
-    __shared__ double sh[8];
-    if (!force && st->status != 3) return;
-    double v[1] = {0.0};
-    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[2 * nb + t];
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) {
-        const double rr64 = v[0];
-        if (init) {
-            st->alpha = st->beta = st->gamma = st->pq = 0.0;
-            st->bnorm2 = rr64;
-            st->goal64 = rtol2 * rr64;
-            st->stop2 = rtol2 * rr64;
-            st->delta2 = mixed ? delta2 : 0.0;
-            st->stop_status = mixed ? 3 : 1;
-            st->iters = st->iter_count = st->ru = st->n_ru = 0;
-        } else {
-            st->n_ru += 1;
-        }
-        st->rr = rr64;
-        st->rr64 = rr64;
-        st->trig2 = st->delta2 * rr64;
-        if (!isfinite(rr64)) {
-            st->status = 2;
-            st->iters = st->iter_count;
-        } else if (rr64 <= st->goal64) {
-            st->status = 1;
-            st->iters = st->iter_count;
-        } else {
-            st->status = 0;
-        }
-        st->ru = st->status == 0 ? 1 : 0;
-    }
-}
-
 }  // namespace
 
 // ---- host side -----------------------------------------------------------------------------
@@ -1097,21 +1236,6 @@ bool can_coarsen(const Grid& g)
 constexpr int64_t kOneBlockCoarse = 32768;
 
 template <typename T>
-Lev<T> level(const MGData* G, int l)
-{
-    Lev<T> L;
-    L.g = G->g[l];
-    L.kx = (const T*)G->K[l][0];
-    L.ky = (const T*)G->K[l][1];
-    L.kz = (const T*)G->K[l][2];
-    L.diag = (const T*)G->diag[l];
-    L.dinv = (const T*)G->dinv[l];
-    L.x = (T*)G->x[l];
-    L.b = (const T*)G->b[l];
-    return L;
-}
-
-template <typename T>
 Op0<T> op0(const pb_problem* pb)
 {
     Op0<T> o;
@@ -1126,152 +1250,256 @@ Op0<T> op0(const pb_problem* pb)
     return o;
 }
 
-// ---- launches on the coarse levels (natural layout) --------------------------------------
+// ---- launch plans --------------------------------------------------------------------------
+// A plan lists, for a set of problems, how many blocks each has in every kind of pass: the
+// level-0 passes (and the streaming CG passes, which use as many blocks), the one-block scalar
+// steps, the one-block small levels, a one-block coarsest level, a large coarsest level
+// (all nodes / one colour), and per coarse level l the pre/post-smoothing passes (all nodes /
+// one colour) and the restriction onto it.  The block offsets of every pass kind go to the
+// device in one table.
+enum PassKind {
+    K_RB0 = 0,
+    K_ONE,
+    K_SUB,
+    K_COARSE1,
+    K_CALL,
+    K_CCOL,
+    K_ALL,
+    K_COL = K_ALL + PB_MG_MAX_LEVELS,
+    K_RES = K_COL + PB_MG_MAX_LEVELS,
+    K_N = K_RES + PB_MG_MAX_LEVELS
+};
 
-template <typename T>
-void launch_sweep(hipStream_t s, const Lev<T>& L, int c, Gate st)
+// blocks of one problem in each pass kind
+void pass_counts(const MGData* G, int* cnt)
 {
-    if (colour_threads(L.g) > 0) k_sweep<T><<<node_grid(L.g, true), 256, 0, s>>>(L, c, st);
-}
-
-// pre-smoothing (red, black) x nu from zero
-template <typename T>
-void launch_pre(hipStream_t s, int nu, const Lev<T>& L, Gate st)
-{
-    k_down1<T><<<node_grid(L.g, false), 256, 0, s>>>(L, st);
-    for (int v = 1; v < nu; ++v) {
-        launch_sweep<T>(s, L, 0, st);
-        launch_sweep<T>(s, L, 1, st);
-    }
-}
-
-// coarse correction and post-smoothing (black, red) x nu
-template <typename T>
-void launch_post(hipStream_t s, int nu, const Lev<T>& L, const Grid& gc, const T* ec, Gate st)
-{
-    k_prolong<T><<<node_grid(L.g, true), 256, 0, s>>>(L.g, L.x, gc, ec, st);
-    for (int v = 0; v < nu; ++v) {
-        launch_sweep<T>(s, L, 1, st);
-        launch_sweep<T>(s, L, 0, st);
-    }
-}
-
-template <typename T>
-void launch_coarsest(hipStream_t s, const MGData* G, const Lev<T>& L, Gate st)
-{
-    if (interior_count(L.g) <= kOneBlockCoarse) {
-        k_coarse<T><<<1, 256, 0, s>>>(L, G->cs, st);
-        return;
-    }
-    // red, black in one pass, then red, then (black, red) x (cs - 1)
-    launch_pre<T>(s, 1, L, st);
-    launch_sweep<T>(s, L, 0, st);
-    for (int v = 1; v < G->cs; ++v) {
-        launch_sweep<T>(s, L, 1, st);
-        launch_sweep<T>(s, L, 0, st);
-    }
-}
-
-// ---- launches on level 0 (red-black layout) ------------------------------------------------
-
-template <typename T>
-OpRB<T> oprb(const pb_problem* pb)
-{
-    const Op0<T> o = op0<T>(pb);
-    return OpRB<T>{pb->mg->code_rb, o.ck, o.kin, o.kout, o.mass};
-}
-
-template <typename T>
-Lev0<T> lev0(const pb_problem* pb)
-{
-    const MGData* G = pb->mg;
-    return Lev0<T>{rb_of(pb->g), (const T*)G->cr, (const T*)G->dinv[0], (T*)G->cz};
-}
-
-template <typename T>
-void launch_rb_sweep(hipStream_t s, const Lev0<T>& L, const OpRB<T>& op, int c, Gate st)
-{
-    k_rb_sweep<T><<<rb_grid(L.r), 256, 0, s>>>(L, op, c, st);
-}
-
-// z = V-cycle(r) at level 0 (x of level 0 is z, b of level 0 is r); with ev, events around
-// the whole V-cycle (ev[0], ev[3]) and around the first level-0 black half-sweep after the
-// coarse correction (ev[1], ev[2]).  With more than one level the last half-sweep also writes
-// the r.z partial sums to G->prz (G->nrz blocks); returns whether it did.
-template <typename T>
-bool launch_vcycle(hipStream_t s, const pb_problem* pb, Gate st, hipEvent_t* ev = nullptr)
-{
-    const MGData* G = pb->mg;
-    const OpRB<T> op = oprb<T>(pb);
-    const Lev0<T> L0 = lev0<T>(pb);
-    const dim3 grid0 = rb_grid(L0.r);
+    for (int k = 0; k < K_N; ++k) cnt[k] = 0;
     const int L = G->nlev;
-    if (L == 1) {
-        // one level: red from zero and black, then red, then (black, red) x (cs - 1)
-        k_rb_down1<T><<<grid0, 256, 0, s>>>(L0, op, st);
-        launch_rb_sweep<T>(s, L0, op, 0, st);
-        for (int v = 1; v < G->cs; ++v) {
-            launch_rb_sweep<T>(s, L0, op, 1, st);
-            launch_rb_sweep<T>(s, L0, op, 0, st);
+    cnt[K_RB0] = G->nb;
+    cnt[K_ONE] = 1;
+    if (L < 2) return;
+    const int top = std::min(G->ls, L - 1);   // levels [1, top) smooth and restrict in launches of their own
+    for (int l = 1; l < top; ++l) {
+        cnt[K_ALL + l] = lev_blocks(G->g[l], false);
+        cnt[K_COL + l] = lev_blocks(G->g[l], true);
+    }
+    for (int l = 1; l <= top; ++l) cnt[K_RES + l] = lev_blocks(G->g[l], false);
+    if (G->ls < L) {
+        cnt[K_SUB] = 1;
+    } else if (interior_count(G->g[L - 1]) <= kOneBlockCoarse) {
+        cnt[K_COARSE1] = 1;
+    } else {
+        cnt[K_CALL] = lev_blocks(G->g[L - 1], false);
+        cnt[K_CCOL] = lev_blocks(G->g[L - 1], true);
+    }
+}
+
+struct Plan {
+    int P = 0;
+    int total[K_N] = {};
+    int top = 0;            // largest first level of the small-level part over the problems
+    int nu = 1, cs = 4;
+    bool single = false;    // one problem with a single level
+    const void* desc = nullptr;   // device: P descriptor pointers
+    const int* off = nullptr;     // device: K_N tables of P + 1 offsets
+};
+
+// the host tables of a plan: offs[k * (P + 1) + p]
+void plan_tables(const std::vector<const MGData*>& Gs, Plan& pl, std::vector<int>& offs)
+{
+    const int P = (int)Gs.size();
+    pl.P = P;
+    offs.assign((size_t)K_N * (P + 1), 0);
+    int cnt[K_N];
+    for (int k = 0; k < K_N; ++k) pl.total[k] = 0;
+    pl.top = 0;
+    for (int p = 0; p < P; ++p) {
+        pass_counts(Gs[p], cnt);
+        for (int k = 0; k < K_N; ++k) {
+            offs[(size_t)k * (P + 1) + p] = pl.total[k];
+            pl.total[k] += cnt[k];
         }
-        return false;
+        if (Gs[p]->nlev >= 2) pl.top = std::max(pl.top, std::min(Gs[p]->ls, Gs[p]->nlev - 1));
+    }
+    for (int k = 0; k < K_N; ++k) offs[(size_t)k * (P + 1) + P] = pl.total[k];
+    pl.nu = P ? Gs[0]->nu : 1;
+    pl.cs = P ? Gs[0]->cs : 4;
+    pl.single = P == 1 && Gs[0]->nlev == 1;
+}
+
+template <typename T>
+Bt<T> bt(const Plan& pl, int kind)
+{
+    return Bt<T>{(const MGDev<T>* const*)pl.desc, pl.off + (size_t)kind * (pl.P + 1), pl.P};
+}
+
+#define PLAUNCH(kind, threads, kernel, ...)                                                          \
+    do {                                                                                             \
+        if (pl.total[kind] > 0) kernel<<<pl.total[kind], threads, 0, s>>>(bt<T>(pl, kind), __VA_ARGS__); \
+    } while (0)
+#define PLAUNCH0(kind, threads, kernel)                                                              \
+    do {                                                                                             \
+        if (pl.total[kind] > 0) kernel<<<pl.total[kind], threads, 0, s>>>(bt<T>(pl, kind));           \
+    } while (0)
+
+// z = V-cycle(r) at level 0 for every problem of the plan; with ev, events around the whole
+// V-cycle (ev[0], ev[3]) and around the first level-0 black half-sweep after the coarse
+// correction (ev[1], ev[2]).  With more than one level the last half-sweep also writes the
+// r.z partial sums (prz).
+template <typename T>
+void run_vcycle(hipStream_t s, const Plan& pl, GateSpec gs, hipEvent_t* ev = nullptr)
+{
+    if (pl.single) {
+        // one level: red from zero and black, then red, then (black, red) x (cs - 1)
+        PLAUNCH(K_RB0, 256, kb_rb_down1<T>, gs);
+        PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 0, gs);
+        for (int v = 1; v < pl.cs; ++v) {
+            PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 1, gs);
+            PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 0, gs);
+        }
+        return;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
     // level 0: pre-smoothing, red residual, restriction to level 1
-    k_rb_down1<T><<<grid0, 256, 0, s>>>(L0, op, st);
-    for (int v = 1; v < G->nu; ++v) {
-        launch_rb_sweep<T>(s, L0, op, 0, st);
-        launch_rb_sweep<T>(s, L0, op, 1, st);
+    PLAUNCH(K_RB0, 256, kb_rb_down1<T>, gs);
+    for (int v = 1; v < pl.nu; ++v) {
+        PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 0, gs);
+        PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 1, gs);
     }
-    k_rb_resid<T><<<grid0, 256, 0, s>>>(L0, op, (T*)G->r[0], st);
-    k_rb_restrict<T><<<node_grid(G->g[1], false), 256, 0, s>>>(L0.r, (const T*)G->r[0], G->g[1], (T*)G->b[1], st);
-    // the first level from which every level has at most kSubcycleNodes unknowns (not 0)
-    int ls = L;
-    while (ls - 1 >= 1 && interior_count(G->g[ls - 1]) <= kSubcycleNodes) --ls;
-    // pre-smoothing and restriction on the coarse levels above the one-block part (or above
-    // the coarsest level)
-    for (int l = 1; l < std::min(ls, L - 1); ++l) {
-        const Lev<T> lv = level<T>(G, l);
-        const Grid& gc = G->g[l + 1];
-        T* r = (T*)G->r[l];
-        launch_pre<T>(s, G->nu, lv, st);
-        k_resid<T><<<node_grid(lv.g, true), 256, 0, s>>>(lv, r, st);
-        k_restrict<T><<<node_grid(gc, false), 256, 0, s>>>(lv.g, r, gc, (T*)G->b[l + 1], st);
-    }
-    if (ls < L) {
-        // levels ls.. in one block; its right-hand side was restricted above
-        SubLevels<T> S;
-        S.nl = L - ls;
-        S.nu = G->nu;
-        S.cs = G->cs;
-        for (int l = ls; l < L; ++l) {
-            S.lv[l - ls] = level<T>(G, l);
-            S.r[l - ls] = (T*)G->r[l];
+    PLAUNCH(K_RB0, 256, kb_rb_resid<T>, gs);
+    PLAUNCH(K_RES + 1, 256, kb_restrict<T>, 1, gs);
+    // coarse levels above the one-block part (or above the coarsest level)
+    for (int l = 1; l < pl.top; ++l) {
+        PLAUNCH(K_ALL + l, 256, kb_down1<T>, l, gs);
+        for (int v = 1; v < pl.nu; ++v) {
+            PLAUNCH(K_COL + l, 256, kb_sweep<T>, l, 0, gs);
+            PLAUNCH(K_COL + l, 256, kb_sweep<T>, l, 1, gs);
         }
-        k_subcycle<T><<<1, kSubThreads, 0, s>>>(S, st);
-    } else {
-        launch_coarsest<T>(s, G, level<T>(G, L - 1), st);
+        PLAUNCH(K_COL + l, 256, kb_resid<T>, l, gs);
+        PLAUNCH(K_RES + l + 1, 256, kb_restrict<T>, l + 1, gs);
     }
-    for (int l = std::min(ls, L - 1) - 1; l >= 1; --l)
-        launch_post<T>(s, G->nu, level<T>(G, l), G->g[l + 1], (const T*)G->x[l + 1], st);
+    // the small levels in one block, or the coarsest level
+    PLAUNCH(K_SUB, kSubThreads, kb_subcycle<T>, gs);
+    PLAUNCH(K_COARSE1, 256, kb_coarse<T>, gs);
+    if (pl.total[K_CALL] > 0) {
+        // red, black in one pass, then red, then (black, red) x (cs - 1)
+        PLAUNCH(K_CALL, 256, kb_down1<T>, -1, gs);
+        PLAUNCH(K_CCOL, 256, kb_sweep<T>, -1, 0, gs);
+        for (int v = 1; v < pl.cs; ++v) {
+            PLAUNCH(K_CCOL, 256, kb_sweep<T>, -1, 1, gs);
+            PLAUNCH(K_CCOL, 256, kb_sweep<T>, -1, 0, gs);
+        }
+    }
+    for (int l = pl.top - 1; l >= 1; --l) {
+        PLAUNCH(K_COL + l, 256, kb_prolong<T>, l, gs);
+        for (int v = 0; v < pl.nu; ++v) {
+            PLAUNCH(K_COL + l, 256, kb_sweep<T>, l, 1, gs);
+            PLAUNCH(K_COL + l, 256, kb_sweep<T>, l, 0, gs);
+        }
+    }
     // level 0: coarse correction at the red nodes, post-smoothing; the last red half-sweep
     // also forms the r.z partial sums
-    k_rb_prolong<T><<<grid0, 256, 0, s>>>(L0.r, L0.x, G->g[1], (const T*)G->x[1], st);
+    PLAUNCH(K_RB0, 256, kb_rb_prolong<T>, gs);
     if (ev) (void)hipEventRecord(ev[1], s);
-    for (int v = 0; v < G->nu; ++v) {
-        launch_rb_sweep<T>(s, L0, op, 1, st);
+    for (int v = 0; v < pl.nu; ++v) {
+        PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 1, gs);
         if (v == 0 && ev) (void)hipEventRecord(ev[2], s);
-        if (v == G->nu - 1)
-            k_rb_sweep_dot<T><<<grid0, 256, 0, s>>>(L0, op, st, G->prz);
+        if (v == pl.nu - 1)
+            PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, true>), 0, gs);
         else
-            launch_rb_sweep<T>(s, L0, op, 0, st);
+            PLAUNCH(K_RB0, 256, (kb_rb_sweep<T, false>), 0, gs);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
-    return true;
 }
 
-// the level hierarchy and the solver vectors, enqueued on stream s (no host wait); the FP64
-// coefficients the element-type copies are rounded from stay allocated with the problem
+// one CG iteration of every problem of the plan
+template <typename T>
+void run_iteration(hipStream_t s, const Plan& pl, hipEvent_t* ev = nullptr)
+{
+    const GateSpec gs{nullptr, 0};
+    PLAUNCH0(K_RB0, 256, kb_rb_apply<T>);
+    PLAUNCH0(K_ONE, 256, kb_alpha<T>);
+    PLAUNCH0(K_RB0, 256, kb_rb_update<T>);
+    run_vcycle<T>(s, pl, gs, ev);
+    if (pl.single) PLAUNCH(K_RB0, 256, kb_rb_dot<T>, gs);
+    PLAUNCH(K_ONE, 256, kb_beta<T>, 0);
+}
+
+// restart from the true residual: fold the correction into the FP64 solution, r = b - A x in
+// FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the state (init: the
+// first residual, x = 0); otherwise only where the iteration stopped with status 3 (the FP32
+// residual reached its goal or fell by inner_rtol).
+template <typename T>
+void run_restart(hipStream_t s, const Plan& pl, int init, int force)
+{
+    const GateSpec gs{nullptr, 1};
+    PLAUNCH(K_RB0, 256, kb_rb_fold<T>, force);
+    PLAUNCH(K_RB0, 256, kb_rb_true_res<T>, force);
+    PLAUNCH(K_ONE, 256, kb_ru_fin<T>, init, force);
+    run_vcycle<T>(s, pl, gs);
+    if (pl.single) PLAUNCH(K_RB0, 256, kb_rb_dot<T>, gs);
+    PLAUNCH(K_ONE, 256, kb_beta<T>, init ? 1 : 2);
+}
+
+template <typename T>
+Lev<T> level(const MGData* G, int l)
+{
+    Lev<T> L;
+    L.g = G->g[l];
+    L.kx = (const T*)G->K[l][0];
+    L.ky = (const T*)G->K[l][1];
+    L.kz = (const T*)G->K[l][2];
+    L.diag = (const T*)G->diag[l];
+    L.dinv = (const T*)G->dinv[l];
+    L.x = (T*)G->x[l];
+    L.b = (const T*)G->b[l];
+    return L;
+}
+
+// the descriptor of a problem's hierarchy (host copy)
+template <typename T>
+MGDev<T> describe(const pb_problem* pb)
+{
+    const MGData* G = pb->mg;
+    const pb_params& P = pb->prm;
+    MGDev<T> d;
+    memset((void*)&d, 0, sizeof d);
+    d.rb = rb_of(pb->g);
+    d.g0 = pb->g;
+    const Op0<T> o = op0<T>(pb);
+    d.op = OpRB<T>{G->code_rb, o.ck, o.kin, o.kout, o.mass};
+    d.op64 = op0<double>(pb);
+    d.cr = (T*)G->cr;
+    d.cz = (T*)G->cz;
+    d.cp = (T*)G->cp;
+    d.cp2 = (T*)G->cp2;
+    d.cq = (T*)G->cq;
+    d.cx = (T*)G->cx;
+    d.dinv0 = (T*)G->dinv[0];
+    d.r0 = (T*)G->r[0];
+    d.x64 = pb->x;
+    d.rhs = pb->rhs;
+    d.nlev = G->nlev;
+    d.ls = G->ls;
+    d.nu = G->nu;
+    d.cs = G->cs;
+    for (int l = 1; l < G->nlev; ++l) {
+        d.lv[l] = level<T>(G, l);
+        d.r[l] = (T*)G->r[l];
+    }
+    d.st = pb->st;
+    d.part = G->part;
+    d.prz = G->prz;
+    d.nb = G->nb;
+    d.mixed = P.precision == PB_MIXED ? 1 : 0;
+    d.rtol2 = P.rtol * P.rtol;
+    d.delta2 = P.inner_rtol * P.inner_rtol;
+    return d;
+}
+
+// the level hierarchy, the solver vectors, the problem's descriptor and its one-problem
+// plan, enqueued on stream s (no host wait); the FP64 coefficients the element-type copies
+// are rounded from stay allocated with the problem
 template <typename T>
 int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
 {
@@ -1283,22 +1511,17 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
         G->g[G->nlev] = coarse_grid(G->g[G->nlev - 1]);
         ++G->nlev;
     }
+    // the first level from which every level has at most kSubcycleNodes unknowns (not 0)
+    G->ls = G->nlev;
+    while (G->ls - 1 >= 1 && interior_count(G->g[G->ls - 1]) <= kSubcycleNodes) --G->ls;
     // FP64 coefficients of every coarse level, then the element-type copies
-    std::vector<double*> tmp;
-    auto get64 = [&](int64_t n) -> double* {
-        double* p = (double*)pb->mem.get(sizeof(double) * (size_t)n);
-        if (p) tmp.push_back(p);
-        return p;
-    };
     const double *pkx = nullptr, *pky = nullptr, *pkz = nullptr, *pm = nullptr;
     for (int l = 1; l < G->nlev; ++l) {
         const Grid& gc = G->g[l];
-        double *kx = get64(gc.N), *ky = get64(gc.N), *kz = get64(gc.N), *m = get64(gc.N);
-        if (!kx || !ky || !kz || !m) return pbi_fail(PB_ENOMEM, "multigrid levels");
-        RCHK(launch_fill(s, kx, sizeof(double) * (size_t)gc.N));
-        RCHK(launch_fill(s, ky, sizeof(double) * (size_t)gc.N));
-        RCHK(launch_fill(s, kz, sizeof(double) * (size_t)gc.N));
-        RCHK(launch_fill(s, m, sizeof(double) * (size_t)gc.N));
+        double* c64 = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)gc.N);
+        if (!c64) return pbi_fail(PB_ENOMEM, "multigrid levels");
+        RCHK(launch_fill(s, c64, sizeof(double) * 4 * (size_t)gc.N));
+        double *kx = c64, *ky = c64 + gc.N, *kz = c64 + 2 * gc.N, *m = c64 + 3 * gc.N;
         FineSrc F;
         F.g = G->g[l - 1];
         F.code = l == 1 ? pb->code : nullptr;
@@ -1312,36 +1535,23 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
         F.m = pm;
         const int64_t nn = (int64_t)gc.nx * gc.ny * gc.nz;
         k_coarsen<<<nblk(nn, 256), 256, 0, s>>>(F, gc, kx, ky, kz, m);
-        T* kT[3];
-        for (int d = 0; d < 3; ++d) {
-            kT[d] = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
-            if (!kT[d]) return pbi_fail(PB_ENOMEM, "multigrid levels");
-            RCHK(launch_fill(s, kT[d], sizeof(T) * (size_t)gc.N));
-            G->K[l][d] = kT[d];
-        }
-        T* dT = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
-        T* DT = (T*)pb->mem.get(sizeof(T) * (size_t)gc.N);
-        if (!dT || !DT) return pbi_fail(PB_ENOMEM, "multigrid levels");
-        RCHK(launch_fill(s, dT, sizeof(T) * (size_t)gc.N));
-        RCHK(launch_fill(s, DT, sizeof(T) * (size_t)gc.N));
-        G->dinv[l] = dT;
-        G->diag[l] = DT;
-        k_level_diag<T><<<nblk(nn, 256), 256, 0, s>>>(gc, kx, ky, kz, m, kT[0], kT[1], kT[2], DT, dT);
+        // K (three), diagonal, 1/diagonal, and the level's residual, iterate and right-hand side
+        T* v = (T*)pb->mem.get(sizeof(T) * 8 * (size_t)gc.N);
+        if (!v) return pbi_fail(PB_ENOMEM, "multigrid levels");
+        RCHK(launch_fill(s, v, sizeof(T) * 8 * (size_t)gc.N));
+        for (int d = 0; d < 3; ++d) G->K[l][d] = v + d * gc.N;
+        G->diag[l] = v + 3 * gc.N;
+        G->dinv[l] = v + 4 * gc.N;
+        G->r[l] = v + 5 * gc.N;
+        G->x[l] = v + 6 * gc.N;
+        G->b[l] = v + 7 * gc.N;
+        k_level_diag<T><<<nblk(nn, 256), 256, 0, s>>>(gc, kx, ky, kz, m, (T*)G->K[l][0], (T*)G->K[l][1],
+                                                       (T*)G->K[l][2], (T*)G->diag[l], (T*)G->dinv[l]);
         RCHK(hipGetLastError());
         pkx = kx;
         pky = ky;
         pkz = kz;
         pm = m;
-    }
-    // coarse-level vectors (natural layout)
-    for (int l = 1; l < G->nlev; ++l) {
-        const Grid& g = G->g[l];
-        void** dst[3] = {&G->r[l], &G->x[l], &G->b[l]};
-        for (int v = 0; v < 3; ++v) {
-            *dst[v] = pb->mem.get(sizeof(T) * (size_t)g.N);
-            if (!*dst[v]) return pbi_fail(PB_ENOMEM, "multigrid vectors");
-            RCHK(launch_fill(s, *dst[v], sizeof(T) * (size_t)g.N));
-        }
     }
     // level 0 in the red-black layout: the codes, 1 / diagonal, the red residual and the CG
     // vectors r, z, p (two), q and the correction x (x and b of level 0 are z and r)
@@ -1352,65 +1562,54 @@ int setup_levels(pb_problem* pb, MGData* G, hipStream_t s)
     G->code_rb = (uint32_t*)pb->mem.get(sizeof(uint32_t) * (size_t)rb.N);
     if (!G->code_rb) return pbi_fail(PB_ENOMEM, "multigrid codes");
     k_rb_code<<<(unsigned)std::min<int64_t>(65536, nblk(rb.N, 256)), 256, 0, s>>>(g0, rb, pb->code, G->code_rb);
-    void** v0[8] = {&G->dinv[0], &G->r[0], &G->cr, &G->cz, &G->cp, &G->cp2, &G->cq, &G->cx};
-    for (int v = 0; v < 8; ++v) {
-        *v0[v] = pb->mem.get(sizeof(T) * (size_t)rb.N);
-        if (!*v0[v]) return pbi_fail(PB_ENOMEM, "multigrid level-0 vectors");
-        RCHK(launch_fill(s, *v0[v], sizeof(T) * (size_t)rb.N));
-    }
-    k_rb_diag0<T><<<rb_grid(rb), 256, 0, s>>>(g0, rb, op0<T>(pb), (T*)G->dinv[0]);
+    T* v0 = (T*)pb->mem.get(sizeof(T) * 8 * (size_t)rb.N);
+    if (!v0) return pbi_fail(PB_ENOMEM, "multigrid level-0 vectors");
+    RCHK(launch_fill(s, v0, sizeof(T) * 8 * (size_t)rb.N));
+    void** dst[8] = {&G->dinv[0], &G->r[0], &G->cr, &G->cz, &G->cp, &G->cp2, &G->cq, &G->cx};
+    for (int v = 0; v < 8; ++v) *dst[v] = v0 + v * rb.N;
+    G->nb = rb_blocks(rb);
+    k_rb_diag0<T><<<G->nb, 256, 0, s>>>(g0, rb, op0<T>(pb), (T*)G->dinv[0]);
     G->x[0] = G->cz;
     G->b[0] = G->cr;
-    {
-        // one partial sum per block of the level-0 launches; the streaming kernels use as many
-        const dim3 ng = rb_grid(rb);
-        G->nb = (int)(ng.x * ng.y * ng.z);
-        G->nrz = G->nb;
-    }
-    G->part = (double*)pb->mem.get(sizeof(double) * 3 * (size_t)G->nb);
+    G->nrz = G->nb;
+    G->part = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)G->nb);
     if (!G->part) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
-    G->prz = (double*)pb->mem.get(sizeof(double) * (size_t)G->nrz);
-    if (!G->prz) return pbi_fail(PB_ENOMEM, "multigrid partial sums");
+    G->prz = G->part + 3 * (size_t)G->nb;
+    // the descriptor, the one-problem plan's tables and the pointer to the descriptor
+    std::vector<const MGData*> one{G};
+    Plan pl;
+    std::vector<int> offs;
+    plan_tables(one, pl, offs);
+    const size_t dbytes = (sizeof(MGDev<T>) + 255) & ~(size_t)255;
+    const size_t tbytes = sizeof(int) * offs.size();
+    char* blob = (char*)pb->mem.get(dbytes + 256 + tbytes);
+    if (!blob) return pbi_fail(PB_ENOMEM, "multigrid descriptor");
+    G->dev = blob;
+    G->solo_desc = blob + dbytes;
+    G->solo_off = (int*)(blob + dbytes + 256);
+    G->solo_host.assign(dbytes + 256 + tbytes, 0);
+    const MGDev<T> d = describe<T>(pb);
+    memcpy(G->solo_host.data(), &d, sizeof d);
+    const void* dptr = G->dev;
+    memcpy(G->solo_host.data() + dbytes, &dptr, sizeof dptr);
+    memcpy(G->solo_host.data() + dbytes + 256, offs.data(), tbytes);
+    // pageable source: the copy is complete when the call returns
+    RCHK(hipMemcpyAsync(blob, G->solo_host.data(), G->solo_host.size(), hipMemcpyHostToDevice, s));
     RCHK(hipGetLastError());
     return PB_OK;
 }
 
-template <typename T>
-void launch_iteration(hipStream_t s, const pb_problem* pb, CGState* st, hipEvent_t* ev = nullptr)
+// the one-problem plan of a problem
+Plan solo_plan(const pb_problem* pb)
 {
     const MGData* G = pb->mg;
-    const RB rb = rb_of(pb->g);
-    T *x = (T*)G->cx, *r = (T*)G->cr, *z = (T*)G->cz, *p0 = (T*)G->cp, *p1 = (T*)G->cp2, *q = (T*)G->cq;
-    const Gate gate{st, 0};
-    k_rb_apply<T><<<rb_grid(rb), 256, 0, s>>>(rb, oprb<T>(pb), z, p0, p1, q, G->part, st);
-    k_alpha<<<1, 256, 0, s>>>(G->part, G->nb, st);
-    k_rb_update<T><<<G->nb, 256, 0, s>>>(rb.N, x, r, p0, p1, q, G->part, G->nb, st);
-    const bool fused = launch_vcycle<T>(s, pb, gate, ev);
-    if (!fused) k_rb_dot<T><<<G->nb, 256, 0, s>>>(rb.N, r, z, G->part, gate);
-    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, 0, fused ? G->prz : nullptr, G->nrz);
-}
-
-// restart from the true residual: fold the correction into the FP64 solution, r = b - A x in
-// FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the state (init: the
-// first residual, x = 0); otherwise only where the iteration stopped with status 3 (the FP32
-// residual reached its goal or fell by inner_rtol).
-template <typename T>
-void launch_restart(hipStream_t s, pb_problem* pb, CGState* st, int init, int force)
-{
-    const MGData* G = pb->mg;
-    const Grid& g = pb->g;
-    const RB rb = rb_of(g);
-    const pb_params& P = pb->prm;
-    const bool mixed = sizeof(T) == 4;
-    k_rb_fold<T><<<rb_grid(rb), 256, 0, s>>>(g, rb, pb->x, (T*)G->cx, st, force);
-    const Op0<double> op64 = op0<double>(pb);
-    k_rb_true_res<T><<<rb_grid(rb), 256, 0, s>>>(g, rb, op64, pb->x, pb->rhs, (T*)G->cr, G->part, G->nb, st, force);
-    k_ru_fin<<<1, 256, 0, s>>>(G->part, G->nb, st, init, mixed ? 1 : 0, P.rtol * P.rtol, P.inner_rtol * P.inner_rtol,
-                               force);
-    const Gate gate{st, 1};
-    const bool fused = launch_vcycle<T>(s, pb, gate);
-    if (!fused) k_rb_dot<T><<<G->nb, 256, 0, s>>>(rb.N, (const T*)G->cr, (const T*)G->cz, G->part, gate);
-    k_beta<<<1, 256, 0, s>>>(G->part, G->nb, st, init ? 1 : 2, fused ? G->prz : nullptr, G->nrz);
+    std::vector<const MGData*> one{G};
+    Plan pl;
+    std::vector<int> offs;
+    plan_tables(one, pl, offs);
+    pl.desc = G->solo_desc;
+    pl.off = G->solo_off;
+    return pl;
 }
 
 template <typename T>
@@ -1437,7 +1636,7 @@ int start_t(pb_problem* pb, hipStream_t s)
     RCHK(launch_fill(s, G->cp, sizeof(T) * (size_t)G->Nrb));
     RCHK(launch_fill(s, G->cp2, sizeof(T) * (size_t)G->Nrb));
     RCHK(launch_fill(s, pb->st, sizeof(CGState)));
-    launch_restart<T>(s, pb, pb->st, 1, 1);
+    run_restart<T>(s, solo_plan(pb), 1, 1);
     RCHK(hipGetLastError());
     return PB_OK;
 }
@@ -1449,11 +1648,12 @@ int start_t(pb_problem* pb, hipStream_t s)
 template <typename T>
 int chunk_t(pb_problem* pb, hipStream_t s, int n, hipEvent_t* const* ev, int* const* ran = nullptr)
 {
+    const Plan pl = solo_plan(pb);
     for (int it = 0; it < n; ++it) {
         if (ran && ran[it]) RCHK(hipMemcpyAsync(ran[it], &pb->st->status, sizeof(int), hipMemcpyDeviceToDevice, s));
-        launch_iteration<T>(s, pb, pb->st, ev ? ev[it] : nullptr);
+        run_iteration<T>(s, pl, ev ? ev[it] : nullptr);
     }
-    if (sizeof(T) == 4) launch_restart<T>(s, pb, pb->st, 0, 0);
+    if (sizeof(T) == 4) run_restart<T>(s, pl, 0, 0);
     RCHK(hipGetLastError());
     return PB_OK;
 }
@@ -1524,8 +1724,8 @@ int solve_t(pb_problem* pb, CGState* out)
     // the correction into the FP64 solution (all of it in FP64; in the mixed form what is left
     // after the last restart)
     {
-        const RB rb = rb_of(pb->g);
-        k_rb_fold<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (T*)pb->mg->cx, pb->st, 1);
+        const Plan pl = solo_plan(pb);
+        PLAUNCH(K_RB0, 256, kb_rb_fold<T>, 1);
     }
     RCHK(hipMemcpyAsync(out, pb->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
@@ -1549,6 +1749,67 @@ int solve_t(pb_problem* pb, CGState* out)
     return PB_OK;
 }
 
+template <typename T>
+void vcycle_natural(pb_problem* pb, hipStream_t s, const CGState* st)
+{
+    MGData* G = pb->mg;
+    const RB rb = rb_of(pb->g);
+    const GateSpec gs{st, 3};
+    k_rb_convert<T><<<G->nb, 256, 0, s>>>(pb->g, rb, (T*)G->nat_b, (T*)G->cr, 1, gs, nullptr);
+    run_vcycle<T>(s, solo_plan(pb), gs);
+    k_rb_convert<T><<<G->nb, 256, 0, s>>>(pb->g, rb, (T*)G->nat_x, (T*)G->cz, 0, gs, nullptr);
+}
+
+void* natural_buffer(pb_problem* pb, void** slot)
+{
+    if (!pb->mg) return nullptr;
+    if (!*slot) {
+        const size_t bytes = (pb->prm.precision == PB_MIXED ? sizeof(float) : sizeof(double)) * (size_t)pb->g.N;
+        *slot = pb->mem.get(bytes);
+        if (*slot && launch_fill(pb->ctx->stream, *slot, bytes) != hipSuccess) return nullptr;
+    }
+    return *slot;
+}
+
+// ---- a batch of problems (the serving loop) --------------------------------------------------
+
+template <typename T>
+int batch_chunk_t(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGBatch* bb, CGState* gather,
+                  hipEvent_t* ev)
+{
+    std::vector<const MGData*> Gs;
+    for (auto* pb : pbs) Gs.push_back(pb->mg);
+    Plan pl;
+    std::vector<int> offs;
+    plan_tables(Gs, pl, offs);
+    const int P = pl.P;
+    // the plan's device tables: P descriptor pointers, then the offsets, through pinned staging
+    const size_t need = sizeof(void*) * P + sizeof(int) * offs.size();
+    if (bb->cap < need) {
+        if (bb->host) (void)hipHostFree(bb->host);
+        if (bb->dev) bb->free_fn(bb->dev, bb->user);
+        bb->host = nullptr;
+        bb->dev = nullptr;
+        bb->cap = 0;
+        const size_t c = std::max<size_t>(need, 16384);
+        RCHK(hipHostMalloc(&bb->host, c, hipHostMallocDefault));
+        bb->dev = bb->alloc(c, bb->user);
+        if (!bb->dev) return pbi_fail(PB_ENOMEM, "multigrid batch tables");
+        bb->cap = c;
+    }
+    char* h = (char*)bb->host;
+    for (int p = 0; p < P; ++p) memcpy(h + sizeof(void*) * p, &pbs[p]->mg->dev, sizeof(void*));
+    memcpy(h + sizeof(void*) * P, offs.data(), sizeof(int) * offs.size());
+    RCHK(hipMemcpyAsync(bb->dev, bb->host, need, hipMemcpyHostToDevice, s));
+    pl.desc = bb->dev;
+    pl.off = (const int*)((char*)bb->dev + sizeof(void*) * P);
+    for (int it = 0; it < n; ++it) run_iteration<T>(s, pl, ev ? ev + 4 * it : nullptr);
+    if (sizeof(T) == 4) run_restart<T>(s, pl, 0, 0);
+    if (gather) kb_gather<T><<<P, 64, 0, s>>>(bt<T>(pl, K_ONE), gather);
+    RCHK(hipGetLastError());
+    return PB_OK;
+}
+
 }  // namespace
 
 int pbi_mg_solve(pb_problem* pb, CGState* out)
@@ -1561,6 +1822,12 @@ int pbi_mg_begin(pb_problem* pb, hipStream_t s)
 {
     if (pb->prm.precision == PB_MIXED) return begin_t<float>(pb, s);
     return begin_t<double>(pb, s);
+}
+
+int pbi_mg_start(pb_problem* pb, hipStream_t s)
+{
+    if (pb->prm.precision == PB_MIXED) return start_t<float>(pb, s);
+    return start_t<double>(pb, s);
 }
 
 int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample)
@@ -1578,45 +1845,46 @@ int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* s
     return rc;
 }
 
+bool pbi_mg_batchable(const pb_problem* pb)
+{
+    const MGData* G = pb->mg;
+    if (!G || G->nlev < 2) return false;
+    // a large coarsest level (no one-block part) runs as launches of its own
+    return G->ls < G->nlev || interior_count(G->g[G->nlev - 1]) <= kOneBlockCoarse;
+}
+
+int pbi_mg_batch_chunk(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGBatch* bb, CGState* gather,
+                       hipEvent_t* ev)
+{
+    if (pbs.empty()) return PB_OK;
+    const pb_params& P0 = pbs[0]->prm;
+    for (auto* pb : pbs) {
+        const pb_params& P = pb->prm;
+        if (!pbi_mg_batchable(pb) || P.precision != P0.precision || pb->mg->nu != pbs[0]->mg->nu ||
+            pb->mg->cs != pbs[0]->mg->cs)
+            return pbi_fail(PB_EINVAL, "multigrid batch: problems of different kinds");
+    }
+    if ((int)pbs.size() > PB_MG_MAX_BATCH) return pbi_fail(PB_EINVAL, "multigrid batch of %d problems", (int)pbs.size());
+    if (P0.precision == PB_MIXED) return batch_chunk_t<float>(pbs, s, n, bb, gather, ev);
+    return batch_chunk_t<double>(pbs, s, n, bb, gather, ev);
+}
+
 int pbi_mg_finish(pb_problem* pb, hipStream_t s)
 {
     if (!pb->mg) return PB_OK;
-    const RB rb = rb_of(pb->g);
-    if (pb->prm.precision == PB_MIXED)
-        k_rb_fold<float><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (float*)pb->mg->cx, pb->st, 1);
-    else
-        k_rb_fold<double><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, pb->x, (double*)pb->mg->cx, pb->st, 1);
+    const Plan pl = solo_plan(pb);
+    if (pb->prm.precision == PB_MIXED) {
+        using T = float;
+        PLAUNCH(K_RB0, 256, kb_rb_fold<T>, 1);
+    } else {
+        using T = double;
+        PLAUNCH(K_RB0, 256, kb_rb_fold<T>, 1);
+    }
     RCHK(hipGetLastError());
     return PB_OK;
 }
 
 int pbi_mg_levels(const pb_problem* pb) { return pb->mg ? pb->mg->nlev : 0; }
-
-namespace {
-
-template <typename T>
-void vcycle_natural(pb_problem* pb, hipStream_t s, const CGState* st)
-{
-    MGData* G = pb->mg;
-    const RB rb = rb_of(pb->g);
-    const Gate gate{st, 0};
-    k_rb_convert<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, (T*)G->nat_b, (T*)G->cr, 1, gate);
-    launch_vcycle<T>(s, pb, gate);
-    k_rb_convert<T><<<rb_grid(rb), 256, 0, s>>>(pb->g, rb, (T*)G->nat_x, (T*)G->cz, 0, gate);
-}
-
-void* natural_buffer(pb_problem* pb, void** slot)
-{
-    if (!pb->mg) return nullptr;
-    if (!*slot) {
-        const size_t bytes = (pb->prm.precision == PB_MIXED ? sizeof(float) : sizeof(double)) * (size_t)pb->g.N;
-        *slot = pb->mem.get(bytes);
-        if (*slot && launch_fill(pb->ctx->stream, *slot, bytes) != hipSuccess) return nullptr;
-    }
-    return *slot;
-}
-
-}  // namespace
 
 void pbi_mg_vcycle_on(pb_problem* pb, hipStream_t s, const CGState* st)
 {
@@ -1640,7 +1908,7 @@ int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
     if (rc) return rc;
     MGData* G = pb->mg;
     const RB rb = rb_of(g);
-    const Gate gate{nullptr, 0};
+    const GateSpec gate{nullptr, 2};
     std::vector<double> r64((size_t)rb.N, 0.0), z64((size_t)rb.N, 0.0);
     for (int i = 1; i < g.nx - 1; ++i)
         for (int j = 1; j < g.ny - 1; ++j)
@@ -1649,13 +1917,13 @@ int pbi_mg_vcycle_test(pb_problem* pb, const double* r_host, double* z_host)
         std::vector<float> tmp((size_t)rb.N);
         for (size_t e = 0; e < tmp.size(); ++e) tmp[e] = (float)r64[e];
         RCHK(hipMemcpyAsync(G->cr, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice, s));
-        launch_vcycle<float>(s, pb, gate);
+        run_vcycle<float>(s, solo_plan(pb), gate);
         RCHK(hipMemcpyAsync(tmp.data(), G->cz, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
         for (size_t e = 0; e < tmp.size(); ++e) z64[e] = tmp[e];
     } else {
         RCHK(hipMemcpyAsync(G->cr, r64.data(), sizeof(double) * r64.size(), hipMemcpyHostToDevice, s));
-        launch_vcycle<double>(s, pb, gate);
+        run_vcycle<double>(s, solo_plan(pb), gate);
         RCHK(hipMemcpyAsync(z64.data(), G->cz, sizeof(double) * z64.size(), hipMemcpyDeviceToHost, s));
         RCHK(hipStreamSynchronize(s));
     }

@@ -15,9 +15,11 @@
 //      (each launch covers the tiles of all problems), then the batched reliable-update
 //      kernels and a gather of all problem states.  Requests with the multigrid
 //      preconditioner (worth it on large grids, where Jacobi-CG needs hundreds of iterations)
-//      run their 16 iterations as their own launches, each followed by its restart from the
-//      true residual where one is due, on side streams that start with the chunk and that
-//      the gather waits for.
+//      run their iterations as batched launches of their own (one launch per pass of the
+//      V-cycle and of the CG step over all of them), then the batched restart from the true
+//      residual where one is due, on a side stream that starts with the chunk and that the
+//      gather waits for; the few that cannot be batched run their own launches on further
+//      side streams.
 // Every problem's blocks run the code and block numbering of its own solo launch, so a result
 // does not depend on which other problems shared the batch.
 #include <hip/hip_runtime.h>
@@ -38,6 +40,7 @@ namespace {
 constexpr int kChunkIters = 16;   // same chunk length as a solo mixed solve
 constexpr int kServerTilePlanes = 32;   // long x-chunks: a batched launch has blocks to spare
 constexpr int kMgStreams = 4;          // streams the multigrid problems are spread over
+constexpr int kMgBatches = 4;          // batched multigrid groups per chunk (of PB_MG_MAX_BATCH)
 // Multigrid problems converge in a few dozen iterations, so a fixed 16-iteration chunk with
 // a second chunk in flight would launch many iterations that find the solve stopped.  Their
 // chunks are sized instead: kMgFirst iterations, kMgSecond while the first is in flight, then
@@ -138,8 +141,8 @@ struct pb_server {
     std::vector<int64_t> prof_nu[2];     // interior unknowns of each member
     double prof_ms = 0, prof_bytes = 0;
     int64_t prof_launches = 0;
-    // multigrid members: the level-0 black half-sweep after the coarse correction and the
-    // whole V-cycle of each chunk's first iteration, timed with events from a pool
+    // multigrid members run alone: the level-0 black half-sweep after the coarse correction
+    // and the whole V-cycle of each chunk's first iteration, timed with events from a pool
     struct MgSample {
         uint64_t id;
         hipEvent_t e[4];
@@ -147,6 +150,17 @@ struct pb_server {
     };
     std::vector<MgSample> mg_samples[2];
     std::vector<hipEvent_t> ev_pool;
+    // batched multigrid chunks: launch tables, and per slot the batches launched (members,
+    // their unknowns, iterations, four timing events per iteration)
+    MGBatch mgb[2][kMgBatches];
+    struct MgBatchRun {
+        std::vector<uint64_t> ids;
+        std::vector<int64_t> nu;
+        int n;
+        std::vector<hipEvent_t> ev;
+    };
+    std::vector<MgBatchRun> mg_batches[2];
+    int64_t mg_batch_launches = 0;   // batched chunks launched
     double prof_mg_ms = 0, prof_mg_bytes = 0, prof_mg_vcycle_ms = 0;
     int64_t prof_mg_n = 0;
     // the energy N-body kernel of every request read back while build_ctx profiles
@@ -217,6 +231,32 @@ int complete_slot(pb_server* s, int k)
         }
         s->prof_launches += kChunkIters;
     }
+    // batched multigrid runs: iteration j of a batch ran for the members whose iteration count
+    // grew by more than j over the chunk (a member that stops stays stopped until the chunk's
+    // restart)
+    for (auto& br : s->mg_batches[k]) {
+        std::vector<int> done(br.ids.size(), 0);
+        for (size_t q = 0; q < br.ids.size(); ++q)
+            for (size_t m = 0; m < s->members[k].size(); ++m)
+                if (s->members[k][m] == br.ids[q])
+                    for (auto& a : s->act)
+                        if (a.id == br.ids[q]) done[q] = s->hgather[k][m].iter_count - a.snap.iter_count;
+        for (int j = 0; j < br.n && !br.ev.empty(); ++j) {
+            double bytes = 0.0;
+            for (size_t q = 0; q < br.ids.size(); ++q)
+                if (j < done[q]) bytes += 12.0 * (double)br.nu[q];
+            if (bytes <= 0.0) continue;
+            float sw = 0, vc = 0;
+            SCHK(hipEventElapsedTime(&sw, br.ev[4 * j + 1], br.ev[4 * j + 2]));
+            SCHK(hipEventElapsedTime(&vc, br.ev[4 * j], br.ev[4 * j + 3]));
+            s->prof_mg_ms += sw;
+            s->prof_mg_vcycle_ms += vc;
+            s->prof_mg_bytes += bytes;
+            s->prof_mg_n += 1;
+        }
+        for (auto e : br.ev) s->ev_pool.push_back(e);
+    }
+    s->mg_batches[k].clear();
     for (size_t m = 0; m < s->members[k].size(); ++m) {
         for (auto& a : s->act) {
             if (a.id != s->members[k][m] || a.last_chunk < s->slot_chunk[k]) continue;
@@ -228,9 +268,10 @@ int complete_slot(pb_server* s, int k)
                 SCHK(hipEventElapsedTime(&vc, smp.e[0], smp.e[3]));
                 s->prof_mg_ms += sw;
                 s->prof_mg_vcycle_ms += vc;
-                // algorithmic bytes per unknown of the FP32 half-sweep: x and the node code of
-                // every node, b and 1/D of the swept colour read, x of that colour written
-                s->prof_mg_bytes += 14.0 * (double)smp.nu;
+                // algorithmic bytes per unknown of the FP32 half-sweep in the red-black layout:
+                // x of the other colour, b and 1/D of the swept colour and the node codes of
+                // both read, x of the swept colour written
+                s->prof_mg_bytes += 12.0 * (double)smp.nu;
                 s->prof_mg_n += 1;
             }
             if (s->prof_slot[k] && !a.mg) {
@@ -480,25 +521,68 @@ int mg_chunk_iters(const Active& a)
     return n;
 }
 
+// an event from the pool (timing only: no system-scope fence, whose cache writeback would count)
+int pool_event(pb_server* s, hipEvent_t* e)
+{
+    if (s->ev_pool.empty()) {
+        hipEvent_t x;
+        SCHK(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
+        s->ev_pool.push_back(x);
+    }
+    *e = s->ev_pool.back();
+    s->ev_pool.pop_back();
+    return PB_OK;
+}
+
+int64_t unknowns(const pb_problem* pb)
+{
+    const Grid& g = pb->g;
+    return (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+}
+
 int launch_chunk(pb_server* s, int k)
 {
-    // Jacobi members first (one batched chunk), then the multigrid members (their own
-    // launches); the gathered states follow the same order
-    std::vector<Active*> mem, mgm;
-    std::vector<int> mgn;
+    // Jacobi members first (one batched chunk), then the multigrid members in batched groups,
+    // then the multigrid members run alone; the gathered states follow the same order
+    std::vector<Active*> mem, solo;
+    std::vector<int> solo_n;
+    std::vector<std::vector<Active*>> grp;
+    std::vector<int> grp_n;
     for (auto& a : s->act) {
         if (a.finished) continue;
         if (!a.mg) {
             mem.push_back(&a);
-        } else {
-            const int n = mg_chunk_iters(a);
-            if (n > 0) {
-                mgm.push_back(&a);
-                mgn.push_back(n);
+            continue;
+        }
+        const int n = mg_chunk_iters(a);
+        if (n <= 0) continue;
+        if (!pbi_mg_batchable(a.pb)) {
+            solo.push_back(&a);
+            solo_n.push_back(n);
+            continue;
+        }
+        // a group of one precision and smoothing counts with room left
+        int gi = -1;
+        for (size_t g = 0; g < grp.size(); ++g) {
+            const pb_problem* f = grp[g][0]->pb;
+            if ((int)grp[g].size() < PB_MG_MAX_BATCH && f->prm.precision == a.pb->prm.precision &&
+                f->mg->nu == a.pb->mg->nu && f->mg->cs == a.pb->mg->cs) {
+                gi = (int)g;
+                break;
             }
         }
+        if (gi < 0) {
+            if ((int)grp.size() == kMgBatches) continue;   // no room in this chunk: the next one
+            grp.emplace_back();
+            grp_n.push_back(0);
+            gi = (int)grp.size() - 1;
+        }
+        grp[gi].push_back(&a);
+        grp_n[gi] = std::max(grp_n[gi], n);
     }
-    const int P = (int)mem.size(), Q = (int)mgm.size();
+    int Q = (int)solo.size();
+    for (auto& g : grp) Q += (int)g.size();
+    const int P = (int)mem.size();
     s->members[k].clear();
     s->members_n[k].clear();
     if (P + Q == 0) return PB_OK;
@@ -519,9 +603,14 @@ int launch_chunk(pb_server* s, int k)
         s->members[k].push_back(mem[p]->id);
         s->members_n[k].push_back(kChunkIters);
     }
-    for (int q = 0; q < Q; ++q) {
-        s->members[k].push_back(mgm[q]->id);
-        s->members_n[k].push_back(mgn[q]);
+    for (size_t g = 0; g < grp.size(); ++g)
+        for (auto* a : grp[g]) {
+            s->members[k].push_back(a->id);
+            s->members_n[k].push_back(grp_n[g]);
+        }
+    for (size_t q = 0; q < solo.size(); ++q) {
+        s->members[k].push_back(solo[q]->id);
+        s->members_n[k].push_back(solo_n[q]);
     }
     o[P] = t.st;
     o[(P + 1) + P] = t.add;
@@ -536,10 +625,7 @@ int launch_chunk(pb_server* s, int k)
         s->pev_made = true;
     }
     s->prof_nu[k].clear();
-    for (int p = 0; p < P; ++p) {
-        const Grid& g = mem[p]->pb->g;
-        s->prof_nu[k].push_back((int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2));
-    }
+    for (int p = 0; p < P; ++p) s->prof_nu[k].push_back(unknowns(mem[p]->pb));
     for (int q = 0; q < Q; ++q) s->prof_nu[k].push_back(0);
     if (P > 0) {
         SCHK(hipMemcpyAsync(s->ddesc[k], s->hdesc[k], sizeof(ProbDev<float>) * P, hipMemcpyHostToDevice, st));
@@ -547,34 +633,57 @@ int launch_chunk(pb_server* s, int k)
         SCHK(launch_batch_chunk(st, s->ddesc[k], s->doff[k], P, t, kChunkIters, s->dgather[k],
                                 s->prof_slot[k] ? s->pev[k] : nullptr));
     }
+    // group g on side stream g, the members alone on the stream of their lane
     bool used[kMgStreams] = {};
-    for (int q = 0; q < Q; ++q) used[mgm[q]->lane] = true;
+    for (size_t g = 0; g < grp.size(); ++g) used[g % kMgStreams] = true;
+    for (auto* a : solo) used[a->lane] = true;
     for (int j = 0; j < kMgStreams; ++j)
         if (used[j]) SCHK(hipStreamWaitEvent(s->mgs[j], s->start_ev[k], 0));
-    for (int q = 0; q < Q; ++q) {
-        pb_problem* pb = mgm[q]->pb;
-        hipStream_t ms = s->mgs[mgm[q]->lane];
+    int slot = P;
+    for (size_t g = 0; g < grp.size(); ++g) {
+        hipStream_t ms = s->mgs[g % kMgStreams];
+        std::vector<pb_problem*> pbs;
+        pb_server::MgBatchRun br;
+        br.n = grp_n[g];
+        for (auto* a : grp[g]) {
+            if (a->launched == 0 && (rc = pbi_mg_start(a->pb, ms))) return rc;
+            pbs.push_back(a->pb);
+            br.ids.push_back(a->id);
+            br.nu.push_back(unknowns(a->pb));
+        }
+        if (s->ctx->profile) {
+            br.ev.resize((size_t)4 * br.n);
+            for (auto& e : br.ev)
+                if ((rc = pool_event(s, &e))) return rc;
+        }
+        if (!s->mgb[k][g].alloc) {
+            s->mgb[k][g].alloc = s->ctx->alloc;
+            s->mgb[k][g].free_fn = s->ctx->free_fn;
+            s->mgb[k][g].user = s->ctx->user;
+        }
+        if ((rc = pbi_mg_batch_chunk(pbs, ms, br.n, &s->mgb[k][g], s->dgather[k] + slot,
+                                     br.ev.empty() ? nullptr : br.ev.data())))
+            return rc;
+        slot += (int)pbs.size();
+        s->mg_batches[k].push_back(std::move(br));
+        ++s->mg_batch_launches;
+    }
+    for (size_t q = 0; q < solo.size(); ++q) {
+        pb_problem* pb = solo[q]->pb;
+        hipStream_t ms = s->mgs[solo[q]->lane];
         hipEvent_t* sample = nullptr;
         if (s->ctx->profile && pb->mg && pb->mg->nlev > 1) {
             pb_server::MgSample smp;
-            smp.id = mgm[q]->id;
-            for (int e = 0; e < 4; ++e) {
-                if (s->ev_pool.empty()) {
-                    // timing only: no system-scope fence (its cache writeback would count)
-                    hipEvent_t x;
-                    SCHK(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
-                    s->ev_pool.push_back(x);
-                }
-                smp.e[e] = s->ev_pool.back();
-                s->ev_pool.pop_back();
-            }
-            const Grid& g = pb->g;
-            smp.nu = (int64_t)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+            smp.id = solo[q]->id;
+            for (int e = 0; e < 4; ++e)
+                if ((rc = pool_event(s, &smp.e[e]))) return rc;
+            smp.nu = unknowns(pb);
             s->mg_samples[k].push_back(smp);
             sample = s->mg_samples[k].back().e;
         }
-        if ((rc = pbi_mg_chunk(pb, ms, mgn[q], mgm[q]->launched == 0, sample))) return rc;
-        SCHK(hipMemcpyAsync(s->dgather[k] + P + q, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, ms));
+        if ((rc = pbi_mg_chunk(pb, ms, solo_n[q], solo[q]->launched == 0, sample))) return rc;
+        SCHK(hipMemcpyAsync(s->dgather[k] + slot, pb->st, sizeof(CGState), hipMemcpyDeviceToDevice, ms));
+        ++slot;
     }
     for (int j = 0; j < kMgStreams; ++j)
         if (used[j]) {
@@ -590,10 +699,16 @@ int launch_chunk(pb_server* s, int k)
         a->pending += kChunkIters;
         a->last_chunk = s->chunk_id;
     }
-    for (int q = 0; q < Q; ++q) {
-        mgm[q]->launched += mgn[q];
-        mgm[q]->pending += mgn[q];
-        mgm[q]->last_chunk = s->chunk_id;
+    for (size_t g = 0; g < grp.size(); ++g)
+        for (auto* a : grp[g]) {
+            a->launched += grp_n[g];
+            a->pending += grp_n[g];
+            a->last_chunk = s->chunk_id;
+        }
+    for (size_t q = 0; q < solo.size(); ++q) {
+        solo[q]->launched += solo_n[q];
+        solo[q]->pending += solo_n[q];
+        solo[q]->last_chunk = s->chunk_id;
     }
     s->chunk_id++;
     return PB_OK;
@@ -805,6 +920,15 @@ void pb_server_destroy(pb_server* s)
         for (auto& smp : s->mg_samples[k])
             for (int e = 0; e < 4; ++e) (void)hipEventDestroy(smp.e[e]);
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k) {
+        for (auto& br : s->mg_batches[k])
+            for (auto e : br.ev) (void)hipEventDestroy(e);
+        for (int g = 0; g < kMgBatches; ++g) {
+            MGBatch& b = s->mgb[k][g];
+            if (b.host) (void)hipHostFree(b.host);
+            if (b.dev) b.free_fn(b.dev, b.user);
+        }
+    }
     for (int k = 0; k < 2; ++k) {
         free_slot(s, k);
         if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
