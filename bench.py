@@ -35,45 +35,52 @@ METRIC = "PBE solves/s + p99 latency at 1e-6 energy err; PCG Gnode-iter/s vs FP6
 
 # Residual tolerance that keeps |dE/E| <= 1e-6 (both forms use it, so they are compared at
 # equal energy error), and the reliable-update factor of the mixed form.
-RTOL = 5e-8
+RTOL = 1e-8
 # algorithmic bytes per unknown of one FP32 CG iteration kernel: read z, w, p, x and the
 # node code, write z, w, p and x (4 bytes each)
 ITER_BYTES_FP32 = 36
 
 # HBM traffic per launch relative to the algorithmic bytes, from rocprofv3 FETCH_SIZE (x2.0)
-# and WRITE_SIZE (x1.0) passes over this same command (each pass compared with the launches
-# it timed), with the fingerprint of the kernel source they were taken on; a kernel changed
-# since then reports null
-COUNTER_TRAFFIC = {"kb_iter<float>": {"fingerprint": "d46412d76b65f4d3", "ratio": 1.314}}
+# and WRITE_SIZE (x1.0) passes (the copy kernel's own counters give the factors), with the
+# fingerprint of the kernel sources they were taken on; a kernel changed since then reports
+# null.  The summaries with the commands are in profiles/.
+COUNTER_TRAFFIC = {
+    # the 385^3 single solve (multigrid_385_counters)
+    "kb_rb_apply<float>@385": {"sources": "mg", "fingerprint": None, "ratio": None},
+    "kb_rb_sweep<float>@385": {"sources": "mg", "fingerprint": None, "ratio": None},
+    "k_cg_iter<float>@385": {"sources": "solve", "fingerprint": None, "ratio": None},
+    # the serving stream's batched launches (serving_stream_512_counters)
+    "kb_rb_apply<float>@stream": {"sources": "mg", "fingerprint": None, "ratio": None},
+    "kb_rb_sweep<float>@stream": {"sources": "mg", "fingerprint": None, "ratio": None},
+}
 
 
-def kernel_fingerprint():
-    """sha256 (first 16 hex digits) of the iteration kernel's sources: pb_solve.hip and the parts
-    of pb_internal.h it uses (the shared types and the solver declarations, not the build and
-    energy declarations)."""
+def kernel_fingerprint(which):
+    """sha256 (first 16 hex digits) of a kernel family's sources: "solve" = the Jacobi iteration
+    kernel (pb_solve.hip and pb_stencil.h), "mg" = the multigrid kernels (pb_mg.hip and
+    pb_stencil.h); with the shared types of pb_internal.h (the text before its kernel
+    declarations)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2502_09323_amd", "csrc")
-    with open(os.path.join(csrc, "pb_solve.hip"), "rb") as fh:
-        h.update(fh.read())
+    for f in ({"solve": "pb_solve.hip", "mg": "pb_mg.hip"}[which], "pb_stencil.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     with open(os.path.join(csrc, "pb_internal.h"), "rb") as fh:
         b = fh.read()
-    i = b.index(b"// ---- build kernels (pb_build.hip)")
-    j = b.index(b"// ---- solver kernels (pb_solve.hip)")
-    k = b.index(b"// ---- energy kernels (pb_energy.hip)")
-    h.update(b[:i])
-    h.update(b[j:k])
+    h.update(b[:b.index(b"// ---- build kernels (pb_build.hip)")])
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, bytes_per_launch):
-    t = COUNTER_TRAFFIC.get(kernel)
-    if not t or t["fingerprint"] != kernel_fingerprint():
+def counter_traffic(key, bytes_per_launch):
+    t = COUNTER_TRAFFIC.get(key)
+    if not t or not t["ratio"] or t["fingerprint"] != kernel_fingerprint(t["sources"]):
         return None
     return round(t["ratio"] * bytes_per_launch)
 DELTA = 1e-2
 DELTA_MG = 1e-4   # reliable-update factor of the multigrid-preconditioned mixed solve
-MG_MIN_N = 129    # serving: grids from this many nodes per axis use the multigrid preconditioner
+MG_MIN_N = 65     # serving: grids from this many nodes per axis use the multigrid preconditioner (all of
+                  # the stream's; batched, the multigrid requests share every launch)
 BIND_COMPLEXES, BIND_DISP, BIND_H = 6, 30, 0.5   # binding workload: complexes, displacements, spacing
 N_REQ = 512
 SEED = 2505
@@ -158,12 +165,6 @@ class NbodyTimes:
                 "launches_timed": self.calls, "total_ms": round(self.ms, 1), "scope": scope}
 
 
-def mg_vcycles(res, reqs):
-    """V-cycles of the multigrid requests in one served run: one per iteration, one per
-    restart from the true residual and one for the first residual."""
-    return sum(res[i]["iters"] + res[i]["outer_iters"] + 1 for i, (_, g) in enumerate(reqs) if g.precond == I.MG)
-
-
 def fifo_latency(arrivals, service):
     """Latency of a single FIFO server with the given arrivals and service times."""
     free = 0.0
@@ -175,28 +176,46 @@ def fifo_latency(arrivals, service):
     return np.array(lat)
 
 
+SERVE_BUDGET = 96 << 30   # HBM budget of the serving loop (a third of the device)
+ERR_BAR = 1e-6            # relative energy error every served result must meet
+
+
+def rf_hbm(kernel, ms_total, bytes_total, launches, scope, traffic_key=None):
+    """An HBM roofline record from timed launches and their algorithmic bytes."""
+    if not launches or ms_total <= 0:
+        return None
+    ach = bytes_total / (ms_total * 1e-3) / 1e9
+    bpl = bytes_total / launches
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": counter_traffic(traffic_key, bpl) if traffic_key else None,
+            "kernel": kernel, "bytes_per_launch": round(bpl), "avg_launch_ms": round(ms_total / launches, 5),
+            "launches_timed": launches, "total_ms": round(ms_total, 1), "scope": scope}
+
+
 def bench_serving(args, B, torch):
-    main = B.Context(0)
+    main = B.Context(0, hbm_budget_bytes=SERVE_BUDGET)
     side = B.Context(0, stream=torch.cuda.Stream(0))
     reqs, unit_arr = stream(N_REQ, args.serve_precond, args.mg_min_n)
     nu = np.array([g.unknowns for _, g in reqs], dtype=np.float64)
     n_mg = sum(1 for _, g in reqs if g.precond == I.MG)
     log(f"generated {N_REQ} requests")
 
-    # Every batched iteration launch of the run (warm-up, closed and open loop) is timed with
-    # HIP events on the serving stream, so that the average launch agrees with a kernel trace
-    # of the whole command.
+    # Every batched launch of the run (warm-up, closed and open loop) is timed with HIP events
+    # on the serving streams, so that the averages agree with a kernel trace of the command.
     main.set_profiling(True)
     side.set_profiling(True)
     prof = dict(stencil_ms=0.0, stencil_bytes=0.0, launches=0, mg_sweep_ms=0.0, mg_sweep_bytes=0.0,
-                mg_vcycle_ms=0.0, mg_samples=0)
+                mg_vcycle_ms=0.0, mg_samples=0, mg_apply_ms=0.0, mg_apply_bytes=0.0, mg_apply_launches=0)
     nbt = NbodyTimes()
+    mem_peak = [0]
 
     def close(srv):
         p = srv.profile()
         for k in prof:
             prof[k] += p[k]
         nbt.add_server(p)
+        mem_peak[0] = max(mem_peak[0], srv.memory()["peak"])
         srv.close()
 
     # warmup: the first requests through a server (untimed)
@@ -232,31 +251,44 @@ def bench_serving(args, B, torch):
                                  "p50_ms": round(1e3 * pct(l_s, 50), 1), "p99_ms": round(1e3 * pct(l_s, 99), 1)}
     log("open-loop sweep done")
 
-    # baseline: one at a time, plain FP64, same tolerance (same energy error)
-    svc, e64 = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for mol, g in reqs:
-        t = time.perf_counter()
-        r = B.solve(mol, replace(g, precision=I.FP64, precond=I.JACOBI), main)
-        svc.append(time.perf_counter() - t)
-        e64.append(r)
-        nbt.add_solve(r)
-    t_fp64 = time.perf_counter() - t0
-    log(f"fp64 one at a time: {N_REQ / t_fp64:.2f} solves/s")
+    # baselines, one request at a time in plain FP64 at the same tolerance (the same energy
+    # error): with Jacobi-CG, and with the served stream's own preconditioner policy
+    def one_at_a_time(precond=None):
+        svc, out = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for mol, g in reqs:
+            t = time.perf_counter()
+            r = B.solve(mol, replace(g, precision=I.FP64, precond=g.precond if precond is None else precond), main)
+            svc.append(time.perf_counter() - t)
+            out.append(r)
+            nbt.add_solve(r)
+        return time.perf_counter() - t0, svc, out
+
+    t_fp64, svc, e64 = one_at_a_time(I.JACOBI)
+    log(f"fp64 Jacobi one at a time: {N_REQ / t_fp64:.2f} solves/s")
+    t_fp64p, svc_p, _ = one_at_a_time()
+    log(f"fp64 same preconditioners one at a time: {N_REQ / t_fp64p:.2f} solves/s")
     lat64 = fifo_latency(arr, svc)
+    lat64p = fifo_latency(arr, svc_p)
     err_mix_vs_64 = max(max(relerr(res[i][k], e64[i][k]) for k in ("e_pol", "e_ion")) for i in range(N_REQ))
 
-    # energy error against tight FP64 solves on a sample of the stream
-    sample = list(range(0, N_REQ, N_REQ // 16))
-    err_ref = 0.0
-    for i in sample:
-        mol, g = reqs[i]
-        ref = B.solve(mol, replace(g, precision=I.FP64, rtol=1e-12, precond=I.JACOBI), main)
-        nbt.add_solve(ref)
-        err_ref = max(err_ref, max(relerr(res[i][k], ref[k]) for k in ("e_pol", "e_ion")))
+    # every served result against a tight FP64 solve of the same request (multigrid, rtol
+    # 1e-12), and against the stored oracle values of 16 requests of the stream
+    err_tight = []
+    for i, (mol, g) in enumerate(reqs):
+        ref = B.solve(mol, replace(g, precision=I.FP64, rtol=1e-12, precond=I.MG), main)
+        err_tight.append(max(relerr(res[i][k], ref[k]) for k in ("e_pol", "e_ion")))
+    err_tight = np.array(err_tight)
+    with open(os.path.join(ROOT, "tests", "golden", "c5_sample_oracle.json")) as fh:
+        gold = json.load(fh)
+    gold_reqs = [r for r in gold["requests"] if r["request"] < N_REQ]
+    err_oracle = max((relerr(res[r["request"]][k], r["energy"][k]) for r in gold_reqs for k in ("e_pol", "e_ion",
+                                                                                               "e_coul")),
+                     default=None)
+    log("energy errors done")
 
-    # precision comparison on the 385^3 single solve
+    # the 385^3 single solve: PCG node-iterations per second in FP64 and mixed (Jacobi-CG)
     mol4, g4 = I.large_c4()
     c4 = {}
     for name, prec in (("mixed", I.MIXED), ("fp64", I.FP64)):
@@ -266,51 +298,38 @@ def bench_serving(args, B, torch):
         nbt.add_solve(r)
         c4[name] = dict(gnode_iter_per_s=round(g4.unknowns * r["iters"] / r["t_solve_s"] / 1e9, 3),
                         iters=r["iters"], t_solve_ms=round(1e3 * r["t_solve_s"], 2))
-
     log("precision comparison done")
-    achieved = prof["stencil_bytes"] / (prof["stencil_ms"] * 1e-3) / 1e9 if prof["stencil_ms"] > 0 else None
-    rf_jacobi = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                 "traffic": counter_traffic("kb_iter<float>", prof["stencil_bytes"] / max(prof["launches"], 1)),
-                 "kernel": "kb_iter<float> (batched FP32 CG iteration)",
-                 "bytes_per_launch": round(prof["stencil_bytes"] / max(prof["launches"], 1)),
-                 "avg_launch_ms": round(prof["stencil_ms"] / max(prof["launches"], 1), 5),
-                 "launches_timed": prof["launches"],
-                 "scope": "every batched iteration launch of the run (warm-up, closed loop, open loop)"}
-    rf_mg = None
-    if prof["mg_samples"] > 0:
-        a_mg = prof["mg_sweep_bytes"] / (prof["mg_sweep_ms"] * 1e-3) / 1e9
-        n = prof["mg_samples"]
-        # the half-sweep runs four times per V-cycle (ν = 1: the black half of the fused first
-        # step, the residual pass, and the two post-smoothing half-sweeps each touch all nodes)
-        rf_mg = {"bound": "hbm", "achieved": round(a_mg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(a_mg / HBM_PEAK_GBS, 4), "traffic": None,
-                 "kernel": "k_sweep<float, true> (level-0 red-black half-sweep of the multigrid V-cycle)",
-                 "bytes_per_launch": round(prof["mg_sweep_bytes"] / n), "avg_launch_ms": round(prof["mg_sweep_ms"] / n, 5),
-                 "launches_timed": n, "avg_vcycle_ms": round(prof["mg_vcycle_ms"] / n, 5),
-                 "scope": "the first iteration of every chunk of every multigrid request (warm-up, closed and "
-                          "open loop)"}
-    # The roofline reported is that of the batched Jacobi iteration kernel: every launch of the
-    # served runs is timed (so its average agrees with a kernel trace of the command) and its
-    # HBM counters are on record.  The level-0 half-sweep of the V-cycle of the multigrid
-    # requests is reported beside it (sampled: the first iteration of every chunk; its total
-    # is estimated as two launches per V-cycle, one V-cycle per iteration and per restart).
-    rf_jacobi["total_ms"] = round(prof["stencil_ms"], 1)
-    if rf_mg is not None:
-        rf_mg["est_total_ms"] = round(rf_mg["avg_launch_ms"] * 2.0 * (mg_vcycles(res, reqs) + mg_vcycles(res_open, reqs)), 1)
-    # The dominant kernel of the run is the energy N-body sum (FP64 ALU bound), timed over every
-    # read-back of the run (served and standalone); the two solver kernels follow it.
-    roofline = nbt.roofline("every energy read-back of the run (served, FP64 baseline, tight references, "
-                            "385^3 comparison)")
     main.set_profiling(False)
     side.set_profiling(False)
-    other = [k for k in (rf_jacobi, rf_mg) if k is not None]
+
+    # Rooflines.  Every served launch of the batched multigrid operator pass is timed; the
+    # level-0 black half-sweep once per batched iteration (and per chunk of a request run alone);
+    # the batched Jacobi iteration kernel (requests below the multigrid threshold) on every
+    # launch; the energy N-body sum on every read-back of the run.  The kernel with the most
+    # timed GPU time is `roofline`, the others follow.
+    scope = "every batched launch of the run (warm-up, closed and open loop)"
+    rf_apply = rf_hbm("kb_rb_apply<float> (batched multigrid CG operator pass, level 0, red-black layout)",
+                      prof["mg_apply_ms"], prof["mg_apply_bytes"], prof["mg_apply_launches"], scope,
+                      "kb_rb_apply<float>@stream")
+    rf_sweep = rf_hbm("kb_rb_sweep<float> (batched level-0 black half-sweep of the V-cycle, red-black layout)",
+                      prof["mg_sweep_ms"], prof["mg_sweep_bytes"], prof["mg_samples"],
+                      "the first black half-sweep of every batched iteration (warm-up, closed and open loop)",
+                      "kb_rb_sweep<float>@stream")
+    if rf_sweep is not None:
+        rf_sweep["avg_vcycle_ms"] = round(prof["mg_vcycle_ms"] / prof["mg_samples"], 5)
+    rf_jacobi = rf_hbm("kb_iter<float> (batched FP32 Jacobi-CG iteration)", prof["stencil_ms"],
+                       prof["stencil_bytes"], prof["launches"], scope)
+    rf_nb = nbt.roofline("every energy read-back of the run (served, FP64 baselines, 385^3 comparison)")
+    ranked = sorted([r for r in (rf_nb, rf_apply, rf_sweep, rf_jacobi) if r is not None],
+                    key=lambda r: -r["total_ms"])
+    roofline, others = ranked[0], ranked[1:]
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline_stream(reqs)
 
     lat_closed = [r["latency_s"] for r in res.values()]
+    n_bad = int((err_tight > ERR_BAR).sum()) + int(err_oracle is not None and err_oracle > ERR_BAR)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * float(np.mean(walls)), 1), "higher_is_better": True,
@@ -318,14 +337,16 @@ def bench_serving(args, B, torch):
         "data": "synthetic",
         "config": {"workload": f"serving stream: {N_REQ} synthetic molecules (200-20000 atoms, log-uniform), "
                                f"grids 65^3-257^3, h in {{0.5,0.75,1.0}} A, mixed precision",
-                   "n_requests": N_REQ, "seed": SEED, "rtol": RTOL, "reliable_update_factor": DELTA,
+                   "n_requests": N_REQ, "seed": SEED, "rtol": RTOL,
+                   "reliable_update_factor": {"jacobi": DELTA, "multigrid": DELTA_MG},
                    "preconditioner": {"auto": f"multigrid V-cycle on grids >= {args.mg_min_n}^3, Jacobi below",
                                       "mg": "multigrid V-cycle", "jacobi": "Jacobi"}[args.serve_precond],
-                   "multigrid_requests": n_mg,
-                   "max_resident": args.max_resident, "unknowns_total": float(nu.sum()),
+                   "multigrid_requests": n_mg, "max_resident": args.max_resident,
+                   "hbm_budget_bytes": SERVE_BUDGET, "unknowns_total": float(nu.sum()),
                    "atoms_total": int(sum(m.n for m, _ in reqs))},
         "served_closed_loop": {"solves_per_s": round(value, 3), "p50_s": round(pct(lat_closed, 50), 3),
-                               "p99_s": round(pct(lat_closed, 99), 3), "codes": codes},
+                               "p99_s": round(pct(lat_closed, 99), 3), "codes": codes,
+                               "hbm_accounted_peak_bytes": mem_peak[0]},
         "served_open_loop": {"arrival_rate_hz": round(rate, 3), "solves_per_s": round(N_REQ / wall_open, 3),
                              "p50_ms": round(1e3 * pct(lat_open, 50), 1), "p99_ms": round(1e3 * pct(lat_open, 99), 1)},
         "served_open_loop_sweep": {"0.5x": sweep["0.5x"], "0.8x": {"arrival_rate_hz": round(rate, 3),
@@ -333,16 +354,31 @@ def bench_serving(args, B, torch):
                                                                   "p50_ms": round(1e3 * pct(lat_open, 50), 1),
                                                                   "p99_ms": round(1e3 * pct(lat_open, 99), 1)},
                                    "1.0x": sweep["1.0x"]},
-        "fp64_one_at_a_time": {"solves_per_s": round(N_REQ / t_fp64, 3), "mean_service_ms": round(1e3 * float(np.mean(svc)), 2),
+        "fp64_one_at_a_time": {"solves_per_s": round(N_REQ / t_fp64, 3), "preconditioner": "Jacobi",
+                               "mean_service_ms": round(1e3 * float(np.mean(svc)), 2),
                                "p50_ms_same_arrivals": round(1e3 * pct(lat64, 50), 1),
                                "p99_ms_same_arrivals": round(1e3 * pct(lat64, 99), 1)},
+        "fp64_one_at_a_time_same_preconditioners": {
+            "solves_per_s": round(N_REQ / t_fp64p, 3), "preconditioner": "as served (multigrid)",
+            "mean_service_ms": round(1e3 * float(np.mean(svc_p)), 2),
+            "p50_ms_same_arrivals": round(1e3 * pct(lat64p, 50), 1),
+            "p99_ms_same_arrivals": round(1e3 * pct(lat64p, 99), 1)},
         "speedup_vs_fp64_one_at_a_time": round(value / (N_REQ / t_fp64), 3),
-        "energy_relerr": {"served_vs_fp64_same_rtol_max": err_mix_vs_64,
-                          "served_vs_fp64_rtol1e-12_sample_max": err_ref, "sample_size": len(sample)},
-        "pcg_gnode_iter_per_s": {"workload": "385^3 single solve (60000 atoms, h=0.5 A)",
+        "speedup_decomposed": {
+            "preconditioner (fp64 multigrid vs fp64 Jacobi, one at a time)": round(t_fp64 / t_fp64p, 3),
+            "mixed precision and batching (served vs fp64 multigrid one at a time)": round(value / (N_REQ / t_fp64p), 3)},
+        "energy_relerr": {"bar": ERR_BAR, "requests_over_bar": n_bad,
+                          "served_vs_fp64_rtol1e-12_all_max": float(err_tight.max()),
+                          "served_vs_fp64_rtol1e-12_all_p50": float(np.median(err_tight)),
+                          "served_vs_fp64_same_rtol_max": err_mix_vs_64,
+                          "vs_oracle": {"max": err_oracle, "requests": len(gold_reqs),
+                                        "reference": "stored FP64 CPU-oracle energies (rtol 1e-12) of requests "
+                                                     + ",".join(str(r["request"]) for r in gold_reqs)}},
+        "pcg_gnode_iter_per_s": {"workload": "385^3 single solve (60000 atoms, h=0.5 A), Jacobi-CG",
                                  "mixed": c4["mixed"], "fp64": c4["fp64"]},
         "roofline": roofline,
-        "roofline_solver_kernels": other,
+        "roofline_solver_kernels": [r for r in others if r["bound"] == "hbm"],
+        "roofline_other": [r for r in others if r["bound"] != "hbm"],
         "stream_copy_GBs": round(main.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": cpu,
     }
@@ -447,8 +483,9 @@ def workload(name: str):
 NBODY_FLOPS_PER_PAIR = 27
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic bytes per interior unknown of one level-0 red-black half-sweep of the V-cycle
-# (FP32): read x and the node code of every node, b and 1/D of the swept colour, write x there
-MG_SWEEP_BYTES_FP32 = 4 + 4 + (4 + 4 + 4) / 2
+# (FP32, red-black layout): read x of the other colour, b and 1/D of the swept colour and the
+# node codes of both colours, write x of the swept colour
+MG_SWEEP_BYTES_FP32 = (4 + 4 + 4 + 4) / 2 + 4
 REFINED_ITER_BYTES = 49 + 17 + 65 + 25
 # ... and with FP32 coefficients and vectors (mixed precision)
 REFINED_ITER_BYTES_FP32 = 25 + 9 + 33 + 13
@@ -581,7 +618,7 @@ def bench_single(args, B, torch):
         return dict(solves_per_s=len(lat) / sum(lat), ms=1e3 * float(np.mean(lat)), p50=1e3 * pct(lat, 50),
                     p99=1e3 * pct(lat, 99), iters=float(iters), gnode=nu * iters / t_solve / 1e9,
                     stencil_ms=stencil_ms, update_ms=update_ms, vcycles=float(iters) + st["outer_iters"] + 1,
-                    err=max(relerr(en[k], ref[k]) for k in ("e_pol", "e_ion")))
+                    err=max(relerr(en[k], ref[k]) for k in ("e_pol", "e_ion")), en=en)
 
     nbt = NbodyTimes()
 
@@ -610,6 +647,7 @@ def bench_single(args, B, torch):
                    "grid_energy_call_ms": round(1e3 * min(hi[2], lo[2]), 3)}
     ach = nu * MG_SWEEP_BYTES_FP32 / (mg["stencil_ms"] * 1e-3) / 1e9
     ach_j = nu * ITER_BYTES_FP32 / (mx["stencil_ms"] * 1e-3) / 1e9
+    nu_tag = f"{grid.n[0]}" if grid.n[0] == grid.n[1] == grid.n[2] else "x".join(map(str, grid.n))
     out = {
         "metric": METRIC, "value": round(mg["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(mg["ms"], 3), "higher_is_better": True,
@@ -626,7 +664,8 @@ def bench_single(args, B, torch):
                          "iters": mx["iters"], "energy_relerr_vs_fp64": mx["err"],
                          "iteration_kernel": {"kernel": "k_cg_iter<float>", "achieved_GBs": round(ach_j, 1),
                                               "avg_launch_ms": round(mx["stencil_ms"], 5),
-                                              "traffic": counter_traffic("k_cg_iter<float>", nu * ITER_BYTES_FP32)}},
+                                              "traffic": counter_traffic(f"k_cg_iter<float>@{nu_tag}",
+                                                                         nu * ITER_BYTES_FP32)}},
         "fp64_plain": {"solves_per_s": round(p64["solves_per_s"], 3), "p50_ms": round(p64["p50"], 3),
                        "p99_ms": round(p64["p99"], 3), "iters": p64["iters"], "energy_relerr_vs_fp64": p64["err"]},
         "two_run_salt": two_run,
@@ -635,10 +674,12 @@ def bench_single(args, B, torch):
         "cpu_baseline": None,
     }
     # the dominant kernel of the multigrid solve's step: the level-0 half-sweep (two per
-    # V-cycle) or the energy N-body sum, whichever takes longer per step
+    # V-cycle) or the energy N-body sum, whichever takes longer per step; the Jacobi iteration
+    # kernel of the mixed Jacobi-CG solve beside them
     rf_sweep = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep<float, true> (level-0 red-black half-sweep of the V-cycle)",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic(f"kb_rb_sweep<float>@{nu_tag}", nu * MG_SWEEP_BYTES_FP32),
+                "kernel": "kb_rb_sweep<float> (level-0 black half-sweep of the V-cycle, red-black layout)",
                 "bytes_per_launch": nu * MG_SWEEP_BYTES_FP32, "avg_launch_ms": round(mg["stencil_ms"], 5),
                 "v_cycle_ms": round(mg["update_ms"], 5), "per_step_ms": round(2.0 * mg["vcycles"] * mg["stencil_ms"], 3)}
     rf_nb = nbt.roofline("every energy read-back of the timed solves (all four configurations)")
@@ -648,6 +689,23 @@ def bench_single(args, B, torch):
         out["roofline"], out["roofline_other"] = rf_nb, rf_sweep
     else:
         out["roofline"], out["roofline_other"] = rf_sweep, rf_nb
+    out["roofline_solver_kernels"] = [
+        rf_sweep,
+        {"bound": "hbm", "achieved": round(ach_j, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(ach_j / HBM_PEAK_GBS, 4),
+         "traffic": counter_traffic(f"k_cg_iter<float>@{nu_tag}", nu * ITER_BYTES_FP32),
+         "kernel": "k_cg_iter<float> (whole Jacobi-CG iteration in one pass, mixed form)",
+         "bytes_per_launch": nu * ITER_BYTES_FP32, "avg_launch_ms": round(mx["stencil_ms"], 5)}]
+    # energy error of every configuration against the oracle: the stored FP64 oracle values of
+    # this workload (rtol 1e-12) where they exist, and the oracle solve of the CPU baseline
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
+    vs = {}
+    if os.path.exists(gold_path):
+        with open(gold_path) as fh:
+            gold = json.load(fh)["energy"]
+        vs["stored_oracle_rtol1e-12"] = {name: max(relerr(r["en"][k], gold[k]) for k in ("e_pol", "e_ion", "e_coul"))
+                                         for name, r in (("multigrid_mixed", mg), ("multigrid_fp64", mg64),
+                                                         ("jacobi_mixed", mx), ("jacobi_fp64", p64))}
     if not args.no_cpu:
         from oracle import oracle as O
 
@@ -657,6 +715,10 @@ def bench_single(args, B, torch):
         out["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": O.num_threads(),
                                "kind": "oracle", "sample": f"one full FP64 oracle solve of the same workload at rtol "
                                                            f"{RTOL}: {dt:.1f} s, {run_o.iters} CG iterations"}
+        vs[f"oracle_rtol{RTOL:g}"] = {name: max(relerr(r["en"][k], run_o.energy[k]) for k in ("e_pol", "e_ion"))
+                                      for name, r in (("multigrid_mixed", mg), ("multigrid_fp64", mg64),
+                                                      ("jacobi_mixed", mx), ("jacobi_fp64", p64))}
+    out["energy_relerr_vs_oracle"] = vs or None
     ctx.close()
     return out
 
@@ -836,7 +898,11 @@ def main():
         out = bench_derefine(args, B, torch)
     else:
         out = bench_single(args, B, torch)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    bad = (out.get("energy_relerr") or {}).get("requests_over_bar", 0)
+    if bad:
+        print(f"[bench] {bad} served results exceed the {ERR_BAR:g} energy-error bar", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -405,13 +405,21 @@ int pb_server_times(const pb_server* srv, double* out4);
 int pb_server_profile(const pb_server* srv, double* stencil_ms_total, double* stencil_bytes_total,
                       int64_t* stencil_launches);
 
-/* The same for the multigrid requests: for the first iteration of every chunk of each such
- * request (more than one level, iteration performed), the HIP-event time (ms) of the level-0
- * black half-sweep after the coarse correction and its algorithmic bytes (14 per interior
- * unknown: x and the node code of every node read, b and 1/D of the swept colour read, x of
- * that colour written), the time of the whole V-cycle, and the number of samples. */
+/* The same for the multigrid requests: for every iteration of the batched multigrid chunks
+ * (and the first iteration of every chunk of a request run alone) in which at least one
+ * request iterated, the HIP-event time (ms) of the level-0 black half-sweep after the coarse
+ * correction and its algorithmic bytes (12 per interior unknown of the requests that
+ * iterated: in the red-black layout x of the other colour, b and 1/D of the swept colour and
+ * the node codes of both read, x of the swept colour written), the time of the whole
+ * V-cycle, and the number of samples. */
 int pb_server_profile_mg(const pb_server* srv, double* sweep_ms_total, double* sweep_bytes_total,
                          double* vcycle_ms_total, int64_t* samples);
+
+/* The batched operator pass of the multigrid CG (q = A p with the new direction), timed the
+ * same way: HIP-event time (ms), algorithmic bytes (20 per interior unknown of the requests
+ * that iterated: z, the old direction and the node codes read, the new direction and q
+ * written), and the number of launches timed. */
+int pb_server_profile_mg_apply(const pb_server* srv, double* ms_total, double* bytes_total, int64_t* launches);
 
 /* With profiling on in build_ctx: the HIP-event time (ms) of the energy N-body kernel summed
  * over every request read back, the pairs (n_atoms * n_cut) summed likewise, and the number

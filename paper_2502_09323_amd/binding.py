@@ -30,7 +30,7 @@ EXPORTED = [
     "pb_server_times", "pb_server_profile", "pb_refine_info", "pb_copy_refined_cells", "pb_copy_fine_potential",
     "pb_mg_vcycle", "pb_server_profile_mg", "pb_binding_ddg", "pb_get_energy_profile", "pb_server_profile_energy",
     "pb_grid_energy", "pb_cancel", "pb_server_set_timeout", "pb_server_memory", "pb_energy_noalloc",
-    "pb_energy_noalloc_limit",
+    "pb_energy_noalloc_limit", "pb_server_profile_mg_apply",
 ]
 
 
@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
     L.pb_mg_vcycle.argtypes = [P, P, P, C.POINTER(i32)]
     L.pb_get_energy_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pb_server_profile_energy.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
+    L.pb_server_profile_mg_apply.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64)]
     L.pb_binding_ddg.argtypes = [C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut), C.POINTER(PbEnergyOut),
                                  C.POINTER(PbBindingOut)]
     _lib = L
@@ -494,6 +495,11 @@ class Server:
         if rc != PB_OK:
             raise _err(rc)
         out.update(nbody_ms=f.value, nbody_pairs=g.value, nbody_calls=k.value)
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        rc = _lib.pb_server_profile_mg_apply(self.h, C.byref(a), C.byref(b), C.byref(n))
+        if rc != PB_OK:
+            raise _err(rc)
+        out.update(mg_apply_ms=a.value, mg_apply_bytes=b.value, mg_apply_launches=n.value)
         return out
 
     def cancel(self, request_id: int):

@@ -298,9 +298,9 @@ int pbi_mg_start(pb_problem* pb, hipStream_t s);
 bool pbi_mg_batchable(const pb_problem* pb);
 // n iterations of every problem of pbs (at most PB_MG_MAX_BATCH, batchable, one precision and
 // the same smoothing counts) in batched launches, then the restart where one is due, and the
-// problems' states into gather[0 .. pbs.size()) (device); ev (optional): 4 events per
-// iteration around its V-cycle and the first level-0 black half-sweep after the coarse
-// correction
+// problems' states into gather[0 .. pbs.size()) (device); ev (optional): 6 events per
+// iteration, two around its operator pass, then four around its V-cycle and the first
+// level-0 black half-sweep after the coarse correction
 int pbi_mg_batch_chunk(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGBatch* bb, pbk::CGState* gather,
                        hipEvent_t* ev);
 // one V-cycle of pb's multigrid (set up by pbi_mg_begin, in pb's precision) on level 0:

@@ -178,6 +178,12 @@ __device__ __forceinline__ bool gated_out(const GateSpec& g, const CGState* st)
 // taking kPlanes x-planes, so that no thread divides to find its node and a launch has few
 // enough blocks that one which finds the iteration stopped costs little.
 constexpr int kPlanes = 4;
+// level 0 (red-black layout): more x-planes per thread, so that fewer neighbour planes are
+// read again at the edges of a block's slab
+#ifndef PB_PLANES_RB
+#define PB_PLANES_RB 8
+#endif
+constexpr int kPlanesRB = PB_PLANES_RB;
 
 struct VB {   // a block of a problem's own 3-D launch
     int x, y, z;
@@ -196,9 +202,19 @@ __device__ __forceinline__ VB vb_of(int local, int gx, int gy)
 __host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz + 1) / 2 + 63) / 64; }
 __host__ __device__ inline int rows_gy(int ny) { return (ny - 2 + 3) / 4; }
 
-inline int rb_blocks(const RB& r) { return rb_gx(r) * rows_gy(r.ny) * ((r.nx - 2 + kPlanes - 1) / kPlanes); }
+inline int rb_blocks(const RB& r) { return rb_gx(r) * rows_gy(r.ny) * ((r.nx - 2 + kPlanesRB - 1) / kPlanesRB); }
 
-__device__ __forceinline__ VB vb_rb(const RB& r, int local) { return vb_of(local, rb_gx(r), rows_gy(r.ny)); }
+// block `local` of a level-0 pass of nb blocks takes tile item(local): blocks are dealt to the
+// 8 XCDs round-robin (a problem's blocks start at a multiple of 8), and this bijection gives
+// each XCD one contiguous range of tiles (x fastest, then rows, then plane slabs), so that the
+// neighbour rows and planes a tile reads were mostly brought into that XCD's L2 by the tiles
+// just before it
+__device__ __forceinline__ VB vb_rb(const RB& r, int local, int nb)
+{
+    const int q8 = nb >> 3, rem = nb & 7, xcd = local & 7;
+    const int item = xcd * q8 + (xcd < rem ? xcd : rem) + (local >> 3);
+    return vb_of(item, rb_gx(r), rows_gy(r.ny));
+}
 
 // blocks along z of a coarse-level pass over all interior nodes or over the nodes of one colour
 __host__ __device__ inline int lev_gx(const Grid& g, bool colour)
@@ -222,7 +238,7 @@ __device__ __forceinline__ bool rb_slot(const VB& b, const RB& r, int p, int& i,
 {
     m = b.x * 64 + (int)(threadIdx.x & 63);
     j = 1 + b.y * 4 + (int)(threadIdx.x >> 6);
-    i = 1 + b.z * kPlanes + p;
+    i = 1 + b.z * kPlanesRB + p;
     return i <= r.nx - 2 && j <= r.ny - 2;
 }
 
@@ -650,14 +666,15 @@ __global__ void __launch_bounds__(256) kb_rb_down1(Bt<T> B, GateSpec gs)
 {
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const T* __restrict__ b = D.cr;
     const T* __restrict__ dinv = D.dinv0;
     T* __restrict__ x = D.cz;
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         if (rb_node(R, i, j, 0, m) >= 0) {
@@ -683,14 +700,15 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
     __shared__ double sh[8];
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const T* __restrict__ b = D.cr;
     const T* __restrict__ x = D.cz;
     double v[1] = {0.0};
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, c, m);
@@ -722,12 +740,13 @@ __global__ void __launch_bounds__(256) kb_rb_resid(Bt<T> B, GateSpec gs)
 {
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const T* __restrict__ x = D.cz;
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, 0, m);
@@ -746,13 +765,14 @@ __global__ void __launch_bounds__(256) kb_rb_prolong(Bt<T> B, GateSpec gs)
 {
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const Grid& gc = D.lv[1].g;
     const T* __restrict__ ec = D.lv[1].x;
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, 0, m);
@@ -786,10 +806,11 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
     __shared__ double sh[8];
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     const CGState* st = D.st;
     if (st->status != 0) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const T* __restrict__ z = D.cz;
     const T* __restrict__ po = p_old(st, (const T*)D.cp, (const T*)D.cp2);
     T* __restrict__ pn = p_new(st, D.cp, D.cp2);
@@ -797,7 +818,7 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
     auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
     double v[1] = {0.0};
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         for (int c = 0; c < 2; ++c) {
@@ -824,6 +845,7 @@ __global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
     __shared__ double sh[8];
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     const CGState* st = D.st;
     if (st->status != 0) return;
     const T* __restrict__ p = p_new(st, D.cp, D.cp2);
@@ -850,6 +872,7 @@ __global__ void __launch_bounds__(256) kb_rb_dot(Bt<T> B, GateSpec gs)
     __shared__ double sh[8];
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     double v[1] = {0.0};
     const int64_t step = (int64_t)D.nb * 256;
@@ -866,11 +889,12 @@ __global__ void __launch_bounds__(256) kb_rb_fold(Bt<T> B, int force)
 {
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (!force && D.st->status != 3) return;
     const RB& R = D.rb;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         for (int c = 0; c < 2; ++c) {
@@ -892,15 +916,16 @@ __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
     __shared__ double sh[8];
     int local;
     const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    if (local >= D.nb) return;   // alignment padding between problems
     if (!force && D.st->status != 3) return;
     const RB& R = D.rb;
     const Grid& g = D.g0;
-    const VB vb = vb_rb(R, local);
+    const VB vb = vb_rb(R, local, D.nb);
     const double* __restrict__ x = D.x64;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
     double v[1] = {0.0};
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         for (int c = 0; c < 2; ++c) {
@@ -1077,9 +1102,9 @@ __global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* _
 template <typename T>
 __global__ void __launch_bounds__(256) k_rb_diag0(Grid g, RB r, Op0<T> op, T* __restrict__ dinv)
 {
-    const VB vb = vb_rb(r, (int)blockIdx.x);
+    const VB vb = vb_rb(r, (int)blockIdx.x, (int)gridDim.x);
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, r, p, i, j, m)) continue;
         for (int c = 0; c < 2; ++c) {
@@ -1098,9 +1123,9 @@ __global__ void __launch_bounds__(256) k_rb_convert(Grid g, RB r, T* __restrict_
                                                     GateSpec gs, const CGState* st)
 {
     if (gated_out(gs, st)) return;
-    const VB vb = vb_rb(r, (int)blockIdx.x);
+    const VB vb = vb_rb(r, (int)blockIdx.x, (int)gridDim.x);
 #pragma unroll
-    for (int p = 0; p < kPlanes; ++p) {
+    for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, r, p, i, j, m)) continue;
         for (int c = 0; c < 2; ++c) {
@@ -1315,6 +1340,9 @@ void plan_tables(const std::vector<const MGData*>& Gs, Plan& pl, std::vector<int
     pl.top = 0;
     for (int p = 0; p < P; ++p) {
         pass_counts(Gs[p], cnt);
+        // a problem's level-0 blocks start at a multiple of 8, so that its block b runs on XCD
+        // b % 8 as in a launch of its own (the tile map depends on it)
+        pl.total[K_RB0] = (pl.total[K_RB0] + 7) & ~7;
         for (int k = 0; k < K_N; ++k) {
             offs[(size_t)k * (P + 1) + p] = pl.total[k];
             pl.total[k] += cnt[k];
@@ -1412,12 +1440,15 @@ void run_vcycle(hipStream_t s, const Plan& pl, GateSpec gs, hipEvent_t* ev = nul
     if (ev) (void)hipEventRecord(ev[3], s);
 }
 
-// one CG iteration of every problem of the plan
+// one CG iteration of every problem of the plan (ev: the V-cycle's four events; ea: two
+// events around the operator pass)
 template <typename T>
-void run_iteration(hipStream_t s, const Plan& pl, hipEvent_t* ev = nullptr)
+void run_iteration(hipStream_t s, const Plan& pl, hipEvent_t* ev = nullptr, hipEvent_t* ea = nullptr)
 {
     const GateSpec gs{nullptr, 0};
+    if (ea) (void)hipEventRecord(ea[0], s);
     PLAUNCH0(K_RB0, 256, kb_rb_apply<T>);
+    if (ea) (void)hipEventRecord(ea[1], s);
     PLAUNCH0(K_ONE, 256, kb_alpha<T>);
     PLAUNCH0(K_RB0, 256, kb_rb_update<T>);
     run_vcycle<T>(s, pl, gs, ev);
@@ -1803,7 +1834,8 @@ int batch_chunk_t(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGB
     RCHK(hipMemcpyAsync(bb->dev, bb->host, need, hipMemcpyHostToDevice, s));
     pl.desc = bb->dev;
     pl.off = (const int*)((char*)bb->dev + sizeof(void*) * P);
-    for (int it = 0; it < n; ++it) run_iteration<T>(s, pl, ev ? ev + 4 * it : nullptr);
+    for (int it = 0; it < n; ++it)
+        run_iteration<T>(s, pl, ev ? ev + 6 * it + 2 : nullptr, ev ? ev + 6 * it : nullptr);
     if (sizeof(T) == 4) run_restart<T>(s, pl, 0, 0);
     if (gather) kb_gather<T><<<P, 64, 0, s>>>(bt<T>(pl, K_ONE), gather);
     RCHK(hipGetLastError());

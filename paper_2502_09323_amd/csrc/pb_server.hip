@@ -163,6 +163,8 @@ struct pb_server {
     int64_t mg_batch_launches = 0;   // batched chunks launched
     double prof_mg_ms = 0, prof_mg_bytes = 0, prof_mg_vcycle_ms = 0;
     int64_t prof_mg_n = 0;
+    double prof_mga_ms = 0, prof_mga_bytes = 0;   // the batched operator pass of the multigrid CG
+    int64_t prof_mga_n = 0;
     // the energy N-body kernel of every request read back while build_ctx profiles
     double prof_nb_ms = 0, prof_nb_pairs = 0;
     int64_t prof_nb_n = 0;
@@ -242,17 +244,25 @@ int complete_slot(pb_server* s, int k)
                     for (auto& a : s->act)
                         if (a.id == br.ids[q]) done[q] = s->hgather[k][m].iter_count - a.snap.iter_count;
         for (int j = 0; j < br.n && !br.ev.empty(); ++j) {
-            double bytes = 0.0;
+            double nu = 0.0;
             for (size_t q = 0; q < br.ids.size(); ++q)
-                if (j < done[q]) bytes += 12.0 * (double)br.nu[q];
-            if (bytes <= 0.0) continue;
-            float sw = 0, vc = 0;
-            SCHK(hipEventElapsedTime(&sw, br.ev[4 * j + 1], br.ev[4 * j + 2]));
-            SCHK(hipEventElapsedTime(&vc, br.ev[4 * j], br.ev[4 * j + 3]));
+                if (j < done[q]) nu += (double)br.nu[q];
+            if (nu <= 0.0) continue;
+            const hipEvent_t* e = br.ev.data() + 6 * j;
+            float ap = 0, sw = 0, vc = 0;
+            SCHK(hipEventElapsedTime(&ap, e[0], e[1]));
+            SCHK(hipEventElapsedTime(&sw, e[3], e[4]));
+            SCHK(hipEventElapsedTime(&vc, e[2], e[5]));
+            // algorithmic bytes per unknown: the black half-sweep 12 (x of the other colour,
+            // b and 1/D of the swept one and the codes of both read, x written), the operator
+            // pass 20 (z, the old direction and the codes read; the new direction and q written)
             s->prof_mg_ms += sw;
             s->prof_mg_vcycle_ms += vc;
-            s->prof_mg_bytes += bytes;
+            s->prof_mg_bytes += 12.0 * nu;
             s->prof_mg_n += 1;
+            s->prof_mga_ms += ap;
+            s->prof_mga_bytes += 20.0 * nu;
+            s->prof_mga_n += 1;
         }
         for (auto e : br.ev) s->ev_pool.push_back(e);
     }
@@ -652,7 +662,7 @@ int launch_chunk(pb_server* s, int k)
             br.nu.push_back(unknowns(a->pb));
         }
         if (s->ctx->profile) {
-            br.ev.resize((size_t)4 * br.n);
+            br.ev.resize((size_t)6 * br.n);
             for (auto& e : br.ev)
                 if ((rc = pool_event(s, &e))) return rc;
         }
@@ -882,6 +892,15 @@ int pb_server_profile_mg(const pb_server* s, double* sweep_ms_total, double* swe
     if (sweep_bytes_total) *sweep_bytes_total = s->prof_mg_bytes;
     if (vcycle_ms_total) *vcycle_ms_total = s->prof_mg_vcycle_ms;
     if (samples) *samples = s->prof_mg_n;
+    return PB_OK;
+}
+
+int pb_server_profile_mg_apply(const pb_server* s, double* ms_total, double* bytes_total, int64_t* launches)
+{
+    if (!s) return pbi_fail(PB_EINVAL, "NULL server");
+    if (ms_total) *ms_total = s->prof_mga_ms;
+    if (bytes_total) *bytes_total = s->prof_mga_bytes;
+    if (launches) *launches = s->prof_mga_n;
     return PB_OK;
 }
 

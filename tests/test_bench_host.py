@@ -43,14 +43,14 @@ def test_serving_stream_policy():
 
 
 def test_counter_traffic_needs_the_fingerprint_it_was_taken_on():
-    fp = BN.kernel_fingerprint()
-    assert len(fp) == 16
-    saved = dict(BN.COUNTER_TRAFFIC)
+    fp = BN.kernel_fingerprint("mg")
+    assert len(fp) == 16 and fp != BN.kernel_fingerprint("solve")
+    saved = {k: dict(v) for k, v in BN.COUNTER_TRAFFIC.items()}
     try:
-        BN.COUNTER_TRAFFIC["kb_iter<float>"] = {"fingerprint": "0" * 16, "ratio": 1.5}
-        assert BN.counter_traffic("kb_iter<float>", 1000) is None
-        BN.COUNTER_TRAFFIC["kb_iter<float>"] = {"fingerprint": fp, "ratio": 1.5}
-        assert BN.counter_traffic("kb_iter<float>", 1000) == 1500
+        BN.COUNTER_TRAFFIC["x@y"] = {"sources": "mg", "fingerprint": "0" * 16, "ratio": 1.5}
+        assert BN.counter_traffic("x@y", 1000) is None
+        BN.COUNTER_TRAFFIC["x@y"] = {"sources": "mg", "fingerprint": fp, "ratio": 1.5}
+        assert BN.counter_traffic("x@y", 1000) == 1500
         assert BN.counter_traffic("no_such_kernel", 1000) is None
     finally:
         BN.COUNTER_TRAFFIC.clear()

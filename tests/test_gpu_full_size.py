@@ -11,7 +11,8 @@ the small-size parity tests (coefficients 1e-13 relative, crossing geometry 1e-1
 weights 1e-12 relative to the largest, fluxes 1e-8, potentials 1e-9 of their largest value).
 The 385^3 problem is compared through the same launch configuration ``bench.py --workload
 c4`` times; the serving-stream sample goes through the serving loop at the benchmark's
-tolerances."""
+tolerances; the refined 193^3 problem (``--workload c3``) with the two-level preconditioner
+its mixed line times."""
 import hashlib
 import json
 import os
@@ -163,4 +164,38 @@ def test_c5_stream_sample_parity(ctx):
         ai = np.asarray(rec["atoms"]["idx"], dtype=np.int64)
         pr = np.asarray(rec["atoms"]["phi_reac"])
         assert np.max(np.abs(en["phi_reac"][ai] - pr)) <= 1e-9 * max(np.max(np.abs(pr)), 1e-300)
+        pb.close()
+
+
+def test_c3_refined_full_size_parity(ctx):
+    """20,000 atoms, 193^3 coarse nodes refined to h/2 near the surface: the refinement flags
+    and the cut count exact, the FP64 solve with the two-level preconditioner at 1e-10 on the
+    energies and 1e-9 on sampled reaction potentials, the benchmark's mixed two-level solve
+    at 1e-6."""
+    ref = golden("c3_oracle.json")
+    mol, grid = I.refined_c3()
+    print("C3 parity: FP64 two-level, rtol 1e-12", flush=True)
+    pb = B.Problem(ctx, mol, replace(grid, precision=I.FP64, precond=I.MG, rtol=1e-12))
+    try:
+        assert sha(pb.refined_cells().astype(np.uint8)) == ref["sha256_refined_cells"], "refinement flags differ"
+        st = pb.solve()
+        assert st["status"] == 0
+        en = pb.energy(per_atom=True)
+        assert en["n_cut"] == ref["n_cut"]
+        check_energies(en, ref, E_TOL64)
+        assert abs(en["q_pol_total"] - ref["energy"]["q_pol_total"]) <= 1e-10 * abs(ref["energy"]["q_pol_total"])
+        assert abs(en["area_total"] - ref["energy"]["area_total"]) <= 1e-12 * ref["energy"]["area_total"]
+        ai = np.asarray(ref["atoms"]["idx"], dtype=np.int64)
+        pr = np.asarray(ref["atoms"]["phi_reac"])
+        assert np.max(np.abs(en["phi_reac"][ai] - pr)) <= 1e-9 * np.max(np.abs(pr))
+    finally:
+        pb.close()
+    print("C3 parity: mixed two-level at the benchmark's tolerances", flush=True)
+    g = replace(grid, precision=I.MIXED, precond=I.MG, rtol=bench.RTOL, inner_rtol=bench.DELTA_MG)
+    pb = B.Problem(ctx, mol, g)
+    try:
+        st = pb.solve()
+        assert st["status"] == 0
+        check_energies(pb.energy(), ref, E_TOL_MIXED)
+    finally:
         pb.close()
