@@ -54,22 +54,38 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Every pointer that the kernels take from a hierarchy descriptor or a launch table points to
+// global memory.  Typed so in the device pass, the loads through it are global loads, and a
+// descriptor's fields are read with scalar loads, instead of flat loads whose addresses are
+// formed per lane.  The host pass sees plain pointers (same size and layout): the host only
+// writes the descriptors.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GMEM __attribute__((address_space(1)))
+#else
+#define GMEM
+#endif
+template <typename T>
+__host__ __device__ inline GMEM T* gmem(T* p)
+{
+    return (GMEM T*)p;
+}
+
 // one coarse level as the kernels see it
 template <typename T>
 struct Lev {
     Grid g;
-    const T *kx, *ky, *kz;   // K of the +x, +y, +z edges
-    const T* diag;           // diagonal
-    const T* dinv;           // 1 / diagonal
-    T* x;                    // iterate
-    const T* b;              // right-hand side
+    const GMEM T *kx, *ky, *kz;   // K of the +x, +y, +z edges
+    const GMEM T* diag;           // diagonal
+    const GMEM T* dinv;           // 1 / diagonal
+    GMEM T* x;                    // iterate
+    const GMEM T* b;              // right-hand side
 };
 
 // the level-0 operator from the natural-layout node codes
 template <typename T>
 struct Op0 {
-    const uint32_t* code;
-    const T* ck;
+    const GMEM uint32_t* code;
+    const GMEM T* ck;
     T kin, kout, mass;
 };
 
@@ -107,8 +123,8 @@ inline RB rb_of(const Grid& g)
 
 template <typename T>
 struct OpRB {
-    const uint32_t* code;   // red-black layout
-    const T* ck;
+    const GMEM uint32_t* code;   // red-black layout
+    const GMEM T* ck;
     T kin, kout, mass;
 };
 
@@ -120,15 +136,16 @@ struct MGDev {
     Grid g0;                     // level 0 in the natural layout (solution, right-hand side)
     OpRB<T> op;
     Op0<double> op64;            // FP64 operator from the natural codes (true residual)
-    T *cr, *cz, *cp, *cp2, *cq, *cx, *dinv0, *r0;   // level 0: CG r, z, p (two), q, correction x; 1/D; red residual
-    double* x64;                 // FP64 solution (natural layout)
-    const double* rhs;           // FP64 right-hand side (natural layout)
+    GMEM T *cr, *cz, *cp, *cp2, *cq, *cx, *dinv0, *r0;   // level 0: CG r, z, p (two), q, correction x; 1/D;
+                                                        // red residual
+    GMEM double* x64;            // FP64 solution (natural layout)
+    const GMEM double* rhs;      // FP64 right-hand side (natural layout)
     int nlev, ls, nu, cs;        // levels, first level of the one-block part (ls == nlev: none)
     Lev<T> lv[PB_MG_MAX_LEVELS]; // levels >= 1
-    T* r[PB_MG_MAX_LEVELS];      // red residual of levels >= 1
-    CGState* st;
-    double* part;                // [3 * nb] block partial sums
-    double* prz;                 // [nb] r.z partial sums of the last half-sweep
+    GMEM T* r[PB_MG_MAX_LEVELS]; // red residual of levels >= 1
+    GMEM CGState* st;
+    GMEM double* part;           // [3 * nb] block partial sums
+    GMEM double* prz;            // [nb] r.z partial sums of the last half-sweep
     int nb;                      // blocks of a level-0 pass
     int mixed;
     double rtol2, delta2;
@@ -138,13 +155,13 @@ struct MGDev {
 // problem may have none).
 template <typename T>
 struct Bt {
-    const MGDev<T>* const* d;
-    const int* off;
+    const GMEM MGDev<T>* const GMEM* d;
+    const GMEM int* off;
     int P;
 };
 
 // the problem of this block and the block's index in that problem's own launch
-__device__ __forceinline__ int bt_find(const int* off, int P, int& local)
+__device__ __forceinline__ int bt_find(const GMEM int* off, int P, int& local)
 {
     const int b = (int)blockIdx.x;
     int lo = 0, hi = P;
@@ -163,11 +180,11 @@ __device__ __forceinline__ int bt_find(const int* off, int P, int& local)
 // restart from the true residual (ru = 1) only while one is in progress; ungated (a V-cycle
 // on its own); or gated on another state (the two-level preconditioner of refined grids)
 struct GateSpec {
-    const CGState* ext;
+    const GMEM CGState* ext;
     int mode;   // 0 iteration, 1 restart, 2 none, 3 ext (running, ru 0; null: none)
 };
 
-__device__ __forceinline__ bool gated_out(const GateSpec& g, const CGState* st)
+__device__ __forceinline__ bool gated_out(const GateSpec& g, const GMEM CGState* st)
 {
     if (g.mode == 2) return false;
     if (g.mode == 3) return g.ext && (g.ext->status != 0 || g.ext->ru != 0);
@@ -273,13 +290,14 @@ template <typename T>
 __device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const RBNb& n)
 {
     const uint32_t c = op.code[n.e];
+    const T* ck = (const T*)op.ck;   // still a global pointer to the compiler (it follows the cast)
     stencil::NodeK<T> k;
-    k.xm = stencil::edgeK(op.code[n.xm], 0, op.ck, op.kin, op.kout);
-    k.xp = stencil::edgeK(c, 0, op.ck, op.kin, op.kout);
-    k.ym = stencil::edgeK(op.code[n.ym], 1, op.ck, op.kin, op.kout);
-    k.yp = stencil::edgeK(c, 1, op.ck, op.kin, op.kout);
-    k.zm = stencil::edgeK(op.code[n.zm], 2, op.ck, op.kin, op.kout);
-    k.zp = stencil::edgeK(c, 2, op.ck, op.kin, op.kout);
+    k.xm = stencil::edgeK(op.code[n.xm], 0, ck, op.kin, op.kout);
+    k.xp = stencil::edgeK(c, 0, ck, op.kin, op.kout);
+    k.ym = stencil::edgeK(op.code[n.ym], 1, ck, op.kin, op.kout);
+    k.yp = stencil::edgeK(c, 1, ck, op.kin, op.kout);
+    k.zm = stencil::edgeK(op.code[n.zm], 2, ck, op.kin, op.kout);
+    k.zp = stencil::edgeK(c, 2, ck, op.kin, op.kout);
     k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
     return k;
 }
@@ -361,7 +379,7 @@ __host__ __device__ inline int64_t interior_count(const Grid& g)
 
 // P e at fine node (i, j, k): trilinear from the coarse corners of its coarse cell
 template <typename T>
-__device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec, int i, int j, int k)
+__device__ __forceinline__ T prolong_at(const Grid& gc, const GMEM T* __restrict__ ec, int i, int j, int k)
 {
     const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
     const T v = ((ec[gc.idx(i0, j0, k0)] + ec[gc.idx(i0, j0, k1)]) + (ec[gc.idx(i0, j1, k0)] + ec[gc.idx(i0, j1, k1)])) +
@@ -371,7 +389,7 @@ __device__ __forceinline__ T prolong_at(const Grid& gc, const T* __restrict__ ec
 
 // the level of a coarse-level pass: l, or the problem's coarsest for l < 0
 template <typename T>
-__device__ __forceinline__ int lev_index(const MGDev<T>& D, int l)
+__device__ __forceinline__ int lev_index(const GMEM MGDev<T>& D, int l)
 {
     return l < 0 ? D.nlev - 1 : l;
 }
@@ -382,12 +400,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_down1(Bt<T> B, int l, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Lev<T>& L = D.lv[lev_index(D, l)];
+    const Lev<T> L = D.lv[lev_index(D, l)];
     const VB vb = vb_lev(L.g, false, local);
-    const T* __restrict__ b = L.b;
-    const T* __restrict__ dinv = L.dinv;
+    const GMEM T* __restrict__ b = L.b;
+    const GMEM T* __restrict__ dinv = L.dinv;
 #pragma unroll
     for (int r = 0; r < kPlanes; ++r) {
         bool red;
@@ -407,11 +425,11 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_sweep(Bt<T> B, int l, int c, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Lev<T>& L = D.lv[lev_index(D, l)];
+    const Lev<T> L = D.lv[lev_index(D, l)];
     const VB vb = vb_lev(L.g, true, local);
-    const T* __restrict__ x = L.x;
+    const GMEM T* __restrict__ x = L.x;
 #pragma unroll
     for (int r = 0; r < kPlanes; ++r) {
         int i, j, k;
@@ -428,12 +446,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_resid(Bt<T> B, int l, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Lev<T>& L = D.lv[l];
-    T* __restrict__ r = D.r[l];
+    const Lev<T> L = D.lv[l];
+    GMEM T* __restrict__ r = D.r[l];
     const VB vb = vb_lev(L.g, true, local);
-    const T* __restrict__ x = L.x;
+    const GMEM T* __restrict__ x = L.x;
 #pragma unroll
     for (int p = 0; p < kPlanes; ++p) {
         int i, j, k;
@@ -452,10 +470,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_restrict(Bt<T> B, int l, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Grid& gc = D.lv[l].g;
-    T* __restrict__ bc = const_cast<T*>(D.lv[l].b);
+    const Grid gc = D.lv[l].g;
+    GMEM T* __restrict__ bc = const_cast<GMEM T*>(D.lv[l].b);
     const VB vb = vb_lev(gc, false, local);
 #pragma unroll
     for (int p = 0; p < kPlanes; ++p) {
@@ -467,15 +485,15 @@ __global__ void __launch_bounds__(256) kb_restrict(Bt<T> B, int l, GateSpec gs)
         const int I = 1 + vb.z * kPlanes + p;
         const int i = 2 * I, j = 2 * J, k = 2 * K;
         if (l == 1) {
-            const T* __restrict__ r = D.r0;
+            const GMEM T* __restrict__ r = D.r0;
             auto R = [&](int a, int b, int c) { return r[D.rb.idx(i + a, j + b, k + c)]; };
             const T xy = (R(-1, -1, 0) + R(-1, 1, 0)) + (R(1, -1, 0) + R(1, 1, 0));
             const T xz = (R(-1, 0, -1) + R(-1, 0, 1)) + (R(1, 0, -1) + R(1, 0, 1));
             const T yz = (R(0, -1, -1) + R(0, -1, 1)) + (R(0, 1, -1) + R(0, 1, 1));
             bc[ec] = R(0, 0, 0) + (T)0.25 * ((xy + xz) + yz);
         } else {
-            const Grid& gf = D.lv[l - 1].g;
-            const T* __restrict__ r = D.r[l - 1];
+            const Grid gf = D.lv[l - 1].g;
+            const GMEM T* __restrict__ r = D.r[l - 1];
             const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
             const int64_t f = gf.idx(i, j, k);
             const T xy = (r[f - sx - sy] + r[f - sx + sy]) + (r[f + sx - sy] + r[f + sx + sy]);
@@ -492,11 +510,11 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_prolong(Bt<T> B, int l, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Lev<T>& L = D.lv[l];
-    const Grid& gc = D.lv[l + 1].g;
-    const T* __restrict__ ec = D.lv[l + 1].x;
+    const Lev<T> L = D.lv[l];
+    const Grid gc = D.lv[l + 1].g;
+    const GMEM T* __restrict__ ec = D.lv[l + 1].x;
     const VB vb = vb_lev(L.g, true, local);
 #pragma unroll
     for (int p = 0; p < kPlanes; ++p) {
@@ -512,9 +530,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_coarse(Bt<T> B, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
-    const Lev<T>& L = D.lv[D.nlev - 1];
+    const Lev<T> L = D.lv[D.nlev - 1];
     const Grid& g = L.g;
     const int n = (int)interior_count(g), nc = (int)colour_threads(g);
     for (int t = threadIdx.x; t < n; t += 256) {
@@ -523,7 +541,7 @@ __global__ void __launch_bounds__(256) kb_coarse(Bt<T> B, GateSpec gs)
         L.x[e] = red ? L.b[e] * L.dinv[e] : (T)0;
     }
     __syncthreads();
-    const T* __restrict__ x = L.x;
+    const GMEM T* __restrict__ x = L.x;
     for (int s = 0; s < 2 * D.cs; ++s) {
         const int c = (s & 1) ? 0 : 1;
         for (int t = threadIdx.x; t < nc; t += 256) {
@@ -548,7 +566,7 @@ template <typename T>
 __device__ __forceinline__ void blk_sweep(const Lev<T>& L, int c)
 {
     const int nc = (int)colour_threads(L.g);
-    const T* __restrict__ x = L.x;
+    const GMEM T* __restrict__ x = L.x;
     for (int t = threadIdx.x; t < nc; t += kSubThreads) {
         const int64_t e = colour_node(L.g, c, t);
         if (e < 0) continue;
@@ -573,12 +591,12 @@ template <typename T>
 __global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (gated_out(gs, D.st)) return;
     const int l0 = D.ls, nl = D.nlev;
     // down: pre-smoothing, residual at the red nodes, restriction
     for (int l = l0; l + 1 < nl; ++l) {
-        const Lev<T>& L = D.lv[l];
+        const Lev<T> L = D.lv[l];
         blk_red_from_zero(L);
         blk_sweep(L, 1);
         for (int v = 1; v < D.nu; ++v) {
@@ -586,8 +604,8 @@ __global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
             blk_sweep(L, 1);
         }
         const int nc = (int)colour_threads(L.g);
-        const T* __restrict__ x = L.x;
-        T* __restrict__ rl = D.r[l];
+        const GMEM T* __restrict__ x = L.x;
+        GMEM T* __restrict__ rl = D.r[l];
         for (int t = threadIdx.x; t < nc; t += kSubThreads) {
             const int64_t e = colour_node(L.g, 0, t);
             if (e < 0) continue;
@@ -597,9 +615,9 @@ __global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
         }
         __syncthreads();
         const Grid& gf = L.g;
-        const Grid& gc = D.lv[l + 1].g;
-        const T* __restrict__ r = rl;
-        T* bc = const_cast<T*>(D.lv[l + 1].b);
+        const Grid gc = D.lv[l + 1].g;
+        const GMEM T* __restrict__ r = rl;
+        GMEM T* bc = const_cast<GMEM T*>(D.lv[l + 1].b);
         const int n = (int)interior_count(gc);
         const int64_t sx = (int64_t)gf.ny * gf.S, sy = gf.S;
         for (int t = threadIdx.x; t < n; t += kSubThreads) {
@@ -617,7 +635,7 @@ __global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
     }
     // coarsest: red from zero, then (black, red) x cs
     {
-        const Lev<T>& L = D.lv[nl - 1];
+        const Lev<T> L = D.lv[nl - 1];
         blk_red_from_zero(L);
         for (int v = 0; v < D.cs; ++v) {
             blk_sweep(L, 1);
@@ -626,9 +644,9 @@ __global__ void __launch_bounds__(kSubThreads) kb_subcycle(Bt<T> B, GateSpec gs)
     }
     // up: coarse correction, post-smoothing
     for (int l = nl - 2; l >= l0; --l) {
-        const Lev<T>& L = D.lv[l];
-        const Grid& gc = D.lv[l + 1].g;
-        const T* __restrict__ ec = D.lv[l + 1].x;
+        const Lev<T> L = D.lv[l];
+        const Grid gc = D.lv[l + 1].g;
+        const GMEM T* __restrict__ ec = D.lv[l + 1].x;
         const int n = (int)colour_threads(L.g);
         for (int t = threadIdx.x; t < n; t += kSubThreads) {
             const int64_t e = colour_node(L.g, 0, t);   // red nodes only, as in kb_prolong
@@ -665,14 +683,14 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_down1(Bt<T> B, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const T* __restrict__ b = D.cr;
-    const T* __restrict__ dinv = D.dinv0;
-    T* __restrict__ x = D.cz;
+    const GMEM T* __restrict__ b = D.cr;
+    const GMEM T* __restrict__ dinv = D.dinv0;
+    GMEM T* __restrict__ x = D.cz;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
@@ -699,13 +717,13 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const T* __restrict__ b = D.cr;
-    const T* __restrict__ x = D.cz;
+    const GMEM T* __restrict__ b = D.cr;
+    const GMEM T* __restrict__ x = D.cz;
     double v[1] = {0.0};
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
@@ -739,12 +757,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_resid(Bt<T> B, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const T* __restrict__ x = D.cz;
+    const GMEM T* __restrict__ x = D.cz;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
@@ -764,13 +782,13 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_prolong(Bt<T> B, GateSpec gs)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const Grid& gc = D.lv[1].g;
-    const T* __restrict__ ec = D.lv[1].x;
+    const Grid gc = D.lv[1].g;
+    const GMEM T* __restrict__ ec = D.lv[1].x;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
@@ -787,12 +805,12 @@ __global__ void __launch_bounds__(256) kb_rb_prolong(Bt<T> B, GateSpec gs)
 // direction from buffer ic & 1 and writes the new one to the other (iter_count counts the
 // iterations that ran, so a restart between two iterations keeps the pairing).
 template <typename T>
-__device__ __forceinline__ const T* p_old(const CGState* st, const T* p0, const T* p1)
+__device__ __forceinline__ const GMEM T* p_old(const GMEM CGState* st, const GMEM T* p0, const GMEM T* p1)
 {
     return (st->iter_count & 1) ? p1 : p0;
 }
 template <typename T>
-__device__ __forceinline__ T* p_new(const CGState* st, T* p0, T* p1)
+__device__ __forceinline__ GMEM T* p_new(const GMEM CGState* st, GMEM T* p0, GMEM T* p1)
 {
     return (st->iter_count & 1) ? p0 : p1;
 }
@@ -805,15 +823,15 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
-    const CGState* st = D.st;
+    const GMEM CGState* st = D.st;
     if (st->status != 0) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const T* __restrict__ z = D.cz;
-    const T* __restrict__ po = p_old(st, (const T*)D.cp, (const T*)D.cp2);
-    T* __restrict__ pn = p_new(st, D.cp, D.cp2);
+    const GMEM T* __restrict__ z = D.cz;
+    const GMEM T* __restrict__ po = p_old(st, (const GMEM T*)D.cp, (const GMEM T*)D.cp2);
+    GMEM T* __restrict__ pn = p_new(st, D.cp, D.cp2);
     const T beta = (T)st->beta;
     auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
     double v[1] = {0.0};
@@ -844,14 +862,14 @@ __global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
-    const CGState* st = D.st;
+    const GMEM CGState* st = D.st;
     if (st->status != 0) return;
-    const T* __restrict__ p = p_new(st, D.cp, D.cp2);
-    T* __restrict__ x = D.cx;
-    T* __restrict__ r = D.cr;
-    const T* __restrict__ q = D.cq;
+    const GMEM T* __restrict__ p = p_new(st, D.cp, D.cp2);
+    GMEM T* __restrict__ x = D.cx;
+    GMEM T* __restrict__ r = D.cr;
+    const GMEM T* __restrict__ q = D.cq;
     const T a = (T)st->alpha;
     double v[1] = {0.0};
     const int64_t step = (int64_t)D.nb * 256;
@@ -871,7 +889,7 @@ __global__ void __launch_bounds__(256) kb_rb_dot(Bt<T> B, GateSpec gs)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
     double v[1] = {0.0};
@@ -888,10 +906,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_fold(Bt<T> B, int force)
 {
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (!force && D.st->status != 3) return;
-    const RB& R = D.rb;
+    const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
@@ -915,13 +933,13 @@ __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (!force && D.st->status != 3) return;
-    const RB& R = D.rb;
-    const Grid& g = D.g0;
+    const RB R = D.rb;
+    const Grid g = D.g0;
     const VB vb = vb_rb(R, local, D.nb);
-    const double* __restrict__ x = D.x64;
+    const GMEM double* __restrict__ x = D.x64;
     const int64_t sx = (int64_t)g.ny * g.S, sy = g.S;
     double v[1] = {0.0};
 #pragma unroll
@@ -933,7 +951,8 @@ __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
             if (k < 0) continue;
             const int64_t e = g.idx(i, j, k);
             const stencil::NodeK<double> K =
-                stencil::node_k(g, D.op64.code, D.op64.ck, D.op64.kin, D.op64.kout, D.op64.mass, e);
+                stencil::node_k(g, (const uint32_t*)D.op64.code, (const double*)D.op64.ck, D.op64.kin, D.op64.kout,
+                                D.op64.mass, e);
             const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
                              (K.zm * x[e - 1] + K.zp * x[e + 1]);
             const double rv = D.rhs[e] - (K.diag() * x[e] - s);
@@ -949,7 +968,7 @@ __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
 
 // sum of n partials in a fixed order (eight interleaved accumulators per thread keep many
 // loads in flight)
-__device__ __forceinline__ double psum(const double* __restrict__ a, int n)
+__device__ __forceinline__ double psum(const GMEM double* __restrict__ a, int n)
 {
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int t = threadIdx.x;
@@ -965,8 +984,8 @@ __global__ void __launch_bounds__(256) kb_alpha(Bt<T> B)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
-    CGState* st = D.st;
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    GMEM CGState* st = D.st;
     if (st->status != 0) return;
     double v[1] = {psum(D.part, D.nb)};
     bsum(v, 1, sh);
@@ -993,8 +1012,8 @@ __global__ void __launch_bounds__(256) kb_beta(Bt<T> B, int mode)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
-    CGState* st = D.st;
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    GMEM CGState* st = D.st;
     if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
     double v[2] = {psum(D.nlev > 1 ? D.prz : D.part, D.nb), mode == 0 ? psum(D.part + D.nb, D.nb) : 0.0};
     bsum(v, 2, sh);
@@ -1035,8 +1054,8 @@ __global__ void __launch_bounds__(256) kb_ru_fin(Bt<T> B, int init, int force)
 {
     __shared__ double sh[8];
     int local;
-    const MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
-    CGState* st = D.st;
+    const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
+    GMEM CGState* st = D.st;
     if (!force && st->status != 3) return;
     double v[1] = {psum(D.part + 2 * D.nb, D.nb)};
     bsum(v, 1, sh);
@@ -1075,7 +1094,7 @@ __global__ void __launch_bounds__(64) kb_gather(Bt<T> B, CGState* out)
 {
     int local;
     const int p = bt_find(B.off, B.P, local);
-    const MGDev<T>& D = *B.d[p];
+    const GMEM MGDev<T>& D = *B.d[p];
     const int n = (int)(sizeof(CGState) / sizeof(int));
     const int* s = (const int*)D.st;
     int* o = (int*)(out + p);
@@ -1111,7 +1130,7 @@ __global__ void __launch_bounds__(256) k_rb_diag0(Grid g, RB r, Op0<T> op, T* __
             const int k = rb_node(r, i, j, c, m);
             if (k < 0) continue;
             dinv[r.at(i, j, c, m)] =
-                (T)1 / stencil::node_k(g, op.code, op.ck, op.kin, op.kout, op.mass, g.idx(i, j, k)).diag();
+                (T)1 / stencil::node_k(g, (const uint32_t*)op.code, (const T*)op.ck, op.kin, op.kout, op.mass, g.idx(i, j, k)).diag();
         }
     }
 }
@@ -1122,7 +1141,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_rb_convert(Grid g, RB r, T* __restrict__ nat, T* __restrict__ rbv, int to_rb,
                                                     GateSpec gs, const CGState* st)
 {
-    if (gated_out(gs, st)) return;
+    if (gated_out(gs, gmem(st))) return;
     const VB vb = vb_rb(r, (int)blockIdx.x, (int)gridDim.x);
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
@@ -1264,11 +1283,11 @@ template <typename T>
 Op0<T> op0(const pb_problem* pb)
 {
     Op0<T> o;
-    o.code = pb->code;
+    o.code = gmem((const uint32_t*)pb->code);
     if constexpr (sizeof(T) == 8)
-        o.ck = (const T*)pb->ck64;
+        o.ck = gmem((const T*)pb->ck64);
     else
-        o.ck = (const T*)pb->ck32;
+        o.ck = gmem((const T*)pb->ck32);
     o.kin = (T)pb->cf.kin;
     o.kout = (T)pb->cf.kout;
     o.mass = (T)pb->cf.mass;
@@ -1358,7 +1377,7 @@ void plan_tables(const std::vector<const MGData*>& Gs, Plan& pl, std::vector<int
 template <typename T>
 Bt<T> bt(const Plan& pl, int kind)
 {
-    return Bt<T>{(const MGDev<T>* const*)pl.desc, pl.off + (size_t)kind * (pl.P + 1), pl.P};
+    return Bt<T>{(const GMEM MGDev<T>* const GMEM*)pl.desc, gmem((const int*)(pl.off + (size_t)kind * (pl.P + 1))), pl.P};
 }
 
 #define PLAUNCH(kind, threads, kernel, ...)                                                          \
@@ -1477,13 +1496,13 @@ Lev<T> level(const MGData* G, int l)
 {
     Lev<T> L;
     L.g = G->g[l];
-    L.kx = (const T*)G->K[l][0];
-    L.ky = (const T*)G->K[l][1];
-    L.kz = (const T*)G->K[l][2];
-    L.diag = (const T*)G->diag[l];
-    L.dinv = (const T*)G->dinv[l];
-    L.x = (T*)G->x[l];
-    L.b = (const T*)G->b[l];
+    L.kx = gmem((const T*)G->K[l][0]);
+    L.ky = gmem((const T*)G->K[l][1]);
+    L.kz = gmem((const T*)G->K[l][2]);
+    L.diag = gmem((const T*)G->diag[l]);
+    L.dinv = gmem((const T*)G->dinv[l]);
+    L.x = gmem((T*)G->x[l]);
+    L.b = gmem((const T*)G->b[l]);
     return L;
 }
 
@@ -1498,29 +1517,29 @@ MGDev<T> describe(const pb_problem* pb)
     d.rb = rb_of(pb->g);
     d.g0 = pb->g;
     const Op0<T> o = op0<T>(pb);
-    d.op = OpRB<T>{G->code_rb, o.ck, o.kin, o.kout, o.mass};
+    d.op = OpRB<T>{gmem((const uint32_t*)G->code_rb), o.ck, o.kin, o.kout, o.mass};
     d.op64 = op0<double>(pb);
-    d.cr = (T*)G->cr;
-    d.cz = (T*)G->cz;
-    d.cp = (T*)G->cp;
-    d.cp2 = (T*)G->cp2;
-    d.cq = (T*)G->cq;
-    d.cx = (T*)G->cx;
-    d.dinv0 = (T*)G->dinv[0];
-    d.r0 = (T*)G->r[0];
-    d.x64 = pb->x;
-    d.rhs = pb->rhs;
+    d.cr = gmem((T*)G->cr);
+    d.cz = gmem((T*)G->cz);
+    d.cp = gmem((T*)G->cp);
+    d.cp2 = gmem((T*)G->cp2);
+    d.cq = gmem((T*)G->cq);
+    d.cx = gmem((T*)G->cx);
+    d.dinv0 = gmem((T*)G->dinv[0]);
+    d.r0 = gmem((T*)G->r[0]);
+    d.x64 = gmem(pb->x);
+    d.rhs = gmem((const double*)pb->rhs);
     d.nlev = G->nlev;
     d.ls = G->ls;
     d.nu = G->nu;
     d.cs = G->cs;
     for (int l = 1; l < G->nlev; ++l) {
         d.lv[l] = level<T>(G, l);
-        d.r[l] = (T*)G->r[l];
+        d.r[l] = gmem((T*)G->r[l]);
     }
-    d.st = pb->st;
-    d.part = G->part;
-    d.prz = G->prz;
+    d.st = gmem(pb->st);
+    d.part = gmem(G->part);
+    d.prz = gmem(G->prz);
     d.nb = G->nb;
     d.mixed = P.precision == PB_MIXED ? 1 : 0;
     d.rtol2 = P.rtol * P.rtol;
@@ -1785,7 +1804,7 @@ void vcycle_natural(pb_problem* pb, hipStream_t s, const CGState* st)
 {
     MGData* G = pb->mg;
     const RB rb = rb_of(pb->g);
-    const GateSpec gs{st, 3};
+    const GateSpec gs{gmem(st), 3};
     k_rb_convert<T><<<G->nb, 256, 0, s>>>(pb->g, rb, (T*)G->nat_b, (T*)G->cr, 1, gs, nullptr);
     run_vcycle<T>(s, solo_plan(pb), gs);
     k_rb_convert<T><<<G->nb, 256, 0, s>>>(pb->g, rb, (T*)G->nat_x, (T*)G->cz, 0, gs, nullptr);
