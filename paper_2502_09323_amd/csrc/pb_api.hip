@@ -419,8 +419,12 @@ size_t pbi_request_bytes(const pb_params& p, int64_t na, const double* radius, i
     const size_t per_cut = 124;
     // per atom: coordinates and charge (40 B), bin ids and deposition cells (52 B)
     const size_t per_atom = 92;
+    // the Debye-Hueckel partial sums of the build (at most kDhMaxRanges per box node)
+    const int64_t nbox = 2 * ((int64_t)p.n[1] * p.n[2] + (int64_t)(p.n[0] - 2) * p.n[2] +
+                              (int64_t)(p.n[0] - 2) * (p.n[1] - 2));
+    const size_t dh = p.bc == PB_BC_DH ? (size_t)nbox * kDhMaxRanges * sizeof(double) : 0;
     return (size_t)N * per_node + (size_t)std::max<int64_t>(ncut, 1) * per_cut + (size_t)std::max<int64_t>(na, 1) * per_atom +
-           energy_bytes(na, ncut, true) + ((size_t)1 << 20);
+           energy_bytes(na, ncut, true) + dh + ((size_t)1 << 20);
 }
 
 int pbi_energy_end(pb_problem* pb, pb_energy_out* out, pb_solve_stats* stats)
@@ -552,7 +556,8 @@ void release_tmp(pb_problem* pb)
     BuildTmp* t = pb->bt;
     if (!t) return;
     for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->cls,
-                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full, (void*)t->acell})
+                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full, (void*)t->acell,
+                    (void*)t->dhpart})
         if (d) pb->mem.put(d);
     if (t->hpin) pb->ctx->pinned.put(t->hpin, t->hpin_cap);   // the build's copies have completed
     delete t;
@@ -817,10 +822,13 @@ int pbi_build_continue(pb_problem* pb)
     HIPCHK(launch_fill(s, pb->gb, sizeof(double) * N));
     HIPCHK(launch_fill(s, pb->x, sizeof(double) * N));
     if (prm->bc == PB_BC_DH && pb->na > 0) {
+        const DhSplit sp = dh_split(g, at.n);
+        T.dhpart = dalloc<double>(pb, (size_t)sp.ranges * sp.nbox, &rc);
+        CK(rc);
         if (prm->precision == PB_MIXED)
-            HIPCHK(launch_bc_dh32(s, g, at, pb->kD, prm->eps_out, pb->gb));
+            HIPCHK(launch_bc_dh32(s, g, at, pb->kD, prm->eps_out, T.dhpart, pb->gb));
         else
-            HIPCHK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, pb->gb));
+            HIPCHK(launch_bc_dh(s, g, at, pb->kD, prm->eps_out, T.dhpart, pb->gb));
     } else if (prm->bc == PB_BC_USER) {
         HIPCHK(launch_bc_user(s, g, T.full, pb->gb));
     }

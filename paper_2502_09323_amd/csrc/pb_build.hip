@@ -13,6 +13,7 @@
 #include "pb_internal.h"
 #include "pb_stencil.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pbk {
@@ -482,66 +483,150 @@ __device__ __forceinline__ int64_t n_box(const Grid& g)
     return 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
 }
 
-// g(x) = sum_i q_i exp(-kD r)/(eps_out r), in atom order (Sect. 2.3, Debye-Hueckel form)
-__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, double eps_out, double* gb)
+// exp(x) for x <= 0 in FP64 by Tang's table-driven method (P. T. P. Tang, ACM TOMS 15(2),
+// 1989): x = (n / 256) ln 2 + r with |r| <= ln 2 / 512, exp(x) = 2^(n >> 8) 2^((n & 255) / 256)
+// e^r.  n comes from the round-to-nearest of a 1.5 * 2^52 shift, r from a two-part ln 2 / 256
+// (the high part has 37 significant bits, so n times it is exact for |n| < 2^16, |x| < 177),
+// e^r from its Taylor polynomial to degree 4 (truncation under 4e-17 relative), and the table
+// T[j] = 2^(j / 256) is formed once per block.  The result is within a few units in the last
+// place of exp(x).
+__device__ __forceinline__ double exp_neg(double x, const double* T)
+{
+    const double shift = 6755399441055744.0;                  // 1.5 * 2^52
+    const double t = fma(x, 369.32993046757458, shift);        // 256 / ln 2
+    const int n = __double2loint(t);
+    const double nd = t - shift;
+    double r = fma(nd, -0.0027076061740558544, x);             // ln 2 / 256, high part
+    r = fma(nd, -6.432011555819173e-15, r);                    // low part
+    double pl = fma(r, 1.0 / 24.0, 1.0 / 6.0);
+    pl = fma(pl, r, 0.5);
+    pl = fma(pl, r, 1.0);
+    pl = fma(pl, r, 1.0);
+    return ldexp(T[n & 255] * pl, n >> 8);
+}
+
+// 1/sqrt(r2) in FP64: the hardware estimate (relative error up to about 5e-8) refined by the
+// third-order step y (1 + e/2 + 3 e^2 / 8), e = 1 - r2 y^2, whose truncation is of order e^3
+__device__ __forceinline__ double rsqrt64(double r2)
+{
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-(r2 * y0), y0, 1.0);
+    return fma(y0, e * fma(e, 0.375, 0.5), y0);
+}
+
+// A thread's box nodes: t and t + 256 of its block's tile of kDhNodesPerBlock
+__device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const DhSplit& sp, int tile, int64_t* t,
+                                         bool* act, double (*p)[3])
+{
+    for (int v = 0; v < 2; ++v) {
+        t[v] = (int64_t)tile * kDhNodesPerBlock + v * 256 + threadIdx.x;
+        act[v] = t[v] < sp.nbox;
+        int i = 0, j = 0, k = 0;
+        if (act[v]) box_node(g, t[v], i, j, k);
+        p[v][0] = node_x(g, 0, i) - at.cx;
+        p[v][1] = node_x(g, 1, j) - at.cy;
+        p[v][2] = node_x(g, 2, k) - at.cz;
+    }
+}
+
+// Debye-Hueckel values at the box nodes in FP64 (Sect. 2.3, the Debye-Hueckel form):
+// g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The distance is formed from the
+// coordinate differences, 1/r by rsqrt64, r = r^2 (1/r), exp(-kD r) by exp_neg; without salt
+// (kD = 0) the exponential is skipped.  Block b takes box-node tile b % tiles (two nodes per
+// thread, so that each atom read from LDS serves two pairs) and the atoms of range b / tiles;
+// its partial sums go to part[range][node], which k_bc_dh_sum adds up in range order.
+__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, DhSplit sp, double* part)
 {
     __shared__ double sa[256 * 4];
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool act = t < n_box(g);
-    int i = 0, j = 0, k = 0;
-    if (act) box_node(g, t, i, j, k);
-    double p[3] = {node_x(g, 0, i), node_x(g, 1, j), node_x(g, 2, k)};
-    double s = 0.0;
-    for (int base = 0; base < at.n; base += 256) {
+    __shared__ double T[256];
+    T[threadIdx.x] = exp2((double)threadIdx.x / 256.0);
+    const int tile = (int)(blockIdx.x % sp.tiles), rg = (int)(blockIdx.x / sp.tiles);
+    int64_t t[2];
+    bool act[2];
+    double p[2][3];
+    dh_nodes(g, at, sp, tile, t, act, p);
+    const double mk = -kD;
+    const bool salt = kD != 0.0;
+    const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
+    double s0 = 0.0, s1 = 0.0;
+    for (int base = a0; base < a1; base += 256) {
         int a = base + threadIdx.x;
         __syncthreads();
-        if (a < at.n) {
-            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0];
-            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1];
-            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2];
+        if (a < a1) {
+            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0] - at.cx;
+            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1] - at.cy;
+            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2] - at.cz;
             sa[4 * threadIdx.x + 3] = at.q[a];
         }
         __syncthreads();
-        int m = at.n - base < 256 ? at.n - base : 256;
-        if (act)
+        int m = a1 - base < 256 ? a1 - base : 256;
+        if (!act[0]) continue;   // act[1] implies act[0]
+        if (salt) {
+#pragma unroll 2
             for (int u = 0; u < m; ++u) {
-                double dx = p[0] - sa[4 * u], dy = p[1] - sa[4 * u + 1], dz = p[2] - sa[4 * u + 2];
-                double r = sqrt(dx * dx + dy * dy + dz * dz);
-                s += sa[4 * u + 3] * exp(-kD * r) / (eps_out * r);
+                const double* A = sa + 4 * u;
+                {
+                    const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const double y = rsqrt64(r2);
+                    s0 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s0);
+                }
+                {
+                    const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const double y = rsqrt64(r2);
+                    s1 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s1);
+                }
             }
+        } else {
+#pragma unroll 2
+            for (int u = 0; u < m; ++u) {
+                const double* A = sa + 4 * u;
+                {
+                    const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
+                    s0 = fma(A[3], rsqrt64(fma(dx, dx, fma(dy, dy, dz * dz))), s0);
+                }
+                {
+                    const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
+                    s1 = fma(A[3], rsqrt64(fma(dx, dx, fma(dy, dy, dz * dz))), s1);
+                }
+            }
+        }
     }
-    if (act) gb[g.idx(i, j, k)] = s;
+    if (act[0]) part[(int64_t)rg * sp.nbox + t[0]] = s0;
+    if (act[1]) part[(int64_t)rg * sp.nbox + t[1]] = s1;
 }
 
-// The same sum for the mixed-precision form: distances from FP64 coordinate differences,
-// then the exponential and the inverse distance in FP32 (a few units in the last place,
-// about 1e-7 relative per term), accumulated in FP64.  The box is tens of Angstrom from the
-// surface, so these errors reach the surface potential screened by exp(-kD d) and stay far
-// below the FP32 iteration's own rounding.  The hardware reciprocal square root and base-2
-// exponential are used directly: r^2 leaves the FP32 normal range only for an atom centre
-// within 1e-19 A of a box node, where the sum is singular anyway, and an exponent below
-// -126 gives 0 in place of a term under 1e-38.
-__global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, double eps_out, double* gb)
+// The same sum for the mixed-precision form: squared distances in FP64, then the exponential
+// and the inverse distance in FP32 (a few units in the last place, about 1e-7 relative per
+// term), accumulated in FP64.  The box is tens of Angstrom from the surface, so these errors
+// reach the surface potential screened by exp(-kD d) and stay far below the FP32 iteration's
+// own rounding.  The hardware reciprocal square root and base-2 exponential are used
+// directly: r^2 leaves the FP32 normal range only for an atom centre within 1e-19 A of a box
+// node, where the sum is singular anyway, and an exponent below -126 gives 0 in place of a
+// term under 1e-38.  The squared distance is taken in the expanded form |p|^2 + |a|^2 - 2 a.p
+// (one add and three fused multiply-adds from -2a and |a|^2 held in LDS), with p and a
+// relative to the atoms' centre so that the cancellation does not grow with the molecule's
+// distance from the coordinate origin (the box is far from every atom, so it costs nothing at
+// FP32 precision).  Tiles, ranges and partial sums as in k_bc_dh.
+__global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, DhSplit sp, double* part)
 {
-    // squared distance in FP64 in the expanded form |p|^2 + |a|^2 - 2 a.p (one add and three
-    // fused multiply-adds from -2a and |a|^2 held in LDS), with p and a relative to the atoms'
-    // centre so that the cancellation does not grow with the molecule's distance from the
-    // coordinate origin (the box is far from every atom, so it costs nothing at FP32
-    // precision), then the FP32 terms
     __shared__ double sa[256 * 4];
     __shared__ float sq[256];
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool act = t < n_box(g);
-    int i = 0, j = 0, k = 0;
-    if (act) box_node(g, t, i, j, k);
-    const double p[3] = {node_x(g, 0, i) - at.cx, node_x(g, 1, j) - at.cy, node_x(g, 2, k) - at.cz};
-    const double pp = fma(p[0], p[0], fma(p[1], p[1], p[2] * p[2]));
+    const int tile = (int)(blockIdx.x % sp.tiles), rg = (int)(blockIdx.x / sp.tiles);
+    int64_t t[2];
+    bool act[2];
+    double p[2][3];
+    dh_nodes(g, at, sp, tile, t, act, p);
+    const double pp0 = fma(p[0][0], p[0][0], fma(p[0][1], p[0][1], p[0][2] * p[0][2]));
+    const double pp1 = fma(p[1][0], p[1][0], fma(p[1][1], p[1][1], p[1][2] * p[1][2]));
     const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
-    double s = 0.0;
-    for (int base = 0; base < at.n; base += 256) {
+    const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
+    double s0 = 0.0, s1 = 0.0;
+    for (int base = a0; base < a1; base += 256) {
         int a = base + threadIdx.x;
         __syncthreads();
-        if (a < at.n) {
+        if (a < a1) {
             const double x = at.xyzr[4 * a + 0] - at.cx, y = at.xyzr[4 * a + 1] - at.cy,
                          z = at.xyzr[4 * a + 2] - at.cz;
             sa[4 * threadIdx.x + 0] = -2.0 * x;
@@ -551,18 +636,33 @@ __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, do
             sq[threadIdx.x] = (float)at.q[a];
         }
         __syncthreads();
-        int m = at.n - base < 256 ? at.n - base : 256;
-        if (act)
+        int m = a1 - base < 256 ? a1 - base : 256;
+        if (act[0])
 #pragma unroll 4
             for (int u = 0; u < m; ++u) {
                 const double* A = sa + 4 * u;
-                const float r2 = (float)fma(A[0], p[0], fma(A[1], p[1], fma(A[2], p[2], pp + A[3])));
-                const float ri = __builtin_amdgcn_rsqf(r2);
-                const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
-                s += (double)(sq[u] * e * ri);
+                const float r20 = (float)fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])));
+                const float r21 = (float)fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])));
+                const float ri0 = __builtin_amdgcn_rsqf(r20), ri1 = __builtin_amdgcn_rsqf(r21);
+                const float e0 = __builtin_amdgcn_exp2f(mk * (r20 * ri0)), e1 = __builtin_amdgcn_exp2f(mk * (r21 * ri1));
+                s0 += (double)(sq[u] * e0 * ri0);
+                s1 += (double)(sq[u] * e1 * ri1);
             }
     }
-    if (act) gb[g.idx(i, j, k)] = s / eps_out;
+    if (act[0]) part[(int64_t)rg * sp.nbox + t[0]] = s0;
+    if (act[1]) part[(int64_t)rg * sp.nbox + t[1]] = s1;
+}
+
+// the box values from the partial sums of the atom ranges, added in range order
+__global__ void __launch_bounds__(256) k_bc_dh_sum(Grid g, DhSplit sp, const double* part, double eps_out, double* gb)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= sp.nbox) return;
+    double s = 0.0;
+    for (int r = 0; r < sp.ranges; ++r) s += part[(int64_t)r * sp.nbox + t];
+    int i, j, k;
+    box_node(g, t, i, j, k);
+    gb[g.idx(i, j, k)] = s / eps_out;
 }
 
 __global__ void __launch_bounds__(256) k_bc_user(Grid g, const double* full, double* gb)
@@ -908,18 +1008,37 @@ hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, con
     return hipGetLastError();
 }
 
-hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
+DhSplit dh_split(const Grid& g, int n_atoms)
+{
+    DhSplit sp;
+    sp.nbox = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
+    sp.tiles = (int)nblk(sp.nbox, kDhNodesPerBlock);
+    const int chunks = std::max(1, (n_atoms + 255) / 256);
+    // enough blocks to fill the device many times over (the last wave of blocks is then a small
+    // part of the run), each with whole 256-atom chunks
+    int r = (int)std::min<int64_t>(kDhMaxRanges, std::max<int64_t>(1, (kDhTargetBlocks + sp.tiles - 1) / sp.tiles));
+    r = std::min(r, chunks);
+    const int cpr = (chunks + r - 1) / r;
+    sp.per = 256 * cpr;
+    sp.ranges = (chunks + cpr - 1) / cpr;
+    return sp;
+}
+
+hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
                         double* gb)
 {
-    int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
-    k_bc_dh<<<nblk(nbx, 256), 256, 0, s>>>(g, at, kD, eps_out, gb);
+    const DhSplit sp = dh_split(g, at.n);
+    k_bc_dh<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, kD, sp, part);
+    k_bc_dh_sum<<<(unsigned)nblk(sp.nbox, 256), 256, 0, s>>>(g, sp, part, eps_out, gb);
     return hipGetLastError();
 }
 
-hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb)
+hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
+                          double* gb)
 {
-    int64_t nbx = 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
-    k_bc_dh32<<<nblk(nbx, 256), 256, 0, s>>>(g, at, kD, eps_out, gb);
+    const DhSplit sp = dh_split(g, at.n);
+    k_bc_dh32<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, kD, sp, part);
+    k_bc_dh_sum<<<(unsigned)nblk(sp.nbox, 256), 256, 0, s>>>(g, sp, part, eps_out, gb);
     return hipGetLastError();
 }
 

@@ -108,6 +108,7 @@ struct BuildTmp {
     int* htot = nullptr;
     double* full = nullptr;   // device copy of user boundary values
     double* acell = nullptr;  // per atom: its deposition cell and offsets (6 doubles)
+    double* dhpart = nullptr; // Debye-Hueckel partial sums per atom range and box node
 };
 
 struct pb_problem;

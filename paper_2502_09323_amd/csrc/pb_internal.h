@@ -125,9 +125,24 @@ hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Ato
 int grid_energy_blocks(int n_atoms);
 hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, const double* x, double scale,
                               double* part);
-hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out,
+// Debye-Hueckel box values: the atoms are split into ranges of whole 256-atom chunks, each
+// block sums one range for one tile of kDhNodesPerBlock box nodes into part[range][node], and
+// a second kernel adds the ranges in order
+constexpr int kDhNodesPerBlock = 512;
+constexpr int kDhMaxRanges = 16;
+constexpr int64_t kDhTargetBlocks = 32768;
+struct DhSplit {
+    int64_t nbox;   // box nodes
+    int tiles;      // tiles of kDhNodesPerBlock box nodes
+    int per;        // atoms per range (a multiple of 256)
+    int ranges;     // atom ranges (at most kDhMaxRanges)
+};
+DhSplit dh_split(const Grid& g, int n_atoms);
+// part holds dh_split(g, at.n).ranges * nbox doubles
+hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
                         double* gb);
-hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* gb);
+hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
+                          double* gb);
 hipError_t launch_bc_user(hipStream_t s, const Grid& g, const double* full, double* gb);
 hipError_t launch_diag_lift(hipStream_t s, const Grid& g, const uint32_t* code, const double* ck64,
                             Coef c, const double* gb, double* rhs, float* dinv, double* diag);

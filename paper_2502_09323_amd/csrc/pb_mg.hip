@@ -266,39 +266,87 @@ __device__ __forceinline__ int rb_node(const RB& r, int i, int j, int c, int m)
     return (k >= 1 && k <= r.nz - 2) ? k : -1;
 }
 
-// element indices of a node and of its six neighbours (x-, x+, y-, y+, z-, z+)
-struct RBNb {
-    int64_t e, xm, xp, ym, yp, zm, zp;
+// A block's frame: a level-0 kernel addresses the vectors from the first element of plane
+// i0 - 1 (i0 the block's first plane).  Every lane offset then fits in 32 bits, and the base of
+// each vector is one scalar add per block, so that a load takes a scalar base and a 32-bit lane
+// offset instead of a 64-bit address formed per lane.
+struct RBFrame {
+    int64_t org;   // element index of (i0 - 1, 0, colour 0, position 0)
+    int i0;
 };
 
-__device__ __forceinline__ RBNb rb_nb(const RB& r, int i, int j, int c, int m, int k)
+__device__ __forceinline__ RBFrame rb_frame(const RB& r, const VB& vb)
+{
+    RBFrame f;
+    f.i0 = 1 + vb.z * kPlanesRB;
+    f.org = (int64_t)(f.i0 - 1) * r.ny * 2 * r.Sh;
+    return f;
+}
+
+// offset of (i, j, c, m) in a frame (planes i0 - 1 ... i0 + kPlanesRB)
+__device__ __forceinline__ uint32_t rb_rel(const RB& r, const RBFrame& f, int i, int j, int c, int m)
+{
+    return ((uint32_t)((i - f.i0 + 1) * r.ny + j) * 2u + (uint32_t)c) * (uint32_t)r.Sh + (uint32_t)m;
+}
+
+// element e of a frame's vector (base = the vector + the frame origin)
+template <typename T>
+__device__ __forceinline__ T ldf(const GMEM T* base, uint32_t e)
+{
+    return *(const GMEM T*)((const GMEM char*)base + e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ GMEM T& stf(GMEM T* base, uint32_t e)
+{
+    return *(GMEM T*)((GMEM char*)base + e * (uint32_t)sizeof(T));
+}
+
+// frame offsets of a node and of its six neighbours (x-, x+, y-, y+, z-, z+)
+struct RBNb {
+    uint32_t e, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ RBNb rb_nb(const RB& r, const RBFrame& f, int i, int j, int c, int m, int k)
 {
     RBNb n;
-    n.e = r.at(i, j, c, m);
-    const int64_t eo = r.at(i, j, 1 - c, m);
-    const int64_t sx = (int64_t)r.ny * 2 * r.Sh, sy = 2 * (int64_t)r.Sh;
+    n.e = rb_rel(r, f, i, j, c, m);
+    const uint32_t eo = rb_rel(r, f, i, j, 1 - c, m);
+    const uint32_t sx = (uint32_t)r.ny * 2u * (uint32_t)r.Sh, sy = 2u * (uint32_t)r.Sh;
     n.xm = eo - sx;
     n.xp = eo + sx;
     n.ym = eo - sy;
     n.yp = eo + sy;
-    n.zm = eo - ((k & 1) ? 0 : 1);
-    n.zp = eo + ((k & 1) ? 1 : 0);
+    n.zm = eo - ((k & 1) ? 0u : 1u);
+    n.zp = eo + ((k & 1) ? 1u : 0u);
     return n;
 }
 
+// In the red-black codes an interior node (whose natural code never carries C_BOX) carries
+// C_BOX when none of its six edges is cut.
+constexpr uint32_t C_RB_UNCUT = C_BOX;
+
+// the six edge weights and the ionic term of node n (code = the frame's code base).  Where no
+// edge of any node of the wave is cut, the six weights are the node's medium value (an uncut
+// edge joins two nodes of one medium), the very values the table path gives, and the
+// neighbours' codes are not read.
 template <typename T>
-__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const RBNb& n)
+__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const GMEM uint32_t* code, const RBNb& n)
 {
-    const uint32_t c = op.code[n.e];
-    const T* ck = (const T*)op.ck;   // still a global pointer to the compiler (it follows the cast)
+    const uint32_t c = ldf(code, n.e);
     stencil::NodeK<T> k;
-    k.xm = stencil::edgeK(op.code[n.xm], 0, ck, op.kin, op.kout);
-    k.xp = stencil::edgeK(c, 0, ck, op.kin, op.kout);
-    k.ym = stencil::edgeK(op.code[n.ym], 1, ck, op.kin, op.kout);
-    k.yp = stencil::edgeK(c, 1, ck, op.kin, op.kout);
-    k.zm = stencil::edgeK(op.code[n.zm], 2, ck, op.kin, op.kout);
-    k.zp = stencil::edgeK(c, 2, ck, op.kin, op.kout);
     k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
+    if (__all((c & C_RB_UNCUT) != 0)) {
+        const T b = (c & C_SOLUTE) ? op.kin : op.kout;
+        k.xm = k.xp = k.ym = k.yp = k.zm = k.zp = b;
+        return k;
+    }
+    const T* ck = (const T*)op.ck;   // still a global pointer to the compiler (it follows the cast)
+    k.xm = stencil::edgeK(ldf(code, n.xm), 0, ck, op.kin, op.kout);
+    k.xp = stencil::edgeK(c, 0, ck, op.kin, op.kout);
+    k.ym = stencil::edgeK(ldf(code, n.ym), 1, ck, op.kin, op.kout);
+    k.yp = stencil::edgeK(c, 1, ck, op.kin, op.kout);
+    k.zm = stencil::edgeK(ldf(code, n.zm), 2, ck, op.kin, op.kout);
+    k.zp = stencil::edgeK(c, 2, ck, op.kin, op.kout);
     return k;
 }
 
@@ -688,23 +736,25 @@ __global__ void __launch_bounds__(256) kb_rb_down1(Bt<T> B, GateSpec gs)
     if (gated_out(gs, D.st)) return;
     const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const GMEM T* __restrict__ b = D.cr;
-    const GMEM T* __restrict__ dinv = D.dinv0;
-    GMEM T* __restrict__ x = D.cz;
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM uint32_t* code = D.op.code + F.org;
+    const GMEM T* b = D.cr + F.org;
+    const GMEM T* dinv = D.dinv0 + F.org;
+    GMEM T* x = D.cz + F.org;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         if (rb_node(R, i, j, 0, m) >= 0) {
-            const int64_t e = R.at(i, j, 0, m);
-            x[e] = b[e] * dinv[e];
+            const uint32_t e = rb_rel(R, F, i, j, 0, m);
+            stf(x, e) = ldf(b, e) * ldf(dinv, e);
         }
         const int k = rb_node(R, i, j, 1, m);
         if (k >= 0) {
-            const RBNb n = rb_nb(R, i, j, 1, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, n);
-            const T s = rb_sum(K, n, [&](int64_t f) { return b[f] * dinv[f]; });
-            x[n.e] = (b[n.e] + s) * dinv[n.e];
+            const RBNb n = rb_nb(R, F, i, j, 1, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, code, n);
+            const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(b, f) * ldf(dinv, f); });
+            stf(x, n.e) = (ldf(b, n.e) + s) * ldf(dinv, n.e);
         }
     }
 }
@@ -722,8 +772,11 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
     if (gated_out(gs, D.st)) return;
     const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const GMEM T* __restrict__ b = D.cr;
-    const GMEM T* __restrict__ x = D.cz;
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM uint32_t* code = D.op.code + F.org;
+    const GMEM T* b = D.cr + F.org;
+    const GMEM T* dinv = D.dinv0 + F.org;
+    GMEM T* x = D.cz + F.org;
     double v[1] = {0.0};
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
@@ -731,17 +784,18 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, c, m);
         if (k >= 0) {
-            const RBNb n = rb_nb(R, i, j, c, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, n);
-            const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
-            const T xn = (b[n.e] + s) * D.dinv0[n.e];
-            D.cz[n.e] = xn;
-            if constexpr (Dot) v[0] += (double)b[n.e] * (double)xn;
+            const RBNb n = rb_nb(R, F, i, j, c, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, code, n);
+            const T s = rb_sum(K, n, [&](uint32_t f) { return ldf((const GMEM T*)x, f); });
+            const T bn = ldf(b, n.e);
+            const T xn = (bn + s) * ldf(dinv, n.e);
+            stf(x, n.e) = xn;
+            if constexpr (Dot) v[0] += (double)bn * (double)xn;
         }
         if constexpr (Dot) {
             if (rb_node(R, i, j, 1 - c, m) >= 0) {
-                const int64_t eb = R.at(i, j, 1 - c, m);
-                v[0] += (double)b[eb] * (double)x[eb];
+                const uint32_t eb = rb_rel(R, F, i, j, 1 - c, m);
+                v[0] += (double)ldf(b, eb) * (double)ldf((const GMEM T*)x, eb);
             }
         }
     }
@@ -762,17 +816,21 @@ __global__ void __launch_bounds__(256) kb_rb_resid(Bt<T> B, GateSpec gs)
     if (gated_out(gs, D.st)) return;
     const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const GMEM T* __restrict__ x = D.cz;
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM uint32_t* code = D.op.code + F.org;
+    const GMEM T* b = D.cr + F.org;
+    const GMEM T* x = D.cz + F.org;
+    GMEM T* r = D.r0 + F.org;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, 0, m);
         if (k < 0) continue;
-        const RBNb n = rb_nb(R, i, j, 0, m, k);
-        const stencil::NodeK<T> K = rb_k(D.op, n);
-        const T s = rb_sum(K, n, [&](int64_t f) { return x[f]; });
-        D.r0[n.e] = D.cr[n.e] - (K.diag() * x[n.e] - s);
+        const RBNb n = rb_nb(R, F, i, j, 0, m, k);
+        const stencil::NodeK<T> K = rb_k(D.op, code, n);
+        const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(x, f); });
+        stf(r, n.e) = ldf(b, n.e) - (K.diag() * ldf(x, n.e) - s);
     }
 }
 
@@ -787,15 +845,17 @@ __global__ void __launch_bounds__(256) kb_rb_prolong(Bt<T> B, GateSpec gs)
     if (gated_out(gs, D.st)) return;
     const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
+    const RBFrame F = rb_frame(R, vb);
     const Grid gc = D.lv[1].g;
     const GMEM T* __restrict__ ec = D.lv[1].x;
+    GMEM T* x = D.cz + F.org;
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
         int i, j, m;
         if (!rb_slot(vb, R, p, i, j, m)) continue;
         const int k = rb_node(R, i, j, 0, m);
         if (k < 0) continue;
-        D.cz[R.at(i, j, 0, m)] += prolong_at(gc, ec, i, j, k);
+        stf(x, rb_rel(R, F, i, j, 0, m)) += prolong_at(gc, ec, i, j, k);
     }
 }
 
@@ -829,11 +889,14 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
     if (st->status != 0) return;
     const RB R = D.rb;
     const VB vb = vb_rb(R, local, D.nb);
-    const GMEM T* __restrict__ z = D.cz;
-    const GMEM T* __restrict__ po = p_old(st, (const GMEM T*)D.cp, (const GMEM T*)D.cp2);
-    GMEM T* __restrict__ pn = p_new(st, D.cp, D.cp2);
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM uint32_t* code = D.op.code + F.org;
+    const GMEM T* z = D.cz + F.org;
+    const GMEM T* po = p_old(st, (const GMEM T*)D.cp, (const GMEM T*)D.cp2) + F.org;
+    GMEM T* pn = p_new(st, D.cp, D.cp2) + F.org;
+    GMEM T* q = D.cq + F.org;
     const T beta = (T)st->beta;
-    auto pd = [&](int64_t f) { return z[f] + beta * po[f]; };
+    auto pd = [&](uint32_t f) { return ldf(z, f) + beta * ldf(po, f); };
     double v[1] = {0.0};
 #pragma unroll
     for (int p = 0; p < kPlanesRB; ++p) {
@@ -842,12 +905,12 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
         for (int c = 0; c < 2; ++c) {
             const int k = rb_node(R, i, j, c, m);
             if (k < 0) continue;
-            const RBNb n = rb_nb(R, i, j, c, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, n);
+            const RBNb n = rb_nb(R, F, i, j, c, m, k);
+            const stencil::NodeK<T> K = rb_k(D.op, code, n);
             const T pe = pd(n.e);
             const T qe = K.diag() * pe - rb_sum(K, n, pd);
-            pn[n.e] = pe;
-            D.cq[n.e] = qe;
+            stf(pn, n.e) = pe;
+            stf(q, n.e) = qe;
             v[0] += (double)pe * (double)qe;
         }
     }
@@ -1103,7 +1166,8 @@ __global__ void __launch_bounds__(64) kb_gather(Bt<T> B, CGState* out)
 
 // ---- set-up and test helpers (one problem) ------------------------------------------------
 
-// codes in the red-black layout (C_BOX on box and padding positions)
+// codes in the red-black layout (C_BOX on box and padding positions); an interior node none
+// of whose six edges is cut also carries C_RB_UNCUT
 __global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* __restrict__ code, uint32_t* __restrict__ out)
 {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < r.N; t += (int64_t)gridDim.x * 256) {
@@ -1113,7 +1177,18 @@ __global__ void __launch_bounds__(256) k_rb_code(Grid g, RB r, const uint32_t* _
         const int64_t row = q >> 1;
         const int j = (int)(row % r.ny), i = (int)(row / r.ny);
         const int k = 2 * m + ((i + j + c) & 1);
-        out[t] = k < r.nz ? code[g.idx(i, j, k)] : C_BOX;
+        if (k >= r.nz) {
+            out[t] = C_BOX;
+            continue;
+        }
+        const int64_t e = g.idx(i, j, k);
+        uint32_t cn = code[e];
+        if (i >= 1 && i <= g.nx - 2 && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2) {
+            const uint32_t cut = (cn & (7u * C_CUTX)) | (code[e - (int64_t)g.ny * g.S] & C_CUTX) |
+                                 (code[e - g.S] & (C_CUTX << 1)) | (code[e - 1] & (C_CUTX << 2));
+            if (!cut) cn |= C_RB_UNCUT;
+        }
+        out[t] = cn;
     }
 }
 

@@ -207,3 +207,75 @@ def test_c2_full_size_parity(ctx):
     ge = O.grid_energy(grid, mol, run.phi, run.lB)
     assert abs(pb.grid_energy() - ge) <= E_TOL64 * abs(ge)
     pb.close()
+
+
+DH_CASES = [
+    # (label, ionic strength M, molecule centre)
+    ("salt", 0.145, (0.0, 0.0, 0.0)),
+    ("no_salt", 0.0, (0.0, 0.0, 0.0)),
+    ("salt_far_from_origin", 0.145, (150.0, -90.0, 230.0)),
+]
+
+
+def dh_abs_scale(grid, mol, kD):
+    """Full-grid array holding, at the box nodes, sum over atoms of |q| exp(-kD r) / (eps_out r):
+    the scale of the rounding error of a Debye-Hueckel value (the sum itself cancels between
+    charges of both signs)."""
+    n = [int(v) for v in grid.n]
+    idx = np.indices(n).reshape(3, -1)
+    box = np.zeros(idx.shape[1], bool)
+    for d in range(3):
+        box |= (idx[d] == 0) | (idx[d] == n[d] - 1)
+    pts = (idx[:, box].T * grid.h + np.asarray(grid.origin)).astype(np.float64)
+    xyz = np.asarray(mol.xyz, np.float64)
+    aq = np.abs(np.asarray(mol.charge, np.float64))
+    out = np.empty(len(pts))
+    for s0 in range(0, len(pts), 1024):
+        r = np.linalg.norm(pts[s0:s0 + 1024, None, :] - xyz[None, :, :], axis=2)
+        out[s0:s0 + 1024] = (aq[None, :] * np.exp(-kD * r) / (grid.eps_out * r)).sum(axis=1)
+    full = np.zeros(idx.shape[1])
+    full[box] = out
+    return full.reshape(n)
+
+
+@pytest.mark.parametrize("label,ionic,center", DH_CASES, ids=[c[0] for c in DH_CASES])
+def test_dh_box_values_parity(ctx, label, ionic, center):
+    """FP64 Debye-Hueckel box values (Sect. 2.3) against the oracle's: at the interior nodes
+    next to the box the right-hand side is the charge deposit plus the boundary lift K g, and
+    it agrees with the oracle's node by node to 1e-13 of the lift's absolute-value scale (the
+    values sum charges of both signs, so they cancel), and to 1e-13 of the largest value."""
+    mol = I.random_molecule(3000, 12.0, 21, center=center)
+    grid = I.cubic_grid(65, 0.5, center=center, ionic_M=ionic)
+    lB, kD = O.constants(grid.temp_K, grid.ionic_M, grid.eps_out)
+    assert (kD == 0.0) == (ionic == 0.0)
+    sol = O.classify(grid, mol)
+    cut = O.cut_edges(grid, mol, sol)
+    g = O.boundary_values(grid, mol, kD)
+    _, lift = O.assemble(grid, sol, cut, g, grid.eps_out * kD * kD)
+    b_or = O.interior(O.deposit(grid, mol)) + lift
+    pb = B.Problem(ctx, mol, grid)
+    try:
+        b_gpu = pb.coeffs()["rhs"][(slice(1, -1),) * 3].reshape(-1)
+    finally:
+        pb.close()
+    ni = [int(v) - 2 for v in grid.n]
+    idx = np.indices(ni).reshape(3, -1)
+    next_to_box = np.zeros(idx.shape[1], bool)
+    for d in range(3):
+        next_to_box |= (idx[d] == 0) | (idx[d] == ni[d] - 1)
+    # scale of the lift's rounding error at each node: K (h eps_out on the solvent edges to the
+    # box) times the absolute-value sums of its box neighbours
+    sabs = dh_abs_scale(grid, mol, kD)
+    lscale = np.zeros(ni)
+    inner = (slice(1, -1),) * 3
+    for d in range(3):
+        for sh in (-1, 1):
+            lscale += np.roll(sabs, sh, axis=d)[inner]
+    lscale = grid.h * grid.eps_out * lscale.reshape(-1)
+    bo, bg, ls = b_or[next_to_box], b_gpu[next_to_box], lscale[next_to_box]
+    assert np.all(ls > 0)
+    err = np.abs(bg - bo) / ls
+    print(f"{label}: {next_to_box.sum()} nodes next to the box, max difference {err.max():.2e} of the lift's "
+          f"absolute-value scale, {np.max(np.abs(bg - bo)) / np.max(np.abs(bo)):.2e} of the largest value")
+    assert err.max() <= 1e-13
+    assert np.max(np.abs(bg - bo)) <= 1e-13 * np.max(np.abs(bo))
