@@ -476,7 +476,7 @@ def workload(name: str):
 # update (role, x, r rw; p, q, D^-1; z), direction (role, z, p rw)
 # FP64 flops per atom x cut-point pair of the energy N-body sum (a fused multiply-add counts
 # two), in the direct form: the three differences, the squared distance (5), the correction of
-# the FP32 reciprocal square root (8; the FP32 start and its two conversions are not counted),
+# the hardware reciprocal square root estimate (8; the estimate itself is not counted),
 # the dot product with the weighted normal (5), F/r into its sum (2) and the r^-3 term (4).
 # The kernel's expanded form (squared distance and dot product from per-point and per-atom
 # terms) performs the same 27 in 16 instructions instead of 18.

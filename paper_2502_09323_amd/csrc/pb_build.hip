@@ -505,15 +505,6 @@ __device__ __forceinline__ double exp_neg(double x, const double* T)
     return ldexp(T[n & 255] * pl, n >> 8);
 }
 
-// 1/sqrt(r2) in FP64: the hardware estimate (relative error up to about 5e-8) refined by the
-// third-order step y (1 + e/2 + 3 e^2 / 8), e = 1 - r2 y^2, whose truncation is of order e^3
-__device__ __forceinline__ double rsqrt64(double r2)
-{
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-(r2 * y0), y0, 1.0);
-    return fma(y0, e * fma(e, 0.375, 0.5), y0);
-}
-
 // A thread's box nodes: t and t + 256 of its block's tile of kDhNodesPerBlock
 __device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const DhSplit& sp, int tile, int64_t* t,
                                          bool* act, double (*p)[3])
@@ -531,7 +522,7 @@ __device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const D
 
 // Debye-Hueckel values at the box nodes in FP64 (Sect. 2.3, the Debye-Hueckel form):
 // g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The distance is formed from the
-// coordinate differences, 1/r by rsqrt64, r = r^2 (1/r), exp(-kD r) by exp_neg; without salt
+// coordinate differences, 1/r by rsqrt_fp64, r = r^2 (1/r), exp(-kD r) by exp_neg; without salt
 // (kD = 0) the exponential is skipped.  Block b takes box-node tile b % tiles (two nodes per
 // thread, so that each atom read from LDS serves two pairs) and the atoms of range b / tiles;
 // its partial sums go to part[range][node], which k_bc_dh_sum adds up in range order.
@@ -568,13 +559,13 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, DhSp
                 {
                     const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double y = rsqrt64(r2);
+                    const double y = rsqrt_fp64(r2);
                     s0 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s0);
                 }
                 {
                     const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double y = rsqrt64(r2);
+                    const double y = rsqrt_fp64(r2);
                     s1 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s1);
                 }
             }
@@ -584,11 +575,11 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, DhSp
                 const double* A = sa + 4 * u;
                 {
                     const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
-                    s0 = fma(A[3], rsqrt64(fma(dx, dx, fma(dy, dy, dz * dz))), s0);
+                    s0 = fma(A[3], rsqrt_fp64(fma(dx, dx, fma(dy, dy, dz * dz))), s0);
                 }
                 {
                     const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
-                    s1 = fma(A[3], rsqrt64(fma(dx, dx, fma(dy, dy, dz * dz))), s1);
+                    s1 = fma(A[3], rsqrt_fp64(fma(dx, dx, fma(dy, dy, dz * dz))), s1);
                 }
             }
         }

@@ -87,19 +87,6 @@ __global__ void __launch_bounds__(256) k_edge_fields(Grid g, Atoms at, double ep
     o[9] = 0.0;
 }
 
-// 1/sqrt(x) in FP64: the hardware FP32 reciprocal square root y as a start (relative error
-// d of about 1e-7), then one step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., with
-// e = 1 - x y^2 = 2d + O(d^2): the first omitted term, 5e^3/16, is below FP64 rounding.
-// Five FP64 operations in place of the library's square root and division.  The raw
-// instruction takes no denormal inputs: x is a squared atom-to-surface distance, which is at
-// least the smallest atom radius squared, since every cut point lies outside or on every ball.
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    const double y = (double)__builtin_amdgcn_rsqf((float)x);
-    const double e = fma(-x, y * y, 1.0);
-    return fma(y, e * fma(e, 0.375, 0.5), y);
-}
-
 constexpr int NB_ATOMS = 4;                       // atoms per thread
 constexpr int NB_BLOCK_ATOMS = 256 * NB_ATOMS;    // atoms per block
 
@@ -163,7 +150,7 @@ __global__ void __launch_bounds__(256) k_nbody(Atoms at, int64_t ncut, const dou
                 for (int k = 0; k < NB_ATOMS; ++k) {
                     const double r2 = fma(mx[k], px, fma(my[k], py, fma(mz[k], pz, pp + aa[k])));
                     const double dn2 = fma(mx[k], ux, fma(my[k], uy, fma(mz[k], uz, pu2)));
-                    const double r = rsqrt_nr(r2);
+                    const double r = rsqrt_fp64(r2);
                     sf[k] = fma(f, r, sf[k]);
                     sd[k] = fma(dn2, (r * r) * r, sd[k]);
                 }
@@ -212,7 +199,7 @@ __global__ void __launch_bounds__(256) k_coulomb(Atoms at, double* __restrict__ 
         if (act)
             for (int u = 0; u < m; ++u) {
                 const double dx = sa[4 * u] - xi, dy = sa[4 * u + 1] - yi, dz = sa[4 * u + 2] - zi;
-                const double t = sa[4 * u + 3] * rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+                const double t = sa[4 * u + 3] * rsqrt_fp64(fma(dx, dx, fma(dy, dy, dz * dz)));
                 s += (base + u == a) ? 0.0 : t;   // the self term (not finite) is dropped by the select
             }
     }

@@ -53,6 +53,17 @@ struct Bins {          // atom cell list: bins of edge bs covering the atom cent
     const int* ids;    // atom ids, ascending within each bin
 };
 
+// 1/sqrt(x) in FP64 for normal x: the hardware FP64 reciprocal square root estimate y
+// (relative error d up to about 5e-8) refined by one step of the series (1 - e)^(-1/2) =
+// 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2 = 2d + O(d^2): the first omitted term, 5e^3/16, is
+// below FP64 rounding.  Five FP64 operations in place of a square root and a division.
+__device__ __forceinline__ double rsqrt_fp64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x, y * y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
+}
+
 struct Atoms {
     int n;
     const double* xyzr;  // 4 per atom: x, y, z, radius

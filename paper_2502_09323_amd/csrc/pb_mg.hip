@@ -216,7 +216,9 @@ __device__ __forceinline__ VB vb_of(int local, int gx, int gy)
     return v;
 }
 
-__host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz + 1) / 2 + 63) / 64; }
+// tiles of 64 positions along a row: the interior nodes k = 1 ... nz - 2 sit at positions
+// 0 ... (nz - 2) / 2 of their colour's segment
+__host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz - 2) / 2 + 1 + 63) / 64; }
 __host__ __device__ inline int rows_gy(int ny) { return (ny - 2 + 3) / 4; }
 
 inline int rb_blocks(const RB& r) { return rb_gx(r) * rows_gy(r.ny) * ((r.nx - 2 + kPlanesRB - 1) / kPlanesRB); }
