@@ -103,6 +103,7 @@ struct RB {
     int nx, ny, nz;
     int Sh;        // positions per colour segment (a multiple of 32: 128-byte aligned segments)
     int64_t N;     // elements per vector: nx * ny * 2 * Sh
+    int lw;        // a wave of a level-0 pass covers 2^lw positions of 64 >> lw rows
     __host__ __device__ int64_t at(int i, int j, int c, int m) const
     {
         return (((int64_t)i * ny + j) * 2 + c) * Sh + m;
@@ -118,6 +119,18 @@ inline RB rb_of(const Grid& g)
     r.nz = g.nz;
     r.Sh = ((g.nz + 1) / 2 + 31) / 32 * 32;
     r.N = (int64_t)g.nx * g.ny * 2 * r.Sh;
+    // the interior positions of a row segment, (nz - 2) / 2 + 1, in as few idle lanes as
+    // possible: 64, 32 or 16 positions per wave row (the widest of the least waste)
+    const int P = (g.nz - 2) / 2 + 1;
+    int best = 1 << 30;
+    r.lw = 6;
+    for (int lw = 6; lw >= 4; --lw) {
+        const int w = 1 << lw, waste = (P + w - 1) / w * w - P;
+        if (waste < best) {
+            best = waste;
+            r.lw = lw;
+        }
+    }
     return r;
 }
 
@@ -216,12 +229,14 @@ __device__ __forceinline__ VB vb_of(int local, int gx, int gy)
     return v;
 }
 
-// tiles of 64 positions along a row: the interior nodes k = 1 ... nz - 2 sit at positions
-// 0 ... (nz - 2) / 2 of their colour's segment
-__host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz - 2) / 2 + 1 + 63) / 64; }
+// tiles of 2^lw positions along a row: the interior nodes k = 1 ... nz - 2 sit at positions
+// 0 ... (nz - 2) / 2 of their colour's segment; a block (4 waves) covers 4 * (64 >> lw) rows
+__host__ __device__ inline int rb_gx(const RB& r) { return ((r.nz - 2) / 2 + 1 + (1 << r.lw) - 1) >> r.lw; }
+__host__ __device__ inline int rb_rows(const RB& r) { return 4 * (64 >> r.lw); }
+__host__ __device__ inline int rb_gy(const RB& r) { return (r.ny - 2 + rb_rows(r) - 1) / rb_rows(r); }
 __host__ __device__ inline int rows_gy(int ny) { return (ny - 2 + 3) / 4; }
 
-inline int rb_blocks(const RB& r) { return rb_gx(r) * rows_gy(r.ny) * ((r.nx - 2 + kPlanesRB - 1) / kPlanesRB); }
+inline int rb_blocks(const RB& r) { return rb_gx(r) * rb_gy(r) * ((r.nx - 2 + kPlanesRB - 1) / kPlanesRB); }
 
 // block `local` of a level-0 pass of nb blocks takes tile item(local): blocks are dealt to the
 // 8 XCDs round-robin (a problem's blocks start at a multiple of 8), and this bijection gives
@@ -232,7 +247,7 @@ __device__ __forceinline__ VB vb_rb(const RB& r, int local, int nb)
 {
     const int q8 = nb >> 3, rem = nb & 7, xcd = local & 7;
     const int item = xcd * q8 + (xcd < rem ? xcd : rem) + (local >> 3);
-    return vb_of(item, rb_gx(r), rows_gy(r.ny));
+    return vb_of(item, rb_gx(r), rb_gy(r));
 }
 
 // blocks along z of a coarse-level pass over all interior nodes or over the nodes of one colour
@@ -255,8 +270,9 @@ __device__ __forceinline__ VB vb_lev(const Grid& g, bool colour, int local)
 // red-black: this thread's row and position in plane p of its block; false outside the rows
 __device__ __forceinline__ bool rb_slot(const VB& b, const RB& r, int p, int& i, int& j, int& m)
 {
-    m = b.x * 64 + (int)(threadIdx.x & 63);
-    j = 1 + b.y * 4 + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63), w = 1 << r.lw;
+    m = b.x * w + (lane & (w - 1));
+    j = 1 + b.y * rb_rows(r) + (int)(threadIdx.x >> 6) * (64 >> r.lw) + (lane >> r.lw);
     i = 1 + b.z * kPlanesRB + p;
     return i <= r.nx - 2 && j <= r.ny - 2;
 }
