@@ -936,8 +936,8 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
     if (threadIdx.x == 0) D.part[local] = v[0];
 }
 
-// x += alpha p, r -= alpha q over every element (box and padding positions hold 0 in p, q and
-// r); partial sums of r.r (after the nb slots of the p.q sums)
+// x += alpha p, r -= alpha q at the level-0 unknowns (box and padding positions hold 0 in p,
+// q and r, and are left alone); partial sums of r.r (after the nb slots of the p.q sums)
 template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
 {
@@ -947,24 +947,33 @@ __global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
     if (local >= D.nb) return;   // alignment padding between problems
     const GMEM CGState* st = D.st;
     if (st->status != 0) return;
-    const GMEM T* __restrict__ p = p_new(st, D.cp, D.cp2);
-    GMEM T* __restrict__ x = D.cx;
-    GMEM T* __restrict__ r = D.cr;
-    const GMEM T* __restrict__ q = D.cq;
+    const RB R = D.rb;
+    const VB vb = vb_rb(R, local, D.nb);
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM T* p = p_new(st, D.cp, D.cp2) + F.org;
+    GMEM T* x = D.cx + F.org;
+    GMEM T* r = D.cr + F.org;
+    const GMEM T* q = D.cq + F.org;
     const T a = (T)st->alpha;
     double v[1] = {0.0};
-    const int64_t step = (int64_t)D.nb * 256;
-    for (int64_t e = (int64_t)local * 256 + threadIdx.x; e < D.rb.N; e += step) {
-        x[e] += a * p[e];
-        const T rv = r[e] - a * q[e];
-        r[e] = rv;
-        v[0] += (double)rv * (double)rv;
+#pragma unroll
+    for (int pl = 0; pl < kPlanesRB; ++pl) {
+        int i, j, m;
+        if (!rb_slot(vb, R, pl, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            if (rb_node(R, i, j, c, m) < 0) continue;
+            const uint32_t e = rb_rel(R, F, i, j, c, m);
+            stf(x, e) += a * ldf(p, e);
+            const T rv = ldf((const GMEM T*)r, e) - a * ldf(q, e);
+            stf(r, e) = rv;
+            v[0] += (double)rv * (double)rv;
+        }
     }
     bsum(v, 1, sh);
     if (threadIdx.x == 0) D.part[D.nb + local] = v[0];
 }
 
-// partial sums of r.z over every element (a single-level V-cycle forms no r.z itself)
+// partial sums of r.z at the level-0 unknowns (a single-level V-cycle forms no r.z itself)
 template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_dot(Bt<T> B, GateSpec gs)
 {
@@ -973,10 +982,22 @@ __global__ void __launch_bounds__(256) kb_rb_dot(Bt<T> B, GateSpec gs)
     const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     if (local >= D.nb) return;   // alignment padding between problems
     if (gated_out(gs, D.st)) return;
+    const RB R = D.rb;
+    const VB vb = vb_rb(R, local, D.nb);
+    const RBFrame F = rb_frame(R, vb);
+    const GMEM T* r = D.cr + F.org;
+    const GMEM T* z = D.cz + F.org;
     double v[1] = {0.0};
-    const int64_t step = (int64_t)D.nb * 256;
-    for (int64_t e = (int64_t)local * 256 + threadIdx.x; e < D.rb.N; e += step)
-        v[0] += (double)D.cr[e] * (double)D.cz[e];
+#pragma unroll
+    for (int pl = 0; pl < kPlanesRB; ++pl) {
+        int i, j, m;
+        if (!rb_slot(vb, R, pl, i, j, m)) continue;
+        for (int c = 0; c < 2; ++c) {
+            if (rb_node(R, i, j, c, m) < 0) continue;
+            const uint32_t e = rb_rel(R, F, i, j, c, m);
+            v[0] += (double)ldf(r, e) * (double)ldf(z, e);
+        }
+    }
     bsum(v, 1, sh);
     if (threadIdx.x == 0) D.part[local] = v[0];
 }
