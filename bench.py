@@ -46,11 +46,12 @@ ITER_BYTES_FP32 = 36
 # null.  The summaries with the commands are in profiles/.
 COUNTER_TRAFFIC = {
     # the 385^3 single solve (multigrid_385_counters)
-    "kb_rb_apply<float>@385": {"sources": "mg", "fingerprint": None, "ratio": None},
-    "kb_rb_sweep<float>@385": {"sources": "mg", "fingerprint": None, "ratio": None},
-    "k_cg_iter<float>@385": {"sources": "solve", "fingerprint": None, "ratio": None},
-    # the serving stream's batched launches (serving_stream_512_counters)
-    "kb_rb_apply<float>@stream": {"sources": "mg", "fingerprint": None, "ratio": None},
+    "kb_rb_apply<float>@385": {"sources": "mg", "fingerprint": "d1fe6399b7590711", "ratio": 1.540},
+    "kb_rb_sweep<float>@385": {"sources": "mg", "fingerprint": "d1fe6399b7590711", "ratio": 1.184},
+    "k_cg_iter<float>@385": {"sources": "solve", "fingerprint": "8f54055871f6891c", "ratio": 1.150},
+    # the serving stream's batched launches (serving_stream_512_counters); the sampled
+    # half-sweeps are a subset of the launches the counters see, so no ratio for them
+    "kb_rb_apply<float>@stream": {"sources": "mg", "fingerprint": "d1fe6399b7590711", "ratio": 1.656},
     "kb_rb_sweep<float>@stream": {"sources": "mg", "fingerprint": None, "ratio": None},
 }
 
@@ -117,8 +118,9 @@ def stream(n, precond="auto", mg_min_n=None):
     return out, unit_arrivals
 
 
-def serve(B, main, side, reqs, arrivals=None, max_resident=MAX_RESIDENT):
-    """Run requests through a fresh server; returns (results by id, wall seconds, server)."""
+def serve(B, main, side, reqs, arrivals=None, max_resident=MAX_RESIDENT, progress=0):
+    """Run requests through a fresh server; returns (results by id, wall seconds, server).
+    With progress > 0 a line is logged each time that many more requests have completed."""
     srv = B.Server(main, side, max_resident=max_resident)
     t0 = srv.now()
     for i, (mol, g) in enumerate(reqs):
@@ -129,6 +131,8 @@ def serve(B, main, side, reqs, arrivals=None, max_resident=MAX_RESIDENT):
         for r in srv.poll():
             r["latency_s"] = r["done_s"] - (t0 if arrivals is None else t0 + float(arrivals[r["id"]]))
             out[r["id"]] = r
+            if progress and len(out) % progress == 0:
+                log(f"{len(out)} of {len(reqs)} requests served")
     wall = srv.now() - t0
     return out, wall, srv
 
@@ -221,18 +225,38 @@ def bench_serving(args, B, torch):
     # warmup: the first requests through a server (untimed)
     for _ in range(args.warmup):
         close(serve(B, main, side, reqs[:32], max_resident=args.max_resident)[2])
+        log("warm-up done")
 
     # timed: the whole stream, closed loop
     walls, res = [], None
     for _ in range(args.steps):
         torch.cuda.synchronize()
-        res, wall, srv = serve(B, main, side, reqs, max_resident=args.max_resident)
+        res, wall, srv = serve(B, main, side, reqs, max_resident=args.max_resident,
+                               progress=64 if args.counters_run else 0)
         torch.cuda.synchronize()
         close(srv)
         walls.append(wall)
     value = N_REQ / float(np.mean(walls))
     codes = sorted({r["code"] for r in res.values()})
     log(f"closed loop: {value:.2f} solves/s")
+    if args.counters_run:
+        # the launches of a hardware-counter pass (which serializes them): the algorithmic
+        # bytes of the batched solver launches beside the counters
+        main.set_profiling(False)
+        side.set_profiling(False)
+        scope = "every batched launch of the run (warm-up and closed loop)"
+        out = {"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "counters_run": True,
+               "roofline_solver_kernels": [
+                   rf_hbm("kb_rb_apply<float>", prof["mg_apply_ms"], prof["mg_apply_bytes"], prof["mg_apply_launches"],
+                          scope),
+                   rf_hbm("kb_rb_sweep<float>", prof["mg_sweep_ms"], prof["mg_sweep_bytes"], prof["mg_samples"],
+                          "the first black half-sweep of every batched iteration (warm-up and closed loop)")],
+               # the copy kernel that scales the counters (1 GiB read and written per launch)
+               "stream_copy_GBs": round(main.stream_copy_gbps(1 << 30, 4), 1)}
+        main.close()
+        side.close()
+        return out
 
     # open loop: Poisson arrivals at OPEN_LOOP_LOAD x the closed-loop rate
     rate = OPEN_LOOP_LOAD * value
@@ -483,9 +507,10 @@ def workload(name: str):
 NBODY_FLOPS_PER_PAIR = 27
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic bytes per interior unknown of one level-0 red-black half-sweep of the V-cycle
-# (FP32, red-black layout): read x of the other colour, b and 1/D of the swept colour and the
-# node codes of both colours, write x of the swept colour
-MG_SWEEP_BYTES_FP32 = (4 + 4 + 4 + 4) / 2 + 4
+# (FP32, red-black layout): read x of the other colour, b, 1/D and the node codes of the swept
+# colour, write x of the swept colour (20 B per node of the swept colour; the codes of the
+# other colour are read only by waves with a cut edge)
+MG_SWEEP_BYTES_FP32 = (4 + 4 + 4 + 4 + 4) / 2
 REFINED_ITER_BYTES = 49 + 17 + 65 + 25
 # ... and with FP32 coefficients and vectors (mixed precision)
 REFINED_ITER_BYTES_FP32 = 25 + 9 + 33 + 13
@@ -588,6 +613,7 @@ def bench_single(args, B, torch):
     mol, grid, desc = workload(args.workload)
     nu = grid.unknowns
     ref = B.solve(mol, replace(grid, rtol=1e-12, precision=I.FP64), ctx)
+    log("tight FP64 reference solved")
 
     def run(g):
         lat, res = [], []
@@ -623,9 +649,13 @@ def bench_single(args, B, torch):
     nbt = NbodyTimes()
 
     mg = run(replace(grid, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA_MG, precond=I.MG))
+    log("mixed multigrid done")
     mg64 = run(replace(grid, precision=I.FP64, rtol=RTOL, precond=I.MG))
+    log("FP64 multigrid done")
     mx = run(replace(grid, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA))
+    log("mixed Jacobi done")
     p64 = run(replace(grid, precision=I.FP64, rtol=RTOL))
+    log("FP64 Jacobi done")
     # the two-run salt term: grid energies of multigrid mixed solves at the actual and at zero
     # ionic strength, against the same change of the surface read-back's solvation energy
     two_run = None
@@ -870,6 +900,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5", choices=["c5", "c1", "c2", "c3", "c4", "binding", "derefine"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--counters-run", action="store_true",
+                    help="serving stream: warm-up and closed loop only, with progress lines, for hardware-counter "
+                         "passes (prints the algorithmic bytes of the batched solver launches)")
     ap.add_argument("--max-resident", type=int, default=MAX_RESIDENT,
                     help="serving stream: problems resident at once")
     ap.add_argument("--serve-precond", default="auto", choices=["auto", "mg", "jacobi"],

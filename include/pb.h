@@ -408,9 +408,9 @@ int pb_server_profile(const pb_server* srv, double* stencil_ms_total, double* st
 /* The same for the multigrid requests: for every iteration of the batched multigrid chunks
  * (and the first iteration of every chunk of a request run alone) in which at least one
  * request iterated, the HIP-event time (ms) of the level-0 black half-sweep after the coarse
- * correction and its algorithmic bytes (12 per interior unknown of the requests that
- * iterated: in the red-black layout x of the other colour, b and 1/D of the swept colour and
- * the node codes of both read, x of the swept colour written), the time of the whole
+ * correction and its algorithmic bytes (10 per interior unknown of the requests that
+ * iterated: in the red-black layout x of the other colour, b, 1/D and the node codes of the
+ * swept colour read, x of the swept colour written), the time of the whole
  * V-cycle, and the number of samples. */
 int pb_server_profile_mg(const pb_server* srv, double* sweep_ms_total, double* sweep_bytes_total,
                          double* vcycle_ms_total, int64_t* samples);

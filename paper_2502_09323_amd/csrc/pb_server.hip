@@ -253,12 +253,13 @@ int complete_slot(pb_server* s, int k)
             SCHK(hipEventElapsedTime(&ap, e[0], e[1]));
             SCHK(hipEventElapsedTime(&sw, e[3], e[4]));
             SCHK(hipEventElapsedTime(&vc, e[2], e[5]));
-            // algorithmic bytes per unknown: the black half-sweep 12 (x of the other colour,
-            // b and 1/D of the swept one and the codes of both read, x written), the operator
-            // pass 20 (z, the old direction and the codes read; the new direction and q written)
+            // algorithmic bytes per unknown: the black half-sweep 10 (x of the other colour,
+            // b, 1/D and the codes of the swept one read, x of the swept one written: 20 B per
+            // node of that colour), the operator pass 20 (z, the old direction and the codes
+            // read; the new direction and q written)
             s->prof_mg_ms += sw;
             s->prof_mg_vcycle_ms += vc;
-            s->prof_mg_bytes += 12.0 * nu;
+            s->prof_mg_bytes += 10.0 * nu;
             s->prof_mg_n += 1;
             s->prof_mga_ms += ap;
             s->prof_mga_bytes += 20.0 * nu;
@@ -279,9 +280,9 @@ int complete_slot(pb_server* s, int k)
                 s->prof_mg_ms += sw;
                 s->prof_mg_vcycle_ms += vc;
                 // algorithmic bytes per unknown of the FP32 half-sweep in the red-black layout:
-                // x of the other colour, b and 1/D of the swept colour and the node codes of
-                // both read, x of the swept colour written
-                s->prof_mg_bytes += 12.0 * (double)smp.nu;
+                // x of the other colour, b, 1/D and the node codes of the swept colour read, x
+                // of the swept colour written
+                s->prof_mg_bytes += 10.0 * (double)smp.nu;
                 s->prof_mg_n += 1;
             }
             if (s->prof_slot[k] && !a.mg) {
