@@ -36,6 +36,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "pb_host.h"
@@ -343,29 +344,56 @@ __device__ __forceinline__ RBNb rb_nb(const RB& r, const RBFrame& f, int i, int 
 // C_BOX when none of its six edges is cut.
 constexpr uint32_t C_RB_UNCUT = C_BOX;
 
-// the six edge weights and the ionic term of node n (code = the frame's code base).  Where no
-// edge of any node of the wave is cut, the six weights are the node's medium value (an uncut
-// edge joins two nodes of one medium), the very values the table path gives, and the
-// neighbours' codes are not read.
-template <typename T>
-__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const GMEM uint32_t* code, const RBNb& n)
+// the six edge weights and the ionic term of node n whose code c is given (code = the frame's
+// code base).  Uncut (every node of the wave carries C_RB_UNCUT): the six weights are the
+// node's medium value (an uncut edge joins two nodes of one medium), the very values the
+// table path gives, and the neighbours' codes are not read.
+template <bool Uncut, typename T>
+__device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const GMEM uint32_t* code, const RBNb& n,
+                                                  uint32_t c)
 {
-    const uint32_t c = ldf(code, n.e);
     stencil::NodeK<T> k;
     k.m = (c & C_SOLUTE) ? (T)0 : op.mass;
-    if (__all((c & C_RB_UNCUT) != 0)) {
+    if constexpr (Uncut) {
         const T b = (c & C_SOLUTE) ? op.kin : op.kout;
         k.xm = k.xp = k.ym = k.yp = k.zm = k.zp = b;
-        return k;
+    } else {
+        const T* ck = (const T*)op.ck;   // still a global pointer to the compiler (it follows the cast)
+        k.xm = stencil::edgeK(ldf(code, n.xm), 0, ck, op.kin, op.kout);
+        k.xp = stencil::edgeK(c, 0, ck, op.kin, op.kout);
+        k.ym = stencil::edgeK(ldf(code, n.ym), 1, ck, op.kin, op.kout);
+        k.yp = stencil::edgeK(c, 1, ck, op.kin, op.kout);
+        k.zm = stencil::edgeK(ldf(code, n.zm), 2, ck, op.kin, op.kout);
+        k.zp = stencil::edgeK(c, 2, ck, op.kin, op.kout);
     }
-    const T* ck = (const T*)op.ck;   // still a global pointer to the compiler (it follows the cast)
-    k.xm = stencil::edgeK(ldf(code, n.xm), 0, ck, op.kin, op.kout);
-    k.xp = stencil::edgeK(c, 0, ck, op.kin, op.kout);
-    k.ym = stencil::edgeK(ldf(code, n.ym), 1, ck, op.kin, op.kout);
-    k.yp = stencil::edgeK(c, 1, ck, op.kin, op.kout);
-    k.zm = stencil::edgeK(ldf(code, n.zm), 2, ck, op.kin, op.kout);
-    k.zp = stencil::edgeK(c, 2, ck, op.kin, op.kout);
     return k;
+}
+
+// A level-0 stencil pass first loads the codes of all its thread's nodes (kPlanesRB x NC,
+// NC colours per plane; C_RB_UNCUT where a slot has no node), then takes one of two
+// branch-free bodies for the whole wave: the uncut one where every node of the wave carries
+// C_RB_UNCUT, else the table one.  With no branch on loaded data inside the body, the loads of
+// all planes can be in flight together.
+template <int NC>
+__device__ __forceinline__ bool rb_codes(const VB& vb, const RB& R, const RBFrame& F, const GMEM uint32_t* code,
+                                         int c0, uint32_t (*cc)[NC])
+{
+    bool uncut = true;
+#pragma unroll
+    for (int p = 0; p < kPlanesRB; ++p) {
+        int i, j, m;
+        const bool ok = rb_slot(vb, R, p, i, j, m);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int c = NC == 2 ? q : c0;
+            cc[p][q] = (ok && rb_node(R, i, j, c, m) >= 0) ? ldf(code, rb_rel(R, F, i, j, c, m)) : C_RB_UNCUT;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kPlanesRB; ++p)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) uncut = uncut && (cc[p][q] & C_RB_UNCUT) != 0;
+    return __all(uncut) != 0;
 }
 
 // sum over the six edges of K * v(neighbour)
@@ -759,22 +787,30 @@ __global__ void __launch_bounds__(256) kb_rb_down1(Bt<T> B, GateSpec gs)
     const GMEM T* b = D.cr + F.org;
     const GMEM T* dinv = D.dinv0 + F.org;
     GMEM T* x = D.cz + F.org;
+    uint32_t cc[kPlanesRB][1];
+    const bool uncut = rb_codes<1>(vb, R, F, code, 1, cc);
+    auto body = [&](auto U) {
 #pragma unroll
-    for (int p = 0; p < kPlanesRB; ++p) {
-        int i, j, m;
-        if (!rb_slot(vb, R, p, i, j, m)) continue;
-        if (rb_node(R, i, j, 0, m) >= 0) {
-            const uint32_t e = rb_rel(R, F, i, j, 0, m);
-            stf(x, e) = ldf(b, e) * ldf(dinv, e);
+        for (int p = 0; p < kPlanesRB; ++p) {
+            int i, j, m;
+            if (!rb_slot(vb, R, p, i, j, m)) continue;
+            if (rb_node(R, i, j, 0, m) >= 0) {
+                const uint32_t e = rb_rel(R, F, i, j, 0, m);
+                stf(x, e) = ldf(b, e) * ldf(dinv, e);
+            }
+            const int k = rb_node(R, i, j, 1, m);
+            if (k >= 0) {
+                const RBNb n = rb_nb(R, F, i, j, 1, m, k);
+                const stencil::NodeK<T> K = rb_k<decltype(U)::value>(D.op, code, n, cc[p][0]);
+                const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(b, f) * ldf(dinv, f); });
+                stf(x, n.e) = (ldf(b, n.e) + s) * ldf(dinv, n.e);
+            }
         }
-        const int k = rb_node(R, i, j, 1, m);
-        if (k >= 0) {
-            const RBNb n = rb_nb(R, F, i, j, 1, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, code, n);
-            const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(b, f) * ldf(dinv, f); });
-            stf(x, n.e) = (ldf(b, n.e) + s) * ldf(dinv, n.e);
-        }
-    }
+    };
+    if (uncut)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
 }
 
 // Gauss-Seidel on the level-0 nodes of colour c; with dot (the last red half-sweep of a
@@ -795,28 +831,36 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
     const GMEM T* b = D.cr + F.org;
     const GMEM T* dinv = D.dinv0 + F.org;
     GMEM T* x = D.cz + F.org;
+    uint32_t cc[kPlanesRB][1];
+    const bool uncut = rb_codes<1>(vb, R, F, code, c, cc);
     double v[1] = {0.0};
+    auto body = [&](auto U) {
 #pragma unroll
-    for (int p = 0; p < kPlanesRB; ++p) {
-        int i, j, m;
-        if (!rb_slot(vb, R, p, i, j, m)) continue;
-        const int k = rb_node(R, i, j, c, m);
-        if (k >= 0) {
-            const RBNb n = rb_nb(R, F, i, j, c, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, code, n);
-            const T s = rb_sum(K, n, [&](uint32_t f) { return ldf((const GMEM T*)x, f); });
-            const T bn = ldf(b, n.e);
-            const T xn = (bn + s) * ldf(dinv, n.e);
-            stf(x, n.e) = xn;
-            if constexpr (Dot) v[0] += (double)bn * (double)xn;
-        }
-        if constexpr (Dot) {
-            if (rb_node(R, i, j, 1 - c, m) >= 0) {
-                const uint32_t eb = rb_rel(R, F, i, j, 1 - c, m);
-                v[0] += (double)ldf(b, eb) * (double)ldf((const GMEM T*)x, eb);
+        for (int p = 0; p < kPlanesRB; ++p) {
+            int i, j, m;
+            if (!rb_slot(vb, R, p, i, j, m)) continue;
+            const int k = rb_node(R, i, j, c, m);
+            if (k >= 0) {
+                const RBNb n = rb_nb(R, F, i, j, c, m, k);
+                const stencil::NodeK<T> K = rb_k<decltype(U)::value>(D.op, code, n, cc[p][0]);
+                const T s = rb_sum(K, n, [&](uint32_t f) { return ldf((const GMEM T*)x, f); });
+                const T bn = ldf(b, n.e);
+                const T xn = (bn + s) * ldf(dinv, n.e);
+                stf(x, n.e) = xn;
+                if constexpr (Dot) v[0] += (double)bn * (double)xn;
+            }
+            if constexpr (Dot) {
+                if (rb_node(R, i, j, 1 - c, m) >= 0) {
+                    const uint32_t eb = rb_rel(R, F, i, j, 1 - c, m);
+                    v[0] += (double)ldf(b, eb) * (double)ldf((const GMEM T*)x, eb);
+                }
             }
         }
-    }
+    };
+    if (uncut)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
     if constexpr (Dot) {
         bsum(v, 1, sh);
         if (threadIdx.x == 0) D.prz[local] = v[0];
@@ -839,17 +883,25 @@ __global__ void __launch_bounds__(256) kb_rb_resid(Bt<T> B, GateSpec gs)
     const GMEM T* b = D.cr + F.org;
     const GMEM T* x = D.cz + F.org;
     GMEM T* r = D.r0 + F.org;
+    uint32_t cc[kPlanesRB][1];
+    const bool uncut = rb_codes<1>(vb, R, F, code, 0, cc);
+    auto body = [&](auto U) {
 #pragma unroll
-    for (int p = 0; p < kPlanesRB; ++p) {
-        int i, j, m;
-        if (!rb_slot(vb, R, p, i, j, m)) continue;
-        const int k = rb_node(R, i, j, 0, m);
-        if (k < 0) continue;
-        const RBNb n = rb_nb(R, F, i, j, 0, m, k);
-        const stencil::NodeK<T> K = rb_k(D.op, code, n);
-        const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(x, f); });
-        stf(r, n.e) = ldf(b, n.e) - (K.diag() * ldf(x, n.e) - s);
-    }
+        for (int p = 0; p < kPlanesRB; ++p) {
+            int i, j, m;
+            if (!rb_slot(vb, R, p, i, j, m)) continue;
+            const int k = rb_node(R, i, j, 0, m);
+            if (k < 0) continue;
+            const RBNb n = rb_nb(R, F, i, j, 0, m, k);
+            const stencil::NodeK<T> K = rb_k<decltype(U)::value>(D.op, code, n, cc[p][0]);
+            const T s = rb_sum(K, n, [&](uint32_t f) { return ldf(x, f); });
+            stf(r, n.e) = ldf(b, n.e) - (K.diag() * ldf(x, n.e) - s);
+        }
+    };
+    if (uncut)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
 }
 
 // x += P e at the red nodes of level 0 from level 1 (the black half-sweep that follows
@@ -915,23 +967,32 @@ __global__ void __launch_bounds__(256) kb_rb_apply(Bt<T> B)
     GMEM T* q = D.cq + F.org;
     const T beta = (T)st->beta;
     auto pd = [&](uint32_t f) { return ldf(z, f) + beta * ldf(po, f); };
+    uint32_t cc[kPlanesRB][2];
+    const bool uncut = rb_codes<2>(vb, R, F, code, 0, cc);
     double v[1] = {0.0};
+    auto body = [&](auto U) {
 #pragma unroll
-    for (int p = 0; p < kPlanesRB; ++p) {
-        int i, j, m;
-        if (!rb_slot(vb, R, p, i, j, m)) continue;
-        for (int c = 0; c < 2; ++c) {
-            const int k = rb_node(R, i, j, c, m);
-            if (k < 0) continue;
-            const RBNb n = rb_nb(R, F, i, j, c, m, k);
-            const stencil::NodeK<T> K = rb_k(D.op, code, n);
-            const T pe = pd(n.e);
-            const T qe = K.diag() * pe - rb_sum(K, n, pd);
-            stf(pn, n.e) = pe;
-            stf(q, n.e) = qe;
-            v[0] += (double)pe * (double)qe;
+        for (int p = 0; p < kPlanesRB; ++p) {
+            int i, j, m;
+            if (!rb_slot(vb, R, p, i, j, m)) continue;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int k = rb_node(R, i, j, c, m);
+                if (k < 0) continue;
+                const RBNb n = rb_nb(R, F, i, j, c, m, k);
+                const stencil::NodeK<T> K = rb_k<decltype(U)::value>(D.op, code, n, cc[p][c]);
+                const T pe = pd(n.e);
+                const T qe = K.diag() * pe - rb_sum(K, n, pd);
+                stf(pn, n.e) = pe;
+                stf(q, n.e) = qe;
+                v[0] += (double)pe * (double)qe;
+            }
         }
-    }
+    };
+    if (uncut)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
     bsum(v, 1, sh);
     if (threadIdx.x == 0) D.part[local] = v[0];
 }
