@@ -99,27 +99,43 @@ __global__ void k_bin_sort(int nbins, const int* start, int* ids)
     }
 }
 
-// single-block exclusive scan of up to n ints (in place into out[0..n]; out[n] = total)
+// single-block exclusive scan of n ints into out[0..n] (out[n] = total; out may be in), in
+// tiles of 4096: each thread takes four consecutive elements, the 1024 partial sums of a tile
+// are scanned with wave shuffles and a pass over the 16 wave totals, and the running total
+// carries from tile to tile.  Each element is read before it is written, by the same thread,
+// so in == out is safe.
 __global__ void __launch_bounds__(1024) k_scan1(const int* in, int n, int* out)
 {
-    __shared__ int sh[1024];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        int i = base + threadIdx.x;
-        int v = i < n ? in[i] : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
+    __shared__ int wtot[16];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    int carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int e0 = base + 4 * (int)threadIdx.x;
+        int v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = e0 + u < n ? in[e0 + u] : 0;
+        const int s = (v[0] + v[1]) + (v[2] + v[3]);
+        int incl = s;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
         }
-        if (i < n) out[i] = carry + sh[threadIdx.x] - v;
+        if (lane == 63) wtot[w] = incl;
         __syncthreads();
-        if (threadIdx.x == 0) carry += sh[1023];
+        int before = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int t = wtot[q];
+            before += q < w ? t : 0;
+            total += t;
+        }
+        int run = carry + before + incl - s;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (e0 + u < n) out[e0 + u] = run;
+            run += v[u];
+        }
+        carry += total;
         __syncthreads();
     }
     if (threadIdx.x == 0) out[n] = carry;
