@@ -499,26 +499,23 @@ __device__ __forceinline__ int64_t n_box(const Grid& g)
     return 2 * ((int64_t)g.ny * g.nz + (int64_t)(g.nx - 2) * g.nz + (int64_t)(g.nx - 2) * (g.ny - 2));
 }
 
-// exp(x) for x <= 0 in FP64 by Tang's table-driven method (P. T. P. Tang, ACM TOMS 15(2),
-// 1989): x = (n / 256) ln 2 + r with |r| <= ln 2 / 512, exp(x) = 2^(n >> 8) 2^((n & 255) / 256)
-// e^r.  n comes from the round-to-nearest of a 1.5 * 2^52 shift, r from a two-part ln 2 / 256
-// (the high part has 37 significant bits, so n times it is exact for |n| < 2^16, |x| < 177),
-// e^r from its Taylor polynomial to degree 4 (truncation under 4e-17 relative), and the table
-// T[j] = 2^(j / 256) is formed once per block.  The result is within a few units in the last
-// place of exp(x).
-__device__ __forceinline__ double exp_neg(double x, const double* T)
+// exp(-kD r) for r >= 0 in FP64 by Tang's table-driven method (P. T. P. Tang, ACM TOMS 15(2),
+// 1989) with the factor -kD folded into the constants: n = round(-kD r 2048 / ln 2), from the
+// round-to-nearest of a 1.5 * 2^52 shift, and s = r + n L with L = ln 2 / (2048 kD), so that
+// -kD r = (n / 2048) ln 2 - kD s with kD |s| <= ln 2 / 4096.  Then exp(-kD r) = 2^(n >> 11)
+// 2^((n & 2047) / 2048) e^(-kD s), the last factor from its Taylor polynomial to degree 3
+// (truncation under 4e-17 relative), the table T[j] = 2^(j / 2048) formed once per block.  L is
+// one FP64 number: its rounding moves s by about r 1e-16, which changes the result by about
+// kD r 1e-16 relative, the size of the rounding of the argument -kD r itself (Tang splits ln 2
+// in two parts for an argument given exactly; here r carries a rounding of its own).
+__device__ __forceinline__ double exp_dh(double r, const DhExp& E, const double* T)
 {
-    const double shift = 6755399441055744.0;                  // 1.5 * 2^52
-    const double t = fma(x, 369.32993046757458, shift);        // 256 / ln 2
+    const double shift = 6755399441055744.0;   // 1.5 * 2^52
+    const double t = fma(r, E.tscale, shift);
     const int n = __double2loint(t);
-    const double nd = t - shift;
-    double r = fma(nd, -0.0027076061740558544, x);             // ln 2 / 256, high part
-    r = fma(nd, -6.432011555819173e-15, r);                    // low part
-    double pl = fma(r, 1.0 / 24.0, 1.0 / 6.0);
-    pl = fma(pl, r, 0.5);
-    pl = fma(pl, r, 1.0);
-    pl = fma(pl, r, 1.0);
-    return ldexp(T[n & 255] * pl, n >> 8);
+    const double s = fma(t - shift, E.L, r);
+    const double p = fma(fma(fma(s, E.c3, E.c2), s, E.c1), s, 1.0);
+    return ldexp(T[n & (kDhTable - 1)] * p, n >> 11);
 }
 
 // A thread's box nodes: t and t + 256 of its block's tile of kDhNodesPerBlock
@@ -537,33 +534,43 @@ __device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const D
 }
 
 // Debye-Hueckel values at the box nodes in FP64 (Sect. 2.3, the Debye-Hueckel form):
-// g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The distance is formed from the
-// coordinate differences, 1/r by rsqrt_fp64, r = r^2 (1/r), exp(-kD r) by exp_neg; without salt
-// (kD = 0) the exponential is skipped.  Block b takes box-node tile b % tiles (two nodes per
-// thread, so that each atom read from LDS serves two pairs) and the atoms of range b / tiles;
-// its partial sums go to part[range][node], which k_bc_dh_sum adds up in range order.
-__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, DhSplit sp, double* part)
+// g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The squared distance is taken in the
+// expanded form |p|^2 + |a|^2 - 2 a.p (one add and three fused multiply-adds from -2a and |a|^2
+// held in LDS), with the node p and the atom a relative to the atoms' centre: its rounding
+// error, about (|p|^2 + |a|^2) 1e-16, is below 1e-13 of r^2 wherever the box is at least a
+// thirtieth of its half-diagonal from every atom centre (the benchmark boxes are tens of
+// Angstrom away).  Then 1/r by rsqrt_fp64, r = r^2 (1/r) and exp(-kD r) by exp_dh; without
+// salt (kD = 0) the exponential is skipped.  Block b takes box-node tile b % tiles (two nodes
+// per thread, so that each atom read from LDS serves two pairs) and the atoms of range
+// b / tiles; its partial sums go to part[range][node], which k_bc_dh_sum adds up in range
+// order.
+__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSplit sp, double* part)
 {
     __shared__ double sa[256 * 4];
-    __shared__ double T[256];
-    T[threadIdx.x] = exp2((double)threadIdx.x / 256.0);
+    __shared__ double sq[256];
+    __shared__ double T[kDhTable];
+    for (int j = threadIdx.x; j < kDhTable; j += 256) T[j] = exp2((double)j / kDhTable);
     const int tile = (int)(blockIdx.x % sp.tiles), rg = (int)(blockIdx.x / sp.tiles);
     int64_t t[2];
     bool act[2];
     double p[2][3];
     dh_nodes(g, at, sp, tile, t, act, p);
-    const double mk = -kD;
-    const bool salt = kD != 0.0;
+    const double pp0 = fma(p[0][0], p[0][0], fma(p[0][1], p[0][1], p[0][2] * p[0][2]));
+    const double pp1 = fma(p[1][0], p[1][0], fma(p[1][1], p[1][1], p[1][2] * p[1][2]));
+    const bool salt = E.c1 != 0.0;
     const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
     double s0 = 0.0, s1 = 0.0;
     for (int base = a0; base < a1; base += 256) {
         int a = base + threadIdx.x;
         __syncthreads();
         if (a < a1) {
-            sa[4 * threadIdx.x + 0] = at.xyzr[4 * a + 0] - at.cx;
-            sa[4 * threadIdx.x + 1] = at.xyzr[4 * a + 1] - at.cy;
-            sa[4 * threadIdx.x + 2] = at.xyzr[4 * a + 2] - at.cz;
-            sa[4 * threadIdx.x + 3] = at.q[a];
+            const double x = at.xyzr[4 * a + 0] - at.cx, y = at.xyzr[4 * a + 1] - at.cy,
+                         z = at.xyzr[4 * a + 2] - at.cz;
+            sa[4 * threadIdx.x + 0] = -2.0 * x;
+            sa[4 * threadIdx.x + 1] = -2.0 * y;
+            sa[4 * threadIdx.x + 2] = -2.0 * z;
+            sa[4 * threadIdx.x + 3] = fma(x, x, fma(y, y, z * z));
+            sq[threadIdx.x] = at.q[a];
         }
         __syncthreads();
         int m = a1 - base < 256 ? a1 - base : 256;
@@ -572,31 +579,20 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, double kD, DhSp
 #pragma unroll 2
             for (int u = 0; u < m; ++u) {
                 const double* A = sa + 4 * u;
-                {
-                    const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
-                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double y = rsqrt_fp64(r2);
-                    s0 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s0);
-                }
-                {
-                    const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
-                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double y = rsqrt_fp64(r2);
-                    s1 = fma(A[3] * exp_neg(mk * (r2 * y), T), y, s1);
-                }
+                const double q = sq[u];
+                const double r20 = fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])));
+                const double r21 = fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])));
+                const double y0 = rsqrt_fp64(r20), y1 = rsqrt_fp64(r21);
+                s0 = fma(q * exp_dh(r20 * y0, E, T), y0, s0);
+                s1 = fma(q * exp_dh(r21 * y1, E, T), y1, s1);
             }
         } else {
 #pragma unroll 2
             for (int u = 0; u < m; ++u) {
                 const double* A = sa + 4 * u;
-                {
-                    const double dx = p[0][0] - A[0], dy = p[0][1] - A[1], dz = p[0][2] - A[2];
-                    s0 = fma(A[3], rsqrt_fp64(fma(dx, dx, fma(dy, dy, dz * dz))), s0);
-                }
-                {
-                    const double dx = p[1][0] - A[0], dy = p[1][1] - A[1], dz = p[1][2] - A[2];
-                    s1 = fma(A[3], rsqrt_fp64(fma(dx, dx, fma(dy, dy, dz * dz))), s1);
-                }
+                const double q = sq[u];
+                s0 = fma(q, rsqrt_fp64(fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])))), s0);
+                s1 = fma(q, rsqrt_fp64(fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])))), s1);
             }
         }
     }
@@ -1015,6 +1011,19 @@ hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, con
     return hipGetLastError();
 }
 
+DhExp dh_exp_consts(double kD)
+{
+    DhExp E{};
+    if (kD == 0.0) return E;
+    const long double ln2 = 0.693147180559945309417232121458176568L;
+    E.L = (double)(ln2 / ((long double)kDhTable * (long double)kD));
+    E.tscale = (double)(-(long double)kD * kDhTable / ln2);
+    E.c1 = -kD;
+    E.c2 = 0.5 * kD * kD;
+    E.c3 = -kD * kD * kD / 6.0;
+    return E;
+}
+
 DhSplit dh_split(const Grid& g, int n_atoms)
 {
     DhSplit sp;
@@ -1035,7 +1044,7 @@ hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD
                         double* gb)
 {
     const DhSplit sp = dh_split(g, at.n);
-    k_bc_dh<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, kD, sp, part);
+    k_bc_dh<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, dh_exp_consts(kD), sp, part);
     k_bc_dh_sum<<<(unsigned)nblk(sp.nbox, 256), 256, 0, s>>>(g, sp, part, eps_out, gb);
     return hipGetLastError();
 }

@@ -149,6 +149,14 @@ struct DhSplit {
     int ranges;     // atom ranges (at most kDhMaxRanges)
 };
 DhSplit dh_split(const Grid& g, int n_atoms);
+// constants of the table-driven exp(-kD r) of the FP64 Debye-Hueckel sum
+constexpr int kDhTable = 2048;   // T[j] = 2^(j / kDhTable)
+struct DhExp {
+    double tscale;      // -kD kDhTable / ln 2
+    double L;           // ln 2 / (kDhTable kD)
+    double c1, c2, c3;  // Taylor coefficients of e^(-kD s): -kD, kD^2 / 2, -kD^3 / 6 (all 0 for kD = 0)
+};
+DhExp dh_exp_consts(double kD);
 // part holds dh_split(g, at.n).ranges * nbox doubles
 hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
                         double* gb);
