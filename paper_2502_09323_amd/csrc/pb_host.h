@@ -284,22 +284,30 @@ int pbi_refine_solve(pb_problem* pb, pbk::CGState* out);
 // multigrid-preconditioned CG (pb_mg.hip)
 int pbi_mg_solve(pb_problem* pb, pbk::CGState* out);
 // the same in steps for the serving loop, all enqueued on stream s: the level hierarchy,
-// then chunks of n iterations (first: x = 0 and the first residual before them), each
-// followed by the restart from the true residual where one is due; finish folds a leftover
-// FP32 correction into the solution
+// then chunks of n iterations (first: x = 0 and the first residual before them; in mixed
+// precision an iteration that follows a stop for a residual replacement runs that
+// replacement instead of a step); finish folds a leftover FP32 correction into the solution
 int pbi_mg_begin(pb_problem* pb, hipStream_t s);
 // (sample: four events for the first iteration's V-cycle, or nullptr; see pb_get_profile)
 int pbi_mg_chunk(pb_problem* pb, hipStream_t s, int n, bool first, hipEvent_t* sample);
 int pbi_mg_finish(pb_problem* pb, hipStream_t s);
 int pbi_mg_levels(const pb_problem* pb);
+// Iterations to launch next for a problem whose last completed chunk ended in state st, with
+// `pending` iterations launched since (at most cap; 0: the chunk in flight is expected to
+// finish it).  At the mean rate at which the squared residual fell from ||b||^2 to rr over
+// iter_count iterations it reaches the goal after some more; in mixed precision each residual
+// replacement (one per delta2 of decrease, the last confirming convergence) takes an
+// iteration of its own.  An estimate that falls short costs one more round trip; one that runs
+// over, launches that return at once.
+int pbi_mg_next_chunk(const pbk::CGState& st, int pending, int cap);
 // x = 0 and the first residual of a multigrid problem, enqueued on s
 int pbi_mg_start(pb_problem* pb, hipStream_t s);
 // whether a problem can join batched multigrid chunks (more than one level, and no large
 // coarsest level run in launches of its own)
 bool pbi_mg_batchable(const pb_problem* pb);
 // n iterations of every problem of pbs (at most PB_MG_MAX_BATCH, batchable, one precision and
-// the same smoothing counts) in batched launches, then the restart where one is due, and the
-// problems' states into gather[0 .. pbs.size()) (device); ev (optional): 6 events per
+// the same smoothing counts) in batched launches, then the problems' states into
+// gather[0 .. pbs.size()) (device); ev (optional): 6 events per
 // iteration, two around its operator pass, then four around its V-cycle and the first
 // level-0 black half-sweep after the coarse correction
 int pbi_mg_batch_chunk(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGBatch* bb, pbk::CGState* gather,

@@ -89,7 +89,8 @@ struct CGState {
     double rr;         // ||r||^2 of the last iterate (recursive residual)
     double pq;         // p.A p of the last iteration
     double stop2;      // the tail stops the iteration when rr <= stop2 ...
-    double trig2;      // mixed: a reliable update runs at a chunk end once rr <= trig2
+    double trig2;      // mixed: a reliable update runs once rr <= trig2 (Jacobi CG: at the
+                       // chunk's end; multigrid: in the next iteration)
     double delta2;     // mixed: after an update trig2 = delta2 * ||r||^2
     double goal64;     // mixed: converged when the FP64 true ||b - A x||^2 <= goal64
     double rr64;       // mixed: FP64 true residual norm^2 at the last update

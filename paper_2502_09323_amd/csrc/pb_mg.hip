@@ -195,13 +195,14 @@ __device__ __forceinline__ int bt_find(const GMEM int* off, int P, int& local)
 // on its own); or gated on another state (the two-level preconditioner of refined grids)
 struct GateSpec {
     const GMEM CGState* ext;
-    int mode;   // 0 iteration, 1 restart, 2 none, 3 ext (running, ru 0; null: none)
+    int mode;   // 0 iteration, 1 restart, 2 none, 3 ext (running, ru 0; null: none), 4 running
 };
 
 __device__ __forceinline__ bool gated_out(const GateSpec& g, const GMEM CGState* st)
 {
     if (g.mode == 2) return false;
     if (g.mode == 3) return g.ext && (g.ext->status != 0 || g.ext->ru != 0);
+    if (g.mode == 4) return st->status != 0;
     return st->status != 0 || st->ru != g.mode;
 }
 
@@ -1167,17 +1168,21 @@ __global__ void __launch_bounds__(256) kb_alpha(Bt<T> B)
 // mode 0 (an iteration): beta = r.z / r.z_old, the iteration count and the stop test on the
 // recursive r.r (status = stop_status once r.r <= stop2, or <= trig2 in mixed precision);
 // mode 1 (first residual): beta = 0; mode 2 (after a residual replacement): the direction
-// update that the stopped step skipped takes beta = r'.z' / (r.z of the step before).
+// update that the stopped step skipped takes beta = r'.z' / (r.z of the step before);
+// mode 3: mode 2 where a replacement has just run in this iteration (ru set), mode 0 otherwise.
 // The r.z partials are those of the fused last half-sweep (prz), or of the dot pass (part)
 // for a single-level V-cycle.
 template <typename T>
-__global__ void __launch_bounds__(256) kb_beta(Bt<T> B, int mode)
+__global__ void __launch_bounds__(256) kb_beta(Bt<T> B, int mode_arg)
 {
     __shared__ double sh[8];
     int local;
     const GMEM MGDev<T>& D = *B.d[bt_find(B.off, B.P, local)];
     GMEM CGState* st = D.st;
-    if (st->status != 0 || st->ru != (mode == 0 ? 0 : 1)) return;
+    if (st->status != 0) return;
+    // read by every thread before the block sums below; thread 0 writes ru after them
+    const int mode = mode_arg == 3 ? (st->ru ? 2 : 0) : mode_arg;
+    if (st->ru != (mode == 0 ? 0 : 1)) return;
     double v[2] = {psum(D.nlev > 1 ? D.prz : D.part, D.nb), mode == 0 ? psum(D.part + D.nb, D.nb) : 0.0};
     bsum(v, 2, sh);
     if (threadIdx.x == 0) {
@@ -1635,25 +1640,34 @@ void run_vcycle(hipStream_t s, const Plan& pl, GateSpec gs, hipEvent_t* ev = nul
 }
 
 // one CG iteration of every problem of the plan (ev: the V-cycle's four events; ea: two
-// events around the operator pass)
+// events around the operator pass).  In mixed precision a problem whose last iteration
+// stopped with status 3 (its FP32 residual reached its goal or fell by inner_rtol) skips the
+// step and instead replaces its residual: fold the correction into the FP64 solution, r = b -
+// A x in FP64 and the convergence test on it; the iteration's V-cycle and beta (mode 3) then
+// serve the replaced residual.  A problem's replacement so follows the iteration that asked
+// for it, wherever the chunks of iterations end.
 template <typename T>
 void run_iteration(hipStream_t s, const Plan& pl, hipEvent_t* ev = nullptr, hipEvent_t* ea = nullptr)
 {
-    const GateSpec gs{nullptr, 0};
+    const GateSpec gs{nullptr, 4};
     if (ea) (void)hipEventRecord(ea[0], s);
     PLAUNCH0(K_RB0, 256, kb_rb_apply<T>);
     if (ea) (void)hipEventRecord(ea[1], s);
     PLAUNCH0(K_ONE, 256, kb_alpha<T>);
     PLAUNCH0(K_RB0, 256, kb_rb_update<T>);
+    if (sizeof(T) == 4) {
+        PLAUNCH(K_RB0, 256, kb_rb_fold<T>, 0);
+        PLAUNCH(K_RB0, 256, kb_rb_true_res<T>, 0);
+        PLAUNCH(K_ONE, 256, kb_ru_fin<T>, 0, 0);
+    }
     run_vcycle<T>(s, pl, gs, ev);
     if (pl.single) PLAUNCH(K_RB0, 256, kb_rb_dot<T>, gs);
-    PLAUNCH(K_ONE, 256, kb_beta<T>, 0);
+    PLAUNCH(K_ONE, 256, kb_beta<T>, 3);
 }
 
 // restart from the true residual: fold the correction into the FP64 solution, r = b - A x in
 // FP64, then z = V-cycle(r), r.z and beta.  With force it runs whatever the state (init: the
-// first residual, x = 0); otherwise only where the iteration stopped with status 3 (the FP32
-// residual reached its goal or fell by inner_rtol).
+// first residual, x = 0); otherwise only where the iteration stopped with status 3.
 template <typename T>
 void run_restart(hipStream_t s, const Plan& pl, int init, int force)
 {
@@ -1866,8 +1880,8 @@ int start_t(pb_problem* pb, hipStream_t s)
     return PB_OK;
 }
 
-// n iterations and the restart that follows them where one is due, enqueued on s; ev[it],
-// where given, receives the four timing events of iteration it's V-cycle
+// n iterations enqueued on s; ev[it], where given, receives the four timing events of
+// iteration it's V-cycle
 // (ran[it], where given: receives the state's status as iteration it starts; 0 means the
 // iteration runs, short of a breakdown in its alpha step: only its scalar steps change it)
 template <typename T>
@@ -1878,13 +1892,13 @@ int chunk_t(pb_problem* pb, hipStream_t s, int n, hipEvent_t* const* ev, int* co
         if (ran && ran[it]) RCHK(hipMemcpyAsync(ran[it], &pb->st->status, sizeof(int), hipMemcpyDeviceToDevice, s));
         run_iteration<T>(s, pl, ev ? ev[it] : nullptr);
     }
-    if (sizeof(T) == 4) run_restart<T>(s, pl, 0, 0);
     RCHK(hipGetLastError());
     return PB_OK;
 }
 
-// Pipelined like the Jacobi solve: chunks of iterations (each followed by the restart where
-// one is due) are enqueued while the state of the previous chunk is read back.
+// Pipelined like the Jacobi solve: a chunk of iterations is enqueued while the state of the
+// previous one is read back, its length from the residual decay seen so far
+// (pbi_mg_next_chunk), so that few iterations are launched past convergence.
 template <typename T>
 int solve_t(pb_problem* pb, CGState* out)
 {
@@ -1895,7 +1909,7 @@ int solve_t(pb_problem* pb, CGState* out)
     if (!rc) rc = start_t<T>(pb, s);
     if (rc) return rc;
     const int M = 8;
-    int launched = 0, c = 0;
+    int launched = 0;
     // sampled timings (context profiling on): every 4th iteration while the V-cycle has
     // more than one level
     const bool prof = ctx->profile != 0 && pb->mg->nlev > 1;
@@ -1908,8 +1922,7 @@ int solve_t(pb_problem* pb, CGState* out)
         ran_dev = (int*)pb->mem.get(sizeof(int) * kMaxSamples);
         if (!ran_dev) return pbi_fail(PB_ENOMEM, "profiling flags");
     }
-    auto enqueue = [&](int slot) -> int {
-        const int n = std::min(M, P.max_iter - launched);
+    auto enqueue = [&](int slot, int n) -> int {
         hipEvent_t* ev[M] = {};
         for (int it = 0; prof && it < n; ++it) {
             if ((launched + it) % 4 != 0 || evs.size() >= 4 * kMaxSamples) continue;
@@ -1937,14 +1950,35 @@ int solve_t(pb_problem* pb, CGState* out)
         RCHK(hipEventRecord(ctx->ev[slot], s));
         return PB_OK;
     };
-    if ((rc = enqueue(0))) return rc;
+    // chunks in flight, oldest first (at most two): iterations and state slot
+    int q_n[2] = {0, 0}, q_slot[2] = {0, 0}, qlen = 0, next_slot = 0;
+    auto push = [&](int n) -> int {
+        const int slot = next_slot;
+        next_slot ^= 1;
+        const int r = enqueue(slot, n);
+        if (r) return r;
+        q_n[qlen] = n;
+        q_slot[qlen] = slot;
+        ++qlen;
+        return PB_OK;
+    };
+    if ((rc = push(std::min(M, P.max_iter)))) return rc;
+    bool seen = false;
+    CGState snap{};
     for (;;) {
-        const bool more = launched < P.max_iter;
-        if (more && (rc = enqueue((c + 1) & 1))) return rc;
-        RCHK(hipEventSynchronize(ctx->ev[c & 1]));
-        const CGState snap = ctx->host_state[c & 1];
-        if (snap.status == 1 || snap.status == 2 || !more) break;
-        ++c;
+        if (qlen < 2 && launched < P.max_iter) {
+            int n = seen ? pbi_mg_next_chunk(snap, qlen ? q_n[0] : 0, M) : M;
+            n = std::min(n, P.max_iter - launched);
+            if (n > 0 && (rc = push(n))) return rc;
+        }
+        RCHK(hipEventSynchronize(ctx->ev[q_slot[0]]));
+        snap = ctx->host_state[q_slot[0]];
+        seen = true;
+        q_n[0] = q_n[1];
+        q_slot[0] = q_slot[1];
+        --qlen;
+        if (snap.status == 1 || snap.status == 2) break;
+        if (qlen == 0 && launched >= P.max_iter) break;
     }
     // the correction into the FP64 solution (all of it in FP64; in the mixed form what is left
     // after the last restart)
@@ -2030,13 +2064,35 @@ int batch_chunk_t(const std::vector<pb_problem*>& pbs, hipStream_t s, int n, MGB
     pl.off = (const int*)((char*)bb->dev + sizeof(void*) * P);
     for (int it = 0; it < n; ++it)
         run_iteration<T>(s, pl, ev ? ev + 6 * it + 2 : nullptr, ev ? ev + 6 * it : nullptr);
-    if (sizeof(T) == 4) run_restart<T>(s, pl, 0, 0);
     if (gather) kb_gather<T><<<P, 64, 0, s>>>(bt<T>(pl, K_ONE), gather);
     RCHK(hipGetLastError());
     return PB_OK;
 }
 
 }  // namespace
+
+int pbi_mg_next_chunk(const CGState& st, int pending, int cap)
+{
+    int need = cap;
+    if (st.goal64 > 0.0 && st.rr > 0.0 && st.rr <= st.goal64) {
+        need = 0;
+    } else if (st.iter_count > 0 && st.rr > 0.0 && st.rr < st.bnorm2 && st.goal64 > 0.0) {
+        const double rate = std::log(st.rr / st.bnorm2) / (double)st.iter_count;   // < 0
+        if (rate < -1e-3) need = (int)std::min<double>(cap, std::ceil(std::log(st.goal64 / st.rr) / rate));
+    }
+    if (st.stop_status == 3) {
+        // mixed precision: a residual replacement per delta2 of decrease, the last one
+        // confirming convergence, each in an iteration of its own
+        int rep = 1;
+        if (st.delta2 > 0.0 && st.delta2 < 1.0 && st.goal64 > 0.0 && st.rr > st.goal64)
+            rep = std::max(1, (int)std::ceil(std::log(st.goal64 / st.rr) / std::log(st.delta2)));
+        need += rep;
+    }
+    int n = std::min(need - pending, cap);
+    if (n < 0) n = 0;
+    if (n == 0 && pending == 0) n = 1;   // nothing in flight: keep it moving
+    return n;
+}
 
 int pbi_mg_solve(pb_problem* pb, CGState* out)
 {

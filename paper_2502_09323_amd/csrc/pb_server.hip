@@ -510,26 +510,11 @@ int admit(pb_server* s)
 }
 
 // Iterations to give a multigrid problem in the next chunk; 0 when the chunk in flight is
-// expected to finish it.  From the state after its last completed chunk: the squared residual
-// fell from ||b||^2 (the solve starts at x = 0) to rr in iter_count iterations; at that mean
-// rate it reaches the goal after `need` more, `pending` of which are already launched.  An
-// estimate that falls short only costs one more chunk; one that runs over, launches that
-// return at once.
+// expected to finish it (pbi_mg_next_chunk, from the state after its last completed chunk).
 int mg_chunk_iters(const Active& a)
 {
     if (!a.seen) return a.pending == 0 ? kMgFirst : kMgSecond;
-    const CGState& st = a.snap;
-    int need = kChunkIters;
-    if (st.rr <= st.goal64) {
-        need = 0;
-    } else if (st.iter_count > 0 && st.rr > 0.0 && st.rr < st.bnorm2 && st.goal64 > 0.0) {
-        const double rate = std::log(st.rr / st.bnorm2) / (double)st.iter_count;   // < 0
-        if (rate < -1e-3) need = (int)std::min<double>(kChunkIters, std::ceil(std::log(st.goal64 / st.rr) / rate));
-    }
-    int n = std::min(need + 1 - a.pending, kChunkIters);
-    if (n < 0) n = 0;
-    if (n == 0 && a.pending == 0) n = 1;   // nothing in flight: keep it moving
-    return n;
+    return pbi_mg_next_chunk(a.snap, a.pending, kChunkIters);
 }
 
 // an event from the pool (timing only: no system-scope fence, whose cache writeback would count)
