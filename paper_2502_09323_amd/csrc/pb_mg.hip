@@ -1091,7 +1091,8 @@ __global__ void __launch_bounds__(256) kb_rb_fold(Bt<T> B, int force)
 
 // r = b - A x in FP64 from the natural-layout solution, right-hand side and codes, stored in
 // the element type in the red-black layout; partial sums of the FP64 r.r in the third slot
-// range, one per block
+// range, one per block.  force 2: x = 0 (the first residual), r = b without the operator (the
+// same values: b - (D 0 - sum K 0) is b)
 template <typename T>
 __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
 {
@@ -1114,12 +1115,15 @@ __global__ void __launch_bounds__(256) kb_rb_true_res(Bt<T> B, int force)
             const int k = rb_node(R, i, j, c, m);
             if (k < 0) continue;
             const int64_t e = g.idx(i, j, k);
-            const stencil::NodeK<double> K =
-                stencil::node_k(g, (const uint32_t*)D.op64.code, (const double*)D.op64.ck, D.op64.kin, D.op64.kout,
-                                D.op64.mass, e);
-            const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
-                             (K.zm * x[e - 1] + K.zp * x[e + 1]);
-            const double rv = D.rhs[e] - (K.diag() * x[e] - s);
+            double rv = D.rhs[e];
+            if (force != 2) {
+                const stencil::NodeK<double> K = stencil::node_k(g, (const uint32_t*)D.op64.code,
+                                                                 (const double*)D.op64.ck, D.op64.kin, D.op64.kout,
+                                                                 D.op64.mass, e);
+                const double s = ((K.xm * x[e - sx] + K.xp * x[e + sx]) + (K.ym * x[e - sy] + K.yp * x[e + sy])) +
+                                 (K.zm * x[e - 1] + K.zp * x[e + 1]);
+                rv -= K.diag() * x[e] - s;
+            }
             D.cr[R.at(i, j, c, m)] = (T)rv;
             v[0] += rv * rv;
         }
@@ -1672,8 +1676,9 @@ template <typename T>
 void run_restart(hipStream_t s, const Plan& pl, int init, int force)
 {
     const GateSpec gs{nullptr, 1};
-    PLAUNCH(K_RB0, 256, kb_rb_fold<T>, force);
-    PLAUNCH(K_RB0, 256, kb_rb_true_res<T>, force);
+    // init: x = 0 (both parts were just cleared): nothing to fold, and r = b
+    if (!init) PLAUNCH(K_RB0, 256, kb_rb_fold<T>, force);
+    PLAUNCH(K_RB0, 256, kb_rb_true_res<T>, init ? 2 : force);
     PLAUNCH(K_ONE, 256, kb_ru_fin<T>, init, force);
     run_vcycle<T>(s, pl, gs);
     if (pl.single) PLAUNCH(K_RB0, 256, kb_rb_dot<T>, gs);
