@@ -349,8 +349,10 @@ size_t pb_problem_bytes(const pb_problem* pb);
  * Requests are admitted first-come first-served once arrived, while at most max_resident
  * problems are resident and ctx's hbm_budget_bytes (if non-zero) is not exceeded; all
  * resident problems advance together, 16 CG iterations per batched chunk.  Requests with
- * precond = PB_PRECOND_MG run their 16 iterations as their own launches after the batched
- * ones (the results equal those of a solve of the same request alone).
+ * precond = PB_PRECOND_MG share batched multigrid launches (groups of up to
+ * 64 requests of one precision and smoothing count; one whose coarsest level is
+ * large runs its own launches), with chunks sized from each request's residual decay.  A
+ * result equals that of a solve of the same request alone, bit for bit.
  * Errors: PB_EINVAL, PB_EDEVICE. */
 int pb_server_create(pb_ctx* ctx, pb_ctx* build_ctx, int32_t max_resident, pb_server** out);
 
