@@ -962,6 +962,12 @@ hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk
     return hipGetLastError();
 }
 
+hipError_t launch_scan1(hipStream_t s, const int* in, int n, int* out)
+{
+    k_scan1<<<1, 1024, 0, s>>>(in, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals)
 {
     // in-place exclusive scans through a copy: out[i] written after in[i] is read by the

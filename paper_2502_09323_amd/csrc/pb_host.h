@@ -129,9 +129,8 @@ struct RefineData {
     int64_t* gfine = nullptr;     // their fine element index
     int64_t* gpar = nullptr;      // [4*ng] coarse parents (unused slots repeat the first)
     int32_t* gnp = nullptr;       // parent counts 1, 2 or 4
-    int64_t nr = 0;               // coarse nodes receiving rows of derived fine nodes
-    int64_t *rnode = nullptr, *rptr = nullptr, *rsrc = nullptr;
-    double* rw = nullptr;
+    int64_t nr = 0;               // coarse nodes that are parents of derived fine nodes
+    int64_t* rnode = nullptr;     // their coarse element index
     double *bc = nullptr, *rc = nullptr, *zc = nullptr, *pc = nullptr, *qc = nullptr, *dc = nullptr;
     double *bf = nullptr, *rf = nullptr, *zf = nullptr, *pf = nullptr, *qf = nullptr, *df = nullptr;
     // mixed precision: FP32 copies of K and D^-1 and the FP32 solver vectors (x: correction);

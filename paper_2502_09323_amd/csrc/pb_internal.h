@@ -124,6 +124,8 @@ hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const At
 hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk_slots,
                            int* blk_cuts, int nblk);
 hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals);
+// exclusive scan of n ints into out[0 .. n] (out[n] = total; out may be in), one block
+hipError_t launch_scan1(hipStream_t s, const int* in, int n, int* out);
 hipError_t launch_assign(hipStream_t s, const Grid& g, const uint32_t* cls, uint32_t* code,
                          const int* blk_slots, const int* blk_cuts, int* cutbase, int64_t* cutkey);
 hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at,

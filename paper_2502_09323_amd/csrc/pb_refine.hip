@@ -357,18 +357,219 @@ __global__ void __launch_bounds__(256) k_apply(Grid g, const T* __restrict__ K, 
                        (kzm * p[e - 1] + kzp * p[e + 1]));
 }
 
-// the rows of the derived fine nodes go to their coarse nodes (one thread per coarse node)
+// the rows of the derived fine nodes go to their coarse parents: one thread per coarse node
+// that is a parent (rnode), gathering the derived fine nodes among the 27 fine nodes around it
+// in fine-lattice order; the derived node at 2C + d is a child of C with weight 1 / 2^(number
+// of nonzero components of d)
 template <typename T>
-__global__ void __launch_bounds__(256) k_restrict(int64_t nr, const int64_t* __restrict__ rnode,
-                                                  const int64_t* __restrict__ rptr, const int64_t* __restrict__ rsrc,
-                                                  const double* __restrict__ rw, const int64_t* __restrict__ gfine,
-                                                  const T* __restrict__ vf, T* __restrict__ vc, const CGState* st)
+__global__ void __launch_bounds__(256) k_restrict(int64_t nr, const int64_t* __restrict__ rnode, Grid gc, Grid gf,
+                                                  const uint8_t* __restrict__ rolef, const T* __restrict__ vf,
+                                                  T* __restrict__ vc, const CGState* st)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= nr || (st && st->status != 0)) return;
+    const int64_t ec = rnode[t];
+    int i, j, k;
+    decode(gc, ec, i, j, k);
+    const int F[3] = {2 * i - gf.off[0], 2 * j - gf.off[1], 2 * k - gf.off[2]};
     T s = (T)0;
-    for (int64_t u = rptr[t]; u < rptr[t + 1]; ++u) s += (T)rw[u] * vf[gfine[rsrc[u]]];
-    vc[rnode[t]] += s;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                const int f0 = F[0] + a, f1 = F[1] + b, f2 = F[2] + c;
+                if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= gf.nx || f1 >= gf.ny || f2 >= gf.nz) continue;
+                const int64_t ef = gf.idx(f0, f1, f2);
+                if (rolef[ef] < 2) continue;
+                const int np = 1 << ((a != 0) + (b != 0) + (c != 0));
+                s += (T)(1.0 / np) * vf[ef];
+            }
+    vc[ec] += s;
+}
+
+// ---- the lists of derived fine nodes and of their coarse parents, built on the device -------
+
+// whether fine element e is a derived node (role 2 or 3)
+__device__ __forceinline__ bool derived_at(const Grid& gf, const uint8_t* rolef, int64_t e)
+{
+    return e < gf.N && rolef[e] >= 2;
+}
+
+// whether coarse element e is the parent of a derived fine node (one among the 27 around it)
+__device__ __forceinline__ bool parent_at(const Grid& gc, const Grid& gf, const uint8_t* rolef, int64_t e)
+{
+    if (e >= gc.N) return false;
+    int i, j, k;
+    decode(gc, e, i, j, k);
+    if (k < 0 || k >= gc.nz) return false;
+    const int F[3] = {2 * i - gf.off[0], 2 * j - gf.off[1], 2 * k - gf.off[2]};
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                const int f0 = F[0] + a, f1 = F[1] + b, f2 = F[2] + c;
+                if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= gf.nx || f1 >= gf.ny || f2 >= gf.nz) continue;
+                if (rolef[gf.idx(f0, f1, f2)] >= 2) return true;
+            }
+    return false;
+}
+
+// rank of this thread's flag among the flagged threads of its block, in thread order (every
+// thread of the block calls it)
+__device__ __forceinline__ int block_rank(bool f, int* wsum)
+{
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int base = 0;
+    for (int q = 0; q < w; ++q) base += wsum[q];
+    return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+
+// flagged elements per block of 256 (mode 0: derived fine nodes over the fine elements; 1:
+// parents over the coarse elements)
+__global__ void __launch_bounds__(256) k_list_count(int mode, Grid gc, Grid gf, const uint8_t* __restrict__ rolef,
+                                                    int* __restrict__ cnt)
+{
+    __shared__ int wsum[4];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool f = mode == 0 ? derived_at(gf, rolef, e) : parent_at(gc, gf, rolef, e);
+    const int r = block_rank(f, wsum);
+    (void)r;
+    if (threadIdx.x == 0) cnt[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// the lists in element order from the scanned block counts (start): mode 0 the derived fine
+// nodes (gfine), their parent counts (gnp) and their coarse parents (gpar, from the node's
+// lattice coordinates: along an odd axis the two coarse nodes around it, along an even one
+// the coarse node it lies on, in (a, b, c) order, unused slots repeating the first); a parent
+// that is not a coarse unknown sets *bad.  Mode 1: the parents (rnode).
+__global__ void __launch_bounds__(256) k_list_assign(int mode, Grid gc, Grid gf, const uint8_t* __restrict__ rolef,
+                                                     const uint8_t* __restrict__ rolec, const int* __restrict__ start,
+                                                     int64_t* gfine, int64_t* gpar, int32_t* gnp, int64_t* rnode,
+                                                     int* bad)
+{
+    __shared__ int wsum[4];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool f = mode == 0 ? derived_at(gf, rolef, e) : parent_at(gc, gf, rolef, e);
+    const int64_t pos = (int64_t)start[blockIdx.x] + block_rank(f, wsum);
+    if (!f) return;
+    if (mode == 1) {
+        rnode[pos] = e;
+        return;
+    }
+    int i, j, k;
+    decode(gf, e, i, j, k);
+    const int F[3] = {i + gf.off[0], j + gf.off[1], k + gf.off[2]};   // global fine lattice
+    int lo[3], hi[3], np = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (F[d] & 1) {
+            lo[d] = (F[d] - 1) / 2;
+            hi[d] = (F[d] + 1) / 2;
+            np *= 2;
+        } else {
+            lo[d] = hi[d] = F[d] / 2;
+        }
+    }
+    if (np > 4) atomicOr(bad, 2);   // not a node of a coarse edge or face
+    gfine[pos] = e;
+    gnp[pos] = np;
+    int u = 0;
+    int64_t first = -1;
+    for (int a = lo[0]; a <= hi[0]; ++a)
+        for (int b = lo[1]; b <= hi[1]; ++b)
+            for (int c = lo[2]; c <= hi[2]; ++c) {
+                const int64_t pe = gc.idx(a, b, c);
+                if (rolec[pe] != 1) atomicOr(bad, 1);
+                if (first < 0) first = pe;
+                if (u < 4) gpar[4 * pos + u] = pe;
+                ++u;
+            }
+    for (; u < 4; ++u) gpar[4 * pos + u] = first;
+}
+
+// counters: [0] coarse unknowns, [1] fine unknowns, [2] hanging nodes
+__global__ void __launch_bounds__(256) k_role_count(int64_t Nc, const uint8_t* __restrict__ rolec, int64_t Nf,
+                                                    const uint8_t* __restrict__ rolef,
+                                                    unsigned long long* __restrict__ out)
+{
+    unsigned long long v[3] = {0, 0, 0};
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < Nc; e += stride) v[0] += rolec[e] == 1;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < Nf; e += stride) {
+        v[1] += rolef[e] == 1;
+        v[2] += rolef[e] == 3;
+    }
+    for (int q = 0; q < 3; ++q) {
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+        if ((threadIdx.x & 63) == 0 && v[q]) atomicAdd(out + q, v[q]);
+    }
+}
+
+// refined coarse cells: out[3] counts them; bit 1 of out[4]: one touches the box boundary
+// layer, bit 2: one lies outside the fine sub-lattice's cells [cl + 1, ch - 1)
+__global__ void __launch_bounds__(256) k_cell_checks(Cells cl, int l0, int l1, int l2, int h0, int h1, int h2,
+                                                     unsigned long long* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)cl.nc[0] * cl.nc[1] * cl.nc[2];
+    bool ref = false;
+    unsigned flags = 0;
+    if (t < n && cl.f[t]) {
+        ref = true;
+        const int c[3] = {(int)(t / ((int64_t)cl.nc[1] * cl.nc[2])), (int)((t / cl.nc[2]) % cl.nc[1]),
+                          (int)(t % cl.nc[2])};
+        const int lo[3] = {l0, l1, l2}, hi[3] = {h0, h1, h2};
+        for (int d = 0; d < 3; ++d) {
+            if (c[d] == 0 || c[d] == cl.nc[d] - 1) flags |= 1u;
+            if (c[d] < lo[d] + 1 || c[d] >= hi[d] - 1) flags |= 2u;
+        }
+    }
+    const unsigned long long m = __ballot(ref);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(out + 3, (unsigned long long)__popcll(m));
+    if (flags) atomicOr(out + 4, (unsigned long long)flags);
+}
+
+// charge loads accumulated on the host (unique elements): dst[idx[t]] = val[t]
+__global__ void __launch_bounds__(256) k_scatter(int64_t n, const int64_t* __restrict__ idx,
+                                                 const double* __restrict__ val, double* __restrict__ dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) dst[idx[t]] = val[t];
+}
+
+// the loads of the derived fine nodes go to their coarse parents: each parent adds v / (its
+// child's parent count) of every child with a nonzero load, in fine-lattice order
+__global__ void __launch_bounds__(256) k_fold_load(int64_t nr, const int64_t* __restrict__ rnode, Grid gc, Grid gf,
+                                                   const uint8_t* __restrict__ rolef, const double* __restrict__ bf,
+                                                   double* __restrict__ bc)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nr) return;
+    const int64_t ec = rnode[t];
+    int i, j, k;
+    decode(gc, ec, i, j, k);
+    const int F[3] = {2 * i - gf.off[0], 2 * j - gf.off[1], 2 * k - gf.off[2]};
+    double h = bc[ec];
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                const int f0 = F[0] + a, f1 = F[1] + b, f2 = F[2] + c;
+                if (f0 < 0 || f1 < 0 || f2 < 0 || f0 >= gf.nx || f1 >= gf.ny || f2 >= gf.nz) continue;
+                const int64_t ef = gf.idx(f0, f1, f2);
+                if (rolef[ef] < 2) continue;
+                const double v = bf[ef];
+                if (v == 0.0) continue;
+                h += v / (double)(1 << ((a != 0) + (b != 0) + (c != 0)));
+            }
+    bc[ec] = h;
+}
+
+// ... and leave the derived fine nodes' own loads at zero
+__global__ void __launch_bounds__(256) k_zero_derived(int64_t ng, const int64_t* __restrict__ gfine,
+                                                      double* __restrict__ bf)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < ng) bf[gfine[t]] = 0.0;
 }
 
 __device__ __forceinline__ void bsum(double* v, int nv, double* sh)
@@ -884,28 +1085,28 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
                                                                        nb[2], bf);
     k_cells_from_bricks<<<nblk(ncell, 256), 256, 0, s>>>(bf, R->nc[0], R->nc[1], R->nc[2], B, nb[1], nb[2], R->cells);
     RCHK(hipGetLastError());
+    // the refined cells: counted and checked on the device; their flags come to the host for
+    // the charge load below (whether an atom's coarse cell is refined)
+    unsigned long long* cnt64 = (unsigned long long*)pb->mem.get(sizeof(unsigned long long) * 8);
+    int* bad = (int*)pb->mem.get(sizeof(int) * 2);
+    if (!cnt64 || !bad) return pbi_fail(PB_ENOMEM, "refinement counters");
+    RCHK(launch_fill(s, cnt64, sizeof(unsigned long long) * 8));
+    RCHK(launch_fill(s, bad, sizeof(int) * 2));
+    Cells cells{R->cells, {R->nc[0], R->nc[1], R->nc[2]}};
+    k_cell_checks<<<nblk(ncell, 256), 256, 0, s>>>(cells, cl[0], cl[1], cl[2], ch[0], ch[1], ch[2], cnt64);
+    RCHK(hipGetLastError());
     std::vector<uint8_t> hcell((size_t)ncell);
+    unsigned long long hc[8] = {};
     RCHK(hipMemcpyAsync(hcell.data(), R->cells, (size_t)ncell, hipMemcpyDeviceToHost, s));
+    RCHK(hipMemcpyAsync(hc, cnt64, sizeof hc, hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
     pb->mem.put(flag);
     pb->mem.put(bf);
-    R->n_refined = 0;
-    for (int i = 0; i < R->nc[0]; ++i)
-        for (int j = 0; j < R->nc[1]; ++j)
-            for (int k = 0; k < R->nc[2]; ++k) {
-                if (!hcell[((size_t)i * R->nc[1] + j) * R->nc[2] + k]) continue;
-                ++R->n_refined;
-                const int c[3] = {i, j, k};
-                for (int d = 0; d < 3; ++d) {
-                    if (c[d] == 0 || c[d] == R->nc[d] - 1)
-                        return pbi_fail(PB_EINVAL, "refined cells touch the box boundary layer");
-                    if (c[d] < cl[d] + 1 || c[d] >= ch[d] - 1)
-                        return pbi_fail(PB_EINVAL, "refined cell outside the fine sub-lattice");
-                }
-            }
+    if (hc[4] & 1u) return pbi_fail(PB_EINVAL, "refined cells touch the box boundary layer");
+    if (hc[4] & 2u) return pbi_fail(PB_EINVAL, "refined cell outside the fine sub-lattice");
+    R->n_refined = (int64_t)hc[3];
 
     // coefficients and roles
-    Cells cells{R->cells, {R->nc[0], R->nc[1], R->nc[2]}};
     R->Kc = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)gc.N);
     R->Kf = (double*)pb->mem.get(sizeof(double) * 4 * (size_t)gf.N);
     R->rolec = (uint8_t*)pb->mem.get((size_t)gc.N);
@@ -914,96 +1115,49 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
     k_coarse_coef<<<nblk(gc.N, 256), 256, 0, s>>>(gc, cells, pb->code, pb->cf, R->Kc, R->rolec);
     k_fine_coef<<<nblk(gf.N, 256), 256, 0, s>>>(gf, gc, cells, fp->code, fp->ck64, fp->cf, R->rolec, R->Kf, R->rolef);
     RCHK(hipGetLastError());
-    std::vector<uint8_t> hrolef((size_t)gf.N), hrolec((size_t)gc.N);
-    RCHK(hipMemcpyAsync(hrolef.data(), R->rolef, (size_t)gf.N, hipMemcpyDeviceToHost, s));
-    RCHK(hipMemcpyAsync(hrolec.data(), R->rolec, (size_t)gc.N, hipMemcpyDeviceToHost, s));
-    RCHK(hipStreamSynchronize(s));
 
-    // derived fine nodes and their coarse parents; the gather lists of the coarse parents
-    std::vector<int64_t> gfine, gpar;
-    std::vector<int32_t> gnp;
-    R->nunk_c = R->nunk_f = R->nhang = 0;
-    for (int64_t e = 0; e < gc.N; ++e) R->nunk_c += hrolec[(size_t)e] == 1;
-    for (int i = 0; i < gf.nx; ++i)
-        for (int j = 0; j < gf.ny; ++j)
-            for (int k = 0; k < gf.nz; ++k) {
-                const int64_t e = gf.idx(i, j, k);
-                const uint8_t r = hrolef[(size_t)e];
-                if (r == 1) ++R->nunk_f;
-                if (r < 2) continue;
-                const int F[3] = {i + off[0], j + off[1], k + off[2]};
-                int lo[3], hi[3];
-                int cnt = 1;
-                for (int d = 0; d < 3; ++d) {
-                    if (F[d] & 1) {
-                        lo[d] = (F[d] - 1) / 2;
-                        hi[d] = (F[d] + 1) / 2;
-                        cnt *= 2;
-                    } else {
-                        lo[d] = hi[d] = F[d] / 2;
-                    }
-                }
-                if (r == 3) ++R->nhang;
-                gfine.push_back(e);
-                gnp.push_back(cnt);
-                int u = 0;
-                int64_t first = -1;
-                for (int a = lo[0]; a <= hi[0]; ++a)
-                    for (int b = lo[1]; b <= hi[1]; ++b)
-                        for (int c = lo[2]; c <= hi[2]; ++c) {
-                            const int64_t pe = gc.idx(a, b, c);
-                            if (hrolec[(size_t)pe] != 1) return pbi_fail(PB_EINVAL, "a derived fine node has a parent that is not an unknown");
-                            if (first < 0) first = pe;
-                            gpar.push_back(pe);
-                            ++u;
-                        }
-                for (; u < 4; ++u) gpar.push_back(first);
-            }
-    R->ng = (int64_t)gfine.size();
-    // gather lists: for each coarse parent, (derived entry, weight) in entry order
-    std::vector<std::vector<std::pair<int64_t, double>>> tmp;
-    std::vector<int64_t> rnode;
-    {
-        std::vector<int64_t> slot((size_t)gc.N, -1);
-        for (int64_t t = 0; t < R->ng; ++t)
-            for (int u = 0; u < gnp[(size_t)t]; ++u) {
-                const int64_t pe = gpar[4 * (size_t)t + u];
-                if (slot[(size_t)pe] < 0) {
-                    slot[(size_t)pe] = (int64_t)rnode.size();
-                    rnode.push_back(pe);
-                    tmp.emplace_back();
-                }
-                tmp[(size_t)slot[(size_t)pe]].emplace_back(t, 1.0 / gnp[(size_t)t]);
-            }
-    }
-    R->nr = (int64_t)rnode.size();
-    std::vector<int64_t> rptr(1, 0), rsrc;
-    std::vector<double> rw;
-    for (auto& v : tmp) {
-        for (auto& pr : v) {
-            rsrc.push_back(pr.first);
-            rw.push_back(pr.second);
-        }
-        rptr.push_back((int64_t)rsrc.size());
-    }
-    auto up = [&](void** dst, const void* src, size_t bytes) -> int {
-        *dst = pb->mem.get(std::max<size_t>(bytes, 8));
-        if (!*dst) return pbi_fail(PB_ENOMEM, "refinement lists");
-        if (bytes && hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-            return pbi_fail(PB_EDEVICE, "refinement lists upload");
-        return PB_OK;
-    };
-    if ((rc = up((void**)&R->gfine, gfine.data(), sizeof(int64_t) * gfine.size()))) return rc;
-    if ((rc = up((void**)&R->gpar, gpar.data(), sizeof(int64_t) * gpar.size()))) return rc;
-    if ((rc = up((void**)&R->gnp, gnp.data(), sizeof(int32_t) * gnp.size()))) return rc;
-    if ((rc = up((void**)&R->rnode, rnode.data(), sizeof(int64_t) * rnode.size()))) return rc;
-    if ((rc = up((void**)&R->rptr, rptr.data(), sizeof(int64_t) * rptr.size()))) return rc;
-    if ((rc = up((void**)&R->rsrc, rsrc.data(), sizeof(int64_t) * rsrc.size()))) return rc;
-    if ((rc = up((void**)&R->rw, rw.data(), sizeof(double) * rw.size()))) return rc;
+    // the derived fine nodes (roles 2 and 3) with their coarse parents, and the coarse nodes
+    // that are parents, as ordered compactions (block counts, a scan, then the lists), and the
+    // role counts
+    const unsigned nbD = nblk(gf.N, 256), nbP = nblk(gc.N, 256);
+    int* startD = (int*)pb->mem.get(sizeof(int) * ((size_t)nbD + 1));
+    int* startP = (int*)pb->mem.get(sizeof(int) * ((size_t)nbP + 1));
+    if (!startD || !startP) return pbi_fail(PB_ENOMEM, "refinement lists");
+    k_list_count<<<nbD, 256, 0, s>>>(0, gc, gf, R->rolef, startD);
+    k_list_count<<<nbP, 256, 0, s>>>(1, gc, gf, R->rolef, startP);
+    RCHK(launch_scan1(s, startD, (int)nbD, startD));
+    RCHK(launch_scan1(s, startP, (int)nbP, startP));
+    k_role_count<<<std::min<unsigned>(1024, nblk(std::max(gc.N, gf.N), 256)), 256, 0, s>>>(gc.N, R->rolec, gf.N,
+                                                                                            R->rolef, cnt64);
+    RCHK(hipGetLastError());
+    int tot[2] = {0, 0};
+    RCHK(hipMemcpyAsync(&tot[0], startD + nbD, sizeof(int), hipMemcpyDeviceToHost, s));
+    RCHK(hipMemcpyAsync(&tot[1], startP + nbP, sizeof(int), hipMemcpyDeviceToHost, s));
+    RCHK(hipMemcpyAsync(hc, cnt64, sizeof hc, hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    R->nunk_c = (int64_t)hc[0];
+    R->nunk_f = (int64_t)hc[1];
+    R->nhang = (int64_t)hc[2];
+    R->ng = tot[0];
+    R->nr = tot[1];
+    R->gfine = (int64_t*)pb->mem.get(sizeof(int64_t) * (size_t)std::max<int64_t>(R->ng, 1));
+    R->gpar = (int64_t*)pb->mem.get(sizeof(int64_t) * 4 * (size_t)std::max<int64_t>(R->ng, 1));
+    R->gnp = (int32_t*)pb->mem.get(sizeof(int32_t) * (size_t)std::max<int64_t>(R->ng, 1));
+    R->rnode = (int64_t*)pb->mem.get(sizeof(int64_t) * (size_t)std::max<int64_t>(R->nr, 1));
+    if (!R->gfine || !R->gpar || !R->gnp || !R->rnode) return pbi_fail(PB_ENOMEM, "refinement lists");
+    if (R->ng)
+        k_list_assign<<<nbD, 256, 0, s>>>(0, gc, gf, R->rolef, R->rolec, startD, R->gfine, R->gpar, R->gnp, nullptr,
+                                          bad);
+    if (R->nr)
+        k_list_assign<<<nbP, 256, 0, s>>>(1, gc, gf, R->rolef, R->rolec, startP, nullptr, nullptr, nullptr, R->rnode,
+                                          bad);
+    RCHK(hipGetLastError());
 
     // load: each charge on the corners of the cell that holds it (the fine cell inside a
-    // refined coarse cell), 4 pi q trilinear; derived fine entries go to their parents
-    std::vector<double> hbc((size_t)gc.N, 0.0), hbf((size_t)gf.N, 0.0);
+    // refined coarse cell), 4 pi q trilinear, summed per node in atom order on the host; the
+    // sums are scattered into the cleared vectors below, and the derived fine entries then go to
+    // their parents
+    std::vector<std::pair<int64_t, double>> depc, depf;
     for (int64_t a = 0; a < na; ++a) {
         int c[3];
         for (int d = 0; d < 3; ++d) {
@@ -1034,17 +1188,31 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
                     const double w = (x ? t[0] : 1.0 - t[0]) * (y ? t[1] : 1.0 - t[1]) * (z ? t[2] : 1.0 - t[2]);
                     const double v = 4.0 * kPi * chg[a] * w;
                     if (fine)
-                        hbf[(size_t)gf.idx(base[0] + x, base[1] + y, base[2] + z)] += v;
+                        depf.emplace_back(gf.idx(base[0] + x, base[1] + y, base[2] + z), v);
                     else
-                        hbc[(size_t)gc.idx(base[0] + x, base[1] + y, base[2] + z)] += v;
+                        depc.emplace_back(gc.idx(base[0] + x, base[1] + y, base[2] + z), v);
                 }
     }
-    for (int64_t t = 0; t < R->ng; ++t) {
-        const double v = hbf[(size_t)gfine[(size_t)t]];
-        if (v == 0.0) continue;
-        for (int u = 0; u < gnp[(size_t)t]; ++u) hbc[(size_t)gpar[4 * (size_t)t + u]] += v / gnp[(size_t)t];
-        hbf[(size_t)gfine[(size_t)t]] = 0.0;
-    }
+    // per element, 0 + the contributions in atom order (a stable sort keeps that order)
+    auto sum_per_node = [](std::vector<std::pair<int64_t, double>>& d, std::vector<int64_t>& idx,
+                           std::vector<double>& val) {
+        std::stable_sort(d.begin(), d.end(),
+                         [](const std::pair<int64_t, double>& x, const std::pair<int64_t, double>& y) {
+                             return x.first < y.first;
+                         });
+        for (size_t u = 0; u < d.size();) {
+            double acc = 0.0;
+            size_t w = u;
+            for (; w < d.size() && d[w].first == d[u].first; ++w) acc += d[w].second;
+            idx.push_back(d[u].first);
+            val.push_back(acc);
+            u = w;
+        }
+    };
+    std::vector<int64_t> ldc_i, ldf_i;
+    std::vector<double> ldc_v, ldf_v;
+    sum_per_node(depc, ldc_i, ldc_v);
+    sum_per_node(depf, ldf_i, ldf_v);
     // solver vectors: b, r, z, p, q, D^-1 of each grid (x: the problems' own x)
     const size_t Nc = (size_t)gc.N, Nf = (size_t)gf.N;
     double** vc[6] = {&R->bc, &R->rc, &R->zc, &R->pc, &R->qc, &R->dc};
@@ -1056,8 +1224,24 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
         RCHK(launch_fill(s, *vc[v], sizeof(double) * Nc));
         RCHK(launch_fill(s, *vf[v], sizeof(double) * Nf));
     }
-    RCHK(hipMemcpyAsync(R->bc, hbc.data(), sizeof(double) * Nc, hipMemcpyHostToDevice, s));
-    RCHK(hipMemcpyAsync(R->bf, hbf.data(), sizeof(double) * Nf, hipMemcpyHostToDevice, s));
+    std::vector<void*> tmp_dev;
+    auto scatter = [&](const std::vector<int64_t>& idx, const std::vector<double>& val, double* dst) -> int {
+        if (idx.empty()) return PB_OK;
+        int64_t* di = (int64_t*)pb->mem.get(sizeof(int64_t) * idx.size());
+        double* dv = (double*)pb->mem.get(sizeof(double) * val.size());
+        if (!di || !dv) return pbi_fail(PB_ENOMEM, "refined charge load");
+        tmp_dev.push_back(di);
+        tmp_dev.push_back(dv);
+        RCHK(hipMemcpyAsync(di, idx.data(), sizeof(int64_t) * idx.size(), hipMemcpyHostToDevice, s));
+        RCHK(hipMemcpyAsync(dv, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, s));
+        k_scatter<<<nblk((int64_t)idx.size(), 256), 256, 0, s>>>((int64_t)idx.size(), di, dv, dst);
+        RCHK(hipGetLastError());
+        return PB_OK;
+    };
+    if ((rc = scatter(ldc_i, ldc_v, R->bc))) return rc;
+    if ((rc = scatter(ldf_i, ldf_v, R->bf))) return rc;
+    if (R->nr) k_fold_load<<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, gc, gf, R->rolef, R->bf, R->bc);
+    if (R->ng) k_zero_derived<<<nblk(R->ng, 256), 256, 0, s>>>(R->ng, R->gfine, R->bf);
     k_lift<<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, pb->code, pb->gb, R->bc);
     k_diag<<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, R->dc);
     k_diag<<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, R->df);
@@ -1089,7 +1273,16 @@ int pbi_refine_build(pb_problem* pb, const double* xyz, const double* rad, const
         k_to_f32<<<nblk(gf.N, 256), 256, 0, s>>>(gf.N, R->df, R->df32);
         RCHK(hipGetLastError());
     }
+    int hbad[2] = {0, 0};
+    RCHK(hipMemcpyAsync(hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s));
     RCHK(hipStreamSynchronize(s));
+    for (void* q : tmp_dev) pb->mem.put(q);
+    pb->mem.put(startD);
+    pb->mem.put(startP);
+    pb->mem.put(cnt64);
+    pb->mem.put(bad);
+    if (hbad[0] & 1) return pbi_fail(PB_EINVAL, "a derived fine node has a parent that is not an unknown");
+    if (hbad[0] & 2) return pbi_fail(PB_EINVAL, "a derived fine node is not on a coarse edge or face");
     return PB_OK;
 }
 
@@ -1112,7 +1305,7 @@ void launch_apply_comp(hipStream_t s, const RefineData* R, const Grid& gc, const
     k_apply<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc, Kc, R->rolec, vc, wc, st);
     k_apply<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf, Kf, R->rolef, vf, wf, st);
     if (R->nr)
-        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, wf, wc,
+        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, gc, gf, R->rolef, wf, wc,
                                                        st);
 }
 
@@ -1148,7 +1341,7 @@ void launch_iteration(hipStream_t s, const RefineData* R, const Grid& gc, const 
     k_apply<T><<<nblk(gc.N, 256), 256, 0, s>>>(gc, c.K, R->rolec, c.p, c.q, st);
     k_apply<T><<<nblk(gf.N, 256), 256, 0, s>>>(gf, f.K, R->rolef, f.p, f.q, st);
     if (R->nr)
-        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, f.q, c.q,
+        k_restrict<T><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, gc, gf, R->rolef, f.q, c.q,
                                                        st);
     k_dot<T><<<nb, 256, 0, s>>>(sp, c.p, c.q, f.p, f.q, R->part, st);
     k_alpha<<<1, 256, 0, s>>>(R->part, nb, st);
@@ -1176,7 +1369,7 @@ void launch_reliable_update(hipStream_t s, pb_problem* pb, const Split& sp, int 
     k_apply<double><<<nblk(gc.N, 256), 256, 0, s>>>(gc, R->Kc, R->rolec, pb->x, R->qc, nullptr);
     k_apply<double><<<nblk(gf.N, 256), 256, 0, s>>>(gf, R->Kf, R->rolef, fp->x, R->qf, nullptr);
     if (R->nr)
-        k_restrict<double><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, R->rptr, R->rsrc, R->rw, R->gfine, R->qf,
+        k_restrict<double><<<nblk(R->nr, 256), 256, 0, s>>>(R->nr, R->rnode, gc, gf, R->rolef, R->qf,
                                                             R->qc, nullptr);
     k_true_res<<<nb, 256, 0, s>>>(sp, R->bc, R->qc, R->rc, R->bf, R->qf, R->rf, R->part + 2 * nb);
     k_replace<<<nb, 256, 0, s>>>(sp, R->rc, R->rc32, R->zc32, R->dc32, R->rf, R->rf32, R->zf32, R->df32, R->part, nb);
