@@ -556,17 +556,24 @@ def bench_refined(args, B, torch):
     nodes = float(nc + nf)
     t_iter = mx["t_solve"] / max(mx["iters"], 1.0)
     ach = nodes * REFINED_ITER_BYTES_FP32 / t_iter / 1e9
-    lat = mx["lat"]
+    # value: the mixed solve with the two-level preconditioner (the fastest form); the
+    # Jacobi-preconditioned mixed solve beside it, whose iteration gives the roofline
+    lat = tlm["lat"]
     out = {
         "metric": METRIC, "value": round(len(lat) / sum(lat), 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * float(np.mean(lat)), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 CG + f64 reliable updates/energy", "data": "synthetic",
-        "config": {"workload": desc, "n_atoms": mol.n, "rtol": RTOL, "reliable_update_factor": DELTA,
+        "config": {"workload": desc, "n_atoms": mol.n, "rtol": RTOL, "reliable_update_factor": DELTA_MG,
+                   "preconditioner": "damped Jacobi + coarse-grid multigrid V-cycle (symmetric two-level)",
                    "unknowns": int(nunk), "refined_cells": int(info["refined_cells"]),
                    "hanging_nodes": int(info["hanging_nodes"]), "fine_lattice": list(info["fine_n"])},
-        "iters": mx["iters"], "reliable_updates": mx["st"]["outer_iters"], "t_solve_ms": round(1e3 * mx["t_solve"], 2),
-        "t_build_ms": round(1e3 * mx["t_build"], 2), "energy_relerr_vs_fp64": mx["err"],
+        "iters": tlm["iters"], "reliable_updates": tlm["st"]["outer_iters"],
+        "t_solve_ms": round(1e3 * tlm["t_solve"], 2), "t_build_ms": round(1e3 * tlm["t_build"], 2),
+        "energy_relerr_vs_fp64": tlm["err"],
+        "jacobi_mixed": {"solves_per_s": round(len(mx["lat"]) / sum(mx["lat"]), 4), "iters": mx["iters"],
+                         "reliable_updates": mx["st"]["outer_iters"], "reliable_update_factor": DELTA,
+                         "t_solve_ms": round(1e3 * mx["t_solve"], 2), "energy_relerr_vs_fp64": mx["err"]},
         "pcg_gnode_iter_per_s": {"mixed": round(nunk * mx["iters"] / mx["t_solve"] / 1e9, 3),
                                  "fp64": round(nunk * p64["iters"] / p64["t_solve"] / 1e9, 3)},
         "fp64_plain": {"solves_per_s": round(len(p64["lat"]) / sum(p64["lat"]), 4), "iters": p64["iters"],
@@ -575,14 +582,11 @@ def bench_refined(args, B, torch):
         "fp64_two_level": {"solves_per_s": round(len(tl["lat"]) / sum(tl["lat"]), 4), "iters": tl["iters"],
                            "t_solve_ms": round(1e3 * tl["t_solve"], 2), "energy_relerr_vs_fp64": tl["err"],
                            "preconditioner": "damped Jacobi + coarse-grid multigrid V-cycle (symmetric two-level)"},
-        "mixed_two_level": {"solves_per_s": round(len(tlm["lat"]) / sum(tlm["lat"]), 4), "iters": tlm["iters"],
-                            "reliable_updates": tlm["st"]["outer_iters"], "t_solve_ms": round(1e3 * tlm["t_solve"], 2),
-                            "energy_relerr_vs_fp64": tlm["err"]},
-        "energies_kT": {k: mx["en"][k] for k in ("e_pol", "e_ion", "e_coul")},
+        "energies_kT": {k: tlm["en"][k] for k in ("e_pol", "e_ion", "e_coul")},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "composite CG iteration in FP32 (all kernels of one iteration, reliable updates "
-                               "included)",
+                     "kernel": "composite CG iteration in FP32 of the Jacobi-preconditioned mixed solve (all "
+                               "kernels of one iteration, reliable updates included)",
                      "bytes_per_launch": round(nodes * REFINED_ITER_BYTES_FP32), "avg_launch_ms": round(1e3 * t_iter, 4)},
         "stream_copy_GBs": round(ctx.stream_copy_gbps(1 << 30, 20), 1),
         "cpu_baseline": None,
@@ -876,24 +880,28 @@ def bench_derefine(args, B, torch):
     v_tm, (st_tm, en_tm, _) = run(replace(g_dr, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA_MG, precond=I.MG))
     v_dh, (st_dh, en_dh, _) = run(replace(g_dh, precision=I.MIXED, rtol=RTOL, inner_rtol=DELTA, precond=I.MG))
     nunk = info["unknowns_coarse"] + info["unknowns_fine"]
+    # value: the mixed solve with the two-level preconditioner (the fastest form), the
+    # Jacobi-preconditioned mixed and the two-level FP64 solves beside it
     out = {
-        "metric": METRIC, "value": round(v_dr, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 / v_dr, 2), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": round(v_tm, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 / v_tm, 2), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 CG + f64 reliable updates/energy", "data": "synthetic",
         "config": {"workload": "2000-atom molecule, null Dirichlet values on a 160 A box, 0.5 A cells within 2 A of the "
                                "solute's extent (4^3-cell bricks), 1 A cells beyond (one de-refinement level)",
+                   "preconditioner": "damped Jacobi + coarse-grid multigrid V-cycle (symmetric two-level)",
+                   "reliable_update_factor": DELTA_MG,
                    "unknowns": int(nunk), "refined_cells": int(info["refined_cells"]),
                    "hanging_nodes": int(info["hanging_nodes"]), "fine_lattice": list(info["fine_n"]), "rtol": RTOL},
-        "iters": st["iters"],
+        "iters": st_tm["iters"],
         "fp64_two_level": {"solves_per_s": round(v_tl, 3), "iters": st_tl["iters"],
-                           "energy_relerr_vs_mixed": max(abs(en_tl[k] / en[k] - 1.0) for k in ("e_pol", "e_ion"))},
-        "mixed_two_level": {"solves_per_s": round(v_tm, 3), "iters": st_tm["iters"],
-                            "energy_relerr_vs_mixed": max(abs(en_tm[k] / en[k] - 1.0) for k in ("e_pol", "e_ion"))},
-        "energies_kT": {k: en[k] for k in ("e_pol", "e_ion", "e_coul")},
+                           "energy_relerr_vs_mixed": max(abs(en_tl[k] / en_tm[k] - 1.0) for k in ("e_pol", "e_ion"))},
+        "jacobi_mixed": {"solves_per_s": round(v_dr, 3), "iters": st["iters"], "reliable_update_factor": DELTA,
+                         "energy_relerr_vs_mixed": max(abs(en[k] / en_tm[k] - 1.0) for k in ("e_pol", "e_ion"))},
+        "energies_kT": {k: en_tm[k] for k in ("e_pol", "e_ion", "e_coul")},
         "vs_tight_uniform_debye_hueckel": {
             "grid": "161^3 at 0.5 A (80 A box), Debye-Hueckel box values, FP64 rtol 1e-10",
-            "e_pol_relerr": abs(en["e_pol"] / ref_dh["e_pol"] - 1.0),
-            "e_ion_relerr": abs(en["e_ion"] / ref_dh["e_ion"] - 1.0),
+            "e_pol_relerr": abs(en_tm["e_pol"] / ref_dh["e_pol"] - 1.0),
+            "e_ion_relerr": abs(en_tm["e_ion"] / ref_dh["e_ion"] - 1.0),
             "uniform_mixed_multigrid_solves_per_s": round(v_dh, 3)},
         "roofline": None,
         "stream_copy_GBs": round(ctx.stream_copy_gbps(1 << 30, 20), 1),
