@@ -315,6 +315,13 @@ __device__ __forceinline__ T ldf(const GMEM T* base, uint32_t e)
 {
     return *(const GMEM T*)((const GMEM char*)base + e * (uint32_t)sizeof(T));
 }
+// the same as a non-temporal load: for data a pass reads once, so that it does not displace
+// the lines of the vectors that neighbouring rows and planes read again
+template <typename T>
+__device__ __forceinline__ T ldf_nt(const GMEM T* base, uint32_t e)
+{
+    return __builtin_nontemporal_load((const GMEM T*)((const GMEM char*)base + e * (uint32_t)sizeof(T)));
+}
 template <typename T>
 __device__ __forceinline__ GMEM T& stf(GMEM T* base, uint32_t e)
 {
@@ -374,7 +381,9 @@ __device__ __forceinline__ stencil::NodeK<T> rb_k(const OpRB<T>& op, const GMEM 
 // NC colours per plane; C_RB_UNCUT where a slot has no node), then takes one of two
 // branch-free bodies for the whole wave: the uncut one where every node of the wave carries
 // C_RB_UNCUT, else the table one.  With no branch on loaded data inside the body, the loads of
-// all planes can be in flight together.
+// all planes can be in flight together.  The one-colour passes load these codes
+// non-temporal (385^3: 3-5 % less time); the operator pass, which reads neighbours' codes
+// too, keeps them cached.
 template <int NC>
 __device__ __forceinline__ bool rb_codes(const VB& vb, const RB& R, const RBFrame& F, const GMEM uint32_t* code,
                                          int c0, uint32_t (*cc)[NC])
@@ -387,7 +396,8 @@ __device__ __forceinline__ bool rb_codes(const VB& vb, const RB& R, const RBFram
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const int c = NC == 2 ? q : c0;
-            cc[p][q] = (ok && rb_node(R, i, j, c, m) >= 0) ? ldf(code, rb_rel(R, F, i, j, c, m)) : C_RB_UNCUT;
+            const uint32_t e = rb_rel(R, F, i, j, c, m);
+            cc[p][q] = (ok && rb_node(R, i, j, c, m) >= 0) ? (NC == 1 ? ldf_nt(code, e) : ldf(code, e)) : C_RB_UNCUT;
         }
     }
 #pragma unroll
@@ -845,8 +855,8 @@ __global__ void __launch_bounds__(256) kb_rb_sweep(Bt<T> B, int c, GateSpec gs)
                 const RBNb n = rb_nb(R, F, i, j, c, m, k);
                 const stencil::NodeK<T> K = rb_k<decltype(U)::value>(D.op, code, n, cc[p][0]);
                 const T s = rb_sum(K, n, [&](uint32_t f) { return ldf((const GMEM T*)x, f); });
-                const T bn = ldf(b, n.e);
-                const T xn = (bn + s) * ldf(dinv, n.e);
+                const T bn = ldf_nt(b, n.e);
+                const T xn = (bn + s) * ldf_nt(dinv, n.e);
                 stf(x, n.e) = xn;
                 if constexpr (Dot) v[0] += (double)bn * (double)xn;
             }
@@ -1025,8 +1035,11 @@ __global__ void __launch_bounds__(256) kb_rb_update(Bt<T> B)
         for (int c = 0; c < 2; ++c) {
             if (rb_node(R, i, j, c, m) < 0) continue;
             const uint32_t e = rb_rel(R, F, i, j, c, m);
-            stf(x, e) += a * ldf(p, e);
-            const T rv = ldf((const GMEM T*)r, e) - a * ldf(q, e);
+            // streamed once: non-temporal, and x (read again only by the next update or a
+            // residual replacement) stored non-temporal; r stays cached for the V-cycle that
+            // follows
+            __builtin_nontemporal_store(ldf_nt((const GMEM T*)x, e) + a * ldf_nt(p, e), &stf(x, e));
+            const T rv = ldf_nt((const GMEM T*)r, e) - a * ldf_nt(q, e);
             stf(r, e) = rv;
             v[0] += (double)rv * (double)rv;
         }
