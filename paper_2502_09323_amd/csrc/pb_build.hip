@@ -14,6 +14,7 @@
 #include "pb_stencil.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace pbk {
@@ -534,70 +535,102 @@ __device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const D
 }
 
 // Debye-Hueckel values at the box nodes in FP64 (Sect. 2.3, the Debye-Hueckel form):
-// g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The squared distance is taken in the
-// expanded form |p|^2 + |a|^2 - 2 a.p (one add and three fused multiply-adds from -2a and |a|^2
-// held in LDS), with the node p and the atom a relative to the atoms' centre: its rounding
-// error, about (|p|^2 + |a|^2) 1e-16, is below 1e-13 of r^2 wherever the box is at least a
-// thirtieth of its half-diagonal from every atom centre (the benchmark boxes are tens of
-// Angstrom away).  Then 1/r by rsqrt_fp64, r = r^2 (1/r) and exp(-kD r) by exp_dh; without
-// salt (kD = 0) the exponential is skipped.  Block b takes box-node tile b % tiles (two nodes
-// per thread, so that each atom read from LDS serves two pairs) and the atoms of range
-// b / tiles; its partial sums go to part[range][node], which k_bc_dh_sum adds up in range
-// order.
-__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSplit sp, double* part)
+// g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The box nodes are taken face by face:
+// on a face with normal axis w and in-plane axes u, v the squared distance separates,
+// r^2 = (w0 - a_w)^2 + (u - a_u)^2 + (v - a_v)^2, so a thread that owns DH_PU x DH_PV nodes of
+// a face forms the u and v terms of an atom once per row and column of its patch and each
+// pair's r^2 in one add (2.75 operations per pair instead of four for |p|^2 + |a|^2 - 2 a.p),
+// from exact coordinate differences taken relative to the atoms' centre.  Then 1/r by
+// rsqrt_fp64, r = r^2 (1/r) and exp(-kD r) by exp_dh; without salt (kD = 0) the exponential is
+// skipped.  A face's patches are numbered row by row (no padding to block tiles, so only the
+// last patch of a row or column is partly outside the face), 256 to a block; block b takes
+// block b % blocks of the faces and the atoms of range b / blocks (staged in LDS with the
+// face's own w term); its partial sums go to part[range][node] (the box-node numbering of
+// box_node), which k_bc_dh_sum adds up in range order.
+constexpr int DH_PU = 2, DH_PV = 4;   // nodes per thread along u, v
+
+__global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSplit sp, DhFaces fc, double* part)
 {
     __shared__ double sa[256 * 4];
-    __shared__ double sq[256];
     __shared__ double T[kDhTable];
     for (int j = threadIdx.x; j < kDhTable; j += 256) T[j] = exp2((double)j / kDhTable);
-    const int tile = (int)(blockIdx.x % sp.tiles), rg = (int)(blockIdx.x / sp.tiles);
-    int64_t t[2];
-    bool act[2];
-    double p[2][3];
-    dh_nodes(g, at, sp, tile, t, act, p);
-    const double pp0 = fma(p[0][0], p[0][0], fma(p[0][1], p[0][1], p[0][2] * p[0][2]));
-    const double pp1 = fma(p[1][0], p[1][0], fma(p[1][1], p[1][1], p[1][2] * p[1][2]));
+    const int tile = (int)(blockIdx.x % fc.tile0[6]), rg = (int)(blockIdx.x / fc.tile0[6]);
+    int f = 0;
+    while (f < 5 && tile >= fc.tile0[f + 1]) ++f;
+    const int64_t patch = (int64_t)(tile - fc.tile0[f]) * 256 + threadIdx.x;
+    const int w = f >> 1, side = f & 1;
+    const int ua = w == 0 ? 1 : 0, va = w == 2 ? 1 : 2;   // in-plane axes: u slower, v faster
+    const int ushift = w == 0 ? 0 : 1, vshift = w == 2 ? 1 : 0;
+    const int U = fc.U[f], V = fc.V[f];
+    const int u0 = (int)(patch / fc.pv[f]) * DH_PU, v0 = (int)(patch % fc.pv[f]) * DH_PV;
+    const double cen[3] = {at.cx, at.cy, at.cz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const double pw = node_x(g, w, side ? nn[w] - 1 : 0) - cen[w];
+    double pu[DH_PU], pv[DH_PV], s[DH_PU][DH_PV];
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a) pu[a] = node_x(g, ua, min(u0 + a, U - 1) + ushift) - cen[ua];
+#pragma unroll
+    for (int b = 0; b < DH_PV; ++b) pv[b] = node_x(g, va, min(v0 + b, V - 1) + vshift) - cen[va];
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+        for (int b = 0; b < DH_PV; ++b) s[a][b] = 0.0;
+    const bool act = patch < fc.np[f];
     const bool salt = E.c1 != 0.0;
     const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
-    double s0 = 0.0, s1 = 0.0;
     for (int base = a0; base < a1; base += 256) {
-        int a = base + threadIdx.x;
+        const int at_i = base + threadIdx.x;
         __syncthreads();
-        if (a < a1) {
-            const double x = at.xyzr[4 * a + 0] - at.cx, y = at.xyzr[4 * a + 1] - at.cy,
-                         z = at.xyzr[4 * a + 2] - at.cz;
-            sa[4 * threadIdx.x + 0] = -2.0 * x;
-            sa[4 * threadIdx.x + 1] = -2.0 * y;
-            sa[4 * threadIdx.x + 2] = -2.0 * z;
-            sa[4 * threadIdx.x + 3] = fma(x, x, fma(y, y, z * z));
-            sq[threadIdx.x] = at.q[a];
+        if (at_i < a1) {
+            const double* A = at.xyzr + 4 * at_i;
+            const double dw = pw - (A[w] - cen[w]);
+            sa[4 * threadIdx.x + 0] = dw * dw;
+            sa[4 * threadIdx.x + 1] = A[ua] - cen[ua];
+            sa[4 * threadIdx.x + 2] = A[va] - cen[va];
+            sa[4 * threadIdx.x + 3] = at.q[at_i];
         }
         __syncthreads();
-        int m = a1 - base < 256 ? a1 - base : 256;
-        if (!act[0]) continue;   // act[1] implies act[0]
-        if (salt) {
-#pragma unroll 2
-            for (int u = 0; u < m; ++u) {
-                const double* A = sa + 4 * u;
-                const double q = sq[u];
-                const double r20 = fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])));
-                const double r21 = fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])));
-                const double y0 = rsqrt_fp64(r20), y1 = rsqrt_fp64(r21);
-                s0 = fma(q * exp_dh(r20 * y0, E, T), y0, s0);
-                s1 = fma(q * exp_dh(r21 * y1, E, T), y1, s1);
+        const int m = a1 - base < 256 ? a1 - base : 256;
+        if (!act) continue;
+        auto body = [&](auto SALT) {
+            for (int q = 0; q < m; ++q) {
+                const double* A = sa + 4 * q;
+                const double aw = A[0], au = A[1], av = A[2], qq = A[3];
+                double ru[DH_PU], rv[DH_PV];
+#pragma unroll
+                for (int a = 0; a < DH_PU; ++a) {
+                    const double d = pu[a] - au;
+                    ru[a] = fma(d, d, aw);
+                }
+#pragma unroll
+                for (int b = 0; b < DH_PV; ++b) {
+                    const double d = pv[b] - av;
+                    rv[b] = d * d;
+                }
+#pragma unroll
+                for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+                    for (int b = 0; b < DH_PV; ++b) {
+                        const double r2 = ru[a] + rv[b];
+                        const double y = rsqrt_fp64(r2);
+                        if constexpr (decltype(SALT)::value)
+                            s[a][b] = fma(qq * exp_dh(r2 * y, E, T), y, s[a][b]);
+                        else
+                            s[a][b] = fma(qq, y, s[a][b]);
+                    }
             }
-        } else {
-#pragma unroll 2
-            for (int u = 0; u < m; ++u) {
-                const double* A = sa + 4 * u;
-                const double q = sq[u];
-                s0 = fma(q, rsqrt_fp64(fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])))), s0);
-                s1 = fma(q, rsqrt_fp64(fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])))), s1);
-            }
-        }
+        };
+        if (salt)
+            body(std::true_type{});
+        else
+            body(std::false_type{});
     }
-    if (act[0]) part[(int64_t)rg * sp.nbox + t[0]] = s0;
-    if (act[1]) part[(int64_t)rg * sp.nbox + t[1]] = s1;
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+        for (int b = 0; b < DH_PV; ++b)
+            if (act && u0 + a < U && v0 + b < V)
+                part[(int64_t)rg * sp.nbox + fc.base[f] + (int64_t)(u0 + a) * V + (v0 + b)] = s[a][b];
 }
 
 // The same sum for the mixed-precision form: squared distances in FP64, then the exponential
@@ -1030,6 +1063,26 @@ DhExp dh_exp_consts(double kD)
     return E;
 }
 
+DhFaces dh_faces(const Grid& g)
+{
+    DhFaces fc{};
+    const int64_t fx = (int64_t)g.ny * g.nz, fy = (int64_t)(g.nx - 2) * g.nz;
+    const int64_t fz = (int64_t)(g.nx - 2) * (g.ny - 2);
+    const int U[3] = {g.ny, g.nx - 2, g.nx - 2}, V[3] = {g.nz, g.nz, g.ny - 2};
+    const int64_t first[3] = {0, 2 * fx, 2 * fx + 2 * fy}, size[3] = {fx, fy, fz};
+    fc.tile0[0] = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int w = f >> 1;
+        fc.base[f] = first[w] + (f & 1) * size[w];
+        fc.U[f] = U[w];
+        fc.V[f] = V[w];
+        fc.pv[f] = (V[w] + DH_PV - 1) / DH_PV;
+        fc.np[f] = (int64_t)((U[w] + DH_PU - 1) / DH_PU) * fc.pv[f];
+        fc.tile0[f + 1] = fc.tile0[f] + (int)((fc.np[f] + 255) / 256);
+    }
+    return fc;
+}
+
 DhSplit dh_split(const Grid& g, int n_atoms)
 {
     DhSplit sp;
@@ -1050,7 +1103,8 @@ hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD
                         double* gb)
 {
     const DhSplit sp = dh_split(g, at.n);
-    k_bc_dh<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, dh_exp_consts(kD), sp, part);
+    const DhFaces fc = dh_faces(g);
+    k_bc_dh<<<(unsigned)(fc.tile0[6] * sp.ranges), 256, 0, s>>>(g, at, dh_exp_consts(kD), sp, fc, part);
     k_bc_dh_sum<<<(unsigned)nblk(sp.nbox, 256), 256, 0, s>>>(g, sp, part, eps_out, gb);
     return hipGetLastError();
 }

@@ -160,6 +160,14 @@ struct DhExp {
     double c1, c2, c3;  // Taylor coefficients of e^(-kD s): -kD, kD^2 / 2, -kD^3 / 6 (all 0 for kD = 0)
 };
 DhExp dh_exp_consts(double kD);
+struct DhFaces {        // the six box faces as row-major U x V arrays of box nodes (FP64 sum)
+    int64_t base[6];    // box-node index of each face's first node
+    int U[6], V[6];
+    int pv[6];          // thread patches per face row (along v)
+    int64_t np[6];      // thread patches per face
+    int tile0[7];       // first block of each face; tile0[6] = all blocks
+};
+DhFaces dh_faces(const Grid& g);
 // part holds dh_split(g, at.n).ranges * nbox doubles
 hipError_t launch_bc_dh(hipStream_t s, const Grid& g, const Atoms& at, double kD, double eps_out, double* part,
                         double* gb);
