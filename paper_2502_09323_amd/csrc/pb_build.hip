@@ -519,21 +519,6 @@ __device__ __forceinline__ double exp_dh(double r, const DhExp& E, const double*
     return ldexp(T[n & (kDhTable - 1)] * p, n >> 11);
 }
 
-// A thread's box nodes: t and t + 256 of its block's tile of kDhNodesPerBlock
-__device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const DhSplit& sp, int tile, int64_t* t,
-                                         bool* act, double (*p)[3])
-{
-    for (int v = 0; v < 2; ++v) {
-        t[v] = (int64_t)tile * kDhNodesPerBlock + v * 256 + threadIdx.x;
-        act[v] = t[v] < sp.nbox;
-        int i = 0, j = 0, k = 0;
-        if (act[v]) box_node(g, t[v], i, j, k);
-        p[v][0] = node_x(g, 0, i) - at.cx;
-        p[v][1] = node_x(g, 1, j) - at.cy;
-        p[v][2] = node_x(g, 2, k) - at.cz;
-    }
-}
-
 // Debye-Hueckel values at the box nodes in FP64 (Sect. 2.3, the Debye-Hueckel form):
 // g(x) = sum over atoms of q exp(-kD r) / (eps_out r).  The box nodes are taken face by face:
 // on a face with normal axis w and in-plane axes u, v the squared distance separates,
@@ -549,64 +534,109 @@ __device__ __forceinline__ void dh_nodes(const Grid& g, const Atoms& at, const D
 // box_node), which k_bc_dh_sum adds up in range order.
 constexpr int DH_PU = 2, DH_PV = 4;   // nodes per thread along u, v
 
+// a thread's patch of box-face nodes: its face (normal axis w, in-plane axes ua slower and va
+// faster), the patch's first node (u0, v0) on the face's U x V array, and the coordinates,
+// relative to the atoms' centre, of the face plane and of the patch's rows and columns
+// (clamped to the face for a patch partly outside it)
+struct DhPatch {
+    int f, w, ua, va, U, V, u0, v0;
+    bool act;
+    double pw, pu[DH_PU], pv[DH_PV];
+};
+
+__device__ __forceinline__ DhPatch dh_patch(const Grid& g, const Atoms& at, const DhFaces& fc, int tile)
+{
+    DhPatch P;
+    P.f = 0;
+    while (P.f < 5 && tile >= fc.tile0[P.f + 1]) ++P.f;
+    const int64_t patch = (int64_t)(tile - fc.tile0[P.f]) * 256 + threadIdx.x;
+    P.w = P.f >> 1;
+    P.ua = P.w == 0 ? 1 : 0;
+    P.va = P.w == 2 ? 1 : 2;
+    // a later axis's faces leave out the edge nodes that the earlier axes' faces hold
+    const int ushift = P.w == 0 ? 0 : 1, vshift = P.w == 2 ? 1 : 0;
+    P.U = fc.U[P.f];
+    P.V = fc.V[P.f];
+    P.u0 = (int)(patch / fc.pv[P.f]) * DH_PU;
+    P.v0 = (int)(patch % fc.pv[P.f]) * DH_PV;
+    P.act = patch < fc.np[P.f];
+    const double cen[3] = {at.cx, at.cy, at.cz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    P.pw = node_x(g, P.w, (P.f & 1) ? nn[P.w] - 1 : 0) - cen[P.w];
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a) P.pu[a] = node_x(g, P.ua, min(P.u0 + a, P.U - 1) + ushift) - cen[P.ua];
+#pragma unroll
+    for (int b = 0; b < DH_PV; ++b) P.pv[b] = node_x(g, P.va, min(P.v0 + b, P.V - 1) + vshift) - cen[P.va];
+    return P;
+}
+
+// an atom's terms for the patch's face: (w0 - a_w)^2, a_u, a_v (relative to the atoms' centre)
+__device__ __forceinline__ void dh_stage(const DhPatch& P, const Atoms& at, int a, double* out)
+{
+    const double* A = at.xyzr + 4 * a;
+    const double cen[3] = {at.cx, at.cy, at.cz};
+    const double dw = P.pw - (A[P.w] - cen[P.w]);
+    out[0] = dw * dw;
+    out[1] = A[P.ua] - cen[P.ua];
+    out[2] = A[P.va] - cen[P.va];
+}
+
+// the squared distances of the patch's rows (with the face term) and columns to an atom
+__device__ __forceinline__ void dh_terms(const DhPatch& P, const double* A, double* ru, double* rv)
+{
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a) {
+        const double d = P.pu[a] - A[1];
+        ru[a] = fma(d, d, A[0]);
+    }
+#pragma unroll
+    for (int b = 0; b < DH_PV; ++b) {
+        const double d = P.pv[b] - A[2];
+        rv[b] = d * d;
+    }
+}
+
+__device__ __forceinline__ void dh_write(const DhPatch& P, const DhFaces& fc, const DhSplit& sp, int rg,
+                                         const double (*s)[DH_PV], double* part)
+{
+#pragma unroll
+    for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+        for (int b = 0; b < DH_PV; ++b)
+            if (P.act && P.u0 + a < P.U && P.v0 + b < P.V)
+                part[(int64_t)rg * sp.nbox + fc.base[P.f] + (int64_t)(P.u0 + a) * P.V + (P.v0 + b)] = s[a][b];
+}
+
 __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSplit sp, DhFaces fc, double* part)
 {
     __shared__ double sa[256 * 4];
     __shared__ double T[kDhTable];
     for (int j = threadIdx.x; j < kDhTable; j += 256) T[j] = exp2((double)j / kDhTable);
     const int tile = (int)(blockIdx.x % fc.tile0[6]), rg = (int)(blockIdx.x / fc.tile0[6]);
-    int f = 0;
-    while (f < 5 && tile >= fc.tile0[f + 1]) ++f;
-    const int64_t patch = (int64_t)(tile - fc.tile0[f]) * 256 + threadIdx.x;
-    const int w = f >> 1, side = f & 1;
-    const int ua = w == 0 ? 1 : 0, va = w == 2 ? 1 : 2;   // in-plane axes: u slower, v faster
-    const int ushift = w == 0 ? 0 : 1, vshift = w == 2 ? 1 : 0;
-    const int U = fc.U[f], V = fc.V[f];
-    const int u0 = (int)(patch / fc.pv[f]) * DH_PU, v0 = (int)(patch % fc.pv[f]) * DH_PV;
-    const double cen[3] = {at.cx, at.cy, at.cz};
-    const int nn[3] = {g.nx, g.ny, g.nz};
-    const double pw = node_x(g, w, side ? nn[w] - 1 : 0) - cen[w];
-    double pu[DH_PU], pv[DH_PV], s[DH_PU][DH_PV];
-#pragma unroll
-    for (int a = 0; a < DH_PU; ++a) pu[a] = node_x(g, ua, min(u0 + a, U - 1) + ushift) - cen[ua];
-#pragma unroll
-    for (int b = 0; b < DH_PV; ++b) pv[b] = node_x(g, va, min(v0 + b, V - 1) + vshift) - cen[va];
+    const DhPatch P = dh_patch(g, at, fc, tile);
+    double s[DH_PU][DH_PV];
 #pragma unroll
     for (int a = 0; a < DH_PU; ++a)
 #pragma unroll
         for (int b = 0; b < DH_PV; ++b) s[a][b] = 0.0;
-    const bool act = patch < fc.np[f];
     const bool salt = E.c1 != 0.0;
     const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
     for (int base = a0; base < a1; base += 256) {
         const int at_i = base + threadIdx.x;
         __syncthreads();
         if (at_i < a1) {
-            const double* A = at.xyzr + 4 * at_i;
-            const double dw = pw - (A[w] - cen[w]);
-            sa[4 * threadIdx.x + 0] = dw * dw;
-            sa[4 * threadIdx.x + 1] = A[ua] - cen[ua];
-            sa[4 * threadIdx.x + 2] = A[va] - cen[va];
+            dh_stage(P, at, at_i, sa + 4 * threadIdx.x);
             sa[4 * threadIdx.x + 3] = at.q[at_i];
         }
         __syncthreads();
         const int m = a1 - base < 256 ? a1 - base : 256;
-        if (!act) continue;
+        if (!P.act) continue;
         auto body = [&](auto SALT) {
             for (int q = 0; q < m; ++q) {
                 const double* A = sa + 4 * q;
-                const double aw = A[0], au = A[1], av = A[2], qq = A[3];
+                const double qq = A[3];
                 double ru[DH_PU], rv[DH_PV];
-#pragma unroll
-                for (int a = 0; a < DH_PU; ++a) {
-                    const double d = pu[a] - au;
-                    ru[a] = fma(d, d, aw);
-                }
-#pragma unroll
-                for (int b = 0; b < DH_PV; ++b) {
-                    const double d = pv[b] - av;
-                    rv[b] = d * d;
-                }
+                dh_terms(P, A, ru, rv);
 #pragma unroll
                 for (int a = 0; a < DH_PU; ++a)
 #pragma unroll
@@ -625,68 +655,57 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSpli
         else
             body(std::false_type{});
     }
+    dh_write(P, fc, sp, rg, s, part);
+}
+
+// The same sum for the mixed-precision form: squared distances in FP64 (the face terms as in
+// k_bc_dh), then the exponential and the inverse distance in FP32 (a few units in the last
+// place, about 1e-7 relative per term), accumulated in FP64.  The box is tens of Angstrom from
+// the surface, so these errors reach the surface potential screened by exp(-kD d) and stay
+// far below the FP32 iteration's own rounding.  The hardware reciprocal square root and
+// base-2 exponential are used directly: r^2 leaves the FP32 normal range only for an atom
+// centre within 1e-19 A of a box node, where the sum is singular anyway, and an exponent
+// below -126 gives 0 in place of a term under 1e-38.  Patches, ranges and partial sums as in
+// k_bc_dh.
+__global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, DhSplit sp, DhFaces fc, double* part)
+{
+    __shared__ double sa[256 * 3];
+    __shared__ float sq[256];
+    const int tile = (int)(blockIdx.x % fc.tile0[6]), rg = (int)(blockIdx.x / fc.tile0[6]);
+    const DhPatch P = dh_patch(g, at, fc, tile);
+    const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
+    double s[DH_PU][DH_PV];
 #pragma unroll
     for (int a = 0; a < DH_PU; ++a)
 #pragma unroll
-        for (int b = 0; b < DH_PV; ++b)
-            if (act && u0 + a < U && v0 + b < V)
-                part[(int64_t)rg * sp.nbox + fc.base[f] + (int64_t)(u0 + a) * V + (v0 + b)] = s[a][b];
-}
-
-// The same sum for the mixed-precision form: squared distances in FP64, then the exponential
-// and the inverse distance in FP32 (a few units in the last place, about 1e-7 relative per
-// term), accumulated in FP64.  The box is tens of Angstrom from the surface, so these errors
-// reach the surface potential screened by exp(-kD d) and stay far below the FP32 iteration's
-// own rounding.  The hardware reciprocal square root and base-2 exponential are used
-// directly: r^2 leaves the FP32 normal range only for an atom centre within 1e-19 A of a box
-// node, where the sum is singular anyway, and an exponent below -126 gives 0 in place of a
-// term under 1e-38.  The squared distance is taken in the expanded form |p|^2 + |a|^2 - 2 a.p
-// (one add and three fused multiply-adds from -2a and |a|^2 held in LDS), with p and a
-// relative to the atoms' centre so that the cancellation does not grow with the molecule's
-// distance from the coordinate origin (the box is far from every atom, so it costs nothing at
-// FP32 precision).  Tiles, ranges and partial sums as in k_bc_dh.
-__global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, DhSplit sp, double* part)
-{
-    __shared__ double sa[256 * 4];
-    __shared__ float sq[256];
-    const int tile = (int)(blockIdx.x % sp.tiles), rg = (int)(blockIdx.x / sp.tiles);
-    int64_t t[2];
-    bool act[2];
-    double p[2][3];
-    dh_nodes(g, at, sp, tile, t, act, p);
-    const double pp0 = fma(p[0][0], p[0][0], fma(p[0][1], p[0][1], p[0][2] * p[0][2]));
-    const double pp1 = fma(p[1][0], p[1][0], fma(p[1][1], p[1][1], p[1][2] * p[1][2]));
-    const float mk = (float)(-kD * 1.4426950408889634);   // -kD log2(e)
+        for (int b = 0; b < DH_PV; ++b) s[a][b] = 0.0;
     const int a0 = rg * sp.per, a1 = min(at.n, a0 + sp.per);
-    double s0 = 0.0, s1 = 0.0;
     for (int base = a0; base < a1; base += 256) {
-        int a = base + threadIdx.x;
+        const int at_i = base + threadIdx.x;
         __syncthreads();
-        if (a < a1) {
-            const double x = at.xyzr[4 * a + 0] - at.cx, y = at.xyzr[4 * a + 1] - at.cy,
-                         z = at.xyzr[4 * a + 2] - at.cz;
-            sa[4 * threadIdx.x + 0] = -2.0 * x;
-            sa[4 * threadIdx.x + 1] = -2.0 * y;
-            sa[4 * threadIdx.x + 2] = -2.0 * z;
-            sa[4 * threadIdx.x + 3] = fma(x, x, fma(y, y, z * z));
-            sq[threadIdx.x] = (float)at.q[a];
+        if (at_i < a1) {
+            dh_stage(P, at, at_i, sa + 3 * threadIdx.x);
+            sq[threadIdx.x] = (float)at.q[at_i];
         }
         __syncthreads();
-        int m = a1 - base < 256 ? a1 - base : 256;
-        if (act[0])
-#pragma unroll 4
-            for (int u = 0; u < m; ++u) {
-                const double* A = sa + 4 * u;
-                const float r20 = (float)fma(A[0], p[0][0], fma(A[1], p[0][1], fma(A[2], p[0][2], pp0 + A[3])));
-                const float r21 = (float)fma(A[0], p[1][0], fma(A[1], p[1][1], fma(A[2], p[1][2], pp1 + A[3])));
-                const float ri0 = __builtin_amdgcn_rsqf(r20), ri1 = __builtin_amdgcn_rsqf(r21);
-                const float e0 = __builtin_amdgcn_exp2f(mk * (r20 * ri0)), e1 = __builtin_amdgcn_exp2f(mk * (r21 * ri1));
-                s0 += (double)(sq[u] * e0 * ri0);
-                s1 += (double)(sq[u] * e1 * ri1);
-            }
+        const int m = a1 - base < 256 ? a1 - base : 256;
+        if (!P.act) continue;
+        for (int q = 0; q < m; ++q) {
+            double ru[DH_PU], rv[DH_PV];
+            dh_terms(P, sa + 3 * q, ru, rv);
+            const float qq = sq[q];
+#pragma unroll
+            for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+                for (int b = 0; b < DH_PV; ++b) {
+                    const float r2 = (float)(ru[a] + rv[b]);
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
+                    s[a][b] += (double)(qq * e * ri);
+                }
+        }
     }
-    if (act[0]) part[(int64_t)rg * sp.nbox + t[0]] = s0;
-    if (act[1]) part[(int64_t)rg * sp.nbox + t[1]] = s1;
+    dh_write(P, fc, sp, rg, s, part);
 }
 
 // the box values from the partial sums of the atom ranges, added in range order
@@ -1113,7 +1132,8 @@ hipError_t launch_bc_dh32(hipStream_t s, const Grid& g, const Atoms& at, double 
                           double* gb)
 {
     const DhSplit sp = dh_split(g, at.n);
-    k_bc_dh32<<<(unsigned)(sp.tiles * sp.ranges), 256, 0, s>>>(g, at, kD, sp, part);
+    const DhFaces fc = dh_faces(g);
+    k_bc_dh32<<<(unsigned)(fc.tile0[6] * sp.ranges), 256, 0, s>>>(g, at, kD, sp, fc, part);
     k_bc_dh_sum<<<(unsigned)nblk(sp.nbox, 256), 256, 0, s>>>(g, sp, part, eps_out, gb);
     return hipGetLastError();
 }

@@ -147,7 +147,7 @@ constexpr int kDhMaxRanges = 16;
 constexpr int64_t kDhTargetBlocks = 32768;
 struct DhSplit {
     int64_t nbox;   // box nodes
-    int tiles;      // tiles of kDhNodesPerBlock box nodes
+    int tiles;      // box nodes / kDhNodesPerBlock (sizes the ranges)
     int per;        // atoms per range (a multiple of 256)
     int ranges;     // atom ranges (at most kDhMaxRanges)
 };
