@@ -139,9 +139,10 @@ hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Ato
 int grid_energy_blocks(int n_atoms);
 hipError_t launch_grid_energy(hipStream_t s, const Grid& g, const Atoms& at, const double* x, double scale,
                               double* part);
-// Debye-Hueckel box values: the atoms are split into ranges of whole 256-atom chunks, each
-// block sums one range for one tile of kDhNodesPerBlock box nodes into part[range][node], and
-// a second kernel adds the ranges in order
+// Debye-Hueckel box values: the atoms are split into ranges of whole 256-atom chunks (as many
+// ranges as kDhTargetBlocks blocks of kDhNodesPerBlock box nodes would ask for, at most
+// kDhMaxRanges), each block sums one range for its patches of box-face nodes into
+// part[range][node], and a second kernel adds the ranges in order
 constexpr int kDhNodesPerBlock = 512;
 constexpr int kDhMaxRanges = 16;
 constexpr int64_t kDhTargetBlocks = 32768;
