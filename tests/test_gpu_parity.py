@@ -238,6 +238,35 @@ def dh_abs_scale(grid, mol, kD):
     return full.reshape(n)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dh_all_box_nodes_non_cubic(ctx, prec):
+    """Debye-Hueckel values (Sect. 2.3) at every box node, the edges and corners of the box
+    included, on a grid with a different node count per axis (so that every face has ragged
+    patch rows and columns): the exported potential at the box nodes is lB g, against the
+    oracle's g, to 1e-13 (FP64) or 1e-6 (mixed: FP32 exponential and inverse distance) of the
+    absolute-value scale of each node."""
+    mol = I.random_molecule(700, 8.0, 23, center=(3.0, -2.0, 1.0))
+    n = (45, 38, 51)
+    h = 0.6
+    origin = tuple(c - 0.5 * (v - 1) * h for c, v in zip((3.0, -2.0, 1.0), n))
+    grid = I.GridSpec(n=n, h=h, origin=origin, ionic_M=0.145,
+                      precision=I.FP64 if prec == "fp64" else I.MIXED)
+    lB, kD = O.constants(grid.temp_K, grid.ionic_M, grid.eps_out)
+    g = O.boundary_values(grid, mol, kD)
+    sabs = dh_abs_scale(grid, mol, kD)
+    pb = B.Problem(ctx, mol, grid)
+    try:
+        phi = pb.potential()
+    finally:
+        pb.close()
+    box = sabs > 0
+    assert box.sum() == 2 * (n[0] * n[1] + n[0] * n[2] + n[1] * n[2]) - 4 * sum(n) + 8
+    err = np.abs(phi[box] / lB - g[box]) / sabs[box]
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    print(f"{prec}: {box.sum()} box nodes, max difference {err.max():.2e} of the absolute-value scale")
+    assert err.max() <= tol
+
+
 @pytest.mark.parametrize("label,ionic,center", DH_CASES, ids=[c[0] for c in DH_CASES])
 def test_dh_box_values_parity(ctx, label, ionic, center):
     """FP64 Debye-Hueckel box values (Sect. 2.3) against the oracle's: at the interior nodes
