@@ -770,15 +770,6 @@ __global__ void __launch_bounds__(256) k_diag_lift(Grid g, const uint32_t* code,
 // Cell corners are numbered x + 2y + 4z.  Cell edges 0..3 run along x at (y,z) = 00,10,01,11;
 // 4..7 along y at (x,z) = 00,10,01,11; 8..11 along z at (x,y) = 00,10,01,11.
 
-__device__ __forceinline__ void cedge(int e, int& ax, int& c0, int& c1)
-{
-    int grp = e >> 2, u = e & 1, v = (e >> 1) & 1;
-    ax = grp;
-    if (grp == 0) { c0 = 2 * u + 4 * v; c1 = c0 + 1; }
-    else if (grp == 1) { c0 = u + 4 * v; c1 = c0 + 2; }
-    else { c0 = u + 2 * v; c1 = c0 + 4; }
-}
-
 __device__ __forceinline__ double tri_area(const double* a, const double* b, const double* c)
 {
     double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};

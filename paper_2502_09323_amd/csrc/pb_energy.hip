@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(256) k_energy_final(const double* __restrict__
     __shared__ double sh[32];
     const double fpi = 1.0 / (4.0 * kPi);
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dummy = 0.0;
-    if (threadIdx.x < nb)
+    if ((int)threadIdx.x < nb)
         for (int k = 0; k < 5; ++k) v[k] = part[5 * threadIdx.x + k];
     block_sum2(v[0], v[1], sh, 4);
     block_sum2(v[2], v[3], sh, 4);

@@ -891,15 +891,6 @@ __global__ void __launch_bounds__(256) k_true_res(Split sp, const double* bc, co
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-__global__ void __launch_bounds__(256) k_sum_to(const double* part, int nb, double* out)
-{
-    __shared__ double sh[8];
-    double v[1] = {0.0};
-    for (int t = threadIdx.x; t < nb; t += 256) v[0] += part[t];
-    bsum(v, 1, sh);
-    if (threadIdx.x == 0) *out = v[0];
-}
-
 // r32 = r64, z32 = D^-1 r32; partial sums of r.z and r.r
 __global__ void __launch_bounds__(256) k_replace(Split sp, const double* r64c, float* rc, float* zc, const float* dc,
                                                  const double* r64f, float* rf, float* zf, const float* df,
