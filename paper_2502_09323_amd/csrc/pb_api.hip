@@ -417,8 +417,9 @@ size_t pbi_request_bytes(const pb_params& p, int64_t na, const double* radius, i
     // per cut edge: key, alpha, K, crossing point, normal, owner, area weight (84 B) and at
     // most one slot of the compact coefficient tables (40 B)
     const size_t per_cut = 124;
-    // per atom: coordinates and charge (40 B), bin ids and deposition cells (52 B)
-    const size_t per_atom = 92;
+    // per atom: coordinates and charge (40 B); the cell list's ids, centres and radii in its
+    // order, and deposition cells with charges (100 B)
+    const size_t per_atom = 140;
     // the Debye-Hueckel partial sums of the build (at most kDhMaxRanges per box node)
     const int64_t nbox = 2 * ((int64_t)p.n[1] * p.n[2] + (int64_t)(p.n[0] - 2) * p.n[2] +
                               (int64_t)(p.n[0] - 2) * (p.n[1] - 2));
@@ -555,9 +556,9 @@ void release_tmp(pb_problem* pb)
 {
     BuildTmp* t = pb->bt;
     if (!t) return;
-    for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->cls,
-                    (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full, (void*)t->acell,
-                    (void*)t->dhpart})
+    for (void* d : {(void*)t->bcnt, (void*)t->bstart, (void*)t->bcur, (void*)t->bids, (void*)t->bxyzr,
+                    (void*)t->cls, (void*)t->bslots, (void*)t->bcuts, (void*)t->tot, (void*)t->full,
+                    (void*)t->acell, (void*)t->dhpart})
         if (d) pb->mem.put(d);
     if (t->hpin) pb->ctx->pinned.put(t->hpin, t->hpin_cap);   // the build's copies have completed
     delete t;
@@ -727,8 +728,10 @@ int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz
     CK(rc);
     T.bids = dalloc<int>(pb, na1, &rc);
     CK(rc);
+    T.bxyzr = dalloc<double>(pb, 4 * (size_t)na1, &rc);
+    CK(rc);
     if (na > 0) {
-        HK(launch_bins(s, at, bn, T.bcnt, T.bstart, T.bids, T.bcur));
+        HK(launch_bins(s, at, bn, T.bcnt, T.bstart, T.bids, T.bcur, T.bxyzr));
     } else {
         HK(launch_fill(s, T.bstart, sizeof(int) * ((size_t)nbins + 1)));
         bn.start = T.bstart;
@@ -738,7 +741,7 @@ int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz
     // classification and counting of the cut edges
     T.cls = dalloc<uint32_t>(pb, N, &rc);
     CK(rc);
-    HK(launch_classify(s, g, bn, at, T.cls));
+    HK(launch_classify(s, g, bn, T.bxyzr, at, T.cls));
     T.nblk = (int)((N + 255) / 256);
     T.bslots = dalloc<int>(pb, (size_t)T.nblk + 1, &rc);
     CK(rc);
@@ -806,7 +809,7 @@ int pbi_build_continue(pb_problem* pb)
     CK(rc);
     pb->wp = dalloc<double>(pb, nc1, &rc);
     CK(rc);
-    HIPCHK(launch_cut_geom(s, g, T.bn, at, prm->eps_in, prm->eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
+    HIPCHK(launch_cut_geom(s, g, T.bn, T.bxyzr, at, prm->eps_in, prm->eps_out, pb->ncut, pb->cutkey, pb->code, pb->alpha,
                            pb->kcut, pb->rp, pb->np, pb->owner, pb->ck64, pb->ck32));
 
     // load vector, boundary values, diagonal and lift
@@ -816,7 +819,7 @@ int pbi_build_continue(pb_problem* pb)
     CK(rc);
     pb->x = dalloc<double>(pb, N, &rc);
     CK(rc);
-    T.acell = dalloc<double>(pb, 6 * (size_t)std::max<int64_t>(pb->na, 1), &rc);
+    T.acell = dalloc<double>(pb, 8 * (size_t)std::max<int64_t>(pb->na, 1), &rc);
     CK(rc);
     HIPCHK(launch_deposit(s, g, T.bn, at, T.acell, pb->rhs));
     HIPCHK(launch_fill(s, pb->gb, sizeof(double) * N));

@@ -83,6 +83,16 @@ __global__ void k_bin_scatter(Atoms at, Bins b, int* cursor, int* ids)
     ids[pos] = a;
 }
 
+// the atoms' centres and radii in bin order (slot u holds atom ids[u]), so that the loops
+// over a bin's atoms read them without first loading their ids
+__global__ void k_bin_gather(Atoms at, const int* __restrict__ ids, double* __restrict__ xyzr_b)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= at.n) return;
+    const int a = ids[u];
+    for (int d = 0; d < 4; ++d) xyzr_b[4 * u + d] = at.xyzr[4 * a + d];
+}
+
 // the scatter order depends on scheduling; sorting each bin makes the list deterministic
 __global__ void k_bin_sort(int nbins, const int* start, int* ids)
 {
@@ -144,7 +154,8 @@ __global__ void __launch_bounds__(1024) k_scan1(const int* in, int n, int* out)
 
 // ---- classification -------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, Atoms at, uint32_t* code)
+__global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, Atoms at, const double* __restrict__ xb,
+                                                  uint32_t* code)
 {
 #pragma clang fp contract(off)
     int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -168,7 +179,7 @@ __global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, Atoms at, uint
                 for (int z = lo[2]; z <= hi[2] && !c; ++z) {
                     int bi = (x * b.nby + y) * b.nbz + z;
                     for (int t = b.start[bi]; t < b.start[bi + 1]; ++t) {
-                        const double* a = at.xyzr + 4 * b.ids[t];
+                        const double* a = xb + 4 * t;
                         double dx = p[0] - a[0], dy = p[1] - a[1], dz = p[2] - a[2];
                         double d2 = dx * dx + dy * dy + dz * dz;
                         if (d2 < a[3] * a[3]) {
@@ -250,7 +261,8 @@ __global__ void __launch_bounds__(256) k_assign(Grid g, const uint32_t* cls, uin
 
 // ---- crossing geometry (first exit from the union of balls) -----------------------------
 
-__global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, double eps_in, double eps_out,
+__global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, const double* __restrict__ xb, Atoms at,
+                                                  double eps_in, double eps_out,
                                                   int64_t ncut, const int64_t* cutkey,
                                                   const uint32_t* code, double* alpha, double* kcut,
                                                   double* rp, double* np, int* owner, double* ck64,
@@ -286,7 +298,7 @@ __global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, doub
                     for (int z = lo[2]; z <= hi[2]; ++z) {
                         int bi = (x * b.nby + y) * b.nbz + z;
                         for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
-                            const double* a = at.xyzr + 4 * b.ids[u];
+                            const double* a = xb + 4 * u;
                             double dperp2 = 0.0;
                             for (int d = 0; d < 3; ++d) {
                                 if (d == ax) continue;
@@ -310,7 +322,7 @@ __global__ void __launch_bounds__(256) k_cut_geom(Grid g, Bins b, Atoms at, doub
                     int bi = (x * b.nby + y) * b.nbz + z;
                     for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
                         int id = b.ids[u];
-                        const double* a = at.xyzr + 4 * id;
+                        const double* a = xb + 4 * u;
                         double dperp2 = 0.0;
                         for (int d = 0; d < 3; ++d) {
                             if (d == ax) continue;
@@ -367,16 +379,21 @@ __device__ __forceinline__ void atom_cell(const Grid& g, const Atoms& at, int a,
     }
 }
 
-__global__ void __launch_bounds__(256) k_atom_cells(Grid g, Atoms at, double* ac)
+// per slot u of the cell list (atom ids[u]): the atom's deposition cell offsets t, its cell
+// fl and its charge, 8 doubles in bin order
+__global__ void __launch_bounds__(256) k_atom_cells(Grid g, Atoms at, const int* __restrict__ ids, double* ac)
 {
-    const int a = blockIdx.x * 256 + threadIdx.x;
-    if (a >= at.n) return;
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= at.n) return;
+    const int a = ids[u];
     double t[3], fl[3];
     atom_cell(g, at, a, t, fl);
     for (int d = 0; d < 3; ++d) {
-        ac[6 * a + d] = t[d];
-        ac[6 * a + 3 + d] = fl[d];
+        ac[8 * u + d] = t[d];
+        ac[8 * u + 3 + d] = fl[d];
     }
+    ac[8 * u + 6] = at.q[a];
+    ac[8 * u + 7] = 0.0;
 }
 
 // sum of v over the 256 threads of a block, the same value in every thread
@@ -452,8 +469,7 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const
                 for (int z = lo[2]; z <= hi[2]; ++z) {
                     int bi = (x * b.nby + y) * b.nbz + z;
                     for (int u = b.start[bi]; u < b.start[bi + 1]; ++u) {
-                        int id = b.ids[u];
-                        const double* c6 = ac + 6 * id;
+                        const double* c6 = ac + 8 * u;
                         double w = 1.0;
                         bool corner = true;
                         for (int d = 0; d < 3; ++d) {
@@ -463,7 +479,7 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const
                             else if (nd[d] == cl + 1) w = w * t;
                             else corner = false;
                         }
-                        if (corner) sum += 4.0 * kPi * at.q[id] * w;
+                        if (corner) sum += 4.0 * kPi * c6[6] * w;
                     }
                 }
     }
@@ -976,7 +992,7 @@ hipError_t launch_fill(hipStream_t s, void* p, size_t bytes)
 }
 
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
-                       int* cursor)
+                       int* cursor, double* xyzr_b)
 {
     int nb = b.nbx * b.nby * b.nbz;
     hipError_t err = launch_fill(s, cnt, sizeof(int) * (size_t)nb);
@@ -987,14 +1003,16 @@ hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* s
     if (err != hipSuccess) return err;
     k_bin_scatter<<<nblk(at.n, 256), 256, 0, s>>>(at, b, cursor, ids);
     k_bin_sort<<<nblk(nb, 256), 256, 0, s>>>(nb, start, ids);
+    k_bin_gather<<<nblk(at.n, 256), 256, 0, s>>>(at, ids, xyzr_b);
     b.start = start;
     b.ids = ids;
     return hipGetLastError();
 }
 
-hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, uint32_t* code)
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
+                           uint32_t* code)
 {
-    k_classify<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, code);
+    k_classify<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, xyzr_b, code);
     return hipGetLastError();
 }
 
@@ -1031,20 +1049,20 @@ hipError_t launch_assign(hipStream_t s, const Grid& g, const uint32_t* cls, uint
     return hipGetLastError();
 }
 
-hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double eps_in,
-                           double eps_out, int64_t ncut, const int64_t* cutkey, const uint32_t* code,
+hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
+                           double eps_in, double eps_out, int64_t ncut, const int64_t* cutkey, const uint32_t* code,
                            double* alpha, double* kcut, double* rp, double* np, int* owner,
                            double* ck64, float* ck32)
 {
     if (ncut == 0) return hipSuccess;
-    k_cut_geom<<<nblk(ncut, 256), 256, 0, s>>>(g, b, at, eps_in, eps_out, ncut, cutkey, code, alpha,
+    k_cut_geom<<<nblk(ncut, 256), 256, 0, s>>>(g, b, xyzr_b, at, eps_in, eps_out, ncut, cutkey, code, alpha,
                                                 kcut, rp, np, owner, ck64, ck32);
     return hipGetLastError();
 }
 
 hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs)
 {
-    if (at.n > 0) k_atom_cells<<<nblk(at.n, 256), 256, 0, s>>>(g, at, ac);
+    if (at.n > 0) k_atom_cells<<<nblk(at.n, 256), 256, 0, s>>>(g, at, b.ids, ac);
     k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, ac, rhs);
     return hipGetLastError();
 }

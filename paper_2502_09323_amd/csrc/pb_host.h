@@ -100,6 +100,7 @@ struct DevAlloc {
 struct BuildTmp {
     pbk::Bins bn;
     int *bcnt = nullptr, *bstart = nullptr, *bcur = nullptr, *bids = nullptr;
+    double* bxyzr = nullptr;  // the atoms' centres and radii in cell-list order
     uint32_t* cls = nullptr;
     int *bslots = nullptr, *bcuts = nullptr, *tot = nullptr;
     int nblk = 0;
@@ -107,7 +108,7 @@ struct BuildTmp {
     size_t hpin_cap = 0;
     int* htot = nullptr;
     double* full = nullptr;   // device copy of user boundary values
-    double* acell = nullptr;  // per atom: its deposition cell and offsets (6 doubles)
+    double* acell = nullptr;  // per cell-list slot: its atom's deposition cell, offsets and charge (8 doubles)
     double* dhpart = nullptr; // Debye-Hueckel partial sums per atom range and box node
 };
 

@@ -117,9 +117,10 @@ constexpr int TY = 2 * NWV;         // y-extent of a tile
 static_assert(NWV >= 2 && TY <= 32, "tile shape");
 
 // ---- build kernels (pb_build.hip) -----------------------------------------------------
+// the cell list, and in xyzr_b (4 n doubles) the atoms' centres and radii in its order
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
-                       int* cursor);
-hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at,
+                       int* cursor, double* xyzr_b);
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
                            uint32_t* code);
 hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk_slots,
                            int* blk_cuts, int nblk);
@@ -128,11 +129,11 @@ hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals);
 hipError_t launch_scan1(hipStream_t s, const int* in, int n, int* out);
 hipError_t launch_assign(hipStream_t s, const Grid& g, const uint32_t* cls, uint32_t* code,
                          const int* blk_slots, const int* blk_cuts, int* cutbase, int64_t* cutkey);
-hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at,
+hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
                            double eps_in, double eps_out, int64_t ncut, const int64_t* cutkey,
                            const uint32_t* code, double* alpha, double* kcut, double* rp,
                            double* np, int* owner, double* ck64, float* ck32);
-// ac: scratch of 6 doubles per atom (the atom's cell and offsets)
+// ac: scratch of 8 doubles per atom (in cell-list order: the atom's cell, offsets and charge)
 hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs);
 // grid energy: part[nb] = scale * sum_a q_a sum_corners w x over interior nodes, with
 // nb = grid_energy_blocks(at.n) and part holding nb + 1 doubles
