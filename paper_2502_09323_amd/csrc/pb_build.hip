@@ -447,6 +447,25 @@ __global__ void __launch_bounds__(256) k_grid_energy_total(double* part, int nb,
     if (threadIdx.x == 0) part[nb] = scale * v;
 }
 
+// the bins that can hold an atom depositing charge at the node p: the atom's deposition cell
+// is one of the eight cells around the node, so its centre lies within one spacing h of p on
+// every axis (widened by h/1000, far beyond the rounding of either position); false when no
+// bin is in reach.  The bin edge is at least 2h, so these bins are a sub-range of
+// bin_range's, visited in the same order: the sum over the atoms is the same to the bit.
+__device__ __forceinline__ bool bin_range_node(const Bins& b, const double* p, double h, int* lo, int* hi)
+{
+    const double l[3] = {b.lox, b.loy, b.loz};
+    const int nb[3] = {b.nbx, b.nby, b.nbz};
+    const double w = 1.001 * h;
+    for (int d = 0; d < 3; ++d) {
+        const double a = floor((p[d] - w - l[d]) / b.bs), c = floor((p[d] + w - l[d]) / b.bs);
+        if (c < 0.0 || a > (double)(nb[d] - 1)) return false;
+        lo[d] = a < 0.0 ? 0 : (int)a;
+        hi[d] = c > (double)(nb[d] - 1) ? nb[d] - 1 : (int)c;
+    }
+    return true;
+}
+
 __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const double* __restrict__ ac,
                                                  double* rhs)
 {
@@ -463,7 +482,7 @@ __global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const
     const int nd[3] = {i, j, k};
     double sum = 0.0;
     int lo[3], hi[3];
-    if (bin_range(b, p, lo, hi)) {
+    if (bin_range_node(b, p, g.h, lo, hi)) {
         for (int x = lo[0]; x <= hi[0]; ++x)
             for (int y = lo[1]; y <= hi[1]; ++y)
                 for (int z = lo[2]; z <= hi[2]; ++z) {
