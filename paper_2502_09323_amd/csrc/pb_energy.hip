@@ -297,17 +297,38 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 }  // namespace
 
+// blocks of k_nbody resident on the device at once: its compute units times the blocks one
+// compute unit holds (queried once, on the device current at the first call)
+static int nbody_slots()
+{
+    static const int slots = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nbody, 256, 0) != hipSuccess || per <= 0) per = 4;
+        return cus * per;
+    }();
+    return slots;
+}
+
 int nbody_chunks(int n_atoms, int64_t ncut)
 {
-    // about 8192 blocks, so that every SIMD holds several waves even for a few thousand atoms
-    // (whose launches are short), each chunk at least 64 cut points
-    const int ab = (n_atoms + NB_BLOCK_ATOMS - 1) / NB_BLOCK_ATOMS;   // blocks of k_nbody along the atoms
-    int64_t want = (8192 + ab - 1) / ab;
-    int64_t maxc = (ncut + 63) / 64;
-    if (want > maxc) want = maxc;
-    if (want < 1) want = 1;
-    if (want > 8192) want = 8192;
-    return (int)want;
+    // The blocks all carry the same work, so they run in rounds of nbody_slots() blocks; a
+    // last round of a few blocks would leave most of the device idle for a whole block's run.
+    // The grid is therefore the largest one of at most NB_ROUNDS rounds whose block count
+    // falls just short of a whole number of rounds, each chunk at least 64 cut points.
+    constexpr int NB_ROUNDS = 8;
+    const int64_t ab = (n_atoms + NB_BLOCK_ATOMS - 1) / NB_BLOCK_ATOMS;   // blocks along the atoms
+    const int64_t slots = nbody_slots();
+    const int64_t maxc = std::max<int64_t>(1, (ncut + 63) / 64);
+    for (int k = NB_ROUNDS; k >= 1; --k) {
+        const int64_t c = k * slots / ab;
+        if (c >= 1 && c <= maxc) return (int)c;
+    }
+    // fewer cut points than one round needs (one partial round), or more atom blocks than
+    // NB_ROUNDS rounds hold (one chunk)
+    return NB_ROUNDS * slots < ab ? 1 : (int)maxc;
 }
 
 hipError_t launch_edge_fields(hipStream_t s, const Grid& g, const Atoms& at, double eps_in, double eps_out, int64_t ncut,
