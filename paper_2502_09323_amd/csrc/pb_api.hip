@@ -741,7 +741,7 @@ int build_begin(pb_ctx* ctx, const pb_params* prm, int64_t na, const double* xyz
     // classification and counting of the cut edges
     T.cls = dalloc<uint32_t>(pb, N, &rc);
     CK(rc);
-    HK(launch_classify(s, g, bn, T.bxyzr, at, T.cls));
+    HK(launch_classify(s, g, bn, T.bxyzr, T.cls));
     T.nblk = (int)((N + 255) / 256);
     T.bslots = dalloc<int>(pb, (size_t)T.nblk + 1, &rc);
     CK(rc);

@@ -154,8 +154,7 @@ __global__ void __launch_bounds__(1024) k_scan1(const int* in, int n, int* out)
 
 // ---- classification -------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, Atoms at, const double* __restrict__ xb,
-                                                  uint32_t* code)
+__global__ void __launch_bounds__(256) k_classify(Grid g, Bins b, const double* __restrict__ xb, uint32_t* code)
 {
 #pragma clang fp contract(off)
     int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -466,8 +465,7 @@ __device__ __forceinline__ bool bin_range_node(const Bins& b, const double* p, d
     return true;
 }
 
-__global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, Atoms at, const double* __restrict__ ac,
-                                                 double* rhs)
+__global__ void __launch_bounds__(256) k_deposit(Grid g, Bins b, const double* __restrict__ ac, double* rhs)
 {
 #pragma clang fp contract(off)
     int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1028,10 +1026,9 @@ hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* s
     return hipGetLastError();
 }
 
-hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
-                           uint32_t* code)
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, uint32_t* code)
 {
-    k_classify<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, xyzr_b, code);
+    k_classify<<<nblk(g.N, 256), 256, 0, s>>>(g, b, xyzr_b, code);
     return hipGetLastError();
 }
 
@@ -1082,7 +1079,7 @@ hipError_t launch_cut_geom(hipStream_t s, const Grid& g, const Bins& b, const do
 hipError_t launch_deposit(hipStream_t s, const Grid& g, const Bins& b, const Atoms& at, double* ac, double* rhs)
 {
     if (at.n > 0) k_atom_cells<<<nblk(at.n, 256), 256, 0, s>>>(g, at, b.ids, ac);
-    k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, at, ac, rhs);
+    k_deposit<<<nblk(g.N, 256), 256, 0, s>>>(g, b, ac, rhs);
     return hipGetLastError();
 }
 

@@ -120,8 +120,7 @@ static_assert(NWV >= 2 && TY <= 32, "tile shape");
 // the cell list, and in xyzr_b (4 n doubles) the atoms' centres and radii in its order
 hipError_t launch_bins(hipStream_t s, const Atoms& at, Bins& b, int* cnt, int* start, int* ids,
                        int* cursor, double* xyzr_b);
-hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, const Atoms& at,
-                           uint32_t* code);
+hipError_t launch_classify(hipStream_t s, const Grid& g, const Bins& b, const double* xyzr_b, uint32_t* code);
 hipError_t launch_cutflags(hipStream_t s, const Grid& g, uint32_t* cls, int* blk_slots,
                            int* blk_cuts, int nblk);
 hipError_t launch_scan2(hipStream_t s, int* a, int* b, int n, int* totals);
