@@ -565,7 +565,8 @@ __device__ __forceinline__ double exp_dh(double r, const DhExp& E, const double*
 // block b % blocks of the faces and the atoms of range b / blocks (staged in LDS with the
 // face's own w term); its partial sums go to part[range][node] (the box-node numbering of
 // box_node), which k_bc_dh_sum adds up in range order.
-constexpr int DH_PU = 2, DH_PV = 4;   // nodes per thread along u, v
+constexpr int DH_PU = 2, DH_PV = 4;
+constexpr int DH_GROUP = 32;   // atoms per FP32 partial sum of the mixed kernel   // nodes per thread along u, v
 
 // a thread's patch of box-face nodes: its face (normal axis w, in-plane axes ua slower and va
 // faster), the patch's first node (u0, v0) on the face's U x V array, and the coordinates,
@@ -691,9 +692,12 @@ __global__ void __launch_bounds__(256) k_bc_dh(Grid g, Atoms at, DhExp E, DhSpli
     dh_write(P, fc, sp, rg, s, part);
 }
 
-// The same sum for the mixed-precision form: squared distances in FP64 (the face terms as in
-// k_bc_dh), then the exponential and the inverse distance in FP32 (a few units in the last
-// place, about 1e-7 relative per term), accumulated in FP64.  The box is tens of Angstrom from
+// The same sum for the mixed-precision form: the row and column terms of the squared
+// distances in FP64 (as in k_bc_dh), rounded to FP32 once per atom and added in FP32, then the
+// exponential and the inverse distance in FP32 (a few units in the last place, about 1e-7
+// relative per term), summed in FP32 over groups of DH_GROUP atoms and the group sums in FP64
+// (a group's rounding, about sqrt(DH_GROUP) units in the last place of its absolute sum, stays
+// near the terms' own).  The box is tens of Angstrom from
 // the surface, so these errors reach the surface potential screened by exp(-kD d) and stay
 // far below the FP32 iteration's own rounding.  The hardware reciprocal square root and
 // base-2 exponential are used directly: r^2 leaves the FP32 normal range only for an atom
@@ -723,19 +727,37 @@ __global__ void __launch_bounds__(256) k_bc_dh32(Grid g, Atoms at, double kD, Dh
         __syncthreads();
         const int m = a1 - base < 256 ? a1 - base : 256;
         if (!P.act) continue;
-        for (int q = 0; q < m; ++q) {
-            double ru[DH_PU], rv[DH_PV];
-            dh_terms(P, sa + 3 * q, ru, rv);
-            const float qq = sq[q];
+        // groups of DH_GROUP atoms summed in FP32, the group sums added in FP64
+        for (int q0 = 0; q0 < m; q0 += DH_GROUP) {
+            const int q1 = q0 + DH_GROUP < m ? q0 + DH_GROUP : m;
+            float t[DH_PU][DH_PV];
 #pragma unroll
             for (int a = 0; a < DH_PU; ++a)
 #pragma unroll
-                for (int b = 0; b < DH_PV; ++b) {
-                    const float r2 = (float)(ru[a] + rv[b]);
-                    const float ri = __builtin_amdgcn_rsqf(r2);
-                    const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
-                    s[a][b] += (double)(qq * e * ri);
-                }
+                for (int b = 0; b < DH_PV; ++b) t[a][b] = 0.0f;
+            for (int q = q0; q < q1; ++q) {
+                double ru[DH_PU], rv[DH_PV];
+                dh_terms(P, sa + 3 * q, ru, rv);
+                float fu[DH_PU], fv[DH_PV];
+#pragma unroll
+                for (int a = 0; a < DH_PU; ++a) fu[a] = (float)ru[a];
+#pragma unroll
+                for (int b = 0; b < DH_PV; ++b) fv[b] = (float)rv[b];
+                const float qq = sq[q];
+#pragma unroll
+                for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+                    for (int b = 0; b < DH_PV; ++b) {
+                        const float r2 = fu[a] + fv[b];
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        const float e = __builtin_amdgcn_exp2f(mk * (r2 * ri));
+                        t[a][b] = fmaf(qq * e, ri, t[a][b]);
+                    }
+            }
+#pragma unroll
+            for (int a = 0; a < DH_PU; ++a)
+#pragma unroll
+                for (int b = 0; b < DH_PV; ++b) s[a][b] += (double)t[a][b];
         }
     }
     dh_write(P, fc, sp, rg, s, part);

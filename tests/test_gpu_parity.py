@@ -243,7 +243,7 @@ def test_dh_all_box_nodes_non_cubic(ctx, prec):
     """Debye-Hueckel values (Sect. 2.3) at every box node, the edges and corners of the box
     included, on a grid with a different node count per axis (so that every face has ragged
     patch rows and columns): the exported potential at the box nodes is lB g, against the
-    oracle's g, to 1e-13 (FP64) or 1e-6 (mixed: FP32 exponential and inverse distance) of the
+    oracle's g, to 1e-13 (FP64) or 1e-6 (mixed: FP32 distance, exponential and group sums) of the
     absolute-value scale of each node."""
     mol = I.random_molecule(700, 8.0, 23, center=(3.0, -2.0, 1.0))
     n = (45, 38, 51)
