@@ -499,12 +499,12 @@ def workload(name: str):
 # on a refined problem: apply (K x3 and the lumped term, role, p; q), dot (role, p, q),
 # update (role, x, r rw; p, q, D^-1; z), direction (role, z, p rw)
 # FP64 flops per atom x cut-point pair of the energy N-body sum (a fused multiply-add counts
-# two), in the direct form: the three differences, the squared distance (5), the correction of
-# the hardware reciprocal square root estimate (8; the estimate itself is not counted),
+# two), in the direct form: the three differences, the squared distance (5), the Newton step
+# on the hardware reciprocal square root estimate (6; the estimate itself is not counted),
 # the dot product with the weighted normal (5), F/r into its sum (2) and the r^-3 term (4).
 # The kernel's expanded form (squared distance and dot product from per-point and per-atom
-# terms) performs the same 27 in 16 instructions instead of 18.
-NBODY_FLOPS_PER_PAIR = 27
+# terms) performs the same 25 in 15 instructions instead of 17.
+NBODY_FLOPS_PER_PAIR = 25
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic bytes per interior unknown of one level-0 red-black half-sweep of the V-cycle
 # (FP32, red-black layout): read x of the other colour, b, 1/D and the node codes of the swept
